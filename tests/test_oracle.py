@@ -1,0 +1,286 @@
+"""Pins for the oracle (CPU only): exact rational arithmetic, the eps-polynomial of the
+symbolic perturbation, brute force on tiny inputs, invariants, order independence, and
+the Moore-curve / BRIO definitions."""
+import itertools
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from synth import cluster_points, lattice_points, shell_points, uniform_points
+from validators import (brute_force_dt, check_invariants, det_exact, insphere_exact,
+                        insphere_perturbed_poly, lifted_rows, orient3d_exact,
+                        perturbed_sign_int, _int_scale)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+rng = np.random.default_rng(12345)
+
+
+def sphere50_points():
+    """All integer points with x^2 + y^2 + z^2 = 50 (84 cospherical points)."""
+    pts = []
+    for x in range(-8, 8):
+        for y in range(-8, 8):
+            for z in range(-8, 8):
+                if x * x + y * y + z * z == 50:
+                    pts.append((x, y, z))
+    return np.array(pts, dtype=np.float64)
+
+
+def nudge(x, k):
+    return np.nextafter(x, np.inf) if k > 0 else (np.nextafter(x, -np.inf) if k < 0 else x)
+
+
+# ------------------------------------------------------------------ orient3d / insphere
+
+def test_orient3d_matches_rational(oracle_mod):
+    cases = [uniform_points(4, s) for s in range(200)]
+    # near-degenerate: 4th point on the plane of the first three, nudged by an ulp
+    for s in range(150):
+        p = uniform_points(3, 500 + s)
+        u, v = rng.random(2)
+        q = p[0] + u * (p[1] - p[0]) + v * (p[2] - p[0])
+        q = np.array([nudge(q[0], int(rng.integers(-1, 2))), q[1], nudge(q[2], int(rng.integers(-1, 2)))])
+        cases.append(np.vstack([p, q]))
+    # exactly degenerate: lattice quadruples
+    lat = lattice_points(100, 7, side=5)
+    for _ in range(150):
+        cases.append(lat[rng.choice(len(lat), 4, replace=False)])
+    pts = np.array(cases)
+    got = oracle_mod.orient3d(pts)
+    want = np.array([orient3d_exact(*c) for c in cases])
+    assert np.array_equal(got, want)
+    assert np.count_nonzero(want == 0) > 10
+
+
+def test_insphere_matches_rational(oracle_mod):
+    cases = [uniform_points(5, 1000 + s) for s in range(150)]
+    sph = sphere50_points() / 8.0
+    for _ in range(150):  # cospherical, some nudged by an ulp
+        c = sph[rng.choice(len(sph), 5, replace=False)].copy()
+        k = int(rng.integers(-1, 2))
+        j = int(np.flatnonzero(c[4])[0])  # nudge a non-zero coordinate (stay in range)
+        c[4, j] = nudge(c[4, j], k)
+        cases.append(c)
+    lat = lattice_points(60, 9, side=4)
+    for _ in range(100):
+        cases.append(lat[rng.choice(len(lat), 5, replace=False)])
+    pts = np.array(cases)
+    got = oracle_mod.insphere(pts)
+    want = np.array([insphere_exact(c) for c in cases])
+    assert np.array_equal(got, want)
+    assert np.count_nonzero(want == 0) > 20
+
+
+def test_insphere_closed_forms(oracle_mod):
+    """Hand-worked determinant values (tests/golden/insphere_closed_forms.txt)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "insphere_closed_forms.txt"))
+            if l.strip() and not l.startswith("#")]
+    base = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]]
+    for ex, ey, ez, val in rows:
+        e = [float(ex), float(ey), float(ez)]
+        det = det_exact(lifted_rows(base + [e]))
+        assert det == Fraction(val)
+        got = int(oracle_mod.insphere(np.array(base + [e]))[0])
+        assert got == (det > 0) - (det < 0)
+    assert int(oracle_mod.orient3d(np.array(base, dtype=float))[0]) == 1
+
+
+def _positive(quad):
+    q = np.array(quad)
+    if orient3d_exact(*q) < 0:
+        q[[0, 1]] = q[[1, 0]]
+    return q
+
+
+def test_perturbed_insphere_matches_eps_polynomial(oracle_mod):
+    """The oracle's perturbation against the eps-polynomial of the definition."""
+    sph = sphere50_points() / 8.0
+    cube = np.array(list(itertools.product([0.0, 1.0], repeat=3)))
+    lat = lattice_points(64, 3, side=4)
+    sets = [sph, cube, lat]
+    pts, idxs = [], []
+    for trial in range(240):
+        src = sets[trial % 3]
+        sel = rng.choice(len(src), 5, replace=False)
+        c = src[sel].copy()
+        if orient3d_exact(*c[:4]) == 0:
+            continue
+        c[:4] = _positive(c[:4])
+        idx = rng.permutation(1000)[:5]
+        pts.append(c)
+        idxs.append(idx)
+    pts, idxs = np.array(pts), np.array(idxs)
+    got = oracle_mod.insphere_sos(pts, idxs)
+    want = np.array([insphere_perturbed_poly(p, i) for p, i in zip(pts, idxs)])
+    assert np.all(want != 0)
+    assert np.array_equal(got, want)
+    # many of these were exact zeros before the perturbation
+    raw = np.array([insphere_exact(p) for p in pts])
+    assert np.count_nonzero(raw == 0) > 40
+
+
+def test_bruteforce_cofactor_sign_matches_eps_polynomial():
+    """The brute-force helper's tie-break agrees with the eps-polynomial definition."""
+    cube = np.array(list(itertools.product([0.0, 1.0], repeat=3)))
+    P = _int_scale(cube)
+    for quad in itertools.combinations(range(8), 4):
+        q = list(quad)
+        if orient3d_exact(*cube[q]) == 0:
+            continue
+        if orient3d_exact(*cube[q]) < 0:
+            q[0], q[1] = q[1], q[0]
+        for e in range(8):
+            if e in quad:
+                continue
+            idx = list(rng.permutation(8))
+            a = perturbed_sign_int(P, q, e, idx)
+            b = insphere_perturbed_poly(cube[q + [e]], [idx[v] for v in q + [e]])
+            assert a == b
+
+
+# ------------------------------------------------------------------ brute force
+
+def _oracle_canon(oracle_mod, xyz, order="brio"):
+    rc, tets, nbrs, st = oracle_mod.delaunay(xyz, order=order)
+    assert rc == 0
+    return oracle_mod.canonical(tets), tets, nbrs
+
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (5, 2), (5, 3), (6, 4), (8, 5), (10, 6), (12, 7), (12, 8)])
+def test_bruteforce_uniform(oracle_mod, n, seed):
+    xyz = uniform_points(n, seed)
+    canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
+    assert np.array_equal(canon, brute_force_dt(xyz))
+
+
+def test_bruteforce_cube_corners(oracle_mod):
+    cube = np.array(list(itertools.product([0.0, 1.0], repeat=3)))
+    for perm_seed in range(4):
+        perm = np.random.default_rng(perm_seed).permutation(8)
+        xyz = cube[perm]
+        canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
+        assert np.array_equal(canon, brute_force_dt(xyz))
+        assert len(canon) in (5, 6)
+        check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(8))
+
+
+def test_bruteforce_cospherical(oracle_mod):
+    sph = sphere50_points() / 8.0
+    for s in range(3):
+        xyz = sph[np.random.default_rng(40 + s).choice(len(sph), 12, replace=False)]
+        canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
+        assert np.array_equal(canon, brute_force_dt(xyz))
+
+
+def test_bruteforce_coplanar_hull(oracle_mod):
+    """3x3 grid in the plane z = 0 plus points above: coplanar and cocircular hull."""
+    grid = np.array([[x, y, 0.0] for x in range(3) for y in range(3)])
+    top = np.array([[0.5, 0.5, 1.0], [1.5, 1.0, 0.75], [1.0, 1.75, 1.25]])
+    for s in range(3):
+        xyz = np.random.default_rng(s).permutation(np.vstack([grid, top]))
+        canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
+        assert np.array_equal(canon, brute_force_dt(xyz))
+        check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(len(xyz)))
+
+
+def test_bruteforce_lattice_3x3x3(oracle_mod):
+    xyz = np.random.default_rng(5).permutation(
+        np.array(list(itertools.product([0.0, 0.5, 1.0], repeat=3))))
+    canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
+    assert np.array_equal(canon, brute_force_dt(xyz))
+    check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(27))
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_errors_and_duplicates(oracle_mod):
+    assert oracle_mod.delaunay(np.zeros((3, 3)))[0] == oracle_mod.E_DEGENERATE
+    plane = np.c_[uniform_points(50, 3)[:, :2], np.zeros(50)]
+    assert oracle_mod.delaunay(plane)[0] == oracle_mod.E_DEGENERATE
+    line = np.outer(np.arange(10.0), [1.0, 2.0, 3.0])
+    assert oracle_mod.delaunay(line)[0] == oracle_mod.E_DEGENERATE
+    bad = uniform_points(10, 4)
+    bad[3, 1] = np.nan
+    assert oracle_mod.delaunay(bad)[0] == oracle_mod.E_INPUT
+    big = uniform_points(10, 4)
+    big[2, 2] = 1e300
+    assert oracle_mod.delaunay(big)[0] == oracle_mod.E_INPUT
+    # duplicates: representative is the lowest index, result as without the copies
+    xyz = uniform_points(300, 5)
+    dup = np.vstack([xyz, xyz[[7, 100, 7, 299]]])
+    rc, tets, nbrs, st = oracle_mod.delaunay(dup)
+    assert rc == 0 and st["duplicates"] == 4
+    canon_dup = oracle_mod.canonical(tets)
+    canon = _oracle_canon(oracle_mod, xyz)[0]
+    assert np.array_equal(canon_dup, canon)
+    # a duplicate placed before its twin: the lower index wins
+    dup2 = np.vstack([xyz[[5]], xyz])
+    canon2 = oracle_mod.canonical(oracle_mod.delaunay(dup2)[1])
+    assert 0 in canon2 and 6 not in canon2
+
+
+# ------------------------------------------------------------------ order independence
+
+def _mix_small(seed):
+    return np.random.default_rng(seed).permutation(np.vstack([
+        lattice_points(700, seed, side=10), cluster_points(700, seed, clusters=5),
+        shell_points(700, seed)]))
+
+
+@pytest.mark.parametrize("kind", ["uniform", "lattice", "mix"])
+def test_order_independence(oracle_mod, kind):
+    xyz = {"uniform": lambda: uniform_points(3000, 11),
+           "lattice": lambda: lattice_points(300, 12, side=7),
+           "mix": lambda: _mix_small(13)}[kind]()
+    ref = _oracle_canon(oracle_mod, xyz, "brio")[0]
+    for order in ("random", "reverse", "input"):
+        assert np.array_equal(_oracle_canon(oracle_mod, xyz, order)[0], ref), order
+
+
+@pytest.mark.parametrize("kind", ["uniform", "mix"])
+def test_invariants(oracle_mod, kind):
+    xyz = uniform_points(20000, 21) if kind == "uniform" else _mix_small(22)
+    rc, tets, nbrs, st = oracle_mod.delaunay(xyz)
+    assert rc == 0
+    info = check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(len(xyz)))
+    if kind == "uniform":
+        # sanity, not a pin: a little more than 6 tetrahedra per point (paper Sec. 2.2)
+        assert 6.0 < len(tets) / len(xyz) < 7.0
+        assert st["insphere_exact"] == 0
+    else:
+        assert st["insphere_zero"] > 0
+
+
+# ------------------------------------------------------------------ Moore curve, BRIO
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4])
+def test_moore_curve_closed_and_adjacent(oracle_mod, m):
+    n = 1 << m
+    cells = np.array(list(itertools.product(range(n), repeat=3)), dtype=np.uint32)
+    keys = np.array([oracle_mod.moore_index(c, m) for c in cells], dtype=np.int64)
+    assert np.array_equal(np.sort(keys), np.arange(n ** 3))
+    path = cells[np.argsort(keys)].astype(np.int64)
+    step = np.abs(np.diff(np.vstack([path, path[:1]]), axis=0)).sum(axis=1)
+    assert np.all(step == 1)  # consecutive cells share a face, last back to first
+
+
+def test_moore_level(oracle_mod):
+    assert oracle_mod.moore_level(1e5) == 6
+    assert oracle_mod.moore_level(1e7) == 8
+    assert oracle_mod.moore_level(1e8) == 9
+    assert oracle_mod.moore_level(2) == 1
+
+
+def test_brio_rounds_match_paper_table(oracle_mod):
+    lines = [l.split() for l in open(os.path.join(GOLDEN, "brio_rounds_1e6.txt"))
+             if l.strip() and not l.startswith("#")]
+    n = int(lines[0][1])
+    want = [int(v) for v in lines[1][1:]]
+    lev, cum = oracle_mod.brio_levels(n, 77)
+    assert list(cum) == want
+    counts = np.cumsum(np.bincount(lev, minlength=len(cum)))
+    for c, w in zip(counts, want):
+        assert abs(c - w) <= 6 * np.sqrt(w) + 1
+    assert counts[-1] == n
