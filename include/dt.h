@@ -1,0 +1,152 @@
+/*
+ * dt.h -- exact 3D Delaunay tetrahedralization on one AMD MI355X (gfx950).
+ *
+ * The library builds the Delaunay tetrahedralization of fp64 point sets by incremental
+ * Bowyer-Watson insertion (the "Delaunay kernel" DT <- DT - C(DT, p) + B(DT, p) of
+ * Marot, Pellerin and Remacle, "One machine, one minute, three billion tetrahedra",
+ * Sec. 2.1, Eq. (1) and Algorithm 1), with thousands of insertions per round on the GPU.
+ *
+ * Problem statement (Sec. 1): for a set S of n points the output is a set of
+ * non-overlapping tetrahedra that covers the convex hull of S, uses every distinct point
+ * of S as a vertex, and whose circumspheres contain no point of S.  Points in
+ * non-general position are resolved by symbolic perturbation (Sec. 2.4, item 3): the
+ * lifted coordinate |p_i|^2 of the point with input index i is perturbed by eps^delta_i,
+ * delta strictly decreasing in i.  The result is therefore unique and does not depend on
+ * the insertion order, the round packing or the launch configuration.
+ *
+ * Conventions (Sec. 2.2): a tetrahedron (v0,v1,v2,v3) has orient3d(v0,v1,v2,v3) > 0 with
+ * orient3d(a,b,c,d) = (b-a).((c-a)x(d-a)); facet j is the facet opposite vertex vj.
+ *
+ * Memory: every pointer argument may be host memory or device memory of the context's
+ * device (the library checks with hipPointerGetAttributes).  The caller owns all buffers
+ * it passes; the library copies what it needs and never keeps a caller pointer.  All work
+ * runs on the context's stream; every call returns after the work has completed.
+ * A context is not thread-safe: use one context per host thread.
+ *
+ * Errors: every function returns DT_OK or one of the DT_E_* codes below and never
+ * throws across the ABI; dt_last_error() gives a readable message for the last failure.
+ */
+#ifndef DT_H
+#define DT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DT_OK = 0,
+    DT_E_ARG = 1,        /* NULL pointer, bad size or bad option                        */
+    DT_E_INPUT = 2,      /* a coordinate is not finite or has magnitude outside the
+                            accepted range (0, or |x| in [2^-120, 2^120))                 */
+    DT_E_DEGENERATE = 3, /* fewer than four affinely independent distinct points        */
+    DT_E_CAPACITY = 4,   /* device memory exhausted or a size limit exceeded            */
+    DT_E_INCOMPLETE = 5, /* the round limit (dt_options.max_rounds) was reached         */
+    DT_E_DEVICE = 6,     /* a HIP runtime call failed                                   */
+    DT_E_INTERNAL = 7    /* an internal consistency check failed (a bug)                */
+};
+
+typedef struct dt_ctx dt_ctx;
+
+typedef struct {
+    int device;             /* HIP device ordinal                                        */
+    void *stream;           /* hipStream_t to run on; NULL: the library creates one       */
+    uint32_t round_size;    /* most insertions attempted per round; 0: automatic         */
+    uint32_t cavity_cap;    /* cavity tetrahedra buffered per insertion; 0: automatic     */
+    uint64_t capacity_tets; /* initial tetrahedron pool (grown on demand); 0: automatic   */
+    uint64_t seed;          /* seed of the randomized insertion levels (BRIO, Sec. 2.3)  */
+    uint32_t max_rounds;    /* 0: unlimited; otherwise DT_E_INCOMPLETE beyond it          */
+    int timing;             /* 1: time the insertion kernels with HIP events              */
+    double round_fraction;  /* round size as a fraction of the current vertex count;
+                               0: automatic                                              */
+} dt_options;
+
+/* Counters of the work done since dt_create or the last dt_clear. */
+typedef struct {
+    uint64_t points;          /* points passed to dt_insert_points                     */
+    uint64_t vertices;        /* distinct points in the triangulation                  */
+    uint64_t duplicates;      /* exact duplicates dropped (lowest input index kept)    */
+    uint64_t tets;            /* finite tetrahedra of the current triangulation        */
+    uint64_t rounds;          /* insertion rounds                                      */
+    uint64_t attempts;        /* insertion attempts (walk + cavity) over all rounds    */
+    uint64_t inserted;        /* successful insertions                                 */
+    uint64_t conflicts;       /* attempts that lost a claim to a lower-ranked insertion */
+    uint64_t overflows;       /* attempts whose cavity outgrew the per-insertion buffer */
+    uint64_t walk_steps;      /* tetrahedra crossed by point location                  */
+    uint64_t cavity_tets;     /* tetrahedra deleted by successful insertions           */
+    uint64_t boundary_facets; /* tetrahedra created by successful insertions           */
+    uint64_t orient_calls, orient_exact;     /* orient3d evaluations / exact fallbacks  */
+    uint64_t insphere_calls, insphere_exact; /* insphere evaluations / exact fallbacks  */
+    uint64_t perturbed;       /* insphere decisions taken by the symbolic perturbation  */
+    double ms_total;          /* wall time of dt_insert_points calls (host clock)      */
+    double ms_sort;           /* validation, Moore keys, radix sort, dedupe, anchors   */
+    double ms_insert;         /* all insertion rounds                                  */
+    /* with dt_options.timing = 1: HIP-event time of the two insertion kernels */
+    uint64_t cavity_launches, ball_launches;
+    double ms_cavity_kernel, ms_ball_kernel;
+    uint64_t cavity_units, ball_units; /* attempts processed / insertions completed   */
+} dt_stats;
+
+/* Fill *opt with the defaults (device 0, library stream, automatic sizes, seed 0x5EED). */
+void dt_default_options(dt_options *opt);
+
+/* Create a context on opt->device (opt may be NULL for the defaults).
+   *out receives the context; release it with dt_destroy. */
+int dt_create(dt_ctx **out, const dt_options *opt);
+
+/* Insert n points, xyz[3*i+0..2] = (x, y, z) of point i, fp64, array of structures,
+   host or device memory.  Point i of this call gets the global input index
+   (points inserted before) + i.  On return the context holds the Delaunay
+   tetrahedralization of all points inserted so far (Algorithm 1 run as concurrent
+   rounds).  An exact duplicate of an earlier point is not a vertex.  The first call
+   must provide four affinely independent points or it fails with DT_E_DEGENERATE and
+   leaves the context empty.  After DT_E_ARG, DT_E_INPUT or DT_E_DEGENERATE the context
+   is as it was before the call; after DT_E_CAPACITY, DT_E_INCOMPLETE, DT_E_DEVICE or
+   DT_E_INTERNAL only dt_clear, dt_get_stats, dt_last_error and dt_destroy are
+   meaningful. */
+int dt_insert_points(dt_ctx *ctx, const double *xyz, uint64_t n);
+
+/* Export the finite tetrahedra.  *num_tets is in/out: on input the capacity of the
+   buffers in tetrahedra, on output the number T of tetrahedra (also when it exceeds the
+   capacity, in which case nothing is written and DT_E_ARG is returned).  tets
+   (4*T uint32, may be NULL) receives the global input indices of each tetrahedron's
+   vertices in positive orientation; nbrs (4*T int64, may be NULL) receives, for facet j,
+   the index of the tetrahedron across it or -1 on the convex hull.  Pass both NULL to
+   query T.  Host or device pointers. */
+int dt_get_tets(dt_ctx *ctx, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
+
+/* Drop every point and tetrahedron but keep the device allocations. */
+int dt_clear(dt_ctx *ctx);
+
+/* Release the context and its device memory. */
+int dt_destroy(dt_ctx *ctx);
+
+/* Copy the counters into *out. */
+int dt_get_stats(const dt_ctx *ctx, dt_stats *out);
+
+/* Readable message of the last error on this context (never NULL). */
+const char *dt_last_error(const dt_ctx *ctx);
+
+/* ---- test hooks: the kernels of the hot path run on caller data ---- */
+
+/* Sort step (Sec. 2.3): for n points (device or host xyz) computes the sort key
+   (BRIO level << 3m | Moore index) of every point and the stable sorted order.
+   keys (n uint64) receives the keys in input order, perm (n uint32) the input index of
+   the point at each sorted position; *moore_m receives m.  Device or host outputs. */
+int dt_debug_sort(dt_ctx *ctx, const double *xyz, uint64_t n, uint64_t *keys, uint32_t *perm,
+                  int *moore_m);
+
+/* Predicates (Sec. 2.4): for k records evaluates, per record r,
+   kind 0: orient3d sign of pts[12r .. 12r+11] (four points);
+   kind 1: insphere sign of the unperturbed lifted determinant of pts[15r ..] (five points);
+   kind 2: sign of the perturbed lifted determinant, input indices idx[5r .. 5r+4].
+   out[r] in {-1, 0, 1}.  Device or host buffers. */
+int dt_debug_predicates(dt_ctx *ctx, int kind, const double *pts, const int64_t *idx,
+                        uint64_t k, int8_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

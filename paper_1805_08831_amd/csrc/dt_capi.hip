@@ -1,0 +1,780 @@
+// Host driver and C ABI of the library (include/dt.h).
+//
+// dt_insert_points: validate + bounding box -> Moore keys and BRIO levels -> radix sort ->
+// vertex records -> duplicates -> initial tetrahedron (first call) -> curve anchors ->
+// insertion rounds until every point of the call is inserted (paper Algorithm 1, with
+// the sequential loop replaced by rounds of concurrent insertions).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dt.h"
+#include "dt_internal.h"
+
+using namespace dtk;
+
+namespace {
+
+constexpr uint32_t DEFAULT_ROUND_MAX = 1u << 20;
+constexpr uint32_t DEFAULT_CAVITY_CAP = 96;
+constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
+constexpr uint32_t ROUND_MIN = 64;
+
+uint64_t host_mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+int moore_level(uint64_t n) {
+    int m = 1;
+    while (m < 21 && (1ull << (3 * m)) < n) ++m;
+    return m;
+}
+
+// cumulative BRIO sizes 2048 * 7^k, capped at n
+std::vector<uint64_t> brio_cum(uint64_t n) {
+    std::vector<uint64_t> cum;
+    uint64_t size = 2048;
+    for (;;) {
+        cum.push_back(std::min(size, n));
+        if (size >= n) break;
+        size *= 7;
+    }
+    return cum;
+}
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;  // elements
+};
+
+}  // namespace
+
+struct dt_ctx {
+    dt_options opt{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err = "no error";
+
+    uint64_t npoints = 0;  // points passed so far (global input indices)
+    uint64_t nv = 0;       // vertex records in V
+    bool have_mesh = false;
+    uint32_t init_v0 = 0;
+    uint64_t round_counter = 0;  // monotonic over the context's lifetime
+    uint64_t mesh_vertices = 0;
+    int fl_idx = 0;
+    int list_idx = 0;
+    int ovf_idx = 0;
+
+    DevBuf<Vert> V;
+    DevBuf<uint32_t> vtet, anchor;
+    DevBuf<uint8_t> dup;
+    uint32_t tcap = 0;
+    uint4 *tv = nullptr, *tn = nullptr;
+    unsigned long long *owner = nullptr;
+    uint32_t *fl[2] = {nullptr, nullptr};
+
+    uint32_t list_cap = 0;
+    uint32_t *lpt[4] = {}, *lrank[4] = {};
+    size_t bufC = 0, bufF = 0;
+    uint32_t capC = 0, capF = 0;
+    uint32_t *cav = nullptr, *bnd = nullptr, *outc = nullptr, *cnt = nullptr;
+    uint8_t *status = nullptr;
+
+    Ctr *ctr = nullptr;
+    Ctr *hctr = nullptr;  // pinned mirror
+
+    // per-call scratch
+    DevBuf<double> staging;
+    DevBuf<unsigned long long> keys, keys_tmp, table;
+    DevBuf<uint32_t> vals, vals_tmp, hist, scan_tmp, small;
+    DevBuf<double> bbox;
+    DevBuf<uint64_t> small64;
+    // output scratch
+    DevBuf<uint32_t> oflags, omap, otets;
+    DevBuf<int64_t> onbrs;
+
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    dt_stats st{};
+};
+
+namespace {
+
+int fail(dt_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail(c, DT_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int ensure(dt_ctx *c, DevBuf<T> &b, size_t n, bool keep = false) {
+    if (b.cap >= n && b.p) return DT_OK;
+    size_t cap = std::max<size_t>(n, 1);
+    if (b.cap) cap = std::max(cap, b.cap + b.cap / 2);
+    T *p = nullptr;
+    if (hipMalloc((void **)&p, cap * sizeof(T)) != hipSuccess) {
+        hipGetLastError();
+        return fail(c, DT_E_CAPACITY, "device allocation of %zu bytes failed", cap * sizeof(T));
+    }
+    if (keep && b.p && b.cap) HIPCHK(hipMemcpyAsync(p, b.p, b.cap * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    if (b.p) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(b.p));
+    }
+    b.p = p;
+    b.cap = cap;
+    return DT_OK;
+}
+
+bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice;
+}
+
+int sync_ctr(dt_ctx *c) {
+    HIPCHK(hipMemcpyAsync(c->hctr, c->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DT_OK;
+}
+
+int grow_tets(dt_ctx *c, uint64_t need) {
+    if (need > MAX_TETS) return fail(c, DT_E_CAPACITY, "more than %u tetrahedra needed", MAX_TETS);
+    uint64_t cap = std::max<uint64_t>(need, (uint64_t)c->tcap + c->tcap / 2);
+    cap = std::min<uint64_t>(cap, MAX_TETS);
+    uint4 *tv = nullptr, *tn = nullptr;
+    unsigned long long *ow = nullptr;
+    uint32_t *f0 = nullptr, *f1 = nullptr;
+    bool ok = hipMalloc((void **)&tv, cap * sizeof(uint4)) == hipSuccess &&
+              hipMalloc((void **)&tn, cap * sizeof(uint4)) == hipSuccess &&
+              hipMalloc((void **)&ow, cap * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc((void **)&f0, cap * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void **)&f1, cap * sizeof(uint32_t)) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        hipFree(tv); hipFree(tn); hipFree(ow); hipFree(f0); hipFree(f1);
+        return fail(c, DT_E_CAPACITY, "device allocation for %llu tetrahedra failed", (unsigned long long)cap);
+    }
+    HIPCHK(hipMemsetAsync(ow, 0xFF, cap * sizeof(unsigned long long), c->stream));
+    if (c->tcap) {
+        uint64_t used = c->hctr->tet_count;
+        HIPCHK(hipMemcpyAsync(tv, c->tv, used * sizeof(uint4), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(tn, c->tn, used * sizeof(uint4), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(ow, c->owner, used * sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        uint64_t nf = c->hctr->fl_n;
+        HIPCHK(hipMemcpyAsync(c->fl_idx == 0 ? f0 : f1, c->fl[c->fl_idx], nf * sizeof(uint32_t),
+                              hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        hipFree(c->tv); hipFree(c->tn); hipFree(c->owner); hipFree(c->fl[0]); hipFree(c->fl[1]);
+    }
+    c->tv = tv; c->tn = tn; c->owner = ow; c->fl[0] = f0; c->fl[1] = f1;
+    c->tcap = (uint32_t)cap;
+    return DT_OK;
+}
+
+int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
+    if (c->list_cap >= rmax && c->cav) return DT_OK;
+    for (int k = 0; k < 4; ++k) {
+        hipFree(c->lpt[k]);
+        hipFree(c->lrank[k]);
+        c->lpt[k] = c->lrank[k] = nullptr;
+    }
+    hipFree(c->cav); hipFree(c->bnd); hipFree(c->outc); hipFree(c->cnt); hipFree(c->status);
+    c->cav = c->bnd = c->outc = c->cnt = nullptr;
+    c->status = nullptr;
+    c->list_cap = rmax;
+    c->bufC = (size_t)rmax * c->capC;
+    c->bufF = (size_t)rmax * c->capF;
+    bool ok = true;
+    for (int k = 0; k < 4; ++k)
+        ok = ok && hipMalloc((void **)&c->lpt[k], rmax * sizeof(uint32_t)) == hipSuccess &&
+             hipMalloc((void **)&c->lrank[k], rmax * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&c->cav, c->bufC * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc((void **)&c->bnd, c->bufF * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc((void **)&c->outc, c->bufF * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc((void **)&c->cnt, 2 * (size_t)rmax * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc((void **)&c->status, rmax) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        c->list_cap = 0;
+        return fail(c, DT_E_CAPACITY, "round buffers for %u insertions do not fit", rmax);
+    }
+    return DT_OK;
+}
+
+struct Levels {
+    int L = 0;
+    std::vector<uint32_t> start_local, start_global, size, bits, prev;
+    std::vector<unsigned long long> rank_base;
+    uint64_t total_ranks = 0;
+};
+
+// device copies of the level tables live in c->small / c->small64
+int upload_levels(dt_ctx *c, const Levels &lv, uint32_t **d_start_local, uint32_t **d_start_global,
+                  uint32_t **d_size, uint32_t **d_bits, uint32_t **d_prev, unsigned long long **d_rank_base) {
+    const int L = lv.L;
+    std::vector<uint32_t> packed;
+    packed.insert(packed.end(), lv.start_local.begin(), lv.start_local.end());    // L + 1
+    packed.insert(packed.end(), lv.start_global.begin(), lv.start_global.end());  // L + 1
+    packed.insert(packed.end(), lv.size.begin(), lv.size.end());                  // L
+    packed.insert(packed.end(), lv.bits.begin(), lv.bits.end());                  // L
+    packed.insert(packed.end(), lv.prev.begin(), lv.prev.end());                  // L
+    int rc = ensure(c, c->small, packed.size() + 64);
+    if (rc) return rc;
+    rc = ensure(c, c->small64, (size_t)2 * (L + 1) + 64);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(c->small.p, packed.data(), packed.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(c->small64.p, lv.rank_base.data(), (L + 1) * sizeof(unsigned long long),
+                          hipMemcpyHostToDevice, c->stream));
+    *d_start_local = c->small.p;
+    *d_start_global = c->small.p + (L + 1);
+    *d_size = c->small.p + 2 * (L + 1);
+    *d_bits = c->small.p + 2 * (L + 1) + L;
+    *d_prev = c->small.p + 2 * (L + 1) + 2 * L;
+    *d_rank_base = (unsigned long long *)c->small64.p;
+    return DT_OK;
+}
+
+int grow_tets(dt_ctx *c, uint64_t need);
+
+int check_errors(dt_ctx *c) {
+    uint32_t e = c->hctr->error;
+    if (e & ERR_POOL) {
+        // some insertions found the pool full and will retry: grow it now
+        HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
+        c->hctr->error &= ~ERR_POOL;
+        e &= ~ERR_POOL;
+        int rc = grow_tets(c, (uint64_t)c->tcap + c->tcap / 2 + 4096);
+        if (rc) return rc;
+    }
+    if (!e) return DT_OK;
+    if (e & ERR_CAPACITY) return fail(c, DT_E_CAPACITY, "tetrahedron pool exhausted inside a round");
+    if (e & ERR_WALK) return fail(c, DT_E_INTERNAL, "point location or ball construction did not terminate");
+    return fail(c, DT_E_INTERNAL, "device error flags 0x%x", e);
+}
+
+void accumulate_timing(dt_ctx *c) {
+    if (!c->opt.timing) return;
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, c->ev[0], c->ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&b, c->ev[1], c->ev[2]) == hipSuccess) {
+        c->st.ms_cavity_kernel += a;
+        c->st.ms_ball_kernel += b;
+        c->st.cavity_launches++;
+        c->st.ball_launches++;
+    } else {
+        hipGetLastError();
+    }
+}
+
+// one round over the candidate list `ci`; losers go to `ni`, overflows to `oi`
+int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t capC, uint32_t capF) {
+    Ctr *d = c->ctr;
+    RoundArgs a{};
+    a.V = c->V.p;
+    a.tv = c->tv;
+    a.tn = c->tn;
+    a.owner = c->owner;
+    a.vtet = c->vtet.p;
+    a.anchor = c->anchor.p;
+    a.cand_pt = c->lpt[ci];
+    a.cand_rank = c->lrank[ci];
+    a.next_pt = c->lpt[ni];
+    a.next_rank = c->lrank[ni];
+    a.ovf_pt = c->lpt[oi];
+    a.ovf_rank = c->lrank[oi];
+    a.ncand_ptr = &d->list_count[ci];
+    a.nnext_ptr = &d->list_count[ni];
+    a.novf_ptr = &d->list_count[oi];
+    a.cav = c->cav;
+    a.bnd = c->bnd;
+    a.outc = c->outc;
+    a.cnt = c->cnt;
+    a.status = c->status;
+    a.fl_cur = c->fl[c->fl_idx];
+    a.fl_next = c->fl[c->fl_idx ^ 1];
+    a.ctr = d;
+    a.stride = std::max<uint32_t>(max_cand, 1);
+    a.capC = capC;
+    a.capF = capF;
+    a.tcap = c->tcap;
+    a.round_hi = (0xFFFFFFFFull - (c->round_counter & 0xFFFFFFFFull)) << 32;
+    c->round_counter++;
+    HIPCHK(launch_round(a, max_cand, c->stream, c->opt.timing ? c->ev : nullptr));
+    HIPCHK(launch_round_end(a, max_cand, false, c->stream));
+    c->fl_idx ^= 1;
+    int rc = sync_ctr(c);
+    if (rc) return rc;
+    if (max_cand) accumulate_timing(c);
+    c->st.rounds++;
+    return check_errors(c);
+}
+
+// Grow the pool ahead of a round when the expected consumption would not fit; an
+// insertion that still finds the pool full retries in the next round.
+int ensure_capacity_for(dt_ctx *c, uint32_t max_cand, uint32_t capF) {
+    const uint64_t per = std::min<uint64_t>(capF, 48);
+    uint64_t need = (uint64_t)c->hctr->tet_count + (uint64_t)max_cand * per + 16;
+    if (need <= c->tcap) return DT_OK;
+    return grow_tets(c, need + need / 8);
+}
+
+// rounds with enlarged per-insertion buffers for candidates whose cavities overflowed
+int drain_overflow(dt_ctx *c) {
+    uint32_t prev_count = 0, prev_cap = 0;
+    while (c->hctr->list_count[2 + c->ovf_idx] > 0) {
+        const int ci = 2 + c->ovf_idx, ni = 2 + (c->ovf_idx ^ 1);
+        const uint32_t cnt = c->hctr->list_count[ci];
+        const uint32_t capC = (uint32_t)std::min<size_t>(c->bufC / cnt, 1u << 24);
+        const uint32_t capF = (uint32_t)std::min<size_t>(c->bufF / cnt, 1u << 24);
+        if (cnt >= prev_count && capC <= prev_cap && prev_count)
+            return fail(c, DT_E_CAPACITY, "a cavity exceeds the per-insertion buffer (%u tetrahedra)", capC);
+        prev_count = cnt;
+        prev_cap = capC;
+        int rc = ensure_capacity_for(c, cnt, capF);
+        if (rc) return rc;
+        const uint32_t won0 = c->hctr->won;
+        rc = run_one_round(c, ci, ni, ni, cnt, capC, capF);
+        if (rc) return rc;
+        c->mesh_vertices += c->hctr->won - won0;
+        c->ovf_idx ^= 1;
+    }
+    return DT_OK;
+}
+
+int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start_global, const uint32_t *d_size,
+               const uint32_t *d_bits, const unsigned long long *d_rank_base) {
+    const uint32_t rmax = c->list_cap;
+    const double frac = c->opt.round_fraction > 0 ? c->opt.round_fraction : DEFAULT_ROUND_FRACTION;
+    uint64_t next_rank = 0;
+    uint64_t rounds_this_call = 0;
+    for (;;) {
+        const int ci = c->list_idx, ni = ci ^ 1, oi = 2 + c->ovf_idx;
+        const uint32_t nl = c->hctr->list_count[ci];
+        uint64_t target = (uint64_t)std::llround(frac * (double)c->mesh_vertices);
+        if (c->opt.round_size) target = c->opt.round_size;
+        target = std::max<uint64_t>(target, ROUND_MIN);
+        target = std::min<uint64_t>(target, rmax);
+        uint32_t W = 0;
+        if (next_rank < lv.total_ranks && target > nl)
+            W = (uint32_t)std::min<uint64_t>(target - nl, lv.total_ranks - next_rank);
+        if (nl == 0 && W == 0) break;
+        if (c->opt.max_rounds && rounds_this_call >= c->opt.max_rounds)
+            return fail(c, DT_E_INCOMPLETE, "round limit %u reached", c->opt.max_rounds);
+        HIPCHK(launch_fill_list(d_start_global, d_size, d_bits, d_rank_base, lv.L, next_rank, W, c->dup.p,
+                                c->vtet.p, c->lpt[ci], c->lrank[ci], &c->ctr->list_count[ci], c->stream));
+        next_rank += W;
+        const uint32_t max_cand = nl + W;
+        int rc = ensure_capacity_for(c, max_cand, c->capF);
+        if (rc) return rc;
+        const uint32_t won0 = c->hctr->won;
+        rc = run_one_round(c, ci, ni, oi, max_cand, c->capC, c->capF);
+        if (rc) return rc;
+        c->mesh_vertices += c->hctr->won - won0;
+        c->list_idx = ni;
+        ++rounds_this_call;
+        rc = drain_overflow(c);
+        if (rc) return rc;
+    }
+    return DT_OK;
+}
+
+void compute_levels(const std::vector<uint32_t> &hist, int L, uint64_t base, Levels &lv) {
+    lv.L = L;
+    lv.start_local.assign(L + 1, 0);
+    lv.start_global.assign(L + 1, 0);
+    lv.size.assign(L, 0);
+    lv.bits.assign(L, 0);
+    lv.prev.assign(L, NONE);
+    lv.rank_base.assign(L + 1, 0);
+    uint64_t acc = 0;
+    for (int k = 0; k < L; ++k) {
+        lv.start_local[k] = (uint32_t)acc;
+        lv.start_global[k] = (uint32_t)(base + acc);
+        lv.size[k] = hist[k];
+        acc += hist[k];
+        uint32_t b = 0;
+        while ((1ull << b) < hist[k]) ++b;
+        lv.bits[k] = b;
+        lv.rank_base[k + 1] = lv.rank_base[k] + (1ull << b);
+    }
+    lv.start_local[L] = (uint32_t)acc;
+    lv.start_global[L] = (uint32_t)(base + acc);
+    int last = -1;
+    for (int k = 0; k < L; ++k) {
+        lv.prev[k] = last < 0 ? NONE : (uint32_t)last;
+        if (hist[k]) last = k;
+    }
+    lv.total_ranks = lv.rank_base[L];
+}
+
+// Moore keys + BRIO levels + radix sort of the n points at dxyz; leaves the sorted keys in
+// *skeys and the sorted input indices in *svals
+int sort_points(dt_ctx *c, const double *dxyz, uint64_t n, int *m_out, std::vector<uint64_t> &cum,
+                unsigned long long **skeys, uint32_t **svals, bool *bad_input) {
+    *bad_input = false;
+    const int m = moore_level(n);
+    cum = brio_cum(n);
+    const int L = (int)cum.size();
+    int rc;
+    if ((rc = ensure(c, c->keys, n)) || (rc = ensure(c, c->keys_tmp, n)) || (rc = ensure(c, c->vals, n)) ||
+        (rc = ensure(c, c->vals_tmp, n)) || (rc = ensure(c, c->hist, radix_hist_entries(n))) ||
+        (rc = ensure(c, c->scan_tmp, scan_tmp_entries(radix_hist_entries(n)) + scan_tmp_entries(n) + 64)) ||
+        (rc = ensure(c, c->bbox, 6 * 1024 + 6)) || (rc = ensure(c, c->small64, 256)))
+        return rc;
+    HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
+    const int nblocks = (int)std::min<uint64_t>((n + 255) / 256, 1024);
+    HIPCHK(launch_validate_bbox(dxyz, n, c->bbox.p, nblocks, c->bbox.p + 6 * 1024, &c->ctr->error, c->stream));
+    int r = sync_ctr(c);
+    if (r) return r;
+    if (c->hctr->error & ERR_INPUT) {
+        *bad_input = true;
+        return DT_OK;
+    }
+    HIPCHK(hipMemcpyAsync(c->small64.p, cum.data(), L * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+    const uint64_t salt = host_mix64(c->opt.seed ^ 0x5851F42D4C957F2Dull);
+    HIPCHK(launch_keys(dxyz, n, c->bbox.p + 6 * 1024, m, salt, c->small64.p, L, c->keys.p, c->vals.p, c->stream));
+    int lbits = 0;
+    while ((1 << lbits) < L) ++lbits;
+    bool swapped = false;
+    HIPCHK(radix_sort_pairs(c->keys.p, c->vals.p, c->keys_tmp.p, c->vals_tmp.p, c->hist.p, c->scan_tmp.p, n,
+                            3 * m + lbits, c->stream, &swapped));
+    *skeys = swapped ? c->keys_tmp.p : c->keys.p;
+    *svals = swapped ? c->vals_tmp.p : c->vals.p;
+    *m_out = m;
+    return DT_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+void dt_default_options(dt_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->stream = nullptr;
+    o->seed = 0x5EED;
+}
+
+int dt_create(dt_ctx **out, const dt_options *opt) {
+    if (!out) return DT_E_ARG;
+    *out = nullptr;
+    dt_ctx *c = new (std::nothrow) dt_ctx();
+    if (!c) return DT_E_CAPACITY;
+    if (opt) c->opt = *opt;
+    else dt_default_options(&c->opt);
+    if (c->opt.round_fraction < 0 || c->opt.round_fraction > 64) {
+        delete c;
+        return DT_E_ARG;
+    }
+    c->device = c->opt.device;
+    if (hipSetDevice(c->device) != hipSuccess) {
+        hipGetLastError();
+        delete c;
+        return DT_E_DEVICE;
+    }
+    int rc = DT_OK;
+    if (c->opt.stream) {
+        c->stream = (hipStream_t)c->opt.stream;
+    } else if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess) {
+        c->own_stream = true;
+    } else {
+        rc = DT_E_DEVICE;
+    }
+    c->capC = c->opt.cavity_cap ? c->opt.cavity_cap : DEFAULT_CAVITY_CAP;
+    c->capF = 2 * c->capC;
+    if (!rc && (hipMalloc((void **)&c->ctr, sizeof(Ctr)) != hipSuccess ||
+                hipHostMalloc((void **)&c->hctr, sizeof(Ctr), hipHostMallocDefault) != hipSuccess))
+        rc = DT_E_DEVICE;
+    for (int k = 0; k < 3 && !rc; ++k)
+        if (hipEventCreate(&c->ev[k]) != hipSuccess) rc = DT_E_DEVICE;
+    if (!rc && (hipMemsetAsync(c->ctr, 0, sizeof(Ctr), c->stream) != hipSuccess ||
+                hipStreamSynchronize(c->stream) != hipSuccess))
+        rc = DT_E_DEVICE;
+    if (rc) {
+        hipGetLastError();
+        dt_destroy(c);
+        return rc;
+    }
+    std::memset(c->hctr, 0, sizeof(Ctr));
+    *out = c;
+    return DT_OK;
+}
+
+int dt_insert_points(dt_ctx *c, const double *xyz, uint64_t n) {
+    if (!c) return DT_E_ARG;
+    if (n == 0) return DT_OK;
+    if (!xyz) return fail(c, DT_E_ARG, "xyz is NULL");
+    if (c->nv + n >= (1ull << 31) || c->npoints + n >= (1ull << 32) - 2)
+        return fail(c, DT_E_CAPACITY, "too many points (limit 2^31 vertices)");
+    auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    const double *dxyz = xyz;
+    if (!is_device_ptr(xyz)) {
+        if ((rc = ensure(c, c->staging, 3 * n))) return rc;
+        HIPCHK(hipMemcpyAsync(c->staging.p, xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        dxyz = c->staging.p;
+    }
+    const uint64_t base = c->nv;
+    if ((rc = ensure(c, c->V, base + n, true)) || (rc = ensure(c, c->vtet, base + n, true)) ||
+        (rc = ensure(c, c->anchor, base + n, true)) || (rc = ensure(c, c->dup, base + n, true)))
+        return rc;
+    // 1-2. validate, keys, sort
+    int m = 1;
+    std::vector<uint64_t> cum;
+    unsigned long long *skeys = nullptr;
+    uint32_t *svals = nullptr;
+    bool bad = false;
+    if ((rc = sort_points(c, dxyz, n, &m, cum, &skeys, &svals, &bad))) return rc;
+    if (bad) return fail(c, DT_E_INPUT, "a coordinate is not finite or outside 0 or [2^-120, 2^120) in magnitude");
+    const int L = (int)cum.size();
+    // 3. vertex records in sorted order
+    HIPCHK(launch_permute(dxyz, svals, n, base, c->npoints, c->V.p, c->vtet.p, c->dup.p, c->stream));
+    // 4. level sizes
+    if ((rc = ensure(c, c->small, 256))) return rc;
+    HIPCHK(hipMemsetAsync(c->small.p, 0, 64 * sizeof(uint32_t), c->stream));
+    HIPCHK(launch_level_hist(skeys, n, 3 * m, c->small.p, c->stream));
+    std::vector<uint32_t> hist(64);
+    HIPCHK(hipMemcpyAsync(hist.data(), c->small.p, 64 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    // 5. duplicates
+    uint64_t tsize = 1;
+    while (tsize < 2 * n) tsize <<= 1;
+    if ((rc = ensure(c, c->table, tsize))) return rc;
+    HIPCHK(hipMemsetAsync(&c->ctr->dups, 0, sizeof(uint32_t), c->stream));
+    HIPCHK(launch_dedupe(c->V.p, base, n, c->table.p, tsize, c->dup.p, &c->ctr->dups, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    Levels lv;
+    compute_levels(hist, L, base, lv);
+    // 6. initial tetrahedron
+    if (!c->have_mesh) {
+        if (c->tcap == 0 || c->tcap < 7 * n + 4096) {
+            uint64_t want = c->opt.capacity_tets ? c->opt.capacity_tets : (uint64_t)(6.9 * (double)n) + 65536;
+            if (c->tcap) {
+                hipFree(c->tv); hipFree(c->tn); hipFree(c->owner); hipFree(c->fl[0]); hipFree(c->fl[1]);
+                c->tcap = 0;
+            }
+            if ((rc = grow_tets(c, std::max<uint64_t>(want, 4096)))) return rc;
+        }
+        HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
+        HIPCHK(launch_init(c->V.p, (uint32_t)base, (uint32_t)n, c->dup.p, c->tv, c->tn, c->vtet.p, c->ctr, c->stream));
+        if ((rc = sync_ctr(c))) return rc;
+        if (c->hctr->error & ERR_DEGENERATE)
+            return fail(c, DT_E_DEGENERATE, "fewer than four affinely independent distinct points");
+        c->init_v0 = c->hctr->init[0];
+        c->mesh_vertices = 4;
+    }
+    // 7. anchors
+    uint32_t *d_sl, *d_sg, *d_size, *d_bits, *d_prev;
+    unsigned long long *d_rb;
+    if ((rc = upload_levels(c, lv, &d_sl, &d_sg, &d_size, &d_bits, &d_prev, &d_rb))) return rc;
+    HIPCHK(launch_anchor(skeys, n, base, m, d_sl, d_prev, L, c->init_v0, c->anchor.p, c->stream));
+    if ((rc = sync_ctr(c))) return rc;
+    c->st.duplicates += c->hctr->dups;
+    auto t1 = std::chrono::steady_clock::now();
+    // 8. insertion rounds
+    c->have_mesh = true;
+    c->nv = base + n;
+    c->npoints += n;
+    c->st.points += n;
+    const uint64_t want_r = c->opt.round_size ? c->opt.round_size : DEFAULT_ROUND_MAX;
+    if ((rc = ensure_round_buffers(c, (uint32_t)std::min<uint64_t>(want_r, std::max<uint64_t>(n, ROUND_MIN)))))
+        return rc;
+    rc = run_rounds(c, lv, d_sg, d_size, d_bits, d_rb);
+    auto t2 = std::chrono::steady_clock::now();
+    c->st.ms_sort += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    c->st.ms_insert += std::chrono::duration<double, std::milli>(t2 - t1).count();
+    c->st.ms_total += std::chrono::duration<double, std::milli>(t2 - t0).count();
+    return rc;
+}
+
+int dt_get_tets(dt_ctx *c, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets) {
+    if (!c || !num_tets) return DT_E_ARG;
+    HIPCHK(hipSetDevice(c->device));
+    if (!c->have_mesh) {
+        *num_tets = 0;
+        return DT_OK;
+    }
+    int rc;
+    const uint32_t count = c->hctr->tet_count;
+    if ((rc = ensure(c, c->oflags, count)) || (rc = ensure(c, c->omap, count + 1)) ||
+        (rc = ensure(c, c->scan_tmp, scan_tmp_entries(count) + 64)))
+        return rc;
+    HIPCHK(launch_output_flags(c->tv, count, c->oflags.p, c->stream));
+    HIPCHK(exclusive_scan_u32(c->oflags.p, c->omap.p, count, c->scan_tmp.p, c->omap.p + count, c->stream));
+    uint32_t T = 0;
+    HIPCHK(hipMemcpyAsync(&T, c->omap.p + count, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->st.tets = T;
+    if (!tets && !nbrs) {
+        *num_tets = T;
+        return DT_OK;
+    }
+    if (*num_tets < T) {
+        *num_tets = T;
+        return fail(c, DT_E_ARG, "output buffers hold %llu tetrahedra, %u needed", (unsigned long long)*num_tets, T);
+    }
+    *num_tets = T;
+    const bool dev_t = tets && is_device_ptr(tets), dev_n = nbrs && is_device_ptr(nbrs);
+    uint32_t *ot = tets;
+    int64_t *on = nbrs;
+    if (tets && !dev_t) {
+        if ((rc = ensure(c, c->otets, 4 * (size_t)T + 4))) return rc;
+        ot = c->otets.p;
+    }
+    if (nbrs && !dev_n) {
+        if ((rc = ensure(c, c->onbrs, 4 * (size_t)T + 4))) return rc;
+        on = c->onbrs.p;
+    }
+    HIPCHK(launch_output(c->tv, c->tn, c->V.p, c->omap.p, count, ot, on, c->stream));
+    if (tets && !dev_t)
+        HIPCHK(hipMemcpyAsync(tets, ot, 4 * (size_t)T * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    if (nbrs && !dev_n)
+        HIPCHK(hipMemcpyAsync(nbrs, on, 4 * (size_t)T * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DT_OK;
+}
+
+int dt_clear(dt_ctx *c) {
+    if (!c) return DT_E_ARG;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipMemsetAsync(c->ctr, 0, sizeof(Ctr), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::memset(c->hctr, 0, sizeof(Ctr));
+    c->npoints = c->nv = 0;
+    c->have_mesh = false;
+    c->mesh_vertices = 0;
+    c->fl_idx = c->list_idx = c->ovf_idx = 0;
+    c->st = dt_stats{};
+    return DT_OK;
+}
+
+int dt_destroy(dt_ctx *c) {
+    if (!c) return DT_E_ARG;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    auto f = [](void *p) { if (p) hipFree(p); };
+    f(c->V.p); f(c->vtet.p); f(c->anchor.p); f(c->dup.p);
+    f(c->tv); f(c->tn); f(c->owner); f(c->fl[0]); f(c->fl[1]);
+    for (int k = 0; k < 4; ++k) { f(c->lpt[k]); f(c->lrank[k]); }
+    f(c->cav); f(c->bnd); f(c->outc); f(c->cnt); f(c->status);
+    f(c->ctr);
+    if (c->hctr) hipHostFree(c->hctr);
+    f(c->staging.p); f(c->keys.p); f(c->keys_tmp.p); f(c->table.p); f(c->vals.p); f(c->vals_tmp.p);
+    f(c->hist.p); f(c->scan_tmp.p); f(c->small.p); f(c->bbox.p); f(c->small64.p);
+    f(c->oflags.p); f(c->omap.p); f(c->otets.p); f(c->onbrs.p);
+    for (int k = 0; k < 3; ++k)
+        if (c->ev[k]) hipEventDestroy(c->ev[k]);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    hipGetLastError();
+    delete c;
+    return DT_OK;
+}
+
+int dt_get_stats(const dt_ctx *c, dt_stats *out) {
+    if (!c || !out) return DT_E_ARG;
+    *out = c->st;
+    const Ctr &h = *c->hctr;
+    out->vertices = c->mesh_vertices;
+    out->attempts = h.attempts;
+    out->inserted = h.won;
+    out->conflicts = h.conflicts;
+    out->overflows = h.overflows;
+    out->walk_steps = h.walk_steps;
+    out->cavity_tets = h.cav_tets;
+    out->boundary_facets = h.bnd_facets;
+    out->orient_calls = h.orient;
+    out->orient_exact = h.orient_exact;
+    out->insphere_calls = h.insphere;
+    out->insphere_exact = h.insphere_exact;
+    out->perturbed = h.perturbed;
+    out->cavity_units = h.attempts;
+    out->ball_units = h.won;
+    return DT_OK;
+}
+
+const char *dt_last_error(const dt_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+int dt_debug_sort(dt_ctx *c, const double *xyz, uint64_t n, uint64_t *keys, uint32_t *perm, int *moore_m) {
+    if (!c || !xyz || n == 0) return DT_E_ARG;
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    const double *dxyz = xyz;
+    if (!is_device_ptr(xyz)) {
+        if ((rc = ensure(c, c->staging, 3 * n))) return rc;
+        HIPCHK(hipMemcpyAsync(c->staging.p, xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        dxyz = c->staging.p;
+    }
+    int m = 1;
+    std::vector<uint64_t> cum;
+    unsigned long long *sk = nullptr;
+    uint32_t *sv = nullptr;
+    bool bad = false;
+    // keys in input order are recomputed into the tmp buffer after the sort
+    if ((rc = sort_points(c, dxyz, n, &m, cum, &sk, &sv, &bad))) return rc;
+    if (bad) return fail(c, DT_E_INPUT, "a coordinate is not finite or outside the accepted range");
+    if (perm) HIPCHK(hipMemcpyAsync(perm, sv, n * sizeof(uint32_t), hipMemcpyDefault, c->stream));
+    if (keys) {
+        // unsorted keys: recompute into the buffer the sort did not leave its result in
+        unsigned long long *kk = (sk == c->keys.p) ? c->keys_tmp.p : c->keys.p;
+        uint32_t *vv = (sv == c->vals.p) ? c->vals_tmp.p : c->vals.p;
+        const uint64_t salt = host_mix64(c->opt.seed ^ 0x5851F42D4C957F2Dull);
+        HIPCHK(launch_keys(dxyz, n, c->bbox.p + 6 * 1024, m, salt, c->small64.p, (int)cum.size(), kk, vv, c->stream));
+        HIPCHK(hipMemcpyAsync(keys, kk, n * sizeof(uint64_t), hipMemcpyDefault, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (moore_m) *moore_m = m;
+    return DT_OK;
+}
+
+int dt_debug_predicates(dt_ctx *c, int kind, const double *pts, const int64_t *idx, uint64_t k, int8_t *out) {
+    if (!c || !pts || !out || kind < 0 || kind > 2 || (kind == 2 && !idx)) return DT_E_ARG;
+    if (k == 0) return DT_OK;
+    HIPCHK(hipSetDevice(c->device));
+    const int np = kind == 0 ? 4 : 5;
+    double *dp = nullptr;
+    int64_t *di = nullptr;
+    int8_t *dout = nullptr;
+    HIPCHK(hipMalloc((void **)&dp, k * np * 3 * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&dout, k));
+    if (kind == 2) HIPCHK(hipMalloc((void **)&di, k * 5 * sizeof(int64_t)));
+    HIPCHK(hipMemcpyAsync(dp, pts, k * np * 3 * sizeof(double), hipMemcpyDefault, c->stream));
+    if (kind == 2) HIPCHK(hipMemcpyAsync(di, idx, k * 5 * sizeof(int64_t), hipMemcpyDefault, c->stream));
+    HIPCHK(launch_predicates(kind, dp, di, k, dout, c->stream));
+    HIPCHK(hipMemcpyAsync(out, dout, k, hipMemcpyDefault, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    hipFree(dp);
+    hipFree(dout);
+    if (di) hipFree(di);
+    return DT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,610 @@
+// Concurrent Bowyer-Watson insertion rounds (paper Sec. 2.1 Algorithm 1, Sec. 2.5, Sec. 2.6;
+// concurrency rules of Sec. 3.2).
+//
+// One thread per candidate point.  A round is three kernels:
+//   k_cavity : Walk (visibility walk, Sec. 2.1) from a live tetrahedron near the point's
+//              curve anchor, then Cavity (breadth-first search by perturbed insphere,
+//              ghosts by the half-space + circumdisk rule of Sec. 2.6).  Every tetrahedron
+//              the search touches is claimed with atomicMin on its 64-bit owner word:
+//              stamp S = (round part, 2 rank) for cavity tetrahedra, S + 1 for tetrahedra
+//              found outside.  Meeting a lower stamp ends the attempt at once.
+//   k_ball   : an attempt wins iff every tetrahedron it touched still holds its stamp, so
+//              the cavities of winners are disjoint from each other and from each other's
+//              adjacent tetrahedra (rules 1a-1c and 2 of Sec. 3.2); the lowest rank in a
+//              round always wins, so every round makes progress.  A winner builds
+//              DelaunayBall (Sec. 2.5): one tetrahedron per boundary facet, glued a priori to
+//              the outer tetrahedron, and glued to its three sibling tetrahedra by pivoting
+//              around each boundary edge through the (still intact) cavity tetrahedra.  Freed
+//              slots are reused in later rounds (Sec. 2.5 end, Sec. 3.6).
+//   k_compact: losers are queued for the next round with their rank; overflowing
+//              cavities are queued for a round with larger per-insertion buffers.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dt_internal.h"
+#include "dt_predicates.h"
+
+namespace dtk {
+
+constexpr uint32_t WALK_LIMIT = 1u << 20;
+
+__device__ __forceinline__ P3 vpos(const Vert *V, uint32_t v) {
+    Vert r = V[v];
+    return {r.x, r.y, r.z};
+}
+
+__device__ __forceinline__ uint32_t comp(uint4 q, int k) {
+    return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w));
+}
+
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void add_stat(unsigned long long *dst, unsigned v) {
+    unsigned s = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, (unsigned long long)s);
+}
+
+// Orders a tetrahedron built from outer tetrahedron vertices w (w[j] replaced by the new
+// point): one transposition restores positive orientation; a ghost vertex is then moved to
+// slot 3 by an even permutation.  Returns the slot of the new point.
+__device__ __forceinline__ int orient_new_tet(uint32_t w[4], int j) {
+    int a = (j + 1) & 3, b = (j + 2) & 3;
+    uint32_t t = w[a]; w[a] = w[b]; w[b] = t;
+    int pf = j;
+    int g = -1;
+    for (int i = 0; i < 3; ++i)
+        if (w[i] == GHOST) g = i;
+    if (g >= 0) {
+        int x = -1, y = -1;
+        for (int i = 0; i < 3; ++i)
+            if (i != g) { if (x < 0) x = i; else y = i; }
+        t = w[g]; w[g] = w[3]; w[3] = t;
+        t = w[x]; w[x] = w[y]; w[y] = t;
+        if (pf == 3) pf = g;
+        else if (pf == x) pf = y;
+        else if (pf == y) pf = x;
+    }
+    return pf;
+}
+
+// ------------------------------------------------------------------ initial tetrahedron
+
+__global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, const uint8_t *__restrict__ dup,
+                       uint4 *__restrict__ tv, uint4 *__restrict__ tn, uint32_t *__restrict__ vtet,
+                       Ctr *__restrict__ ctr) {
+    __shared__ uint32_t sel[4];
+    __shared__ uint32_t best;
+    PredStats st;
+    for (int stage = 0; stage < 4; ++stage) {
+        if (threadIdx.x == 0) best = NONE;
+        __syncthreads();
+        for (uint32_t chunk = 0; chunk < n; chunk += blockDim.x) {
+            uint32_t i = chunk + threadIdx.x;
+            bool ok = i < n && !dup[base + i];
+            for (int s = 0; s < stage && ok; ++s) ok = sel[s] != base + i;
+            if (ok && stage == 2) ok = !collinear(vpos(V, sel[0]), vpos(V, sel[1]), vpos(V, base + i));
+            if (ok && stage == 3)
+                ok = orient3d(vpos(V, sel[0]), vpos(V, sel[1]), vpos(V, sel[2]), vpos(V, base + i), st) != 0;
+            if (ok) atomicMin(&best, i);
+            __syncthreads();
+            if (best != NONE) break;
+            __syncthreads();
+        }
+        if (best == NONE) {
+            if (threadIdx.x == 0) atomicOr(&ctr->error, ERR_DEGENERATE);
+            return;
+        }
+        if (threadIdx.x == 0) sel[stage] = base + best;
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    uint32_t v[4] = {sel[0], sel[1], sel[2], sel[3]};
+    if (orient3d(vpos(V, v[0]), vpos(V, v[1]), vpos(V, v[2]), vpos(V, v[3]), st) < 0) {
+        uint32_t t = v[0]; v[0] = v[1]; v[1] = t;
+    }
+    uint32_t T[5][4], N[5][4];
+    for (int k = 0; k < 4; ++k) T[0][k] = v[k];
+    for (int j = 0; j < 4; ++j) {
+        uint32_t w[4] = {v[0], v[1], v[2], v[3]};
+        w[j] = GHOST;
+        orient_new_tet(w, j);  // G ends in slot 3: finite facet (w0,w1,w2) faces outward
+        for (int k = 0; k < 4; ++k) T[1 + j][k] = w[k];
+        N[0][j] = ((1u + j) << 2) | 3u;
+        N[1 + j][3] = (0u << 2) | (uint32_t)j;
+    }
+    // ghost-ghost adjacencies: facets through G with the same three vertices
+    for (int g1 = 1; g1 < 5; ++g1)
+        for (int f1 = 0; f1 < 3; ++f1)
+            for (int g2 = 1; g2 < 5; ++g2) {
+                if (g2 == g1) continue;
+                for (int f2 = 0; f2 < 3; ++f2) {
+                    int same = 0;
+                    for (int i = 0; i < 4; ++i) {
+                        if (i == f1) continue;
+                        for (int k = 0; k < 4; ++k)
+                            if (k != f2 && T[g2][k] == T[g1][i]) same++;
+                    }
+                    if (same == 3) N[g1][f1] = ((uint32_t)g2 << 2) | (uint32_t)f2;
+                }
+            }
+    for (int t = 0; t < 5; ++t) {
+        tv[t] = make_uint4(T[t][0], T[t][1], T[t][2], T[t][3]);
+        tn[t] = make_uint4(N[t][0], N[t][1], N[t][2], N[t][3]);
+    }
+    for (int k = 0; k < 4; ++k) {
+        vtet[v[k]] = 0;
+        ctr->init[k] = v[k];
+    }
+    ctr->tet_count = 5;
+}
+
+hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, uint4 *tv, uint4 *tn,
+                       uint32_t *vtet, Ctr *ctr, hipStream_t s) {
+    k_init<<<1, 256, 0, s>>>(V, base, n, dup, tv, tn, vtet, ctr);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ candidate fill
+
+// Ranks: level k owns ranks [rank_base[k], rank_base[k] + 2^bits[k]); rank r maps to the
+// level position bitreverse(r - rank_base[k]), so any window of consecutive ranks is
+// spread evenly along the level's part of the Moore curve.
+__global__ void k_fill(const uint32_t *__restrict__ lvl_start, const uint32_t *__restrict__ lvl_size,
+                       const uint32_t *__restrict__ lvl_bits, const unsigned long long *__restrict__ rank_base, int L,
+                       unsigned long long first_rank, uint32_t count, const uint8_t *__restrict__ dup,
+                       const uint32_t *__restrict__ vtet, uint32_t *__restrict__ cand_pt,
+                       uint32_t *__restrict__ cand_rank, uint32_t *__restrict__ ncand) {
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    unsigned long long r = first_rank + t;
+    int k = 0;
+    while (k + 1 < L && rank_base[k + 1] <= r) ++k;
+    uint32_t local = (uint32_t)(r - rank_base[k]);
+    uint32_t bits = lvl_bits[k];
+    uint32_t q = bits ? (__brev(local) >> (32 - bits)) : 0u;
+    if (q >= lvl_size[k]) return;
+    uint32_t p = lvl_start[k] + q;
+    if (dup[p] || vtet[p] != NONE) return;
+    uint32_t pos = atomicAdd(ncand, 1u);
+    cand_pt[pos] = p;
+    cand_rank[pos] = (uint32_t)r;
+}
+
+hipError_t launch_fill_list(const uint32_t *lvl_start, const uint32_t *lvl_size, const uint32_t *lvl_bits,
+                            const unsigned long long *rank_base, int L, unsigned long long first_rank,
+                            uint32_t count, const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt,
+                            uint32_t *cand_rank, uint32_t *ncand, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    k_fill<<<(count + 255) / 256, 256, 0, s>>>(lvl_start, lvl_size, lvl_bits, rank_base, L, first_rank, count,
+                                               dup, vtet, cand_pt, cand_rank, ncand);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ walk + cavity + claim
+
+struct TetView {
+    const Vert *V;
+    const uint4 *tv;
+    const uint4 *tn;
+};
+
+// perturbed "P strictly inside the circumsphere of finite tetrahedron w"
+__device__ __forceinline__ bool finite_inside(const Vert *V, uint4 w, P3 P, unsigned long long pidx,
+                                              PredStats &st) {
+    Vert a = V[w.x], b = V[w.y], c = V[w.z], d = V[w.w];
+    return insphere_perturbed({a.x, a.y, a.z}, {b.x, b.y, b.z}, {c.x, c.y, c.z}, {d.x, d.y, d.z}, P, a.idx, b.idx,
+                              c.idx, d.idx, pidx, st) < 0;
+}
+
+// Sec. 2.6: a ghost (a,b,c,G) contains the open half-space beyond abc and abc's circumdisk
+__device__ __forceinline__ bool tet_inside(const RoundArgs &a, uint32_t u, P3 P, unsigned long long pidx,
+                                           PredStats &st) {
+    uint4 w = a.tv[u];
+    if (w.w != GHOST) return finite_inside(a.V, w, P, pidx, st);
+    int o = orient3d(vpos(a.V, w.x), vpos(a.V, w.y), vpos(a.V, w.z), P, st);
+    if (o != 0) return o > 0;
+    uint32_t x = a.tn[u].w >> 2;
+    return finite_inside(a.V, a.tv[x], P, pidx, st);
+}
+
+__global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ncand = *a.ncand_ptr;
+    const uint32_t stride = a.stride;
+    PredStats st;
+    unsigned steps = 0, attempt = 0;
+    if (i < ncand) {
+        attempt = 1;
+        uint8_t status = ST_NONE;
+        const uint32_t p = a.cand_pt[i];
+        const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
+        const Vert pv = a.V[p];
+        const P3 P = {pv.x, pv.y, pv.z};
+        // start: a live tetrahedron of the nearest inserted anchor
+        uint32_t av = a.anchor[p];
+        uint32_t t = a.vtet[av];
+        while (t == NONE) {
+            av = a.anchor[av];
+            t = a.vtet[av];
+        }
+        uint4 w = a.tv[t];
+        if (w.w == GHOST) {
+            t = a.tn[t].w >> 2;
+            w = a.tv[t];
+        }
+        // Walk
+        int entry = -1;
+        bool in_ghost = false;
+        P3 q0, q1, q2, q3;
+        for (;;) {
+            q0 = vpos(a.V, w.x);
+            q1 = vpos(a.V, w.y);
+            q2 = vpos(a.V, w.z);
+            q3 = vpos(a.V, w.w);
+            const uint4 nn = a.tn[t];
+            int moved = -1;
+            const int rot = (int)((p + steps) & 3u);
+            for (int jj = 0; jj < 4; ++jj) {
+                const int j = (jj + rot) & 3;
+                if (j == entry) continue;
+                int o;
+                if (j == 0) o = orient3d(P, q1, q2, q3, st);
+                else if (j == 1) o = orient3d(q0, P, q2, q3, st);
+                else if (j == 2) o = orient3d(q0, q1, P, q3, st);
+                else o = orient3d(q0, q1, q2, P, st);
+                if (o < 0) {
+                    moved = j;
+                    break;
+                }
+            }
+            if (moved < 0) break;
+            const uint32_t code = comp(nn, moved);
+            t = code >> 2;
+            entry = (int)(code & 3u);
+            w = a.tv[t];
+            if (++steps > WALK_LIMIT) {
+                status = ST_ERROR;
+                break;
+            }
+            if (w.w == GHOST) {
+                in_ghost = true;
+                break;
+            }
+        }
+        if (status == ST_NONE && !in_ghost) {
+            const P3 q[4] = {q0, q1, q2, q3};
+            for (int k = 0; k < 4; ++k)
+                if (q[k].x == P.x && q[k].y == P.y && q[k].z == P.z) status = ST_DUP;
+        }
+        uint32_t ncav = 0, nbnd = 0;
+        if (status == ST_NONE) {
+            // Cavity: breadth-first search; cav entries hold (tetrahedron << 2 | facet it was
+            // entered through), which is skipped when the tetrahedron is expanded
+            if (atomicMin(&a.owner[t], S) < S) {
+                status = ST_CONFLICT;
+            } else {
+                a.cav[i] = t << 2;
+                ncav = 1;
+            }
+            for (uint32_t k = 0; k < ncav && status == ST_NONE; ++k) {
+                const uint32_t code = a.cav[(size_t)k * stride + i];
+                const uint32_t c = code >> 2;
+                const int pf = k == 0 ? -1 : (int)(code & 3u);
+                const uint4 cn = a.tn[c];
+                for (int f = 0; f < 4; ++f) {
+                    if (f == pf) continue;
+                    const uint32_t ncode = comp(cn, f);
+                    const uint32_t u = ncode >> 2;
+                    const unsigned long long o1 = atomicMin(&a.owner[u], S + 1);
+                    if (o1 < S) {
+                        status = ST_CONFLICT;
+                        break;
+                    }
+                    if (o1 == S) continue;  // already in this cavity: internal facet
+                    bool inside = false;
+                    if (o1 != S + 1) inside = tet_inside(a, u, P, pv.idx, st);
+                    if (inside) {
+                        if (atomicMin(&a.owner[u], S) < S) {
+                            status = ST_CONFLICT;
+                            break;
+                        }
+                        if (ncav == a.capC) {
+                            status = ST_OVERFLOW;
+                            break;
+                        }
+                        a.cav[(size_t)ncav * stride + i] = ncode;
+                        ++ncav;
+                    } else {
+                        if (nbnd == a.capF) {
+                            status = ST_OVERFLOW;
+                            break;
+                        }
+                        a.bnd[(size_t)nbnd * stride + i] = (c << 2) | (uint32_t)f;
+                        a.outc[(size_t)nbnd * stride + i] = ncode;
+                        ++nbnd;
+                    }
+                }
+            }
+            if (status == ST_NONE) status = ST_CAND;
+        }
+        a.status[i] = status;
+        a.cnt[i] = ncav;
+        a.cnt[stride + i] = nbnd;
+    }
+    add_stat(&a.ctr->attempts, attempt);
+    add_stat(&a.ctr->walk_steps, steps);
+    add_stat(&a.ctr->orient, st.orient);
+    add_stat(&a.ctr->orient_exact, st.orient_exact);
+    add_stat(&a.ctr->insphere, st.insphere);
+    add_stat(&a.ctr->insphere_exact, st.insphere_exact);
+    add_stat(&a.ctr->perturbed, st.perturbed);
+}
+
+// ------------------------------------------------------------------ check + DelaunayBall
+
+// Rotate around the boundary edge (e0,e1) inside the cavity, starting in cavity tetrahedron
+// c through its facet f (which contains the edge), until the next boundary facet; returns
+// the code (new tetrahedron << 2 | facet opposite its vertex outside {e0, e1, p}).
+__device__ uint32_t pivot(const RoundArgs &a, uint32_t c, int f, uint32_t e0, uint32_t e1, uint32_t p,
+                          unsigned long long S, uint32_t limit) {
+    for (uint32_t guard = 0; guard <= limit; ++guard) {
+        const uint4 cv = a.tv[c];
+        const uint32_t v[4] = {cv.x, cv.y, cv.z, cv.w};
+        int xpos = -1;
+        for (int k = 0; k < 4; ++k)
+            if (k != f && v[k] != e0 && v[k] != e1) xpos = k;
+        if (xpos < 0) break;
+        const uint32_t code = reinterpret_cast<const uint32_t *>(a.tn)[4 * (size_t)c + xpos];
+        const uint32_t nt = code >> 2;
+        if (a.owner[nt] == S) {  // another tetrahedron of this cavity
+            c = nt;
+            f = (int)(code & 3u);
+            continue;
+        }
+        const uint4 nv = a.tv[nt];  // the sibling new tetrahedron
+        const uint32_t w[4] = {nv.x, nv.y, nv.z, nv.w};
+        int q2 = -1;
+        for (int k = 0; k < 4; ++k)
+            if (w[k] != e0 && w[k] != e1 && w[k] != p) q2 = k;
+        if (q2 < 0) break;
+        return (nt << 2) | (uint32_t)q2;
+    }
+    atomicOr(&a.ctr->error, ERR_WALK);
+    return 0;
+}
+
+__global__ __launch_bounds__(256) void k_ball(RoundArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ncand = *a.ncand_ptr;
+    const uint32_t stride = a.stride;
+    unsigned won = 0, ncav_w = 0, nbnd_w = 0;
+    if (i < ncand && a.status[i] == ST_CAND) {
+        const uint32_t p = a.cand_pt[i];
+        const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
+        const uint32_t nc = a.cnt[i], nb = a.cnt[stride + i];
+        bool win = true;
+        for (uint32_t k = 0; k < nc && win; ++k) win = a.owner[a.cav[(size_t)k * stride + i] >> 2] == S;
+        for (uint32_t k = 0; k < nb && win; ++k) win = a.owner[a.outc[(size_t)k * stride + i] >> 2] == S + 1;
+        if (!win) {
+            a.status[i] = ST_CONFLICT;
+        } else {
+            // slots: free list of earlier rounds first, then the bump pointer
+            const uint32_t take = atomicAdd(&a.ctr->fl_take, nb);
+            const uint32_t fln = a.ctr->fl_n;
+            const uint32_t from_fl = fln > take ? min(nb, fln - take) : 0u;
+            const uint32_t rest = nb - from_fl;
+            const uint32_t bump = rest ? atomicAdd(&a.ctr->tet_count, rest) : 0u;
+            if (rest && bump + rest > a.tcap) {
+                // pool full: give the slots back (those inside the pool are marked free),
+                // retry next round after the host has grown the pool
+                uint32_t *tv32 = reinterpret_cast<uint32_t *>(a.tv);
+                uint32_t give = from_fl;
+                for (uint32_t k = 0; k < rest; ++k)
+                    if (bump + k < a.tcap) ++give;
+                const uint32_t fb = atomicAdd(&a.ctr->fl_next, give);
+                uint32_t q = 0;
+                for (uint32_t k = 0; k < from_fl; ++k) a.fl_next[fb + q++] = a.fl_cur[take + k];
+                for (uint32_t k = 0; k < rest; ++k)
+                    if (bump + k < a.tcap) {
+                        tv32[4 * (size_t)(bump + k)] = DEAD;
+                        a.fl_next[fb + q++] = bump + k;
+                    }
+                atomicOr(&a.ctr->error, ERR_POOL);
+                a.status[i] = ST_CONFLICT;
+            } else {
+                uint32_t *tn32 = reinterpret_cast<uint32_t *>(a.tn);
+                // 1. create the ball: tetrahedron k on boundary facet k
+                for (uint32_t k = 0; k < nb; ++k) {
+                    const uint32_t slot = k < from_fl ? a.fl_cur[take + k] : bump + (k - from_fl);
+                    const uint32_t bc = a.bnd[(size_t)k * stride + i];
+                    const uint32_t oc = a.outc[(size_t)k * stride + i];
+                    const uint32_t u = oc >> 2;
+                    const int j = (int)(oc & 3u);
+                    const uint4 uw = a.tv[u];
+                    uint32_t w[4] = {uw.x, uw.y, uw.z, uw.w};
+                    w[j] = p;
+                    const int pf = orient_new_tet(w, j);
+                    a.tv[slot] = make_uint4(w[0], w[1], w[2], w[3]);
+                    const uint32_t me = (slot << 2) | (uint32_t)pf;
+                    tn32[4 * (size_t)slot + pf] = oc;             // facet opposite p: outer tetrahedron
+                    tn32[4 * (size_t)u + j] = me;                 // and back
+                    tn32[4 * (size_t)(bc >> 2) + (bc & 3u)] = me;  // cavity side now names the new tetrahedron
+                    a.outc[(size_t)k * stride + i] = me;
+                }
+                // 2. glue the new tetrahedra to each other
+                for (uint32_t k = 0; k < nb; ++k) {
+                    const uint32_t me = a.outc[(size_t)k * stride + i];
+                    const uint32_t slot = me >> 2;
+                    const int pf = (int)(me & 3u);
+                    const uint32_t bc = a.bnd[(size_t)k * stride + i];
+                    const uint4 sw = a.tv[slot];
+                    const uint32_t w[4] = {sw.x, sw.y, sw.z, sw.w};
+                    for (int q = 0; q < 4; ++q) {
+                        if (q == pf) continue;
+                        uint32_t e[2];
+                        int ne = 0;
+                        for (int r = 0; r < 4; ++r)
+                            if (r != q && r != pf) e[ne++] = w[r];
+                        tn32[4 * (size_t)slot + q] = pivot(a, bc >> 2, (int)(bc & 3u), e[0], e[1], p, S, nc + 2);
+                        if (w[q] != GHOST) a.vtet[w[q]] = slot;
+                    }
+                }
+                a.vtet[p] = a.outc[i] >> 2;
+                // 3. free the cavity
+                const uint32_t fb = atomicAdd(&a.ctr->fl_next, nc);
+                uint32_t *tv32 = reinterpret_cast<uint32_t *>(a.tv);
+                for (uint32_t k = 0; k < nc; ++k) {
+                    const uint32_t c = a.cav[(size_t)k * stride + i] >> 2;
+                    tv32[4 * (size_t)c] = DEAD;
+                    a.fl_next[fb + k] = c;
+                }
+                a.status[i] = ST_WON;
+                won = 1;
+                ncav_w = nc;
+                nbnd_w = nb;
+            }
+        }
+    }
+    add_stat(&a.ctr->cav_tets, ncav_w);
+    add_stat(&a.ctr->bnd_facets, nbnd_w);
+    (void)won;
+}
+
+// ------------------------------------------------------------------ round end
+
+__global__ void k_compact(RoundArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ncand = *a.ncand_ptr;
+    if (i >= ncand) return;
+    const uint8_t s = a.status[i];
+    if (s == ST_CONFLICT || s == ST_CAND) {
+        const uint32_t pos = atomicAdd(a.nnext_ptr, 1u);
+        a.next_pt[pos] = a.cand_pt[i];
+        a.next_rank[pos] = a.cand_rank[i];
+        atomicAdd(&a.ctr->conflicts, 1u);
+    } else if (s == ST_OVERFLOW) {
+        const uint32_t pos = atomicAdd(a.novf_ptr, 1u);
+        a.ovf_pt[pos] = a.cand_pt[i];
+        a.ovf_rank[pos] = a.cand_rank[i];
+        atomicAdd(&a.ctr->overflows, 1u);
+    } else if (s == ST_WON) {
+        atomicAdd(&a.ctr->won, 1u);
+    } else if (s == ST_DUP) {
+        atomicAdd(&a.ctr->dups, 1u);
+    } else {
+        atomicOr(&a.ctr->error, ERR_WALK);
+    }
+}
+
+// carry the unused part of this round's free list behind the slots freed this round
+__global__ void k_freelist_carry(RoundArgs a) {
+    const uint32_t fln = a.ctr->fl_n, take = a.ctr->fl_take, nxt = a.ctr->fl_next;
+    if (take >= fln) return;
+    const uint32_t left = fln - take;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < left; k += gridDim.x * blockDim.x)
+        a.fl_next[nxt + k] = a.fl_cur[take + k];
+}
+
+__global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap) {
+    const uint32_t left = ctr->fl_take < ctr->fl_n ? ctr->fl_n - ctr->fl_take : 0u;
+    if (ctr->tet_count > tcap) ctr->tet_count = tcap;  // slots beyond the pool were never used
+    ctr->fl_n = ctr->fl_next + left;
+    ctr->fl_take = 0;
+    ctr->fl_next = 0;
+    *consumed = 0;  // the list this round read from is empty now
+}
+
+hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, hipStream_t s, hipEvent_t *ev) {
+    if (max_cand == 0) return hipSuccess;
+    const unsigned nb = (max_cand + 255) / 256;
+    if (ev) hipEventRecord(ev[0], s);
+    k_cavity<<<nb, 256, 0, s>>>(a);
+    if (ev) hipEventRecord(ev[1], s);
+    k_ball<<<nb, 256, 0, s>>>(a);
+    if (ev) hipEventRecord(ev[2], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, bool big, hipStream_t s) {
+    (void)big;
+    if (max_cand) k_compact<<<(max_cand + 255) / 256, 256, 0, s>>>(a);
+    k_freelist_carry<<<256, 256, 0, s>>>(a);
+    k_roll<<<1, 1, 0, s>>>(a.ctr, const_cast<uint32_t *>(a.ncand_ptr), a.tcap);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ output
+
+__global__ void k_out_flags(const uint4 *__restrict__ tv, uint32_t count, uint32_t *__restrict__ flags) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const uint4 w = tv[t];
+    flags[t] = (w.x != DEAD && w.w != GHOST) ? 1u : 0u;
+}
+
+hipError_t launch_output_flags(const uint4 *tv, uint32_t count, uint32_t *flags, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    k_out_flags<<<(count + 255) / 256, 256, 0, s>>>(tv, count, flags);
+    return hipGetLastError();
+}
+
+__global__ void k_output(const uint4 *__restrict__ tv, const uint4 *__restrict__ tn, const Vert *__restrict__ V,
+                         const uint32_t *__restrict__ map, uint32_t count, uint32_t *__restrict__ tets,
+                         int64_t *__restrict__ nbrs) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const uint4 w = tv[t];
+    if (w.x == DEAD || w.w == GHOST) return;
+    const uint32_t o = map[t];
+    if (tets) {
+        tets[4 * (size_t)o + 0] = (uint32_t)V[w.x].idx;
+        tets[4 * (size_t)o + 1] = (uint32_t)V[w.y].idx;
+        tets[4 * (size_t)o + 2] = (uint32_t)V[w.z].idx;
+        tets[4 * (size_t)o + 3] = (uint32_t)V[w.w].idx;
+    }
+    if (nbrs) {
+        const uint4 nn = tn[t];
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t nt = comp(nn, k) >> 2;
+            nbrs[4 * (size_t)o + k] = tv[nt].w == GHOST ? -1 : (int64_t)map[nt];
+        }
+    }
+}
+
+hipError_t launch_output(const uint4 *tv, const uint4 *tn, const Vert *V, const uint32_t *map, uint32_t count,
+                         uint32_t *tets, int64_t *nbrs, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    k_output<<<(count + 255) / 256, 256, 0, s>>>(tv, tn, V, map, count, tets, nbrs);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ predicate test hook
+
+__global__ void k_predicates(int kind, const double *__restrict__ pts, const int64_t *__restrict__ idx, uint64_t k,
+                             int8_t *__restrict__ out) {
+    const uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (r >= k) return;
+    PredStats st;
+    const int np = kind == 0 ? 4 : 5;
+    P3 q[5];
+    for (int j = 0; j < np; ++j) q[j] = {pts[3 * (np * r + j)], pts[3 * (np * r + j) + 1], pts[3 * (np * r + j) + 2]};
+    int s;
+    if (kind == 0) s = orient3d(q[0], q[1], q[2], q[3], st);
+    else if (kind == 1) s = insphere_raw(q[0], q[1], q[2], q[3], q[4], st);
+    else
+        s = insphere_perturbed(q[0], q[1], q[2], q[3], q[4], (unsigned long long)idx[5 * r],
+                               (unsigned long long)idx[5 * r + 1], (unsigned long long)idx[5 * r + 2],
+                               (unsigned long long)idx[5 * r + 3], (unsigned long long)idx[5 * r + 4], st);
+    out[r] = (int8_t)s;
+}
+
+hipError_t launch_predicates(int kind, const double *pts, const int64_t *idx, uint64_t k, int8_t *out, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    k_predicates<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(kind, pts, idx, k, out);
+    return hipGetLastError();
+}
+
+}  // namespace dtk

@@ -1,0 +1,125 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dtk {
+
+constexpr uint32_t GHOST = 0xFFFFFFFFu;  // ghost vertex id (paper Sec. 2.6); always slot 3
+constexpr uint32_t DEAD = 0xFFFFFFFEu;   // first vertex slot of a freed tetrahedron
+constexpr uint32_t NONE = 0xFFFFFFFFu;   // "no tetrahedron" in the vertex -> tetrahedron hints
+constexpr uint32_t MAX_TETS = (1u << 30) - 1;  // adjacency code 4 t + f must fit 32 bits
+
+// A vertex record: 32 bytes so that one aligned fetch brings a whole vertex (Sec. 2.2,
+// Listing 1); `idx` holds the global input index (the key of the symbolic perturbation).
+struct __align__(32) Vert {
+    double x, y, z;
+    unsigned long long idx;
+};
+
+// candidate status after a round
+enum : uint8_t {
+    ST_NONE = 0,
+    ST_CAND = 1,      // cavity built and claimed, waiting for the check
+    ST_CONFLICT = 2,  // met a claim of a lower-ranked insertion
+    ST_OVERFLOW = 3,  // cavity larger than this round's per-insertion buffer
+    ST_DUP = 4,       // exact duplicate of a vertex already in the mesh
+    ST_WON = 5,       // inserted
+    ST_ERROR = 6      // walk did not terminate (never expected)
+};
+
+enum : uint32_t {
+    ERR_WALK = 1u,
+    ERR_CAPACITY = 2u,
+    ERR_INPUT = 4u,
+    ERR_DEGENERATE = 8u,
+    ERR_POOL = 16u  // not an error: the tetrahedron pool filled up during a round
+};
+
+// Device-resident counters of the round driver.
+struct Ctr {
+    uint32_t list_count[4];  // lengths of the candidate lists (two normal, two overflow)
+    uint32_t fl_n;       // free slots available this round
+    uint32_t fl_take;    // free slots taken this round (may exceed fl_n)
+    uint32_t fl_next;    // slots freed this round
+    uint32_t tet_count;  // bump pointer of the tetrahedron pool
+    uint32_t won;        // insertions this round
+    uint32_t conflicts;  // conflicts this round
+    uint32_t overflows;  // overflows this round
+    uint32_t dups;       // duplicates found this round
+    uint32_t error;      // ERR_* flags
+    uint32_t init[4];    // sorted positions of the initial tetrahedron's vertices
+    uint32_t pad[3];
+    unsigned long long walk_steps, cav_tets, bnd_facets;
+    unsigned long long orient, orient_exact, insphere, insphere_exact, perturbed;
+    unsigned long long attempts;
+};
+
+// Arguments of one insertion round.
+struct RoundArgs {
+    const Vert *V;
+    uint4 *tv;                   // tetrahedron vertices (ghost in slot 3)
+    uint4 *tn;                   // neighbour codes 4 t' + f'
+    unsigned long long *owner;   // claim word per tetrahedron
+    uint32_t *vtet;              // vertex -> a live tetrahedron containing it
+    const uint32_t *anchor;      // vertex -> an earlier vertex near it on the curve
+    const uint32_t *cand_pt;     // current candidate list
+    const uint32_t *cand_rank;
+    uint32_t *next_pt;           // losers for the next round
+    uint32_t *next_rank;
+    uint32_t *ovf_pt;            // overflowed candidates
+    uint32_t *ovf_rank;
+    const uint32_t *ncand_ptr;   // device count of the current list
+    uint32_t *nnext_ptr;         // device count of the next list
+    uint32_t *novf_ptr;          // device count of the overflow list
+    uint32_t *cav;               // [capC][stride] cavity tetrahedra (code 4 t + entry facet)
+    uint32_t *bnd;               // [capF][stride] boundary facets (4 c + f, c in the cavity)
+    uint32_t *outc;              // [capF][stride] outer codes, then new tetrahedra
+    uint32_t *cnt;               // [2][stride] cavity size, boundary size
+    uint8_t *status;             // [stride]
+    uint32_t *fl_cur;            // free list consumed this round
+    uint32_t *fl_next;           // free list filled this round
+    Ctr *ctr;
+    uint32_t stride, capC, capF, tcap;
+    unsigned long long round_hi;  // (0xFFFFFFFF - round) << 32: newer rounds claim lower
+};
+
+// ---- launch wrappers (dt_sort.hip) ----
+hipError_t launch_validate_bbox(const double *xyz, uint64_t n, double *bbox_blocks, int nblocks,
+                                double *bbox_out, uint32_t *err, hipStream_t s);
+hipError_t launch_keys(const double *xyz, uint64_t n, const double *bbox, int m, uint64_t salt,
+                       const uint64_t *cum, int L, unsigned long long *keys, uint32_t *vals,
+                       hipStream_t s);
+hipError_t radix_sort_pairs(unsigned long long *keys, uint32_t *vals, unsigned long long *keys_tmp,
+                            uint32_t *vals_tmp, uint32_t *hist, uint32_t *scan_tmp, uint64_t n,
+                            int nbits, hipStream_t s, bool *swapped);
+size_t radix_hist_entries(uint64_t n);
+hipError_t launch_permute(const double *xyz, const uint32_t *vals, uint64_t n, uint64_t base,
+                          uint64_t idx_offset, Vert *V, uint32_t *vtet, uint8_t *dup, hipStream_t s);
+hipError_t launch_level_hist(const unsigned long long *keys, uint64_t n, int shift, uint32_t *hist,
+                             hipStream_t s);
+hipError_t launch_anchor(const unsigned long long *keys, uint64_t n, uint64_t base, int m,
+                         const uint32_t *lvl_start, const uint32_t *prev_level, int L,
+                         uint32_t fallback, uint32_t *anchor, hipStream_t s);
+hipError_t launch_dedupe(const Vert *V, uint64_t base, uint64_t n, unsigned long long *table,
+                         uint64_t tsize, uint8_t *dup, uint32_t *ndup, hipStream_t s);
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tmp,
+                              uint32_t *total, hipStream_t s);
+size_t scan_tmp_entries(uint64_t n);
+
+// ---- launch wrappers (dt_insert.hip) ----
+hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, uint4 *tv, uint4 *tn,
+                       uint32_t *vtet, Ctr *ctr, hipStream_t s);
+hipError_t launch_fill_list(const uint32_t *lvl_start, const uint32_t *lvl_size, const uint32_t *lvl_bits,
+                            const unsigned long long *rank_base, int L, unsigned long long first_rank,
+                            uint32_t count, const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt,
+                            uint32_t *cand_rank, uint32_t *ncand, hipStream_t s);
+hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, bool big, hipStream_t s);
+hipError_t launch_output_flags(const uint4 *tv, uint32_t count, uint32_t *flags, hipStream_t s);
+hipError_t launch_output(const uint4 *tv, const uint4 *tn, const Vert *V, const uint32_t *map,
+                         uint32_t count, uint32_t *tets, int64_t *nbrs, hipStream_t s);
+hipError_t launch_predicates(int kind, const double *pts, const int64_t *idx, uint64_t k, int8_t *out,
+                             hipStream_t s);
+
+}  // namespace dtk

@@ -1,0 +1,351 @@
+// Exact geometric predicates on the GPU (paper Sec. 2.4 "Implementation details").
+//
+//   orient3d(a,b,c,d) = (b-a).((c-a)x(d-a))                       (Sec. 2.4)
+//   insphere(a,b,c,d,e) = det of rows (x, y, z, |p|^2, 1), a..e    (Sec. 2.4, 5x5 form)
+//                       = det of rows (p-e, |p-e|^2) for p = a,b,c,d (translated form)
+//   For orient3d(a,b,c,d) > 0, e is strictly inside the circumsphere iff insphere < 0.
+//
+// Stage 1: fp64 evaluation in a fixed order plus a dynamic filter.  Every monomial of the
+// expansion passes through at most 8 (orient3d) or 16 (insphere) roundings, so with the
+// unit roundoff u = 2^-53 the absolute error is below gamma_k/(1-gamma_k) times the
+// permanent (the same expansion with absolute values, evaluated alongside).  That factor
+// is < 8.9e-16 (k = 8) and < 1.8e-15 (k = 16); the filter uses 2^-49 and 2^-48, about
+// twice that.  Inputs are restricted to 0 or |x| in [2^-120, 2^120): every difference and
+// product then stays a multiple of 2^(-172 k) at degree k <= 5, far above the underflow
+// threshold, and far below overflow.
+//
+// Stage 2 (when the filter cannot decide): the coordinates are scaled by a common power
+// of two into exact integers and the same determinant is evaluated in two's-complement
+// multi-limb integers modulo 2^(32 W).  W is chosen from the exponent spread of the call
+// so that every true intermediate value fits; the result is then exact.  This replaces
+// the floating-point expansion arithmetic of the CPU implementation: its exact stage
+// needs expansions of up to thousands of doubles per lane, while the integer form is
+// bounded by the exponent spread (at most 47 limbs here) and needs no branches.
+//
+// Stage 3: symbolic perturbation for an exact zero of insphere (Sec. 2.4 item 3): the
+// lifted coordinate of the point with input index i is |p_i|^2 + eps^delta_i, delta
+// strictly decreasing in i.  The determinant is linear in that column, so its perturbed
+// sign is the sign of the first non-zero cofactor (-1)^r orient3d(other four rows),
+// rows r taken by decreasing input index.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dtk {
+
+struct P3 {
+    double x, y, z;
+};
+
+// per-thread predicate counters
+struct PredStats {
+    uint32_t orient = 0, orient_exact = 0, insphere = 0, insphere_exact = 0, perturbed = 0;
+};
+
+// ------------------------------------------------------------------ exact integers
+
+constexpr int LIMBS_MAX = 48;
+
+struct Dyadic {
+    long long m;  // |m| < 2^53
+    int e;        // value = m * 2^e
+};
+
+__device__ inline Dyadic split_dyadic(double x) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    int ex = (int)((b >> 52) & 0x7FF);
+    if (ex == 0) return {0, 0};  // zero (subnormals are outside the accepted range)
+    long long m = (long long)((b & 0xFFFFFFFFFFFFFull) | (1ull << 52));
+    if (b >> 63) m = -m;
+    return {m, ex - 1075};
+}
+
+// r (w limbs) = m * 2^sh, two's complement
+__device__ inline void ei_set(uint32_t *r, int w, long long m, int sh) {
+    for (int i = 0; i < w; ++i) r[i] = 0;
+    unsigned long long mag = m < 0 ? (unsigned long long)(-m) : (unsigned long long)m;
+    int q = sh >> 5, s = sh & 31;
+    unsigned long long lo = mag << s;
+    unsigned long long hi = s ? (mag >> (64 - s)) : 0ull;
+    if (q < w) r[q] = (uint32_t)lo;
+    if (q + 1 < w) r[q + 1] = (uint32_t)(lo >> 32);
+    if (q + 2 < w) r[q + 2] = (uint32_t)hi;
+    if (m < 0) {
+        unsigned long long c = 1;
+        for (int i = 0; i < w; ++i) {
+            unsigned long long t = (unsigned long long)(uint32_t)~r[i] + c;
+            r[i] = (uint32_t)t;
+            c = t >> 32;
+        }
+    }
+}
+
+__device__ inline uint32_t ei_get(const uint32_t *a, int wa, int k) {
+    return k < wa ? a[k] : ((a[wa - 1] >> 31) ? 0xFFFFFFFFu : 0u);
+}
+
+// r = a + s*b (s = +1/-1) modulo 2^(32 w); operands sign-extended
+__device__ inline void ei_addsub(uint32_t *r, int w, const uint32_t *a, int wa, const uint32_t *b,
+                                 int wb, bool sub) {
+    unsigned long long c = sub ? 1ull : 0ull;
+    for (int i = 0; i < w; ++i) {
+        uint32_t bi = ei_get(b, wb, i);
+        if (sub) bi = ~bi;
+        unsigned long long t = (unsigned long long)ei_get(a, wa, i) + bi + c;
+        r[i] = (uint32_t)t;
+        c = t >> 32;
+    }
+}
+
+// r = a * b modulo 2^(32 w); r must not alias a or b
+__device__ inline void ei_mul(uint32_t *r, int w, const uint32_t *a, int wa, const uint32_t *b,
+                              int wb) {
+    for (int i = 0; i < w; ++i) r[i] = 0;
+    for (int i = 0; i < w; ++i) {
+        uint32_t ai = ei_get(a, wa, i);
+        if (ai == 0) continue;
+        unsigned long long c = 0;
+        for (int j = 0; i + j < w; ++j) {
+            unsigned long long t = (unsigned long long)ai * ei_get(b, wb, j) + r[i + j] + c;
+            r[i + j] = (uint32_t)t;
+            c = t >> 32;
+        }
+    }
+}
+
+__device__ inline int ei_sign(const uint32_t *a, int w) {
+    if (a[w - 1] >> 31) return -1;
+    for (int i = 0; i < w; ++i)
+        if (a[i]) return 1;
+    return 0;
+}
+
+// Scale `cnt` coordinates to exact integers with a common exponent; returns the number of
+// bits of the largest magnitude (the exponent spread plus 53).
+__device__ inline int ei_load(const double *v, int cnt, uint32_t (*X)[12], int wx) {
+    Dyadic d[15];
+    int emin = 1 << 20, emax = -(1 << 20);
+    for (int i = 0; i < cnt; ++i) {
+        d[i] = split_dyadic(v[i]);
+        if (d[i].m != 0) {
+            emin = min(emin, d[i].e);
+            emax = max(emax, d[i].e);
+        }
+    }
+    if (emax < emin) emin = emax = 0;
+    for (int i = 0; i < cnt; ++i) ei_set(X[i], wx, d[i].m, d[i].m ? d[i].e - emin : 0);
+    return emax - emin + 54;
+}
+
+// exact sign of orient3d(a,b,c,d)
+__device__ __noinline__ int orient3d_exact(P3 a, P3 b, P3 c, P3 d) {
+    double v[12] = {a.x, a.y, a.z, b.x, b.y, b.z, c.x, c.y, c.z, d.x, d.y, d.z};
+    uint32_t X[12][12];
+    // coordinates: bits <= 53 + 239 + 1 (sign) -> at most 10 limbs
+    int bits = ei_load(v, 12, X, 10);
+    int w1 = (bits + 1 + 31) / 32 + 1;        // differences
+    int w2 = (2 * bits + 3 + 31) / 32 + 1;    // 2x2 minors
+    int w3 = (3 * bits + 6 + 31) / 32 + 1;    // 3x3 determinant
+    w1 = min(w1, 12);
+    w2 = min(w2, 24);
+    w3 = min(w3, 36);
+    uint32_t D[9][12];  // u = b-a, v = c-a, w = d-a
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) ei_addsub(D[3 * r + k], w1, X[3 * (r + 1) + k], 10, X[k], 10, true);
+    // det = u.(v x w) = ux (vy wz - vz wy) + uy (vz wx - vx wz) + uz (vx wy - vy wx)
+    uint32_t t1[24], t2[24], m[24], t3[36], acc[36];
+    for (int i = 0; i < w3; ++i) acc[i] = 0;
+    const int cyc[3][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}};
+    for (int q = 0; q < 3; ++q) {
+        int i = cyc[q][0], j = cyc[q][1], k = cyc[q][2];
+        ei_mul(t1, w2, D[3 + j], w1, D[6 + k], w1);
+        ei_mul(t2, w2, D[3 + k], w1, D[6 + j], w1);
+        ei_addsub(m, w2, t1, w2, t2, w2, true);
+        ei_mul(t3, w3, D[i], w1, m, w2);
+        ei_addsub(acc, w3, acc, w3, t3, w3, false);
+    }
+    return ei_sign(acc, w3);
+}
+
+// exact sign of the lifted determinant, translated by e
+__device__ __noinline__ int insphere_exact(P3 a, P3 b, P3 c, P3 d, P3 e) {
+    double v[15] = {a.x, a.y, a.z, b.x, b.y, b.z, c.x, c.y, c.z, d.x, d.y, d.z, e.x, e.y, e.z};
+    uint32_t X[15][12];
+    int bits = ei_load(v, 15, X, 10);
+    int w1 = min((bits + 1 + 31) / 32 + 1, 11);          // differences
+    int w2 = min((2 * bits + 4 + 31) / 32 + 1, 21);      // minors and lifts
+    int w3 = min((3 * bits + 7 + 31) / 32 + 1, 31);      // 3x3 determinants
+    int w5 = min((5 * bits + 14 + 31) / 32 + 1, 48);     // final sum
+    uint32_t D[12][11];  // rows p - e for p = a, b, c, d
+    for (int r = 0; r < 4; ++r)
+        for (int k = 0; k < 3; ++k) ei_addsub(D[3 * r + k], w1, X[3 * r + k], 10, X[12 + k], 10, true);
+    // D = l_d det3(a,b,c) - l_c det3(a,b,d) + l_b det3(a,c,d) - l_a det3(b,c,d)
+    const int others[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    const bool neg[4] = {true, false, true, false};  // rows a, b, c, d
+    uint32_t t1[21], t2[21], m[21], lift[21], tz[31], det3[31], prod[48], acc[48];
+    for (int i = 0; i < w5; ++i) acc[i] = 0;
+    for (int row = 0; row < 4; ++row) {
+        int p = others[row][0], q = others[row][1], s = others[row][2];
+        // det3(p,q,s) = p_z m(q,s) - q_z m(p,s) + s_z m(p,q),  m(x,y) = x_x y_y - y_x x_y
+        for (int i = 0; i < w3; ++i) det3[i] = 0;
+        const int zr[3] = {p, q, s};
+        const int mr[3][2] = {{q, s}, {p, s}, {p, q}};
+        for (int z = 0; z < 3; ++z) {
+            int x0 = mr[z][0], y0 = mr[z][1];
+            ei_mul(t1, w2, D[3 * x0 + 0], w1, D[3 * y0 + 1], w1);
+            ei_mul(t2, w2, D[3 * y0 + 0], w1, D[3 * x0 + 1], w1);
+            ei_addsub(m, w2, t1, w2, t2, w2, true);
+            ei_mul(tz, w3, D[3 * zr[z] + 2], w1, m, w2);
+            ei_addsub(det3, w3, det3, w3, tz, w3, z == 1);
+        }
+        for (int i = 0; i < w2; ++i) lift[i] = 0;
+        for (int k = 0; k < 3; ++k) {
+            ei_mul(t1, w2, D[3 * row + k], w1, D[3 * row + k], w1);
+            ei_addsub(lift, w2, lift, w2, t1, w2, false);
+        }
+        ei_mul(prod, w5, lift, w2, det3, w3);
+        ei_addsub(acc, w5, acc, w5, prod, w5, neg[row]);
+    }
+    return ei_sign(acc, w5);
+}
+
+// exact test of collinearity of a, b, c (cross product of b-a and c-a is zero)
+__device__ __noinline__ bool collinear_exact(P3 a, P3 b, P3 c) {
+    double v[9] = {a.x, a.y, a.z, b.x, b.y, b.z, c.x, c.y, c.z};
+    uint32_t X[9][12];
+    int bits = ei_load(v, 9, X, 10);
+    int w1 = min((bits + 1 + 31) / 32 + 1, 12);
+    int w2 = min((2 * bits + 3 + 31) / 32 + 1, 24);
+    uint32_t U[3][12], V[3][12], t1[24], t2[24], cr[24];
+    for (int k = 0; k < 3; ++k) {
+        ei_addsub(U[k], w1, X[3 + k], 10, X[k], 10, true);
+        ei_addsub(V[k], w1, X[6 + k], 10, X[k], 10, true);
+    }
+    for (int k = 0; k < 3; ++k) {
+        int i = (k + 1) % 3, j = (k + 2) % 3;
+        ei_mul(t1, w2, U[i], w1, V[j], w1);
+        ei_mul(t2, w2, U[j], w1, V[i], w1);
+        ei_addsub(cr, w2, t1, w2, t2, w2, true);
+        if (ei_sign(cr, w2) != 0) return false;
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------ filtered predicates
+
+// sign of orient3d, or 2 when the fp64 filter cannot decide
+__device__ __forceinline__ int orient3d_filter(P3 a, P3 b, P3 c, P3 d) {
+    double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
+    double vx = c.x - a.x, vy = c.y - a.y, vz = c.z - a.z;
+    double wx = d.x - a.x, wy = d.y - a.y, wz = d.z - a.z;
+    double p1 = vy * wz, p2 = vz * wy, p3 = vz * wx, p4 = vx * wz, p5 = vx * wy, p6 = vy * wx;
+    double det = ux * (p1 - p2) + uy * (p3 - p4) + uz * (p5 - p6);
+    double perm = fabs(ux) * (fabs(p1) + fabs(p2)) + fabs(uy) * (fabs(p3) + fabs(p4)) +
+                  fabs(uz) * (fabs(p5) + fabs(p6));
+    double bound = perm * 0x1p-49;
+    if (det > bound) return 1;
+    if (-det > bound) return -1;
+    if (perm == 0.0) return 0;
+    return 2;
+}
+
+__device__ __forceinline__ int orient3d(P3 a, P3 b, P3 c, P3 d, PredStats &st) {
+    st.orient++;
+    int s = orient3d_filter(a, b, c, d);
+    if (s != 2) return s;
+    st.orient_exact++;
+    return orient3d_exact(a, b, c, d);
+}
+
+// sign of the unperturbed lifted determinant, or 2 when the filter cannot decide
+__device__ __forceinline__ int insphere_filter(P3 a, P3 b, P3 c, P3 d, P3 e) {
+    double ax = a.x - e.x, ay = a.y - e.y, az = a.z - e.z;
+    double bx = b.x - e.x, by = b.y - e.y, bz = b.z - e.z;
+    double cx = c.x - e.x, cy = c.y - e.y, cz = c.z - e.z;
+    double dx = d.x - e.x, dy = d.y - e.y, dz = d.z - e.z;
+    // 2x2 minors m(p,q) = p_x q_y - q_x p_y
+    double ab1 = ax * by, ab2 = bx * ay, ab = ab1 - ab2;
+    double ac1 = ax * cy, ac2 = cx * ay, ac = ac1 - ac2;
+    double ad1 = ax * dy, ad2 = dx * ay, ad = ad1 - ad2;
+    double bc1 = bx * cy, bc2 = cx * by, bc = bc1 - bc2;
+    double bd1 = bx * dy, bd2 = dx * by, bd = bd1 - bd2;
+    double cd1 = cx * dy, cd2 = dx * cy, cd = cd1 - cd2;
+    double pab = fabs(ab1) + fabs(ab2), pac = fabs(ac1) + fabs(ac2), pad = fabs(ad1) + fabs(ad2);
+    double pbc = fabs(bc1) + fabs(bc2), pbd = fabs(bd1) + fabs(bd2), pcd = fabs(cd1) + fabs(cd2);
+    // 3x3 determinants det3(p,q,s) = p_z m(q,s) - q_z m(p,s) + s_z m(p,q)
+    double abc = az * bc - bz * ac + cz * ab;
+    double abd = az * bd - bz * ad + dz * ab;
+    double acd = az * cd - cz * ad + dz * ac;
+    double bcd = bz * cd - cz * bd + dz * bc;
+    double pabc = fabs(az) * pbc + fabs(bz) * pac + fabs(cz) * pab;
+    double pabd = fabs(az) * pbd + fabs(bz) * pad + fabs(dz) * pab;
+    double pacd = fabs(az) * pcd + fabs(cz) * pad + fabs(dz) * pac;
+    double pbcd = fabs(bz) * pcd + fabs(cz) * pbd + fabs(dz) * pbc;
+    double la = ax * ax + ay * ay + az * az;
+    double lb = bx * bx + by * by + bz * bz;
+    double lc = cx * cx + cy * cy + cz * cz;
+    double ld = dx * dx + dy * dy + dz * dz;
+    double det = (ld * abc - lc * abd) + (lb * acd - la * bcd);
+    double perm = (ld * pabc + lc * pabd) + (lb * pacd + la * pbcd);
+    double bound = perm * 0x1p-48;
+    if (det > bound) return 1;
+    if (-det > bound) return -1;
+    if (perm == 0.0) return 0;
+    return 2;
+}
+
+__device__ __forceinline__ int insphere_raw(P3 a, P3 b, P3 c, P3 d, P3 e, PredStats &st) {
+    st.insphere++;
+    int s = insphere_filter(a, b, c, d, e);
+    if (s != 2) return s;
+    st.insphere_exact++;
+    return insphere_exact(a, b, c, d, e);
+}
+
+// sign of the perturbed lifted determinant of rows (a,b,c,d,e), input indices ia..ie;
+// requires orient3d(a,b,c,d) > 0.  -1 means e is inside the circumsphere.
+__device__ __noinline__ int insphere_perturbed_tail(P3 a, P3 b, P3 c, P3 d, P3 e,
+                                                    unsigned long long ia, unsigned long long ib,
+                                                    unsigned long long ic, unsigned long long id,
+                                                    unsigned long long ie, PredStats *st) {
+    P3 p[5] = {a, b, c, d, e};
+    unsigned long long key[5] = {ia, ib, ic, id, ie};
+    bool used[5] = {false, false, false, false, false};
+    for (int q = 0; q < 5; ++q) {
+        int r = -1;
+        for (int i = 0; i < 5; ++i)
+            if (!used[i] && (r < 0 || key[i] > key[r])) r = i;
+        used[r] = true;
+        P3 o[4];
+        int k = 0;
+        for (int i = 0; i < 5; ++i)
+            if (i != r) o[k++] = p[i];
+        int s = orient3d(o[0], o[1], o[2], o[3], *st);
+        if (s != 0) return (r & 1) ? -s : s;
+    }
+    return 1;  // unreachable: row e's cofactor is orient3d(a,b,c,d) > 0
+}
+
+__device__ __forceinline__ int insphere_perturbed(P3 a, P3 b, P3 c, P3 d, P3 e, unsigned long long ia,
+                                                  unsigned long long ib, unsigned long long ic,
+                                                  unsigned long long id, unsigned long long ie,
+                                                  PredStats &st) {
+    int s = insphere_raw(a, b, c, d, e, st);
+    if (s != 0) return s;
+    st.perturbed++;
+    return insphere_perturbed_tail(a, b, c, d, e, ia, ib, ic, id, ie, &st);
+}
+
+// filtered orient2d-free collinearity test used only by the initial tetrahedron search
+__device__ __forceinline__ bool collinear(P3 a, P3 b, P3 c) {
+    double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
+    double vx = c.x - a.x, vy = c.y - a.y, vz = c.z - a.z;
+    double c0a = uy * vz, c0b = uz * vy, c1a = uz * vx, c1b = ux * vz, c2a = ux * vy, c2b = uy * vx;
+    // each component has 4 roundings: error < gamma_4/(1-gamma_4) * (|a|+|b|) < 2^-50 (..)
+    if (fabs(c0a - c0b) > (fabs(c0a) + fabs(c0b)) * 0x1p-50) return false;
+    if (fabs(c1a - c1b) > (fabs(c1a) + fabs(c1b)) * 0x1p-50) return false;
+    if (fabs(c2a - c2b) > (fabs(c2a) + fabs(c2b)) * 0x1p-50) return false;
+    return collinear_exact(a, b, c);
+}
+
+}  // namespace dtk

@@ -1,0 +1,209 @@
+"""Thin ctypes binding of libdt.so (include/dt.h).  Argument marshalling only: every step
+of the triangulation runs in the library's HIP kernels.  PyTorch, when given, only supplies
+device memory (tensor.data_ptr()) and the stream."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdt.so")
+
+DT_OK, DT_E_ARG, DT_E_INPUT, DT_E_DEGENERATE, DT_E_CAPACITY, DT_E_INCOMPLETE, DT_E_DEVICE, DT_E_INTERNAL = range(8)
+ERROR_NAMES = {0: "DT_OK", 1: "DT_E_ARG", 2: "DT_E_INPUT", 3: "DT_E_DEGENERATE", 4: "DT_E_CAPACITY",
+               5: "DT_E_INCOMPLETE", 6: "DT_E_DEVICE", 7: "DT_E_INTERNAL"}
+
+
+class DTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class dt_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("round_size", ctypes.c_uint32),
+                ("cavity_cap", ctypes.c_uint32), ("capacity_tets", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("max_rounds", ctypes.c_uint32), ("timing", ctypes.c_int), ("round_fraction", ctypes.c_double)]
+
+
+_STAT_U64 = ["points", "vertices", "duplicates", "tets", "rounds", "attempts", "inserted", "conflicts",
+             "overflows", "walk_steps", "cavity_tets", "boundary_facets", "orient_calls", "orient_exact",
+             "insphere_calls", "insphere_exact", "perturbed"]
+
+
+class dt_stats(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_uint64) for n in _STAT_U64] +
+                [("ms_total", ctypes.c_double), ("ms_sort", ctypes.c_double), ("ms_insert", ctypes.c_double),
+                 ("cavity_launches", ctypes.c_uint64), ("ball_launches", ctypes.c_uint64),
+                 ("ms_cavity_kernel", ctypes.c_double), ("ms_ball_kernel", ctypes.c_double),
+                 ("cavity_units", ctypes.c_uint64), ("ball_units", ctypes.c_uint64)])
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libdt.so; fails loudly when the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1805_08831_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+        L.dt_default_options.argtypes = [ctypes.POINTER(dt_options)]
+        L.dt_default_options.restype = None
+        L.dt_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(dt_options)]
+        L.dt_insert_points.argtypes = [vp, vp, u64]
+        L.dt_get_tets.argtypes = [vp, vp, vp, ctypes.POINTER(u64)]
+        L.dt_clear.argtypes = [vp]
+        L.dt_destroy.argtypes = [vp]
+        L.dt_get_stats.argtypes = [vp, ctypes.POINTER(dt_stats)]
+        L.dt_last_error.argtypes = [vp]
+        L.dt_last_error.restype = ctypes.c_char_p
+        L.dt_debug_sort.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(i32)]
+        L.dt_debug_predicates.argtypes = [vp, i32, vp, vp, u64, vp]
+        for f in ("dt_create", "dt_insert_points", "dt_get_tets", "dt_clear", "dt_destroy", "dt_get_stats",
+                  "dt_debug_sort", "dt_debug_predicates"):
+            getattr(L, f).restype = i32
+        _lib = L
+    return _lib
+
+
+def _ptr(x):
+    """Address of a numpy array or torch tensor (contiguous), or None."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"]
+        return x.ctypes.data
+    assert x.is_contiguous()
+    return x.data_ptr()
+
+
+# --------------------------------------------------------------------- C-ABI mirror
+
+def dt_default_options():
+    o = dt_options()
+    lib().dt_default_options(ctypes.byref(o))
+    return o
+
+
+def dt_create(opt=None):
+    h = ctypes.c_void_p()
+    rc = lib().dt_create(ctypes.byref(h), ctypes.byref(opt) if opt is not None else None)
+    if rc != DT_OK:
+        raise DTError(rc, "dt_create failed")
+    return h
+
+
+def _check(ctx, rc):
+    if rc != DT_OK:
+        raise DTError(rc, lib().dt_last_error(ctx).decode())
+
+
+def dt_insert_points(ctx, xyz, n=None):
+    n = int(xyz.shape[0]) if n is None else int(n)
+    _check(ctx, lib().dt_insert_points(ctx, _ptr(xyz), n))
+
+
+def dt_get_tets(ctx, tets=None, nbrs=None, capacity=0):
+    num = ctypes.c_uint64(capacity)
+    _check(ctx, lib().dt_get_tets(ctx, _ptr(tets), _ptr(nbrs), ctypes.byref(num)))
+    return int(num.value)
+
+
+def dt_clear(ctx):
+    _check(ctx, lib().dt_clear(ctx))
+
+
+def dt_destroy(ctx):
+    lib().dt_destroy(ctx)
+
+
+def dt_get_stats(ctx):
+    s = dt_stats()
+    _check(ctx, lib().dt_get_stats(ctx, ctypes.byref(s)))
+    return s.as_dict()
+
+
+def dt_debug_sort(ctx, xyz):
+    n = int(xyz.shape[0])
+    keys = np.empty(n, dtype=np.uint64)
+    perm = np.empty(n, dtype=np.uint32)
+    m = ctypes.c_int(0)
+    _check(ctx, lib().dt_debug_sort(ctx, _ptr(xyz), n, keys.ctypes.data, perm.ctypes.data, ctypes.byref(m)))
+    return keys, perm, int(m.value)
+
+
+def dt_debug_predicates(ctx, kind, pts, idx=None):
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    k = int(pts.shape[0])
+    out = np.empty(k, dtype=np.int8)
+    idx = None if idx is None else np.ascontiguousarray(idx, dtype=np.int64)
+    _check(ctx, lib().dt_debug_predicates(ctx, int(kind), pts.ctypes.data, _ptr(idx), k, out.ctypes.data))
+    return out
+
+
+# --------------------------------------------------------------------- convenience class
+
+class Triangulation:
+    """One library context.  `insert` takes an (n, 3) float64 numpy array or torch tensor
+    (host or device); `tets` returns (tets[T,4] uint32, nbrs[T,4] int64)."""
+
+    def __init__(self, device=0, stream=None, round_size=0, cavity_cap=0, capacity_tets=0, seed=0x5EED,
+                 max_rounds=0, timing=False, round_fraction=0.0):
+        o = dt_default_options()
+        o.device, o.round_size, o.cavity_cap = int(device), int(round_size), int(cavity_cap)
+        o.capacity_tets, o.seed, o.max_rounds = int(capacity_tets), int(seed), int(max_rounds)
+        o.timing, o.round_fraction = int(bool(timing)), float(round_fraction)
+        o.stream = stream
+        self.ctx = dt_create(o)
+
+    def insert(self, xyz):
+        if isinstance(xyz, np.ndarray):
+            xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        assert xyz.ndim == 2 and xyz.shape[1] == 3
+        dt_insert_points(self.ctx, xyz)
+
+    def num_tets(self):
+        return dt_get_tets(self.ctx)
+
+    def tets(self, device_tensors=False):
+        T = dt_get_tets(self.ctx)
+        if device_tensors:
+            import torch
+            tets = torch.empty((T, 4), dtype=torch.int32, device="cuda")
+            nbrs = torch.empty((T, 4), dtype=torch.int64, device="cuda")
+        else:
+            tets = np.empty((T, 4), dtype=np.uint32)
+            nbrs = np.empty((T, 4), dtype=np.int64)
+        dt_get_tets(self.ctx, tets, nbrs, T)
+        return tets, nbrs
+
+    def stats(self):
+        return dt_get_stats(self.ctx)
+
+    def clear(self):
+        dt_clear(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            dt_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

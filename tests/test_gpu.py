@@ -1,0 +1,260 @@
+"""GPU parity: the HIP library, called through its C ABI, against the oracle.
+
+The triangulation is unique (perturbed Delaunay), so parity is bit-exact equality of the
+canonically sorted vertex quadruples; the invariants (orientation, adjacency, Euler
+characteristic, vertex coverage, volume, local Delaunay) are checked on the GPU output too.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from synth import cluster_points, lattice_points, shell_points, uniform_points
+from validators import check_invariants
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dtlib():
+    from paper_1805_08831_amd import dt
+    dt.lib()
+    return dt
+
+
+def gpu_dt(dtlib, xyz, **opts):
+    with dtlib.Triangulation(**opts) as tri:
+        tri.insert(np.ascontiguousarray(xyz, dtype=np.float64))
+        tets, nbrs = tri.tets()
+        return tets.astype(np.int64), nbrs, tri.stats()
+
+
+def oracle_dt(oracle_mod, xyz):
+    rc, tets, nbrs, st = oracle_mod.delaunay(xyz)
+    assert rc == 0
+    return tets, nbrs, st
+
+
+def assert_parity(oracle_mod, xyz, tets_gpu, label):
+    ref_tets, _, _ = oracle_dt(oracle_mod, xyz)
+    a, b = oracle_mod.canonical(tets_gpu), oracle_mod.canonical(ref_tets)
+    assert a.shape == b.shape, f"{label}: {a.shape} vs {b.shape}"
+    assert np.array_equal(a, b), f"{label}: quadruples differ"
+
+
+def sphere50():
+    return np.array([(x, y, z) for x in range(-8, 8) for y in range(-8, 8) for z in range(-8, 8)
+                     if x * x + y * y + z * z == 50], dtype=np.float64) / 8.0
+
+
+def mix_small(seed, n_each):
+    return np.random.default_rng(seed).permutation(np.vstack([
+        lattice_points(n_each, seed, side=int(np.ceil((1.05 * n_each) ** (1 / 3))) + 1),
+        cluster_points(n_each, seed, clusters=5), shell_points(n_each, seed)]))
+
+
+# ------------------------------------------------------------------ predicates
+
+def test_predicates_match_oracle(dtlib, oracle_mod):
+    say("predicates")
+    rng = np.random.default_rng(7)
+    cases4, cases5, idx5 = [], [], []
+    for s in range(2000):
+        cases4.append(uniform_points(4, 10000 + s))
+        cases5.append(uniform_points(5, 20000 + s))
+    lat = lattice_points(120, 3, side=5)
+    sph = sphere50()
+    cube = np.array(list(itertools.product([0.0, 1.0], repeat=3)))
+    for _ in range(2000):
+        cases4.append(lat[rng.choice(len(lat), 4, replace=False)])
+        src = [lat, sph, cube][rng.integers(3)]
+        cases5.append(src[rng.choice(len(src), 5, replace=False)])
+    for s in range(500):  # near-degenerate: a point on the plane of three, nudged
+        p = uniform_points(3, 30000 + s)
+        u, v = rng.random(2)
+        q = p[0] + u * (p[1] - p[0]) + v * (p[2] - p[0])
+        q[0] = np.nextafter(q[0], np.inf if s % 2 else -np.inf)
+        cases4.append(np.vstack([p, q]))
+    # wide exponent spread
+    for s in range(300):
+        c = uniform_points(5, 40000 + s) * (2.0 ** rng.integers(-100, 100, size=(5, 1)))
+        cases5.append(c)
+        cases4.append(c[:4])
+    p4, p5 = np.array(cases4), np.array(cases5)
+    ctx = dtlib.dt_create()
+    try:
+        o4 = dtlib.dt_debug_predicates(ctx, 0, p4.reshape(len(p4), -1))
+        assert np.array_equal(o4, oracle_mod.orient3d(p4))
+        o5 = dtlib.dt_debug_predicates(ctx, 1, p5.reshape(len(p5), -1))
+        assert np.array_equal(o5, oracle_mod.insphere(p5))
+        # perturbed: rows abcd must be positive
+        ori = oracle_mod.orient3d(p5[:, :4])
+        keep = ori != 0
+        q5 = p5[keep].copy()
+        neg = ori[keep] < 0
+        q5[neg, 0], q5[neg, 1] = p5[keep][neg, 1], p5[keep][neg, 0]
+        idx = np.array([rng.permutation(10 ** 6)[:5] for _ in range(len(q5))])
+        s5 = dtlib.dt_debug_predicates(ctx, 2, q5.reshape(len(q5), -1), idx)
+        assert np.array_equal(s5, oracle_mod.insphere_sos(q5, idx))
+        assert np.count_nonzero(oracle_mod.insphere(q5) == 0) > 100
+    finally:
+        dtlib.dt_destroy(ctx)
+
+
+# ------------------------------------------------------------------ sort
+
+@pytest.mark.parametrize("kind,n", [("uniform", 1017), ("uniform", 100000), ("mix", 30000)])
+def test_sort_matches_oracle(dtlib, oracle_mod, kind, n):
+    say(f"sort {kind} {n}")
+    xyz = uniform_points(n, 1001) if kind == "uniform" else mix_small(5, n // 3)
+    ctx = dtlib.dt_create()
+    try:
+        keys, perm, m = dtlib.dt_debug_sort(ctx, xyz)
+    finally:
+        dtlib.dt_destroy(ctx)
+    rkeys, rperm, rm, _ = oracle_mod.sort_reference(xyz, 0x5EED)
+    assert m == rm
+    assert np.array_equal(keys, rkeys)
+    assert np.array_equal(perm.astype(np.int64), rperm)
+
+
+# ------------------------------------------------------------------ triangulations
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (5, 2), (6, 3), (8, 4), (12, 5), (33, 6), (100, 7), (1000, 8),
+                                    (4999, 9), (20000, 10)])
+def test_uniform_small(dtlib, oracle_mod, n, seed):
+    say(f"uniform n={n} seed={seed}")
+    xyz = uniform_points(n, seed)
+    tets, nbrs, st = gpu_dt(dtlib, xyz)
+    assert_parity(oracle_mod, xyz, tets, f"uniform {n}")
+    check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(n))
+
+
+def test_uniform_1e5(dtlib, oracle_mod):
+    """1e5 i.i.d. uniform points, seed 1001: exact match with the oracle."""
+    say("uniform 1e5")
+    xyz = uniform_points(100000, 1001)
+    tets, nbrs, st = gpu_dt(dtlib, xyz)
+    assert_parity(oracle_mod, xyz, tets, "uniform 1e5")
+    check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(len(xyz)))
+    say(f"stats {st}")
+
+
+@pytest.mark.parametrize("case", ["cube", "cube_center", "lattice3", "lattice6", "sphere", "coplanar_hull"])
+def test_degenerate_sets(dtlib, oracle_mod, case):
+    say(f"degenerate {case}")
+    cube = np.array(list(itertools.product([0.0, 1.0], repeat=3)))
+    grid = np.array([[x, y, 0.0] for x in range(4) for y in range(4)])
+    xyz = {
+        "cube": cube,
+        "cube_center": np.vstack([cube, [[0.5, 0.5, 0.5]]]),
+        "lattice3": np.array(list(itertools.product([0.0, 0.5, 1.0], repeat=3))),
+        "lattice6": np.array(list(itertools.product(np.arange(6.0) / 8, repeat=3))),
+        "sphere": sphere50(),
+        "coplanar_hull": np.vstack([grid, [[1.5, 1.5, 1.0], [0.5, 2.5, 0.75], [2.5, 0.5, 1.25]]]),
+    }[case]
+    xyz = np.random.default_rng(11).permutation(xyz)
+    tets, nbrs, st = gpu_dt(dtlib, xyz)
+    assert_parity(oracle_mod, xyz, tets, case)
+    check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(len(xyz)))
+
+
+@pytest.mark.parametrize("n_each", [3000, 20000])
+def test_mix(dtlib, oracle_mod, n_each):
+    say(f"mix {n_each}")
+    xyz = mix_small(21, n_each)
+    tets, nbrs, st = gpu_dt(dtlib, xyz)
+    assert_parity(oracle_mod, xyz, tets, "mix")
+    check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(len(xyz)))
+    assert st["insphere_exact"] > 0 and st["perturbed"] > 0
+
+
+def test_errors(dtlib):
+    say("errors")
+    cases = {
+        "coplanar": (np.c_[uniform_points(100, 3)[:, :2], np.zeros(100)], dtlib.DT_E_DEGENERATE),
+        "three": (uniform_points(3, 3), dtlib.DT_E_DEGENERATE),
+        "nan": (np.where(np.arange(30).reshape(10, 3) == 7, np.nan, uniform_points(10, 4)), dtlib.DT_E_INPUT),
+        "huge": (np.where(np.arange(30).reshape(10, 3) == 5, 1e300, uniform_points(10, 4)), dtlib.DT_E_INPUT),
+        "tiny": (np.where(np.arange(30).reshape(10, 3) == 5, 1e-300, uniform_points(10, 4)), dtlib.DT_E_INPUT),
+    }
+    for name, (xyz, code) in cases.items():
+        with dtlib.Triangulation() as tri:
+            with pytest.raises(dtlib.DTError) as e:
+                tri.insert(np.ascontiguousarray(xyz))
+            assert e.value.code == code, name
+            assert tri.num_tets() == 0
+
+
+def test_duplicates_within_and_across_calls(dtlib, oracle_mod):
+    say("duplicates")
+    xyz = uniform_points(3000, 31)
+    dup = np.vstack([xyz[[5]], xyz, xyz[[7, 100, 7, 2999]]])  # index 0 duplicates index 6
+    tets, nbrs, st = gpu_dt(dtlib, dup)
+    assert_parity(oracle_mod, dup, tets, "duplicates")
+    assert st["duplicates"] == 5
+    assert 6 not in set(tets.reshape(-1).tolist())
+    # across calls: the second call repeats points of the first
+    with dtlib.Triangulation() as tri:
+        tri.insert(xyz[:2000])
+        tri.insert(np.vstack([xyz[2000:], xyz[:10]]))
+        t2, n2 = tri.tets()
+    assert_parity(oracle_mod, np.vstack([xyz, xyz[:10]]), t2.astype(np.int64), "duplicates across calls")
+
+
+def test_append_and_clear(dtlib, oracle_mod):
+    say("append")
+    xyz = uniform_points(30000, 41)
+    with dtlib.Triangulation() as tri:
+        for a, b in [(0, 7), (7, 5000), (5000, 5001), (5001, 30000)]:
+            tri.insert(xyz[a:b])
+        t, nb = tri.tets()
+        assert_parity(oracle_mod, xyz, t.astype(np.int64), "append")
+        check_invariants(xyz, t.astype(np.int64), nb, oracle_mod, expect_vertices=np.arange(len(xyz)))
+        tri.clear()
+        other = uniform_points(5000, 42)
+        tri.insert(other)
+        t, nb = tri.tets()
+        assert_parity(oracle_mod, other, t.astype(np.int64), "after clear")
+
+
+@pytest.mark.parametrize("opts", [dict(cavity_cap=4), dict(cavity_cap=12), dict(round_size=64),
+                                  dict(round_size=1 << 16), dict(round_fraction=2.0), dict(seed=99)])
+def test_launch_options_do_not_change_result(dtlib, oracle_mod, opts):
+    say(f"options {opts}")
+    xyz = mix_small(51, 4000)
+    tets, nbrs, st = gpu_dt(dtlib, xyz, **opts)
+    assert_parity(oracle_mod, xyz, tets, str(opts))
+    if opts.get("cavity_cap") == 4:
+        assert st["overflows"] > 0
+
+
+def test_round_limit(dtlib):
+    say("round limit")
+    with dtlib.Triangulation(max_rounds=1) as tri:
+        with pytest.raises(dtlib.DTError) as e:
+            tri.insert(uniform_points(20000, 5))
+        assert e.value.code == dtlib.DT_E_INCOMPLETE
+
+
+def test_device_buffers_through_torch(dtlib, oracle_mod):
+    """Device input and device outputs (the benchmark's path)."""
+    say("device buffers")
+    import torch
+    xyz = uniform_points(50000, 61)
+    d = torch.from_numpy(xyz).cuda()
+    torch.cuda.synchronize()
+    with dtlib.Triangulation(stream=torch.cuda.current_stream().cuda_stream) as tri:
+        tri.insert(d)
+        t, nb = tri.tets(device_tensors=True)
+        torch.cuda.synchronize()
+        t = t.cpu().numpy().astype(np.int64)
+        nb = nb.cpu().numpy()
+    assert_parity(oracle_mod, xyz, t, "device buffers")
+    check_invariants(xyz, t, nb, oracle_mod, expect_vertices=np.arange(len(xyz)))
