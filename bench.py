@@ -1,0 +1,169 @@
+"""Benchmark: tetrahedra per second of the exact Delaunay tetrahedralization on one MI355X.
+
+A step is one pass of the whole path over one batch: clear the context, insert the n points
+(validation, Moore keys, radix sort, duplicates, initial tetrahedron, anchors and every
+insertion round) and export the tetrahedra with their neighbours into device buffers.  The
+points are resident in HBM before the timed region starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic bytes of the cavity kernel (walk + cavity + claim) per attempt, from the
+# counters: candidate/hint/point (48 B), per walk step one tetrahedron row (vertices 16 B +
+# neighbours 16 B) and one new vertex record (32 B), per cavity tetrahedron its two rows
+# (32 B) and per outer tetrahedron its vertex row (16 B), an 8-byte owner word read and
+# written per touched tetrahedron (16 B), the boundary's vertex records (F/2 + 2 records of
+# 32 B) and the per-insertion buffers written (4 B per cavity tetrahedron, 8 B per facet).
+def cavity_bytes_per_attempt(walk, C, F):
+    return 48 + 64 * walk + 32 * C + 16 * F + 16 * (C + F) + 32 * (F / 2 + 2) + 4 * C + 8 * F
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--seed", type=int, default=1007)
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--round-fraction", type=float, default=0.0)
+    ap.add_argument("--round-size", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the triangulation of one point cloud is not "
+              "distributed across GPUs in this library (see DESIGN.md, sharding).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1805_08831_amd import Triangulation, dt_get_tets
+    from synth import uniform_points
+
+    xyz = uniform_points(args.n, args.seed)
+    d_xyz = torch.from_numpy(xyz).cuda()
+    stream = torch.cuda.current_stream()
+    tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True,
+                        round_fraction=args.round_fraction, round_size=args.round_size)
+
+    def step():
+        tri.clear()
+        tri.insert(d_xyz)
+        T = dt_get_tets(tri.ctx)
+        return T
+
+    # output buffers sized once (outside the timed region) from a first run
+    tri.insert(d_xyz)
+    T0 = dt_get_tets(tri.ctx)
+    out_t = torch.empty((T0 + 1024, 4), dtype=torch.int32, device="cuda")
+    out_n = torch.empty((T0 + 1024, 4), dtype=torch.int64, device="cuda")
+
+    def full_step():
+        tri.clear()
+        tri.insert(d_xyz)
+        return dt_get_tets(tri.ctx, out_t, out_n, T0 + 1024)
+
+    for _ in range(args.warmup):
+        full_step()
+    torch.cuda.synchronize()
+    tri.clear()
+    base_stats = tri.stats()
+    times = []
+    T = 0
+    agg = dict(attempts=0, walk=0, cav=0, bnd=0, won=0, ms_cav=0.0, ms_ball=0.0, launches=0, rounds=0,
+               orient=0, orient_exact=0, insphere=0, insphere_exact=0, perturbed=0, conflicts=0)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        T = full_step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        s = tri.stats()
+        agg["attempts"] += s["attempts"]
+        agg["walk"] += s["walk_steps"]
+        agg["cav"] += s["cavity_tets"]
+        agg["bnd"] += s["boundary_facets"]
+        agg["won"] += s["inserted"]
+        agg["ms_cav"] += s["ms_cavity_kernel"]
+        agg["ms_ball"] += s["ms_ball_kernel"]
+        agg["launches"] += s["cavity_launches"]
+        agg["rounds"] += s["rounds"]
+        agg["conflicts"] += s["conflicts"]
+        for k in ("orient", "orient_exact", "insphere", "insphere_exact", "perturbed"):
+            agg[k] += s[k + ("_calls" if k in ("orient", "insphere") else "")]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    ms_per_step = 1000.0 * total / args.steps
+    value = T / (ms_per_step / 1000.0)
+
+    # roofline of the dominant kernel (walk + cavity + claim), HBM-bound
+    att = max(agg["attempts"], 1)
+    won = max(agg["won"], 1)
+    walk = agg["walk"] / att
+    C = agg["cav"] / won
+    F = agg["bnd"] / won
+    b_unit = cavity_bytes_per_attempt(walk, C, F)
+    launches = max(agg["launches"], 1)
+    avg_launch_ms = agg["ms_cav"] / launches
+    bytes_per_launch = b_unit * agg["attempts"] / launches
+    achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
+    peak = 8000.0
+    roofline = {"bound": "hbm", "kernel": "k_cavity", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "GB/s", "frac": round(achieved / peak, 5), "traffic": None,
+                "bytes_per_attempt": round(b_unit, 1), "attempts_per_launch": round(agg["attempts"] / launches, 1),
+                "avg_launch_ms": round(avg_launch_ms, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = uniform_points(args.cpu_sample, args.seed + 1)
+        t0 = time.perf_counter()
+        rc, tets, _, _ = oracle.delaunay(sample)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(len(tets) / dt, 1), "unit": "tetrahedra/s", "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_sample} uniform points (seed {args.seed + 1}), full serial triangulation "
+                         f"in {dt:.2f} s, {len(tets)} tetrahedra"}
+
+    line = {
+        "metric": "tetrahedra/sec (exact 3D Delaunay, uniform points)",
+        "value": round(value, 1),
+        "unit": "tetrahedra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.n} i.i.d. uniform fp64 points in [0,1)^3, seed {args.seed}",
+                   "points": args.n, "tetrahedra": T, "scheduler": "plain"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {"rounds_per_step": agg["rounds"] / args.steps, "attempts_per_point": agg["attempts"] / max(args.n * args.steps, 1),
+                   "conflict_rate": agg["conflicts"] / att, "walk_steps_per_attempt": round(walk, 3),
+                   "cavity_tets": round(C, 2), "boundary_facets": round(F, 2),
+                   "ms_cavity_kernel_per_step": round(agg["ms_cav"] / args.steps, 3),
+                   "ms_ball_kernel_per_step": round(agg["ms_ball"] / args.steps, 3),
+                   "orient_exact_rate": agg["orient_exact"] / max(agg["orient"], 1),
+                   "insphere_exact_rate": agg["insphere_exact"] / max(agg["insphere"], 1),
+                   "perturbed": agg["perturbed"], "step_ms": [round(1000 * t, 2) for t in times]},
+    }
+    print(json.dumps(line), flush=True)
+    tri.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -51,6 +51,13 @@ def lib():
     """Load libdt.so; fails loudly when the HIP library has not been built."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: when PyTorch is installed its bundled runtime (same
+        # soname as ROCm's) is loaded first so that the library binds to it and device
+        # pointers and streams are shared with torch.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1805_08831_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
