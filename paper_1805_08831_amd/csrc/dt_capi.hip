@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -82,7 +83,7 @@ struct dt_ctx {
     DevBuf<uint8_t> dup;
     uint32_t tcap = 0;
     uint4 *tv = nullptr, *tn = nullptr;
-    unsigned long long *owner = nullptr;
+    unsigned long long *owner = nullptr;  // [2][tcap]: claims of any kind, cavity claims
     uint32_t *fl[2] = {nullptr, nullptr};
 
     uint32_t list_cap = 0;
@@ -90,6 +91,7 @@ struct dt_ctx {
     size_t bufC = 0, bufF = 0;
     uint32_t capC = 0, capF = 0;
     uint32_t *cav = nullptr, *bnd = nullptr, *outc = nullptr, *cnt = nullptr;
+    uint32_t *winners = nullptr, *w_take = nullptr, *w_bump = nullptr, *w_free = nullptr;
     uint8_t *status = nullptr;
 
     Ctr *ctr = nullptr;
@@ -107,6 +109,8 @@ struct dt_ctx {
 
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     dt_stats st{};
+    uint32_t trace_prev_won = 0;
+    bool trace = false;  // DT_TRACE=1 in the environment: one line per round on stderr
 };
 
 namespace {
@@ -171,7 +175,7 @@ int grow_tets(dt_ctx *c, uint64_t need) {
     uint32_t *f0 = nullptr, *f1 = nullptr;
     bool ok = hipMalloc((void **)&tv, cap * sizeof(uint4)) == hipSuccess &&
               hipMalloc((void **)&tn, cap * sizeof(uint4)) == hipSuccess &&
-              hipMalloc((void **)&ow, cap * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc((void **)&ow, 2 * cap * sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc((void **)&f0, cap * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void **)&f1, cap * sizeof(uint32_t)) == hipSuccess;
     if (!ok) {
@@ -179,12 +183,14 @@ int grow_tets(dt_ctx *c, uint64_t need) {
         hipFree(tv); hipFree(tn); hipFree(ow); hipFree(f0); hipFree(f1);
         return fail(c, DT_E_CAPACITY, "device allocation for %llu tetrahedra failed", (unsigned long long)cap);
     }
-    HIPCHK(hipMemsetAsync(ow, 0xFF, cap * sizeof(unsigned long long), c->stream));
+    HIPCHK(hipMemsetAsync(ow, 0xFF, 2 * cap * sizeof(unsigned long long), c->stream));
     if (c->tcap) {
         uint64_t used = c->hctr->tet_count;
         HIPCHK(hipMemcpyAsync(tv, c->tv, used * sizeof(uint4), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(tn, c->tn, used * sizeof(uint4), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(ow, c->owner, used * sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(ow + cap, c->owner + c->tcap, used * sizeof(unsigned long long),
+                              hipMemcpyDeviceToDevice, c->stream));
         uint64_t nf = c->hctr->fl_n;
         HIPCHK(hipMemcpyAsync(c->fl_idx == 0 ? f0 : f1, c->fl[c->fl_idx], nf * sizeof(uint32_t),
                               hipMemcpyDeviceToDevice, c->stream));
@@ -204,7 +210,9 @@ int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
         c->lpt[k] = c->lrank[k] = nullptr;
     }
     hipFree(c->cav); hipFree(c->bnd); hipFree(c->outc); hipFree(c->cnt); hipFree(c->status);
+    hipFree(c->winners); hipFree(c->w_take); hipFree(c->w_bump); hipFree(c->w_free);
     c->cav = c->bnd = c->outc = c->cnt = nullptr;
+    c->winners = c->w_take = c->w_bump = c->w_free = nullptr;
     c->status = nullptr;
     c->list_cap = rmax;
     c->bufC = (size_t)rmax * c->capC;
@@ -217,7 +225,11 @@ int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
          hipMalloc((void **)&c->bnd, c->bufF * sizeof(uint32_t)) == hipSuccess &&
          hipMalloc((void **)&c->outc, c->bufF * sizeof(uint32_t)) == hipSuccess &&
          hipMalloc((void **)&c->cnt, 2 * (size_t)rmax * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void **)&c->status, rmax) == hipSuccess;
+         hipMalloc((void **)&c->status, rmax) == hipSuccess &&
+         hipMalloc((void **)&c->winners, rmax * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc((void **)&c->w_take, rmax * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc((void **)&c->w_bump, rmax * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc((void **)&c->w_free, rmax * sizeof(uint32_t)) == hipSuccess;
     if (!ok) {
         hipGetLastError();
         c->list_cap = 0;
@@ -299,7 +311,12 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.V = c->V.p;
     a.tv = c->tv;
     a.tn = c->tn;
-    a.owner = c->owner;
+    a.own_any = c->owner;
+    a.own_cav = c->owner + c->tcap;
+    a.winners = c->winners;
+    a.w_take = c->w_take;
+    a.w_bump = c->w_bump;
+    a.w_free = c->w_free;
     a.vtet = c->vtet.p;
     a.anchor = c->anchor.p;
     a.cand_pt = c->lpt[ci];
@@ -332,6 +349,19 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     if (rc) return rc;
     if (max_cand) accumulate_timing(c);
     c->st.rounds++;
+    if (c->trace) {
+        uint32_t &prev_won = c->trace_prev_won;
+        if (prev_won > c->hctr->won) prev_won = 0;
+        float a = 0.f, b = 0.f;
+        if (c->opt.timing && max_cand) {
+            hipEventElapsedTime(&a, c->ev[0], c->ev[1]);
+            hipEventElapsedTime(&b, c->ev[1], c->ev[2]);
+        }
+        fprintf(stderr, "round %llu cand<=%u won=%u tets=%u free=%u cavity_ms=%.3f ball_ms=%.3f\n",
+                (unsigned long long)c->st.rounds, max_cand, c->hctr->won - prev_won, c->hctr->tet_count,
+                c->hctr->fl_n, a, b);
+        prev_won = c->hctr->won;
+    }
     return check_errors(c);
 }
 
@@ -496,6 +526,7 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
         return DT_E_ARG;
     }
     c->device = c->opt.device;
+    c->trace = getenv("DT_TRACE") && getenv("DT_TRACE")[0] == '1';
     if (hipSetDevice(c->device) != hipSuccess) {
         hipGetLastError();
         delete c;
@@ -686,6 +717,7 @@ int dt_destroy(dt_ctx *c) {
     f(c->tv); f(c->tn); f(c->owner); f(c->fl[0]); f(c->fl[1]);
     for (int k = 0; k < 4; ++k) { f(c->lpt[k]); f(c->lrank[k]); }
     f(c->cav); f(c->bnd); f(c->outc); f(c->cnt); f(c->status);
+    f(c->winners); f(c->w_take); f(c->w_bump); f(c->w_free);
     f(c->ctr);
     if (c->hctr) hipHostFree(c->hctr);
     f(c->staging.p); f(c->keys.p); f(c->keys_tmp.p); f(c->table.p); f(c->vals.p); f(c->vals_tmp.p);

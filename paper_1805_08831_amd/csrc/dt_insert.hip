@@ -282,12 +282,19 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
         uint32_t ncav = 0, nbnd = 0;
         if (status == ST_NONE) {
             // Cavity: breadth-first search; cav entries hold (tetrahedron << 2 | facet it was
-            // entered through), which is skipped when the tetrahedron is expanded
-            if (atomicMin(&a.owner[t], S) < S) {
-                status = ST_CONFLICT;
-            } else {
-                a.cav[i] = t << 2;
-                ncav = 1;
+            // entered through), which is skipped when the tetrahedron is expanded.
+            // Claims: own_any[t] = min stamp of every attempt touching t, S for this cavity's
+            // tetrahedra and S + 1 for those found outside (so the parity tells the kind);
+            // own_cav[t] = min stamp of the attempts with t in their cavity.
+            {
+                const unsigned long long o0 = atomicMin(&a.own_any[t], S);
+                if (o0 < S) {
+                    status = ST_CONFLICT;
+                } else {
+                    atomicMin(&a.own_cav[t], S);
+                    a.cav[i] = t << 2;
+                    ncav = 1;
+                }
             }
             for (uint32_t k = 0; k < ncav && status == ST_NONE; ++k) {
                 const uint32_t code = a.cav[(size_t)k * stride + i];
@@ -298,19 +305,25 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
                     if (f == pf) continue;
                     const uint32_t ncode = comp(cn, f);
                     const uint32_t u = ncode >> 2;
-                    const unsigned long long o1 = atomicMin(&a.owner[u], S + 1);
-                    if (o1 < S) {
-                        status = ST_CONFLICT;
-                        break;
-                    }
+                    const unsigned long long o1 = atomicMin(&a.own_any[u], S + 1);
                     if (o1 == S) continue;  // already in this cavity: internal facet
                     bool inside = false;
-                    if (o1 != S + 1) inside = tet_inside(a, u, P, pv.idx, st);
-                    if (inside) {
-                        if (atomicMin(&a.owner[u], S) < S) {
+                    if (o1 != S + 1) {
+                        // a lower attempt has u in its cavity: this one loses whatever u is
+                        if (o1 < S && !(o1 & 1ull)) {
                             status = ST_CONFLICT;
                             break;
                         }
+                        inside = tet_inside(a, u, P, pv.idx, st);
+                    }
+                    if (inside) {
+                        // u joins the cavity; a lower attempt touching it at all wins over this one
+                        const unsigned long long o2 = atomicMin(&a.own_any[u], S);
+                        if (o2 < S) {
+                            status = ST_CONFLICT;
+                            break;
+                        }
+                        atomicMin(&a.own_cav[u], S);
                         if (ncav == a.capC) {
                             status = ST_OVERFLOW;
                             break;
@@ -359,7 +372,7 @@ __device__ uint32_t pivot(const RoundArgs &a, uint32_t c, int f, uint32_t e0, ui
         if (xpos < 0) break;
         const uint32_t code = reinterpret_cast<const uint32_t *>(a.tn)[4 * (size_t)c + xpos];
         const uint32_t nt = code >> 2;
-        if (a.owner[nt] == S) {  // another tetrahedron of this cavity
+        if (a.own_any[nt] == S) {  // another tetrahedron of this cavity
             c = nt;
             f = (int)(code & 3u);
             continue;
@@ -376,101 +389,127 @@ __device__ uint32_t pivot(const RoundArgs &a, uint32_t c, int f, uint32_t e0, ui
     return 0;
 }
 
-__global__ __launch_bounds__(256) void k_ball(RoundArgs a) {
+// Winner test and slot reservation, one thread per candidate.  An attempt wins iff it still
+// holds the lowest claim on every tetrahedron of its cavity (own_any) and no lower attempt
+// has one of its outer tetrahedra in its cavity (own_cav).  Winners of one round therefore
+// have disjoint cavities, and no cavity meets another winner's outer tetrahedra.
+__global__ __launch_bounds__(256) void k_check(RoundArgs a) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ncand = *a.ncand_ptr;
     const uint32_t stride = a.stride;
-    unsigned won = 0, ncav_w = 0, nbnd_w = 0;
-    if (i < ncand && a.status[i] == ST_CAND) {
+    if (i >= ncand || a.status[i] != ST_CAND) return;
+    const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
+    const uint32_t nc = a.cnt[i], nb = a.cnt[stride + i];
+    bool win = true;
+    for (uint32_t k = 0; k < nc; ++k) win &= a.own_any[a.cav[(size_t)k * stride + i] >> 2] == S;
+    for (uint32_t k = 0; k < nb; ++k) win &= a.own_cav[a.outc[(size_t)k * stride + i] >> 2] > S;
+    if (!win) {
+        a.status[i] = ST_CONFLICT;
+        return;
+    }
+    // slots: free list of earlier rounds first, then the bump pointer
+    const uint32_t take = atomicAdd(&a.ctr->fl_take, nb);
+    const uint32_t fln = a.ctr->fl_n;
+    const uint32_t from_fl = fln > take ? min(nb, fln - take) : 0u;
+    const uint32_t rest = nb - from_fl;
+    const uint32_t bump = rest ? atomicAdd(&a.ctr->tet_count, rest) : 0u;
+    if (rest && bump + rest > a.tcap) {
+        // pool full: give the slots back (those inside the pool are marked free) and
+        // retry next round after the host has grown the pool
+        uint32_t *tv32 = reinterpret_cast<uint32_t *>(a.tv);
+        uint32_t give = from_fl;
+        for (uint32_t k = 0; k < rest; ++k)
+            if (bump + k < a.tcap) ++give;
+        const uint32_t fb = atomicAdd(&a.ctr->fl_next, give);
+        uint32_t q = 0;
+        for (uint32_t k = 0; k < from_fl; ++k) a.fl_next[fb + q++] = a.fl_cur[take + k];
+        for (uint32_t k = 0; k < rest; ++k)
+            if (bump + k < a.tcap) {
+                tv32[4 * (size_t)(bump + k)] = DEAD;
+                a.fl_next[fb + q++] = bump + k;
+            }
+        atomicOr(&a.ctr->error, ERR_POOL);
+        a.status[i] = ST_CONFLICT;
+        return;
+    }
+    a.status[i] = ST_WON;
+    a.w_take[i] = take;
+    a.w_bump[i] = bump;
+    a.w_free[i] = atomicAdd(&a.ctr->fl_next, nc);
+    a.winners[atomicAdd(&a.ctr->nwin, 1u)] = i;
+}
+
+// DelaunayBall of one winner per 64-lane workgroup: (1) one new tetrahedron per boundary
+// facet, glued to its outer tetrahedron; (2) after a barrier, each new tetrahedron finds its
+// three siblings by pivoting around boundary edges through the intact cavity; (3) after a
+// barrier, the cavity tetrahedra are freed.
+__global__ __launch_bounds__(64) void k_build(RoundArgs a) {
+    const uint32_t nwin = a.ctr->nwin;
+    const uint32_t stride = a.stride;
+    const uint32_t fln = a.ctr->fl_n;
+    uint32_t *tn32 = reinterpret_cast<uint32_t *>(a.tn);
+    uint32_t *tv32 = reinterpret_cast<uint32_t *>(a.tv);
+    unsigned cav_w = 0, bnd_w = 0;
+    for (uint32_t w = blockIdx.x; w < nwin; w += gridDim.x) {
+        const uint32_t i = a.winners[w];
         const uint32_t p = a.cand_pt[i];
         const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
         const uint32_t nc = a.cnt[i], nb = a.cnt[stride + i];
-        bool win = true;
-        for (uint32_t k = 0; k < nc && win; ++k) win = a.owner[a.cav[(size_t)k * stride + i] >> 2] == S;
-        for (uint32_t k = 0; k < nb && win; ++k) win = a.owner[a.outc[(size_t)k * stride + i] >> 2] == S + 1;
-        if (!win) {
-            a.status[i] = ST_CONFLICT;
-        } else {
-            // slots: free list of earlier rounds first, then the bump pointer
-            const uint32_t take = atomicAdd(&a.ctr->fl_take, nb);
-            const uint32_t fln = a.ctr->fl_n;
-            const uint32_t from_fl = fln > take ? min(nb, fln - take) : 0u;
-            const uint32_t rest = nb - from_fl;
-            const uint32_t bump = rest ? atomicAdd(&a.ctr->tet_count, rest) : 0u;
-            if (rest && bump + rest > a.tcap) {
-                // pool full: give the slots back (those inside the pool are marked free),
-                // retry next round after the host has grown the pool
-                uint32_t *tv32 = reinterpret_cast<uint32_t *>(a.tv);
-                uint32_t give = from_fl;
-                for (uint32_t k = 0; k < rest; ++k)
-                    if (bump + k < a.tcap) ++give;
-                const uint32_t fb = atomicAdd(&a.ctr->fl_next, give);
-                uint32_t q = 0;
-                for (uint32_t k = 0; k < from_fl; ++k) a.fl_next[fb + q++] = a.fl_cur[take + k];
-                for (uint32_t k = 0; k < rest; ++k)
-                    if (bump + k < a.tcap) {
-                        tv32[4 * (size_t)(bump + k)] = DEAD;
-                        a.fl_next[fb + q++] = bump + k;
-                    }
-                atomicOr(&a.ctr->error, ERR_POOL);
-                a.status[i] = ST_CONFLICT;
-            } else {
-                uint32_t *tn32 = reinterpret_cast<uint32_t *>(a.tn);
-                // 1. create the ball: tetrahedron k on boundary facet k
-                for (uint32_t k = 0; k < nb; ++k) {
-                    const uint32_t slot = k < from_fl ? a.fl_cur[take + k] : bump + (k - from_fl);
-                    const uint32_t bc = a.bnd[(size_t)k * stride + i];
-                    const uint32_t oc = a.outc[(size_t)k * stride + i];
-                    const uint32_t u = oc >> 2;
-                    const int j = (int)(oc & 3u);
-                    const uint4 uw = a.tv[u];
-                    uint32_t w[4] = {uw.x, uw.y, uw.z, uw.w};
-                    w[j] = p;
-                    const int pf = orient_new_tet(w, j);
-                    a.tv[slot] = make_uint4(w[0], w[1], w[2], w[3]);
-                    const uint32_t me = (slot << 2) | (uint32_t)pf;
-                    tn32[4 * (size_t)slot + pf] = oc;             // facet opposite p: outer tetrahedron
-                    tn32[4 * (size_t)u + j] = me;                 // and back
-                    tn32[4 * (size_t)(bc >> 2) + (bc & 3u)] = me;  // cavity side now names the new tetrahedron
-                    a.outc[(size_t)k * stride + i] = me;
-                }
-                // 2. glue the new tetrahedra to each other
-                for (uint32_t k = 0; k < nb; ++k) {
-                    const uint32_t me = a.outc[(size_t)k * stride + i];
-                    const uint32_t slot = me >> 2;
-                    const int pf = (int)(me & 3u);
-                    const uint32_t bc = a.bnd[(size_t)k * stride + i];
-                    const uint4 sw = a.tv[slot];
-                    const uint32_t w[4] = {sw.x, sw.y, sw.z, sw.w};
-                    for (int q = 0; q < 4; ++q) {
-                        if (q == pf) continue;
-                        uint32_t e[2];
-                        int ne = 0;
-                        for (int r = 0; r < 4; ++r)
-                            if (r != q && r != pf) e[ne++] = w[r];
-                        tn32[4 * (size_t)slot + q] = pivot(a, bc >> 2, (int)(bc & 3u), e[0], e[1], p, S, nc + 2);
-                        if (w[q] != GHOST) a.vtet[w[q]] = slot;
-                    }
-                }
-                a.vtet[p] = a.outc[i] >> 2;
-                // 3. free the cavity
-                const uint32_t fb = atomicAdd(&a.ctr->fl_next, nc);
-                uint32_t *tv32 = reinterpret_cast<uint32_t *>(a.tv);
-                for (uint32_t k = 0; k < nc; ++k) {
-                    const uint32_t c = a.cav[(size_t)k * stride + i] >> 2;
-                    tv32[4 * (size_t)c] = DEAD;
-                    a.fl_next[fb + k] = c;
-                }
-                a.status[i] = ST_WON;
-                won = 1;
-                ncav_w = nc;
-                nbnd_w = nb;
+        const uint32_t take = a.w_take[i], bump = a.w_bump[i];
+        const uint32_t from_fl = fln > take ? min(nb, fln - take) : 0u;
+        for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) {
+            const uint32_t slot = k < from_fl ? a.fl_cur[take + k] : bump + (k - from_fl);
+            const uint32_t bc = a.bnd[(size_t)k * stride + i];
+            const uint32_t oc = a.outc[(size_t)k * stride + i];
+            const uint32_t u = oc >> 2;
+            const int j = (int)(oc & 3u);
+            const uint4 uw = a.tv[u];
+            uint32_t wv[4] = {uw.x, uw.y, uw.z, uw.w};
+            wv[j] = p;
+            const int pf = orient_new_tet(wv, j);
+            a.tv[slot] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+            const uint32_t me = (slot << 2) | (uint32_t)pf;
+            tn32[4 * (size_t)slot + pf] = oc;              // facet opposite p: outer tetrahedron
+            tn32[4 * (size_t)u + j] = me;                  // and back
+            tn32[4 * (size_t)(bc >> 2) + (bc & 3u)] = me;  // cavity side now names the new tetrahedron
+            a.outc[(size_t)k * stride + i] = me;
+            if (k == 0) a.vtet[p] = slot;
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) {
+            const uint32_t me = a.outc[(size_t)k * stride + i];
+            const uint32_t slot = me >> 2;
+            const int pf = (int)(me & 3u);
+            const uint32_t bc = a.bnd[(size_t)k * stride + i];
+            const uint4 sw = a.tv[slot];
+            const uint32_t wv[4] = {sw.x, sw.y, sw.z, sw.w};
+            for (int q = 0; q < 4; ++q) {
+                if (q == pf) continue;
+                uint32_t e[2];
+                int ne = 0;
+                for (int r = 0; r < 4; ++r)
+                    if (r != q && r != pf) e[ne++] = wv[r];
+                tn32[4 * (size_t)slot + q] = pivot(a, bc >> 2, (int)(bc & 3u), e[0], e[1], p, S, nc + 2);
+                if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
             }
         }
+        __syncthreads();
+        const uint32_t fb = a.w_free[i];
+        for (uint32_t k = threadIdx.x; k < nc; k += blockDim.x) {
+            const uint32_t c = a.cav[(size_t)k * stride + i] >> 2;
+            tv32[4 * (size_t)c] = DEAD;
+            a.fl_next[fb + k] = c;
+        }
+        if (threadIdx.x == 0) {
+            cav_w += nc;
+            bnd_w += nb;
+        }
+        __syncthreads();
     }
-    add_stat(&a.ctr->cav_tets, ncav_w);
-    add_stat(&a.ctr->bnd_facets, nbnd_w);
-    (void)won;
+    if (threadIdx.x == 0) {
+        if (cav_w) atomicAdd(&a.ctr->cav_tets, (unsigned long long)cav_w);
+        if (bnd_w) atomicAdd(&a.ctr->bnd_facets, (unsigned long long)bnd_w);
+    }
 }
 
 // ------------------------------------------------------------------ round end
@@ -514,6 +553,7 @@ __global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap) {
     ctr->fl_n = ctr->fl_next + left;
     ctr->fl_take = 0;
     ctr->fl_next = 0;
+    ctr->nwin = 0;
     *consumed = 0;  // the list this round read from is empty now
 }
 
@@ -523,7 +563,8 @@ hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, hipStream_t s, hi
     if (ev) hipEventRecord(ev[0], s);
     k_cavity<<<nb, 256, 0, s>>>(a);
     if (ev) hipEventRecord(ev[1], s);
-    k_ball<<<nb, 256, 0, s>>>(a);
+    k_check<<<nb, 256, 0, s>>>(a);
+    k_build<<<max_cand < 16384u ? max_cand : 16384u, 64, 0, s>>>(a);
     if (ev) hipEventRecord(ev[2], s);
     return hipGetLastError();
 }

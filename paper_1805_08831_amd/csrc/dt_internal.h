@@ -49,7 +49,8 @@ struct Ctr {
     uint32_t dups;       // duplicates found this round
     uint32_t error;      // ERR_* flags
     uint32_t init[4];    // sorted positions of the initial tetrahedron's vertices
-    uint32_t pad[3];
+    uint32_t nwin;       // winners this round
+    uint32_t pad[2];
     unsigned long long walk_steps, cav_tets, bnd_facets;
     unsigned long long orient, orient_exact, insphere, insphere_exact, perturbed;
     unsigned long long attempts;
@@ -60,7 +61,8 @@ struct RoundArgs {
     const Vert *V;
     uint4 *tv;                   // tetrahedron vertices (ghost in slot 3)
     uint4 *tn;                   // neighbour codes 4 t' + f'
-    unsigned long long *owner;   // claim word per tetrahedron
+    unsigned long long *own_any; // lowest claim of any attempt touching the tetrahedron
+    unsigned long long *own_cav; // lowest claim of an attempt with it in its cavity
     uint32_t *vtet;              // vertex -> a live tetrahedron containing it
     const uint32_t *anchor;      // vertex -> an earlier vertex near it on the curve
     const uint32_t *cand_pt;     // current candidate list
@@ -77,6 +79,8 @@ struct RoundArgs {
     uint32_t *outc;              // [capF][stride] outer codes, then new tetrahedra
     uint32_t *cnt;               // [2][stride] cavity size, boundary size
     uint8_t *status;             // [stride]
+    uint32_t *winners;           // [stride] candidates that won this round
+    uint32_t *w_take, *w_bump, *w_free;  // [stride] slot reservations of winners
     uint32_t *fl_cur;            // free list consumed this round
     uint32_t *fl_next;           // free list filled this round
     Ctr *ctr;
