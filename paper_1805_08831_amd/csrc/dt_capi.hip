@@ -82,8 +82,7 @@ struct dt_ctx {
     DevBuf<uint32_t> vtet, anchor;
     DevBuf<uint8_t> dup;
     uint32_t tcap = 0;
-    uint4 *tv = nullptr, *tn = nullptr;
-    unsigned long long *owner = nullptr;  // [2][tcap]: claims of any kind, cavity claims
+    Tet *T = nullptr;
     uint32_t *fl[2] = {nullptr, nullptr};
 
     uint32_t list_cap = 0;
@@ -110,6 +109,9 @@ struct dt_ctx {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     dt_stats st{};
     uint32_t trace_prev_won = 0;
+    unsigned long long trace_prev_att = 0, trace_prev_walk = 0;
+    const uint32_t *d_lvl_start = nullptr;  // level starts (global positions) of the current call
+    int cur_L = 0;
     bool trace = false;  // DT_TRACE=1 in the environment: one line per round on stderr
 };
 
@@ -170,34 +172,28 @@ int grow_tets(dt_ctx *c, uint64_t need) {
     if (need > MAX_TETS) return fail(c, DT_E_CAPACITY, "more than %u tetrahedra needed", MAX_TETS);
     uint64_t cap = std::max<uint64_t>(need, (uint64_t)c->tcap + c->tcap / 2);
     cap = std::min<uint64_t>(cap, MAX_TETS);
-    uint4 *tv = nullptr, *tn = nullptr;
-    unsigned long long *ow = nullptr;
+    Tet *T = nullptr;
     uint32_t *f0 = nullptr, *f1 = nullptr;
-    bool ok = hipMalloc((void **)&tv, cap * sizeof(uint4)) == hipSuccess &&
-              hipMalloc((void **)&tn, cap * sizeof(uint4)) == hipSuccess &&
-              hipMalloc((void **)&ow, 2 * cap * sizeof(unsigned long long)) == hipSuccess &&
+    bool ok = hipMalloc((void **)&T, cap * sizeof(Tet)) == hipSuccess &&
               hipMalloc((void **)&f0, cap * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void **)&f1, cap * sizeof(uint32_t)) == hipSuccess;
     if (!ok) {
         hipGetLastError();
-        hipFree(tv); hipFree(tn); hipFree(ow); hipFree(f0); hipFree(f1);
+        hipFree(T); hipFree(f0); hipFree(f1);
         return fail(c, DT_E_CAPACITY, "device allocation for %llu tetrahedra failed", (unsigned long long)cap);
     }
-    HIPCHK(hipMemsetAsync(ow, 0xFF, 2 * cap * sizeof(unsigned long long), c->stream));
+    // claim words start above every stamp
+    HIPCHK(hipMemsetAsync(T, 0xFF, cap * sizeof(Tet), c->stream));
     if (c->tcap) {
         uint64_t used = c->hctr->tet_count;
-        HIPCHK(hipMemcpyAsync(tv, c->tv, used * sizeof(uint4), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(tn, c->tn, used * sizeof(uint4), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(ow, c->owner, used * sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(ow + cap, c->owner + c->tcap, used * sizeof(unsigned long long),
-                              hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(T, c->T, used * sizeof(Tet), hipMemcpyDeviceToDevice, c->stream));
         uint64_t nf = c->hctr->fl_n;
         HIPCHK(hipMemcpyAsync(c->fl_idx == 0 ? f0 : f1, c->fl[c->fl_idx], nf * sizeof(uint32_t),
                               hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        hipFree(c->tv); hipFree(c->tn); hipFree(c->owner); hipFree(c->fl[0]); hipFree(c->fl[1]);
+        hipFree(c->T); hipFree(c->fl[0]); hipFree(c->fl[1]);
     }
-    c->tv = tv; c->tn = tn; c->owner = ow; c->fl[0] = f0; c->fl[1] = f1;
+    c->T = T; c->fl[0] = f0; c->fl[1] = f1;
     c->tcap = (uint32_t)cap;
     return DT_OK;
 }
@@ -309,10 +305,9 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     Ctr *d = c->ctr;
     RoundArgs a{};
     a.V = c->V.p;
-    a.tv = c->tv;
-    a.tn = c->tn;
-    a.own_any = c->owner;
-    a.own_cav = c->owner + c->tcap;
+    a.T = c->T;
+    a.lvl_start = c->d_lvl_start;
+    a.L = c->cur_L;
     a.winners = c->winners;
     a.w_take = c->w_take;
     a.w_bump = c->w_bump;
@@ -351,16 +346,18 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     c->st.rounds++;
     if (c->trace) {
         uint32_t &prev_won = c->trace_prev_won;
-        if (prev_won > c->hctr->won) prev_won = 0;
+        if (prev_won > c->hctr->won) prev_won = 0, c->trace_prev_att = c->trace_prev_walk = 0;
         float a = 0.f, b = 0.f;
         if (c->opt.timing && max_cand) {
             hipEventElapsedTime(&a, c->ev[0], c->ev[1]);
             hipEventElapsedTime(&b, c->ev[1], c->ev[2]);
         }
-        fprintf(stderr, "round %llu cand<=%u won=%u tets=%u free=%u cavity_ms=%.3f ball_ms=%.3f\n",
+        fprintf(stderr, "round %llu cand<=%u won=%u tets=%u free=%u cavity_ms=%.3f ball_ms=%.3f att=%llu walk=%llu\n",
                 (unsigned long long)c->st.rounds, max_cand, c->hctr->won - prev_won, c->hctr->tet_count,
-                c->hctr->fl_n, a, b);
+                c->hctr->fl_n, a, b, c->hctr->attempts - c->trace_prev_att, c->hctr->walk_steps - c->trace_prev_walk);
         prev_won = c->hctr->won;
+        c->trace_prev_att = c->hctr->attempts;
+        c->trace_prev_walk = c->hctr->walk_steps;
     }
     return check_errors(c);
 }
@@ -541,7 +538,7 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
         rc = DT_E_DEVICE;
     }
     c->capC = c->opt.cavity_cap ? c->opt.cavity_cap : DEFAULT_CAVITY_CAP;
-    c->capF = 2 * c->capC;
+    c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
     if (!rc && (hipMalloc((void **)&c->ctr, sizeof(Ctr)) != hipSuccess ||
                 hipHostMalloc((void **)&c->hctr, sizeof(Ctr), hipHostMallocDefault) != hipSuccess))
         rc = DT_E_DEVICE;
@@ -610,13 +607,13 @@ int dt_insert_points(dt_ctx *c, const double *xyz, uint64_t n) {
         if (c->tcap == 0 || c->tcap < 7 * n + 4096) {
             uint64_t want = c->opt.capacity_tets ? c->opt.capacity_tets : (uint64_t)(6.9 * (double)n) + 65536;
             if (c->tcap) {
-                hipFree(c->tv); hipFree(c->tn); hipFree(c->owner); hipFree(c->fl[0]); hipFree(c->fl[1]);
+                hipFree(c->T); hipFree(c->fl[0]); hipFree(c->fl[1]);
                 c->tcap = 0;
             }
             if ((rc = grow_tets(c, std::max<uint64_t>(want, 4096)))) return rc;
         }
         HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
-        HIPCHK(launch_init(c->V.p, (uint32_t)base, (uint32_t)n, c->dup.p, c->tv, c->tn, c->vtet.p, c->ctr, c->stream));
+        HIPCHK(launch_init(c->V.p, (uint32_t)base, (uint32_t)n, c->dup.p, c->T, c->vtet.p, c->ctr, c->stream));
         if ((rc = sync_ctr(c))) return rc;
         if (c->hctr->error & ERR_DEGENERATE)
             return fail(c, DT_E_DEGENERATE, "fewer than four affinely independent distinct points");
@@ -628,6 +625,8 @@ int dt_insert_points(dt_ctx *c, const double *xyz, uint64_t n) {
     unsigned long long *d_rb;
     if ((rc = upload_levels(c, lv, &d_sl, &d_sg, &d_size, &d_bits, &d_prev, &d_rb))) return rc;
     HIPCHK(launch_anchor(skeys, n, base, m, d_sl, d_prev, L, c->init_v0, c->anchor.p, c->stream));
+    c->d_lvl_start = d_sg;
+    c->cur_L = L;
     if ((rc = sync_ctr(c))) return rc;
     c->st.duplicates += c->hctr->dups;
     auto t1 = std::chrono::steady_clock::now();
@@ -659,7 +658,7 @@ int dt_get_tets(dt_ctx *c, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets) {
     if ((rc = ensure(c, c->oflags, count)) || (rc = ensure(c, c->omap, count + 1)) ||
         (rc = ensure(c, c->scan_tmp, scan_tmp_entries(count) + 64)))
         return rc;
-    HIPCHK(launch_output_flags(c->tv, count, c->oflags.p, c->stream));
+    HIPCHK(launch_output_flags(c->T, count, c->oflags.p, c->stream));
     HIPCHK(exclusive_scan_u32(c->oflags.p, c->omap.p, count, c->scan_tmp.p, c->omap.p + count, c->stream));
     uint32_t T = 0;
     HIPCHK(hipMemcpyAsync(&T, c->omap.p + count, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
@@ -685,7 +684,7 @@ int dt_get_tets(dt_ctx *c, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets) {
         if ((rc = ensure(c, c->onbrs, 4 * (size_t)T + 4))) return rc;
         on = c->onbrs.p;
     }
-    HIPCHK(launch_output(c->tv, c->tn, c->V.p, c->omap.p, count, ot, on, c->stream));
+    HIPCHK(launch_output(c->T, c->V.p, c->omap.p, count, ot, on, c->stream));
     if (tets && !dev_t)
         HIPCHK(hipMemcpyAsync(tets, ot, 4 * (size_t)T * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     if (nbrs && !dev_n)
@@ -714,7 +713,7 @@ int dt_destroy(dt_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     auto f = [](void *p) { if (p) hipFree(p); };
     f(c->V.p); f(c->vtet.p); f(c->anchor.p); f(c->dup.p);
-    f(c->tv); f(c->tn); f(c->owner); f(c->fl[0]); f(c->fl[1]);
+    f(c->T); f(c->fl[0]); f(c->fl[1]);
     for (int k = 0; k < 4; ++k) { f(c->lpt[k]); f(c->lrank[k]); }
     f(c->cav); f(c->bnd); f(c->outc); f(c->cnt); f(c->status);
     f(c->winners); f(c->w_take); f(c->w_bump); f(c->w_free);

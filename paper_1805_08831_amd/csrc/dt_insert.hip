@@ -5,7 +5,7 @@
 //   k_cavity : Walk (visibility walk, Sec. 2.1) from a live tetrahedron near the point's
 //              curve anchor, then Cavity (breadth-first search by perturbed insphere,
 //              ghosts by the half-space + circumdisk rule of Sec. 2.6).  Every tetrahedron
-//              the search touches is claimed with atomicMin on its 64-bit owner word:
+//              the search touches is claimed with atomicMin on 64-bit claim words:
 //              stamp S = (round part, 2 rank) for cavity tetrahedra, S + 1 for tetrahedra
 //              found outside.  Meeting a lower stamp ends the attempt at once.
 //   k_ball   : an attempt wins iff every tetrahedron it touched still holds its stamp, so
@@ -27,6 +27,7 @@
 namespace dtk {
 
 constexpr uint32_t WALK_LIMIT = 1u << 20;
+constexpr int HINT_RANGE = 4;
 
 __device__ __forceinline__ P3 vpos(const Vert *V, uint32_t v) {
     Vert r = V[v];
@@ -35,6 +36,11 @@ __device__ __forceinline__ P3 vpos(const Vert *V, uint32_t v) {
 
 __device__ __forceinline__ uint32_t comp(uint4 q, int k) {
     return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w));
+}
+
+// neighbour code of facet f of tetrahedron t, as a 4-byte lvalue
+__device__ __forceinline__ uint32_t &nref(Tet *T, uint32_t t, uint32_t f) {
+    return reinterpret_cast<uint32_t *>(&T[t].n)[f];
 }
 
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
@@ -73,7 +79,7 @@ __device__ __forceinline__ int orient_new_tet(uint32_t w[4], int j) {
 // ------------------------------------------------------------------ initial tetrahedron
 
 __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, const uint8_t *__restrict__ dup,
-                       uint4 *__restrict__ tv, uint4 *__restrict__ tn, uint32_t *__restrict__ vtet,
+                       Tet *__restrict__ T, uint32_t *__restrict__ vtet,
                        Ctr *__restrict__ ctr) {
     __shared__ uint32_t sel[4];
     __shared__ uint32_t best;
@@ -105,13 +111,13 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
     if (orient3d(vpos(V, v[0]), vpos(V, v[1]), vpos(V, v[2]), vpos(V, v[3]), st) < 0) {
         uint32_t t = v[0]; v[0] = v[1]; v[1] = t;
     }
-    uint32_t T[5][4], N[5][4];
-    for (int k = 0; k < 4; ++k) T[0][k] = v[k];
+    uint32_t TV[5][4], N[5][4];
+    for (int k = 0; k < 4; ++k) TV[0][k] = v[k];
     for (int j = 0; j < 4; ++j) {
         uint32_t w[4] = {v[0], v[1], v[2], v[3]};
         w[j] = GHOST;
         orient_new_tet(w, j);  // G ends in slot 3: finite facet (w0,w1,w2) faces outward
-        for (int k = 0; k < 4; ++k) T[1 + j][k] = w[k];
+        for (int k = 0; k < 4; ++k) TV[1 + j][k] = w[k];
         N[0][j] = ((1u + j) << 2) | 3u;
         N[1 + j][3] = (0u << 2) | (uint32_t)j;
     }
@@ -125,14 +131,18 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
                     for (int i = 0; i < 4; ++i) {
                         if (i == f1) continue;
                         for (int k = 0; k < 4; ++k)
-                            if (k != f2 && T[g2][k] == T[g1][i]) same++;
+                            if (k != f2 && TV[g2][k] == TV[g1][i]) same++;
                     }
                     if (same == 3) N[g1][f1] = ((uint32_t)g2 << 2) | (uint32_t)f2;
                 }
             }
     for (int t = 0; t < 5; ++t) {
-        tv[t] = make_uint4(T[t][0], T[t][1], T[t][2], T[t][3]);
-        tn[t] = make_uint4(N[t][0], N[t][1], N[t][2], N[t][3]);
+        Tet r;
+        r.v = make_uint4(TV[t][0], TV[t][1], TV[t][2], TV[t][3]);
+        r.n = make_uint4(N[t][0], N[t][1], N[t][2], N[t][3]);
+        r.any = r.cav = ~0ull;
+        r.spare[0] = r.spare[1] = 0;
+        T[t] = r;
     }
     for (int k = 0; k < 4; ++k) {
         vtet[v[k]] = 0;
@@ -141,9 +151,9 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
     ctr->tet_count = 5;
 }
 
-hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, uint4 *tv, uint4 *tn,
-                       uint32_t *vtet, Ctr *ctr, hipStream_t s) {
-    k_init<<<1, 256, 0, s>>>(V, base, n, dup, tv, tn, vtet, ctr);
+hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, Tet *T, uint32_t *vtet,
+                       Ctr *ctr, hipStream_t s) {
+    k_init<<<1, 256, 0, s>>>(V, base, n, dup, T, vtet, ctr);
     return hipGetLastError();
 }
 
@@ -185,29 +195,24 @@ hipError_t launch_fill_list(const uint32_t *lvl_start, const uint32_t *lvl_size,
 
 // ------------------------------------------------------------------ walk + cavity + claim
 
-struct TetView {
-    const Vert *V;
-    const uint4 *tv;
-    const uint4 *tn;
-};
 
 // perturbed "P strictly inside the circumsphere of finite tetrahedron w"
 __device__ __forceinline__ bool finite_inside(const Vert *V, uint4 w, P3 P, unsigned long long pidx,
                                               PredStats &st) {
-    Vert a = V[w.x], b = V[w.y], c = V[w.z], d = V[w.w];
-    return insphere_perturbed({a.x, a.y, a.z}, {b.x, b.y, b.z}, {c.x, c.y, c.z}, {d.x, d.y, d.z}, P, a.idx, b.idx,
-                              c.idx, d.idx, pidx, st) < 0;
+    const uint32_t ids[4] = {w.x, w.y, w.z, w.w};
+    return insphere_perturbed(vpos(V, w.x), vpos(V, w.y), vpos(V, w.z), vpos(V, w.w), P,
+                              [&](int k) { return k < 4 ? V[ids[k]].idx : pidx; }, st) < 0;
 }
 
 // Sec. 2.6: a ghost (a,b,c,G) contains the open half-space beyond abc and abc's circumdisk
 __device__ __forceinline__ bool tet_inside(const RoundArgs &a, uint32_t u, P3 P, unsigned long long pidx,
                                            PredStats &st) {
-    uint4 w = a.tv[u];
+    uint4 w = a.T[u].v;
     if (w.w != GHOST) return finite_inside(a.V, w, P, pidx, st);
     int o = orient3d(vpos(a.V, w.x), vpos(a.V, w.y), vpos(a.V, w.z), P, st);
     if (o != 0) return o > 0;
-    uint32_t x = a.tn[u].w >> 2;
-    return finite_inside(a.V, a.tv[x], P, pidx, st);
+    uint32_t x = a.T[u].n.w >> 2;
+    return finite_inside(a.V, a.T[x].v, P, pidx, st);
 }
 
 __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
@@ -223,38 +228,53 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
         const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
         const Vert pv = a.V[p];
         const P3 P = {pv.x, pv.y, pv.z};
-        // start: a live tetrahedron of the nearest inserted anchor
-        uint32_t av = a.anchor[p];
-        uint32_t t = a.vtet[av];
-        while (t == NONE) {
-            av = a.anchor[av];
+        // start: a live tetrahedron of the nearest inserted point on the curve among the
+        // HINT_RANGE points on either side in the same level, else of the anchor chain
+        uint32_t lo = a.lvl_start[0], hi = a.lvl_start[a.L];
+        for (int k = 1; k < a.L; ++k) {
+            if (a.lvl_start[k] <= p) lo = a.lvl_start[k];
+            if (a.lvl_start[k] > p && a.lvl_start[k] < hi) hi = a.lvl_start[k];
+        }
+        uint32_t t = NONE;
+        uint32_t near[2 * HINT_RANGE];
+        for (int d = 1; d <= HINT_RANGE; ++d) {
+            near[2 * d - 2] = p >= lo + d ? a.vtet[p - d] : NONE;
+            near[2 * d - 1] = p + d < hi ? a.vtet[p + d] : NONE;
+        }
+        for (int k = 0; k < 2 * HINT_RANGE && t == NONE; ++k) t = near[k];
+        if (t == NONE) {
+            uint32_t av = a.anchor[p];
             t = a.vtet[av];
+            while (t == NONE) {
+                av = a.anchor[av];
+                t = a.vtet[av];
+            }
         }
-        uint4 w = a.tv[t];
+        uint4 w = a.T[t].v;
         if (w.w == GHOST) {
-            t = a.tn[t].w >> 2;
-            w = a.tv[t];
+            t = a.T[t].n.w >> 2;
+            w = a.T[t].v;
         }
-        // Walk
+        // Walk.  The current tetrahedron's vertex ids and positions are kept; after crossing
+        // a facet only the apex of the next tetrahedron is fetched.
         int entry = -1;
         bool in_ghost = false;
-        P3 q0, q1, q2, q3;
+        uint32_t id[4] = {w.x, w.y, w.z, w.w};
+        P3 q[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = vpos(a.V, id[k]);
         for (;;) {
-            q0 = vpos(a.V, w.x);
-            q1 = vpos(a.V, w.y);
-            q2 = vpos(a.V, w.z);
-            q3 = vpos(a.V, w.w);
-            const uint4 nn = a.tn[t];
+            const uint4 nn = a.T[t].n;
             int moved = -1;
             const int rot = (int)((p + steps) & 3u);
             for (int jj = 0; jj < 4; ++jj) {
                 const int j = (jj + rot) & 3;
                 if (j == entry) continue;
                 int o;
-                if (j == 0) o = orient3d(P, q1, q2, q3, st);
-                else if (j == 1) o = orient3d(q0, P, q2, q3, st);
-                else if (j == 2) o = orient3d(q0, q1, P, q3, st);
-                else o = orient3d(q0, q1, q2, P, st);
+                if (j == 0) o = orient3d(P, q[1], q[2], q[3], st);
+                else if (j == 1) o = orient3d(q[0], P, q[2], q[3], st);
+                else if (j == 2) o = orient3d(q[0], q[1], P, q[3], st);
+                else o = orient3d(q[0], q[1], q[2], P, st);
                 if (o < 0) {
                     moved = j;
                     break;
@@ -264,7 +284,7 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
             const uint32_t code = comp(nn, moved);
             t = code >> 2;
             entry = (int)(code & 3u);
-            w = a.tv[t];
+            w = a.T[t].v;
             if (++steps > WALK_LIMIT) {
                 status = ST_ERROR;
                 break;
@@ -273,9 +293,27 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
                 in_ghost = true;
                 break;
             }
+            const uint32_t id2[4] = {w.x, w.y, w.z, w.w};
+            P3 q2[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                q2[k] = q[0];
+#pragma unroll
+                for (int m = 1; m < 4; ++m)
+                    if (id[m] == id2[k]) q2[k] = q[m];
+            }
+            // the apex (opposite the entry facet) is the one new vertex
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k == entry) q2[k] = vpos(a.V, id2[k]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                id[k] = id2[k];
+                q[k] = q2[k];
+            }
         }
         if (status == ST_NONE && !in_ghost) {
-            const P3 q[4] = {q0, q1, q2, q3};
+#pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (q[k].x == P.x && q[k].y == P.y && q[k].z == P.z) status = ST_DUP;
         }
@@ -283,60 +321,106 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
         if (status == ST_NONE) {
             // Cavity: breadth-first search; cav entries hold (tetrahedron << 2 | facet it was
             // entered through), which is skipped when the tetrahedron is expanded.
-            // Claims: own_any[t] = min stamp of every attempt touching t, S for this cavity's
+            // Claims: T[t].any = min stamp of every attempt touching t, S for this cavity's
             // tetrahedra and S + 1 for those found outside (so the parity tells the kind);
-            // own_cav[t] = min stamp of the attempts with t in their cavity.
+            // T[t].cav = min stamp of the attempts with t in their cavity.  All neighbours of
+            // a cavity tetrahedron are claimed tentatively (S + 1) and fetched together; a
+            // neighbour of a finite cavity tetrahedron c shares the facet's three vertices
+            // with c, so only its apex vertex is fetched.
             {
-                const unsigned long long o0 = atomicMin(&a.own_any[t], S);
+                const unsigned long long o0 = atomicMin(&a.T[t].any, S);
                 if (o0 < S) {
                     status = ST_CONFLICT;
                 } else {
-                    atomicMin(&a.own_cav[t], S);
-                    a.cav[i] = t << 2;
+                    atomicMin(&a.T[t].cav, S);
+                    a.cav[(size_t)i * a.capC] = t << 2;
                     ncav = 1;
                 }
             }
             for (uint32_t k = 0; k < ncav && status == ST_NONE; ++k) {
-                const uint32_t code = a.cav[(size_t)k * stride + i];
+                const uint32_t code = a.cav[(size_t)i * a.capC + k];
                 const uint32_t c = code >> 2;
                 const int pf = k == 0 ? -1 : (int)(code & 3u);
-                const uint4 cn = a.tn[c];
+                const uint4 cv = a.T[c].v;
+                const uint4 cn = a.T[c].n;
+                const bool cghost = cv.w == GHOST;
+                unsigned long long o1[4];
+                uint4 uw[4];
+#pragma unroll
                 for (int f = 0; f < 4; ++f) {
+                    o1[f] = S;
                     if (f == pf) continue;
+                    const uint32_t u = comp(cn, f) >> 2;
+                    o1[f] = atomicMin(&a.T[u].any, S + 1);
+                    uw[f] = a.T[u].v;
+                }
+                P3 cw[4];
+                if (!cghost) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) cw[m] = vpos(a.V, comp(cv, m));
+                }
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    if (status != ST_NONE) break;
+                    const unsigned long long o = o1[f];
+                    if (o == S) continue;  // already in this cavity, or the parent: internal facet
+                    if (o < S && !(o & 1ull)) {
+                        // a lower attempt has this neighbour in its cavity: this one loses
+                        status = ST_CONFLICT;
+                        break;
+                    }
                     const uint32_t ncode = comp(cn, f);
                     const uint32_t u = ncode >> 2;
-                    const unsigned long long o1 = atomicMin(&a.own_any[u], S + 1);
-                    if (o1 == S) continue;  // already in this cavity: internal facet
                     bool inside = false;
-                    if (o1 != S + 1) {
-                        // a lower attempt has u in its cavity: this one loses whatever u is
-                        if (o1 < S && !(o1 & 1ull)) {
+                    if (o != S + 1) {
+                        const uint32_t apex = comp(uw[f], (int)(ncode & 3u));
+                        if (!cghost && apex != GHOST) {
+                            // u = facet f of c + apex; c with vertex f replaced by the apex and
+                            // two entries swapped is positively oriented
+                            P3 r[4] = {cw[0], cw[1], cw[2], cw[3]};
+                            uint32_t rid[4] = {cv.x, cv.y, cv.z, cv.w};
+                            r[f] = vpos(a.V, apex);
+                            rid[f] = apex;
+                            const P3 tmp = r[(f + 1) & 3];
+                            r[(f + 1) & 3] = r[(f + 2) & 3];
+                            r[(f + 2) & 3] = tmp;
+                            const uint32_t tid = rid[(f + 1) & 3];
+                            rid[(f + 1) & 3] = rid[(f + 2) & 3];
+                            rid[(f + 2) & 3] = tid;
+                            inside = insphere_perturbed(r[0], r[1], r[2], r[3], P,
+                                                        [&](int kk) { return kk < 4 ? a.V[rid[kk]].idx : pv.idx; },
+                                                        st) < 0;
+                        } else if (!cghost) {
+                            // u is the ghost beyond facet f of the finite cavity tetrahedron c:
+                            // inside iff p is beyond the facet, or on it (then c decides: inside)
+                            P3 r[4] = {cw[0], cw[1], cw[2], cw[3]};
+                            r[f] = P;
+                            inside = orient3d(r[0], r[1], r[2], r[3], st) <= 0;
+                        } else {
+                            inside = tet_inside(a, u, P, pv.idx, st);
+                        }
+                        if (inside && o < S) {
+                            // a lower attempt touched a tetrahedron of this cavity
                             status = ST_CONFLICT;
                             break;
                         }
-                        inside = tet_inside(a, u, P, pv.idx, st);
                     }
                     if (inside) {
-                        // u joins the cavity; a lower attempt touching it at all wins over this one
-                        const unsigned long long o2 = atomicMin(&a.own_any[u], S);
-                        if (o2 < S) {
-                            status = ST_CONFLICT;
-                            break;
-                        }
-                        atomicMin(&a.own_cav[u], S);
+                        atomicMin(&a.T[u].any, S);
+                        atomicMin(&a.T[u].cav, S);
                         if (ncav == a.capC) {
                             status = ST_OVERFLOW;
                             break;
                         }
-                        a.cav[(size_t)ncav * stride + i] = ncode;
+                        a.cav[(size_t)i * a.capC + ncav] = ncode;
                         ++ncav;
                     } else {
                         if (nbnd == a.capF) {
                             status = ST_OVERFLOW;
                             break;
                         }
-                        a.bnd[(size_t)nbnd * stride + i] = (c << 2) | (uint32_t)f;
-                        a.outc[(size_t)nbnd * stride + i] = ncode;
+                        a.bnd[(size_t)i * a.capF + nbnd] = (c << 2) | (uint32_t)f;
+                        a.outc[(size_t)i * a.capF + nbnd] = ncode;
                         ++nbnd;
                     }
                 }
@@ -364,20 +448,20 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
 __device__ uint32_t pivot(const RoundArgs &a, uint32_t c, int f, uint32_t e0, uint32_t e1, uint32_t p,
                           unsigned long long S, uint32_t limit) {
     for (uint32_t guard = 0; guard <= limit; ++guard) {
-        const uint4 cv = a.tv[c];
+        const uint4 cv = a.T[c].v;
         const uint32_t v[4] = {cv.x, cv.y, cv.z, cv.w};
         int xpos = -1;
         for (int k = 0; k < 4; ++k)
             if (k != f && v[k] != e0 && v[k] != e1) xpos = k;
         if (xpos < 0) break;
-        const uint32_t code = reinterpret_cast<const uint32_t *>(a.tn)[4 * (size_t)c + xpos];
+        const uint32_t code = comp(a.T[c].n, xpos);
         const uint32_t nt = code >> 2;
-        if (a.own_any[nt] == S) {  // another tetrahedron of this cavity
+        if (a.T[nt].any == S) {  // another tetrahedron of this cavity
             c = nt;
             f = (int)(code & 3u);
             continue;
         }
-        const uint4 nv = a.tv[nt];  // the sibling new tetrahedron
+        const uint4 nv = a.T[nt].v;  // the sibling new tetrahedron
         const uint32_t w[4] = {nv.x, nv.y, nv.z, nv.w};
         int q2 = -1;
         for (int k = 0; k < 4; ++k)
@@ -390,8 +474,8 @@ __device__ uint32_t pivot(const RoundArgs &a, uint32_t c, int f, uint32_t e0, ui
 }
 
 // Winner test and slot reservation, one thread per candidate.  An attempt wins iff it still
-// holds the lowest claim on every tetrahedron of its cavity (own_any) and no lower attempt
-// has one of its outer tetrahedra in its cavity (own_cav).  Winners of one round therefore
+// holds the lowest claim on every tetrahedron of its cavity (any) and no lower attempt
+// has one of its outer tetrahedra in its cavity (cav).  Winners of one round therefore
 // have disjoint cavities, and no cavity meets another winner's outer tetrahedra.
 __global__ __launch_bounds__(256) void k_check(RoundArgs a) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -401,8 +485,8 @@ __global__ __launch_bounds__(256) void k_check(RoundArgs a) {
     const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
     const uint32_t nc = a.cnt[i], nb = a.cnt[stride + i];
     bool win = true;
-    for (uint32_t k = 0; k < nc; ++k) win &= a.own_any[a.cav[(size_t)k * stride + i] >> 2] == S;
-    for (uint32_t k = 0; k < nb; ++k) win &= a.own_cav[a.outc[(size_t)k * stride + i] >> 2] > S;
+    for (uint32_t k = 0; k < nc; ++k) win &= a.T[a.cav[(size_t)i * a.capC + k] >> 2].any == S;
+    for (uint32_t k = 0; k < nb; ++k) win &= a.T[a.outc[(size_t)i * a.capF + k] >> 2].cav > S;
     if (!win) {
         a.status[i] = ST_CONFLICT;
         return;
@@ -416,7 +500,6 @@ __global__ __launch_bounds__(256) void k_check(RoundArgs a) {
     if (rest && bump + rest > a.tcap) {
         // pool full: give the slots back (those inside the pool are marked free) and
         // retry next round after the host has grown the pool
-        uint32_t *tv32 = reinterpret_cast<uint32_t *>(a.tv);
         uint32_t give = from_fl;
         for (uint32_t k = 0; k < rest; ++k)
             if (bump + k < a.tcap) ++give;
@@ -425,7 +508,7 @@ __global__ __launch_bounds__(256) void k_check(RoundArgs a) {
         for (uint32_t k = 0; k < from_fl; ++k) a.fl_next[fb + q++] = a.fl_cur[take + k];
         for (uint32_t k = 0; k < rest; ++k)
             if (bump + k < a.tcap) {
-                tv32[4 * (size_t)(bump + k)] = DEAD;
+                a.T[bump + k].v.x = DEAD;
                 a.fl_next[fb + q++] = bump + k;
             }
         atomicOr(&a.ctr->error, ERR_POOL);
@@ -447,8 +530,6 @@ __global__ __launch_bounds__(64) void k_build(RoundArgs a) {
     const uint32_t nwin = a.ctr->nwin;
     const uint32_t stride = a.stride;
     const uint32_t fln = a.ctr->fl_n;
-    uint32_t *tn32 = reinterpret_cast<uint32_t *>(a.tn);
-    uint32_t *tv32 = reinterpret_cast<uint32_t *>(a.tv);
     unsigned cav_w = 0, bnd_w = 0;
     for (uint32_t w = blockIdx.x; w < nwin; w += gridDim.x) {
         const uint32_t i = a.winners[w];
@@ -459,29 +540,29 @@ __global__ __launch_bounds__(64) void k_build(RoundArgs a) {
         const uint32_t from_fl = fln > take ? min(nb, fln - take) : 0u;
         for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) {
             const uint32_t slot = k < from_fl ? a.fl_cur[take + k] : bump + (k - from_fl);
-            const uint32_t bc = a.bnd[(size_t)k * stride + i];
-            const uint32_t oc = a.outc[(size_t)k * stride + i];
+            const uint32_t bc = a.bnd[(size_t)i * a.capF + k];
+            const uint32_t oc = a.outc[(size_t)i * a.capF + k];
             const uint32_t u = oc >> 2;
             const int j = (int)(oc & 3u);
-            const uint4 uw = a.tv[u];
+            const uint4 uw = a.T[u].v;
             uint32_t wv[4] = {uw.x, uw.y, uw.z, uw.w};
             wv[j] = p;
             const int pf = orient_new_tet(wv, j);
-            a.tv[slot] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+            a.T[slot].v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
             const uint32_t me = (slot << 2) | (uint32_t)pf;
-            tn32[4 * (size_t)slot + pf] = oc;              // facet opposite p: outer tetrahedron
-            tn32[4 * (size_t)u + j] = me;                  // and back
-            tn32[4 * (size_t)(bc >> 2) + (bc & 3u)] = me;  // cavity side now names the new tetrahedron
-            a.outc[(size_t)k * stride + i] = me;
+            nref(a.T, slot, pf) = oc;              // facet opposite p: outer tetrahedron
+            nref(a.T, u, j) = me;                  // and back
+            nref(a.T, bc >> 2, bc & 3u) = me;  // cavity side now names the new tetrahedron
+            a.outc[(size_t)i * a.capF + k] = me;
             if (k == 0) a.vtet[p] = slot;
         }
         __syncthreads();
         for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) {
-            const uint32_t me = a.outc[(size_t)k * stride + i];
+            const uint32_t me = a.outc[(size_t)i * a.capF + k];
             const uint32_t slot = me >> 2;
             const int pf = (int)(me & 3u);
-            const uint32_t bc = a.bnd[(size_t)k * stride + i];
-            const uint4 sw = a.tv[slot];
+            const uint32_t bc = a.bnd[(size_t)i * a.capF + k];
+            const uint4 sw = a.T[slot].v;
             const uint32_t wv[4] = {sw.x, sw.y, sw.z, sw.w};
             for (int q = 0; q < 4; ++q) {
                 if (q == pf) continue;
@@ -489,15 +570,15 @@ __global__ __launch_bounds__(64) void k_build(RoundArgs a) {
                 int ne = 0;
                 for (int r = 0; r < 4; ++r)
                     if (r != q && r != pf) e[ne++] = wv[r];
-                tn32[4 * (size_t)slot + q] = pivot(a, bc >> 2, (int)(bc & 3u), e[0], e[1], p, S, nc + 2);
+                nref(a.T, slot, q) = pivot(a, bc >> 2, (int)(bc & 3u), e[0], e[1], p, S, nc + 2);
                 if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
             }
         }
         __syncthreads();
         const uint32_t fb = a.w_free[i];
         for (uint32_t k = threadIdx.x; k < nc; k += blockDim.x) {
-            const uint32_t c = a.cav[(size_t)k * stride + i] >> 2;
-            tv32[4 * (size_t)c] = DEAD;
+            const uint32_t c = a.cav[(size_t)i * a.capC + k] >> 2;
+            a.T[c].v.x = DEAD;
             a.fl_next[fb + k] = c;
         }
         if (threadIdx.x == 0) {
@@ -510,6 +591,309 @@ __global__ __launch_bounds__(64) void k_build(RoundArgs a) {
         if (cav_w) atomicAdd(&a.ctr->cav_tets, (unsigned long long)cav_w);
         if (bnd_w) atomicAdd(&a.ctr->bnd_facets, (unsigned long long)bnd_w);
     }
+}
+
+// ------------------------------------------------------------------ 16 lanes per insertion
+
+constexpr int GS = 16;              // lanes per insertion
+constexpr int GPB = 256 / GS;       // insertions per 256-thread block
+constexpr uint32_t LCAPC = 96;      // cavity tetrahedra held in LDS per insertion
+constexpr uint32_t LCAPF = 160;     // boundary facets held in LDS per insertion
+
+// keeps the compiler from moving LDS accesses across a point where other lanes of the
+// same wave consume them (the hardware processes one wave's LDS requests in order)
+__device__ __forceinline__ void lane_fence() { __asm__ volatile("" ::: "memory"); }
+
+// Same computation as k_cavity, with 16 lanes cooperating on one insertion: the walk
+// tests the four facets of the current tetrahedron on four lanes at once, and the cavity
+// search expands four cavity tetrahedra (four facets each) per step.  Cavity and boundary
+// lists live in LDS and are appended by ballot prefix counts.  Control flow is uniform
+// within each group of 16 lanes.
+__global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
+    __shared__ uint32_t s_cav[GPB][LCAPC];
+    __shared__ uint32_t s_bnd[GPB][LCAPF];
+    __shared__ uint32_t s_out[GPB][LCAPF];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t gl = threadIdx.x & (GS - 1);
+    const uint32_t gi = threadIdx.x / GS;
+    const uint32_t gbase = lane & ~(uint32_t)(GS - 1);
+    const unsigned long long gmask = 0xFFFFull << gbase;
+    const unsigned long long below = gmask & ((1ull << lane) - 1ull);
+    const uint32_t i = blockIdx.x * GPB + gi;
+    const uint32_t ncand = *a.ncand_ptr;
+    const uint32_t stride = a.stride;
+    PredStats st;
+    unsigned steps = 0, attempt = 0;
+    if (i < ncand) {
+        uint8_t status = ST_NONE;
+        const uint32_t p = a.cand_pt[i];
+        const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
+        const Vert pv = a.V[p];
+        const P3 P = {pv.x, pv.y, pv.z};
+        // start: nearest inserted point among 8 on either side of p on the curve (same
+        // level), one probe per lane; else the anchor chain
+        uint32_t lo = a.lvl_start[0], hi = a.lvl_start[a.L];
+        for (int k = 1; k < a.L; ++k) {
+            if (a.lvl_start[k] <= p) lo = a.lvl_start[k];
+            if (a.lvl_start[k] > p && a.lvl_start[k] < hi) hi = a.lvl_start[k];
+        }
+        const uint32_t d = (gl >> 1) + 1;
+        const bool inr = (gl & 1) ? (p + d < hi) : (p >= lo + d);
+        const uint32_t ht = inr ? a.vtet[(gl & 1) ? p + d : p - d] : NONE;
+        const unsigned long long hm = __ballot(ht != NONE) & gmask;
+        uint32_t t;
+        if (hm) {
+            t = __shfl(ht, __ffsll((long long)hm) - 1);
+        } else {
+            uint32_t av = a.anchor[p];
+            t = a.vtet[av];
+            while (t == NONE) {
+                av = a.anchor[av];
+                t = a.vtet[av];
+            }
+        }
+        uint4 w = a.T[t].v;
+        if (w.w == GHOST) {
+            t = a.T[t].n.w >> 2;
+            w = a.T[t].v;
+        }
+        // Walk: lane j < 4 tests facet j
+        int entry = -1;
+        bool in_ghost = false;
+        P3 q0, q1, q2, q3;
+        const int jl = (int)(gl & 3u);
+        for (;;) {
+            q0 = vpos(a.V, w.x);
+            q1 = vpos(a.V, w.y);
+            q2 = vpos(a.V, w.z);
+            q3 = vpos(a.V, w.w);
+            const uint4 nn = a.T[t].n;
+            int o = 1;
+            if (gl < 4 && jl != entry)
+                o = orient3d(jl == 0 ? P : q0, jl == 1 ? P : q1, jl == 2 ? P : q2, jl == 3 ? P : q3, st);
+            const unsigned bits = (unsigned)((__ballot(o < 0) & gmask) >> gbase) & 0xFu;
+            if (!bits) break;
+            const unsigned rot = (p + steps) & 3u;
+            const unsigned rb = ((bits >> rot) | (bits << (4u - rot))) & 0xFu;
+            const int moved = (int)(((unsigned)__ffs(rb) - 1u + rot) & 3u);
+            const uint32_t code = comp(nn, moved);
+            t = code >> 2;
+            entry = (int)(code & 3u);
+            w = a.T[t].v;
+            if (++steps > WALK_LIMIT) {
+                status = ST_ERROR;
+                break;
+            }
+            if (w.w == GHOST) {
+                in_ghost = true;
+                break;
+            }
+        }
+        if (status == ST_NONE && !in_ghost) {
+            if ((q0.x == P.x && q0.y == P.y && q0.z == P.z) || (q1.x == P.x && q1.y == P.y && q1.z == P.z) ||
+                (q2.x == P.x && q2.y == P.y && q2.z == P.z) || (q3.x == P.x && q3.y == P.y && q3.z == P.z))
+                status = ST_DUP;
+        }
+        uint32_t ncav = 0, nbnd = 0;
+        const uint32_t capC = a.capC, capF = a.capF;
+        if (status == ST_NONE) {
+            // Cavity (same claims as k_cavity): step k expands cavity tetrahedra
+            // k0 .. k0+3, lane (slot, facet) = (gl / 4, gl % 4)
+            unsigned long long o0 = 0;
+            if (gl == 0) o0 = atomicMin(&a.T[t].any, S);
+            o0 = __shfl(o0, (int)gbase);
+            if (o0 < S) {
+                status = ST_CONFLICT;
+            } else {
+                if (gl == 0) {
+                    atomicMin(&a.T[t].cav, S);
+                    s_cav[gi][0] = t << 2;
+                }
+                ncav = 1;
+            }
+            lane_fence();
+            for (uint32_t k0 = 0, nproc = 0; k0 < ncav && status == ST_NONE; k0 += nproc) {
+                nproc = min(4u, ncav - k0);  // entries expanded in this step
+                const uint32_t slot = k0 + (gl >> 2);
+                const int f = jl;
+                const bool lv = slot < k0 + nproc;
+                const uint32_t code = lv ? s_cav[gi][slot] : 0u;
+                const uint32_t c = code >> 2;
+                const int pf = slot == 0 ? -1 : (int)(code & 3u);
+                const bool act = lv && f != pf;
+                uint4 cv = make_uint4(0u, 0u, 0u, 0u), cn = cv, uw = cv;
+                if (lv) {
+                    cv = a.T[c].v;
+                    cn = a.T[c].n;
+                }
+                const uint32_t ncode = comp(cn, f);
+                const uint32_t u = ncode >> 2;
+                unsigned long long o1 = S;
+                if (act) {
+                    o1 = atomicMin(&a.T[u].any, S + 1);
+                    uw = a.T[u].v;
+                }
+                const bool lower_cav = act && o1 < S && !(o1 & 1ull);
+                const bool need = act && o1 != S && !lower_cav;
+                bool inside = false;
+                if (need) {
+                    const bool cghost = cv.w == GHOST;
+                    const uint32_t apex = comp(uw, (int)(ncode & 3u));
+                    if (!cghost && apex != GHOST) {
+                        // u = facet f of c + apex; c with vertex f replaced by the apex and
+                        // two entries swapped is positively oriented
+                        const uint32_t cid[4] = {cv.x, cv.y, cv.z, cv.w};
+                        uint32_t rid[4];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) rid[m] = m == f ? apex : cid[m];
+                        const int sa = (f + 1) & 3, sb = (f + 2) & 3;
+                        uint32_t r2[4];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) r2[m] = m == sa ? rid[sb] : (m == sb ? rid[sa] : rid[m]);
+                        inside = insphere_perturbed(vpos(a.V, r2[0]), vpos(a.V, r2[1]), vpos(a.V, r2[2]),
+                                                    vpos(a.V, r2[3]), P,
+                                                    [&](int kk) { return kk < 4 ? a.V[r2[kk]].idx : pv.idx; },
+                                                    st) < 0;
+                    } else if (!cghost) {
+                        // u is the ghost beyond facet f of the finite cavity tetrahedron c:
+                        // inside iff p is beyond the facet, or on it (then c decides: inside)
+                        const P3 c0 = vpos(a.V, cv.x), c1 = vpos(a.V, cv.y), c2 = vpos(a.V, cv.z),
+                                 c3 = vpos(a.V, cv.w);
+                        inside = orient3d(f == 0 ? P : c0, f == 1 ? P : c1, f == 2 ? P : c2, f == 3 ? P : c3, st) <= 0;
+                    } else {
+                        inside = tet_inside(a, u, P, pv.idx, st);
+                    }
+                }
+                const bool conflict = lower_cav || (inside && o1 < S);
+                if (__ballot(conflict) & gmask) {
+                    status = ST_CONFLICT;
+                    break;
+                }
+                // a tetrahedron reached through several facets in this step is added once
+                bool first = inside;
+                for (int m = 0; m < GS; ++m) {
+                    const uint32_t um = __shfl(u, (int)gbase + m);
+                    const int im = __shfl((int)inside, (int)gbase + m);
+                    if ((uint32_t)m < gl && im && um == u) first = false;
+                }
+                const bool outside = need && !inside;
+                const unsigned long long mi = __ballot(first) & gmask;
+                const unsigned long long mo = __ballot(outside) & gmask;
+                const uint32_t ni = (uint32_t)__popcll(mi), no = (uint32_t)__popcll(mo);
+                if (ncav + ni > capC || nbnd + no > capF) {
+                    status = ST_OVERFLOW;
+                    break;
+                }
+                if (first) {
+                    s_cav[gi][ncav + __popcll(mi & below)] = ncode;
+                    atomicMin(&a.T[u].any, S);
+                    atomicMin(&a.T[u].cav, S);
+                }
+                if (outside) {
+                    const uint32_t pos = nbnd + (uint32_t)__popcll(mo & below);
+                    s_bnd[gi][pos] = (c << 2) | (uint32_t)f;
+                    s_out[gi][pos] = ncode;
+                }
+                ncav += ni;
+                nbnd += no;
+                lane_fence();
+            }
+            if (status == ST_NONE) status = ST_CAND;
+        }
+        if (status == ST_CAND) {
+            for (uint32_t k = gl; k < ncav; k += GS) a.cav[(size_t)i * capC + k] = s_cav[gi][k];
+            for (uint32_t k = gl; k < nbnd; k += GS) {
+                a.bnd[(size_t)i * capF + k] = s_bnd[gi][k];
+                a.outc[(size_t)i * capF + k] = s_out[gi][k];
+            }
+        }
+        if (gl == 0) {
+            a.status[i] = status;
+            a.cnt[i] = ncav;
+            a.cnt[stride + i] = nbnd;
+            attempt = 1;
+        } else {
+            steps = 0;
+        }
+    }
+    add_stat(&a.ctr->attempts, attempt);
+    add_stat(&a.ctr->walk_steps, steps);
+    add_stat(&a.ctr->orient, st.orient);
+    add_stat(&a.ctr->orient_exact, st.orient_exact);
+    add_stat(&a.ctr->insphere, st.insphere);
+    add_stat(&a.ctr->insphere_exact, st.insphere_exact);
+    add_stat(&a.ctr->perturbed, st.perturbed);
+}
+
+// DelaunayBall with 16 lanes per winner (16 winners per block): the same three phases as
+// k_build; the three pivots of each new tetrahedron are spread over the lanes.
+__global__ __launch_bounds__(256) void k_build16(RoundArgs a) {
+    const uint32_t nwin = a.ctr->nwin;
+    const uint32_t stride = a.stride;
+    const uint32_t fln = a.ctr->fl_n;
+    const uint32_t gl = threadIdx.x & (GS - 1);
+    const uint32_t gi = threadIdx.x / GS;
+    const uint32_t capC = a.capC, capF = a.capF;
+    unsigned cav_w = 0, bnd_w = 0;
+    for (uint32_t base = blockIdx.x * GPB; base < nwin; base += gridDim.x * GPB) {
+        const uint32_t w = base + gi;
+        const bool act = w < nwin;
+        const uint32_t i = act ? a.winners[w] : 0u;
+        const uint32_t p = act ? a.cand_pt[i] : 0u;
+        const unsigned long long S = act ? (a.round_hi | (2ull * a.cand_rank[i])) : 0ull;
+        const uint32_t nc = act ? a.cnt[i] : 0u, nb = act ? a.cnt[stride + i] : 0u;
+        const uint32_t take = act ? a.w_take[i] : 0u, bump = act ? a.w_bump[i] : 0u;
+        const uint32_t from_fl = fln > take ? min(nb, fln - take) : 0u;
+        for (uint32_t k = gl; k < nb; k += GS) {
+            const uint32_t slot = k < from_fl ? a.fl_cur[take + k] : bump + (k - from_fl);
+            const uint32_t bc = a.bnd[(size_t)i * capF + k];
+            const uint32_t oc = a.outc[(size_t)i * capF + k];
+            const uint32_t u = oc >> 2;
+            const int j = (int)(oc & 3u);
+            const uint4 uw = a.T[u].v;
+            uint32_t wv[4] = {uw.x, uw.y, uw.z, uw.w};
+            wv[j] = p;
+            const int pf = orient_new_tet(wv, j);
+            a.T[slot].v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+            const uint32_t me = (slot << 2) | (uint32_t)pf;
+            nref(a.T, slot, pf) = oc;             // facet opposite p: outer tetrahedron
+            nref(a.T, u, j) = me;                 // and back
+            nref(a.T, bc >> 2, bc & 3u) = me;     // cavity side now names the new tetrahedron
+            a.outc[(size_t)i * capF + k] = me;
+            if (k == 0) a.vtet[p] = slot;
+        }
+        __syncthreads();
+        for (uint32_t task = gl; task < 3 * nb; task += GS) {
+            const uint32_t k = task / 3, qi = task - 3 * k;
+            const uint32_t me = a.outc[(size_t)i * capF + k];
+            const uint32_t slot = me >> 2;
+            const int pf = (int)(me & 3u);
+            const int q = (pf + 1 + (int)qi) & 3;  // the three facets through p
+            const uint32_t bc = a.bnd[(size_t)i * capF + k];
+            const uint4 sw = a.T[slot].v;
+            const uint32_t wv[4] = {sw.x, sw.y, sw.z, sw.w};
+            uint32_t e[2];
+            int ne = 0;
+            for (int r = 0; r < 4; ++r)
+                if (r != q && r != pf) e[ne++] = wv[r];
+            nref(a.T, slot, q) = pivot(a, bc >> 2, (int)(bc & 3u), e[0], e[1], p, S, nc + 2);
+            if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
+        }
+        __syncthreads();
+        const uint32_t fb = act ? a.w_free[i] : 0u;
+        for (uint32_t k = gl; k < nc; k += GS) {
+            const uint32_t c = a.cav[(size_t)i * capC + k] >> 2;
+            a.T[c].v.x = DEAD;
+            a.fl_next[fb + k] = c;
+        }
+        if (gl == 0) {
+            cav_w += nc;
+            bnd_w += nb;
+        }
+        __syncthreads();
+    }
+    add_stat(&a.ctr->cav_tets, cav_w);
+    add_stat(&a.ctr->bnd_facets, bnd_w);
 }
 
 // ------------------------------------------------------------------ round end
@@ -557,14 +941,23 @@ __global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap) {
     *consumed = 0;  // the list this round read from is empty now
 }
 
+bool round_fits_lds(uint32_t capC, uint32_t capF) { return capC <= LCAPC && capF <= LCAPF; }
+
 hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, hipStream_t s, hipEvent_t *ev) {
     if (max_cand == 0) return hipSuccess;
     const unsigned nb = (max_cand + 255) / 256;
+    const bool grouped = round_fits_lds(a.capC, a.capF);
     if (ev) hipEventRecord(ev[0], s);
-    k_cavity<<<nb, 256, 0, s>>>(a);
+    if (grouped) k_cavity16<<<(max_cand + GPB - 1) / GPB, 256, 0, s>>>(a);
+    else k_cavity<<<nb, 256, 0, s>>>(a);
     if (ev) hipEventRecord(ev[1], s);
     k_check<<<nb, 256, 0, s>>>(a);
-    k_build<<<max_cand < 16384u ? max_cand : 16384u, 64, 0, s>>>(a);
+    if (grouped) {
+        const unsigned gb = (max_cand + GPB - 1) / GPB;
+        k_build16<<<gb < 4096u ? gb : 4096u, 256, 0, s>>>(a);
+    } else {
+        k_build<<<max_cand < 16384u ? max_cand : 16384u, 64, 0, s>>>(a);
+    }
     if (ev) hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
@@ -579,25 +972,25 @@ hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, bool big, hip
 
 // ------------------------------------------------------------------ output
 
-__global__ void k_out_flags(const uint4 *__restrict__ tv, uint32_t count, uint32_t *__restrict__ flags) {
+__global__ void k_out_flags(const Tet *__restrict__ T, uint32_t count, uint32_t *__restrict__ flags) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
-    const uint4 w = tv[t];
+    const uint4 w = T[t].v;
     flags[t] = (w.x != DEAD && w.w != GHOST) ? 1u : 0u;
 }
 
-hipError_t launch_output_flags(const uint4 *tv, uint32_t count, uint32_t *flags, hipStream_t s) {
+hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    k_out_flags<<<(count + 255) / 256, 256, 0, s>>>(tv, count, flags);
+    k_out_flags<<<(count + 255) / 256, 256, 0, s>>>(T, count, flags);
     return hipGetLastError();
 }
 
-__global__ void k_output(const uint4 *__restrict__ tv, const uint4 *__restrict__ tn, const Vert *__restrict__ V,
+__global__ void k_output(const Tet *__restrict__ T, const Vert *__restrict__ V,
                          const uint32_t *__restrict__ map, uint32_t count, uint32_t *__restrict__ tets,
                          int64_t *__restrict__ nbrs) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
-    const uint4 w = tv[t];
+    const uint4 w = T[t].v;
     if (w.x == DEAD || w.w == GHOST) return;
     const uint32_t o = map[t];
     if (tets) {
@@ -607,18 +1000,18 @@ __global__ void k_output(const uint4 *__restrict__ tv, const uint4 *__restrict__
         tets[4 * (size_t)o + 3] = (uint32_t)V[w.w].idx;
     }
     if (nbrs) {
-        const uint4 nn = tn[t];
+        const uint4 nn = T[t].n;
         for (int k = 0; k < 4; ++k) {
             const uint32_t nt = comp(nn, k) >> 2;
-            nbrs[4 * (size_t)o + k] = tv[nt].w == GHOST ? -1 : (int64_t)map[nt];
+            nbrs[4 * (size_t)o + k] = T[nt].v.w == GHOST ? -1 : (int64_t)map[nt];
         }
     }
 }
 
-hipError_t launch_output(const uint4 *tv, const uint4 *tn, const Vert *V, const uint32_t *map, uint32_t count,
-                         uint32_t *tets, int64_t *nbrs, hipStream_t s) {
+hipError_t launch_output(const Tet *T, const Vert *V, const uint32_t *map, uint32_t count, uint32_t *tets,
+                         int64_t *nbrs, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    k_output<<<(count + 255) / 256, 256, 0, s>>>(tv, tn, V, map, count, tets, nbrs);
+    k_output<<<(count + 255) / 256, 256, 0, s>>>(T, V, map, count, tets, nbrs);
     return hipGetLastError();
 }
 
@@ -636,9 +1029,8 @@ __global__ void k_predicates(int kind, const double *__restrict__ pts, const int
     if (kind == 0) s = orient3d(q[0], q[1], q[2], q[3], st);
     else if (kind == 1) s = insphere_raw(q[0], q[1], q[2], q[3], q[4], st);
     else
-        s = insphere_perturbed(q[0], q[1], q[2], q[3], q[4], (unsigned long long)idx[5 * r],
-                               (unsigned long long)idx[5 * r + 1], (unsigned long long)idx[5 * r + 2],
-                               (unsigned long long)idx[5 * r + 3], (unsigned long long)idx[5 * r + 4], st);
+        s = insphere_perturbed(q[0], q[1], q[2], q[3], q[4],
+                               [&](int k) { return (unsigned long long)idx[5 * r + k]; }, st);
     out[r] = (int8_t)s;
 }
 

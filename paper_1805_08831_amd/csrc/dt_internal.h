@@ -17,6 +17,17 @@ struct __align__(32) Vert {
     unsigned long long idx;
 };
 
+// One tetrahedron: 64 bytes, so that a visit touches one cache line.  Facet j is opposite
+// v[j]; n[j] = 4 t' + f' names the neighbour across it (Sec. 2.2, adjacency code).  The
+// two claim words of the concurrent rounds live in the same record.
+struct __align__(64) Tet {
+    uint4 v;                    // vertex ids (ghost in slot 3); v.x = DEAD once freed
+    uint4 n;                    // neighbour codes
+    unsigned long long any;     // lowest claim of any attempt touching the tetrahedron
+    unsigned long long cav;     // lowest claim of an attempt with it in its cavity
+    unsigned long long spare[2];
+};
+
 // candidate status after a round
 enum : uint8_t {
     ST_NONE = 0,
@@ -59,12 +70,11 @@ struct Ctr {
 // Arguments of one insertion round.
 struct RoundArgs {
     const Vert *V;
-    uint4 *tv;                   // tetrahedron vertices (ghost in slot 3)
-    uint4 *tn;                   // neighbour codes 4 t' + f'
-    unsigned long long *own_any; // lowest claim of any attempt touching the tetrahedron
-    unsigned long long *own_cav; // lowest claim of an attempt with it in its cavity
+    Tet *T;                      // tetrahedron pool
     uint32_t *vtet;              // vertex -> a live tetrahedron containing it
     const uint32_t *anchor;      // vertex -> an earlier vertex near it on the curve
+    const uint32_t *lvl_start;   // [L + 1] first vertex of each level of the current call
+    int L;
     const uint32_t *cand_pt;     // current candidate list
     const uint32_t *cand_rank;
     uint32_t *next_pt;           // losers for the next round
@@ -74,9 +84,9 @@ struct RoundArgs {
     const uint32_t *ncand_ptr;   // device count of the current list
     uint32_t *nnext_ptr;         // device count of the next list
     uint32_t *novf_ptr;          // device count of the overflow list
-    uint32_t *cav;               // [capC][stride] cavity tetrahedra (code 4 t + entry facet)
-    uint32_t *bnd;               // [capF][stride] boundary facets (4 c + f, c in the cavity)
-    uint32_t *outc;              // [capF][stride] outer codes, then new tetrahedra
+    uint32_t *cav;               // [stride][capC] cavity tetrahedra (code 4 t + entry facet)
+    uint32_t *bnd;               // [stride][capF] boundary facets (4 c + f, c in the cavity)
+    uint32_t *outc;              // [stride][capF] outer codes, then new tetrahedra
     uint32_t *cnt;               // [2][stride] cavity size, boundary size
     uint8_t *status;             // [stride]
     uint32_t *winners;           // [stride] candidates that won this round
@@ -112,17 +122,17 @@ hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uin
 size_t scan_tmp_entries(uint64_t n);
 
 // ---- launch wrappers (dt_insert.hip) ----
-hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, uint4 *tv, uint4 *tn,
-                       uint32_t *vtet, Ctr *ctr, hipStream_t s);
+hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, Tet *T, uint32_t *vtet,
+                       Ctr *ctr, hipStream_t s);
 hipError_t launch_fill_list(const uint32_t *lvl_start, const uint32_t *lvl_size, const uint32_t *lvl_bits,
                             const unsigned long long *rank_base, int L, unsigned long long first_rank,
                             uint32_t count, const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt,
                             uint32_t *cand_rank, uint32_t *ncand, hipStream_t s);
 hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, bool big, hipStream_t s);
-hipError_t launch_output_flags(const uint4 *tv, uint32_t count, uint32_t *flags, hipStream_t s);
-hipError_t launch_output(const uint4 *tv, const uint4 *tn, const Vert *V, const uint32_t *map,
-                         uint32_t count, uint32_t *tets, int64_t *nbrs, hipStream_t s);
+hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s);
+hipError_t launch_output(const Tet *T, const Vert *V, const uint32_t *map, uint32_t count, uint32_t *tets,
+                         int64_t *nbrs, hipStream_t s);
 hipError_t launch_predicates(int kind, const double *pts, const int64_t *idx, uint64_t k, int8_t *out,
                              hipStream_t s);
 

@@ -5,14 +5,17 @@
 //                       = det of rows (p-e, |p-e|^2) for p = a,b,c,d (translated form)
 //   For orient3d(a,b,c,d) > 0, e is strictly inside the circumsphere iff insphere < 0.
 //
-// Stage 1: fp64 evaluation in a fixed order plus a dynamic filter.  Every monomial of the
-// expansion passes through at most 8 (orient3d) or 16 (insphere) roundings, so with the
-// unit roundoff u = 2^-53 the absolute error is below gamma_k/(1-gamma_k) times the
-// permanent (the same expansion with absolute values, evaluated alongside).  That factor
-// is < 8.9e-16 (k = 8) and < 1.8e-15 (k = 16); the filter uses 2^-49 and 2^-48, about
-// twice that.  Inputs are restricted to 0 or |x| in [2^-120, 2^120): every difference and
-// product then stays a multiple of 2^(-172 k) at degree k <= 5, far above the underflow
-// threshold, and far below overflow.
+// Stage 1: fp64 evaluation in a fixed order plus a semi-static filter.  Every monomial of
+// the expansion passes through at most 8 (orient3d) or 16 (insphere) roundings, so with the
+// unit roundoff u = 2^-53 the absolute error is below gamma_k times the sum of the
+// monomials' magnitudes.  With M the largest magnitude of the computed coordinate
+// differences, that sum is at most 6 M^3 (orient3d: six products of three differences) and
+// 72 M^5 (insphere: 4 lifted terms of 3 squares times 6 products of three differences).
+// gamma_8 * 6 < 2^-46 and gamma_16 * 72 < 2^-42 leave a margin of more than two for the
+// rounding of the differences and of M^k itself; the filter uses 2^-46 M^3 and 2^-41 M^5.
+// Inputs are restricted to 0 or |x| in [2^-120, 2^120): every difference and product then
+// stays a multiple of 2^(-172 k) at degree k <= 5, far above the underflow threshold, and
+// far below overflow.
 //
 // Stage 2 (when the filter cannot decide): the coordinates are scaled by a common power
 // of two into exact integers and the same determinant is evaluated in two's-complement
@@ -235,17 +238,16 @@ __device__ __noinline__ bool collinear_exact(P3 a, P3 b, P3 c) {
 
 // sign of orient3d, or 2 when the fp64 filter cannot decide
 __device__ __forceinline__ int orient3d_filter(P3 a, P3 b, P3 c, P3 d) {
-    double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
-    double vx = c.x - a.x, vy = c.y - a.y, vz = c.z - a.z;
-    double wx = d.x - a.x, wy = d.y - a.y, wz = d.z - a.z;
-    double p1 = vy * wz, p2 = vz * wy, p3 = vz * wx, p4 = vx * wz, p5 = vx * wy, p6 = vy * wx;
-    double det = ux * (p1 - p2) + uy * (p3 - p4) + uz * (p5 - p6);
-    double perm = fabs(ux) * (fabs(p1) + fabs(p2)) + fabs(uy) * (fabs(p3) + fabs(p4)) +
-                  fabs(uz) * (fabs(p5) + fabs(p6));
-    double bound = perm * 0x1p-49;
+    const double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
+    const double vx = c.x - a.x, vy = c.y - a.y, vz = c.z - a.z;
+    const double wx = d.x - a.x, wy = d.y - a.y, wz = d.z - a.z;
+    const double det = ux * (vy * wz - vz * wy) + uy * (vz * wx - vx * wz) + uz * (vx * wy - vy * wx);
+    double M = fmax(fmax(fmax(fabs(ux), fabs(uy)), fmax(fabs(uz), fabs(vx))),
+                    fmax(fmax(fabs(vy), fabs(vz)), fmax(fmax(fabs(wx), fabs(wy)), fabs(wz))));
+    const double bound = (M * M) * M * 0x1p-46;
     if (det > bound) return 1;
     if (-det > bound) return -1;
-    if (perm == 0.0) return 0;
+    if (M == 0.0) return 0;
     return 2;
 }
 
@@ -259,38 +261,31 @@ __device__ __forceinline__ int orient3d(P3 a, P3 b, P3 c, P3 d, PredStats &st) {
 
 // sign of the unperturbed lifted determinant, or 2 when the filter cannot decide
 __device__ __forceinline__ int insphere_filter(P3 a, P3 b, P3 c, P3 d, P3 e) {
-    double ax = a.x - e.x, ay = a.y - e.y, az = a.z - e.z;
-    double bx = b.x - e.x, by = b.y - e.y, bz = b.z - e.z;
-    double cx = c.x - e.x, cy = c.y - e.y, cz = c.z - e.z;
-    double dx = d.x - e.x, dy = d.y - e.y, dz = d.z - e.z;
+    const double ax = a.x - e.x, ay = a.y - e.y, az = a.z - e.z;
+    const double bx = b.x - e.x, by = b.y - e.y, bz = b.z - e.z;
+    const double cx = c.x - e.x, cy = c.y - e.y, cz = c.z - e.z;
+    const double dx = d.x - e.x, dy = d.y - e.y, dz = d.z - e.z;
     // 2x2 minors m(p,q) = p_x q_y - q_x p_y
-    double ab1 = ax * by, ab2 = bx * ay, ab = ab1 - ab2;
-    double ac1 = ax * cy, ac2 = cx * ay, ac = ac1 - ac2;
-    double ad1 = ax * dy, ad2 = dx * ay, ad = ad1 - ad2;
-    double bc1 = bx * cy, bc2 = cx * by, bc = bc1 - bc2;
-    double bd1 = bx * dy, bd2 = dx * by, bd = bd1 - bd2;
-    double cd1 = cx * dy, cd2 = dx * cy, cd = cd1 - cd2;
-    double pab = fabs(ab1) + fabs(ab2), pac = fabs(ac1) + fabs(ac2), pad = fabs(ad1) + fabs(ad2);
-    double pbc = fabs(bc1) + fabs(bc2), pbd = fabs(bd1) + fabs(bd2), pcd = fabs(cd1) + fabs(cd2);
+    const double ab = ax * by - bx * ay, ac = ax * cy - cx * ay, ad = ax * dy - dx * ay;
+    const double bc = bx * cy - cx * by, bd = bx * dy - dx * by, cd = cx * dy - dx * cy;
     // 3x3 determinants det3(p,q,s) = p_z m(q,s) - q_z m(p,s) + s_z m(p,q)
-    double abc = az * bc - bz * ac + cz * ab;
-    double abd = az * bd - bz * ad + dz * ab;
-    double acd = az * cd - cz * ad + dz * ac;
-    double bcd = bz * cd - cz * bd + dz * bc;
-    double pabc = fabs(az) * pbc + fabs(bz) * pac + fabs(cz) * pab;
-    double pabd = fabs(az) * pbd + fabs(bz) * pad + fabs(dz) * pab;
-    double pacd = fabs(az) * pcd + fabs(cz) * pad + fabs(dz) * pac;
-    double pbcd = fabs(bz) * pcd + fabs(cz) * pbd + fabs(dz) * pbc;
-    double la = ax * ax + ay * ay + az * az;
-    double lb = bx * bx + by * by + bz * bz;
-    double lc = cx * cx + cy * cy + cz * cz;
-    double ld = dx * dx + dy * dy + dz * dz;
-    double det = (ld * abc - lc * abd) + (lb * acd - la * bcd);
-    double perm = (ld * pabc + lc * pabd) + (lb * pacd + la * pbcd);
-    double bound = perm * 0x1p-48;
+    const double abc = az * bc - bz * ac + cz * ab;
+    const double abd = az * bd - bz * ad + dz * ab;
+    const double acd = az * cd - cz * ad + dz * ac;
+    const double bcd = bz * cd - cz * bd + dz * bc;
+    const double la = ax * ax + ay * ay + az * az;
+    const double lb = bx * bx + by * by + bz * bz;
+    const double lc = cx * cx + cy * cy + cz * cz;
+    const double ld = dx * dx + dy * dy + dz * dz;
+    const double det = (ld * abc - lc * abd) + (lb * acd - la * bcd);
+    const double M = fmax(fmax(fmax(fmax(fabs(ax), fabs(ay)), fmax(fabs(az), fabs(bx))),
+                               fmax(fmax(fabs(by), fabs(bz)), fmax(fabs(cx), fabs(cy)))),
+                          fmax(fmax(fabs(cz), fabs(dx)), fmax(fabs(dy), fabs(dz))));
+    const double M2 = M * M;
+    const double bound = (M2 * M2) * M * 0x1p-41;
     if (det > bound) return 1;
     if (-det > bound) return -1;
-    if (perm == 0.0) return 0;
+    if (M == 0.0) return 0;
     return 2;
 }
 
@@ -302,14 +297,11 @@ __device__ __forceinline__ int insphere_raw(P3 a, P3 b, P3 c, P3 d, P3 e, PredSt
     return insphere_exact(a, b, c, d, e);
 }
 
-// sign of the perturbed lifted determinant of rows (a,b,c,d,e), input indices ia..ie;
-// requires orient3d(a,b,c,d) > 0.  -1 means e is inside the circumsphere.
-__device__ __noinline__ int insphere_perturbed_tail(P3 a, P3 b, P3 c, P3 d, P3 e,
-                                                    unsigned long long ia, unsigned long long ib,
-                                                    unsigned long long ic, unsigned long long id,
-                                                    unsigned long long ie, PredStats *st) {
+// sign of the perturbed lifted determinant of rows (a,b,c,d,e) with perturbation keys
+// key[0..4] (input indices); requires orient3d(a,b,c,d) > 0.  -1 means e is inside.
+__device__ __noinline__ int insphere_perturbed_tail(P3 a, P3 b, P3 c, P3 d, P3 e, const unsigned long long *key,
+                                                    PredStats *st) {
     P3 p[5] = {a, b, c, d, e};
-    unsigned long long key[5] = {ia, ib, ic, id, ie};
     bool used[5] = {false, false, false, false, false};
     for (int q = 0; q < 5; ++q) {
         int r = -1;
@@ -326,14 +318,16 @@ __device__ __noinline__ int insphere_perturbed_tail(P3 a, P3 b, P3 c, P3 d, P3 e
     return 1;  // unreachable: row e's cofactor is orient3d(a,b,c,d) > 0
 }
 
-__device__ __forceinline__ int insphere_perturbed(P3 a, P3 b, P3 c, P3 d, P3 e, unsigned long long ia,
-                                                  unsigned long long ib, unsigned long long ic,
-                                                  unsigned long long id, unsigned long long ie,
-                                                  PredStats &st) {
+// Perturbed insphere with the keys supplied by `keys(k)` (called only when the unperturbed
+// determinant is zero), k = 0..4 for rows a..e.
+template <class Keys>
+__device__ __forceinline__ int insphere_perturbed(P3 a, P3 b, P3 c, P3 d, P3 e, Keys keys, PredStats &st) {
     int s = insphere_raw(a, b, c, d, e, st);
     if (s != 0) return s;
     st.perturbed++;
-    return insphere_perturbed_tail(a, b, c, d, e, ia, ib, ic, id, ie, &st);
+    unsigned long long key[5];
+    for (int k = 0; k < 5; ++k) key[k] = keys(k);
+    return insphere_perturbed_tail(a, b, c, d, e, key, &st);
 }
 
 // filtered orient2d-free collinearity test used only by the initial tetrahedron search
