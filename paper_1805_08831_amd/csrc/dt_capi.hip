@@ -1,9 +1,10 @@
 // Host driver and C ABI of the library (include/dt.h).
 //
-// dt_insert_points: validate + bounding box -> Moore keys and BRIO levels -> radix sort ->
-// vertex records -> duplicates -> initial tetrahedron (first call) -> curve anchors ->
-// insertion rounds until every point of the call is inserted (paper Algorithm 1, with
-// the sequential loop replaced by rounds of concurrent insertions).
+// dt_insert_points: validate + bounding box -> Moore keys -> radix sort -> vertex records
+// in Moore order -> BRIO levels and the level-major order of the records -> duplicates ->
+// initial tetrahedron (first call) -> insertion rounds until every point of the call is
+// inserted (paper Algorithm 1, with the sequential loop replaced by rounds of concurrent
+// insertions).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,7 +25,7 @@ using namespace dtk;
 namespace {
 
 constexpr uint32_t DEFAULT_ROUND_MAX = 1u << 20;
-constexpr uint32_t DEFAULT_CAVITY_CAP = 96;
+constexpr uint32_t DEFAULT_CAVITY_CAP = 128;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t ROUND_MIN = 64;
 
@@ -91,6 +92,7 @@ struct dt_ctx {
     uint32_t capC = 0, capF = 0;
     uint32_t *cav = nullptr, *bnd = nullptr, *outc = nullptr, *cnt = nullptr;
     uint32_t *winners = nullptr, *w_take = nullptr, *w_bump = nullptr, *w_free = nullptr;
+    uint4 *scr_v = nullptr, *scr_n = nullptr;
     uint8_t *status = nullptr;
 
     Ctr *ctr = nullptr;
@@ -110,8 +112,7 @@ struct dt_ctx {
     dt_stats st{};
     uint32_t trace_prev_won = 0;
     unsigned long long trace_prev_att = 0, trace_prev_walk = 0;
-    const uint32_t *d_lvl_start = nullptr;  // level starts (global positions) of the current call
-    int cur_L = 0;
+    const uint32_t *lord = nullptr;  // level-major order of the current call's vertex records
     bool trace = false;  // DT_TRACE=1 in the environment: one line per round on stderr
 };
 
@@ -207,6 +208,8 @@ int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
     }
     hipFree(c->cav); hipFree(c->bnd); hipFree(c->outc); hipFree(c->cnt); hipFree(c->status);
     hipFree(c->winners); hipFree(c->w_take); hipFree(c->w_bump); hipFree(c->w_free);
+    hipFree(c->scr_v); hipFree(c->scr_n);
+    c->scr_v = c->scr_n = nullptr;
     c->cav = c->bnd = c->outc = c->cnt = nullptr;
     c->winners = c->w_take = c->w_bump = c->w_free = nullptr;
     c->status = nullptr;
@@ -225,7 +228,9 @@ int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
          hipMalloc((void **)&c->winners, rmax * sizeof(uint32_t)) == hipSuccess &&
          hipMalloc((void **)&c->w_take, rmax * sizeof(uint32_t)) == hipSuccess &&
          hipMalloc((void **)&c->w_bump, rmax * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void **)&c->w_free, rmax * sizeof(uint32_t)) == hipSuccess;
+         hipMalloc((void **)&c->w_free, rmax * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc((void **)&c->scr_v, c->bufC * sizeof(uint4)) == hipSuccess &&
+         hipMalloc((void **)&c->scr_n, c->bufC * sizeof(uint4)) == hipSuccess;
     if (!ok) {
         hipGetLastError();
         c->list_cap = 0;
@@ -236,21 +241,19 @@ int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
 
 struct Levels {
     int L = 0;
-    std::vector<uint32_t> start_local, start_global, size, bits, prev;
+    std::vector<uint32_t> start, size, bits;  // start: offsets into the level-major order
     std::vector<unsigned long long> rank_base;
     uint64_t total_ranks = 0;
 };
 
 // device copies of the level tables live in c->small / c->small64
-int upload_levels(dt_ctx *c, const Levels &lv, uint32_t **d_start_local, uint32_t **d_start_global,
-                  uint32_t **d_size, uint32_t **d_bits, uint32_t **d_prev, unsigned long long **d_rank_base) {
+int upload_levels(dt_ctx *c, const Levels &lv, uint32_t **d_start, uint32_t **d_size, uint32_t **d_bits,
+                  unsigned long long **d_rank_base) {
     const int L = lv.L;
     std::vector<uint32_t> packed;
-    packed.insert(packed.end(), lv.start_local.begin(), lv.start_local.end());    // L + 1
-    packed.insert(packed.end(), lv.start_global.begin(), lv.start_global.end());  // L + 1
-    packed.insert(packed.end(), lv.size.begin(), lv.size.end());                  // L
-    packed.insert(packed.end(), lv.bits.begin(), lv.bits.end());                  // L
-    packed.insert(packed.end(), lv.prev.begin(), lv.prev.end());                  // L
+    packed.insert(packed.end(), lv.start.begin(), lv.start.end());  // L + 1
+    packed.insert(packed.end(), lv.size.begin(), lv.size.end());    // L
+    packed.insert(packed.end(), lv.bits.begin(), lv.bits.end());    // L
     int rc = ensure(c, c->small, packed.size() + 64);
     if (rc) return rc;
     rc = ensure(c, c->small64, (size_t)2 * (L + 1) + 64);
@@ -259,11 +262,9 @@ int upload_levels(dt_ctx *c, const Levels &lv, uint32_t **d_start_local, uint32_
                           c->stream));
     HIPCHK(hipMemcpyAsync(c->small64.p, lv.rank_base.data(), (L + 1) * sizeof(unsigned long long),
                           hipMemcpyHostToDevice, c->stream));
-    *d_start_local = c->small.p;
-    *d_start_global = c->small.p + (L + 1);
-    *d_size = c->small.p + 2 * (L + 1);
-    *d_bits = c->small.p + 2 * (L + 1) + L;
-    *d_prev = c->small.p + 2 * (L + 1) + 2 * L;
+    *d_start = c->small.p;
+    *d_size = c->small.p + (L + 1);
+    *d_bits = c->small.p + (L + 1) + L;
     *d_rank_base = (unsigned long long *)c->small64.p;
     return DT_OK;
 }
@@ -301,26 +302,35 @@ void accumulate_timing(dt_ctx *c) {
 }
 
 // one round over the candidate list `ci`; losers go to `ni`, overflows to `oi`
-int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t capC, uint32_t capF) {
+// (slice: the candidates are entries off .. off + max_cand of list ci, not the whole list)
+int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t capC, uint32_t capF,
+                  uint64_t base, uint64_t n, bool slice = false, uint32_t off = 0) {
     Ctr *d = c->ctr;
     RoundArgs a{};
     a.V = c->V.p;
     a.T = c->T;
-    a.lvl_start = c->d_lvl_start;
-    a.L = c->cur_L;
     a.winners = c->winners;
     a.w_take = c->w_take;
     a.w_bump = c->w_bump;
     a.w_free = c->w_free;
+    a.scr_v = c->scr_v;
+    a.scr_n = c->scr_n;
     a.vtet = c->vtet.p;
+    a.vlo = (uint32_t)base;
+    a.vhi = (uint32_t)(base + n);
     a.anchor = c->anchor.p;
-    a.cand_pt = c->lpt[ci];
-    a.cand_rank = c->lrank[ci];
+    a.cand_pt = c->lpt[ci] + off;
+    a.cand_rank = c->lrank[ci] + off;
     a.next_pt = c->lpt[ni];
     a.next_rank = c->lrank[ni];
     a.ovf_pt = c->lpt[oi];
     a.ovf_rank = c->lrank[oi];
     a.ncand_ptr = &d->list_count[ci];
+    if (slice) {
+        c->hctr->chunk = max_cand;
+        HIPCHK(hipMemcpyAsync(&d->chunk, &c->hctr->chunk, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+        a.ncand_ptr = &d->chunk;
+    }
     a.nnext_ptr = &d->list_count[ni];
     a.novf_ptr = &d->list_count[oi];
     a.cav = c->cav;
@@ -371,31 +381,42 @@ int ensure_capacity_for(dt_ctx *c, uint32_t max_cand, uint32_t capF) {
     return grow_tets(c, need + need / 8);
 }
 
-// rounds with enlarged per-insertion buffers for candidates whose cavities overflowed
-int drain_overflow(dt_ctx *c) {
-    uint32_t prev_count = 0, prev_cap = 0;
+// Rounds for candidates whose cavities overflowed, in slices small enough that each
+// insertion gets at least `need` buffer entries; `need` grows while a pass over the list
+// inserts nothing.
+int drain_overflow(dt_ctx *c, uint64_t base, uint64_t n) {
+    size_t need = std::max<size_t>(4 * (size_t)c->capC, 512);
     while (c->hctr->list_count[2 + c->ovf_idx] > 0) {
         const int ci = 2 + c->ovf_idx, ni = 2 + (c->ovf_idx ^ 1);
         const uint32_t cnt = c->hctr->list_count[ci];
-        const uint32_t capC = (uint32_t)std::min<size_t>(c->bufC / cnt, 1u << 24);
-        const uint32_t capF = (uint32_t)std::min<size_t>(c->bufF / cnt, 1u << 24);
-        if (cnt >= prev_count && capC <= prev_cap && prev_count)
-            return fail(c, DT_E_CAPACITY, "a cavity exceeds the per-insertion buffer (%u tetrahedra)", capC);
-        prev_count = cnt;
-        prev_cap = capC;
-        int rc = ensure_capacity_for(c, cnt, capF);
-        if (rc) return rc;
+        const uint32_t chunk = (uint32_t)std::max<size_t>(1, std::min<size_t>(cnt, c->bufC / need));
+        const uint32_t capC = (uint32_t)std::min<size_t>(c->bufC / chunk, 1u << 24);
+        const uint32_t capF = (uint32_t)std::min<size_t>(c->bufF / chunk, 1u << 24);
         const uint32_t won0 = c->hctr->won;
-        rc = run_one_round(c, ci, ni, ni, cnt, capC, capF);
-        if (rc) return rc;
-        c->mesh_vertices += c->hctr->won - won0;
+        for (uint32_t off = 0; off < cnt; off += chunk) {
+            const uint32_t k = std::min(chunk, cnt - off);
+            int rc = ensure_capacity_for(c, k, capF);
+            if (rc) return rc;
+            const uint32_t w0 = c->hctr->won;
+            rc = run_one_round(c, ci, ni, ni, k, capC, capF, base, n, true, off);
+            if (rc) return rc;
+            c->mesh_vertices += c->hctr->won - w0;
+        }
+        // list ci is consumed; its losers and overflows are in list ni
+        HIPCHK(hipMemsetAsync(&c->ctr->list_count[ci], 0, sizeof(uint32_t), c->stream));
+        c->hctr->list_count[ci] = 0;
         c->ovf_idx ^= 1;
+        if (c->hctr->won == won0) {
+            if (chunk == 1)  // the whole buffer did not hold one cavity
+                return fail(c, DT_E_CAPACITY, "a cavity exceeds the per-insertion buffer (%u tetrahedra)", capC);
+            need *= 4;
+        }
     }
     return DT_OK;
 }
 
-int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start_global, const uint32_t *d_size,
-               const uint32_t *d_bits, const unsigned long long *d_rank_base) {
+int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint32_t *d_size,
+               const uint32_t *d_bits, const unsigned long long *d_rank_base, uint64_t base, uint64_t n) {
     const uint32_t rmax = c->list_cap;
     const double frac = c->opt.round_fraction > 0 ? c->opt.round_fraction : DEFAULT_ROUND_FRACTION;
     uint64_t next_rank = 0;
@@ -410,39 +431,47 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start_global, cons
         uint32_t W = 0;
         if (next_rank < lv.total_ranks && target > nl)
             W = (uint32_t)std::min<uint64_t>(target - nl, lv.total_ranks - next_rank);
-        if (nl == 0 && W == 0) break;
+        if (nl == 0 && W == 0) {
+            if (c->hctr->list_count[oi] == 0) break;
+            int rc = drain_overflow(c, base, n);
+            if (rc) return rc;
+            continue;
+        }
+        // overflowed candidates wait until the regular lists are done (by then their
+        // neighbourhoods are filled in and their cavities are smaller), or until their
+        // list could not take another round's worth
+        if (c->hctr->list_count[oi] + nl + W > rmax) {
+            int rc = drain_overflow(c, base, n);
+            if (rc) return rc;
+            continue;
+        }
         if (c->opt.max_rounds && rounds_this_call >= c->opt.max_rounds)
             return fail(c, DT_E_INCOMPLETE, "round limit %u reached", c->opt.max_rounds);
-        HIPCHK(launch_fill_list(d_start_global, d_size, d_bits, d_rank_base, lv.L, next_rank, W, c->dup.p,
+        HIPCHK(launch_fill_list(d_start, d_size, d_bits, d_rank_base, lv.L, c->lord, next_rank, W, c->dup.p,
                                 c->vtet.p, c->lpt[ci], c->lrank[ci], &c->ctr->list_count[ci], c->stream));
         next_rank += W;
         const uint32_t max_cand = nl + W;
         int rc = ensure_capacity_for(c, max_cand, c->capF);
         if (rc) return rc;
         const uint32_t won0 = c->hctr->won;
-        rc = run_one_round(c, ci, ni, oi, max_cand, c->capC, c->capF);
+        rc = run_one_round(c, ci, ni, oi, max_cand, c->capC, c->capF, base, n);
         if (rc) return rc;
         c->mesh_vertices += c->hctr->won - won0;
         c->list_idx = ni;
         ++rounds_this_call;
-        rc = drain_overflow(c);
-        if (rc) return rc;
     }
     return DT_OK;
 }
 
-void compute_levels(const std::vector<uint32_t> &hist, int L, uint64_t base, Levels &lv) {
+void compute_levels(const std::vector<uint32_t> &hist, int L, Levels &lv) {
     lv.L = L;
-    lv.start_local.assign(L + 1, 0);
-    lv.start_global.assign(L + 1, 0);
+    lv.start.assign(L + 1, 0);
     lv.size.assign(L, 0);
     lv.bits.assign(L, 0);
-    lv.prev.assign(L, NONE);
     lv.rank_base.assign(L + 1, 0);
     uint64_t acc = 0;
     for (int k = 0; k < L; ++k) {
-        lv.start_local[k] = (uint32_t)acc;
-        lv.start_global[k] = (uint32_t)(base + acc);
+        lv.start[k] = (uint32_t)acc;
         lv.size[k] = hist[k];
         acc += hist[k];
         uint32_t b = 0;
@@ -450,20 +479,14 @@ void compute_levels(const std::vector<uint32_t> &hist, int L, uint64_t base, Lev
         lv.bits[k] = b;
         lv.rank_base[k + 1] = lv.rank_base[k] + (1ull << b);
     }
-    lv.start_local[L] = (uint32_t)acc;
-    lv.start_global[L] = (uint32_t)(base + acc);
-    int last = -1;
-    for (int k = 0; k < L; ++k) {
-        lv.prev[k] = last < 0 ? NONE : (uint32_t)last;
-        if (hist[k]) last = k;
-    }
+    lv.start[L] = (uint32_t)acc;
     lv.total_ranks = lv.rank_base[L];
 }
 
-// Moore keys + BRIO levels + radix sort of the n points at dxyz; leaves the sorted keys in
-// *skeys and the sorted input indices in *svals
+// Moore keys + radix sort of the n points at dxyz: *svals receives, for each position of
+// the curve order, the point's index within the call (equal keys keep input order)
 int sort_points(dt_ctx *c, const double *dxyz, uint64_t n, int *m_out, std::vector<uint64_t> &cum,
-                unsigned long long **skeys, uint32_t **svals, bool *bad_input) {
+                uint32_t **svals, bool *bad_input) {
     *bad_input = false;
     const int m = moore_level(n);
     cum = brio_cum(n);
@@ -472,7 +495,8 @@ int sort_points(dt_ctx *c, const double *dxyz, uint64_t n, int *m_out, std::vect
     if ((rc = ensure(c, c->keys, n)) || (rc = ensure(c, c->keys_tmp, n)) || (rc = ensure(c, c->vals, n)) ||
         (rc = ensure(c, c->vals_tmp, n)) || (rc = ensure(c, c->hist, radix_hist_entries(n))) ||
         (rc = ensure(c, c->scan_tmp, scan_tmp_entries(radix_hist_entries(n)) + scan_tmp_entries(n) + 64)) ||
-        (rc = ensure(c, c->bbox, 6 * 1024 + 6)) || (rc = ensure(c, c->small64, 256)))
+        (rc = ensure(c, c->bbox, 6 * 1024 + 6)) || (rc = ensure(c, c->small64, 256)) ||
+        (rc = ensure(c, c->small, 256)))
         return rc;
     HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
     const int nblocks = (int)std::min<uint64_t>((n + 255) / 256, 1024);
@@ -484,16 +508,32 @@ int sort_points(dt_ctx *c, const double *dxyz, uint64_t n, int *m_out, std::vect
         return DT_OK;
     }
     HIPCHK(hipMemcpyAsync(c->small64.p, cum.data(), L * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(launch_keys(dxyz, n, c->bbox.p + 6 * 1024, m, 0, c->small64.p, 1, c->keys.p, c->vals.p, c->stream));
+    bool swapped = false;
+    HIPCHK(radix_sort_pairs(c->keys.p, c->vals.p, c->keys_tmp.p, c->vals_tmp.p, c->hist.p, c->scan_tmp.p, n,
+                            3 * m, c->stream, &swapped));
+    *svals = swapped ? c->vals_tmp.p : c->vals.p;
+    *m_out = m;
+    return DT_OK;
+}
+
+// BRIO level of every Moore-ordered position and the stable level-major order of the
+// positions (base + i) in *lord; the level sizes go to hist (asynchronously, pinned or
+// pageable host memory; the caller synchronizes).  svals is consumed.
+int level_order(dt_ctx *c, uint32_t *svals, uint64_t n, uint64_t base, int L, uint32_t **lord,
+                uint32_t *hist_host) {
+    uint32_t *other = (svals == c->vals.p) ? c->vals_tmp.p : c->vals.p;
     const uint64_t salt = host_mix64(c->opt.seed ^ 0x5851F42D4C957F2Dull);
-    HIPCHK(launch_keys(dxyz, n, c->bbox.p + 6 * 1024, m, salt, c->small64.p, L, c->keys.p, c->vals.p, c->stream));
+    HIPCHK(launch_levels(svals, n, base, salt, c->small64.p, L, c->keys.p, other, c->stream));
     int lbits = 0;
     while ((1 << lbits) < L) ++lbits;
     bool swapped = false;
-    HIPCHK(radix_sort_pairs(c->keys.p, c->vals.p, c->keys_tmp.p, c->vals_tmp.p, c->hist.p, c->scan_tmp.p, n,
-                            3 * m + lbits, c->stream, &swapped));
-    *skeys = swapped ? c->keys_tmp.p : c->keys.p;
-    *svals = swapped ? c->vals_tmp.p : c->vals.p;
-    *m_out = m;
+    HIPCHK(radix_sort_pairs(c->keys.p, other, c->keys_tmp.p, svals, c->hist.p, c->scan_tmp.p, n, lbits, c->stream,
+                            &swapped));
+    *lord = swapped ? svals : other;
+    HIPCHK(hipMemsetAsync(c->small.p, 0, 64 * sizeof(uint32_t), c->stream));
+    HIPCHK(launch_level_hist(c->keys.p, n, 0, c->small.p, c->stream));
+    HIPCHK(hipMemcpyAsync(hist_host, c->small.p, 64 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     return DT_OK;
 }
 
@@ -574,25 +614,22 @@ int dt_insert_points(dt_ctx *c, const double *xyz, uint64_t n) {
     }
     const uint64_t base = c->nv;
     if ((rc = ensure(c, c->V, base + n, true)) || (rc = ensure(c, c->vtet, base + n, true)) ||
-        (rc = ensure(c, c->anchor, base + n, true)) || (rc = ensure(c, c->dup, base + n, true)))
+        (rc = ensure(c, c->dup, base + n, true)) || (rc = ensure(c, c->anchor, n)))
         return rc;
-    // 1-2. validate, keys, sort
+    // 1-2. validate, Moore keys, sort
     int m = 1;
     std::vector<uint64_t> cum;
-    unsigned long long *skeys = nullptr;
     uint32_t *svals = nullptr;
     bool bad = false;
-    if ((rc = sort_points(c, dxyz, n, &m, cum, &skeys, &svals, &bad))) return rc;
+    if ((rc = sort_points(c, dxyz, n, &m, cum, &svals, &bad))) return rc;
     if (bad) return fail(c, DT_E_INPUT, "a coordinate is not finite or outside 0 or [2^-120, 2^120) in magnitude");
     const int L = (int)cum.size();
-    // 3. vertex records in sorted order
+    // 3. vertex records in curve order
     HIPCHK(launch_permute(dxyz, svals, n, base, c->npoints, c->V.p, c->vtet.p, c->dup.p, c->stream));
-    // 4. level sizes
-    if ((rc = ensure(c, c->small, 256))) return rc;
-    HIPCHK(hipMemsetAsync(c->small.p, 0, 64 * sizeof(uint32_t), c->stream));
-    HIPCHK(launch_level_hist(skeys, n, 3 * m, c->small.p, c->stream));
+    // 4. BRIO levels: level-major order of the records and level sizes
     std::vector<uint32_t> hist(64);
-    HIPCHK(hipMemcpyAsync(hist.data(), c->small.p, 64 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    uint32_t *lord = nullptr;
+    if ((rc = level_order(c, svals, n, base, L, &lord, hist.data()))) return rc;
     // 5. duplicates
     uint64_t tsize = 1;
     while (tsize < 2 * n) tsize <<= 1;
@@ -601,7 +638,7 @@ int dt_insert_points(dt_ctx *c, const double *xyz, uint64_t n) {
     HIPCHK(launch_dedupe(c->V.p, base, n, c->table.p, tsize, c->dup.p, &c->ctr->dups, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     Levels lv;
-    compute_levels(hist, L, base, lv);
+    compute_levels(hist, L, lv);
     // 6. initial tetrahedron
     if (!c->have_mesh) {
         if (c->tcap == 0 || c->tcap < 7 * n + 4096) {
@@ -620,13 +657,12 @@ int dt_insert_points(dt_ctx *c, const double *xyz, uint64_t n) {
         c->init_v0 = c->hctr->init[0];
         c->mesh_vertices = 4;
     }
-    // 7. anchors
-    uint32_t *d_sl, *d_sg, *d_size, *d_bits, *d_prev;
+    // 7. level tables
+    uint32_t *d_start, *d_size, *d_bits;
     unsigned long long *d_rb;
-    if ((rc = upload_levels(c, lv, &d_sl, &d_sg, &d_size, &d_bits, &d_prev, &d_rb))) return rc;
-    HIPCHK(launch_anchor(skeys, n, base, m, d_sl, d_prev, L, c->init_v0, c->anchor.p, c->stream));
-    c->d_lvl_start = d_sg;
-    c->cur_L = L;
+    if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
+    HIPCHK(launch_anchor(lord, d_start, L, base, n, c->anchor.p, c->stream));
+    c->lord = lord;
     if ((rc = sync_ctr(c))) return rc;
     c->st.duplicates += c->hctr->dups;
     auto t1 = std::chrono::steady_clock::now();
@@ -638,7 +674,7 @@ int dt_insert_points(dt_ctx *c, const double *xyz, uint64_t n) {
     const uint64_t want_r = c->opt.round_size ? c->opt.round_size : DEFAULT_ROUND_MAX;
     if ((rc = ensure_round_buffers(c, (uint32_t)std::min<uint64_t>(want_r, std::max<uint64_t>(n, ROUND_MIN)))))
         return rc;
-    rc = run_rounds(c, lv, d_sg, d_size, d_bits, d_rb);
+    rc = run_rounds(c, lv, d_start, d_size, d_bits, d_rb, base, n);
     auto t2 = std::chrono::steady_clock::now();
     c->st.ms_sort += std::chrono::duration<double, std::milli>(t1 - t0).count();
     c->st.ms_insert += std::chrono::duration<double, std::milli>(t2 - t1).count();
@@ -716,7 +752,7 @@ int dt_destroy(dt_ctx *c) {
     f(c->T); f(c->fl[0]); f(c->fl[1]);
     for (int k = 0; k < 4; ++k) { f(c->lpt[k]); f(c->lrank[k]); }
     f(c->cav); f(c->bnd); f(c->outc); f(c->cnt); f(c->status);
-    f(c->winners); f(c->w_take); f(c->w_bump); f(c->w_free);
+    f(c->winners); f(c->w_take); f(c->w_bump); f(c->w_free); f(c->scr_v); f(c->scr_n);
     f(c->ctr);
     if (c->hctr) hipHostFree(c->hctr);
     f(c->staging.p); f(c->keys.p); f(c->keys_tmp.p); f(c->table.p); f(c->vals.p); f(c->vals_tmp.p);
@@ -766,22 +802,30 @@ int dt_debug_sort(dt_ctx *c, const double *xyz, uint64_t n, uint64_t *keys, uint
     }
     int m = 1;
     std::vector<uint64_t> cum;
-    unsigned long long *sk = nullptr;
     uint32_t *sv = nullptr;
     bool bad = false;
-    // keys in input order are recomputed into the tmp buffer after the sort
-    if ((rc = sort_points(c, dxyz, n, &m, cum, &sk, &sv, &bad))) return rc;
+    // the same two sorts as dt_insert_points: Moore order, then level-major order of it
+    if ((rc = sort_points(c, dxyz, n, &m, cum, &sv, &bad))) return rc;
     if (bad) return fail(c, DT_E_INPUT, "a coordinate is not finite or outside the accepted range");
-    if (perm) HIPCHK(hipMemcpyAsync(perm, sv, n * sizeof(uint32_t), hipMemcpyDefault, c->stream));
+    std::vector<uint32_t> moore_order(n), lord_h(n), hist(64);
+    HIPCHK(hipMemcpyAsync(moore_order.data(), sv, n * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    uint32_t *lord = nullptr;
+    if ((rc = level_order(c, sv, n, 0, (int)cum.size(), &lord, hist.data()))) return rc;
+    HIPCHK(hipMemcpyAsync(lord_h.data(), lord, n * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     if (keys) {
-        // unsorted keys: recompute into the buffer the sort did not leave its result in
-        unsigned long long *kk = (sk == c->keys.p) ? c->keys_tmp.p : c->keys.p;
-        uint32_t *vv = (sv == c->vals.p) ? c->vals_tmp.p : c->vals.p;
+        // keys in input order: level << 3m | Moore index
         const uint64_t salt = host_mix64(c->opt.seed ^ 0x5851F42D4C957F2Dull);
-        HIPCHK(launch_keys(dxyz, n, c->bbox.p + 6 * 1024, m, salt, c->small64.p, (int)cum.size(), kk, vv, c->stream));
-        HIPCHK(hipMemcpyAsync(keys, kk, n * sizeof(uint64_t), hipMemcpyDefault, c->stream));
+        HIPCHK(launch_keys(dxyz, n, c->bbox.p + 6 * 1024, m, salt, c->small64.p, (int)cum.size(), c->keys_tmp.p,
+                           c->vals_tmp.p, c->stream));
+        HIPCHK(hipMemcpyAsync(keys, c->keys_tmp.p, n * sizeof(uint64_t), hipMemcpyDefault, c->stream));
     }
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (perm) {
+        std::vector<uint32_t> ph(n);
+        for (uint64_t j = 0; j < n; ++j) ph[j] = moore_order[lord_h[j]];
+        HIPCHK(hipMemcpy(perm, ph.data(), n * sizeof(uint32_t), hipMemcpyDefault));
+    }
     if (moore_m) *moore_m = m;
     return DT_OK;
 }

@@ -2,8 +2,8 @@
 // concurrency rules of Sec. 3.2).
 //
 // One thread per candidate point.  A round is three kernels:
-//   k_cavity : Walk (visibility walk, Sec. 2.1) from a live tetrahedron near the point's
-//              curve anchor, then Cavity (breadth-first search by perturbed insphere,
+//   k_cavity : Walk (visibility walk, Sec. 2.1) from a live tetrahedron of an already
+//              inserted neighbour on the space-filling curve, then Cavity (breadth-first search by perturbed insphere,
 //              ghosts by the half-space + circumdisk rule of Sec. 2.6).  Every tetrahedron
 //              the search touches is claimed with atomicMin on 64-bit claim words:
 //              stamp S = (round part, 2 rank) for cavity tetrahedra, S + 1 for tetrahedra
@@ -149,6 +149,7 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
         ctr->init[k] = v[k];
     }
     ctr->tet_count = 5;
+    ctr->any_live = 0;
 }
 
 hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, Tet *T, uint32_t *vtet,
@@ -160,11 +161,12 @@ hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *
 // ------------------------------------------------------------------ candidate fill
 
 // Ranks: level k owns ranks [rank_base[k], rank_base[k] + 2^bits[k]); rank r maps to the
-// level position bitreverse(r - rank_base[k]), so any window of consecutive ranks is
-// spread evenly along the level's part of the Moore curve.
+// level position bitreverse(r - rank_base[k]) (lord lists each level's records in Moore
+// order), so any window of consecutive ranks is spread evenly along the level's points.
 __global__ void k_fill(const uint32_t *__restrict__ lvl_start, const uint32_t *__restrict__ lvl_size,
                        const uint32_t *__restrict__ lvl_bits, const unsigned long long *__restrict__ rank_base, int L,
-                       unsigned long long first_rank, uint32_t count, const uint8_t *__restrict__ dup,
+                       const uint32_t *__restrict__ lord, unsigned long long first_rank, uint32_t count,
+                       const uint8_t *__restrict__ dup,
                        const uint32_t *__restrict__ vtet, uint32_t *__restrict__ cand_pt,
                        uint32_t *__restrict__ cand_rank, uint32_t *__restrict__ ncand) {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,7 +178,7 @@ __global__ void k_fill(const uint32_t *__restrict__ lvl_start, const uint32_t *_
     uint32_t bits = lvl_bits[k];
     uint32_t q = bits ? (__brev(local) >> (32 - bits)) : 0u;
     if (q >= lvl_size[k]) return;
-    uint32_t p = lvl_start[k] + q;
+    uint32_t p = lord[lvl_start[k] + q];
     if (dup[p] || vtet[p] != NONE) return;
     uint32_t pos = atomicAdd(ncand, 1u);
     cand_pt[pos] = p;
@@ -184,12 +186,13 @@ __global__ void k_fill(const uint32_t *__restrict__ lvl_start, const uint32_t *_
 }
 
 hipError_t launch_fill_list(const uint32_t *lvl_start, const uint32_t *lvl_size, const uint32_t *lvl_bits,
-                            const unsigned long long *rank_base, int L, unsigned long long first_rank,
-                            uint32_t count, const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt,
-                            uint32_t *cand_rank, uint32_t *ncand, hipStream_t s) {
+                            const unsigned long long *rank_base, int L, const uint32_t *lord,
+                            unsigned long long first_rank, uint32_t count, const uint8_t *dup,
+                            const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank, uint32_t *ncand,
+                            hipStream_t s) {
     if (count == 0) return hipSuccess;
-    k_fill<<<(count + 255) / 256, 256, 0, s>>>(lvl_start, lvl_size, lvl_bits, rank_base, L, first_rank, count,
-                                               dup, vtet, cand_pt, cand_rank, ncand);
+    k_fill<<<(count + 255) / 256, 256, 0, s>>>(lvl_start, lvl_size, lvl_bits, rank_base, L, lord, first_rank,
+                                               count, dup, vtet, cand_pt, cand_rank, ncand);
     return hipGetLastError();
 }
 
@@ -228,29 +231,24 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
         const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
         const Vert pv = a.V[p];
         const P3 P = {pv.x, pv.y, pv.z};
-        // start: a live tetrahedron of the nearest inserted point on the curve among the
-        // HINT_RANGE points on either side in the same level, else of the anchor chain
-        uint32_t lo = a.lvl_start[0], hi = a.lvl_start[a.L];
-        for (int k = 1; k < a.L; ++k) {
-            if (a.lvl_start[k] <= p) lo = a.lvl_start[k];
-            if (a.lvl_start[k] > p && a.lvl_start[k] < hi) hi = a.lvl_start[k];
-        }
+        // start: a live tetrahedron near the nearest inserted point among the HINT_RANGE
+        // records on either side on the curve, else near the point's anchor (a record of
+        // a lower level), else any live tetrahedron
         uint32_t t = NONE;
-        uint32_t near[2 * HINT_RANGE];
-        for (int d = 1; d <= HINT_RANGE; ++d) {
-            near[2 * d - 2] = p >= lo + d ? a.vtet[p - d] : NONE;
-            near[2 * d - 1] = p + d < hi ? a.vtet[p + d] : NONE;
+        for (int d = 1; d <= HINT_RANGE && t == NONE; ++d) {
+            if (p >= a.vlo + d) t = a.vtet[p - d];
+            if (t == NONE && p + d < a.vhi) t = a.vtet[p + d];
         }
-        for (int k = 0; k < 2 * HINT_RANGE && t == NONE; ++k) t = near[k];
         if (t == NONE) {
-            uint32_t av = a.anchor[p];
-            t = a.vtet[av];
-            while (t == NONE) {
-                av = a.anchor[av];
-                t = a.vtet[av];
-            }
+            const uint32_t q = a.anchor[p - a.vlo];
+            if (q != NONE) t = a.vtet[q];
         }
+        if (t == NONE) t = a.ctr->any_live;
         uint4 w = a.T[t].v;
+        if (w.x == DEAD) {
+            t = a.ctr->any_live;
+            w = a.T[t].v;
+        }
         if (w.w == GHOST) {
             t = a.T[t].n.w >> 2;
             w = a.T[t].v;
@@ -442,37 +440,6 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
 
 // ------------------------------------------------------------------ check + DelaunayBall
 
-// Rotate around the boundary edge (e0,e1) inside the cavity, starting in cavity tetrahedron
-// c through its facet f (which contains the edge), until the next boundary facet; returns
-// the code (new tetrahedron << 2 | facet opposite its vertex outside {e0, e1, p}).
-__device__ uint32_t pivot(const RoundArgs &a, uint32_t c, int f, uint32_t e0, uint32_t e1, uint32_t p,
-                          unsigned long long S, uint32_t limit) {
-    for (uint32_t guard = 0; guard <= limit; ++guard) {
-        const uint4 cv = a.T[c].v;
-        const uint32_t v[4] = {cv.x, cv.y, cv.z, cv.w};
-        int xpos = -1;
-        for (int k = 0; k < 4; ++k)
-            if (k != f && v[k] != e0 && v[k] != e1) xpos = k;
-        if (xpos < 0) break;
-        const uint32_t code = comp(a.T[c].n, xpos);
-        const uint32_t nt = code >> 2;
-        if (a.T[nt].any == S) {  // another tetrahedron of this cavity
-            c = nt;
-            f = (int)(code & 3u);
-            continue;
-        }
-        const uint4 nv = a.T[nt].v;  // the sibling new tetrahedron
-        const uint32_t w[4] = {nv.x, nv.y, nv.z, nv.w};
-        int q2 = -1;
-        for (int k = 0; k < 4; ++k)
-            if (w[k] != e0 && w[k] != e1 && w[k] != p) q2 = k;
-        if (q2 < 0) break;
-        return (nt << 2) | (uint32_t)q2;
-    }
-    atomicOr(&a.ctr->error, ERR_WALK);
-    return 0;
-}
-
 // Winner test and slot reservation, one thread per candidate.  An attempt wins iff it still
 // holds the lowest claim on every tetrahedron of its cavity (any) and no lower attempt
 // has one of its outer tetrahedra in its cavity (cav).  Winners of one round therefore
@@ -491,11 +458,13 @@ __global__ __launch_bounds__(256) void k_check(RoundArgs a) {
         a.status[i] = ST_CONFLICT;
         return;
     }
-    // slots: free list of earlier rounds first, then the bump pointer
-    const uint32_t take = atomicAdd(&a.ctr->fl_take, nb);
+    // the ball reuses the cavity's slots; F - C more come from the free list of earlier
+    // rounds, then from the bump pointer; C - F surplus cavity slots are freed
+    const uint32_t need = nb > nc ? nb - nc : 0u;
+    const uint32_t take = need ? atomicAdd(&a.ctr->fl_take, need) : 0u;
     const uint32_t fln = a.ctr->fl_n;
-    const uint32_t from_fl = fln > take ? min(nb, fln - take) : 0u;
-    const uint32_t rest = nb - from_fl;
+    const uint32_t from_fl = fln > take ? min(need, fln - take) : 0u;
+    const uint32_t rest = need - from_fl;
     const uint32_t bump = rest ? atomicAdd(&a.ctr->tet_count, rest) : 0u;
     if (rest && bump + rest > a.tcap) {
         // pool full: give the slots back (those inside the pool are marked free) and
@@ -518,87 +487,16 @@ __global__ __launch_bounds__(256) void k_check(RoundArgs a) {
     a.status[i] = ST_WON;
     a.w_take[i] = take;
     a.w_bump[i] = bump;
-    a.w_free[i] = atomicAdd(&a.ctr->fl_next, nc);
+    a.w_free[i] = nc > nb ? atomicAdd(&a.ctr->fl_next, nc - nb) : 0u;
     a.winners[atomicAdd(&a.ctr->nwin, 1u)] = i;
-}
-
-// DelaunayBall of one winner per 64-lane workgroup: (1) one new tetrahedron per boundary
-// facet, glued to its outer tetrahedron; (2) after a barrier, each new tetrahedron finds its
-// three siblings by pivoting around boundary edges through the intact cavity; (3) after a
-// barrier, the cavity tetrahedra are freed.
-__global__ __launch_bounds__(64) void k_build(RoundArgs a) {
-    const uint32_t nwin = a.ctr->nwin;
-    const uint32_t stride = a.stride;
-    const uint32_t fln = a.ctr->fl_n;
-    unsigned cav_w = 0, bnd_w = 0;
-    for (uint32_t w = blockIdx.x; w < nwin; w += gridDim.x) {
-        const uint32_t i = a.winners[w];
-        const uint32_t p = a.cand_pt[i];
-        const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
-        const uint32_t nc = a.cnt[i], nb = a.cnt[stride + i];
-        const uint32_t take = a.w_take[i], bump = a.w_bump[i];
-        const uint32_t from_fl = fln > take ? min(nb, fln - take) : 0u;
-        for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) {
-            const uint32_t slot = k < from_fl ? a.fl_cur[take + k] : bump + (k - from_fl);
-            const uint32_t bc = a.bnd[(size_t)i * a.capF + k];
-            const uint32_t oc = a.outc[(size_t)i * a.capF + k];
-            const uint32_t u = oc >> 2;
-            const int j = (int)(oc & 3u);
-            const uint4 uw = a.T[u].v;
-            uint32_t wv[4] = {uw.x, uw.y, uw.z, uw.w};
-            wv[j] = p;
-            const int pf = orient_new_tet(wv, j);
-            a.T[slot].v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
-            const uint32_t me = (slot << 2) | (uint32_t)pf;
-            nref(a.T, slot, pf) = oc;              // facet opposite p: outer tetrahedron
-            nref(a.T, u, j) = me;                  // and back
-            nref(a.T, bc >> 2, bc & 3u) = me;  // cavity side now names the new tetrahedron
-            a.outc[(size_t)i * a.capF + k] = me;
-            if (k == 0) a.vtet[p] = slot;
-        }
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) {
-            const uint32_t me = a.outc[(size_t)i * a.capF + k];
-            const uint32_t slot = me >> 2;
-            const int pf = (int)(me & 3u);
-            const uint32_t bc = a.bnd[(size_t)i * a.capF + k];
-            const uint4 sw = a.T[slot].v;
-            const uint32_t wv[4] = {sw.x, sw.y, sw.z, sw.w};
-            for (int q = 0; q < 4; ++q) {
-                if (q == pf) continue;
-                uint32_t e[2];
-                int ne = 0;
-                for (int r = 0; r < 4; ++r)
-                    if (r != q && r != pf) e[ne++] = wv[r];
-                nref(a.T, slot, q) = pivot(a, bc >> 2, (int)(bc & 3u), e[0], e[1], p, S, nc + 2);
-                if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
-            }
-        }
-        __syncthreads();
-        const uint32_t fb = a.w_free[i];
-        for (uint32_t k = threadIdx.x; k < nc; k += blockDim.x) {
-            const uint32_t c = a.cav[(size_t)i * a.capC + k] >> 2;
-            a.T[c].v.x = DEAD;
-            a.fl_next[fb + k] = c;
-        }
-        if (threadIdx.x == 0) {
-            cav_w += nc;
-            bnd_w += nb;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        if (cav_w) atomicAdd(&a.ctr->cav_tets, (unsigned long long)cav_w);
-        if (bnd_w) atomicAdd(&a.ctr->bnd_facets, (unsigned long long)bnd_w);
-    }
 }
 
 // ------------------------------------------------------------------ 16 lanes per insertion
 
 constexpr int GS = 16;              // lanes per insertion
 constexpr int GPB = 256 / GS;       // insertions per 256-thread block
-constexpr uint32_t LCAPC = 96;      // cavity tetrahedra held in LDS per insertion
-constexpr uint32_t LCAPF = 160;     // boundary facets held in LDS per insertion
+constexpr uint32_t LCAPC = 128;     // cavity tetrahedra held in LDS per insertion
+constexpr uint32_t LCAPF = 224;     // boundary facets held in LDS per insertion
 
 // keeps the compiler from moving LDS accesses across a point where other lanes of the
 // same wave consume them (the hardware processes one wave's LDS requests in order)
@@ -630,29 +528,21 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
         const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
         const Vert pv = a.V[p];
         const P3 P = {pv.x, pv.y, pv.z};
-        // start: nearest inserted point among 8 on either side of p on the curve (same
-        // level), one probe per lane; else the anchor chain
-        uint32_t lo = a.lvl_start[0], hi = a.lvl_start[a.L];
-        for (int k = 1; k < a.L; ++k) {
-            if (a.lvl_start[k] <= p) lo = a.lvl_start[k];
-            if (a.lvl_start[k] > p && a.lvl_start[k] < hi) hi = a.lvl_start[k];
-        }
+        // start: near the nearest inserted point among 8 records on either side of p on the
+        // curve, one probe per lane; else near the point's anchor (a record of a lower
+        // level); else any live tetrahedron
         const uint32_t d = (gl >> 1) + 1;
-        const bool inr = (gl & 1) ? (p + d < hi) : (p >= lo + d);
+        const bool inr = (gl & 1) ? (p + d < a.vhi) : (p >= a.vlo + d);
         const uint32_t ht = inr ? a.vtet[(gl & 1) ? p + d : p - d] : NONE;
+        const uint32_t q = a.anchor[p - a.vlo];
         const unsigned long long hm = __ballot(ht != NONE) & gmask;
-        uint32_t t;
-        if (hm) {
-            t = __shfl(ht, __ffsll((long long)hm) - 1);
-        } else {
-            uint32_t av = a.anchor[p];
-            t = a.vtet[av];
-            while (t == NONE) {
-                av = a.anchor[av];
-                t = a.vtet[av];
-            }
-        }
+        uint32_t t = hm ? __shfl(ht, __ffsll((long long)hm) - 1) : (q != NONE ? a.vtet[q] : NONE);
+        if (t == NONE) t = a.ctr->any_live;
         uint4 w = a.T[t].v;
+        if (w.x == DEAD) {
+            t = a.ctr->any_live;
+            w = a.T[t].v;
+        }
         if (w.w == GHOST) {
             t = a.T[t].n.w >> 2;
             w = a.T[t].v;
@@ -825,17 +715,26 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
     add_stat(&a.ctr->perturbed, st.perturbed);
 }
 
-// DelaunayBall with 16 lanes per winner (16 winners per block): the same three phases as
-// k_build; the three pivots of each new tetrahedron are spread over the lanes.
-__global__ __launch_bounds__(256) void k_build16(RoundArgs a) {
+// DelaunayBall, GL lanes per winner (Sec. 2.5).  The cavity tetrahedra are first copied to
+// the winner's scratch area and their facets resolved to local codes (another cavity
+// tetrahedron, or the new tetrahedron on that boundary facet); the new tetrahedra take the cavity's own slots
+// (and F - C more when the ball is larger), each glued a priori to its outer tetrahedron;
+// finally each new tetrahedron finds its three siblings by pivoting around boundary edges
+// through the scratch copies.  Reusing the cavity's slots keeps the tetrahedra of a region
+// together in memory.
+constexpr uint32_t LOC_BOUNDARY = 0x80000000u;
+
+template <int GL>
+__global__ __launch_bounds__(256) void k_build_t(RoundArgs a) {
+    constexpr uint32_t WPB = 256 / GL;
     const uint32_t nwin = a.ctr->nwin;
     const uint32_t stride = a.stride;
     const uint32_t fln = a.ctr->fl_n;
-    const uint32_t gl = threadIdx.x & (GS - 1);
-    const uint32_t gi = threadIdx.x / GS;
+    const uint32_t gl = threadIdx.x % GL;
+    const uint32_t gi = threadIdx.x / GL;
     const uint32_t capC = a.capC, capF = a.capF;
     unsigned cav_w = 0, bnd_w = 0;
-    for (uint32_t base = blockIdx.x * GPB; base < nwin; base += gridDim.x * GPB) {
+    for (uint32_t base = blockIdx.x * WPB; base < nwin; base += gridDim.x * WPB) {
         const uint32_t w = base + gi;
         const bool act = w < nwin;
         const uint32_t i = act ? a.winners[w] : 0u;
@@ -843,11 +742,46 @@ __global__ __launch_bounds__(256) void k_build16(RoundArgs a) {
         const unsigned long long S = act ? (a.round_hi | (2ull * a.cand_rank[i])) : 0ull;
         const uint32_t nc = act ? a.cnt[i] : 0u, nb = act ? a.cnt[stride + i] : 0u;
         const uint32_t take = act ? a.w_take[i] : 0u, bump = act ? a.w_bump[i] : 0u;
-        const uint32_t from_fl = fln > take ? min(nb, fln - take) : 0u;
-        for (uint32_t k = gl; k < nb; k += GS) {
-            const uint32_t slot = k < from_fl ? a.fl_cur[take + k] : bump + (k - from_fl);
-            const uint32_t bc = a.bnd[(size_t)i * capF + k];
-            const uint32_t oc = a.outc[(size_t)i * capF + k];
+        const uint32_t extra = nb > nc ? nb - nc : 0u;
+        const uint32_t from_fl = fln > take ? min(extra, fln - take) : 0u;
+        const uint32_t *cavl = a.cav + (size_t)i * capC;
+        uint32_t *bl = a.bnd + (size_t)i * capF;
+        uint32_t *ol = a.outc + (size_t)i * capF;
+        uint4 *sv = a.scr_v + (size_t)i * capC;
+        uint4 *sn = a.scr_n + (size_t)i * capC;
+        // A: copies of the cavity tetrahedra; each records its local index in its spare word
+        for (uint32_t k = gl; k < nc; k += GL) {
+            const uint32_t c = cavl[k] >> 2;
+            sv[k] = a.T[c].v;
+            sn[k] = a.T[c].n;
+            a.T[c].spare[0] = k;
+        }
+        __syncthreads();
+        // B: facets between two cavity tetrahedra -> (local index << 2 | facet), found by the
+        // claim word (only this cavity's tetrahedra hold S); the other facets are boundary
+        // facets and are rewritten in C.  C: the ball, in the cavity's slots first; the copy
+        // of each boundary facet names its new tetrahedron (LOC_BOUNDARY | slot).  C never
+        // writes the claim or spare words.
+        for (uint32_t task = gl; task < 4 * nc; task += GL) {
+            const uint32_t k = task >> 2;
+            const int f = (int)(task & 3u);
+            const uint32_t code = comp(sn[k], f);
+            const uint32_t nt = code >> 2;
+            if (a.T[nt].any == S)
+                reinterpret_cast<uint32_t *>(&sn[k])[f] = ((uint32_t)a.T[nt].spare[0] << 2) | (code & 3u);
+        }
+        __syncthreads();
+        for (uint32_t b = gl; b < nb; b += GL) {
+            uint32_t slot;
+            if (b < nc) {
+                slot = cavl[b] >> 2;
+            } else {
+                const uint32_t e = b - nc;
+                slot = e < from_fl ? a.fl_cur[take + e] : bump + (e - from_fl);
+            }
+            const uint32_t bc = bl[b];
+            const uint32_t kb = (uint32_t)a.T[bc >> 2].spare[0];
+            const uint32_t oc = ol[b];
             const uint32_t u = oc >> 2;
             const int j = (int)(oc & 3u);
             const uint4 uw = a.T[u].v;
@@ -856,35 +790,68 @@ __global__ __launch_bounds__(256) void k_build16(RoundArgs a) {
             const int pf = orient_new_tet(wv, j);
             a.T[slot].v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
             const uint32_t me = (slot << 2) | (uint32_t)pf;
-            nref(a.T, slot, pf) = oc;             // facet opposite p: outer tetrahedron
-            nref(a.T, u, j) = me;                 // and back
-            nref(a.T, bc >> 2, bc & 3u) = me;     // cavity side now names the new tetrahedron
-            a.outc[(size_t)i * capF + k] = me;
-            if (k == 0) a.vtet[p] = slot;
+            nref(a.T, slot, pf) = oc;  // facet opposite p: the outer tetrahedron
+            nref(a.T, u, j) = me;      // and back
+            reinterpret_cast<uint32_t *>(&sn[kb])[bc & 3u] = LOC_BOUNDARY | slot;
+            ol[b] = me;
+            bl[b] = (kb << 2) | (bc & 3u);
+            for (int q = 0; q < 4; ++q)
+                if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
+            if (b == 0) a.ctr->any_live = slot;
         }
         __syncthreads();
-        for (uint32_t task = gl; task < 3 * nb; task += GS) {
-            const uint32_t k = task / 3, qi = task - 3 * k;
-            const uint32_t me = a.outc[(size_t)i * capF + k];
+        // D: siblings by pivoting around the boundary edges through the copies
+        for (uint32_t task = gl; task < 3 * nb; task += GL) {
+            const uint32_t b = task / 3, qi = task - 3 * b;
+            const uint32_t me = ol[b];
             const uint32_t slot = me >> 2;
             const int pf = (int)(me & 3u);
             const int q = (pf + 1 + (int)qi) & 3;  // the three facets through p
-            const uint32_t bc = a.bnd[(size_t)i * capF + k];
             const uint4 sw = a.T[slot].v;
             const uint32_t wv[4] = {sw.x, sw.y, sw.z, sw.w};
             uint32_t e[2];
             int ne = 0;
             for (int r = 0; r < 4; ++r)
                 if (r != q && r != pf) e[ne++] = wv[r];
-            nref(a.T, slot, q) = pivot(a, bc >> 2, (int)(bc & 3u), e[0], e[1], p, S, nc + 2);
-            if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
+            uint32_t k = bl[b] >> 2;
+            int f = (int)(bl[b] & 3u);
+            uint32_t res = 0;
+            bool ok = false;
+            for (uint32_t guard = 0; guard <= nc + 1; ++guard) {
+                const uint4 cv = sv[k];
+                const uint32_t v4[4] = {cv.x, cv.y, cv.z, cv.w};
+                int xpos = -1;
+                for (int m = 0; m < 4; ++m)
+                    if (m != f && v4[m] != e[0] && v4[m] != e[1]) xpos = m;
+                if (xpos < 0) break;
+                const uint32_t lc = comp(sn[k], xpos);
+                if (lc & LOC_BOUNDARY) {
+                    const uint32_t s2 = lc & ~LOC_BOUNDARY;
+                    const uint4 nv = a.T[s2].v;
+                    const uint32_t w2[4] = {nv.x, nv.y, nv.z, nv.w};
+                    int q2 = -1;
+                    for (int m = 0; m < 4; ++m)
+                        if (w2[m] != e[0] && w2[m] != e[1] && w2[m] != p) q2 = m;
+                    if (q2 >= 0) {
+                        res = (s2 << 2) | (uint32_t)q2;
+                        ok = true;
+                    }
+                    break;
+                }
+                k = lc >> 2;
+                f = (int)(lc & 3u);
+                if (k >= nc) break;
+            }
+            if (!ok) atomicOr(&a.ctr->error, ERR_WALK);
+            nref(a.T, slot, q) = res;
         }
         __syncthreads();
+        // E: cavity slots beyond the ball's size are freed
         const uint32_t fb = act ? a.w_free[i] : 0u;
-        for (uint32_t k = gl; k < nc; k += GS) {
-            const uint32_t c = a.cav[(size_t)i * capC + k] >> 2;
+        for (uint32_t k = nb + gl; k < nc; k += GL) {
+            const uint32_t c = cavl[k] >> 2;
             a.T[c].v.x = DEAD;
-            a.fl_next[fb + k] = c;
+            a.fl_next[fb + (k - nb)] = c;
         }
         if (gl == 0) {
             cav_w += nc;
@@ -954,9 +921,10 @@ hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, hipStream_t s, hi
     k_check<<<nb, 256, 0, s>>>(a);
     if (grouped) {
         const unsigned gb = (max_cand + GPB - 1) / GPB;
-        k_build16<<<gb < 4096u ? gb : 4096u, 256, 0, s>>>(a);
+        k_build_t<16><<<gb < 4096u ? gb : 4096u, 256, 0, s>>>(a);
     } else {
-        k_build<<<max_cand < 16384u ? max_cand : 16384u, 64, 0, s>>>(a);
+        const unsigned gb = (max_cand + 3) / 4;
+        k_build_t<64><<<gb < 4096u ? gb : 4096u, 256, 0, s>>>(a);
     }
     if (ev) hipEventRecord(ev[2], s);
     return hipGetLastError();

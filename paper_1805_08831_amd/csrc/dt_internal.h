@@ -61,7 +61,8 @@ struct Ctr {
     uint32_t error;      // ERR_* flags
     uint32_t init[4];    // sorted positions of the initial tetrahedron's vertices
     uint32_t nwin;       // winners this round
-    uint32_t pad[2];
+    uint32_t any_live;   // some live tetrahedron (walk start of last resort)
+    uint32_t chunk;      // length of a list slice processed as one round
     unsigned long long walk_steps, cav_tets, bnd_facets;
     unsigned long long orient, orient_exact, insphere, insphere_exact, perturbed;
     unsigned long long attempts;
@@ -72,9 +73,8 @@ struct RoundArgs {
     const Vert *V;
     Tet *T;                      // tetrahedron pool
     uint32_t *vtet;              // vertex -> a live tetrahedron containing it
-    const uint32_t *anchor;      // vertex -> an earlier vertex near it on the curve
-    const uint32_t *lvl_start;   // [L + 1] first vertex of each level of the current call
-    int L;
+    uint32_t vlo, vhi;           // vertex records of the current call (Moore order)
+    const uint32_t *anchor;      // [vhi - vlo] walk anchor of each record (a lower-level record)
     const uint32_t *cand_pt;     // current candidate list
     const uint32_t *cand_rank;
     uint32_t *next_pt;           // losers for the next round
@@ -91,6 +91,7 @@ struct RoundArgs {
     uint8_t *status;             // [stride]
     uint32_t *winners;           // [stride] candidates that won this round
     uint32_t *w_take, *w_bump, *w_free;  // [stride] slot reservations of winners
+    uint4 *scr_v, *scr_n;        // [stride][capC] copies of the winners' cavity tetrahedra
     uint32_t *fl_cur;            // free list consumed this round
     uint32_t *fl_next;           // free list filled this round
     Ctr *ctr;
@@ -112,9 +113,10 @@ hipError_t launch_permute(const double *xyz, const uint32_t *vals, uint64_t n, u
                           uint64_t idx_offset, Vert *V, uint32_t *vtet, uint8_t *dup, hipStream_t s);
 hipError_t launch_level_hist(const unsigned long long *keys, uint64_t n, int shift, uint32_t *hist,
                              hipStream_t s);
-hipError_t launch_anchor(const unsigned long long *keys, uint64_t n, uint64_t base, int m,
-                         const uint32_t *lvl_start, const uint32_t *prev_level, int L,
-                         uint32_t fallback, uint32_t *anchor, hipStream_t s);
+hipError_t launch_levels(const uint32_t *src, uint64_t n, uint64_t base, uint64_t salt, const uint64_t *cum,
+                         int L, unsigned long long *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_anchor(const uint32_t *lord, const uint32_t *start, int L, uint64_t base, uint64_t n,
+                         uint32_t *anchor, hipStream_t s);
 hipError_t launch_dedupe(const Vert *V, uint64_t base, uint64_t n, unsigned long long *table,
                          uint64_t tsize, uint8_t *dup, uint32_t *ndup, hipStream_t s);
 hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tmp,
@@ -125,9 +127,10 @@ size_t scan_tmp_entries(uint64_t n);
 hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, Tet *T, uint32_t *vtet,
                        Ctr *ctr, hipStream_t s);
 hipError_t launch_fill_list(const uint32_t *lvl_start, const uint32_t *lvl_size, const uint32_t *lvl_bits,
-                            const unsigned long long *rank_base, int L, unsigned long long first_rank,
-                            uint32_t count, const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt,
-                            uint32_t *cand_rank, uint32_t *ncand, hipStream_t s);
+                            const unsigned long long *rank_base, int L, const uint32_t *lord,
+                            unsigned long long first_rank, uint32_t count, const uint8_t *dup,
+                            const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank, uint32_t *ncand,
+                            hipStream_t s);
 hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, bool big, hipStream_t s);
 hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s);

@@ -1,8 +1,8 @@
 // Point ingest and spatial sort (paper Sec. 2.1 "Sort", Sec. 2.3).
 //
 // validate + bounding box -> Moore key and BRIO level per point -> stable LSD radix sort of
-// (key, input index) -> 32-byte vertex records in sorted order -> per-level ranges, curve
-// anchors (the previous-level point just before each point on the curve) and exact
+// (Moore index, input index) -> 32-byte vertex records in Moore order -> BRIO level of
+// each record and the level-major order of the records (a one-pass counting sort) -> exact
 // duplicate removal by hashing.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -202,6 +202,70 @@ hipError_t launch_keys(const double *xyz, uint64_t n, const double *bbox, int m,
     return hipGetLastError();
 }
 
+// BRIO level of the point at each Moore-sorted position (src[i] = its index within the
+// call), as the key of a stable counting sort that yields the level-major order of the
+// positions; vals[i] = base + i
+__global__ void k_levels(const uint32_t *__restrict__ src, uint64_t n, uint64_t base,
+                         unsigned long long salt, const uint64_t *__restrict__ cum, int L,
+                         unsigned long long *__restrict__ keys, uint32_t *__restrict__ vals) {
+    uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long u = mix64(salt + (unsigned long long)src[i]) >> 11;
+    int lev = 0;
+    while (lev < L - 1) {
+        unsigned long long lo = u * n, hi = __umul64hi(u, n);
+        unsigned long long clo = (unsigned long long)cum[lev] << 53, chi = (unsigned long long)cum[lev] >> 11;
+        if (hi < chi || (hi == chi && lo < clo)) break;
+        ++lev;
+    }
+    keys[i] = (unsigned long long)lev;
+    vals[i] = (uint32_t)(base + i);
+}
+
+hipError_t launch_levels(const uint32_t *src, uint64_t n, uint64_t base, uint64_t salt, const uint64_t *cum,
+                         int L, unsigned long long *keys, uint32_t *vals, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_levels<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, n, base, salt, cum, L, keys, vals);
+    return hipGetLastError();
+}
+
+// Walk anchor of every record of level k >= 1: the record of the nearest non-empty lower
+// level that precedes it on the curve (else that level's first record).  lord lists each
+// level's positions in increasing order; anchor is indexed by position - base.
+__global__ void k_anchor(const uint32_t *__restrict__ lord, const uint32_t *__restrict__ start, int L,
+                         uint64_t base, uint64_t n, uint32_t *__restrict__ anchor) {
+    const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int k = 0;
+    while (k + 1 < L && start[k + 1] <= j) ++k;
+    const uint32_t p = lord[j];
+    int kk = k - 1;
+    while (kk >= 0 && start[kk + 1] == start[kk]) --kk;
+    if (kk < 0) {
+        anchor[p - base] = 0xFFFFFFFFu;
+        return;
+    }
+    uint32_t lo = start[kk], hi = start[kk + 1];  // last entry < p in [lo, hi), else lo
+    uint32_t res = lo;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (lord[mid] < p) {
+            res = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid;
+        }
+    }
+    anchor[p - base] = lord[res];
+}
+
+hipError_t launch_anchor(const uint32_t *lord, const uint32_t *start, int L, uint64_t base, uint64_t n,
+                         uint32_t *anchor, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_anchor<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lord, start, L, base, n, anchor);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ scan
 
 constexpr int SCAN_TILE = 1024;  // 256 threads x 4 items
@@ -384,37 +448,6 @@ hipError_t launch_level_hist(const unsigned long long *keys, uint64_t n, int shi
     unsigned nb = (unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
     if (nb == 0) return hipSuccess;
     k_level_hist<<<nb, 256, 0, s>>>(keys, n, shift, hist);
-    return hipGetLastError();
-}
-
-__global__ void k_anchor(const unsigned long long *__restrict__ keys, uint64_t n, uint64_t base, int m,
-                         const uint32_t *__restrict__ lvl_start, const uint32_t *__restrict__ prev_level,
-                         uint32_t fallback, uint32_t *__restrict__ anchor) {
-    uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    unsigned long long key = keys[i], mask = (1ull << (3 * m)) - 1ull;
-    unsigned lev = (unsigned)(key >> (3 * m));
-    uint32_t pl = prev_level[lev];
-    uint32_t a = fallback;
-    if (pl != NONE) {
-        uint64_t lo = lvl_start[pl], hi = lvl_start[pl + 1];  // non-empty range
-        unsigned long long mo = key & mask;
-        // last j in [lo, hi) with moore(j) <= mo, else lo
-        uint64_t a0 = lo, a1 = hi;
-        while (a1 - a0 > 1) {
-            uint64_t mid = (a0 + a1) / 2;
-            if ((keys[mid] & mask) <= mo) a0 = mid; else a1 = mid;
-        }
-        a = (uint32_t)(base + a0);
-    }
-    anchor[base + i] = a;
-}
-
-hipError_t launch_anchor(const unsigned long long *keys, uint64_t n, uint64_t base, int m, const uint32_t *lvl_start,
-                         const uint32_t *prev_level, int L, uint32_t fallback, uint32_t *anchor, hipStream_t s) {
-    (void)L;
-    if (n == 0) return hipSuccess;
-    k_anchor<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(keys, n, base, m, lvl_start, prev_level, fallback, anchor);
     return hipGetLastError();
 }
 
