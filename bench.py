@@ -16,6 +16,52 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# Sources of the dominant kernel; the measured HBM traffic in PMC_SUMMARY is used only while
+# their hash matches the one recorded there.
+KERNEL_SOURCES = ["paper_1805_08831_amd/csrc/dt_insert.hip", "paper_1805_08831_amd/csrc/dt_internal.h",
+                  "paper_1805_08831_amd/csrc/dt_predicates.h"]
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_cavity16_uniform_1e7_pmc.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the cavity kernel from the committed counter summary, or
+    None when the summary is missing or the kernel sources changed since it was taken."""
+    try:
+        kv = {}
+        with open(PMC_SUMMARY) as fh:
+            for line in fh:
+                if line.startswith("- ") and " = " in line:
+                    k, v = line[2:].split(" = ", 1)
+                    kv[k.strip()] = v.strip().strip("`")
+        if kv.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """Plain device-to-device copy of 256 MiB, three times: the reference for the units of
+    the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = 256 * 1024 * 1024
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {n} bytes three times", flush=True)
+
 # Algorithmic bytes of the cavity kernel (walk + cavity + claim) per attempt, from the
 # counters: candidate/hint/point (48 B), per walk step one tetrahedron row (vertices 16 B +
 # neighbours 16 B) and one new vertex record (32 B), per cavity tetrahedron its two rows
@@ -37,7 +83,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--round-fraction", type=float, default=0.0)
     ap.add_argument("--round-size", type=int, default=0)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per insertion (4, 8, 16, 64; 0: automatic)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the triangulation of one point cloud is not "
@@ -54,7 +107,8 @@ def main():
     d_xyz = torch.from_numpy(xyz).cuda()
     stream = torch.cuda.current_stream()
     tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True,
-                        round_fraction=args.round_fraction, round_size=args.round_size)
+                        round_fraction=args.round_fraction, round_size=args.round_size,
+                        lanes_per_insert=args.lanes)
 
     def step():
         tri.clear()
@@ -119,8 +173,8 @@ def main():
     bytes_per_launch = b_unit * agg["attempts"] / launches
     achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
     peak = 8000.0
-    roofline = {"bound": "hbm", "kernel": "k_cavity", "achieved": round(achieved, 2), "peak": peak,
-                "unit": "GB/s", "frac": round(achieved / peak, 5), "traffic": None,
+    roofline = {"bound": "hbm", "kernel": "k_cavity16", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "GB/s", "frac": round(achieved / peak, 5), "traffic": measured_traffic(),
                 "bytes_per_attempt": round(b_unit, 1), "attempts_per_launch": round(agg["attempts"] / launches, 1),
                 "avg_launch_ms": round(avg_launch_ms, 4)}
 

@@ -61,6 +61,8 @@ typedef struct {
     int timing;             /* 1: time the insertion kernels with HIP events              */
     double round_fraction;  /* round size as a fraction of the current vertex count;
                                0: automatic                                              */
+    uint32_t lanes_per_insert; /* lanes of a wavefront cooperating on one insertion in the
+                                  walk and cavity search: 4, 8, 16 or 64; 0: automatic   */
 } dt_options;
 
 /* Counters of the work done since dt_create or the last dt_clear. */
@@ -105,7 +107,8 @@ int dt_create(dt_ctx **out, const dt_options *opt);
    leaves the context empty.  After DT_E_ARG, DT_E_INPUT or DT_E_DEGENERATE the context
    is as it was before the call; after DT_E_CAPACITY, DT_E_INCOMPLETE, DT_E_DEVICE or
    DT_E_INTERNAL only dt_clear, dt_get_stats, dt_last_error and dt_destroy are
-   meaningful. */
+   meaningful.  Limits: fewer than 2^30 points per call and 2^31 in all (DT_E_CAPACITY),
+   and fewer than 2^30 tetrahedra slots. */
 int dt_insert_points(dt_ctx *ctx, const double *xyz, uint64_t n);
 
 /* Export the finite tetrahedra.  *num_tets is in/out: on input the capacity of the

@@ -26,6 +26,7 @@ namespace {
 
 constexpr uint32_t DEFAULT_ROUND_MAX = 1u << 20;
 constexpr uint32_t DEFAULT_CAVITY_CAP = 128;
+constexpr uint32_t DEFAULT_LANES = 8;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t ROUND_MIN = 64;
 
@@ -90,13 +91,14 @@ struct dt_ctx {
     uint32_t *lpt[4] = {}, *lrank[4] = {};
     size_t bufC = 0, bufF = 0;
     uint32_t capC = 0, capF = 0;
+    uint32_t lanes = 8;  // lanes per insertion of the cavity kernel
     uint32_t *cav = nullptr, *bnd = nullptr, *outc = nullptr, *cnt = nullptr;
-    uint32_t *winners = nullptr, *w_take = nullptr, *w_bump = nullptr, *w_free = nullptr;
     uint4 *scr_v = nullptr, *scr_n = nullptr;
     uint8_t *status = nullptr;
 
     Ctr *ctr = nullptr;
     Ctr *hctr = nullptr;  // pinned mirror
+    unsigned long long *stat = nullptr;  // spread work statistics (summed into ctr each round)
 
     // per-call scratch
     DevBuf<double> staging;
@@ -207,11 +209,9 @@ int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
         c->lpt[k] = c->lrank[k] = nullptr;
     }
     hipFree(c->cav); hipFree(c->bnd); hipFree(c->outc); hipFree(c->cnt); hipFree(c->status);
-    hipFree(c->winners); hipFree(c->w_take); hipFree(c->w_bump); hipFree(c->w_free);
     hipFree(c->scr_v); hipFree(c->scr_n);
     c->scr_v = c->scr_n = nullptr;
     c->cav = c->bnd = c->outc = c->cnt = nullptr;
-    c->winners = c->w_take = c->w_bump = c->w_free = nullptr;
     c->status = nullptr;
     c->list_cap = rmax;
     c->bufC = (size_t)rmax * c->capC;
@@ -225,10 +225,6 @@ int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
          hipMalloc((void **)&c->outc, c->bufF * sizeof(uint32_t)) == hipSuccess &&
          hipMalloc((void **)&c->cnt, 2 * (size_t)rmax * sizeof(uint32_t)) == hipSuccess &&
          hipMalloc((void **)&c->status, rmax) == hipSuccess &&
-         hipMalloc((void **)&c->winners, rmax * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void **)&c->w_take, rmax * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void **)&c->w_bump, rmax * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void **)&c->w_free, rmax * sizeof(uint32_t)) == hipSuccess &&
          hipMalloc((void **)&c->scr_v, c->bufC * sizeof(uint4)) == hipSuccess &&
          hipMalloc((void **)&c->scr_n, c->bufC * sizeof(uint4)) == hipSuccess;
     if (!ok) {
@@ -309,10 +305,6 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     RoundArgs a{};
     a.V = c->V.p;
     a.T = c->T;
-    a.winners = c->winners;
-    a.w_take = c->w_take;
-    a.w_bump = c->w_bump;
-    a.w_free = c->w_free;
     a.scr_v = c->scr_v;
     a.scr_n = c->scr_n;
     a.vtet = c->vtet.p;
@@ -341,14 +333,15 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.fl_cur = c->fl[c->fl_idx];
     a.fl_next = c->fl[c->fl_idx ^ 1];
     a.ctr = d;
+    a.stat = c->stat;
     a.stride = std::max<uint32_t>(max_cand, 1);
     a.capC = capC;
     a.capF = capF;
     a.tcap = c->tcap;
     a.round_hi = (0xFFFFFFFFull - (c->round_counter & 0xFFFFFFFFull)) << 32;
     c->round_counter++;
-    HIPCHK(launch_round(a, max_cand, c->stream, c->opt.timing ? c->ev : nullptr));
-    HIPCHK(launch_round_end(a, max_cand, false, c->stream));
+    HIPCHK(launch_round(a, max_cand, c->lanes, c->stream, c->opt.timing ? c->ev : nullptr));
+    HIPCHK(launch_round_end(a, max_cand, c->stream));
     c->fl_idx ^= 1;
     int rc = sync_ctr(c);
     if (rc) return rc;
@@ -415,6 +408,37 @@ int drain_overflow(dt_ctx *c, uint64_t base, uint64_t n) {
     return DT_OK;
 }
 
+// Splits ranks [first, first + W) into at most FILL_BLOCKS aligned power-of-two blocks within
+// levels; returns the number of ranks covered (W or fewer).
+uint64_t plan_fill(const Levels &lv, uint64_t first, uint64_t W, FillPlan &plan) {
+    plan.nblk = 0;
+    uint32_t total = 0;
+    uint64_t r = first;
+    const uint64_t end = first + W;
+    while (r < end && plan.nblk < (uint32_t)FILL_BLOCKS) {
+        int k = 0;
+        while (k + 1 < lv.L && lv.rank_base[k + 1] <= r) ++k;
+        const uint64_t lend = std::min<uint64_t>(end, lv.rank_base[k + 1]);
+        uint64_t a = r - lv.rank_base[k];
+        const uint64_t b = lend - lv.rank_base[k];
+        while (a < b && plan.nblk < (uint32_t)FILL_BLOCKS) {
+            int w = 31;
+            if (a) w = std::min(w, __builtin_ctzll(a));
+            while ((1ull << w) > b - a) --w;
+            plan.lvl[plan.nblk] = (uint32_t)k;
+            plan.a[plan.nblk] = (uint32_t)a;
+            plan.w[plan.nblk] = (uint32_t)w;
+            plan.off[plan.nblk] = total;
+            total += 1u << w;
+            a += 1ull << w;
+            ++plan.nblk;
+        }
+        r = lv.rank_base[k] + a;
+    }
+    plan.off[plan.nblk] = total;
+    return r - first;
+}
+
 int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint32_t *d_size,
                const uint32_t *d_bits, const unsigned long long *d_rank_base, uint64_t base, uint64_t n) {
     const uint32_t rmax = c->list_cap;
@@ -447,8 +471,10 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint3
         }
         if (c->opt.max_rounds && rounds_this_call >= c->opt.max_rounds)
             return fail(c, DT_E_INCOMPLETE, "round limit %u reached", c->opt.max_rounds);
-        HIPCHK(launch_fill_list(d_start, d_size, d_bits, d_rank_base, lv.L, c->lord, next_rank, W, c->dup.p,
-                                c->vtet.p, c->lpt[ci], c->lrank[ci], &c->ctr->list_count[ci], c->stream));
+        FillPlan plan;
+        W = (uint32_t)plan_fill(lv, next_rank, W, plan);
+        HIPCHK(launch_fill_list(plan, d_start, d_size, d_bits, d_rank_base, c->lord, c->dup.p, c->vtet.p,
+                                c->lpt[ci], c->lrank[ci], &c->ctr->list_count[ci], c->stream));
         next_rank += W;
         const uint32_t max_cand = nl + W;
         int rc = ensure_capacity_for(c, max_cand, c->capF);
@@ -558,7 +584,9 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
     if (!c) return DT_E_CAPACITY;
     if (opt) c->opt = *opt;
     else dt_default_options(&c->opt);
-    if (c->opt.round_fraction < 0 || c->opt.round_fraction > 64) {
+    if (c->opt.round_fraction < 0 || c->opt.round_fraction > 64 ||
+        (c->opt.lanes_per_insert != 0 && c->opt.lanes_per_insert != 4 && c->opt.lanes_per_insert != 8 &&
+         c->opt.lanes_per_insert != 16 && c->opt.lanes_per_insert != 64)) {
         delete c;
         return DT_E_ARG;
     }
@@ -578,13 +606,16 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
         rc = DT_E_DEVICE;
     }
     c->capC = c->opt.cavity_cap ? c->opt.cavity_cap : DEFAULT_CAVITY_CAP;
+    c->lanes = c->opt.lanes_per_insert ? c->opt.lanes_per_insert : DEFAULT_LANES;
     c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
     if (!rc && (hipMalloc((void **)&c->ctr, sizeof(Ctr)) != hipSuccess ||
+                hipMalloc((void **)&c->stat, STAT_WORDS * sizeof(unsigned long long)) != hipSuccess ||
                 hipHostMalloc((void **)&c->hctr, sizeof(Ctr), hipHostMallocDefault) != hipSuccess))
         rc = DT_E_DEVICE;
     for (int k = 0; k < 3 && !rc; ++k)
         if (hipEventCreate(&c->ev[k]) != hipSuccess) rc = DT_E_DEVICE;
     if (!rc && (hipMemsetAsync(c->ctr, 0, sizeof(Ctr), c->stream) != hipSuccess ||
+                hipMemsetAsync(c->stat, 0, STAT_WORDS * sizeof(unsigned long long), c->stream) != hipSuccess ||
                 hipStreamSynchronize(c->stream) != hipSuccess))
         rc = DT_E_DEVICE;
     if (rc) {
@@ -601,8 +632,8 @@ int dt_insert_points(dt_ctx *c, const double *xyz, uint64_t n) {
     if (!c) return DT_E_ARG;
     if (n == 0) return DT_OK;
     if (!xyz) return fail(c, DT_E_ARG, "xyz is NULL");
-    if (c->nv + n >= (1ull << 31) || c->npoints + n >= (1ull << 32) - 2)
-        return fail(c, DT_E_CAPACITY, "too many points (limit 2^31 vertices)");
+    if (c->nv + n >= (1ull << 31) || c->npoints + n >= (1ull << 32) - 2 || n >= (1ull << 30))
+        return fail(c, DT_E_CAPACITY, "too many points (limits: 2^30 per call, 2^31 in all)");
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(hipSetDevice(c->device));
     int rc;
@@ -733,6 +764,7 @@ int dt_clear(dt_ctx *c) {
     if (!c) return DT_E_ARG;
     HIPCHK(hipSetDevice(c->device));
     HIPCHK(hipMemsetAsync(c->ctr, 0, sizeof(Ctr), c->stream));
+    HIPCHK(hipMemsetAsync(c->stat, 0, STAT_WORDS * sizeof(unsigned long long), c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     std::memset(c->hctr, 0, sizeof(Ctr));
     c->npoints = c->nv = 0;
@@ -752,8 +784,9 @@ int dt_destroy(dt_ctx *c) {
     f(c->T); f(c->fl[0]); f(c->fl[1]);
     for (int k = 0; k < 4; ++k) { f(c->lpt[k]); f(c->lrank[k]); }
     f(c->cav); f(c->bnd); f(c->outc); f(c->cnt); f(c->status);
-    f(c->winners); f(c->w_take); f(c->w_bump); f(c->w_free); f(c->scr_v); f(c->scr_n);
+    f(c->scr_v); f(c->scr_n);
     f(c->ctr);
+    f(c->stat);
     if (c->hctr) hipHostFree(c->hctr);
     f(c->staging.p); f(c->keys.p); f(c->keys_tmp.p); f(c->table.p); f(c->vals.p); f(c->vals_tmp.p);
     f(c->hist.p); f(c->scan_tmp.p); f(c->small.p); f(c->bbox.p); f(c->small64.p);

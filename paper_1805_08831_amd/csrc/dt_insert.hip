@@ -1,23 +1,25 @@
 // Concurrent Bowyer-Watson insertion rounds (paper Sec. 2.1 Algorithm 1, Sec. 2.5, Sec. 2.6;
 // concurrency rules of Sec. 3.2).
 //
-// One thread per candidate point.  A round is three kernels:
-//   k_cavity : Walk (visibility walk, Sec. 2.1) from a live tetrahedron of an already
-//              inserted neighbour on the space-filling curve, then Cavity (breadth-first search by perturbed insphere,
-//              ghosts by the half-space + circumdisk rule of Sec. 2.6).  Every tetrahedron
-//              the search touches is claimed with atomicMin on 64-bit claim words:
-//              stamp S = (round part, 2 rank) for cavity tetrahedra, S + 1 for tetrahedra
-//              found outside.  Meeting a lower stamp ends the attempt at once.
+// A round is two kernels over the round's candidate points:
+//   k_cavity_g / k_cavity : Walk (visibility walk, Sec. 2.1) from a live tetrahedron of an
+//              already inserted neighbour on the space-filling curve, then Cavity (breadth-
+//              first search by perturbed insphere, ghosts by the half-space + circumdisk rule
+//              of Sec. 2.6), by a group of lanes (k_cavity_g) or one thread (k_cavity, for
+//              cavities beyond the LDS queue).  Every tetrahedron the search touches is
+//              claimed with atomicMin on 64-bit claim words: stamp S = (round part, 2 rank)
+//              for cavity tetrahedra, S + 1 for tetrahedra found outside.  Meeting a lower
+//              stamp ends the attempt at once.
 //   k_ball   : an attempt wins iff every tetrahedron it touched still holds its stamp, so
 //              the cavities of winners are disjoint from each other and from each other's
 //              adjacent tetrahedra (rules 1a-1c and 2 of Sec. 3.2); the lowest rank in a
 //              round always wins, so every round makes progress.  A winner builds
 //              DelaunayBall (Sec. 2.5): one tetrahedron per boundary facet, glued a priori to
 //              the outer tetrahedron, and glued to its three sibling tetrahedra by pivoting
-//              around each boundary edge through the (still intact) cavity tetrahedra.  Freed
+//              around each boundary edge through copies of the cavity tetrahedra.  Freed
 //              slots are reused in later rounds (Sec. 2.5 end, Sec. 3.6).
-//   k_compact: losers are queued for the next round with their rank; overflowing
-//              cavities are queued for a round with larger per-insertion buffers.
+// Then k_compact queues losers for the next round with their rank, and overflowing
+// cavities for rounds with larger per-insertion buffers.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -43,14 +45,54 @@ __device__ __forceinline__ uint32_t &nref(Tet *T, uint32_t t, uint32_t f) {
     return reinterpret_cast<uint32_t *>(&T[t].n)[f];
 }
 
+// appends the lanes with `keep` to a list at *count, in lane order, with one atomic per wave;
+// returns the position of this lane's entry (valid where keep)
+__device__ __forceinline__ uint32_t wave_append(bool keep, uint32_t *count) {
+    const unsigned long long m = __ballot(keep);
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t base = 0;
+    if (lane == 0 && m) base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = __shfl(base, 0);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-__device__ __forceinline__ void add_stat(unsigned long long *dst, unsigned v) {
+__device__ __forceinline__ void add_stat(unsigned long long *stat, int id, unsigned v) {
     unsigned s = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, (unsigned long long)s);
+    if ((threadIdx.x & 63) == 0 && s)
+        atomicAdd(&stat[((size_t)id * STAT_SPREAD + (blockIdx.x % STAT_SPREAD)) * STAT_PAD], (unsigned long long)s);
+}
+
+// Reserves v units of the counter *count per thread with one atomic per block (the block is
+// 256 threads; every thread must call it): returns the first unit of this thread's range.
+__device__ __forceinline__ uint32_t block_reserve(uint32_t v, uint32_t *count) {
+    __shared__ uint32_t s_wave[4];
+    __shared__ uint32_t s_base;
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63) s_wave[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t c = s_wave[w];
+            s_wave[w] = t;
+            t += c;
+        }
+        s_base = t ? atomicAdd(count, t) : 0u;
+    }
+    __syncthreads();
+    const uint32_t r = s_base + s_wave[wid] + x - v;
+    __syncthreads();  // s_wave and s_base may be reused by a later call
+    return r;
 }
 
 // Orders a tetrahedron built from outer tetrahedron vertices w (w[j] replaced by the new
@@ -160,39 +202,50 @@ hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *
 
 // ------------------------------------------------------------------ candidate fill
 
-// Ranks: level k owns ranks [rank_base[k], rank_base[k] + 2^bits[k]); rank r maps to the
-// level position bitreverse(r - rank_base[k]) (lord lists each level's records in Moore
-// order), so any window of consecutive ranks is spread evenly along the level's points.
-__global__ void k_fill(const uint32_t *__restrict__ lvl_start, const uint32_t *__restrict__ lvl_size,
-                       const uint32_t *__restrict__ lvl_bits, const unsigned long long *__restrict__ rank_base, int L,
-                       const uint32_t *__restrict__ lord, unsigned long long first_rank, uint32_t count,
-                       const uint8_t *__restrict__ dup,
+// Ranks: level k owns ranks [rank_base[k], rank_base[k] + 2^bits[k]); local rank l maps to
+// the level position q = bitreverse(l) (lord lists each level's records in curve order), so
+// any window of consecutive ranks is spread evenly along the level's points.  Within an
+// aligned block of 2^w local ranks the positions form an arithmetic progression in the
+// order of bitreverse_w of the rank's low bits: thread s takes l = a + bitreverse_w(s), so
+// the block's candidates come out in curve order.  A wave appends its valid candidates
+// with one atomic, in thread order.
+__global__ void k_fill(FillPlan plan, const uint32_t *__restrict__ lvl_start, const uint32_t *__restrict__ lvl_size,
+                       const uint32_t *__restrict__ lvl_bits, const unsigned long long *__restrict__ rank_base,
+                       const uint32_t *__restrict__ lord, const uint8_t *__restrict__ dup,
                        const uint32_t *__restrict__ vtet, uint32_t *__restrict__ cand_pt,
                        uint32_t *__restrict__ cand_rank, uint32_t *__restrict__ ncand) {
-    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count) return;
-    unsigned long long r = first_rank + t;
-    int k = 0;
-    while (k + 1 < L && rank_base[k + 1] <= r) ++k;
-    uint32_t local = (uint32_t)(r - rank_base[k]);
-    uint32_t bits = lvl_bits[k];
-    uint32_t q = bits ? (__brev(local) >> (32 - bits)) : 0u;
-    if (q >= lvl_size[k]) return;
-    uint32_t p = lord[lvl_start[k] + q];
-    if (dup[p] || vtet[p] != NONE) return;
-    uint32_t pos = atomicAdd(ncand, 1u);
-    cand_pt[pos] = p;
-    cand_rank[pos] = (uint32_t)r;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = t < plan.off[plan.nblk];
+    uint32_t p = 0, r = 0;
+    if (ok) {
+        uint32_t j = 0;
+        while (j + 1 < plan.nblk && plan.off[j + 1] <= t) ++j;
+        const uint32_t s = t - plan.off[j], w = plan.w[j], k = plan.lvl[j];
+        const uint32_t local = plan.a[j] + (w ? (__brev(s) >> (32 - w)) : 0u);
+        const uint32_t bits = lvl_bits[k];
+        const uint32_t q = bits ? (__brev(local) >> (32 - bits)) : 0u;
+        ok = q < lvl_size[k];
+        if (ok) {
+            p = lord[lvl_start[k] + q];
+            ok = !dup[p] && vtet[p] == NONE;
+            r = (uint32_t)(rank_base[k] + local);
+        }
+    }
+    const uint32_t pos = wave_append(ok, ncand);
+    if (ok) {
+        cand_pt[pos] = p;
+        cand_rank[pos] = r;
+    }
 }
 
-hipError_t launch_fill_list(const uint32_t *lvl_start, const uint32_t *lvl_size, const uint32_t *lvl_bits,
-                            const unsigned long long *rank_base, int L, const uint32_t *lord,
-                            unsigned long long first_rank, uint32_t count, const uint8_t *dup,
-                            const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank, uint32_t *ncand,
-                            hipStream_t s) {
+hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, const uint32_t *lvl_size,
+                            const uint32_t *lvl_bits, const unsigned long long *rank_base, const uint32_t *lord,
+                            const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank,
+                            uint32_t *ncand, hipStream_t s) {
+    const uint32_t count = plan.off[plan.nblk];
     if (count == 0) return hipSuccess;
-    k_fill<<<(count + 255) / 256, 256, 0, s>>>(lvl_start, lvl_size, lvl_bits, rank_base, L, lord, first_rank,
-                                               count, dup, vtet, cand_pt, cand_rank, ncand);
+    k_fill<<<(count + 255) / 256, 256, 0, s>>>(plan, lvl_start, lvl_size, lvl_bits, rank_base, lord, dup, vtet,
+                                               cand_pt, cand_rank, ncand);
     return hipGetLastError();
 }
 
@@ -417,7 +470,7 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
                             status = ST_OVERFLOW;
                             break;
                         }
-                        a.bnd[(size_t)i * a.capF + nbnd] = (c << 2) | (uint32_t)f;
+                        a.bnd[(size_t)i * a.capF + nbnd] = (k << 2) | (uint32_t)f;
                         a.outc[(size_t)i * a.capF + nbnd] = ncode;
                         ++nbnd;
                     }
@@ -429,93 +482,40 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
         a.cnt[i] = ncav;
         a.cnt[stride + i] = nbnd;
     }
-    add_stat(&a.ctr->attempts, attempt);
-    add_stat(&a.ctr->walk_steps, steps);
-    add_stat(&a.ctr->orient, st.orient);
-    add_stat(&a.ctr->orient_exact, st.orient_exact);
-    add_stat(&a.ctr->insphere, st.insphere);
-    add_stat(&a.ctr->insphere_exact, st.insphere_exact);
-    add_stat(&a.ctr->perturbed, st.perturbed);
+    add_stat(a.stat, STAT_ATTEMPTS, attempt);
+    add_stat(a.stat, STAT_WALK, steps);
+    add_stat(a.stat, STAT_ORIENT, st.orient);
+    add_stat(a.stat, STAT_ORIENT_EXACT, st.orient_exact);
+    add_stat(a.stat, STAT_INSPHERE, st.insphere);
+    add_stat(a.stat, STAT_INSPHERE_EXACT, st.insphere_exact);
+    add_stat(a.stat, STAT_PERTURBED, st.perturbed);
 }
 
 // ------------------------------------------------------------------ check + DelaunayBall
 
-// Winner test and slot reservation, one thread per candidate.  An attempt wins iff it still
-// holds the lowest claim on every tetrahedron of its cavity (any) and no lower attempt
-// has one of its outer tetrahedra in its cavity (cav).  Winners of one round therefore
-// have disjoint cavities, and no cavity meets another winner's outer tetrahedra.
-__global__ __launch_bounds__(256) void k_check(RoundArgs a) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t ncand = *a.ncand_ptr;
-    const uint32_t stride = a.stride;
-    if (i >= ncand || a.status[i] != ST_CAND) return;
-    const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
-    const uint32_t nc = a.cnt[i], nb = a.cnt[stride + i];
-    bool win = true;
-    for (uint32_t k = 0; k < nc; ++k) win &= a.T[a.cav[(size_t)i * a.capC + k] >> 2].any == S;
-    for (uint32_t k = 0; k < nb; ++k) win &= a.T[a.outc[(size_t)i * a.capF + k] >> 2].cav > S;
-    if (!win) {
-        a.status[i] = ST_CONFLICT;
-        return;
-    }
-    // the ball reuses the cavity's slots; F - C more come from the free list of earlier
-    // rounds, then from the bump pointer; C - F surplus cavity slots are freed
-    const uint32_t need = nb > nc ? nb - nc : 0u;
-    const uint32_t take = need ? atomicAdd(&a.ctr->fl_take, need) : 0u;
-    const uint32_t fln = a.ctr->fl_n;
-    const uint32_t from_fl = fln > take ? min(need, fln - take) : 0u;
-    const uint32_t rest = need - from_fl;
-    const uint32_t bump = rest ? atomicAdd(&a.ctr->tet_count, rest) : 0u;
-    if (rest && bump + rest > a.tcap) {
-        // pool full: give the slots back (those inside the pool are marked free) and
-        // retry next round after the host has grown the pool
-        uint32_t give = from_fl;
-        for (uint32_t k = 0; k < rest; ++k)
-            if (bump + k < a.tcap) ++give;
-        const uint32_t fb = atomicAdd(&a.ctr->fl_next, give);
-        uint32_t q = 0;
-        for (uint32_t k = 0; k < from_fl; ++k) a.fl_next[fb + q++] = a.fl_cur[take + k];
-        for (uint32_t k = 0; k < rest; ++k)
-            if (bump + k < a.tcap) {
-                a.T[bump + k].v.x = DEAD;
-                a.fl_next[fb + q++] = bump + k;
-            }
-        atomicOr(&a.ctr->error, ERR_POOL);
-        a.status[i] = ST_CONFLICT;
-        return;
-    }
-    a.status[i] = ST_WON;
-    a.w_take[i] = take;
-    a.w_bump[i] = bump;
-    a.w_free[i] = nc > nb ? atomicAdd(&a.ctr->fl_next, nc - nb) : 0u;
-    a.winners[atomicAdd(&a.ctr->nwin, 1u)] = i;
-}
+// ------------------------------------------------------------------ GS lanes per insertion
 
-// ------------------------------------------------------------------ 16 lanes per insertion
-
-constexpr int GS = 16;              // lanes per insertion
-constexpr int GPB = 256 / GS;       // insertions per 256-thread block
-constexpr uint32_t LCAPC = 128;     // cavity tetrahedra held in LDS per insertion
-constexpr uint32_t LCAPF = 224;     // boundary facets held in LDS per insertion
+constexpr uint32_t LCAPC = 128;  // cavity tetrahedra queued in LDS per insertion
 
 // keeps the compiler from moving LDS accesses across a point where other lanes of the
 // same wave consume them (the hardware processes one wave's LDS requests in order)
 __device__ __forceinline__ void lane_fence() { __asm__ volatile("" ::: "memory"); }
 
-// Same computation as k_cavity, with 16 lanes cooperating on one insertion: the walk
-// tests the four facets of the current tetrahedron on four lanes at once, and the cavity
-// search expands four cavity tetrahedra (four facets each) per step.  Cavity and boundary
-// lists live in LDS and are appended by ballot prefix counts.  Control flow is uniform
-// within each group of 16 lanes.
-__global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
+// Same computation as k_cavity, with GS lanes (4, 8, 16 or 64) cooperating on one
+// insertion: the walk tests the four facets of the current tetrahedron on four lanes at
+// once, and the cavity search expands GS / 4 cavity tetrahedra (four facets each) per step.
+// The cavity queue lives in LDS; cavity and boundary entries are appended by ballot prefix
+// counts.  Control flow is uniform within each group of GS lanes.
+template <int GS>
+__global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
+    constexpr uint32_t GPB = 256 / GS;  // insertions per 256-thread block
+    constexpr uint32_t NP = GS / 4;     // cavity tetrahedra expanded per step
     __shared__ uint32_t s_cav[GPB][LCAPC];
-    __shared__ uint32_t s_bnd[GPB][LCAPF];
-    __shared__ uint32_t s_out[GPB][LCAPF];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t gl = threadIdx.x & (GS - 1);
     const uint32_t gi = threadIdx.x / GS;
     const uint32_t gbase = lane & ~(uint32_t)(GS - 1);
-    const unsigned long long gmask = 0xFFFFull << gbase;
+    const unsigned long long gmask = GS == 64 ? ~0ull : (((1ull << (GS & 63)) - 1ull) << gbase);
     const unsigned long long below = gmask & ((1ull << lane) - 1ull);
     const uint32_t i = blockIdx.x * GPB + gi;
     const uint32_t ncand = *a.ncand_ptr;
@@ -528,8 +528,8 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
         const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
         const Vert pv = a.V[p];
         const P3 P = {pv.x, pv.y, pv.z};
-        // start: near the nearest inserted point among 8 records on either side of p on the
-        // curve, one probe per lane; else near the point's anchor (a record of a lower
+        // start: near the nearest inserted point among GS / 2 records on either side of p on
+        // the curve, one probe per lane; else near the point's anchor (a record of a lower
         // level); else any live tetrahedron
         const uint32_t d = (gl >> 1) + 1;
         const bool inr = (gl & 1) ? (p + d < a.vhi) : (p >= a.vlo + d);
@@ -550,13 +550,9 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
         // Walk: lane j < 4 tests facet j
         int entry = -1;
         bool in_ghost = false;
-        P3 q0, q1, q2, q3;
         const int jl = (int)(gl & 3u);
         for (;;) {
-            q0 = vpos(a.V, w.x);
-            q1 = vpos(a.V, w.y);
-            q2 = vpos(a.V, w.z);
-            q3 = vpos(a.V, w.w);
+            const P3 q0 = vpos(a.V, w.x), q1 = vpos(a.V, w.y), q2 = vpos(a.V, w.z), q3 = vpos(a.V, w.w);
             const uint4 nn = a.T[t].n;
             int o = 1;
             if (gl < 4 && jl != entry)
@@ -580,15 +576,21 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
             }
         }
         if (status == ST_NONE && !in_ghost) {
-            if ((q0.x == P.x && q0.y == P.y && q0.z == P.z) || (q1.x == P.x && q1.y == P.y && q1.z == P.z) ||
-                (q2.x == P.x && q2.y == P.y && q2.z == P.z) || (q3.x == P.x && q3.y == P.y && q3.z == P.z))
-                status = ST_DUP;
+            // p equal to a vertex of its containing tetrahedron: lane j < 4 compares vertex j
+            bool same = false;
+            if (gl < 4) {
+                const P3 v = vpos(a.V, comp(w, jl));
+                same = v.x == P.x && v.y == P.y && v.z == P.z;
+            }
+            if (__ballot(same) & gmask) status = ST_DUP;
         }
         uint32_t ncav = 0, nbnd = 0;
         const uint32_t capC = a.capC, capF = a.capF;
+        uint32_t *bnd = a.bnd + (size_t)i * capF;
+        uint32_t *outc = a.outc + (size_t)i * capF;
         if (status == ST_NONE) {
             // Cavity (same claims as k_cavity): step k expands cavity tetrahedra
-            // k0 .. k0+3, lane (slot, facet) = (gl / 4, gl % 4)
+            // k0 .. k0 + NP - 1, lane (slot, facet) = (gl / 4, gl % 4)
             unsigned long long o0 = 0;
             if (gl == 0) o0 = atomicMin(&a.T[t].any, S);
             o0 = __shfl(o0, (int)gbase);
@@ -603,7 +605,7 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
             }
             lane_fence();
             for (uint32_t k0 = 0, nproc = 0; k0 < ncav && status == ST_NONE; k0 += nproc) {
-                nproc = min(4u, ncav - k0);  // entries expanded in this step
+                nproc = min(NP, ncav - k0);  // entries expanded in this step
                 const uint32_t slot = k0 + (gl >> 2);
                 const int f = jl;
                 const bool lv = slot < k0 + nproc;
@@ -659,18 +661,20 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
                     status = ST_CONFLICT;
                     break;
                 }
-                // a tetrahedron reached through several facets in this step is added once
+                // a tetrahedron reached through several facets in this step is added once:
+                // by the lowest such lane of the group
+                const unsigned long long min_ = __ballot(inside) & gmask;
                 bool first = inside;
-                for (int m = 0; m < GS; ++m) {
-                    const uint32_t um = __shfl(u, (int)gbase + m);
-                    const int im = __shfl((int)inside, (int)gbase + m);
-                    if ((uint32_t)m < gl && im && um == u) first = false;
+                for (unsigned long long mm = min_; mm; mm &= mm - 1ull) {
+                    const int m = __ffsll((long long)mm) - 1;
+                    const uint32_t um = __shfl(u, m);
+                    if ((uint32_t)m < lane && um == u) first = false;
                 }
                 const bool outside = need && !inside;
                 const unsigned long long mi = __ballot(first) & gmask;
                 const unsigned long long mo = __ballot(outside) & gmask;
                 const uint32_t ni = (uint32_t)__popcll(mi), no = (uint32_t)__popcll(mo);
-                if (ncav + ni > capC || nbnd + no > capF) {
+                if (ncav + ni > min(capC, LCAPC) || nbnd + no > capF) {
                     status = ST_OVERFLOW;
                     break;
                 }
@@ -680,9 +684,10 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
                     atomicMin(&a.T[u].cav, S);
                 }
                 if (outside) {
+                    // boundary facet: (local index of c) << 2 | f, and the outer tetrahedron
                     const uint32_t pos = nbnd + (uint32_t)__popcll(mo & below);
-                    s_bnd[gi][pos] = (c << 2) | (uint32_t)f;
-                    s_out[gi][pos] = ncode;
+                    bnd[pos] = (slot << 2) | (uint32_t)f;
+                    outc[pos] = ncode;
                 }
                 ncav += ni;
                 nbnd += no;
@@ -690,13 +695,8 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
             }
             if (status == ST_NONE) status = ST_CAND;
         }
-        if (status == ST_CAND) {
+        if (status == ST_CAND)
             for (uint32_t k = gl; k < ncav; k += GS) a.cav[(size_t)i * capC + k] = s_cav[gi][k];
-            for (uint32_t k = gl; k < nbnd; k += GS) {
-                a.bnd[(size_t)i * capF + k] = s_bnd[gi][k];
-                a.outc[(size_t)i * capF + k] = s_out[gi][k];
-            }
-        }
         if (gl == 0) {
             a.status[i] = status;
             a.cnt[i] = ncav;
@@ -706,161 +706,282 @@ __global__ __launch_bounds__(256) void k_cavity16(RoundArgs a) {
             steps = 0;
         }
     }
-    add_stat(&a.ctr->attempts, attempt);
-    add_stat(&a.ctr->walk_steps, steps);
-    add_stat(&a.ctr->orient, st.orient);
-    add_stat(&a.ctr->orient_exact, st.orient_exact);
-    add_stat(&a.ctr->insphere, st.insphere);
-    add_stat(&a.ctr->insphere_exact, st.insphere_exact);
-    add_stat(&a.ctr->perturbed, st.perturbed);
+    add_stat(a.stat, STAT_ATTEMPTS, attempt);
+    add_stat(a.stat, STAT_WALK, steps);
+    add_stat(a.stat, STAT_ORIENT, st.orient);
+    add_stat(a.stat, STAT_ORIENT_EXACT, st.orient_exact);
+    add_stat(a.stat, STAT_INSPHERE, st.insphere);
+    add_stat(a.stat, STAT_INSPHERE_EXACT, st.insphere_exact);
+    add_stat(a.stat, STAT_PERTURBED, st.perturbed);
 }
 
-// DelaunayBall, GL lanes per winner (Sec. 2.5).  The cavity tetrahedra are first copied to
-// the winner's scratch area and their facets resolved to local codes (another cavity
-// tetrahedron, or the new tetrahedron on that boundary facet); the new tetrahedra take the cavity's own slots
-// (and F - C more when the ball is larger), each glued a priori to its outer tetrahedron;
-// finally each new tetrahedron finds its three siblings by pivoting around boundary edges
-// through the scratch copies.  Reusing the cavity's slots keeps the tetrahedra of a region
-// together in memory.
+// Winner test, slot reservation and DelaunayBall (Sec. 2.5), GL lanes per candidate, all in
+// one wave.  An attempt wins iff it still holds the lowest claim on every tetrahedron of its
+// cavity (any) and no lower attempt has one of its outer tetrahedra in its cavity (cav);
+// winners of one round therefore have disjoint cavities, and no cavity meets another
+// winner's outer tetrahedra, so winners build concurrently without further coordination
+// (claim words are only written by the cavity kernel, so the test of one candidate is not
+// affected by the building of another).
+//
+// The ball takes the cavity's own slots (and F - C more when it is larger).  The
+// tetrahedron on boundary facet f of cavity tetrahedron k is k with vertex f replaced by p
+// (the cavity is star-shaped from p, so p lies on v_f's side of the facet and the
+// orientation is kept; a ghost vertex stays in slot 3), glued a priori to the outer
+// tetrahedron.  Its other three facets pass through p and one edge of its boundary facet;
+// the cavity boundary is a closed surface, so each edge lies on exactly two boundary
+// facets, and the two new tetrahedra on them are the siblings.  They are paired through a
+// hash table of edges in LDS.  Balls too large for the table pair siblings by pivoting
+// around the edge through copies of the cavity tetrahedra instead.
 constexpr uint32_t LOC_BOUNDARY = 0x80000000u;
+constexpr uint32_t HT = 128;             // edge table entries per candidate
+constexpr uint32_t HT_MAX_FACETS = 64;   // balls up to this size use the table (load <= 3/4)
+constexpr unsigned long long HT_EMPTY = ~0ull;
+
+// orders the memory accesses of one group (all in one wave) across phases
+__device__ __forceinline__ void group_fence() {
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t edge_hash(unsigned long long key) {
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits: HT = 128
+}
 
 template <int GL>
-__global__ __launch_bounds__(256) void k_build_t(RoundArgs a) {
-    constexpr uint32_t WPB = 256 / GL;
-    const uint32_t nwin = a.ctr->nwin;
-    const uint32_t stride = a.stride;
-    const uint32_t fln = a.ctr->fl_n;
+__global__ __launch_bounds__(256) void k_ball(RoundArgs a) {
+    constexpr uint32_t GPB = 256 / GL;
+    __shared__ unsigned long long s_key[GPB][HT];
+    __shared__ uint32_t s_val[GPB][HT][2];
+    const uint32_t lane = threadIdx.x & 63u;
     const uint32_t gl = threadIdx.x % GL;
     const uint32_t gi = threadIdx.x / GL;
-    const uint32_t capC = a.capC, capF = a.capF;
+    const uint32_t gbase = lane & ~(uint32_t)(GL - 1);
+    const unsigned long long gmask = GL == 64 ? ~0ull : (((1ull << (GL & 63)) - 1ull) << gbase);
+    const uint32_t i = blockIdx.x * GPB + gi;
+    const uint32_t ncand = *a.ncand_ptr;
+    const uint32_t stride = a.stride, capC = a.capC, capF = a.capF;
     unsigned cav_w = 0, bnd_w = 0;
-    for (uint32_t base = blockIdx.x * WPB; base < nwin; base += gridDim.x * WPB) {
-        const uint32_t w = base + gi;
-        const bool act = w < nwin;
-        const uint32_t i = act ? a.winners[w] : 0u;
-        const uint32_t p = act ? a.cand_pt[i] : 0u;
-        const unsigned long long S = act ? (a.round_hi | (2ull * a.cand_rank[i])) : 0ull;
-        const uint32_t nc = act ? a.cnt[i] : 0u, nb = act ? a.cnt[stride + i] : 0u;
-        const uint32_t take = act ? a.w_take[i] : 0u, bump = act ? a.w_bump[i] : 0u;
-        const uint32_t extra = nb > nc ? nb - nc : 0u;
-        const uint32_t from_fl = fln > take ? min(extra, fln - take) : 0u;
-        const uint32_t *cavl = a.cav + (size_t)i * capC;
-        uint32_t *bl = a.bnd + (size_t)i * capF;
-        uint32_t *ol = a.outc + (size_t)i * capF;
-        uint4 *sv = a.scr_v + (size_t)i * capC;
-        uint4 *sn = a.scr_n + (size_t)i * capC;
-        // A: copies of the cavity tetrahedra; each records its local index in its spare word
+    const bool cand = i < ncand && a.status[i] == ST_CAND;
+    uint32_t p = 0, nc = 0, nb = 0;
+    unsigned long long S = 0;
+    const uint32_t *cavl = a.cav + (size_t)i * capC;
+    const uint32_t *bl = a.bnd + (size_t)i * capF;
+    uint32_t *ol = a.outc + (size_t)i * capF;
+    uint4 *sv = a.scr_v + (size_t)i * capC;
+    uint4 *sn = a.scr_n + (size_t)i * capC;
+    bool ok = true;
+    if (cand) {
+        p = a.cand_pt[i];
+        S = a.round_hi | (2ull * a.cand_rank[i]);
+        nc = a.cnt[i];
+        nb = a.cnt[stride + i];
+        // winner test
+        for (uint32_t k = gl; k < nc; k += GL) ok &= a.T[cavl[k] >> 2].any == S;
+        for (uint32_t k = gl; k < nb; k += GL) ok &= a.T[ol[k] >> 2].cav > S;
+    }
+    const bool win = cand && (__ballot(!ok) & gmask) == 0;
+    // slot reservation by each winner's first lane, one atomic per block: the F - C extra
+    // slots are units of fl_take (units below fl_n are free-list entries of earlier rounds,
+    // the rest are fresh pool slots from tet_count on); C - F surplus cavity slots are freed
+    const bool leader = win && gl == 0;
+    const uint32_t need = leader && nb > nc ? nb - nc : 0u;
+    const uint32_t u0 = block_reserve(need, &a.ctr->fl_take);
+    const uint32_t fln = a.ctr->fl_n, tc0 = a.ctr->tet_count;
+    const bool full = need && u0 + need > fln && tc0 + (u0 + need - fln) > a.tcap;
+    if (full) {
+        // pool full: give the units back (pool slots inside the pool are marked free) and
+        // retry next round after the host has grown the pool
+        uint32_t give = 0;
+        for (uint32_t k = 0; k < need; ++k) {
+            const uint32_t u = u0 + k;
+            if (u < fln || tc0 + (u - fln) < a.tcap) ++give;
+        }
+        const uint32_t g0 = atomicAdd(&a.ctr->fl_next, give);
+        uint32_t q = 0;
+        for (uint32_t k = 0; k < need; ++k) {
+            const uint32_t u = u0 + k;
+            if (u < fln) {
+                a.fl_next[g0 + q++] = a.fl_cur[u];
+            } else if (tc0 + (u - fln) < a.tcap) {
+                a.T[tc0 + (u - fln)].v.x = DEAD;
+                a.fl_next[g0 + q++] = tc0 + (u - fln);
+            }
+        }
+        atomicOr(&a.ctr->error, ERR_POOL);
+    }
+    const bool lbuilt = leader && !full;
+    const uint32_t fb = lbuilt && nc > nb ? atomicAdd(&a.ctr->fl_next, nc - nb) : 0u;  // rare
+    if (cand && gl == 0) a.status[i] = lbuilt ? ST_WON : ST_CONFLICT;
+    const bool built = __shfl((int)lbuilt, (int)gbase) != 0;
+    const uint32_t g_u0 = __shfl(u0, (int)gbase), g_fb = __shfl(fb, (int)gbase);
+    if (built) {
+        const bool table = nb <= HT_MAX_FACETS;
+        // A: copies of the cavity tetrahedra (vertices; for the pivot also the neighbours and
+        // the local index in the spare word); the edge table is cleared
         for (uint32_t k = gl; k < nc; k += GL) {
             const uint32_t c = cavl[k] >> 2;
             sv[k] = a.T[c].v;
-            sn[k] = a.T[c].n;
-            a.T[c].spare[0] = k;
+            if (!table) {
+                sn[k] = a.T[c].n;
+                a.T[c].spare[0] = k;
+            }
         }
-        __syncthreads();
-        // B: facets between two cavity tetrahedra -> (local index << 2 | facet), found by the
-        // claim word (only this cavity's tetrahedra hold S); the other facets are boundary
-        // facets and are rewritten in C.  C: the ball, in the cavity's slots first; the copy
-        // of each boundary facet names its new tetrahedron (LOC_BOUNDARY | slot).  C never
-        // writes the claim or spare words.
-        for (uint32_t task = gl; task < 4 * nc; task += GL) {
-            const uint32_t k = task >> 2;
-            const int f = (int)(task & 3u);
-            const uint32_t code = comp(sn[k], f);
-            const uint32_t nt = code >> 2;
-            if (a.T[nt].any == S)
-                reinterpret_cast<uint32_t *>(&sn[k])[f] = ((uint32_t)a.T[nt].spare[0] << 2) | (code & 3u);
+        if (table)
+            for (uint32_t h = gl; h < HT; h += GL) s_key[gi][h] = HT_EMPTY;
+        group_fence();
+        if (!table) {
+            // B (pivot only): facets between two cavity tetrahedra -> local codes
+            for (uint32_t task = gl; task < 4 * nc; task += GL) {
+                const uint32_t k = task >> 2;
+                const int f = (int)(task & 3u);
+                const uint32_t code = comp(sn[k], f);
+                const uint32_t nt = code >> 2;
+                if (a.T[nt].any == S)
+                    reinterpret_cast<uint32_t *>(&sn[k])[f] = ((uint32_t)a.T[nt].spare[0] << 2) | (code & 3u);
+            }
+            group_fence();
         }
-        __syncthreads();
+        // C: one new tetrahedron per boundary facet (k, f): k with v_f replaced by p
         for (uint32_t b = gl; b < nb; b += GL) {
             uint32_t slot;
             if (b < nc) {
                 slot = cavl[b] >> 2;
             } else {
-                const uint32_t e = b - nc;
-                slot = e < from_fl ? a.fl_cur[take + e] : bump + (e - from_fl);
+                const uint32_t u = g_u0 + (b - nc);
+                slot = u < fln ? a.fl_cur[u] : tc0 + (u - fln);
             }
-            const uint32_t bc = bl[b];
-            const uint32_t kb = (uint32_t)a.T[bc >> 2].spare[0];
+            const uint32_t bc = bl[b];  // local index of the cavity tetrahedron << 2 | facet
+            const uint32_t kb = bc >> 2;
+            const int f = (int)(bc & 3u);
             const uint32_t oc = ol[b];
-            const uint32_t u = oc >> 2;
-            const int j = (int)(oc & 3u);
-            const uint4 uw = a.T[u].v;
-            uint32_t wv[4] = {uw.x, uw.y, uw.z, uw.w};
-            wv[j] = p;
-            const int pf = orient_new_tet(wv, j);
+            const uint4 cw = sv[kb];
+            uint32_t wv[4] = {cw.x, cw.y, cw.z, cw.w};
+            wv[f] = p;
             a.T[slot].v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
-            const uint32_t me = (slot << 2) | (uint32_t)pf;
-            nref(a.T, slot, pf) = oc;  // facet opposite p: the outer tetrahedron
-            nref(a.T, u, j) = me;      // and back
-            reinterpret_cast<uint32_t *>(&sn[kb])[bc & 3u] = LOC_BOUNDARY | slot;
+            const uint32_t me = (slot << 2) | (uint32_t)f;
+            nref(a.T, slot, f) = oc;           // facet opposite p: the outer tetrahedron
+            nref(a.T, oc >> 2, oc & 3u) = me;  // and back
             ol[b] = me;
-            bl[b] = (kb << 2) | (bc & 3u);
             for (int q = 0; q < 4; ++q)
                 if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
             if (b == 0) a.ctr->any_live = slot;
-        }
-        __syncthreads();
-        // D: siblings by pivoting around the boundary edges through the copies
-        for (uint32_t task = gl; task < 3 * nb; task += GL) {
-            const uint32_t b = task / 3, qi = task - 3 * b;
-            const uint32_t me = ol[b];
-            const uint32_t slot = me >> 2;
-            const int pf = (int)(me & 3u);
-            const int q = (pf + 1 + (int)qi) & 3;  // the three facets through p
-            const uint4 sw = a.T[slot].v;
-            const uint32_t wv[4] = {sw.x, sw.y, sw.z, sw.w};
-            uint32_t e[2];
-            int ne = 0;
-            for (int r = 0; r < 4; ++r)
-                if (r != q && r != pf) e[ne++] = wv[r];
-            uint32_t k = bl[b] >> 2;
-            int f = (int)(bl[b] & 3u);
-            uint32_t res = 0;
-            bool ok = false;
-            for (uint32_t guard = 0; guard <= nc + 1; ++guard) {
-                const uint4 cv = sv[k];
-                const uint32_t v4[4] = {cv.x, cv.y, cv.z, cv.w};
-                int xpos = -1;
-                for (int m = 0; m < 4; ++m)
-                    if (m != f && v4[m] != e[0] && v4[m] != e[1]) xpos = m;
-                if (xpos < 0) break;
-                const uint32_t lc = comp(sn[k], xpos);
-                if (lc & LOC_BOUNDARY) {
-                    const uint32_t s2 = lc & ~LOC_BOUNDARY;
-                    const uint4 nv = a.T[s2].v;
-                    const uint32_t w2[4] = {nv.x, nv.y, nv.z, nv.w};
-                    int q2 = -1;
-                    for (int m = 0; m < 4; ++m)
-                        if (w2[m] != e[0] && w2[m] != e[1] && w2[m] != p) q2 = m;
-                    if (q2 >= 0) {
-                        res = (s2 << 2) | (uint32_t)q2;
-                        ok = true;
+            if (table) {
+                // the three facets through p: facet q holds p and the edge of the boundary
+                // facet without vertex q
+                for (int q = 0; q < 4; ++q) {
+                    if (q == f) continue;
+                    uint32_t e0 = NONE, e1 = NONE;
+                    for (int r = 0; r < 4; ++r)
+                        if (r != q && r != f) {
+                            if (e0 == NONE) e0 = wv[r];
+                            else e1 = wv[r];
+                        }
+                    const unsigned long long key = e0 < e1 ? ((unsigned long long)e0 << 32) | e1
+                                                           : ((unsigned long long)e1 << 32) | e0;
+                    uint32_t h = edge_hash(key);
+                    bool placed = false;
+                    for (uint32_t probe = 0; probe < HT && !placed; ++probe) {
+                        const unsigned long long old = atomicCAS(&s_key[gi][h], HT_EMPTY, key);
+                        if (old == HT_EMPTY || old == key) {
+                            s_val[gi][h][old == HT_EMPTY ? 0 : 1] = (slot << 2) | (uint32_t)q;
+                            placed = true;
+                        }
+                        h = (h + 1) & (HT - 1);
                     }
-                    break;
+                    if (!placed) atomicOr(&a.ctr->error, ERR_WALK);
                 }
-                k = lc >> 2;
-                f = (int)(lc & 3u);
-                if (k >= nc) break;
+            } else {
+                reinterpret_cast<uint32_t *>(&sn[kb])[f] = LOC_BOUNDARY | b;
             }
-            if (!ok) atomicOr(&a.ctr->error, ERR_WALK);
-            nref(a.T, slot, q) = res;
         }
-        __syncthreads();
+        group_fence();
+        // D: the three siblings of each new tetrahedron
+        if (table) {
+            for (uint32_t b = gl; b < nb; b += GL) {
+                const uint32_t me = ol[b];
+                const uint32_t slot = me >> 2;
+                const int f = (int)(me & 3u);
+                const uint4 cw = sv[bl[b] >> 2];
+                uint32_t wv[4] = {cw.x, cw.y, cw.z, cw.w};
+                wv[f] = p;
+                for (int q = 0; q < 4; ++q) {
+                    if (q == f) continue;
+                    uint32_t e0 = NONE, e1 = NONE;
+                    for (int r = 0; r < 4; ++r)
+                        if (r != q && r != f) {
+                            if (e0 == NONE) e0 = wv[r];
+                            else e1 = wv[r];
+                        }
+                    const unsigned long long key = e0 < e1 ? ((unsigned long long)e0 << 32) | e1
+                                                           : ((unsigned long long)e1 << 32) | e0;
+                    const uint32_t mine = (slot << 2) | (uint32_t)q;
+                    uint32_t h = edge_hash(key), res = NONE;
+                    for (uint32_t probe = 0; probe < HT; ++probe) {
+                        if (s_key[gi][h] == key) {
+                            const uint32_t v0 = s_val[gi][h][0], v1 = s_val[gi][h][1];
+                            res = v0 == mine ? v1 : v0;
+                            break;
+                        }
+                        h = (h + 1) & (HT - 1);
+                    }
+                    if (res == NONE) atomicOr(&a.ctr->error, ERR_WALK);
+                    nref(a.T, slot, q) = res;
+                }
+            }
+        } else {
+            for (uint32_t task = gl; task < 3 * nb; task += GL) {
+                const uint32_t b = task / 3, qi = task - 3 * b;
+                const uint32_t me = ol[b];
+                const uint32_t slot = me >> 2;
+                const int pf = (int)(me & 3u);
+                const int q = (pf + 1 + (int)qi) & 3;  // the three facets through p
+                const uint32_t kb = bl[b] >> 2;
+                const uint4 cw = sv[kb];
+                const uint32_t c4[4] = {cw.x, cw.y, cw.z, cw.w};
+                uint32_t e[2];
+                int ne = 0;
+                for (int r = 0; r < 4; ++r)
+                    if (r != q && r != pf) e[ne++] = c4[r];
+                uint32_t k = kb;
+                int f = pf;
+                uint32_t res = 0;
+                bool found = false;
+                for (uint32_t guard = 0; guard <= nc + 1; ++guard) {
+                    const uint4 cv = sv[k];
+                    const uint32_t v4[4] = {cv.x, cv.y, cv.z, cv.w};
+                    int xpos = -1;
+                    for (int m = 0; m < 4; ++m)
+                        if (m != f && v4[m] != e[0] && v4[m] != e[1]) xpos = m;
+                    if (xpos < 0) break;
+                    const uint32_t lc = comp(sn[k], xpos);
+                    if (lc & LOC_BOUNDARY) {
+                        // boundary facet (k, xpos): its new tetrahedron has p at xpos, and
+                        // the facet through p, e0, e1 is opposite its vertex f
+                        res = (ol[lc & ~LOC_BOUNDARY] & ~3u) | (uint32_t)f;
+                        found = true;
+                        break;
+                    }
+                    k = lc >> 2;
+                    f = (int)(lc & 3u);
+                    if (k >= nc) break;
+                }
+                if (!found) atomicOr(&a.ctr->error, ERR_WALK);
+                nref(a.T, slot, q) = res;
+            }
+        }
         // E: cavity slots beyond the ball's size are freed
-        const uint32_t fb = act ? a.w_free[i] : 0u;
         for (uint32_t k = nb + gl; k < nc; k += GL) {
             const uint32_t c = cavl[k] >> 2;
             a.T[c].v.x = DEAD;
-            a.fl_next[fb + (k - nb)] = c;
+            a.fl_next[g_fb + (k - nb)] = c;
         }
         if (gl == 0) {
-            cav_w += nc;
-            bnd_w += nb;
+            cav_w = nc;
+            bnd_w = nb;
         }
-        __syncthreads();
     }
-    add_stat(&a.ctr->cav_tets, cav_w);
-    add_stat(&a.ctr->bnd_facets, bnd_w);
+    add_stat(a.stat, STAT_CAV_TETS, cav_w);
+    add_stat(a.stat, STAT_BND_FACETS, bnd_w);
 }
 
 // ------------------------------------------------------------------ round end
@@ -868,25 +989,30 @@ __global__ __launch_bounds__(256) void k_build_t(RoundArgs a) {
 __global__ void k_compact(RoundArgs a) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ncand = *a.ncand_ptr;
-    if (i >= ncand) return;
-    const uint8_t s = a.status[i];
-    if (s == ST_CONFLICT || s == ST_CAND) {
-        const uint32_t pos = atomicAdd(a.nnext_ptr, 1u);
-        a.next_pt[pos] = a.cand_pt[i];
-        a.next_rank[pos] = a.cand_rank[i];
-        atomicAdd(&a.ctr->conflicts, 1u);
-    } else if (s == ST_OVERFLOW) {
-        const uint32_t pos = atomicAdd(a.novf_ptr, 1u);
-        a.ovf_pt[pos] = a.cand_pt[i];
-        a.ovf_rank[pos] = a.cand_rank[i];
-        atomicAdd(&a.ctr->overflows, 1u);
-    } else if (s == ST_WON) {
-        atomicAdd(&a.ctr->won, 1u);
-    } else if (s == ST_DUP) {
-        atomicAdd(&a.ctr->dups, 1u);
-    } else {
-        atomicOr(&a.ctr->error, ERR_WALK);
+    const uint8_t s = i < ncand ? a.status[i] : (uint8_t)ST_NONE;
+    const bool again = i < ncand && (s == ST_CONFLICT || s == ST_CAND);
+    const bool ovf = i < ncand && s == ST_OVERFLOW;
+    const uint32_t pn = wave_append(again, a.nnext_ptr);
+    const uint32_t po = wave_append(ovf, a.novf_ptr);
+    if (again) {
+        a.next_pt[pn] = a.cand_pt[i];
+        a.next_rank[pn] = a.cand_rank[i];
     }
+    if (ovf) {
+        a.ovf_pt[po] = a.cand_pt[i];
+        a.ovf_rank[po] = a.cand_rank[i];
+    }
+    const unsigned n_again = wave_sum(again ? 1u : 0u), n_ovf = wave_sum(ovf ? 1u : 0u);
+    const unsigned n_won = wave_sum(i < ncand && s == ST_WON ? 1u : 0u);
+    const unsigned n_dup = wave_sum(i < ncand && s == ST_DUP ? 1u : 0u);
+    const bool bad = i < ncand && !(again || ovf || s == ST_WON || s == ST_DUP);
+    if ((threadIdx.x & 63u) == 0) {
+        if (n_again) atomicAdd(&a.ctr->conflicts, n_again);
+        if (n_ovf) atomicAdd(&a.ctr->overflows, n_ovf);
+        if (n_won) atomicAdd(&a.ctr->won, n_won);
+        if (n_dup) atomicAdd(&a.ctr->dups, n_dup);
+    }
+    if (bad) atomicOr(&a.ctr->error, ERR_WALK);
 }
 
 // carry the unused part of this round's free list behind the slots freed this round
@@ -898,43 +1024,56 @@ __global__ void k_freelist_carry(RoundArgs a) {
         a.fl_next[nxt + k] = a.fl_cur[take + k];
 }
 
-__global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap) {
-    const uint32_t left = ctr->fl_take < ctr->fl_n ? ctr->fl_n - ctr->fl_take : 0u;
-    if (ctr->tet_count > tcap) ctr->tet_count = tcap;  // slots beyond the pool were never used
+__global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, const unsigned long long *stat) {
+    const uint32_t t = threadIdx.x;
+    if (t < NSTAT) {
+        unsigned long long sum = 0;
+        for (int k = 0; k < STAT_SPREAD; ++k) sum += stat[((size_t)t * STAT_SPREAD + k) * STAT_PAD];
+        unsigned long long *dst[NSTAT] = {&ctr->attempts, &ctr->walk_steps, &ctr->orient, &ctr->orient_exact,
+                                         &ctr->insphere, &ctr->insphere_exact, &ctr->perturbed,
+                                         &ctr->cav_tets, &ctr->bnd_facets};
+        *dst[t] = sum;
+    }
+    if (t != 0) return;
+    const uint32_t fln = ctr->fl_n, take = ctr->fl_take;
+    if (take > fln) {
+        // units beyond the free list were fresh pool slots (beyond the pool: never used)
+        const unsigned long long tc = (unsigned long long)ctr->tet_count + (take - fln);
+        ctr->tet_count = tc > tcap ? tcap : (uint32_t)tc;
+    }
+    const uint32_t left = take < fln ? fln - take : 0u;
     ctr->fl_n = ctr->fl_next + left;
     ctr->fl_take = 0;
     ctr->fl_next = 0;
-    ctr->nwin = 0;
     *consumed = 0;  // the list this round read from is empty now
 }
 
-bool round_fits_lds(uint32_t capC, uint32_t capF) { return capC <= LCAPC && capF <= LCAPF; }
-
-hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, hipStream_t s, hipEvent_t *ev) {
+hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, hipStream_t s, hipEvent_t *ev) {
     if (max_cand == 0) return hipSuccess;
     const unsigned nb = (max_cand + 255) / 256;
-    const bool grouped = round_fits_lds(a.capC, a.capF);
+    const bool grouped = a.capC <= LCAPC;
     if (ev) hipEventRecord(ev[0], s);
-    if (grouped) k_cavity16<<<(max_cand + GPB - 1) / GPB, 256, 0, s>>>(a);
-    else k_cavity<<<nb, 256, 0, s>>>(a);
-    if (ev) hipEventRecord(ev[1], s);
-    k_check<<<nb, 256, 0, s>>>(a);
-    if (grouped) {
-        const unsigned gb = (max_cand + GPB - 1) / GPB;
-        k_build_t<16><<<gb < 4096u ? gb : 4096u, 256, 0, s>>>(a);
+    if (!grouped) {
+        k_cavity<<<nb, 256, 0, s>>>(a);
+    } else if (lanes == 4) {
+        k_cavity_g<4><<<(max_cand + 63) / 64, 256, 0, s>>>(a);
+    } else if (lanes == 8) {
+        k_cavity_g<8><<<(max_cand + 31) / 32, 256, 0, s>>>(a);
+    } else if (lanes == 64) {
+        k_cavity_g<64><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
     } else {
-        const unsigned gb = (max_cand + 3) / 4;
-        k_build_t<64><<<gb < 4096u ? gb : 4096u, 256, 0, s>>>(a);
+        k_cavity_g<16><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
     }
+    if (ev) hipEventRecord(ev[1], s);
+    k_ball<16><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
     if (ev) hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 
-hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, bool big, hipStream_t s) {
-    (void)big;
+hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s) {
     if (max_cand) k_compact<<<(max_cand + 255) / 256, 256, 0, s>>>(a);
     k_freelist_carry<<<256, 256, 0, s>>>(a);
-    k_roll<<<1, 1, 0, s>>>(a.ctr, const_cast<uint32_t *>(a.ncand_ptr), a.tcap);
+    k_roll<<<1, 64, 0, s>>>(a.ctr, const_cast<uint32_t *>(a.ncand_ptr), a.tcap, a.stat);
     return hipGetLastError();
 }
 

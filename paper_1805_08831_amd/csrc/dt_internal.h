@@ -47,11 +47,23 @@ enum : uint32_t {
     ERR_POOL = 16u  // not an error: the tetrahedron pool filled up during a round
 };
 
+// Work statistics accumulated by the round kernels.  Each is spread over STAT_SPREAD
+// counters 128 bytes apart (block b adds to counter b % STAT_SPREAD), so that concurrent
+// waves do not serialize on one address; k_roll sums them into Ctr.
+enum : int {
+    STAT_ATTEMPTS = 0, STAT_WALK, STAT_ORIENT, STAT_ORIENT_EXACT, STAT_INSPHERE, STAT_INSPHERE_EXACT,
+    STAT_PERTURBED, STAT_CAV_TETS, STAT_BND_FACETS, NSTAT
+};
+constexpr int STAT_SPREAD = 64;
+constexpr int STAT_PAD = 16;  // u64 words per counter (128 bytes)
+constexpr size_t STAT_WORDS = (size_t)NSTAT * STAT_SPREAD * STAT_PAD;
+
 // Device-resident counters of the round driver.
 struct Ctr {
     uint32_t list_count[4];  // lengths of the candidate lists (two normal, two overflow)
     uint32_t fl_n;       // free slots available this round
-    uint32_t fl_take;    // free slots taken this round (may exceed fl_n)
+    uint32_t fl_take;    // slot units taken this round: unit u < fl_n is free-list entry u,
+                         // unit u >= fl_n is pool slot tet_count + (u - fl_n)
     uint32_t fl_next;    // slots freed this round
     uint32_t tet_count;  // bump pointer of the tetrahedron pool
     uint32_t won;        // insertions this round
@@ -60,7 +72,7 @@ struct Ctr {
     uint32_t dups;       // duplicates found this round
     uint32_t error;      // ERR_* flags
     uint32_t init[4];    // sorted positions of the initial tetrahedron's vertices
-    uint32_t nwin;       // winners this round
+    uint32_t unused0;
     uint32_t any_live;   // some live tetrahedron (walk start of last resort)
     uint32_t chunk;      // length of a list slice processed as one round
     unsigned long long walk_steps, cav_tets, bnd_facets;
@@ -89,14 +101,22 @@ struct RoundArgs {
     uint32_t *outc;              // [stride][capF] outer codes, then new tetrahedra
     uint32_t *cnt;               // [2][stride] cavity size, boundary size
     uint8_t *status;             // [stride]
-    uint32_t *winners;           // [stride] candidates that won this round
-    uint32_t *w_take, *w_bump, *w_free;  // [stride] slot reservations of winners
     uint4 *scr_v, *scr_n;        // [stride][capC] copies of the winners' cavity tetrahedra
     uint32_t *fl_cur;            // free list consumed this round
     uint32_t *fl_next;           // free list filled this round
     Ctr *ctr;
+    unsigned long long *stat;    // [NSTAT][STAT_SPREAD][STAT_PAD] work statistics
     uint32_t stride, capC, capF, tcap;
     unsigned long long round_hi;  // (0xFFFFFFFF - round) << 32: newer rounds claim lower
+};
+
+// New candidates of one round: a window of ranks split into aligned power-of-two blocks,
+// block j covering local ranks a[j] .. a[j] + 2^w[j] of level lvl[j]; threads off[j] ..
+// off[j+1] handle block j, in the order of the records on the curve.
+constexpr int FILL_BLOCKS = 48;
+struct FillPlan {
+    uint32_t nblk;
+    uint32_t lvl[FILL_BLOCKS], a[FILL_BLOCKS], w[FILL_BLOCKS], off[FILL_BLOCKS + 1];
 };
 
 // ---- launch wrappers (dt_sort.hip) ----
@@ -126,13 +146,12 @@ size_t scan_tmp_entries(uint64_t n);
 // ---- launch wrappers (dt_insert.hip) ----
 hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, Tet *T, uint32_t *vtet,
                        Ctr *ctr, hipStream_t s);
-hipError_t launch_fill_list(const uint32_t *lvl_start, const uint32_t *lvl_size, const uint32_t *lvl_bits,
-                            const unsigned long long *rank_base, int L, const uint32_t *lord,
-                            unsigned long long first_rank, uint32_t count, const uint8_t *dup,
-                            const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank, uint32_t *ncand,
-                            hipStream_t s);
-hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, hipStream_t s, hipEvent_t *ev);
-hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, bool big, hipStream_t s);
+hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, const uint32_t *lvl_size,
+                            const uint32_t *lvl_bits, const unsigned long long *rank_base, const uint32_t *lord,
+                            const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank,
+                            uint32_t *ncand, hipStream_t s);
+hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s);
 hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s);
 hipError_t launch_output(const Tet *T, const Vert *V, const uint32_t *map, uint32_t count, uint32_t *tets,
                          int64_t *nbrs, hipStream_t s);

@@ -25,7 +25,8 @@ class DTError(RuntimeError):
 class dt_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("round_size", ctypes.c_uint32),
                 ("cavity_cap", ctypes.c_uint32), ("capacity_tets", ctypes.c_uint64), ("seed", ctypes.c_uint64),
-                ("max_rounds", ctypes.c_uint32), ("timing", ctypes.c_int), ("round_fraction", ctypes.c_double)]
+                ("max_rounds", ctypes.c_uint32), ("timing", ctypes.c_int), ("round_fraction", ctypes.c_double),
+                ("lanes_per_insert", ctypes.c_uint32)]
 
 
 _STAT_U64 = ["points", "vertices", "duplicates", "tets", "rounds", "attempts", "inserted", "conflicts",
@@ -163,11 +164,12 @@ class Triangulation:
     (host or device); `tets` returns (tets[T,4] uint32, nbrs[T,4] int64)."""
 
     def __init__(self, device=0, stream=None, round_size=0, cavity_cap=0, capacity_tets=0, seed=0x5EED,
-                 max_rounds=0, timing=False, round_fraction=0.0):
+                 max_rounds=0, timing=False, round_fraction=0.0, lanes_per_insert=0):
         o = dt_default_options()
         o.device, o.round_size, o.cavity_cap = int(device), int(round_size), int(cavity_cap)
         o.capacity_tets, o.seed, o.max_rounds = int(capacity_tets), int(seed), int(max_rounds)
         o.timing, o.round_fraction = int(bool(timing)), float(round_fraction)
+        o.lanes_per_insert = int(lanes_per_insert)
         o.stream = stream
         self.ctx = dt_create(o)
 

@@ -44,6 +44,13 @@ def test_default_options_and_argument_errors(libdt):
     assert dt.lib().dt_get_tets(None, None, None, None) == dt.DT_E_ARG
     assert dt.lib().dt_destroy(None) == dt.DT_E_ARG
     assert dt.lib().dt_last_error(None) == b"no context"
+    # invalid options are rejected before any device work
+    h = ctypes.c_void_p()
+    for field, bad in [("lanes_per_insert", 5), ("lanes_per_insert", 32), ("round_fraction", -1.0)]:
+        o2 = dt.dt_options()
+        dt.lib().dt_default_options(ctypes.byref(o2))
+        setattr(o2, field, bad)
+        assert dt.lib().dt_create(ctypes.byref(h), ctypes.byref(o2)) == dt.DT_E_ARG, field
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
