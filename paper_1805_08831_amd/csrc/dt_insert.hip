@@ -6,13 +6,14 @@
 //              already inserted neighbour on the space-filling curve, then Cavity (breadth-
 //              first search by perturbed insphere, ghosts by the half-space + circumdisk rule
 //              of Sec. 2.6), by a group of lanes (k_cavity_g) or one thread (k_cavity, for
-//              cavities beyond the LDS queue).  Every tetrahedron the search touches is
-//              claimed with atomicMin on 64-bit claim words: stamp S = (round part, 2 rank)
-//              for cavity tetrahedra, S + 1 for tetrahedra found outside.  Meeting a lower
-//              stamp ends the attempt at once.
-//   k_ball   : an attempt wins iff every tetrahedron it touched still holds its stamp, so
-//              the cavities of winners are disjoint from each other and from each other's
-//              adjacent tetrahedra (rules 1a-1c and 2 of Sec. 3.2); the lowest rank in a
+//              cavities beyond the LDS queue).  The attempt claims every tetrahedron it
+//              touches with atomicMin on the tetrahedron's 64-bit claim word: its stamp
+//              S = (round part, 2 rank) for cavity tetrahedra, S + 1 for tetrahedra found
+//              outside.  Meeting a lower claim that excludes it ends the attempt at once.
+//   k_ball   : an attempt wins iff no lower attempt claimed a tetrahedron of its cavity
+//              (either way) or has one of its outer tetrahedra in its cavity, so the cavities
+//              of winners are disjoint from each other and from each other's adjacent
+//              tetrahedra (rules 1a-1c and 2 of Sec. 3.2); the lowest rank in a
 //              round always wins, so every round makes progress.  A winner builds
 //              DelaunayBall (Sec. 2.5): one tetrahedron per boundary facet, glued a priori to
 //              the outer tetrahedron, and glued to its three sibling tetrahedra by pivoting
@@ -69,9 +70,9 @@ __device__ __forceinline__ void add_stat(unsigned long long *stat, int id, unsig
 
 // Reserves v units of the counter *count per thread with one atomic per block (the block is
 // 256 threads; every thread must call it): returns the first unit of this thread's range.
-__device__ __forceinline__ uint32_t block_reserve(uint32_t v, uint32_t *count) {
-    __shared__ uint32_t s_wave[4];
-    __shared__ uint32_t s_base;
+// tmp: 5 words of LDS the block does not use meanwhile.
+__device__ __forceinline__ uint32_t block_reserve(uint32_t v, uint32_t *count, uint32_t *tmp) {
+    uint32_t *s_wave = tmp, &s_base = tmp[4];
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     uint32_t x = v;
     for (int o = 1; o < 64; o <<= 1) {
@@ -91,7 +92,7 @@ __device__ __forceinline__ uint32_t block_reserve(uint32_t v, uint32_t *count) {
     }
     __syncthreads();
     const uint32_t r = s_base + s_wave[wid] + x - v;
-    __syncthreads();  // s_wave and s_base may be reused by a later call
+    __syncthreads();  // tmp may be reused after the call
     return r;
 }
 
@@ -182,8 +183,8 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
         Tet r;
         r.v = make_uint4(TV[t][0], TV[t][1], TV[t][2], TV[t][3]);
         r.n = make_uint4(N[t][0], N[t][1], N[t][2], N[t][3]);
-        r.any = r.cav = ~0ull;
-        r.spare[0] = r.spare[1] = 0;
+        r.claim = ~0ull;
+        r.spare[0] = r.spare[1] = r.spare[2] = 0;
         T[t] = r;
     }
     for (int k = 0; k < 4; ++k) {
@@ -371,19 +372,17 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
         uint32_t ncav = 0, nbnd = 0;
         if (status == ST_NONE) {
             // Cavity: breadth-first search; cav entries hold (tetrahedron << 2 | facet it was
-            // entered through), which is skipped when the tetrahedron is expanded.
-            // Claims: T[t].any = min stamp of every attempt touching t, S for this cavity's
-            // tetrahedra and S + 1 for those found outside (so the parity tells the kind);
-            // T[t].cav = min stamp of the attempts with t in their cavity.  All neighbours of
-            // a cavity tetrahedron are claimed tentatively (S + 1) and fetched together; a
-            // neighbour of a finite cavity tetrahedron c shares the facet's three vertices
-            // with c, so only its apex vertex is fetched.
+            // entered through), which is skipped when the tetrahedron is expanded.  Every
+            // neighbour examined is claimed with S + 1 first; the value returned says whether
+            // it is already in this cavity (S) or outside it (S + 1), or whether a lower
+            // attempt has it in its cavity (lower even value: this attempt loses).  A
+            // tetrahedron found inside is then claimed with S; a lower odd value on it means a
+            // lower attempt has it outside its cavity, and this attempt loses too.
             {
-                const unsigned long long o0 = atomicMin(&a.T[t].any, S);
+                const unsigned long long o0 = atomicMin(&a.T[t].claim, S);
                 if (o0 < S) {
                     status = ST_CONFLICT;
                 } else {
-                    atomicMin(&a.T[t].cav, S);
                     a.cav[(size_t)i * a.capC] = t << 2;
                     ncav = 1;
                 }
@@ -395,36 +394,25 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
                 const uint4 cv = a.T[c].v;
                 const uint4 cn = a.T[c].n;
                 const bool cghost = cv.w == GHOST;
-                unsigned long long o1[4];
-                uint4 uw[4];
-#pragma unroll
-                for (int f = 0; f < 4; ++f) {
-                    o1[f] = S;
-                    if (f == pf) continue;
-                    const uint32_t u = comp(cn, f) >> 2;
-                    o1[f] = atomicMin(&a.T[u].any, S + 1);
-                    uw[f] = a.T[u].v;
-                }
                 P3 cw[4];
                 if (!cghost) {
 #pragma unroll
                     for (int m = 0; m < 4; ++m) cw[m] = vpos(a.V, comp(cv, m));
                 }
-#pragma unroll
-                for (int f = 0; f < 4; ++f) {
-                    if (status != ST_NONE) break;
-                    const unsigned long long o = o1[f];
-                    if (o == S) continue;  // already in this cavity, or the parent: internal facet
+                for (int f = 0; f < 4 && status == ST_NONE; ++f) {
+                    if (f == pf) continue;
+                    const uint32_t ncode = comp(cn, f);
+                    const uint32_t u = ncode >> 2;
+                    const unsigned long long o = atomicMin(&a.T[u].claim, S + 1);
+                    if (o == S) continue;  // already in this cavity: internal facet
                     if (o < S && !(o & 1ull)) {
-                        // a lower attempt has this neighbour in its cavity: this one loses
                         status = ST_CONFLICT;
                         break;
                     }
-                    const uint32_t ncode = comp(cn, f);
-                    const uint32_t u = ncode >> 2;
                     bool inside = false;
                     if (o != S + 1) {
-                        const uint32_t apex = comp(uw[f], (int)(ncode & 3u));
+                        const uint4 uw = a.T[u].v;
+                        const uint32_t apex = comp(uw, (int)(ncode & 3u));
                         if (!cghost && apex != GHOST) {
                             // u = facet f of c + apex; c with vertex f replaced by the apex and
                             // two entries swapped is positively oriented
@@ -451,18 +439,16 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
                             inside = tet_inside(a, u, P, pv.idx, st);
                         }
                         if (inside && o < S) {
-                            // a lower attempt touched a tetrahedron of this cavity
                             status = ST_CONFLICT;
                             break;
                         }
                     }
                     if (inside) {
-                        atomicMin(&a.T[u].any, S);
-                        atomicMin(&a.T[u].cav, S);
                         if (ncav == a.capC) {
                             status = ST_OVERFLOW;
                             break;
                         }
+                        atomicMin(&a.T[u].claim, S);
                         a.cav[(size_t)i * a.capC + ncav] = ncode;
                         ++ncav;
                     } else {
@@ -496,6 +482,35 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
 // ------------------------------------------------------------------ GS lanes per insertion
 
 constexpr uint32_t LCAPC = 128;  // cavity tetrahedra queued in LDS per insertion
+constexpr uint32_t HM = 256;     // LDS set of the attempt's own cavity and outer tetrahedra
+constexpr uint32_t MEM_EMPTY = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t mem_hash(uint32_t t) { return (t * 2654435761u) >> 24; }  // 8 bits
+
+// kind of tetrahedron t in the set (0 cavity, 1 outer) or -1
+__device__ __forceinline__ int mem_find(const uint32_t *mem, uint32_t t) {
+    uint32_t h = mem_hash(t);
+    for (uint32_t probe = 0; probe < HM; ++probe) {
+        const uint32_t e = mem[h];
+        if (e == MEM_EMPTY) return -1;
+        if ((e >> 1) == t) return (int)(e & 1u);
+        h = (h + 1) & (HM - 1);
+    }
+    return -1;
+}
+
+// adds t with `kind`: 1 if this call added it, 0 if it was there, -1 if the set is full
+__device__ __forceinline__ int mem_insert(uint32_t *mem, uint32_t t, uint32_t kind) {
+    uint32_t h = mem_hash(t);
+    const uint32_t e = (t << 1) | kind;
+    for (uint32_t probe = 0; probe < HM; ++probe) {
+        const uint32_t old = atomicCAS(&mem[h], MEM_EMPTY, e);
+        if (old == MEM_EMPTY) return 1;
+        if ((old >> 1) == t) return 0;
+        h = (h + 1) & (HM - 1);
+    }
+    return -1;
+}
 
 // keeps the compiler from moving LDS accesses across a point where other lanes of the
 // same wave consume them (the hardware processes one wave's LDS requests in order)
@@ -511,6 +526,7 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
     constexpr uint32_t GPB = 256 / GS;  // insertions per 256-thread block
     constexpr uint32_t NP = GS / 4;     // cavity tetrahedra expanded per step
     __shared__ uint32_t s_cav[GPB][LCAPC];
+    __shared__ uint32_t s_mem[GPB][HM];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t gl = threadIdx.x & (GS - 1);
     const uint32_t gi = threadIdx.x / GS;
@@ -585,21 +601,28 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
             if (__ballot(same) & gmask) status = ST_DUP;
         }
         uint32_t ncav = 0, nbnd = 0;
-        const uint32_t capC = a.capC, capF = a.capF;
-        uint32_t *bnd = a.bnd + (size_t)i * capF;
-        uint32_t *outc = a.outc + (size_t)i * capF;
+        const uint32_t capL = min(a.capC, LCAPC), capF = a.capF;
+        uint32_t *bnd = a.bnd + (size_t)i * a.capF;
+        uint32_t *outc = a.outc + (size_t)i * a.capF;
+        uint32_t *mem = s_mem[gi];
         if (status == ST_NONE) {
-            // Cavity (same claims as k_cavity): step k expands cavity tetrahedra
-            // k0 .. k0 + NP - 1, lane (slot, facet) = (gl / 4, gl % 4)
+            // Cavity.  Step k expands cavity tetrahedra k0 .. k0 + NP - 1, lane (slot, facet)
+            // = (gl / 4, gl % 4).  Claims as in k_cavity: S + 1 on a tetrahedron met for the
+            // first time (the returned value shows a lower cavity claim: this attempt loses),
+            // lowered to S once it is found inside (a lower odd value on it: loses too).  The
+            // attempt's own tetrahedra are tracked in the LDS set `mem`, so each is claimed
+            // and tested once.
+            for (uint32_t h = gl; h < HM; h += GS) mem[h] = MEM_EMPTY;
+            lane_fence();
             unsigned long long o0 = 0;
-            if (gl == 0) o0 = atomicMin(&a.T[t].any, S);
+            if (gl == 0) o0 = atomicMin(&a.T[t].claim, S);
             o0 = __shfl(o0, (int)gbase);
             if (o0 < S) {
                 status = ST_CONFLICT;
             } else {
                 if (gl == 0) {
-                    atomicMin(&a.T[t].cav, S);
                     s_cav[gi][0] = t << 2;
+                    mem_insert(mem, t, 0u);
                 }
                 ncav = 1;
             }
@@ -620,15 +643,17 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 }
                 const uint32_t ncode = comp(cn, f);
                 const uint32_t u = ncode >> 2;
-                unsigned long long o1 = S;
-                if (act) {
-                    o1 = atomicMin(&a.T[u].any, S + 1);
+                const int kind = act ? mem_find(mem, u) : -1;  // 0: in this cavity, 1: outside it
+                const bool need = act && kind < 0;
+                unsigned long long o1 = ~0ull;
+                if (need) {
+                    o1 = atomicMin(&a.T[u].claim, S + 1);
                     uw = a.T[u].v;
                 }
-                const bool lower_cav = act && o1 < S && !(o1 & 1ull);
-                const bool need = act && o1 != S && !lower_cav;
+                // a lower attempt has u in its cavity: this one loses either way
+                bool conflict = need && o1 < S && !(o1 & 1ull);
                 bool inside = false;
-                if (need) {
+                if (need && !conflict) {
                     const bool cghost = cv.w == GHOST;
                     const uint32_t apex = comp(uw, (int)(ncode & 3u));
                     if (!cghost && apex != GHOST) {
@@ -655,34 +680,31 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                     } else {
                         inside = tet_inside(a, u, P, pv.idx, st);
                     }
+                    // a lower attempt has u next to its cavity: it cannot be in this one
+                    conflict = inside && o1 < S;
                 }
-                const bool conflict = lower_cav || (inside && o1 < S);
                 if (__ballot(conflict) & gmask) {
                     status = ST_CONFLICT;
                     break;
                 }
-                // a tetrahedron reached through several facets in this step is added once:
-                // by the lowest such lane of the group
-                const unsigned long long min_ = __ballot(inside) & gmask;
-                bool first = inside;
-                for (unsigned long long mm = min_; mm; mm &= mm - 1ull) {
-                    const int m = __ffsll((long long)mm) - 1;
-                    const uint32_t um = __shfl(u, m);
-                    if ((uint32_t)m < lane && um == u) first = false;
-                }
-                const bool outside = need && !inside;
-                const unsigned long long mi = __ballot(first) & gmask;
+                // record u in the set; a tetrahedron reached through several facets in this
+                // step is queued (if inside) by the lane that records it
+                int ins = 0;
+                if (need) ins = mem_insert(mem, u, inside ? 0u : 1u);
+                const bool first_in = ins == 1 && inside;
+                const bool outside = (act && kind == 1) || (need && !inside);  // boundary facet (c, f)
+                const unsigned long long mi = __ballot(first_in) & gmask;
                 const unsigned long long mo = __ballot(outside) & gmask;
                 const uint32_t ni = (uint32_t)__popcll(mi), no = (uint32_t)__popcll(mo);
-                if (ncav + ni > min(capC, LCAPC) || nbnd + no > capF) {
+                if (ncav + ni > capL || nbnd + no > capF || (__ballot(ins < 0) & gmask)) {
                     status = ST_OVERFLOW;
                     break;
                 }
-                if (first) {
+                if (first_in) {
                     s_cav[gi][ncav + __popcll(mi & below)] = ncode;
-                    atomicMin(&a.T[u].any, S);
-                    atomicMin(&a.T[u].cav, S);
+                    atomicMin(&a.T[u].claim, S);
                 }
+
                 if (outside) {
                     // boundary facet: (local index of c) << 2 | f, and the outer tetrahedron
                     const uint32_t pos = nbnd + (uint32_t)__popcll(mo & below);
@@ -696,7 +718,7 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
             if (status == ST_NONE) status = ST_CAND;
         }
         if (status == ST_CAND)
-            for (uint32_t k = gl; k < ncav; k += GS) a.cav[(size_t)i * capC + k] = s_cav[gi][k];
+            for (uint32_t k = gl; k < ncav; k += GS) a.cav[(size_t)i * a.capC + k] = s_cav[gi][k];
         if (gl == 0) {
             a.status[i] = status;
             a.cnt[i] = ncav;
@@ -716,8 +738,9 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
 }
 
 // Winner test, slot reservation and DelaunayBall (Sec. 2.5), GL lanes per candidate, all in
-// one wave.  An attempt wins iff it still holds the lowest claim on every tetrahedron of its
-// cavity (any) and no lower attempt has one of its outer tetrahedra in its cavity (cav);
+// one wave.  An attempt wins iff no lower attempt touched a tetrahedron of its cavity (the
+// claim word still holds its stamp) and the lowest claim on each of its outer tetrahedra is
+// an outer claim (a lower attempt with that tetrahedron in its cavity then loses on it);
 // winners of one round therefore have disjoint cavities, and no cavity meets another
 // winner's outer tetrahedra, so winners build concurrently without further coordination
 // (claim words are only written by the cavity kernel, so the test of one candidate is not
@@ -776,8 +799,10 @@ __global__ __launch_bounds__(256) void k_ball(RoundArgs a) {
         nc = a.cnt[i];
         nb = a.cnt[stride + i];
         // winner test
-        for (uint32_t k = gl; k < nc; k += GL) ok &= a.T[cavl[k] >> 2].any == S;
-        for (uint32_t k = gl; k < nb; k += GL) ok &= a.T[ol[k] >> 2].cav > S;
+        // cavity tetrahedra: no lower claim; outer tetrahedra: the lowest claim is an outer
+        // one (any lower attempt with it in its cavity then loses on that claim)
+        for (uint32_t k = gl; k < nc; k += GL) ok &= a.T[cavl[k] >> 2].claim == S;
+        for (uint32_t k = gl; k < nb; k += GL) ok &= (a.T[ol[k] >> 2].claim & 1ull) != 0;
     }
     const bool win = cand && (__ballot(!ok) & gmask) == 0;
     // slot reservation by each winner's first lane, one atomic per block: the F - C extra
@@ -785,7 +810,7 @@ __global__ __launch_bounds__(256) void k_ball(RoundArgs a) {
     // the rest are fresh pool slots from tet_count on); C - F surplus cavity slots are freed
     const bool leader = win && gl == 0;
     const uint32_t need = leader && nb > nc ? nb - nc : 0u;
-    const uint32_t u0 = block_reserve(need, &a.ctr->fl_take);
+    const uint32_t u0 = block_reserve(need, &a.ctr->fl_take, &s_val[0][0][0]);
     const uint32_t fln = a.ctr->fl_n, tc0 = a.ctr->tet_count;
     const bool full = need && u0 + need > fln && tc0 + (u0 + need - fln) > a.tcap;
     if (full) {
@@ -836,7 +861,7 @@ __global__ __launch_bounds__(256) void k_ball(RoundArgs a) {
                 const int f = (int)(task & 3u);
                 const uint32_t code = comp(sn[k], f);
                 const uint32_t nt = code >> 2;
-                if (a.T[nt].any == S)
+                if (a.T[nt].claim == S)  // only this winner's cavity tetrahedra hold S
                     reinterpret_cast<uint32_t *>(&sn[k])[f] = ((uint32_t)a.T[nt].spare[0] << 2) | (code & 3u);
             }
             group_fence();

@@ -23,9 +23,9 @@ struct __align__(32) Vert {
 struct __align__(64) Tet {
     uint4 v;                    // vertex ids (ghost in slot 3); v.x = DEAD once freed
     uint4 n;                    // neighbour codes
-    unsigned long long any;     // lowest claim of any attempt touching the tetrahedron
-    unsigned long long cav;     // lowest claim of an attempt with it in its cavity
-    unsigned long long spare[2];
+    unsigned long long claim;   // lowest claim of the attempts touching it this round:
+                                // stamp S (in the attempt's cavity) or S + 1 (outside it)
+    unsigned long long spare[3];
 };
 
 // candidate status after a round
