@@ -20,7 +20,7 @@ sys.path.insert(0, ROOT)
 # their hash matches the one recorded there.
 KERNEL_SOURCES = ["paper_1805_08831_amd/csrc/dt_insert.hip", "paper_1805_08831_amd/csrc/dt_internal.h",
                   "paper_1805_08831_amd/csrc/dt_predicates.h"]
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_cavity16_uniform_1e7_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_cavity_g_uniform_1e7_pmc.md")
 
 
 def kernel_source_hash():
@@ -173,7 +173,7 @@ def main():
     bytes_per_launch = b_unit * agg["attempts"] / launches
     achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
     peak = 8000.0
-    roofline = {"bound": "hbm", "kernel": "k_cavity16", "achieved": round(achieved, 2), "peak": peak,
+    roofline = {"bound": "hbm", "kernel": "k_cavity_g<8>", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "GB/s", "frac": round(achieved / peak, 5), "traffic": measured_traffic(),
                 "bytes_per_attempt": round(b_unit, 1), "attempts_per_launch": round(agg["attempts"] / launches, 1),
                 "avg_launch_ms": round(avg_launch_ms, 4)}
