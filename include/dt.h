@@ -120,6 +120,24 @@ int dt_insert_points(dt_ctx *ctx, const double *xyz, uint64_t n);
    query T.  Host or device pointers. */
 int dt_get_tets(dt_ctx *ctx, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
 
+/* Triangulate num_clouds independent point clouds in one pass (the rounds of all clouds run
+   in the same kernel launches).  Cloud k is xyz[3*offsets[k] .. 3*offsets[k+1]) (fp64 AoS,
+   host or device memory); offsets (host memory, num_clouds + 1 entries, offsets[0] = 0,
+   at least 4 points per cloud) are not retained.  Each cloud gets the Delaunay
+   tetrahedralization of its own points (Algorithm 1), exactly as if it were inserted alone
+   into a fresh context.  The context must be empty (new or after dt_clear), and
+   dt_insert_points is refused until the next dt_clear.  Errors as dt_insert_points;
+   DT_E_DEGENERATE names the first degenerate cloud in dt_last_error.  Limits: fewer than 2^30
+   points in all, fewer than 2^30 tetrahedron slots in all. */
+int dt_insert_batch(dt_ctx *ctx, const double *xyz, const uint64_t *offsets, uint32_t num_clouds);
+
+/* Export the finite tetrahedra of one cloud of the context (cloud 0 after dt_insert_points),
+   with the same conventions as dt_get_tets but local to the cloud: vertex indices are
+   input indices within the cloud (0 .. its size - 1), and neighbour indices refer to this
+   call's output (-1 on the cloud's convex hull).  *num_tets is in/out as in dt_get_tets;
+   pass both buffers NULL to query the count.  Host or device pointers. */
+int dt_get_tets_batch(dt_ctx *ctx, uint32_t cloud, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
+
 /* Drop every point and tetrahedron but keep the device allocations. */
 int dt_clear(dt_ctx *ctx);
 

@@ -73,7 +73,6 @@ struct dt_ctx {
     uint64_t npoints = 0;  // points passed so far (global input indices)
     uint64_t nv = 0;       // vertex records in V
     bool have_mesh = false;
-    uint32_t init_v0 = 0;
     uint64_t round_counter = 0;  // monotonic over the context's lifetime
     uint64_t mesh_vertices = 0;
     int fl_idx = 0;
@@ -104,7 +103,6 @@ struct dt_ctx {
     DevBuf<double> staging;
     DevBuf<unsigned long long> keys, keys_tmp, table;
     DevBuf<uint32_t> vals, vals_tmp, hist, scan_tmp, small;
-    DevBuf<double> bbox;
     DevBuf<uint64_t> small64;
     // output scratch
     DevBuf<uint32_t> oflags, omap, otets;
@@ -115,6 +113,23 @@ struct dt_ctx {
     uint32_t trace_prev_won = 0;
     unsigned long long trace_prev_att = 0, trace_prev_walk = 0;
     const uint32_t *lord = nullptr;  // level-major order of the current call's vertex records
+    // clouds of the current call (one for dt_insert_points)
+    uint32_t nclouds = 0;
+    bool batch = false;                  // the context holds a dt_insert_batch result
+    DevBuf<Cloud> clouds;
+    DevBuf<uint64_t> off, ch_start, ch_end;
+    DevBuf<uint32_t> cloud_ch;
+    DevBuf<double> partial;
+    std::vector<uint64_t> h_off;         // input offsets of the clouds (nclouds + 1)
+    // per-cloud output index (batch): tetrahedra grouped by cloud
+    bool out_index = false;
+    DevBuf<unsigned long long> okeys;
+    DevBuf<uint32_t> osorted, omap2;
+    std::vector<uint64_t> h_toff;
+    const uint32_t *osorted_live = nullptr;
+    // scratch of dt_debug_sort (kept apart from the mesh's own buffers)
+    DevBuf<Vert> dbgV;
+    DevBuf<Cloud> dbg_cloud;
     bool trace = false;  // DT_TRACE=1 in the environment: one line per round on stderr
 };
 
@@ -311,6 +326,7 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.vlo = (uint32_t)base;
     a.vhi = (uint32_t)(base + n);
     a.anchor = c->anchor.p;
+    a.clouds = c->clouds.p;
     a.cand_pt = c->lpt[ci] + off;
     a.cand_rank = c->lrank[ci] + off;
     a.next_pt = c->lpt[ni];
@@ -509,48 +525,95 @@ void compute_levels(const std::vector<uint32_t> &hist, int L, Levels &lv) {
     lv.total_ranks = lv.rank_base[L];
 }
 
-// Moore keys + radix sort of the n points at dxyz: *svals receives, for each position of
-// the curve order, the point's index within the call (equal keys keep input order)
-int sort_points(dt_ctx *c, const double *dxyz, uint64_t n, int *m_out, std::vector<uint64_t> &cum,
-                uint32_t **svals, bool *bad_input) {
+// Clouds of one call: cloud k holds input points [off[k], off[k+1]) and vertex records
+// [base + off[k], base + off[k+1]).  Uploads the offsets and the chunk table of the box
+// reduction; writes the cloud table (all fields when fresh; otherwise only the record range
+// and Moore level, so that the cloud's live tetrahedron survives an append).
+int prepare_clouds(dt_ctx *c, const std::vector<uint64_t> &off, uint64_t base, bool fresh, int *mmax,
+                   uint32_t *nchunks, DevBuf<Cloud> &clouds) {
+    const uint32_t C = (uint32_t)(off.size() - 1);
+    constexpr uint64_t CHUNK = 65536;
+    std::vector<uint64_t> cs, ce;
+    std::vector<uint32_t> cch(C + 1, 0);
+    std::vector<Cloud> h(C);
+    *mmax = 1;
+    for (uint32_t k = 0; k < C; ++k) {
+        cch[k] = (uint32_t)cs.size();
+        for (uint64_t b = off[k]; b < off[k + 1]; b += CHUNK) {
+            cs.push_back(b);
+            ce.push_back(std::min(off[k + 1], b + CHUNK));
+        }
+        const uint64_t nk = off[k + 1] - off[k];
+        std::memset(&h[k], 0, sizeof(Cloud));
+        h[k].lo = (uint32_t)(base + off[k]);
+        h[k].hi = (uint32_t)(base + off[k + 1]);
+        h[k].m = (uint32_t)moore_level(nk);
+        *mmax = std::max(*mmax, (int)h[k].m);
+    }
+    cch[C] = (uint32_t)cs.size();
+    *nchunks = (uint32_t)cs.size();
+    int rc;
+    if ((rc = ensure(c, clouds, C)) || (rc = ensure(c, c->off, C + 1)) ||
+        (rc = ensure(c, c->ch_start, cs.size() + 1)) || (rc = ensure(c, c->ch_end, cs.size() + 1)) ||
+        (rc = ensure(c, c->cloud_ch, C + 1)) || (rc = ensure(c, c->partial, 6 * cs.size() + 6)))
+        return rc;
+    HIPCHK(hipMemcpyAsync(c->off.p, off.data(), (C + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ch_start.p, cs.data(), cs.size() * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ch_end.p, ce.data(), ce.size() * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->cloud_ch.p, cch.data(), (C + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+    if (fresh) {
+        HIPCHK(hipMemcpyAsync(clouds.p, h.data(), C * sizeof(Cloud), hipMemcpyHostToDevice, c->stream));
+    } else {
+        for (uint32_t k = 0; k < C; ++k) {
+            HIPCHK(hipMemcpyAsync(&clouds.p[k].lo, &h[k].lo, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(&clouds.p[k].m, &h[k].m, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+        }
+    }
+    // the host vectors are pageable: finish the copies before they go out of scope
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DT_OK;
+}
+
+// Validation, per-cloud boxes, (cloud, Moore) keys and their radix sort.  *svals receives,
+// for each position of the curve order, the point's index within the call; *skeys the
+// sorted keys (cloud << 3 mmax | Moore index).
+int sort_points(dt_ctx *c, const double *dxyz, uint64_t n, Cloud *clouds, const uint64_t *d_off, uint32_t C,
+                uint32_t nchunks, int mmax, uint32_t **svals, unsigned long long **skeys, bool *bad_input) {
     *bad_input = false;
-    const int m = moore_level(n);
-    cum = brio_cum(n);
-    const int L = (int)cum.size();
+    int cb = 0;
+    while ((1ull << cb) < C) ++cb;
     int rc;
     if ((rc = ensure(c, c->keys, n)) || (rc = ensure(c, c->keys_tmp, n)) || (rc = ensure(c, c->vals, n)) ||
         (rc = ensure(c, c->vals_tmp, n)) || (rc = ensure(c, c->hist, radix_hist_entries(n))) ||
         (rc = ensure(c, c->scan_tmp, scan_tmp_entries(radix_hist_entries(n)) + scan_tmp_entries(n) + 64)) ||
-        (rc = ensure(c, c->bbox, 6 * 1024 + 6)) || (rc = ensure(c, c->small64, 256)) ||
-        (rc = ensure(c, c->small, 256)))
+        (rc = ensure(c, c->small64, 256)) || (rc = ensure(c, c->small, 256)))
         return rc;
     HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
-    const int nblocks = (int)std::min<uint64_t>((n + 255) / 256, 1024);
-    HIPCHK(launch_validate_bbox(dxyz, n, c->bbox.p, nblocks, c->bbox.p + 6 * 1024, &c->ctr->error, c->stream));
+    HIPCHK(launch_cloud_bbox(dxyz, c->ch_start.p, c->ch_end.p, nchunks, c->partial.p, c->cloud_ch.p, C, clouds,
+                             &c->ctr->error, c->stream));
     int r = sync_ctr(c);
     if (r) return r;
     if (c->hctr->error & ERR_INPUT) {
         *bad_input = true;
         return DT_OK;
     }
-    HIPCHK(hipMemcpyAsync(c->small64.p, cum.data(), L * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(launch_keys(dxyz, n, c->bbox.p + 6 * 1024, m, 0, c->small64.p, 1, c->keys.p, c->vals.p, c->stream));
+    HIPCHK(launch_keys(dxyz, n, d_off, C, clouds, 3 * mmax, c->keys.p, c->vals.p, c->stream));
     bool swapped = false;
     HIPCHK(radix_sort_pairs(c->keys.p, c->vals.p, c->keys_tmp.p, c->vals_tmp.p, c->hist.p, c->scan_tmp.p, n,
-                            3 * m, c->stream, &swapped));
+                            cb + 3 * mmax, c->stream, &swapped));
     *svals = swapped ? c->vals_tmp.p : c->vals.p;
-    *m_out = m;
+    *skeys = swapped ? c->keys_tmp.p : c->keys.p;
     return DT_OK;
 }
 
-// BRIO level of every Moore-ordered position and the stable level-major order of the
-// positions (base + i) in *lord; the level sizes go to hist (asynchronously, pinned or
-// pageable host memory; the caller synchronizes).  svals is consumed.
-int level_order(dt_ctx *c, uint32_t *svals, uint64_t n, uint64_t base, int L, uint32_t **lord,
-                uint32_t *hist_host) {
+// BRIO level of every curve-ordered record within its cloud and the stable level-major order
+// of the records (base + i) in *lord; the level sizes go to hist_host (asynchronously; the
+// caller synchronizes).  svals and the key buffers are consumed.
+int level_order(dt_ctx *c, uint32_t *svals, const Vert *V, uint64_t n, uint64_t base, const uint64_t *d_off,
+                const Cloud *clouds, int L, uint32_t **lord, uint32_t *hist_host) {
     uint32_t *other = (svals == c->vals.p) ? c->vals_tmp.p : c->vals.p;
     const uint64_t salt = host_mix64(c->opt.seed ^ 0x5851F42D4C957F2Dull);
-    HIPCHK(launch_levels(svals, n, base, salt, c->small64.p, L, c->keys.p, other, c->stream));
+    HIPCHK(launch_levels(svals, V, n, base, d_off, clouds, salt, c->keys.p, other, c->stream));
     int lbits = 0;
     while ((1 << lbits) < L) ++lbits;
     bool swapped = false;
@@ -561,6 +624,105 @@ int level_order(dt_ctx *c, uint32_t *svals, uint64_t n, uint64_t base, int L, ui
     HIPCHK(launch_level_hist(c->keys.p, n, 0, c->small.p, c->stream));
     HIPCHK(hipMemcpyAsync(hist_host, c->small.p, 64 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     return DT_OK;
+}
+
+// Inserts the n points at xyz, split into clouds by off (C + 1 offsets, off[0] = 0).
+int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<uint64_t> &off) {
+    const uint32_t C = (uint32_t)(off.size() - 1);
+    auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    const double *dxyz = xyz;
+    if (!is_device_ptr(xyz)) {
+        if ((rc = ensure(c, c->staging, 3 * n))) return rc;
+        HIPCHK(hipMemcpyAsync(c->staging.p, xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        dxyz = c->staging.p;
+    }
+    const uint64_t base = c->nv;
+    const bool fresh = !c->have_mesh;
+    if ((rc = ensure(c, c->V, base + n, true)) || (rc = ensure(c, c->vtet, base + n, true)) ||
+        (rc = ensure(c, c->dup, base + n, true)) || (rc = ensure(c, c->anchor, n)))
+        return rc;
+    c->out_index = false;
+    // 1-2. clouds, validation, boxes, keys, sort
+    int mmax = 1;
+    uint32_t nchunks = 0;
+    if ((rc = prepare_clouds(c, off, base, fresh, &mmax, &nchunks, c->clouds))) return rc;
+    int cb = 0;
+    while ((1ull << cb) < C) ++cb;
+    if (cb + 3 * mmax > 64) return fail(c, DT_E_ARG, "too many clouds for the key width (%u clouds)", C);
+    uint32_t *svals = nullptr;
+    unsigned long long *skeys = nullptr;
+    bool bad = false;
+    if ((rc = sort_points(c, dxyz, n, c->clouds.p, c->off.p, C, nchunks, mmax, &svals, &skeys, &bad))) return rc;
+    if (bad) return fail(c, DT_E_INPUT, "a coordinate is not finite or outside 0 or [2^-120, 2^120) in magnitude");
+    // 3. vertex records in curve order (cloud id in the upper half of idx)
+    HIPCHK(launch_permute(dxyz, svals, skeys, 3 * mmax, n, base, c->npoints, c->V.p, c->vtet.p, c->dup.p, c->stream));
+    // 4. BRIO levels per cloud: level-major order of the records and level sizes
+    int L = 1;
+    for (uint32_t k = 0; k < C; ++k) L = std::max(L, (int)brio_cum(off[k + 1] - off[k]).size());
+    std::vector<uint32_t> hist(64);
+    uint32_t *lord = nullptr;
+    if ((rc = level_order(c, svals, c->V.p, n, base, c->off.p, c->clouds.p, L, &lord, hist.data()))) return rc;
+    // 5. duplicates (within each cloud)
+    uint64_t tsize = 1;
+    while (tsize < 2 * n) tsize <<= 1;
+    if ((rc = ensure(c, c->table, tsize))) return rc;
+    HIPCHK(hipMemsetAsync(&c->ctr->dups, 0, sizeof(uint32_t), c->stream));
+    HIPCHK(launch_dedupe(c->V.p, base, n, c->table.p, tsize, c->dup.p, &c->ctr->dups, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    Levels lv;
+    compute_levels(hist, L, lv);
+    // 6. initial tetrahedron of each cloud
+    if (fresh) {
+        if (c->tcap == 0 || c->tcap < 7 * n + 4096 + 5ull * C) {
+            uint64_t want = c->opt.capacity_tets ? c->opt.capacity_tets : (uint64_t)(6.9 * (double)n) + 65536 + 5ull * C;
+            if (c->tcap) {
+                hipFree(c->T); hipFree(c->fl[0]); hipFree(c->fl[1]);
+                c->tcap = 0;
+            }
+            if ((rc = grow_tets(c, std::max<uint64_t>(want, 4096)))) return rc;
+        }
+        HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
+        c->hctr->bad_cloud = NONE;
+        c->hctr->tet_count = 5 * C;
+        HIPCHK(hipMemcpyAsync(&c->ctr->bad_cloud, &c->hctr->bad_cloud, sizeof(uint32_t), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipMemcpyAsync(&c->ctr->tet_count, &c->hctr->tet_count, sizeof(uint32_t), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(launch_init(c->V.p, c->clouds.p, C, 0, c->dup.p, c->T, c->vtet.p, c->ctr, c->stream));
+        if ((rc = sync_ctr(c))) return rc;
+        if (c->hctr->error & ERR_DEGENERATE) {
+            if (C == 1) return fail(c, DT_E_DEGENERATE, "fewer than four affinely independent distinct points");
+            return fail(c, DT_E_DEGENERATE, "cloud %u has fewer than four affinely independent distinct points",
+                        c->hctr->bad_cloud);
+        }
+        c->mesh_vertices = 4ull * C;
+    }
+    // 7. level tables and walk anchors
+    uint32_t *d_start, *d_size, *d_bits;
+    unsigned long long *d_rb;
+    if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
+    HIPCHK(launch_anchor(lord, d_start, L, c->V.p, base, n, c->anchor.p, c->stream));
+    c->lord = lord;
+    if ((rc = sync_ctr(c))) return rc;
+    c->st.duplicates += c->hctr->dups;
+    auto t1 = std::chrono::steady_clock::now();
+    // 8. insertion rounds
+    c->have_mesh = true;
+    c->nclouds = C;
+    c->nv = base + n;
+    c->npoints += n;
+    c->st.points += n;
+    const uint64_t want_r = c->opt.round_size ? c->opt.round_size : DEFAULT_ROUND_MAX;
+    if ((rc = ensure_round_buffers(c, (uint32_t)std::min<uint64_t>(want_r, std::max<uint64_t>(n, ROUND_MIN)))))
+        return rc;
+    rc = run_rounds(c, lv, d_start, d_size, d_bits, d_rb, base, n);
+    auto t2 = std::chrono::steady_clock::now();
+    c->st.ms_sort += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    c->st.ms_insert += std::chrono::duration<double, std::milli>(t2 - t1).count();
+    c->st.ms_total += std::chrono::duration<double, std::milli>(t2 - t0).count();
+    return rc;
 }
 
 }  // namespace
@@ -632,84 +794,26 @@ int dt_insert_points(dt_ctx *c, const double *xyz, uint64_t n) {
     if (!c) return DT_E_ARG;
     if (n == 0) return DT_OK;
     if (!xyz) return fail(c, DT_E_ARG, "xyz is NULL");
+    if (c->batch) return fail(c, DT_E_ARG, "the context holds a batch of clouds: dt_clear it first");
     if (c->nv + n >= (1ull << 31) || c->npoints + n >= (1ull << 32) - 2 || n >= (1ull << 30))
         return fail(c, DT_E_CAPACITY, "too many points (limits: 2^30 per call, 2^31 in all)");
-    auto t0 = std::chrono::steady_clock::now();
-    HIPCHK(hipSetDevice(c->device));
-    int rc;
-    const double *dxyz = xyz;
-    if (!is_device_ptr(xyz)) {
-        if ((rc = ensure(c, c->staging, 3 * n))) return rc;
-        HIPCHK(hipMemcpyAsync(c->staging.p, xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        dxyz = c->staging.p;
-    }
-    const uint64_t base = c->nv;
-    if ((rc = ensure(c, c->V, base + n, true)) || (rc = ensure(c, c->vtet, base + n, true)) ||
-        (rc = ensure(c, c->dup, base + n, true)) || (rc = ensure(c, c->anchor, n)))
-        return rc;
-    // 1-2. validate, Moore keys, sort
-    int m = 1;
-    std::vector<uint64_t> cum;
-    uint32_t *svals = nullptr;
-    bool bad = false;
-    if ((rc = sort_points(c, dxyz, n, &m, cum, &svals, &bad))) return rc;
-    if (bad) return fail(c, DT_E_INPUT, "a coordinate is not finite or outside 0 or [2^-120, 2^120) in magnitude");
-    const int L = (int)cum.size();
-    // 3. vertex records in curve order
-    HIPCHK(launch_permute(dxyz, svals, n, base, c->npoints, c->V.p, c->vtet.p, c->dup.p, c->stream));
-    // 4. BRIO levels: level-major order of the records and level sizes
-    std::vector<uint32_t> hist(64);
-    uint32_t *lord = nullptr;
-    if ((rc = level_order(c, svals, n, base, L, &lord, hist.data()))) return rc;
-    // 5. duplicates
-    uint64_t tsize = 1;
-    while (tsize < 2 * n) tsize <<= 1;
-    if ((rc = ensure(c, c->table, tsize))) return rc;
-    HIPCHK(hipMemsetAsync(&c->ctr->dups, 0, sizeof(uint32_t), c->stream));
-    HIPCHK(launch_dedupe(c->V.p, base, n, c->table.p, tsize, c->dup.p, &c->ctr->dups, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    Levels lv;
-    compute_levels(hist, L, lv);
-    // 6. initial tetrahedron
-    if (!c->have_mesh) {
-        if (c->tcap == 0 || c->tcap < 7 * n + 4096) {
-            uint64_t want = c->opt.capacity_tets ? c->opt.capacity_tets : (uint64_t)(6.9 * (double)n) + 65536;
-            if (c->tcap) {
-                hipFree(c->T); hipFree(c->fl[0]); hipFree(c->fl[1]);
-                c->tcap = 0;
-            }
-            if ((rc = grow_tets(c, std::max<uint64_t>(want, 4096)))) return rc;
-        }
-        HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
-        HIPCHK(launch_init(c->V.p, (uint32_t)base, (uint32_t)n, c->dup.p, c->T, c->vtet.p, c->ctr, c->stream));
-        if ((rc = sync_ctr(c))) return rc;
-        if (c->hctr->error & ERR_DEGENERATE)
-            return fail(c, DT_E_DEGENERATE, "fewer than four affinely independent distinct points");
-        c->init_v0 = c->hctr->init[0];
-        c->mesh_vertices = 4;
-    }
-    // 7. level tables
-    uint32_t *d_start, *d_size, *d_bits;
-    unsigned long long *d_rb;
-    if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
-    HIPCHK(launch_anchor(lord, d_start, L, base, n, c->anchor.p, c->stream));
-    c->lord = lord;
-    if ((rc = sync_ctr(c))) return rc;
-    c->st.duplicates += c->hctr->dups;
-    auto t1 = std::chrono::steady_clock::now();
-    // 8. insertion rounds
-    c->have_mesh = true;
-    c->nv = base + n;
-    c->npoints += n;
-    c->st.points += n;
-    const uint64_t want_r = c->opt.round_size ? c->opt.round_size : DEFAULT_ROUND_MAX;
-    if ((rc = ensure_round_buffers(c, (uint32_t)std::min<uint64_t>(want_r, std::max<uint64_t>(n, ROUND_MIN)))))
-        return rc;
-    rc = run_rounds(c, lv, d_start, d_size, d_bits, d_rb, base, n);
-    auto t2 = std::chrono::steady_clock::now();
-    c->st.ms_sort += std::chrono::duration<double, std::milli>(t1 - t0).count();
-    c->st.ms_insert += std::chrono::duration<double, std::milli>(t2 - t1).count();
-    c->st.ms_total += std::chrono::duration<double, std::milli>(t2 - t0).count();
+    c->h_off = {0, n};
+    return insert_clouds(c, xyz, n, c->h_off);
+}
+
+int dt_insert_batch(dt_ctx *c, const double *xyz, const uint64_t *offsets, uint32_t num_clouds) {
+    if (!c) return DT_E_ARG;
+    if (!xyz || !offsets || num_clouds == 0) return fail(c, DT_E_ARG, "xyz or offsets is NULL, or no clouds");
+    if (c->have_mesh || c->nv) return fail(c, DT_E_ARG, "dt_insert_batch needs an empty context (dt_clear it)");
+    std::vector<uint64_t> off(offsets, offsets + num_clouds + 1);
+    if (off[0] != 0) return fail(c, DT_E_ARG, "offsets[0] must be 0");
+    for (uint32_t k = 0; k < num_clouds; ++k)
+        if (off[k + 1] < off[k] + 4) return fail(c, DT_E_ARG, "cloud %u has fewer than 4 points", k);
+    const uint64_t n = off[num_clouds];
+    if (n >= (1ull << 30)) return fail(c, DT_E_CAPACITY, "too many points (limit 2^30 per call)");
+    c->h_off = off;
+    int rc = insert_clouds(c, xyz, n, c->h_off);
+    c->batch = true;
     return rc;
 }
 
@@ -760,6 +864,79 @@ int dt_get_tets(dt_ctx *c, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets) {
     return DT_OK;
 }
 
+// Groups the live finite tetrahedra by cloud (cached until the mesh changes).
+static int build_cloud_index(dt_ctx *c) {
+    if (c->out_index) return DT_OK;
+    const uint32_t count = c->hctr->tet_count, C = c->nclouds;
+    int rc;
+    if ((rc = ensure(c, c->okeys, 2 * (size_t)count + 2)) || (rc = ensure(c, c->osorted, 2 * (size_t)count + 2)) ||
+        (rc = ensure(c, c->omap2, (size_t)count + 1)) || (rc = ensure(c, c->hist, radix_hist_entries(count))) ||
+        (rc = ensure(c, c->scan_tmp, scan_tmp_entries(radix_hist_entries(count)) + scan_tmp_entries(count) + 64)) ||
+        (rc = ensure(c, c->cloud_ch, (size_t)C + 1)))
+        return rc;
+    unsigned long long *k0 = c->okeys.p, *k1 = c->okeys.p + count + 1;
+    uint32_t *v0 = c->osorted.p, *v1 = c->osorted.p + count + 1;
+    HIPCHK(launch_tet_cloud(c->T, c->V.p, count, C, k0, v0, c->stream));
+    int bits = 0;
+    while ((1ull << bits) <= C) ++bits;
+    bool swapped = false;
+    HIPCHK(radix_sort_pairs(k0, v0, k1, v1, c->hist.p, c->scan_tmp.p, count, bits, c->stream, &swapped));
+    unsigned long long *sk = swapped ? k1 : k0;
+    uint32_t *sv = swapped ? v1 : v0;
+    // toff[C] = first non-finite position (count when every slot is a finite tetrahedron)
+    std::vector<uint32_t> toff(C + 1, 0);
+    toff[C] = count;
+    HIPCHK(hipMemcpyAsync(c->cloud_ch.p, toff.data(), (C + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(launch_seg_bounds(sk, count, C, c->cloud_ch.p, c->stream));
+    HIPCHK(hipMemcpyAsync(toff.data(), c->cloud_ch.p, (C + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(launch_tet_map(sv, toff[C], c->omap2.p, c->stream));
+    c->h_toff.assign(toff.begin(), toff.end());
+    c->osorted_live = sv;
+    c->out_index = true;
+    return DT_OK;
+}
+
+int dt_get_tets_batch(dt_ctx *c, uint32_t cloud, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets) {
+    if (!c || !num_tets) return DT_E_ARG;
+    if (!c->have_mesh || cloud >= c->nclouds)
+        return fail(c, DT_E_ARG, "no cloud %u in this context (%u clouds)", cloud, c->nclouds);
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    if ((rc = build_cloud_index(c))) return rc;
+    const uint32_t tb = (uint32_t)c->h_toff[cloud], te = (uint32_t)c->h_toff[cloud + 1];
+    const uint64_t T = te - tb;
+    if (!tets && !nbrs) {
+        *num_tets = T;
+        return DT_OK;
+    }
+    if (*num_tets < T) {
+        *num_tets = T;
+        return fail(c, DT_E_ARG, "output buffers hold %llu tetrahedra, %llu needed", (unsigned long long)*num_tets,
+                    (unsigned long long)T);
+    }
+    *num_tets = T;
+    const bool dev_t = tets && is_device_ptr(tets), dev_n = nbrs && is_device_ptr(nbrs);
+    uint32_t *ot = tets;
+    int64_t *on = nbrs;
+    if (tets && !dev_t) {
+        if ((rc = ensure(c, c->otets, 4 * (size_t)T + 4))) return rc;
+        ot = c->otets.p;
+    }
+    if (nbrs && !dev_n) {
+        if ((rc = ensure(c, c->onbrs, 4 * (size_t)T + 4))) return rc;
+        on = c->onbrs.p;
+    }
+    HIPCHK(launch_output_cloud(c->T, c->V.p, c->osorted_live, c->omap2.p, tb, te, c->h_off[cloud], ot, on,
+                               c->stream));
+    if (tets && !dev_t)
+        HIPCHK(hipMemcpyAsync(tets, ot, 4 * T * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    if (nbrs && !dev_n)
+        HIPCHK(hipMemcpyAsync(nbrs, on, 4 * T * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DT_OK;
+}
+
 int dt_clear(dt_ctx *c) {
     if (!c) return DT_E_ARG;
     HIPCHK(hipSetDevice(c->device));
@@ -772,6 +949,9 @@ int dt_clear(dt_ctx *c) {
     c->mesh_vertices = 0;
     c->fl_idx = c->list_idx = c->ovf_idx = 0;
     c->st = dt_stats{};
+    c->batch = false;
+    c->nclouds = 0;
+    c->out_index = false;
     return DT_OK;
 }
 
@@ -789,7 +969,9 @@ int dt_destroy(dt_ctx *c) {
     f(c->stat);
     if (c->hctr) hipHostFree(c->hctr);
     f(c->staging.p); f(c->keys.p); f(c->keys_tmp.p); f(c->table.p); f(c->vals.p); f(c->vals_tmp.p);
-    f(c->hist.p); f(c->scan_tmp.p); f(c->small.p); f(c->bbox.p); f(c->small64.p);
+    f(c->hist.p); f(c->scan_tmp.p); f(c->small.p); f(c->small64.p);
+    f(c->clouds.p); f(c->off.p); f(c->ch_start.p); f(c->ch_end.p); f(c->cloud_ch.p); f(c->partial.p);
+    f(c->okeys.p); f(c->osorted.p); f(c->omap2.p); f(c->dbgV.p); f(c->dbg_cloud.p);
     f(c->oflags.p); f(c->omap.p); f(c->otets.p); f(c->onbrs.p);
     for (int k = 0; k < 3; ++k)
         if (c->ev[k]) hipEventDestroy(c->ev[k]);
@@ -825,6 +1007,7 @@ const char *dt_last_error(const dt_ctx *c) { return c ? c->err.c_str() : "no con
 
 int dt_debug_sort(dt_ctx *c, const double *xyz, uint64_t n, uint64_t *keys, uint32_t *perm, int *moore_m) {
     if (!c || !xyz || n == 0) return DT_E_ARG;
+    if (n >= (1ull << 30)) return fail(c, DT_E_CAPACITY, "too many points");
     HIPCHK(hipSetDevice(c->device));
     int rc;
     const double *dxyz = xyz;
@@ -833,33 +1016,45 @@ int dt_debug_sort(dt_ctx *c, const double *xyz, uint64_t n, uint64_t *keys, uint
         HIPCHK(hipMemcpyAsync(c->staging.p, xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
         dxyz = c->staging.p;
     }
-    int m = 1;
-    std::vector<uint64_t> cum;
+    // the same steps as dt_insert_points for one cloud, on scratch records: curve order, then
+    // the level-major order of it
+    const std::vector<uint64_t> off = {0, n};
+    int mmax = 1;
+    uint32_t nchunks = 0;
+    if ((rc = prepare_clouds(c, off, 0, true, &mmax, &nchunks, c->dbg_cloud))) return rc;
+    if ((rc = ensure(c, c->dbgV, n))) return rc;
     uint32_t *sv = nullptr;
+    unsigned long long *sk = nullptr;
     bool bad = false;
-    // the same two sorts as dt_insert_points: Moore order, then level-major order of it
-    if ((rc = sort_points(c, dxyz, n, &m, cum, &sv, &bad))) return rc;
+    if ((rc = sort_points(c, dxyz, n, c->dbg_cloud.p, c->off.p, 1, nchunks, mmax, &sv, &sk, &bad))) return rc;
     if (bad) return fail(c, DT_E_INPUT, "a coordinate is not finite or outside the accepted range");
     std::vector<uint32_t> moore_order(n), lord_h(n), hist(64);
     HIPCHK(hipMemcpyAsync(moore_order.data(), sv, n * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(launch_permute(dxyz, sv, sk, 3 * mmax, n, 0, 0, c->dbgV.p, nullptr, nullptr, c->stream));
+    const int L = (int)brio_cum(n).size();
     uint32_t *lord = nullptr;
-    if ((rc = level_order(c, sv, n, 0, (int)cum.size(), &lord, hist.data()))) return rc;
+    if ((rc = level_order(c, sv, c->dbgV.p, n, 0, c->off.p, c->dbg_cloud.p, L, &lord, hist.data()))) return rc;
     HIPCHK(hipMemcpyAsync(lord_h.data(), lord, n * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-    if (keys) {
-        // keys in input order: level << 3m | Moore index
-        const uint64_t salt = host_mix64(c->opt.seed ^ 0x5851F42D4C957F2Dull);
-        HIPCHK(launch_keys(dxyz, n, c->bbox.p + 6 * 1024, m, salt, c->small64.p, (int)cum.size(), c->keys_tmp.p,
-                           c->vals_tmp.p, c->stream));
-        HIPCHK(hipMemcpyAsync(keys, c->keys_tmp.p, n * sizeof(uint64_t), hipMemcpyDefault, c->stream));
-    }
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (keys) {
+        // keys in input order: level << 3m | Moore index (the level of the record at
+        // level-major position j is the level whose range holds j)
+        HIPCHK(launch_keys(dxyz, n, c->off.p, 1, c->dbg_cloud.p, 3 * mmax, c->keys_tmp.p, c->vals_tmp.p, c->stream));
+        std::vector<uint64_t> kh(n);
+        HIPCHK(hipMemcpyAsync(kh.data(), c->keys_tmp.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        uint64_t j = 0;
+        for (int k = 0; k < L; ++k)
+            for (uint32_t q = 0; q < hist[k]; ++q, ++j)
+                kh[moore_order[lord_h[j]]] |= (uint64_t)k << (3 * mmax);
+        HIPCHK(hipMemcpy(keys, kh.data(), n * sizeof(uint64_t), hipMemcpyDefault));
+    }
     if (perm) {
         std::vector<uint32_t> ph(n);
-        for (uint64_t j = 0; j < n; ++j) ph[j] = moore_order[lord_h[j]];
+        for (uint64_t q = 0; q < n; ++q) ph[q] = moore_order[lord_h[q]];
         HIPCHK(hipMemcpy(perm, ph.data(), n * sizeof(uint32_t), hipMemcpyDefault));
     }
-    if (moore_m) *moore_m = m;
+    if (moore_m) *moore_m = mmax;
     return DT_OK;
 }
 

@@ -121,12 +121,18 @@ __device__ __forceinline__ int orient_new_tet(uint32_t w[4], int j) {
 
 // ------------------------------------------------------------------ initial tetrahedron
 
-__global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, const uint8_t *__restrict__ dup,
-                       Tet *__restrict__ T, uint32_t *__restrict__ vtet,
+// One block per cloud: the first four affinely independent distinct points of the cloud's
+// records (any choice gives the same triangulation), positively oriented, plus the four
+// ghosts (each holds G in slot 3, its finite facet facing outward), at slots
+// first_slot + 5 c .. + 4.
+__global__ void k_init(const Vert *__restrict__ V, Cloud *__restrict__ clouds, uint32_t first_slot,
+                       const uint8_t *__restrict__ dup, Tet *__restrict__ T, uint32_t *__restrict__ vtet,
                        Ctr *__restrict__ ctr) {
     __shared__ uint32_t sel[4];
     __shared__ uint32_t best;
     PredStats st;
+    const uint32_t c = blockIdx.x;
+    const uint32_t base = clouds[c].lo, n = clouds[c].hi - clouds[c].lo;
     for (int stage = 0; stage < 4; ++stage) {
         if (threadIdx.x == 0) best = NONE;
         __syncthreads();
@@ -143,7 +149,10 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
             __syncthreads();
         }
         if (best == NONE) {
-            if (threadIdx.x == 0) atomicOr(&ctr->error, ERR_DEGENERATE);
+            if (threadIdx.x == 0) {
+                atomicOr(&ctr->error, ERR_DEGENERATE);
+                atomicMin(&ctr->bad_cloud, c);
+            }
             return;
         }
         if (threadIdx.x == 0) sel[stage] = base + best;
@@ -154,6 +163,7 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
     if (orient3d(vpos(V, v[0]), vpos(V, v[1]), vpos(V, v[2]), vpos(V, v[3]), st) < 0) {
         uint32_t t = v[0]; v[0] = v[1]; v[1] = t;
     }
+    const uint32_t s0 = first_slot + 5 * c;
     uint32_t TV[5][4], N[5][4];
     for (int k = 0; k < 4; ++k) TV[0][k] = v[k];
     for (int j = 0; j < 4; ++j) {
@@ -161,8 +171,8 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
         w[j] = GHOST;
         orient_new_tet(w, j);  // G ends in slot 3: finite facet (w0,w1,w2) faces outward
         for (int k = 0; k < 4; ++k) TV[1 + j][k] = w[k];
-        N[0][j] = ((1u + j) << 2) | 3u;
-        N[1 + j][3] = (0u << 2) | (uint32_t)j;
+        N[0][j] = ((s0 + 1u + j) << 2) | 3u;
+        N[1 + j][3] = (s0 << 2) | (uint32_t)j;
     }
     // ghost-ghost adjacencies: facets through G with the same three vertices
     for (int g1 = 1; g1 < 5; ++g1)
@@ -176,7 +186,7 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
                         for (int k = 0; k < 4; ++k)
                             if (k != f2 && TV[g2][k] == TV[g1][i]) same++;
                     }
-                    if (same == 3) N[g1][f1] = ((uint32_t)g2 << 2) | (uint32_t)f2;
+                    if (same == 3) N[g1][f1] = ((s0 + (uint32_t)g2) << 2) | (uint32_t)f2;
                 }
             }
     for (int t = 0; t < 5; ++t) {
@@ -185,19 +195,16 @@ __global__ void k_init(const Vert *__restrict__ V, uint32_t base, uint32_t n, co
         r.n = make_uint4(N[t][0], N[t][1], N[t][2], N[t][3]);
         r.claim = ~0ull;
         r.spare[0] = r.spare[1] = r.spare[2] = 0;
-        T[t] = r;
+        T[s0 + t] = r;
     }
-    for (int k = 0; k < 4; ++k) {
-        vtet[v[k]] = 0;
-        ctr->init[k] = v[k];
-    }
-    ctr->tet_count = 5;
-    ctr->any_live = 0;
+    for (int k = 0; k < 4; ++k) vtet[v[k]] = s0;
+    clouds[c].any_live = s0;
 }
 
-hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, Tet *T, uint32_t *vtet,
-                       Ctr *ctr, hipStream_t s) {
-    k_init<<<1, 256, 0, s>>>(V, base, n, dup, T, vtet, ctr);
+hipError_t launch_init(const Vert *V, Cloud *clouds, uint32_t nclouds, uint32_t first_slot, const uint8_t *dup,
+                       Tet *T, uint32_t *vtet, Ctr *ctr, hipStream_t s) {
+    if (nclouds == 0) return hipSuccess;
+    k_init<<<nclouds, 256, 0, s>>>(V, clouds, first_slot, dup, T, vtet, ctr);
     return hipGetLastError();
 }
 
@@ -286,21 +293,23 @@ __global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
         const Vert pv = a.V[p];
         const P3 P = {pv.x, pv.y, pv.z};
         // start: a live tetrahedron near the nearest inserted point among the HINT_RANGE
-        // records on either side on the curve, else near the point's anchor (a record of
-        // a lower level), else any live tetrahedron
+        // records on either side on the curve (in the point's cloud), else near the point's
+        // anchor (a record of a lower level), else the cloud's known live tetrahedron
+        Cloud *cl = &a.clouds[pv.idx >> 32];
+        const uint32_t clo = cl->lo, chi = cl->hi;
         uint32_t t = NONE;
         for (int d = 1; d <= HINT_RANGE && t == NONE; ++d) {
-            if (p >= a.vlo + d) t = a.vtet[p - d];
-            if (t == NONE && p + d < a.vhi) t = a.vtet[p + d];
+            if (p >= clo + d) t = a.vtet[p - d];
+            if (t == NONE && p + d < chi) t = a.vtet[p + d];
         }
         if (t == NONE) {
             const uint32_t q = a.anchor[p - a.vlo];
             if (q != NONE) t = a.vtet[q];
         }
-        if (t == NONE) t = a.ctr->any_live;
+        if (t == NONE) t = cl->any_live;
         uint4 w = a.T[t].v;
         if (w.x == DEAD) {
-            t = a.ctr->any_live;
+            t = cl->any_live;
             w = a.T[t].v;
         }
         if (w.w == GHOST) {
@@ -545,18 +554,22 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
         const Vert pv = a.V[p];
         const P3 P = {pv.x, pv.y, pv.z};
         // start: near the nearest inserted point among GS / 2 records on either side of p on
-        // the curve, one probe per lane; else near the point's anchor (a record of a lower
-        // level); else any live tetrahedron
+        // the curve (in p's cloud), one probe per lane; else near the point's anchor (a
+        // record of a lower level); else the cloud's known live tetrahedron
         const uint32_t d = (gl >> 1) + 1;
+        const uint32_t hp = (gl & 1) ? p + d : p - d;
         const bool inr = (gl & 1) ? (p + d < a.vhi) : (p >= a.vlo + d);
-        const uint32_t ht = inr ? a.vtet[(gl & 1) ? p + d : p - d] : NONE;
+        uint32_t ht = inr ? a.vtet[hp] : NONE;
         const uint32_t q = a.anchor[p - a.vlo];
+        Cloud *cl = &a.clouds[pv.idx >> 32];
+        const uint32_t clo = cl->lo, chi = cl->hi;
+        if (hp < clo || hp >= chi) ht = NONE;
         const unsigned long long hm = __ballot(ht != NONE) & gmask;
         uint32_t t = hm ? __shfl(ht, __ffsll((long long)hm) - 1) : (q != NONE ? a.vtet[q] : NONE);
-        if (t == NONE) t = a.ctr->any_live;
+        if (t == NONE) t = cl->any_live;
         uint4 w = a.T[t].v;
         if (w.x == DEAD) {
-            t = a.ctr->any_live;
+            t = cl->any_live;
             w = a.T[t].v;
         }
         if (w.w == GHOST) {
@@ -889,7 +902,7 @@ __global__ __launch_bounds__(256) void k_ball(RoundArgs a) {
             ol[b] = me;
             for (int q = 0; q < 4; ++q)
                 if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
-            if (b == 0) a.ctr->any_live = slot;
+            if (b == 0) a.clouds[a.V[p].idx >> 32].any_live = slot;
             if (table) {
                 // the three facets through p: facet q holds p and the edge of the boundary
                 // facet without vertex q
@@ -1109,6 +1122,79 @@ __global__ void k_out_flags(const Tet *__restrict__ T, uint32_t count, uint32_t 
     if (t >= count) return;
     const uint4 w = T[t].v;
     flags[t] = (w.x != DEAD && w.w != GHOST) ? 1u : 0u;
+}
+
+// Per-cloud output.  The live finite tetrahedra are sorted by the cloud of their vertices
+// (keys: cloud, or nclouds for ghosts and free slots); cloud c owns sorted positions
+// [toff[c], toff[c + 1]); map[t] is the sorted position of tetrahedron t.
+__global__ void k_tet_cloud(const Tet *__restrict__ T, const Vert *__restrict__ V, uint32_t count, uint32_t nclouds,
+                            unsigned long long *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const uint4 w = T[t].v;
+    keys[t] = (w.x != DEAD && w.w != GHOST) ? (V[w.x].idx >> 32) : (unsigned long long)nclouds;
+    vals[t] = t;
+}
+
+__global__ void k_seg_bounds(const unsigned long long *__restrict__ keys, uint32_t count, uint32_t nclouds,
+                             uint32_t *__restrict__ toff) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const unsigned long long k = keys[j];
+    if (j == 0 || keys[j - 1] != k) toff[k < nclouds ? k : nclouds] = j;
+}
+
+__global__ void k_tet_map(const uint32_t *__restrict__ sorted, uint32_t nlive, uint32_t *__restrict__ map) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nlive) map[sorted[j]] = j;
+}
+
+__global__ void k_output_cloud(const Tet *__restrict__ T, const Vert *__restrict__ V, const uint32_t *__restrict__ sorted,
+                               const uint32_t *__restrict__ map, uint32_t tb, uint32_t te, uint64_t vbase,
+                               uint32_t *__restrict__ tets, int64_t *__restrict__ nbrs) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= te - tb) return;
+    const uint32_t t = sorted[tb + j];
+    const uint4 w = T[t].v;
+    if (tets) {
+        const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+        for (int k = 0; k < 4; ++k) tets[4 * (size_t)j + k] = (uint32_t)((uint32_t)V[wv[k]].idx - vbase);
+    }
+    if (nbrs) {
+        const uint4 nn = T[t].n;
+        const uint32_t nv[4] = {nn.x, nn.y, nn.z, nn.w};
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t nt = nv[k] >> 2;
+            nbrs[4 * (size_t)j + k] = T[nt].v.w == GHOST ? -1 : (int64_t)map[nt] - (int64_t)tb;
+        }
+    }
+}
+
+hipError_t launch_tet_cloud(const Tet *T, const Vert *V, uint32_t count, uint32_t nclouds, unsigned long long *keys,
+                            uint32_t *vals, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    k_tet_cloud<<<(count + 255) / 256, 256, 0, s>>>(T, V, count, nclouds, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_bounds(const unsigned long long *keys, uint32_t count, uint32_t nclouds, uint32_t *toff,
+                             hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    k_seg_bounds<<<(count + 255) / 256, 256, 0, s>>>(keys, count, nclouds, toff);
+    return hipGetLastError();
+}
+
+hipError_t launch_tet_map(const uint32_t *sorted, uint32_t nlive, uint32_t *map, hipStream_t s) {
+    if (nlive == 0) return hipSuccess;
+    k_tet_map<<<(nlive + 255) / 256, 256, 0, s>>>(sorted, nlive, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_output_cloud(const Tet *T, const Vert *V, const uint32_t *sorted, const uint32_t *map, uint32_t tb,
+                               uint32_t te, uint64_t vbase, uint32_t *tets, int64_t *nbrs, hipStream_t s) {
+    if (te <= tb) return hipSuccess;
+    k_output_cloud<<<(te - tb + 255) / 256, 256, 0, s>>>(T, V, sorted, map, tb, te, vbase, tets, nbrs);
+    return hipGetLastError();
 }
 
 hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s) {

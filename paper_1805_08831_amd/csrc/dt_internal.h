@@ -72,7 +72,7 @@ struct Ctr {
     uint32_t dups;       // duplicates found this round
     uint32_t error;      // ERR_* flags
     uint32_t init[4];    // sorted positions of the initial tetrahedron's vertices
-    uint32_t unused0;
+    uint32_t bad_cloud;  // first cloud found degenerate by the initial-tetrahedron search
     uint32_t any_live;   // some live tetrahedron (walk start of last resort)
     uint32_t chunk;      // length of a list slice processed as one round
     unsigned long long walk_steps, cav_tets, bnd_facets;
@@ -80,13 +80,25 @@ struct Ctr {
     unsigned long long attempts;
 };
 
+// One independent point cloud of a call (a single-cloud call is a batch of one).  Its vertex
+// records are [lo, hi) in curve order; the cloud id is stored in the upper 32 bits of each
+// record's idx.
+struct Cloud {
+    uint32_t lo, hi;     // vertex records of this call belonging to the cloud
+    uint32_t any_live;   // a live tetrahedron of the cloud's mesh (walk start of last resort)
+    uint32_t m;          // Moore level of the cloud's cubic grid
+    double box[4];       // grid origin (x, y, z) and scale 2^m / largest extent
+};
+
 // Arguments of one insertion round.
 struct RoundArgs {
     const Vert *V;
     Tet *T;                      // tetrahedron pool
     uint32_t *vtet;              // vertex -> a live tetrahedron containing it
-    uint32_t vlo, vhi;           // vertex records of the current call (Moore order)
-    const uint32_t *anchor;      // [vhi - vlo] walk anchor of each record (a lower-level record)
+    uint32_t vlo, vhi;           // vertex records of the current call
+    const uint32_t *anchor;      // walk anchor of each record of the call (a lower-level record
+                                 // of the same cloud), indexed by record - vlo
+    Cloud *clouds;               // the call's clouds (walk bounds, live tetrahedron)
     const uint32_t *cand_pt;     // current candidate list
     const uint32_t *cand_rank;
     uint32_t *next_pt;           // losers for the next round
@@ -120,32 +132,53 @@ struct FillPlan {
 };
 
 // ---- launch wrappers (dt_sort.hip) ----
-hipError_t launch_validate_bbox(const double *xyz, uint64_t n, double *bbox_blocks, int nblocks,
-                                double *bbox_out, uint32_t *err, hipStream_t s);
-hipError_t launch_keys(const double *xyz, uint64_t n, const double *bbox, int m, uint64_t salt,
-                       const uint64_t *cum, int L, unsigned long long *keys, uint32_t *vals,
-                       hipStream_t s);
+// Validation and per-cloud bounding boxes: chunk j covers input points [ch_start[j],
+// ch_end[j]) of cloud ch_cloud[j]; cloud c owns chunks [cloud_ch[c], cloud_ch[c + 1]).
+hipError_t launch_cloud_bbox(const double *xyz, const uint64_t *ch_start, const uint64_t *ch_end,
+                             uint32_t nchunks, double *partial, const uint32_t *cloud_ch, uint32_t nclouds,
+                             Cloud *clouds, uint32_t *err, hipStream_t s);
+// keys[i] = cloud << shift | Moore index of point i in its cloud's grid; vals[i] = i
+hipError_t launch_keys(const double *xyz, uint64_t n, const uint64_t *off, uint32_t nclouds, const Cloud *clouds,
+                       int shift, unsigned long long *keys, uint32_t *vals, hipStream_t s);
 hipError_t radix_sort_pairs(unsigned long long *keys, uint32_t *vals, unsigned long long *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *hist, uint32_t *scan_tmp, uint64_t n,
                             int nbits, hipStream_t s, bool *swapped);
 size_t radix_hist_entries(uint64_t n);
-hipError_t launch_permute(const double *xyz, const uint32_t *vals, uint64_t n, uint64_t base,
-                          uint64_t idx_offset, Vert *V, uint32_t *vtet, uint8_t *dup, hipStream_t s);
+hipError_t launch_permute(const double *xyz, const uint32_t *vals, const unsigned long long *skeys, int shift,
+                          uint64_t n, uint64_t base, uint64_t idx_offset, Vert *V, uint32_t *vtet, uint8_t *dup,
+                          hipStream_t s);
 hipError_t launch_level_hist(const unsigned long long *keys, uint64_t n, int shift, uint32_t *hist,
                              hipStream_t s);
-hipError_t launch_levels(const uint32_t *src, uint64_t n, uint64_t base, uint64_t salt, const uint64_t *cum,
-                         int L, unsigned long long *keys, uint32_t *vals, hipStream_t s);
-hipError_t launch_anchor(const uint32_t *lord, const uint32_t *start, int L, uint64_t base, uint64_t n,
-                         uint32_t *anchor, hipStream_t s);
+hipError_t launch_levels(const uint32_t *src, const Vert *V, uint64_t n, uint64_t base, const uint64_t *off,
+                         const Cloud *clouds, uint64_t salt, unsigned long long *keys, uint32_t *vals,
+                         hipStream_t s);
+hipError_t launch_anchor(const uint32_t *lord, const uint32_t *start, int L, const Vert *V, uint64_t base,
+                         uint64_t n, uint32_t *anchor, hipStream_t s);
 hipError_t launch_dedupe(const Vert *V, uint64_t base, uint64_t n, unsigned long long *table,
                          uint64_t tsize, uint8_t *dup, uint32_t *ndup, hipStream_t s);
 hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tmp,
                               uint32_t *total, hipStream_t s);
 size_t scan_tmp_entries(uint64_t n);
+// the level of point i (local index li in a cloud of n points): first k with u n < cum_k 2^53
+__device__ __forceinline__ int brio_level(unsigned long long u, unsigned long long n) {
+    unsigned long long size = 2048;
+    int lev = 0;
+    for (;;) {
+        const unsigned long long cum = size < n ? size : n;
+        if (cum >= n) return lev;
+        // u * n < cum * 2^53, in 128 bits
+        const unsigned long long lo = u * n, hi = __umul64hi(u, n);
+        const unsigned long long clo = cum << 53, chi = cum >> 11;
+        if (hi < chi || (hi == chi && lo < clo)) return lev;
+        ++lev;
+        size *= 7;
+    }
+}
 
 // ---- launch wrappers (dt_insert.hip) ----
-hipError_t launch_init(const Vert *V, uint32_t base, uint32_t n, const uint8_t *dup, Tet *T, uint32_t *vtet,
-                       Ctr *ctr, hipStream_t s);
+// initial tetrahedron and four ghosts of each cloud c at slots 5 c0 + 5 c .. + 4 (c0: first)
+hipError_t launch_init(const Vert *V, Cloud *clouds, uint32_t nclouds, uint32_t first_slot, const uint8_t *dup,
+                       Tet *T, uint32_t *vtet, Ctr *ctr, hipStream_t s);
 hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, const uint32_t *lvl_size,
                             const uint32_t *lvl_bits, const unsigned long long *rank_base, const uint32_t *lord,
                             const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank,
@@ -155,6 +188,14 @@ hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s
 hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s);
 hipError_t launch_output(const Tet *T, const Vert *V, const uint32_t *map, uint32_t count, uint32_t *tets,
                          int64_t *nbrs, hipStream_t s);
+// grouping of the live finite tetrahedra by cloud (see dt_get_tets_batch)
+hipError_t launch_tet_cloud(const Tet *T, const Vert *V, uint32_t count, uint32_t nclouds, unsigned long long *keys,
+                            uint32_t *vals, hipStream_t s);
+hipError_t launch_seg_bounds(const unsigned long long *keys, uint32_t count, uint32_t nclouds, uint32_t *toff,
+                             hipStream_t s);
+hipError_t launch_tet_map(const uint32_t *sorted, uint32_t nlive, uint32_t *map, hipStream_t s);
+hipError_t launch_output_cloud(const Tet *T, const Vert *V, const uint32_t *sorted, const uint32_t *map, uint32_t tb,
+                               uint32_t te, uint64_t vbase, uint32_t *tets, int64_t *nbrs, hipStream_t s);
 hipError_t launch_predicates(int kind, const double *pts, const int64_t *idx, uint64_t k, int8_t *out,
                              hipStream_t s);
 

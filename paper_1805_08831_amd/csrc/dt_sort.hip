@@ -1,9 +1,9 @@
 // Point ingest and spatial sort (paper Sec. 2.1 "Sort", Sec. 2.3).
 //
-// validate + bounding box -> Moore key and BRIO level per point -> stable LSD radix sort of
-// (Moore index, input index) -> 32-byte vertex records in Moore order -> BRIO level of
-// each record and the level-major order of the records (a one-pass counting sort) -> exact
-// duplicate removal by hashing.
+// validate + bounding box of each cloud -> (cloud, Moore index) key per point -> stable LSD
+// radix sort of (key, input index) -> 32-byte vertex records in curve order -> BRIO level of
+// each record within its cloud and the level-major order of the records (a counting sort) ->
+// exact duplicate removal by hashing, within each cloud.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -50,49 +50,68 @@ __device__ uint32_t block_scan_256(uint32_t v, uint32_t *total) {
 
 // ------------------------------------------------------------------ validate + bbox
 
-__global__ void k_validate_bbox(const double *__restrict__ xyz, uint64_t n, double *__restrict__ blocks,
-                                uint32_t *__restrict__ err) {
+// one block per chunk of one cloud: validity of the coordinates and the chunk's box
+__global__ void k_chunk_bbox(const double *__restrict__ xyz, const uint64_t *__restrict__ ch_start,
+                             const uint64_t *__restrict__ ch_end, double *__restrict__ partial,
+                             uint32_t *__restrict__ err) {
+    const uint64_t b = ch_start[blockIdx.x], e = ch_end[blockIdx.x];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool ok = true;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
         for (int k = 0; k < 3; ++k) {
-            double v = xyz[3 * i + k];
+            const double v = xyz[3 * i + k];
             ok = ok && coord_ok(v);
             lo[k] = fmin(lo[k], v);
             hi[k] = fmax(hi[k], v);
         }
     }
     if (!ok) atomicOr(err, ERR_INPUT);
-    __shared__ double s[6][256];
+    __shared__ double sh[6][256];
     for (int k = 0; k < 3; ++k) {
-        s[k][threadIdx.x] = lo[k];
-        s[3 + k][threadIdx.x] = hi[k];
+        sh[k][threadIdx.x] = lo[k];
+        sh[3 + k][threadIdx.x] = hi[k];
     }
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
             for (int k = 0; k < 3; ++k) {
-                s[k][threadIdx.x] = fmin(s[k][threadIdx.x], s[k][threadIdx.x + w]);
-                s[3 + k][threadIdx.x] = fmax(s[3 + k][threadIdx.x], s[3 + k][threadIdx.x + w]);
+                sh[k][threadIdx.x] = fmin(sh[k][threadIdx.x], sh[k][threadIdx.x + w]);
+                sh[3 + k][threadIdx.x] = fmax(sh[3 + k][threadIdx.x], sh[3 + k][threadIdx.x + w]);
             }
         __syncthreads();
     }
-    if (threadIdx.x < 6) blocks[6 * blockIdx.x + threadIdx.x] = s[threadIdx.x][0];
+    if (threadIdx.x < 6) partial[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const double *__restrict__ blocks, int nb, double *__restrict__ out) {
-    if (threadIdx.x >= 6) return;
-    int k = threadIdx.x;
-    double v = k < 3 ? INFINITY : -INFINITY;
-    for (int b = 0; b < nb; ++b) v = k < 3 ? fmin(v, blocks[6 * b + k]) : fmax(v, blocks[6 * b + k]);
-    out[k] = v;
+// one thread per cloud: its box from its chunks; the grid origin and the cubic scale
+// 2^m / (largest extent)
+__global__ void k_cloud_box(const double *__restrict__ partial, const uint32_t *__restrict__ cloud_ch,
+                            uint32_t nclouds, Cloud *__restrict__ clouds) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nclouds) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t j = cloud_ch[c]; j < cloud_ch[c + 1]; ++j)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], partial[6 * j + k]);
+            hi[k] = fmax(hi[k], partial[6 * j + 3 + k]);
+        }
+    double ext = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double e = hi[k] - lo[k];
+        if (e > ext) ext = e;
+    }
+    const double cells = ldexp(1.0, (int)clouds[c].m);
+    clouds[c].box[0] = lo[0];
+    clouds[c].box[1] = lo[1];
+    clouds[c].box[2] = lo[2];
+    clouds[c].box[3] = ext > 0.0 ? cells / ext : 0.0;
 }
 
-hipError_t launch_validate_bbox(const double *xyz, uint64_t n, double *bbox_blocks, int nblocks,
-                                double *bbox_out, uint32_t *err, hipStream_t s) {
-    k_validate_bbox<<<nblocks, 256, 0, s>>>(xyz, n, bbox_blocks, err);
-    k_bbox_final<<<1, 64, 0, s>>>(bbox_blocks, nblocks, bbox_out);
+hipError_t launch_cloud_bbox(const double *xyz, const uint64_t *ch_start, const uint64_t *ch_end,
+                             uint32_t nchunks, double *partial, const uint32_t *cloud_ch, uint32_t nclouds,
+                             Cloud *clouds, uint32_t *err, hipStream_t s) {
+    if (nchunks) k_chunk_bbox<<<nchunks, 256, 0, s>>>(xyz, ch_start, ch_end, partial, err);
+    k_cloud_box<<<(nclouds + 255) / 256, 256, 0, s>>>(partial, cloud_ch, nclouds, clouds);
     return hipGetLastError();
 }
 
@@ -160,80 +179,76 @@ __device__ __forceinline__ unsigned long long moore_index(unsigned cx, unsigned 
     return h;
 }
 
-__global__ void k_keys(const double *__restrict__ xyz, uint64_t n, const double *__restrict__ bbox, int m,
-                       unsigned long long salt, const uint64_t *__restrict__ cum, int L,
-                       unsigned long long states, unsigned long long *__restrict__ keys,
-                       uint32_t *__restrict__ vals) {
+// cloud of input point i: the last c with off[c] <= i
+__device__ __forceinline__ uint32_t cloud_of(const uint64_t *__restrict__ off, uint32_t nclouds, uint64_t i) {
+    uint32_t lo = 0, hi = nclouds;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_keys(const double *__restrict__ xyz, uint64_t n, const uint64_t *__restrict__ off,
+                       uint32_t nclouds, const Cloud *__restrict__ clouds, int shift, unsigned long long states,
+                       unsigned long long *__restrict__ keys, uint32_t *__restrict__ vals) {
     uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double ext = 0.0;
+    const uint32_t c = cloud_of(off, nclouds, i);
+    const Cloud cl = clouds[c];
+    const int m = (int)cl.m;
+    const unsigned top = (1u << m) - 1u;
+    unsigned cell[3];
     for (int k = 0; k < 3; ++k) {
-        double e = bbox[3 + k] - bbox[k];
-        if (e > ext) ext = e;
+        const double t = floor((xyz[3 * i + k] - cl.box[k]) * cl.box[3]);
+        cell[k] = t >= (double)top ? top : (unsigned)t;
     }
-    double cells = ldexp(1.0, m);
-    double sc = ext > 0.0 ? cells / ext : 0.0;
-    unsigned top = (1u << m) - 1u, c[3];
-    for (int k = 0; k < 3; ++k) {
-        double t = floor((xyz[3 * i + k] - bbox[k]) * sc);
-        c[k] = t >= (double)top ? top : (unsigned)t;
-    }
-    unsigned long long key = moore_index(c[0], c[1], c[2], m, states);
-    // BRIO level: 53 uniform bits u; level = first k with u * n < cum_k * 2^53
-    unsigned long long u = mix64(salt + i) >> 11;
-    int lev = 0;
-    while (lev < L - 1) {
-        unsigned long long lo = u * n, hi = __umul64hi(u, n);
-        unsigned long long clo = (unsigned long long)cum[lev] << 53, chi = (unsigned long long)cum[lev] >> 11;
-        bool less = hi < chi || (hi == chi && lo < clo);
-        if (less) break;
-        ++lev;
-    }
-    keys[i] = ((unsigned long long)lev << (3 * m)) | key;
+    keys[i] = ((unsigned long long)c << shift) | moore_index(cell[0], cell[1], cell[2], m, states);
     vals[i] = (uint32_t)i;
 }
 
-hipError_t launch_keys(const double *xyz, uint64_t n, const double *bbox, int m, uint64_t salt,
-                       const uint64_t *cum, int L, unsigned long long *keys, uint32_t *vals, hipStream_t s) {
+hipError_t launch_keys(const double *xyz, uint64_t n, const uint64_t *off, uint32_t nclouds, const Cloud *clouds,
+                       int shift, unsigned long long *keys, uint32_t *vals, hipStream_t s) {
     unsigned long long st = moore_states();
     if (!st) return hipErrorUnknown;
     if (n == 0) return hipSuccess;
-    k_keys<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(xyz, n, bbox, m, salt, cum, L, st, keys, vals);
+    k_keys<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(xyz, n, off, nclouds, clouds, shift, st, keys, vals);
     return hipGetLastError();
 }
 
-// BRIO level of the point at each Moore-sorted position (src[i] = its index within the
-// call), as the key of a stable counting sort that yields the level-major order of the
-// positions; vals[i] = base + i
-__global__ void k_levels(const uint32_t *__restrict__ src, uint64_t n, uint64_t base,
-                         unsigned long long salt, const uint64_t *__restrict__ cum, int L,
-                         unsigned long long *__restrict__ keys, uint32_t *__restrict__ vals) {
+// BRIO level of the point at each curve-ordered position, within its cloud (src[i] = its
+// input index within the call; the cloud of the record is in the upper half of its idx), as
+// the key of a stable counting sort that yields the level-major order of the positions;
+// vals[i] = base + i
+__global__ void k_levels(const uint32_t *__restrict__ src, const Vert *__restrict__ V, uint64_t n, uint64_t base,
+                         const uint64_t *__restrict__ off, const Cloud *__restrict__ clouds,
+                         unsigned long long salt, unsigned long long *__restrict__ keys,
+                         uint32_t *__restrict__ vals) {
     uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const unsigned long long u = mix64(salt + (unsigned long long)src[i]) >> 11;
-    int lev = 0;
-    while (lev < L - 1) {
-        unsigned long long lo = u * n, hi = __umul64hi(u, n);
-        unsigned long long clo = (unsigned long long)cum[lev] << 53, chi = (unsigned long long)cum[lev] >> 11;
-        if (hi < chi || (hi == chi && lo < clo)) break;
-        ++lev;
-    }
-    keys[i] = (unsigned long long)lev;
+    const uint32_t c = (uint32_t)(V[base + i].idx >> 32);
+    const unsigned long long local = (unsigned long long)src[i] - off[c];
+    const unsigned long long nc = clouds[c].hi - clouds[c].lo;
+    const unsigned long long u = mix64(salt + local) >> 11;
+    keys[i] = (unsigned long long)brio_level(u, nc);
     vals[i] = (uint32_t)(base + i);
 }
 
-hipError_t launch_levels(const uint32_t *src, uint64_t n, uint64_t base, uint64_t salt, const uint64_t *cum,
-                         int L, unsigned long long *keys, uint32_t *vals, hipStream_t s) {
+hipError_t launch_levels(const uint32_t *src, const Vert *V, uint64_t n, uint64_t base, const uint64_t *off,
+                         const Cloud *clouds, uint64_t salt, unsigned long long *keys, uint32_t *vals,
+                         hipStream_t s) {
     if (n == 0) return hipSuccess;
-    k_levels<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, n, base, salt, cum, L, keys, vals);
+    k_levels<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, V, n, base, off, clouds, salt, keys, vals);
     return hipGetLastError();
 }
 
 // Walk anchor of every record of level k >= 1: the record of the nearest non-empty lower
-// level that precedes it on the curve (else that level's first record).  lord lists each
-// level's positions in increasing order; anchor is indexed by position - base.
+// level that precedes it on the curve, or else follows it, if that record is in the same
+// cloud.  lord lists each level's positions in increasing order; anchor is indexed by
+// position - base.
 __global__ void k_anchor(const uint32_t *__restrict__ lord, const uint32_t *__restrict__ start, int L,
-                         uint64_t base, uint64_t n, uint32_t *__restrict__ anchor) {
+                         const Vert *__restrict__ V, uint64_t base, uint64_t n, uint32_t *__restrict__ anchor) {
     const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (j >= n) return;
     int k = 0;
@@ -241,28 +256,30 @@ __global__ void k_anchor(const uint32_t *__restrict__ lord, const uint32_t *__re
     const uint32_t p = lord[j];
     int kk = k - 1;
     while (kk >= 0 && start[kk + 1] == start[kk]) --kk;
-    if (kk < 0) {
-        anchor[p - base] = 0xFFFFFFFFu;
-        return;
-    }
-    uint32_t lo = start[kk], hi = start[kk + 1];  // last entry < p in [lo, hi), else lo
-    uint32_t res = lo;
-    while (lo < hi) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        if (lord[mid] < p) {
-            res = mid;
-            lo = mid + 1;
-        } else {
-            hi = mid;
+    uint32_t res = 0xFFFFFFFFu;
+    if (kk >= 0) {
+        const uint32_t b = start[kk], e = start[kk + 1];
+        uint32_t lo = b, hi = e, pos = b;  // last entry < p in [b, e), else b
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (lord[mid] < p) {
+                pos = mid;
+                lo = mid + 1;
+            } else {
+                hi = mid;
+            }
         }
+        const uint32_t cp = (uint32_t)(V[p].idx >> 32);
+        if ((uint32_t)(V[lord[pos]].idx >> 32) == cp) res = lord[pos];
+        else if (pos + 1 < e && (uint32_t)(V[lord[pos + 1]].idx >> 32) == cp) res = lord[pos + 1];
     }
-    anchor[p - base] = lord[res];
+    anchor[p - base] = res;
 }
 
-hipError_t launch_anchor(const uint32_t *lord, const uint32_t *start, int L, uint64_t base, uint64_t n,
-                         uint32_t *anchor, hipStream_t s) {
+hipError_t launch_anchor(const uint32_t *lord, const uint32_t *start, int L, const Vert *V, uint64_t base,
+                         uint64_t n, uint32_t *anchor, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    k_anchor<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lord, start, L, base, n, anchor);
+    k_anchor<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lord, start, L, V, base, n, anchor);
     return hipGetLastError();
 }
 
@@ -410,8 +427,9 @@ hipError_t radix_sort_pairs(unsigned long long *keys, uint32_t *vals, unsigned l
 
 // ------------------------------------------------------------------ permutation, levels, anchors
 
-__global__ void k_permute(const double *__restrict__ xyz, const uint32_t *__restrict__ vals, uint64_t n,
-                          uint64_t base, uint64_t idx_offset, Vert *__restrict__ V, uint32_t *__restrict__ vtet,
+__global__ void k_permute(const double *__restrict__ xyz, const uint32_t *__restrict__ vals,
+                          const unsigned long long *__restrict__ skeys, int shift, uint64_t n, uint64_t base,
+                          uint64_t idx_offset, Vert *__restrict__ V, uint32_t *__restrict__ vtet,
                           uint8_t *__restrict__ dup) {
     uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -420,16 +438,18 @@ __global__ void k_permute(const double *__restrict__ xyz, const uint32_t *__rest
     v.x = xyz[3ull * src + 0];
     v.y = xyz[3ull * src + 1];
     v.z = xyz[3ull * src + 2];
-    v.idx = idx_offset + src;
+    v.idx = ((skeys[i] >> shift) << 32) | (idx_offset + src);
     V[base + i] = v;
-    vtet[base + i] = NONE;
-    dup[base + i] = 0;
+    if (vtet) vtet[base + i] = NONE;
+    if (dup) dup[base + i] = 0;
 }
 
-hipError_t launch_permute(const double *xyz, const uint32_t *vals, uint64_t n, uint64_t base, uint64_t idx_offset,
-                          Vert *V, uint32_t *vtet, uint8_t *dup, hipStream_t s) {
+hipError_t launch_permute(const double *xyz, const uint32_t *vals, const unsigned long long *skeys, int shift,
+                          uint64_t n, uint64_t base, uint64_t idx_offset, Vert *V, uint32_t *vtet, uint8_t *dup,
+                          hipStream_t s) {
     if (n == 0) return hipSuccess;
-    k_permute<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(xyz, vals, n, base, idx_offset, V, vtet, dup);
+    k_permute<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(xyz, vals, skeys, shift, n, base, idx_offset, V, vtet,
+                                                          dup);
     return hipGetLastError();
 }
 
@@ -470,6 +490,7 @@ __global__ void k_dedupe_insert(const Vert *__restrict__ V, uint64_t base, uint6
     uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     Vert v = V[base + i];
+    // smallest input index first (the cloud id in the upper half of idx is shifted out)
     unsigned long long mine = (v.idx << 32) | (unsigned long long)(base + i);
     uint64_t h = coord_hash(v.x, v.y, v.z) & tmask;
     for (;;) {
@@ -479,7 +500,7 @@ __global__ void k_dedupe_insert(const Vert *__restrict__ V, uint64_t base, uint6
             if (cur == ~0ull) return;
         }
         Vert w = V[(uint32_t)cur];
-        if (w.x == v.x && w.y == v.y && w.z == v.z) {
+        if (w.x == v.x && w.y == v.y && w.z == v.z && (w.idx >> 32) == (v.idx >> 32)) {
             atomicMin(&table[h], mine);
             return;
         }
@@ -498,7 +519,7 @@ __global__ void k_dedupe_resolve(const Vert *__restrict__ V, uint64_t base, uint
         unsigned long long cur = table[h];
         if (cur == ~0ull) return;  // unreachable: the point's own slot precedes any empty one
         Vert w = V[(uint32_t)cur];
-        if (w.x == v.x && w.y == v.y && w.z == v.z) {
+        if (w.x == v.x && w.y == v.y && w.z == v.z && (w.idx >> 32) == (v.idx >> 32)) {
             if ((uint32_t)cur != (uint32_t)(base + i)) {
                 dup[base + i] = 1;
                 atomicAdd(ndup, 1u);

@@ -73,10 +73,12 @@ def lib():
         L.dt_get_stats.argtypes = [vp, ctypes.POINTER(dt_stats)]
         L.dt_last_error.argtypes = [vp]
         L.dt_last_error.restype = ctypes.c_char_p
+        L.dt_insert_batch.argtypes = [vp, vp, vp, ctypes.c_uint32]
+        L.dt_get_tets_batch.argtypes = [vp, ctypes.c_uint32, vp, vp, ctypes.POINTER(u64)]
         L.dt_debug_sort.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(i32)]
         L.dt_debug_predicates.argtypes = [vp, i32, vp, vp, u64, vp]
         for f in ("dt_create", "dt_insert_points", "dt_get_tets", "dt_clear", "dt_destroy", "dt_get_stats",
-                  "dt_debug_sort", "dt_debug_predicates"):
+                  "dt_insert_batch", "dt_get_tets_batch", "dt_debug_sort", "dt_debug_predicates"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -122,6 +124,18 @@ def dt_insert_points(ctx, xyz, n=None):
 def dt_get_tets(ctx, tets=None, nbrs=None, capacity=0):
     num = ctypes.c_uint64(capacity)
     _check(ctx, lib().dt_get_tets(ctx, _ptr(tets), _ptr(nbrs), ctypes.byref(num)))
+    return int(num.value)
+
+
+def dt_insert_batch(ctx, xyz, offsets):
+    """offsets: host array of num_clouds + 1 uint64 (numpy)."""
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    _check(ctx, lib().dt_insert_batch(ctx, _ptr(xyz), off.ctypes.data, int(len(off) - 1)))
+
+
+def dt_get_tets_batch(ctx, cloud, tets=None, nbrs=None, capacity=0):
+    num = ctypes.c_uint64(capacity)
+    _check(ctx, lib().dt_get_tets_batch(ctx, int(cloud), _ptr(tets), _ptr(nbrs), ctypes.byref(num)))
     return int(num.value)
 
 
@@ -178,6 +192,20 @@ class Triangulation:
             xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         assert xyz.ndim == 2 and xyz.shape[1] == 3
         dt_insert_points(self.ctx, xyz)
+
+    def insert_batch(self, xyz, offsets):
+        """Independent clouds: cloud k is xyz[offsets[k]:offsets[k+1]]."""
+        if isinstance(xyz, np.ndarray):
+            xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        dt_insert_batch(self.ctx, xyz, offsets)
+
+    def tets_batch(self, cloud):
+        """(tets[T,4] uint32, nbrs[T,4] int64) of one cloud, in its local indices."""
+        T = dt_get_tets_batch(self.ctx, cloud)
+        tets = np.empty((T, 4), dtype=np.uint32)
+        nbrs = np.empty((T, 4), dtype=np.int64)
+        dt_get_tets_batch(self.ctx, cloud, tets, nbrs, T)
+        return tets, nbrs
 
     def num_tets(self):
         return dt_get_tets(self.ctx)

@@ -10,7 +10,7 @@ import sys
 import numpy as np
 import pytest
 
-from synth import cluster_points, lattice_points, shell_points, uniform_points
+from synth import batch_clouds, cluster_points, lattice_points, shell_points, uniform_points
 from validators import check_invariants
 
 pytestmark = pytest.mark.gpu
@@ -260,3 +260,59 @@ def test_device_buffers_through_torch(dtlib, oracle_mod):
         nb = nb.cpu().numpy()
     assert_parity(oracle_mod, xyz, t, "device buffers")
     check_invariants(xyz, t, nb, oracle_mod, expect_vertices=np.arange(len(xyz)))
+
+
+# ------------------------------------------------------------------ batches of clouds
+
+def _concat(clouds):
+    off = np.concatenate([[0], np.cumsum([len(c) for c in clouds])]).astype(np.uint64)
+    return np.ascontiguousarray(np.vstack(clouds), dtype=np.float64), off
+
+
+def test_batch_clouds_match_oracle(dtlib, oracle_mod):
+    """Many independent clouds in one call: each equals the oracle run on that cloud alone."""
+    say("batch: 40 clouds of 4 .. 3000 points in random boxes")
+    xyz, off = batch_clouds(40, seed_base=7000, nmin=4, nmax=3000)
+    with dtlib.Triangulation() as tri:
+        tri.insert_batch(xyz, off)
+        for k in range(40):
+            pts = xyz[off[k]:off[k + 1]]
+            t, nb = tri.tets_batch(k)
+            assert_parity(oracle_mod, pts, t.astype(np.int64), f"cloud {k}")
+            if k % 8 == 0:
+                check_invariants(pts, t.astype(np.int64), nb, oracle_mod, expect_vertices=np.arange(len(pts)))
+        assert tri.stats()["points"] == int(off[-1])
+
+
+def test_batch_mixed_clouds(dtlib, oracle_mod):
+    """Clouds sharing coordinates stay independent; duplicates are removed within a cloud;
+    a cospherical lattice and a lone tetrahedron; no dt_insert_points on a batch."""
+    say("batch: shared coordinates, duplicates, lattice, single tetrahedron")
+    a = uniform_points(500, 11)
+    dups = np.vstack([uniform_points(300, 12), uniform_points(300, 12)[:50]])
+    clouds = [a, a.copy(), dups, lattice_points(216, 5, side=6),
+              np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)]
+    xyz, off = _concat(clouds)
+    with dtlib.Triangulation() as tri:
+        tri.insert_batch(xyz, off)
+        for k, pts in enumerate(clouds):
+            t, _ = tri.tets_batch(k)
+            assert_parity(oracle_mod, pts, t.astype(np.int64), f"cloud {k}")
+        assert tri.stats()["duplicates"] == 50
+        with pytest.raises(dtlib.DTError) as e:
+            tri.insert(uniform_points(10, 1))
+        assert e.value.code == dtlib.DT_E_ARG
+        tri.clear()
+        tri.insert(uniform_points(1000, 13))
+        t, _ = tri.tets_batch(0)
+        assert_parity(oracle_mod, uniform_points(1000, 13), t.astype(np.int64), "single cloud after clear")
+
+
+def test_batch_degenerate_cloud(dtlib):
+    say("batch: a coplanar cloud is reported by index")
+    flat = np.array([[x, y, 0.0] for x in range(3) for y in range(3)], dtype=np.float64)
+    xyz, off = _concat([uniform_points(100, 3), flat])
+    with dtlib.Triangulation() as tri:
+        with pytest.raises(dtlib.DTError) as e:
+            tri.insert_batch(xyz, off)
+        assert e.value.code == dtlib.DT_E_DEGENERATE and "cloud 1" in str(e.value)
