@@ -84,6 +84,12 @@ def main():
     ap.add_argument("--round-fraction", type=float, default=0.0)
     ap.add_argument("--round-size", type=int, default=0)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per insertion (4, 8, 16, 64; 0: automatic)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick lanes per insertion, round fraction and cavity cap on a 2e6-point sample first")
+    ap.add_argument("--workload", choices=["uniform", "batch"], default="uniform")
+    ap.add_argument("--clouds", type=int, default=4096, help="batch: number of clouds")
+    ap.add_argument("--chunk", type=int, default=1024, help="batch: clouds per dt_insert_batch call")
+    ap.add_argument("--loop-sample", type=int, default=64, help="batch: clouds timed one call each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -93,9 +99,13 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the triangulation of one point cloud is not "
-              "distributed across GPUs in this library (see DESIGN.md, sharding).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library triangulates on one device and has no "
+              "multi-GPU path; run it without --gpus or with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        run_batch(args)
+        return
 
     import numpy as np
     import torch
@@ -109,6 +119,9 @@ def main():
     tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True,
                         round_fraction=args.round_fraction, round_size=args.round_size,
                         lanes_per_insert=args.lanes)
+    tuned = None
+    if args.autotune:
+        tuned = tri.autotune(torch.from_numpy(uniform_points(2_000_000, args.seed + 2)).cuda())
 
     def step():
         tri.clear()
@@ -173,7 +186,8 @@ def main():
     bytes_per_launch = b_unit * agg["attempts"] / launches
     achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
     peak = 8000.0
-    roofline = {"bound": "hbm", "kernel": "k_cavity_g<8>", "achieved": round(achieved, 2), "peak": peak,
+    lanes = (tuned or {}).get("lanes_per_insert") or args.lanes or 8
+    roofline = {"bound": "hbm", "kernel": f"k_cavity_g<{lanes}>", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "GB/s", "frac": round(achieved / peak, 5), "traffic": measured_traffic(),
                 "bytes_per_attempt": round(b_unit, 1), "attempts_per_launch": round(agg["attempts"] / launches, 1),
                 "avg_launch_ms": round(avg_launch_ms, 4)}
@@ -203,8 +217,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.n} i.i.d. uniform fp64 points in [0,1)^3, seed {args.seed}",
-                   "points": args.n, "tetrahedra": T, "scheduler": "plain"},
-        "roofline": roofline,
+                   "points": args.n, "tetrahedra": T, "scheduler": "plain",
+                   "launch": tuned if tuned else "defaults"},
+        "roofline": roofline if lanes == 8 and not args.round_fraction and not args.round_size else
+        dict(roofline, traffic=None),
         "cpu_baseline": cpu,
         "detail": {"rounds_per_step": agg["rounds"] / args.steps, "attempts_per_point": agg["attempts"] / max(args.n * args.steps, 1),
                    "conflict_rate": agg["conflicts"] / att, "walk_steps_per_attempt": round(walk, 3),
@@ -214,6 +230,80 @@ def main():
                    "orient_exact_rate": agg["orient_exact"] / max(agg["orient"], 1),
                    "insphere_exact_rate": agg["insphere_exact"] / max(agg["insphere"], 1),
                    "perturbed": agg["perturbed"], "step_ms": [round(1000 * t, 2) for t in times]},
+    }
+    print(json.dumps(line), flush=True)
+    tri.close()
+
+
+def run_batch(args):
+    """Independent clouds (sizes log-uniform in [1e3, 2e5], each uniform in its own random
+    box), dt_insert_batch over chunks of clouds; a step triangulates every cloud once.  Also
+    times a sample of clouds inserted one call each (the single-cloud path in a loop)."""
+    import numpy as np
+    import torch
+
+    from paper_1805_08831_amd import Triangulation
+    from synth import batch_clouds
+
+    xyz, off = batch_clouds(args.clouds, seed_base=3000)
+    off = off.astype(np.int64)
+    d_xyz = torch.from_numpy(xyz).cuda()
+    stream = torch.cuda.current_stream()
+    tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True, lanes_per_insert=args.lanes)
+    chunks = [(c, min(c + args.chunk, args.clouds)) for c in range(0, args.clouds, args.chunk)]
+
+    def step():
+        total = 0
+        for c0, c1 in chunks:
+            p0, p1 = int(off[c0]), int(off[c1])
+            tri.clear()
+            tri.insert_batch(d_xyz[p0:p1], (off[c0:c1 + 1] - p0).astype(np.uint64))
+            total += tri.num_tets()
+        return total
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = 0
+    rounds = 0
+    for _ in range(args.steps):
+        T = step()
+        rounds += tri.stats()["rounds"]
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    # the same clouds, one dt_insert_points call each, on a sample
+    sample = list(range(0, args.clouds, max(1, args.clouds // args.loop_sample)))[:args.loop_sample]
+    tl, tt, pts = 0.0, 0, 0
+    for c in sample:
+        p0, p1 = int(off[c]), int(off[c + 1])
+        tri.clear()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tri.insert(d_xyz[p0:p1])
+        tt += tri.num_tets()
+        torch.cuda.synchronize()
+        tl += time.perf_counter() - t1
+        pts += p1 - p0
+    line = {
+        "metric": "tetrahedra/sec (exact 3D Delaunay, batch of independent clouds)",
+        "value": round(T / (ms / 1000.0), 1),
+        "unit": "tetrahedra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.clouds} clouds, sizes log-uniform in [1e3, 2e5], uniform in random boxes, "
+                               f"seeds 3000 + cloud",
+                   "points": int(off[-1]), "tetrahedra": T, "clouds_per_call": args.chunk,
+                   "calls_per_step": len(chunks), "rounds_per_step": rounds / max(args.steps, 1)},
+        "loop_single": {"value": round(tt / tl, 1), "unit": "tetrahedra/s",
+                        "sample": f"{len(sample)} of the clouds ({pts} points), one dt_insert_points call each"},
     }
     print(json.dumps(line), flush=True)
     tri.close()

@@ -138,6 +138,15 @@ int dt_insert_batch(dt_ctx *ctx, const double *xyz, const uint64_t *offsets, uin
    pass both buffers NULL to query the count.  Host or device pointers. */
 int dt_get_tets_batch(dt_ctx *ctx, uint32_t cloud, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
 
+/* Autotuner: triangulates the n sample points (host or device memory) once per launch
+   configuration - lanes per insertion {4, 8, 16, 64} (64: one wavefront per insertion),
+   round fraction {1/32, 1/16, 1/8}, cavity cap {64, 128} - after one warm-up run, and keeps
+   the fastest (host wall time of dt_insert_points) in the context's options.  *best (may be
+   NULL) receives the chosen options, *best_ms (may be NULL) its time.  The context must be
+   empty and is empty again on return; the statistics are reset.  Results never depend on
+   these options. */
+int dt_autotune(dt_ctx *ctx, const double *xyz, uint64_t n, dt_options *best, double *best_ms);
+
 /* Drop every point and tetrahedron but keep the device allocations. */
 int dt_clear(dt_ctx *ctx);
 

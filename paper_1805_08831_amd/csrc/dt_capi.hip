@@ -217,7 +217,10 @@ int grow_tets(dt_ctx *c, uint64_t need) {
 }
 
 int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
-    if (c->list_cap >= rmax && c->cav) return DT_OK;
+    if (c->list_cap >= rmax && c->cav && c->bufC == (size_t)c->list_cap * c->capC &&
+        c->bufF == (size_t)c->list_cap * c->capF)
+        return DT_OK;
+    rmax = std::max(rmax, c->list_cap);
     for (int k = 0; k < 4; ++k) {
         hipFree(c->lpt[k]);
         hipFree(c->lrank[k]);
@@ -281,6 +284,13 @@ int upload_levels(dt_ctx *c, const Levels &lv, uint32_t **d_start, uint32_t **d_
 }
 
 int grow_tets(dt_ctx *c, uint64_t need);
+
+// launch parameters from the options
+void apply_options(dt_ctx *c) {
+    c->capC = c->opt.cavity_cap ? c->opt.cavity_cap : DEFAULT_CAVITY_CAP;
+    c->lanes = c->opt.lanes_per_insert ? c->opt.lanes_per_insert : DEFAULT_LANES;
+    c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
+}
 
 int check_errors(dt_ctx *c) {
     uint32_t e = c->hctr->error;
@@ -767,9 +777,7 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
     } else {
         rc = DT_E_DEVICE;
     }
-    c->capC = c->opt.cavity_cap ? c->opt.cavity_cap : DEFAULT_CAVITY_CAP;
-    c->lanes = c->opt.lanes_per_insert ? c->opt.lanes_per_insert : DEFAULT_LANES;
-    c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
+    apply_options(c);
     if (!rc && (hipMalloc((void **)&c->ctr, sizeof(Ctr)) != hipSuccess ||
                 hipMalloc((void **)&c->stat, STAT_WORDS * sizeof(unsigned long long)) != hipSuccess ||
                 hipHostMalloc((void **)&c->hctr, sizeof(Ctr), hipHostMallocDefault) != hipSuccess))
@@ -934,6 +942,56 @@ int dt_get_tets_batch(dt_ctx *c, uint32_t cloud, uint32_t *tets, int64_t *nbrs, 
     if (nbrs && !dev_n)
         HIPCHK(hipMemcpyAsync(nbrs, on, 4 * T * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    return DT_OK;
+}
+
+int dt_autotune(dt_ctx *c, const double *xyz, uint64_t n, dt_options *best, double *best_ms) {
+    if (!c || !xyz || n < 4) return DT_E_ARG;
+    if (c->have_mesh || c->nv) return fail(c, DT_E_ARG, "dt_autotune needs an empty context (dt_clear it)");
+    if (n >= (1ull << 30)) return fail(c, DT_E_CAPACITY, "sample too large");
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    const double *dxyz = xyz;
+    DevBuf<double> sample;
+    if (!is_device_ptr(xyz)) {
+        if ((rc = ensure(c, sample, 3 * n))) return rc;
+        HIPCHK(hipMemcpyAsync(sample.p, xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        dxyz = sample.p;
+    }
+    static const uint32_t lanes[] = {4, 8, 16, 64};
+    static const double fracs[] = {1.0 / 32, 1.0 / 16, 1.0 / 8};
+    static const uint32_t caps[] = {64, 128};
+    const dt_options saved = c->opt;
+    dt_options bo = saved;
+    double bms = 1e300;
+    rc = DT_OK;
+    for (int warm = 1, k = 0; k < 4 * 3 * 2 && rc == DT_OK; warm = 0) {
+        c->opt.lanes_per_insert = lanes[k / 6];
+        c->opt.round_fraction = fracs[(k / 2) % 3];
+        c->opt.cavity_cap = caps[k % 2];
+        apply_options(c);
+        auto t0 = std::chrono::steady_clock::now();
+        rc = dt_insert_points(c, dxyz, n);
+        if (rc == DT_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = DT_E_DEVICE;
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        const int rc2 = dt_clear(c);
+        if (rc == DT_OK) rc = rc2;
+        if (warm) continue;  // the first run only warms up allocations
+        if (rc == DT_OK && ms < bms) {
+            bms = ms;
+            bo = c->opt;
+        }
+        ++k;
+    }
+    if (sample.p) {
+        hipStreamSynchronize(c->stream);
+        hipFree(sample.p);
+    }
+    c->opt = rc == DT_OK ? bo : saved;
+    apply_options(c);
+    if (rc != DT_OK) return rc;
+    if (best) *best = bo;
+    if (best_ms) *best_ms = bms;
     return DT_OK;
 }
 

@@ -75,10 +75,11 @@ def lib():
         L.dt_last_error.restype = ctypes.c_char_p
         L.dt_insert_batch.argtypes = [vp, vp, vp, ctypes.c_uint32]
         L.dt_get_tets_batch.argtypes = [vp, ctypes.c_uint32, vp, vp, ctypes.POINTER(u64)]
+        L.dt_autotune.argtypes = [vp, vp, u64, ctypes.POINTER(dt_options), ctypes.POINTER(ctypes.c_double)]
         L.dt_debug_sort.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(i32)]
         L.dt_debug_predicates.argtypes = [vp, i32, vp, vp, u64, vp]
         for f in ("dt_create", "dt_insert_points", "dt_get_tets", "dt_clear", "dt_destroy", "dt_get_stats",
-                  "dt_insert_batch", "dt_get_tets_batch", "dt_debug_sort", "dt_debug_predicates"):
+                  "dt_insert_batch", "dt_get_tets_batch", "dt_autotune", "dt_debug_sort", "dt_debug_predicates"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -137,6 +138,13 @@ def dt_get_tets_batch(ctx, cloud, tets=None, nbrs=None, capacity=0):
     num = ctypes.c_uint64(capacity)
     _check(ctx, lib().dt_get_tets_batch(ctx, int(cloud), _ptr(tets), _ptr(nbrs), ctypes.byref(num)))
     return int(num.value)
+
+
+def dt_autotune(ctx, xyz):
+    """Returns (chosen dt_options, ms of the chosen configuration on the sample)."""
+    best, ms = dt_options(), ctypes.c_double(0.0)
+    _check(ctx, lib().dt_autotune(ctx, _ptr(xyz), int(xyz.shape[0]), ctypes.byref(best), ctypes.byref(ms)))
+    return best, float(ms.value)
 
 
 def dt_clear(ctx):
@@ -206,6 +214,14 @@ class Triangulation:
         nbrs = np.empty((T, 4), dtype=np.int64)
         dt_get_tets_batch(self.ctx, cloud, tets, nbrs, T)
         return tets, nbrs
+
+    def autotune(self, xyz):
+        """Picks lanes per insertion, round fraction and cavity cap on a sample (see dt.h)."""
+        if isinstance(xyz, np.ndarray):
+            xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        best, ms = dt_autotune(self.ctx, xyz)
+        return {"lanes_per_insert": best.lanes_per_insert, "round_fraction": best.round_fraction,
+                "cavity_cap": best.cavity_cap, "ms": ms}
 
     def num_tets(self):
         return dt_get_tets(self.ctx)

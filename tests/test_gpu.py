@@ -316,3 +316,16 @@ def test_batch_degenerate_cloud(dtlib):
         with pytest.raises(dtlib.DTError) as e:
             tri.insert_batch(xyz, off)
         assert e.value.code == dtlib.DT_E_DEGENERATE and "cloud 1" in str(e.value)
+
+
+def test_autotune_keeps_results(dtlib, oracle_mod):
+    say("autotune on a 20000-point sample, then a triangulation with the chosen options")
+    with dtlib.Triangulation() as tri:
+        best = tri.autotune(uniform_points(20000, 31))
+        assert best["lanes_per_insert"] in (4, 8, 16, 64) and best["cavity_cap"] in (64, 128)
+        assert best["round_fraction"] in (1 / 32, 1 / 16, 1 / 8) and best["ms"] > 0
+        assert tri.stats()["points"] == 0
+        xyz = uniform_points(5000, 32)
+        tri.insert(xyz)
+        t, _ = tri.tets()
+        assert_parity(oracle_mod, xyz, t.astype(np.int64), f"tuned {best}")
