@@ -63,7 +63,12 @@ typedef struct {
                                0: automatic                                              */
     uint32_t lanes_per_insert; /* lanes of a wavefront cooperating on one insertion in the
                                   walk and cavity search: 4, 8, 16 or 64; 0: automatic   */
+    int scheduler;          /* DT_SCHED_PLAIN (0) or DT_SCHED_LEARNED (1, needs a model:
+                               dt_load_model or dt_train_model)                          */
+    int log_points;         /* 1: record the attempts of every point (dt_get_point_log)  */
 } dt_options;
+
+enum { DT_SCHED_PLAIN = 0, DT_SCHED_LEARNED = 1 };
 
 /* Counters of the work done since dt_create or the last dt_clear. */
 typedef struct {
@@ -146,6 +151,39 @@ int dt_get_tets_batch(dt_ctx *ctx, uint32_t cloud, uint32_t *tets, int64_t *nbrs
    empty and is empty again on return; the statistics are reset.  Results never depend on
    these options. */
 int dt_autotune(dt_ctx *ctx, const double *xyz, uint64_t n, dt_options *best, double *best_ms);
+
+/* ---- learned insertion scheduler (not in the paper; the output never depends on it) ----
+   An MLP 16 -> 64 -> 64 -> 3 (BF16 weights, FP32 accumulation) maps features of each point
+   (log distances to its curve neighbours and anchor, BRIO level, position in the box) to a
+   cost (predicted log2(1 + attempts)) and two walk-start logits (curve neighbour / anchor).
+   With dt_options.scheduler = DT_SCHED_LEARNED each BRIO level is inserted in two halves,
+   the points predicted cheap first, and the walk starts where the MLP predicts. */
+
+/* After a dt_insert_points run with dt_options.log_points = 1: training samples of its
+   points, in curve order - features (num_points x 16 fp32), cost target log2(1 + attempts)
+   and bucket label (1 when the anchor is closer to the point than both curve neighbours).
+   *num_points in/out as in dt_get_tets (NULL buffers: query).  Host or device pointers. */
+int dt_get_point_log(dt_ctx *ctx, float *features, float *cost, uint8_t *bucket, uint64_t *num_points);
+
+/* Train a model from scratch on n samples (host memory, as from dt_get_point_log): squared
+   error on the cost plus softmax cross-entropy on the bucket, Adam (learning rate lr),
+   minibatches of 4096 in a seeded random order, `epochs` passes, on the device.  The model
+   (a header and the fp32 weights) is written to model (*model_bytes in/out; NULL model:
+   query the size) and loaded into the context. */
+int dt_train_model(dt_ctx *ctx, const float *features, const float *cost, const uint8_t *bucket, uint64_t n,
+                   uint32_t epochs, float lr, uint64_t seed, void *model, size_t *model_bytes);
+
+/* Load a model written by dt_train_model (host memory, not retained). */
+int dt_load_model(dt_ctx *ctx, const void *model, size_t bytes);
+
+/* Test hook: the loaded model's outputs (n x 3 fp32) for n feature rows (n x 16 fp32). */
+int dt_debug_mlp(dt_ctx *ctx, const float *features, uint64_t n, float *out);
+
+/* Test hook: gradient (NPARAM fp32, parameter order W1[16][64], b1, W2[64][64], b2,
+   W3[64][3], b3) of the mean training loss of the loaded model over n samples, and *loss
+   (may be NULL) = the summed per-sample loss.  Host or device pointers. */
+int dt_debug_mlp_grad(dt_ctx *ctx, const float *features, const float *cost, const uint8_t *bucket, uint32_t n,
+                      float *grad, float *loss);
 
 /* Drop every point and tetrahedron but keep the device allocations. */
 int dt_clear(dt_ctx *ctx);

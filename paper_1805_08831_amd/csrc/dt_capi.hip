@@ -127,6 +127,16 @@ struct dt_ctx {
     DevBuf<uint32_t> osorted, omap2;
     std::vector<uint64_t> h_toff;
     const uint32_t *osorted_live = nullptr;
+    // learned scheduler: per-record level, attempts log, walk bucket, features, predictions;
+    // the model (fp32 master weights, bf16 copy, Adam moments)
+    DevBuf<uint8_t> lev, wbucket;
+    DevBuf<uint32_t> log_att;
+    DevBuf<float> feat, ypred;
+    bool have_model = false, logged = false;
+    float thr = 0.0f;
+    uint64_t log_base = 0, log_n = 0;
+    DevBuf<float> w32, m1, m2, grad, loss;
+    DevBuf<uint16_t> wbf;
     // scratch of dt_debug_sort (kept apart from the mesh's own buffers)
     DevBuf<Vert> dbgV;
     DevBuf<Cloud> dbg_cloud;
@@ -337,6 +347,8 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.vhi = (uint32_t)(base + n);
     a.anchor = c->anchor.p;
     a.clouds = c->clouds.p;
+    a.log_att = c->logged ? c->log_att.p : nullptr;
+    a.wbucket = c->opt.scheduler == DT_SCHED_LEARNED ? c->wbucket.p : nullptr;
     a.cand_pt = c->lpt[ci] + off;
     a.cand_rank = c->lrank[ci] + off;
     a.next_pt = c->lpt[ni];
@@ -620,10 +632,10 @@ int sort_points(dt_ctx *c, const double *dxyz, uint64_t n, Cloud *clouds, const 
 // of the records (base + i) in *lord; the level sizes go to hist_host (asynchronously; the
 // caller synchronizes).  svals and the key buffers are consumed.
 int level_order(dt_ctx *c, uint32_t *svals, const Vert *V, uint64_t n, uint64_t base, const uint64_t *d_off,
-                const Cloud *clouds, int L, uint32_t **lord, uint32_t *hist_host) {
+                const Cloud *clouds, int L, uint32_t **lord, uint32_t *hist_host, uint8_t *lev_out) {
     uint32_t *other = (svals == c->vals.p) ? c->vals_tmp.p : c->vals.p;
     const uint64_t salt = host_mix64(c->opt.seed ^ 0x5851F42D4C957F2Dull);
-    HIPCHK(launch_levels(svals, V, n, base, d_off, clouds, salt, c->keys.p, other, c->stream));
+    HIPCHK(launch_levels(svals, V, n, base, d_off, clouds, salt, c->keys.p, other, lev_out, c->stream));
     int lbits = 0;
     while ((1 << lbits) < L) ++lbits;
     bool swapped = false;
@@ -673,7 +685,9 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
     for (uint32_t k = 0; k < C; ++k) L = std::max(L, (int)brio_cum(off[k + 1] - off[k]).size());
     std::vector<uint32_t> hist(64);
     uint32_t *lord = nullptr;
-    if ((rc = level_order(c, svals, c->V.p, n, base, c->off.p, c->clouds.p, L, &lord, hist.data()))) return rc;
+    if ((rc = ensure(c, c->lev, n))) return rc;
+    if ((rc = level_order(c, svals, c->V.p, n, base, c->off.p, c->clouds.p, L, &lord, hist.data(), c->lev.p)))
+        return rc;
     // 5. duplicates (within each cloud)
     uint64_t tsize = 1;
     while (tsize < 2 * n) tsize <<= 1;
@@ -715,6 +729,40 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
     if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
     HIPCHK(launch_anchor(lord, d_start, L, c->V.p, base, n, c->anchor.p, c->stream));
     c->lord = lord;
+    const bool learned = c->opt.scheduler == DT_SCHED_LEARNED;
+    if (learned) {
+        // learned order: each BRIO level split into the points predicted cheap, then the
+        // costly ones; walk-start buckets from the same MLP pass
+        if (!c->have_model) return fail(c, DT_E_ARG, "the learned scheduler needs a model (dt_load_model)");
+        if ((rc = ensure(c, c->feat, (size_t)n * NFEAT)) || (rc = ensure(c, c->ypred, (size_t)n * NOUT)) ||
+            (rc = ensure(c, c->wbucket, n)))
+            return rc;
+        HIPCHK(launch_features(c->V.p, base, n, c->clouds.p, c->anchor.p, c->lev.p, L, c->feat.p, c->stream));
+        HIPCHK(launch_mlp_infer(c->wbf.p, c->feat.p, n, c->ypred.p, c->stream));
+        HIPCHK(launch_learned_keys(c->ypred.p, c->lev.p, n, base, c->thr, c->keys.p, c->vals.p, c->wbucket.p,
+                                   c->stream));
+        int lbits = 0;
+        while ((1 << lbits) < 2 * L) ++lbits;
+        bool swapped = false;
+        HIPCHK(radix_sort_pairs(c->keys.p, c->vals.p, c->keys_tmp.p, c->vals_tmp.p, c->hist.p, c->scan_tmp.p, n,
+                                lbits, c->stream, &swapped));
+        c->lord = swapped ? c->vals_tmp.p : c->vals.p;
+        HIPCHK(hipMemsetAsync(c->small.p, 0, 64 * sizeof(uint32_t), c->stream));
+        HIPCHK(launch_level_hist(swapped ? c->keys_tmp.p : c->keys.p, n, 0, c->small.p, c->stream));
+        HIPCHK(hipMemcpyAsync(hist.data(), c->small.p, 64 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        L *= 2;
+        compute_levels(hist, L, lv);
+        if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
+        HIPCHK(launch_anchor(c->lord, d_start, L, c->V.p, base, n, c->anchor.p, c->stream));
+    }
+    c->logged = c->opt.log_points != 0;
+    if (c->logged) {
+        if ((rc = ensure(c, c->log_att, n))) return rc;
+        HIPCHK(hipMemsetAsync(c->log_att.p, 0, n * sizeof(uint32_t), c->stream));
+        c->log_base = base;
+        c->log_n = n;
+    }
     if ((rc = sync_ctr(c))) return rc;
     c->st.duplicates += c->hctr->dups;
     auto t1 = std::chrono::steady_clock::now();
@@ -995,6 +1043,204 @@ int dt_autotune(dt_ctx *c, const double *xyz, uint64_t n, dt_options *best, doub
     return DT_OK;
 }
 
+// ------------------------------------------------------------------ learned scheduler
+
+namespace {
+
+constexpr uint32_t MODEL_MAGIC = 0x4C4D5444u;  // "DTML"
+struct ModelHeader {
+    uint32_t magic, version, nfeat, nhid, nout, nparam;
+    float thr, loss;
+};
+
+int model_buffers(dt_ctx *c) {
+    int rc;
+    if ((rc = ensure(c, c->w32, NPARAM)) || (rc = ensure(c, c->wbf, NPARAM)) || (rc = ensure(c, c->m1, NPARAM)) ||
+        (rc = ensure(c, c->m2, NPARAM)) || (rc = ensure(c, c->grad, NPARAM)) || (rc = ensure(c, c->loss, 4)))
+        return rc;
+    return DT_OK;
+}
+
+}  // namespace
+
+int dt_get_point_log(dt_ctx *c, float *features, float *cost, uint8_t *bucket, uint64_t *num_points) {
+    if (!c || !num_points) return DT_E_ARG;
+    if (!c->logged) return fail(c, DT_E_ARG, "the last insertion did not log points (dt_options.log_points)");
+    const uint64_t n = c->log_n;
+    if (!features && !cost && !bucket) {
+        *num_points = n;
+        return DT_OK;
+    }
+    if (*num_points < n) {
+        *num_points = n;
+        return fail(c, DT_E_ARG, "buffers hold %llu points, %llu needed", (unsigned long long)*num_points,
+                    (unsigned long long)n);
+    }
+    *num_points = n;
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    if ((rc = ensure(c, c->feat, (size_t)n * NFEAT)) || (rc = ensure(c, c->ypred, (size_t)n * NOUT)) ||
+        (rc = ensure(c, c->wbucket, n)))
+        return rc;
+    int L = 1;
+    for (size_t k = 0; k + 1 < c->h_off.size(); ++k)
+        L = std::max(L, (int)brio_cum(c->h_off[k + 1] - c->h_off[k]).size());
+    HIPCHK(launch_features(c->V.p, c->log_base, n, c->clouds.p, c->anchor.p, c->lev.p, L, c->feat.p, c->stream));
+    // labels: cost in ypred (stride 1), bucket in wbucket
+    HIPCHK(launch_labels(c->V.p, c->log_base, n, c->clouds.p, c->anchor.p, c->log_att.p, c->ypred.p, c->wbucket.p,
+                         c->stream));
+    if (features)
+        HIPCHK(hipMemcpyAsync(features, c->feat.p, n * NFEAT * sizeof(float), hipMemcpyDefault, c->stream));
+    if (cost) HIPCHK(hipMemcpyAsync(cost, c->ypred.p, n * sizeof(float), hipMemcpyDefault, c->stream));
+    if (bucket) HIPCHK(hipMemcpyAsync(bucket, c->wbucket.p, n, hipMemcpyDefault, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DT_OK;
+}
+
+int dt_train_model(dt_ctx *c, const float *features, const float *cost, const uint8_t *bucket, uint64_t n,
+                   uint32_t epochs, float lr, uint64_t seed, void *model, size_t *model_bytes) {
+    if (!c || !features || !cost || !bucket || n == 0 || !model_bytes) return DT_E_ARG;
+    const size_t bytes = sizeof(ModelHeader) + NPARAM * sizeof(float);
+    if (!model) {
+        *model_bytes = bytes;
+        return DT_OK;
+    }
+    if (*model_bytes < bytes) {
+        *model_bytes = bytes;
+        return fail(c, DT_E_ARG, "model buffer holds %zu bytes, %zu needed", *model_bytes, bytes);
+    }
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    if ((rc = model_buffers(c))) return rc;
+    // samples in a seeded random order (host), on the device
+    std::vector<uint64_t> order(n);
+    for (uint64_t i = 0; i < n; ++i) order[i] = i;
+    uint64_t st = seed;
+    for (uint64_t i = n - 1; i > 0; --i) {
+        const uint64_t j = host_mix64(st++) % (i + 1);
+        std::swap(order[i], order[j]);
+    }
+    std::vector<float> hf(n * NFEAT), hc(n);
+    std::vector<uint8_t> hb(n);
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t o = order[i];
+        std::memcpy(&hf[i * NFEAT], &features[o * NFEAT], NFEAT * sizeof(float));
+        hc[i] = cost[o];
+        hb[i] = bucket[o];
+    }
+    DevBuf<float> df, dc;
+    DevBuf<uint8_t> db;
+    if ((rc = ensure(c, df, n * NFEAT)) || (rc = ensure(c, dc, n)) || (rc = ensure(c, db, n))) return rc;
+    HIPCHK(hipMemcpyAsync(df.p, hf.data(), n * NFEAT * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dc.p, hc.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(db.p, hb.data(), n, hipMemcpyHostToDevice, c->stream));
+    // Glorot-uniform weights, zero biases (seeded)
+    std::vector<float> w(NPARAM, 0.0f);
+    const int fan[3][2] = {{NFEAT, NHID}, {NHID, NHID}, {NHID, NOUT}};
+    int o = 0;
+    for (int l = 0; l < 3; ++l) {
+        const double a = std::sqrt(6.0 / (fan[l][0] + fan[l][1]));
+        for (int k = 0; k < fan[l][0] * fan[l][1]; ++k)
+            w[o + k] = (float)(a * (2.0 * ((host_mix64(st++) >> 11) * 0x1p-53) - 1.0));
+        o += fan[l][0] * fan[l][1] + fan[l][1];
+    }
+    HIPCHK(hipMemcpyAsync(c->w32.p, w.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemsetAsync(c->m1.p, 0, NPARAM * sizeof(float), c->stream));
+    HIPCHK(hipMemsetAsync(c->m2.p, 0, NPARAM * sizeof(float), c->stream));
+    HIPCHK(hipMemsetAsync(c->grad.p, 0, NPARAM * sizeof(float), c->stream));
+    HIPCHK(launch_to_bf16(c->w32.p, c->wbf.p, c->stream));
+    constexpr uint32_t BATCH = 4096;
+    int t = 0;
+    float last = 0.0f;
+    for (uint32_t e = 0; e < epochs; ++e) {
+        HIPCHK(hipMemsetAsync(c->loss.p, 0, sizeof(float), c->stream));
+        for (uint64_t b0 = 0; b0 < n; b0 += BATCH) {
+            const uint32_t nb = (uint32_t)std::min<uint64_t>(BATCH, n - b0);
+            HIPCHK(launch_mlp_grad(c->wbf.p, df.p, dc.p, db.p, b0, nb, c->grad.p, c->loss.p, c->stream));
+            HIPCHK(launch_adam(c->w32.p, c->grad.p, c->m1.p, c->m2.p, c->wbf.p, lr, ++t, c->stream));
+        }
+        HIPCHK(hipMemcpyAsync(&last, c->loss.p, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        last /= (float)n;
+    }
+    HIPCHK(hipMemcpyAsync(w.data(), c->w32.p, NPARAM * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    hipFree(df.p);
+    hipFree(dc.p);
+    hipFree(db.p);
+    // split threshold of the scheduler: the median predicted cost of the training points
+    std::vector<float> med(hc);
+    std::nth_element(med.begin(), med.begin() + med.size() / 2, med.end());
+    ModelHeader h{MODEL_MAGIC, 1, NFEAT, NHID, NOUT, NPARAM, med[med.size() / 2], last};
+    std::memcpy(model, &h, sizeof h);
+    std::memcpy((char *)model + sizeof h, w.data(), NPARAM * sizeof(float));
+    *model_bytes = bytes;
+    c->thr = h.thr;
+    c->have_model = true;
+    return DT_OK;
+}
+
+int dt_load_model(dt_ctx *c, const void *model, size_t bytes) {
+    if (!c || !model) return DT_E_ARG;
+    ModelHeader h;
+    if (bytes < sizeof h) return fail(c, DT_E_ARG, "model too short");
+    std::memcpy(&h, model, sizeof h);
+    if (h.magic != MODEL_MAGIC || h.version != 1 || h.nfeat != (uint32_t)NFEAT || h.nhid != (uint32_t)NHID ||
+        h.nout != (uint32_t)NOUT || h.nparam != (uint32_t)NPARAM || bytes < sizeof h + NPARAM * sizeof(float))
+        return fail(c, DT_E_ARG, "not a model of this library (%u-%u-%u)", h.nfeat, h.nhid, h.nout);
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    if ((rc = model_buffers(c))) return rc;
+    HIPCHK(hipMemcpyAsync(c->w32.p, (const char *)model + sizeof h, NPARAM * sizeof(float), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(launch_to_bf16(c->w32.p, c->wbf.p, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->thr = h.thr;
+    c->have_model = true;
+    return DT_OK;
+}
+
+int dt_debug_mlp_grad(dt_ctx *c, const float *features, const float *cost, const uint8_t *bucket, uint32_t n,
+                      float *grad, float *loss) {
+    if (!c || !features || !cost || !bucket || !grad || n == 0) return DT_E_ARG;
+    if (!c->have_model) return fail(c, DT_E_ARG, "no model loaded");
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    DevBuf<float> df, dc;
+    DevBuf<uint8_t> db;
+    if ((rc = model_buffers(c)) || (rc = ensure(c, df, (size_t)n * NFEAT)) || (rc = ensure(c, dc, n)) ||
+        (rc = ensure(c, db, n)))
+        return rc;
+    HIPCHK(hipMemcpyAsync(df.p, features, (size_t)n * NFEAT * sizeof(float), hipMemcpyDefault, c->stream));
+    HIPCHK(hipMemcpyAsync(dc.p, cost, n * sizeof(float), hipMemcpyDefault, c->stream));
+    HIPCHK(hipMemcpyAsync(db.p, bucket, n, hipMemcpyDefault, c->stream));
+    HIPCHK(hipMemsetAsync(c->grad.p, 0, NPARAM * sizeof(float), c->stream));
+    HIPCHK(hipMemsetAsync(c->loss.p, 0, sizeof(float), c->stream));
+    HIPCHK(launch_mlp_grad(c->wbf.p, df.p, dc.p, db.p, 0, n, c->grad.p, c->loss.p, c->stream));
+    HIPCHK(hipMemcpyAsync(grad, c->grad.p, NPARAM * sizeof(float), hipMemcpyDefault, c->stream));
+    if (loss) HIPCHK(hipMemcpyAsync(loss, c->loss.p, sizeof(float), hipMemcpyDefault, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemsetAsync(c->grad.p, 0, NPARAM * sizeof(float), c->stream));
+    hipFree(df.p);
+    hipFree(dc.p);
+    hipFree(db.p);
+    return DT_OK;
+}
+
+int dt_debug_mlp(dt_ctx *c, const float *features, uint64_t n, float *out) {
+    if (!c || !features || !out) return DT_E_ARG;
+    if (!c->have_model) return fail(c, DT_E_ARG, "no model loaded");
+    if (n == 0) return DT_OK;
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    if ((rc = ensure(c, c->feat, (size_t)n * NFEAT)) || (rc = ensure(c, c->ypred, (size_t)n * NOUT))) return rc;
+    HIPCHK(hipMemcpyAsync(c->feat.p, features, n * NFEAT * sizeof(float), hipMemcpyDefault, c->stream));
+    HIPCHK(launch_mlp_infer(c->wbf.p, c->feat.p, n, c->ypred.p, c->stream));
+    HIPCHK(hipMemcpyAsync(out, c->ypred.p, n * NOUT * sizeof(float), hipMemcpyDefault, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DT_OK;
+}
+
 int dt_clear(dt_ctx *c) {
     if (!c) return DT_E_ARG;
     HIPCHK(hipSetDevice(c->device));
@@ -1030,6 +1276,8 @@ int dt_destroy(dt_ctx *c) {
     f(c->hist.p); f(c->scan_tmp.p); f(c->small.p); f(c->small64.p);
     f(c->clouds.p); f(c->off.p); f(c->ch_start.p); f(c->ch_end.p); f(c->cloud_ch.p); f(c->partial.p);
     f(c->okeys.p); f(c->osorted.p); f(c->omap2.p); f(c->dbgV.p); f(c->dbg_cloud.p);
+    f(c->lev.p); f(c->wbucket.p); f(c->log_att.p); f(c->feat.p); f(c->ypred.p);
+    f(c->w32.p); f(c->m1.p); f(c->m2.p); f(c->grad.p); f(c->loss.p); f(c->wbf.p);
     f(c->oflags.p); f(c->omap.p); f(c->otets.p); f(c->onbrs.p);
     for (int k = 0; k < 3; ++k)
         if (c->ev[k]) hipEventDestroy(c->ev[k]);
@@ -1091,7 +1339,8 @@ int dt_debug_sort(dt_ctx *c, const double *xyz, uint64_t n, uint64_t *keys, uint
     HIPCHK(launch_permute(dxyz, sv, sk, 3 * mmax, n, 0, 0, c->dbgV.p, nullptr, nullptr, c->stream));
     const int L = (int)brio_cum(n).size();
     uint32_t *lord = nullptr;
-    if ((rc = level_order(c, sv, c->dbgV.p, n, 0, c->off.p, c->dbg_cloud.p, L, &lord, hist.data()))) return rc;
+    if ((rc = level_order(c, sv, c->dbgV.p, n, 0, c->off.p, c->dbg_cloud.p, L, &lord, hist.data(), nullptr)))
+        return rc;
     HIPCHK(hipMemcpyAsync(lord_h.data(), lord, n * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (keys) {

@@ -566,6 +566,11 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
         if (hp < clo || hp >= chi) ht = NONE;
         const unsigned long long hm = __ballot(ht != NONE) & gmask;
         uint32_t t = hm ? __shfl(ht, __ffsll((long long)hm) - 1) : (q != NONE ? a.vtet[q] : NONE);
+        if (a.wbucket && q != NONE && a.wbucket[p - a.vlo]) {
+            // the learned scheduler predicts the anchor to be the closer start
+            const uint32_t tq = a.vtet[q];
+            if (tq != NONE) t = tq;
+        }
         if (t == NONE) t = cl->any_live;
         uint4 w = a.T[t].v;
         if (w.x == DEAD) {
@@ -1030,6 +1035,7 @@ __global__ void k_compact(RoundArgs a) {
     const uint8_t s = i < ncand ? a.status[i] : (uint8_t)ST_NONE;
     const bool again = i < ncand && (s == ST_CONFLICT || s == ST_CAND);
     const bool ovf = i < ncand && s == ST_OVERFLOW;
+    if (a.log_att && i < ncand) atomicAdd(&a.log_att[a.cand_pt[i] - a.vlo], 1u);
     const uint32_t pn = wave_append(again, a.nnext_ptr);
     const uint32_t po = wave_append(ovf, a.novf_ptr);
     if (again) {

@@ -80,6 +80,10 @@ struct Ctr {
     unsigned long long attempts;
 };
 
+// learned scheduler: MLP NFEAT -> NHID -> NHID -> NOUT
+constexpr int NFEAT = 16, NHID = 64, NOUT = 3;
+constexpr int NPARAM = NFEAT * NHID + NHID + NHID * NHID + NHID + NHID * NOUT + NOUT;
+
 // One independent point cloud of a call (a single-cloud call is a batch of one).  Its vertex
 // records are [lo, hi) in curve order; the cloud id is stored in the upper 32 bits of each
 // record's idx.
@@ -99,6 +103,8 @@ struct RoundArgs {
     const uint32_t *anchor;      // walk anchor of each record of the call (a lower-level record
                                  // of the same cloud), indexed by record - vlo
     Cloud *clouds;               // the call's clouds (walk bounds, live tetrahedron)
+    uint32_t *log_att;           // if set: attempts per record of the call (record - vlo)
+    const uint8_t *wbucket;      // if set: 1 = start the walk at the anchor (record - vlo)
     const uint32_t *cand_pt;     // current candidate list
     const uint32_t *cand_rank;
     uint32_t *next_pt;           // losers for the next round
@@ -151,7 +157,7 @@ hipError_t launch_level_hist(const unsigned long long *keys, uint64_t n, int shi
                              hipStream_t s);
 hipError_t launch_levels(const uint32_t *src, const Vert *V, uint64_t n, uint64_t base, const uint64_t *off,
                          const Cloud *clouds, uint64_t salt, unsigned long long *keys, uint32_t *vals,
-                         hipStream_t s);
+                         uint8_t *lev_out, hipStream_t s);
 hipError_t launch_anchor(const uint32_t *lord, const uint32_t *start, int L, const Vert *V, uint64_t base,
                          uint64_t n, uint32_t *anchor, hipStream_t s);
 hipError_t launch_dedupe(const Vert *V, uint64_t base, uint64_t n, unsigned long long *table,
@@ -174,6 +180,19 @@ __device__ __forceinline__ int brio_level(unsigned long long u, unsigned long lo
         size *= 7;
     }
 }
+
+// ---- launch wrappers (dt_learn.hip) ----
+hipError_t launch_features(const Vert *V, uint64_t base, uint64_t n, const Cloud *clouds, const uint32_t *anchor,
+                           const uint8_t *level, int L, float *feat, hipStream_t s);
+hipError_t launch_mlp_infer(const uint16_t *wbf, const float *feat, uint64_t n, float *y, hipStream_t s);
+hipError_t launch_to_bf16(const float *w, uint16_t *wbf, hipStream_t s);
+hipError_t launch_mlp_grad(const uint16_t *wbf, const float *feat, const float *cost, const uint8_t *bucket,
+                           uint64_t b0, uint32_t nb, float *grad, float *loss, hipStream_t s);
+hipError_t launch_adam(float *w, float *grad, float *m1, float *m2, uint16_t *wbf, float lr, int t, hipStream_t s);
+hipError_t launch_learned_keys(const float *y, const uint8_t *level, uint64_t n, uint64_t base, float thr,
+                               unsigned long long *keys, uint32_t *vals, uint8_t *wbucket, hipStream_t s);
+hipError_t launch_labels(const Vert *V, uint64_t base, uint64_t n, const Cloud *clouds, const uint32_t *anchor,
+                         const uint32_t *attempts, float *cost, uint8_t *bucket, hipStream_t s);
 
 // ---- launch wrappers (dt_insert.hip) ----
 // initial tetrahedron and four ghosts of each cloud c at slots 5 c0 + 5 c .. + 4 (c0: first)

@@ -224,22 +224,24 @@ hipError_t launch_keys(const double *xyz, uint64_t n, const uint64_t *off, uint3
 __global__ void k_levels(const uint32_t *__restrict__ src, const Vert *__restrict__ V, uint64_t n, uint64_t base,
                          const uint64_t *__restrict__ off, const Cloud *__restrict__ clouds,
                          unsigned long long salt, unsigned long long *__restrict__ keys,
-                         uint32_t *__restrict__ vals) {
+                         uint32_t *__restrict__ vals, uint8_t *__restrict__ lev_out) {
     uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t c = (uint32_t)(V[base + i].idx >> 32);
     const unsigned long long local = (unsigned long long)src[i] - off[c];
     const unsigned long long nc = clouds[c].hi - clouds[c].lo;
     const unsigned long long u = mix64(salt + local) >> 11;
-    keys[i] = (unsigned long long)brio_level(u, nc);
+    const int lev = brio_level(u, nc);
+    keys[i] = (unsigned long long)lev;
     vals[i] = (uint32_t)(base + i);
+    if (lev_out) lev_out[i] = (uint8_t)lev;
 }
 
 hipError_t launch_levels(const uint32_t *src, const Vert *V, uint64_t n, uint64_t base, const uint64_t *off,
                          const Cloud *clouds, uint64_t salt, unsigned long long *keys, uint32_t *vals,
-                         hipStream_t s) {
+                         uint8_t *lev_out, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    k_levels<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, V, n, base, off, clouds, salt, keys, vals);
+    k_levels<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, V, n, base, off, clouds, salt, keys, vals, lev_out);
     return hipGetLastError();
 }
 

@@ -26,7 +26,11 @@ class dt_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("round_size", ctypes.c_uint32),
                 ("cavity_cap", ctypes.c_uint32), ("capacity_tets", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("max_rounds", ctypes.c_uint32), ("timing", ctypes.c_int), ("round_fraction", ctypes.c_double),
-                ("lanes_per_insert", ctypes.c_uint32)]
+                ("lanes_per_insert", ctypes.c_uint32), ("scheduler", ctypes.c_int), ("log_points", ctypes.c_int)]
+
+DT_SCHED_PLAIN, DT_SCHED_LEARNED = 0, 1
+NFEAT, NHID, NOUT = 16, 64, 3
+NPARAM = NFEAT * NHID + NHID + NHID * NHID + NHID + NHID * NOUT + NOUT
 
 
 _STAT_U64 = ["points", "vertices", "duplicates", "tets", "rounds", "attempts", "inserted", "conflicts",
@@ -76,10 +80,17 @@ def lib():
         L.dt_insert_batch.argtypes = [vp, vp, vp, ctypes.c_uint32]
         L.dt_get_tets_batch.argtypes = [vp, ctypes.c_uint32, vp, vp, ctypes.POINTER(u64)]
         L.dt_autotune.argtypes = [vp, vp, u64, ctypes.POINTER(dt_options), ctypes.POINTER(ctypes.c_double)]
+        L.dt_get_point_log.argtypes = [vp, vp, vp, vp, ctypes.POINTER(u64)]
+        L.dt_train_model.argtypes = [vp, vp, vp, vp, u64, ctypes.c_uint32, ctypes.c_float, u64, vp,
+                                     ctypes.POINTER(ctypes.c_size_t)]
+        L.dt_load_model.argtypes = [vp, vp, ctypes.c_size_t]
+        L.dt_debug_mlp.argtypes = [vp, vp, u64, vp]
+        L.dt_debug_mlp_grad.argtypes = [vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
         L.dt_debug_sort.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(i32)]
         L.dt_debug_predicates.argtypes = [vp, i32, vp, vp, u64, vp]
         for f in ("dt_create", "dt_insert_points", "dt_get_tets", "dt_clear", "dt_destroy", "dt_get_stats",
-                  "dt_insert_batch", "dt_get_tets_batch", "dt_autotune", "dt_debug_sort", "dt_debug_predicates"):
+                  "dt_insert_batch", "dt_get_tets_batch", "dt_autotune", "dt_get_point_log", "dt_train_model",
+                  "dt_load_model", "dt_debug_mlp", "dt_debug_mlp_grad", "dt_debug_sort", "dt_debug_predicates"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -147,6 +158,55 @@ def dt_autotune(ctx, xyz):
     return best, float(ms.value)
 
 
+def dt_get_point_log(ctx):
+    """(features[n,16] f32, cost[n] f32, bucket[n] u8) of the last logged insertion."""
+    num = ctypes.c_uint64(0)
+    _check(ctx, lib().dt_get_point_log(ctx, None, None, None, ctypes.byref(num)))
+    n = int(num.value)
+    f = np.empty((n, NFEAT), dtype=np.float32)
+    c = np.empty(n, dtype=np.float32)
+    b = np.empty(n, dtype=np.uint8)
+    _check(ctx, lib().dt_get_point_log(ctx, f.ctypes.data, c.ctypes.data, b.ctypes.data, ctypes.byref(num)))
+    return f, c, b
+
+
+def dt_train_model(ctx, features, cost, bucket, epochs=4, lr=1e-3, seed=1):
+    """Trains (and loads) a model; returns its bytes."""
+    f = np.ascontiguousarray(features, dtype=np.float32)
+    c = np.ascontiguousarray(cost, dtype=np.float32)
+    b = np.ascontiguousarray(bucket, dtype=np.uint8)
+    size = ctypes.c_size_t(0)
+    _check(ctx, lib().dt_train_model(ctx, f.ctypes.data, c.ctypes.data, b.ctypes.data, len(c), 0, 0.0, 0, None,
+                                     ctypes.byref(size)))
+    buf = ctypes.create_string_buffer(size.value)
+    _check(ctx, lib().dt_train_model(ctx, f.ctypes.data, c.ctypes.data, b.ctypes.data, len(c), int(epochs),
+                                     float(lr), int(seed), buf, ctypes.byref(size)))
+    return bytes(buf.raw[:size.value])
+
+
+def dt_load_model(ctx, model):
+    buf = ctypes.create_string_buffer(model, len(model))
+    _check(ctx, lib().dt_load_model(ctx, buf, len(model)))
+
+
+def dt_debug_mlp(ctx, features):
+    f = np.ascontiguousarray(features, dtype=np.float32)
+    out = np.empty((len(f), NOUT), dtype=np.float32)
+    _check(ctx, lib().dt_debug_mlp(ctx, f.ctypes.data, len(f), out.ctypes.data))
+    return out
+
+
+def dt_debug_mlp_grad(ctx, features, cost, bucket):
+    f = np.ascontiguousarray(features, dtype=np.float32)
+    c = np.ascontiguousarray(cost, dtype=np.float32)
+    b = np.ascontiguousarray(bucket, dtype=np.uint8)
+    g = np.empty(NPARAM, dtype=np.float32)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(ctx, lib().dt_debug_mlp_grad(ctx, f.ctypes.data, c.ctypes.data, b.ctypes.data, len(c), g.ctypes.data,
+                                        loss.ctypes.data))
+    return g, float(loss[0])
+
+
 def dt_clear(ctx):
     _check(ctx, lib().dt_clear(ctx))
 
@@ -186,12 +246,13 @@ class Triangulation:
     (host or device); `tets` returns (tets[T,4] uint32, nbrs[T,4] int64)."""
 
     def __init__(self, device=0, stream=None, round_size=0, cavity_cap=0, capacity_tets=0, seed=0x5EED,
-                 max_rounds=0, timing=False, round_fraction=0.0, lanes_per_insert=0):
+                 max_rounds=0, timing=False, round_fraction=0.0, lanes_per_insert=0, scheduler=0, log_points=False):
         o = dt_default_options()
         o.device, o.round_size, o.cavity_cap = int(device), int(round_size), int(cavity_cap)
         o.capacity_tets, o.seed, o.max_rounds = int(capacity_tets), int(seed), int(max_rounds)
         o.timing, o.round_fraction = int(bool(timing)), float(round_fraction)
         o.lanes_per_insert = int(lanes_per_insert)
+        o.scheduler, o.log_points = int(scheduler), int(bool(log_points))
         o.stream = stream
         self.ctx = dt_create(o)
 

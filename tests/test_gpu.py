@@ -329,3 +329,88 @@ def test_autotune_keeps_results(dtlib, oracle_mod):
         tri.insert(xyz)
         t, _ = tri.tets()
         assert_parity(oracle_mod, xyz, t.astype(np.int64), f"tuned {best}")
+
+
+# ------------------------------------------------------------------ learned scheduler
+
+def _bf16(a):
+    """fp32 -> bf16 (round to nearest even) -> fp32: the kernels' weight copies."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return (u & 0xFFFFFFFF).astype(np.uint32).view(np.float32)
+
+
+def _unpack(model, F=16, H=64, O=3):
+    hdr = np.frombuffer(model[:24], dtype=np.uint32)
+    assert tuple(hdr[2:6]) == (F, H, O, F * H + H + H * H + H + H * O + O)
+    w = np.frombuffer(model[32:], dtype=np.float32)
+    out, o = [], 0
+    for shape in [(F, H), (H,), (H, H), (H,), (H, O), (O,)]:
+        k = int(np.prod(shape))
+        out.append(w[o:o + k].reshape(shape))
+        o += k
+    return out
+
+
+def _synthetic_samples(n, seed):
+    rng = np.random.default_rng(seed)
+    f = rng.normal(size=(n, 16)).astype(np.float32)
+    cost = (0.5 * f[:, 0] - 0.3 * f[:, 3] + 0.2 * f[:, 5] * f[:, 6] + 1.0).astype(np.float32)
+    bucket = (f[:, 1] + 0.5 * f[:, 2] > 0).astype(np.uint8)
+    return f, cost, bucket
+
+
+def test_mlp_matches_cpu_reference(dtlib):
+    """The BF16-weight / FP32-accumulate inference and training-gradient kernels against
+    PyTorch CPU float32 with the same bf16-rounded weights; training fits a known target."""
+    import torch
+    say("mlp: inference and gradient vs CPU reference, training fit")
+    f, cost, bucket = _synthetic_samples(16384, 5)
+    with dtlib.Triangulation() as tri:
+        model = dtlib.dt_train_model(tri.ctx, f, cost, bucket, epochs=10, lr=3e-3, seed=7)
+        ps = [torch.tensor(_bf16(p)).requires_grad_(True) for p in _unpack(model)]
+
+        def forward(x):
+            h1 = torch.relu(x @ ps[0] + ps[1])
+            h2 = torch.relu(h1 @ ps[2] + ps[3])
+            return h2 @ ps[4] + ps[5]
+
+        y = dtlib.dt_debug_mlp(tri.ctx, f[:2048])
+        np.testing.assert_allclose(y, forward(torch.tensor(f[:2048])).detach().numpy(), rtol=1e-4, atol=1e-4)
+        n = 3000
+        g, loss = dtlib.dt_debug_mlp_grad(tri.ctx, f[:n], cost[:n], bucket[:n])
+        out = forward(torch.tensor(f[:n]))
+        ref = ((out[:, 0] - torch.tensor(cost[:n])) ** 2).mean() + \
+            torch.nn.functional.cross_entropy(out[:, 1:3], torch.tensor(bucket[:n]).long())
+        ref.backward()
+        gr = torch.cat([p.grad.reshape(-1) for p in ps]).numpy()
+        np.testing.assert_allclose(g, gr, rtol=2e-3, atol=2e-6)
+        assert abs(loss / n - ref.item()) < 1e-3 * (1.0 + ref.item())
+        yall = dtlib.dt_debug_mlp(tri.ctx, f)
+        assert np.corrcoef(yall[:, 0], cost)[0, 1] > 0.85
+        assert ((yall[:, 2] > yall[:, 1]) == (bucket == 1)).mean() > 0.85
+
+
+def test_learned_scheduler_keeps_result(dtlib, oracle_mod):
+    """Trained on the log of a plain run (another seed); the learned order gives the same
+    triangulation as the oracle."""
+    say("learned scheduler: train on a plain MIX log, run MIX of another seed")
+    train = mix_small(61, 5000)
+    with dtlib.Triangulation(log_points=True) as tri:
+        tri.insert(train)
+        f, c, b = dtlib.dt_get_point_log(tri.ctx)
+        assert f.shape == (len(train), 16) and np.isfinite(f).all()
+        # every point but the 4 of the initial tetrahedron took at least one attempt
+        assert (c < 1.0).sum() == 4 and c.mean() > 1.0
+        model = dtlib.dt_train_model(tri.ctx, f, c, b, epochs=4, seed=3)
+    xyz = mix_small(62, 7000)
+    with dtlib.Triangulation(scheduler=dtlib.DT_SCHED_LEARNED) as tri:
+        with pytest.raises(dtlib.DTError) as e:
+            tri.insert(xyz)
+        assert e.value.code == dtlib.DT_E_ARG
+    with dtlib.Triangulation(scheduler=dtlib.DT_SCHED_LEARNED) as tri:
+        dtlib.dt_load_model(tri.ctx, model)
+        tri.insert(xyz)
+        t, nb = tri.tets()
+        assert_parity(oracle_mod, xyz, t.astype(np.int64), "learned scheduler")
+        check_invariants(xyz, t.astype(np.int64), nb, oracle_mod, expect_vertices=None)
