@@ -86,7 +86,10 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per insertion (4, 8, 16, 64; 0: automatic)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick lanes per insertion, round fraction and cavity cap on a 2e6-point sample first")
-    ap.add_argument("--workload", choices=["uniform", "batch"], default="uniform")
+    ap.add_argument("--workload", choices=["uniform", "batch", "mix"], default="uniform")
+    ap.add_argument("--train-seeds", type=str, default="9001,9002", help="mix: seeds of the plain runs logged for training")
+    ap.add_argument("--train-samples", type=int, default=4_000_000, help="mix: samples drawn from the logs")
+    ap.add_argument("--mix-scale", type=float, default=1.0, help="mix: fraction of the 1e7 points")
     ap.add_argument("--clouds", type=int, default=4096, help="batch: number of clouds")
     ap.add_argument("--chunk", type=int, default=1024, help="batch: clouds per dt_insert_batch call")
     ap.add_argument("--loop-sample", type=int, default=64, help="batch: clouds timed one call each")
@@ -105,6 +108,9 @@ def main():
 
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "mix":
+        run_mix(args)
         return
 
     import numpy as np
@@ -233,6 +239,95 @@ def main():
     }
     print(json.dumps(line), flush=True)
     tri.close()
+
+
+def run_mix(args):
+    """MIX (4e6 lattice nodes + 3e6 points in 50 Gaussian clusters + 3e6 points near the
+    unit sphere, shuffled), plain against learned scheduler on the same GPU.  The model is
+    trained on the point logs of plain runs on other seeds (outside the timed region)."""
+    import numpy as np
+    import torch
+
+    from paper_1805_08831_amd import Triangulation, dt_get_point_log, dt_get_tets, dt_load_model, dt_train_model
+    from synth import mix_points
+
+    seed = args.seed if args.seed != 1007 else 2007
+    stream = torch.cuda.current_stream()
+    sc = args.mix_scale
+    counts = (int(4_000_000 * sc), int(3_000_000 * sc), int(3_000_000 * sc))
+
+    def progress(msg):
+        print(f"[mix] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
+    t_start = time.perf_counter()
+    t_train = time.perf_counter()
+    feats, costs, buckets = [], [], []
+    rng = np.random.default_rng(1)
+    seeds = [int(x) for x in args.train_seeds.split(",") if x]
+    with Triangulation(device=0, stream=stream.cuda_stream, log_points=True) as tri:
+        for s in seeds:
+            tri.clear()
+            pts = mix_points(s, *counts)
+            progress(f"training run, seed {s}: {len(pts)} points generated")
+            tri.insert(torch.from_numpy(pts).cuda())
+            progress(f"training run, seed {s}: triangulated, {tri.stats()['rounds']} rounds")
+            f, c, b = dt_get_point_log(tri.ctx)
+            keep = rng.choice(len(c), min(len(c), args.train_samples // max(len(seeds), 1)), replace=False)
+            feats.append(f[keep])
+            costs.append(c[keep])
+            buckets.append(b[keep])
+        model = dt_train_model(tri.ctx, np.concatenate(feats), np.concatenate(costs), np.concatenate(buckets),
+                               epochs=3, lr=1e-3, seed=1)
+    t_train = time.perf_counter() - t_train
+    progress("model trained")
+    d_xyz = torch.from_numpy(mix_points(seed, *counts)).cuda()
+    res = {}
+    for name, sched in (("plain", 0), ("learned", 1)):
+        tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True, scheduler=sched)
+        if sched:
+            dt_load_model(tri.ctx, model)
+        for _ in range(args.warmup):
+            tri.clear()
+            tri.insert(d_xyz)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        agg = dict(rounds=0, attempts=0, conflicts=0, overflows=0, perturbed=0, insphere_exact=0, orient_exact=0)
+        T = 0
+        for _ in range(args.steps):
+            tri.clear()
+            tri.insert(d_xyz)
+            T = dt_get_tets(tri.ctx)
+            st = tri.stats()
+            progress(f"{name}: step done, {T} tetrahedra, {st['rounds']} rounds")
+            for k in agg:
+                agg[k] += st[k]
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+        res[name] = {"value": round(T / (ms / 1000.0), 1), "ms_per_step": round(ms, 3), "tetrahedra": T,
+                     **{k: v / args.steps for k, v in agg.items()}}
+        tri.close()
+    line = {
+        "metric": "tetrahedra/sec (exact 3D Delaunay, MIX: lattice + clusters + shell)",
+        "value": res["plain"]["value"],
+        "unit": "tetrahedra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["plain"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"MIX {sum(counts)} ({counts[0]} nodes of the 160^3 lattice, {counts[1]} in 50 "
+                               f"clusters, {counts[2]} within 1e-4 of the unit sphere), seed {seed}",
+                   "scheduler": "plain"},
+        "learned": dict(res["learned"], same_count=res["learned"]["tetrahedra"] == res["plain"]["tetrahedra"],
+                        training={"seeds": seeds, "samples": int(sum(len(c) for c in costs)), "epochs": 3,
+                                  "seconds": round(t_train, 2)}),
+        "plain": res["plain"],
+    }
+    print(json.dumps(line), flush=True)
 
 
 def run_batch(args):

@@ -29,6 +29,7 @@ constexpr uint32_t DEFAULT_CAVITY_CAP = 128;
 constexpr uint32_t DEFAULT_LANES = 8;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t ROUND_MIN = 64;
+constexpr uint32_t DRAIN_SLICE = 1024;  // candidates per round when draining overflowed cavities
 
 uint64_t host_mix64(uint64_t z) {
     z += 0x9E3779B97F4A7C15ull;
@@ -376,6 +377,7 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.capC = capC;
     a.capF = capF;
     a.tcap = c->tcap;
+    a.hmg = 1u << (31 - __builtin_clz(std::min<uint32_t>(4u * std::min<uint32_t>(capC, 1u << 24), 1u << 30)));
     a.round_hi = (0xFFFFFFFFull - (c->round_counter & 0xFFFFFFFFull)) << 32;
     c->round_counter++;
     HIPCHK(launch_round(a, max_cand, c->lanes, c->stream, c->opt.timing ? c->ev : nullptr));
@@ -412,17 +414,21 @@ int ensure_capacity_for(dt_ctx *c, uint32_t max_cand, uint32_t capF) {
     return grow_tets(c, need + need / 8);
 }
 
-// Rounds for candidates whose cavities overflowed, in slices small enough that each
-// insertion gets at least `need` buffer entries; `need` grows while a pass over the list
-// inserts nothing.
+// Rounds for candidates whose cavities overflowed, in slices of the list in which each
+// insertion gets `need` buffer entries (first 1024, the wave-per-insertion kernel with its
+// queue in LDS, then the same kernel with queue and set in global memory); `need` grows
+// while a pass over the list inserts nothing.
 int drain_overflow(dt_ctx *c, uint64_t base, uint64_t n) {
-    size_t need = std::max<size_t>(4 * (size_t)c->capC, 512);
+    size_t need = std::max<size_t>(4 * (size_t)c->capC, 1024);
     while (c->hctr->list_count[2 + c->ovf_idx] > 0) {
         const int ci = 2 + c->ovf_idx, ni = 2 + (c->ovf_idx ^ 1);
         const uint32_t cnt = c->hctr->list_count[ci];
-        const uint32_t chunk = (uint32_t)std::max<size_t>(1, std::min<size_t>(cnt, c->bufC / need));
-        const uint32_t capC = (uint32_t)std::min<size_t>(c->bufC / chunk, 1u << 24);
-        const uint32_t capF = (uint32_t)std::min<size_t>(c->bufF / chunk, 1u << 24);
+        // large cavities overlap, so few of them win per round however many are tried:
+        // slices of at most DRAIN_SLICE keep the wasted attempts low
+        const uint32_t chunk =
+            (uint32_t)std::max<size_t>(1, std::min<size_t>(std::min<size_t>(cnt, DRAIN_SLICE), c->bufC / need));
+        const uint32_t capC = (uint32_t)std::min<size_t>(std::min(c->bufC / chunk, need), 1u << 24);
+        const uint32_t capF = (uint32_t)std::min<size_t>(std::min(c->bufF / chunk, 2 * need), 1u << 24);
         const uint32_t won0 = c->hctr->won;
         for (uint32_t off = 0; off < cnt; off += chunk) {
             const uint32_t k = std::min(chunk, cnt - off);
@@ -438,7 +444,7 @@ int drain_overflow(dt_ctx *c, uint64_t base, uint64_t n) {
         c->hctr->list_count[ci] = 0;
         c->ovf_idx ^= 1;
         if (c->hctr->won == won0) {
-            if (chunk == 1)  // the whole buffer did not hold one cavity
+            if (chunk == 1 && need >= c->bufC)  // the whole buffer did not hold one cavity
                 return fail(c, DT_E_CAPACITY, "a cavity exceeds the per-insertion buffer (%u tetrahedra)", capC);
             need *= 4;
         }

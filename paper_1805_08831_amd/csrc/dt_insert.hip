@@ -30,7 +30,6 @@
 namespace dtk {
 
 constexpr uint32_t WALK_LIMIT = 1u << 20;
-constexpr int HINT_RANGE = 4;
 
 __device__ __forceinline__ P3 vpos(const Vert *V, uint32_t v) {
     Vert r = V[v];
@@ -279,263 +278,78 @@ __device__ __forceinline__ bool tet_inside(const RoundArgs &a, uint32_t u, P3 P,
     return finite_inside(a.V, a.T[x].v, P, pidx, st);
 }
 
-__global__ __launch_bounds__(256) void k_cavity(RoundArgs a) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t ncand = *a.ncand_ptr;
-    const uint32_t stride = a.stride;
-    PredStats st;
-    unsigned steps = 0, attempt = 0;
-    if (i < ncand) {
-        attempt = 1;
-        uint8_t status = ST_NONE;
-        const uint32_t p = a.cand_pt[i];
-        const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
-        const Vert pv = a.V[p];
-        const P3 P = {pv.x, pv.y, pv.z};
-        // start: a live tetrahedron near the nearest inserted point among the HINT_RANGE
-        // records on either side on the curve (in the point's cloud), else near the point's
-        // anchor (a record of a lower level), else the cloud's known live tetrahedron
-        Cloud *cl = &a.clouds[pv.idx >> 32];
-        const uint32_t clo = cl->lo, chi = cl->hi;
-        uint32_t t = NONE;
-        for (int d = 1; d <= HINT_RANGE && t == NONE; ++d) {
-            if (p >= clo + d) t = a.vtet[p - d];
-            if (t == NONE && p + d < chi) t = a.vtet[p + d];
-        }
-        if (t == NONE) {
-            const uint32_t q = a.anchor[p - a.vlo];
-            if (q != NONE) t = a.vtet[q];
-        }
-        if (t == NONE) t = cl->any_live;
-        uint4 w = a.T[t].v;
-        if (w.x == DEAD) {
-            t = cl->any_live;
-            w = a.T[t].v;
-        }
-        if (w.w == GHOST) {
-            t = a.T[t].n.w >> 2;
-            w = a.T[t].v;
-        }
-        // Walk.  The current tetrahedron's vertex ids and positions are kept; after crossing
-        // a facet only the apex of the next tetrahedron is fetched.
-        int entry = -1;
-        bool in_ghost = false;
-        uint32_t id[4] = {w.x, w.y, w.z, w.w};
-        P3 q[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) q[k] = vpos(a.V, id[k]);
-        for (;;) {
-            const uint4 nn = a.T[t].n;
-            int moved = -1;
-            const int rot = (int)((p + steps) & 3u);
-            for (int jj = 0; jj < 4; ++jj) {
-                const int j = (jj + rot) & 3;
-                if (j == entry) continue;
-                int o;
-                if (j == 0) o = orient3d(P, q[1], q[2], q[3], st);
-                else if (j == 1) o = orient3d(q[0], P, q[2], q[3], st);
-                else if (j == 2) o = orient3d(q[0], q[1], P, q[3], st);
-                else o = orient3d(q[0], q[1], q[2], P, st);
-                if (o < 0) {
-                    moved = j;
-                    break;
-                }
-            }
-            if (moved < 0) break;
-            const uint32_t code = comp(nn, moved);
-            t = code >> 2;
-            entry = (int)(code & 3u);
-            w = a.T[t].v;
-            if (++steps > WALK_LIMIT) {
-                status = ST_ERROR;
-                break;
-            }
-            if (w.w == GHOST) {
-                in_ghost = true;
-                break;
-            }
-            const uint32_t id2[4] = {w.x, w.y, w.z, w.w};
-            P3 q2[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                q2[k] = q[0];
-#pragma unroll
-                for (int m = 1; m < 4; ++m)
-                    if (id[m] == id2[k]) q2[k] = q[m];
-            }
-            // the apex (opposite the entry facet) is the one new vertex
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (k == entry) q2[k] = vpos(a.V, id2[k]);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                id[k] = id2[k];
-                q[k] = q2[k];
-            }
-        }
-        if (status == ST_NONE && !in_ghost) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (q[k].x == P.x && q[k].y == P.y && q[k].z == P.z) status = ST_DUP;
-        }
-        uint32_t ncav = 0, nbnd = 0;
-        if (status == ST_NONE) {
-            // Cavity: breadth-first search; cav entries hold (tetrahedron << 2 | facet it was
-            // entered through), which is skipped when the tetrahedron is expanded.  Every
-            // neighbour examined is claimed with S + 1 first; the value returned says whether
-            // it is already in this cavity (S) or outside it (S + 1), or whether a lower
-            // attempt has it in its cavity (lower even value: this attempt loses).  A
-            // tetrahedron found inside is then claimed with S; a lower odd value on it means a
-            // lower attempt has it outside its cavity, and this attempt loses too.
-            {
-                const unsigned long long o0 = atomicMin(&a.T[t].claim, S);
-                if (o0 < S) {
-                    status = ST_CONFLICT;
-                } else {
-                    a.cav[(size_t)i * a.capC] = t << 2;
-                    ncav = 1;
-                }
-            }
-            for (uint32_t k = 0; k < ncav && status == ST_NONE; ++k) {
-                const uint32_t code = a.cav[(size_t)i * a.capC + k];
-                const uint32_t c = code >> 2;
-                const int pf = k == 0 ? -1 : (int)(code & 3u);
-                const uint4 cv = a.T[c].v;
-                const uint4 cn = a.T[c].n;
-                const bool cghost = cv.w == GHOST;
-                P3 cw[4];
-                if (!cghost) {
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) cw[m] = vpos(a.V, comp(cv, m));
-                }
-                for (int f = 0; f < 4 && status == ST_NONE; ++f) {
-                    if (f == pf) continue;
-                    const uint32_t ncode = comp(cn, f);
-                    const uint32_t u = ncode >> 2;
-                    const unsigned long long o = atomicMin(&a.T[u].claim, S + 1);
-                    if (o == S) continue;  // already in this cavity: internal facet
-                    if (o < S && !(o & 1ull)) {
-                        status = ST_CONFLICT;
-                        break;
-                    }
-                    bool inside = false;
-                    if (o != S + 1) {
-                        const uint4 uw = a.T[u].v;
-                        const uint32_t apex = comp(uw, (int)(ncode & 3u));
-                        if (!cghost && apex != GHOST) {
-                            // u = facet f of c + apex; c with vertex f replaced by the apex and
-                            // two entries swapped is positively oriented
-                            P3 r[4] = {cw[0], cw[1], cw[2], cw[3]};
-                            uint32_t rid[4] = {cv.x, cv.y, cv.z, cv.w};
-                            r[f] = vpos(a.V, apex);
-                            rid[f] = apex;
-                            const P3 tmp = r[(f + 1) & 3];
-                            r[(f + 1) & 3] = r[(f + 2) & 3];
-                            r[(f + 2) & 3] = tmp;
-                            const uint32_t tid = rid[(f + 1) & 3];
-                            rid[(f + 1) & 3] = rid[(f + 2) & 3];
-                            rid[(f + 2) & 3] = tid;
-                            inside = insphere_perturbed(r[0], r[1], r[2], r[3], P,
-                                                        [&](int kk) { return kk < 4 ? a.V[rid[kk]].idx : pv.idx; },
-                                                        st) < 0;
-                        } else if (!cghost) {
-                            // u is the ghost beyond facet f of the finite cavity tetrahedron c:
-                            // inside iff p is beyond the facet, or on it (then c decides: inside)
-                            P3 r[4] = {cw[0], cw[1], cw[2], cw[3]};
-                            r[f] = P;
-                            inside = orient3d(r[0], r[1], r[2], r[3], st) <= 0;
-                        } else {
-                            inside = tet_inside(a, u, P, pv.idx, st);
-                        }
-                        if (inside && o < S) {
-                            status = ST_CONFLICT;
-                            break;
-                        }
-                    }
-                    if (inside) {
-                        if (ncav == a.capC) {
-                            status = ST_OVERFLOW;
-                            break;
-                        }
-                        atomicMin(&a.T[u].claim, S);
-                        a.cav[(size_t)i * a.capC + ncav] = ncode;
-                        ++ncav;
-                    } else {
-                        if (nbnd == a.capF) {
-                            status = ST_OVERFLOW;
-                            break;
-                        }
-                        a.bnd[(size_t)i * a.capF + nbnd] = (k << 2) | (uint32_t)f;
-                        a.outc[(size_t)i * a.capF + nbnd] = ncode;
-                        ++nbnd;
-                    }
-                }
-            }
-            if (status == ST_NONE) status = ST_CAND;
-        }
-        a.status[i] = status;
-        a.cnt[i] = ncav;
-        a.cnt[stride + i] = nbnd;
-    }
-    add_stat(a.stat, STAT_ATTEMPTS, attempt);
-    add_stat(a.stat, STAT_WALK, steps);
-    add_stat(a.stat, STAT_ORIENT, st.orient);
-    add_stat(a.stat, STAT_ORIENT_EXACT, st.orient_exact);
-    add_stat(a.stat, STAT_INSPHERE, st.insphere);
-    add_stat(a.stat, STAT_INSPHERE_EXACT, st.insphere_exact);
-    add_stat(a.stat, STAT_PERTURBED, st.perturbed);
-}
+// ------------------------------------------------------------------ walk + cavity + claim
 
-// ------------------------------------------------------------------ check + DelaunayBall
-
-// ------------------------------------------------------------------ GS lanes per insertion
-
-constexpr uint32_t LCAPC = 128;  // cavity tetrahedra queued in LDS per insertion
-constexpr uint32_t HM = 256;     // LDS set of the attempt's own cavity and outer tetrahedra
+// Sizes of the cavity kernel's per-insertion state: a queue of CAPL cavity tetrahedra and a
+// set of HM entries holding the attempt's own cavity and outer tetrahedra.  Regular rounds
+// keep both in LDS at (128, 256) with 4 to 64 lanes per insertion; rounds for large
+// cavities use (1024, 2048) with 64 lanes, and beyond that the same 64-lane search keeps
+// both in global memory (the candidate's cavity buffer and its part of the ball scratch).
+constexpr uint32_t LCAPC = 128, LHM = 256;
+constexpr uint32_t BIG_CAPC = 1024, BIG_HM = 2048;
 constexpr uint32_t MEM_EMPTY = 0xFFFFFFFFu;
 
-__device__ __forceinline__ uint32_t mem_hash(uint32_t t) { return (t * 2654435761u) >> 24; }  // 8 bits
+// open addressing in a power-of-two table of hm entries, (t << 1 | kind) per entry
+__device__ __forceinline__ uint32_t mem_hash(uint32_t t, uint32_t hm) {
+    return (t * 2654435761u) >> (32 - __builtin_ctz(hm));
+}
 
-// kind of tetrahedron t in the set (0 cavity, 1 outer) or -1
-__device__ __forceinline__ int mem_find(const uint32_t *mem, uint32_t t) {
-    uint32_t h = mem_hash(t);
-    for (uint32_t probe = 0; probe < HM; ++probe) {
-        const uint32_t e = mem[h];
+// kind of tetrahedron t in the set (0 cavity, 1 outer) or -1; a set in global memory is
+// read at device scope, past any vector L1 copy, since other lanes fill it by atomics
+template <bool GLOBAL>
+__device__ __forceinline__ int mem_find(uint32_t *mem, uint32_t hm, uint32_t t) {
+    uint32_t h = mem_hash(t, hm);
+    for (uint32_t probe = 0; probe < hm; ++probe) {
+        const uint32_t e =
+            GLOBAL ? __hip_atomic_load(&mem[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : mem[h];
         if (e == MEM_EMPTY) return -1;
         if ((e >> 1) == t) return (int)(e & 1u);
-        h = (h + 1) & (HM - 1);
+        h = (h + 1) & (hm - 1);
     }
     return -1;
 }
 
 // adds t with `kind`: 1 if this call added it, 0 if it was there, -1 if the set is full
-__device__ __forceinline__ int mem_insert(uint32_t *mem, uint32_t t, uint32_t kind) {
-    uint32_t h = mem_hash(t);
+__device__ __forceinline__ int mem_insert(uint32_t *mem, uint32_t hm, uint32_t t, uint32_t kind) {
+    uint32_t h = mem_hash(t, hm);
     const uint32_t e = (t << 1) | kind;
-    for (uint32_t probe = 0; probe < HM; ++probe) {
+    for (uint32_t probe = 0; probe < hm; ++probe) {
         const uint32_t old = atomicCAS(&mem[h], MEM_EMPTY, e);
         if (old == MEM_EMPTY) return 1;
         if ((old >> 1) == t) return 0;
-        h = (h + 1) & (HM - 1);
+        h = (h + 1) & (hm - 1);
     }
     return -1;
 }
 
-// keeps the compiler from moving LDS accesses across a point where other lanes of the
-// same wave consume them (the hardware processes one wave's LDS requests in order)
-__device__ __forceinline__ void lane_fence() { __asm__ volatile("" ::: "memory"); }
+// Orders the accesses of one group (all in one wave) to its queue and set where other lanes
+// consume them: the hardware processes one wave's LDS requests in order, so LDS needs only a
+// compiler barrier; global memory also waits for the wave's outstanding accesses.
+template <bool GLOBAL>
+__device__ __forceinline__ void lane_fence() {
+    if (GLOBAL) __threadfence_block();
+    __asm__ volatile("" ::: "memory");
+}
 
-// Same computation as k_cavity, with GS lanes (4, 8, 16 or 64) cooperating on one
-// insertion: the walk tests the four facets of the current tetrahedron on four lanes at
-// once, and the cavity search expands GS / 4 cavity tetrahedra (four facets each) per step.
-// The cavity queue lives in LDS; cavity and boundary entries are appended by ballot prefix
-// counts.  Control flow is uniform within each group of GS lanes.
-template <int GS>
+// Walk (Sec. 2.3) and cavity search (Sec. 2.4) of one candidate per group of GS lanes
+// (4, 8, 16 or 64): the walk tests the four facets of the current tetrahedron on four lanes
+// at once, and the cavity search expands GS / 4 cavity tetrahedra (four facets each) per
+// step, appending cavity and boundary entries by ballot prefix counts.  Control flow is
+// uniform within each group.  Cavity entries hold (tetrahedron << 2 | facet it was entered
+// through), which is skipped when the tetrahedron is expanded.
+//
+// Claims: every neighbour examined for the first time is claimed with S + 1 (S is the
+// attempt's stamp: round, then rank); a lower even value returned means a lower attempt has
+// it in its cavity, and this attempt loses.  A tetrahedron found inside is then claimed with
+// S; a lower odd value on it means a lower attempt has it outside its cavity, and this
+// attempt loses too.  The attempt's own tetrahedra are tracked in the set, so each is
+// claimed and tested once.  GLOBAL keeps queue and set in global memory (any capC).
+template <int GS, uint32_t CAPL, uint32_t HM, bool GLOBAL>
 __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
     constexpr uint32_t GPB = 256 / GS;  // insertions per 256-thread block
     constexpr uint32_t NP = GS / 4;     // cavity tetrahedra expanded per step
-    __shared__ uint32_t s_cav[GPB][LCAPC];
-    __shared__ uint32_t s_mem[GPB][HM];
+    __shared__ uint32_t s_cav[GPB][GLOBAL ? 1 : CAPL];
+    __shared__ uint32_t s_mem[GPB][GLOBAL ? 1 : HM];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t gl = threadIdx.x & (GS - 1);
     const uint32_t gi = threadIdx.x / GS;
@@ -619,19 +433,19 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
             if (__ballot(same) & gmask) status = ST_DUP;
         }
         uint32_t ncav = 0, nbnd = 0;
-        const uint32_t capL = min(a.capC, LCAPC), capF = a.capF;
+        const uint32_t capL = GLOBAL ? a.capC : min(a.capC, CAPL), capF = a.capF;
         uint32_t *bnd = a.bnd + (size_t)i * a.capF;
         uint32_t *outc = a.outc + (size_t)i * a.capF;
-        uint32_t *mem = s_mem[gi];
+        uint32_t *cavq = GLOBAL ? a.cav + (size_t)i * a.capC : s_cav[gi];
+        // the set in global memory: hms (a power of two, at most 4 capC) words of the
+        // candidate's part of the ball scratch, which the ball kernel uses only later
+        const uint32_t hms = GLOBAL ? a.hmg : HM;
+        uint32_t *mem = GLOBAL ? reinterpret_cast<uint32_t *>(a.scr_v + (size_t)i * a.capC) : s_mem[gi];
         if (status == ST_NONE) {
             // Cavity.  Step k expands cavity tetrahedra k0 .. k0 + NP - 1, lane (slot, facet)
-            // = (gl / 4, gl % 4).  Claims as in k_cavity: S + 1 on a tetrahedron met for the
-            // first time (the returned value shows a lower cavity claim: this attempt loses),
-            // lowered to S once it is found inside (a lower odd value on it: loses too).  The
-            // attempt's own tetrahedra are tracked in the LDS set `mem`, so each is claimed
-            // and tested once.
-            for (uint32_t h = gl; h < HM; h += GS) mem[h] = MEM_EMPTY;
-            lane_fence();
+            // = (gl / 4, gl % 4).
+            for (uint32_t h = gl; h < hms; h += GS) mem[h] = MEM_EMPTY;
+            lane_fence<GLOBAL>();
             unsigned long long o0 = 0;
             if (gl == 0) o0 = atomicMin(&a.T[t].claim, S);
             o0 = __shfl(o0, (int)gbase);
@@ -639,18 +453,18 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 status = ST_CONFLICT;
             } else {
                 if (gl == 0) {
-                    s_cav[gi][0] = t << 2;
-                    mem_insert(mem, t, 0u);
+                    cavq[0] = t << 2;
+                    mem_insert(mem, hms, t, 0u);
                 }
                 ncav = 1;
             }
-            lane_fence();
+            lane_fence<GLOBAL>();
             for (uint32_t k0 = 0, nproc = 0; k0 < ncav && status == ST_NONE; k0 += nproc) {
                 nproc = min(NP, ncav - k0);  // entries expanded in this step
                 const uint32_t slot = k0 + (gl >> 2);
                 const int f = jl;
                 const bool lv = slot < k0 + nproc;
-                const uint32_t code = lv ? s_cav[gi][slot] : 0u;
+                const uint32_t code = lv ? cavq[slot] : 0u;
                 const uint32_t c = code >> 2;
                 const int pf = slot == 0 ? -1 : (int)(code & 3u);
                 const bool act = lv && f != pf;
@@ -661,7 +475,7 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 }
                 const uint32_t ncode = comp(cn, f);
                 const uint32_t u = ncode >> 2;
-                const int kind = act ? mem_find(mem, u) : -1;  // 0: in this cavity, 1: outside it
+                const int kind = act ? mem_find<GLOBAL>(mem, hms, u) : -1;  // 0: in this cavity, 1: outside it
                 const bool need = act && kind < 0;
                 unsigned long long o1 = ~0ull;
                 if (need) {
@@ -708,7 +522,7 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 // record u in the set; a tetrahedron reached through several facets in this
                 // step is queued (if inside) by the lane that records it
                 int ins = 0;
-                if (need) ins = mem_insert(mem, u, inside ? 0u : 1u);
+                if (need) ins = mem_insert(mem, hms, u, inside ? 0u : 1u);
                 const bool first_in = ins == 1 && inside;
                 const bool outside = (act && kind == 1) || (need && !inside);  // boundary facet (c, f)
                 const unsigned long long mi = __ballot(first_in) & gmask;
@@ -719,7 +533,7 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                     break;
                 }
                 if (first_in) {
-                    s_cav[gi][ncav + __popcll(mi & below)] = ncode;
+                    cavq[ncav + __popcll(mi & below)] = ncode;
                     atomicMin(&a.T[u].claim, S);
                 }
 
@@ -731,12 +545,12 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 }
                 ncav += ni;
                 nbnd += no;
-                lane_fence();
+                lane_fence<GLOBAL>();
             }
             if (status == ST_NONE) status = ST_CAND;
         }
-        if (status == ST_CAND)
-            for (uint32_t k = gl; k < ncav; k += GS) a.cav[(size_t)i * a.capC + k] = s_cav[gi][k];
+        if (!GLOBAL && status == ST_CAND)
+            for (uint32_t k = gl; k < ncav; k += GS) a.cav[(size_t)i * a.capC + k] = cavq[k];
         if (gl == 0) {
             a.status[i] = status;
             a.cnt[i] = ncav;
@@ -1095,18 +909,21 @@ __global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, const unsign
 hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, hipStream_t s, hipEvent_t *ev) {
     if (max_cand == 0) return hipSuccess;
     const unsigned nb = (max_cand + 255) / 256;
-    const bool grouped = a.capC <= LCAPC;
     if (ev) hipEventRecord(ev[0], s);
-    if (!grouped) {
-        k_cavity<<<nb, 256, 0, s>>>(a);
+    if (a.capC > BIG_CAPC) {
+        // the set takes hmg words of the candidate's 4 capC words of ball scratch
+        if (a.hmg < 4096 || (a.hmg & (a.hmg - 1)) || a.hmg > 4ull * a.capC) return hipErrorInvalidValue;
+        k_cavity_g<64, 1, 1, true><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
+    } else if (a.capC > LCAPC) {
+        k_cavity_g<64, BIG_CAPC, BIG_HM, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
     } else if (lanes == 4) {
-        k_cavity_g<4><<<(max_cand + 63) / 64, 256, 0, s>>>(a);
+        k_cavity_g<4, LCAPC, LHM, false><<<(max_cand + 63) / 64, 256, 0, s>>>(a);
     } else if (lanes == 8) {
-        k_cavity_g<8><<<(max_cand + 31) / 32, 256, 0, s>>>(a);
+        k_cavity_g<8, LCAPC, LHM, false><<<(max_cand + 31) / 32, 256, 0, s>>>(a);
     } else if (lanes == 64) {
-        k_cavity_g<64><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
+        k_cavity_g<64, LCAPC, LHM, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
     } else {
-        k_cavity_g<16><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
+        k_cavity_g<16, LCAPC, LHM, false><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
     }
     if (ev) hipEventRecord(ev[1], s);
     k_ball<16><<<(max_cand + 15) / 16, 256, 0, s>>>(a);

@@ -125,6 +125,7 @@ struct RoundArgs {
     Ctr *ctr;
     unsigned long long *stat;    // [NSTAT][STAT_SPREAD][STAT_PAD] work statistics
     uint32_t stride, capC, capF, tcap;
+    uint32_t hmg;                // capC > 1024: size of the cavity set in global memory
     unsigned long long round_hi;  // (0xFFFFFFFF - round) << 32: newer rounds claim lower
 };
 

@@ -227,7 +227,8 @@ def test_append_and_clear(dtlib, oracle_mod):
 @pytest.mark.parametrize("opts", [dict(cavity_cap=4), dict(cavity_cap=12), dict(round_size=64),
                                   dict(round_size=1 << 16), dict(round_fraction=2.0), dict(seed=99),
                                   dict(lanes_per_insert=4), dict(lanes_per_insert=16),
-                                  dict(lanes_per_insert=64), dict(lanes_per_insert=4, cavity_cap=200)])
+                                  dict(lanes_per_insert=64), dict(lanes_per_insert=4, cavity_cap=200),
+                                  dict(cavity_cap=2048), dict(lanes_per_insert=16, cavity_cap=1500)])
 def test_launch_options_do_not_change_result(dtlib, oracle_mod, opts):
     say(f"options {opts}")
     xyz = mix_small(51, 4000)
