@@ -111,8 +111,8 @@ struct dt_ctx {
 
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     dt_stats st{};
-    uint32_t trace_prev_won = 0;
-    unsigned long long trace_prev_att = 0, trace_prev_walk = 0;
+    uint32_t trace_prev_won = 0, trace_prev_conf = 0, trace_prev_ovf = 0;
+    unsigned long long trace_prev_att = 0, trace_prev_walk = 0, trace_prev_cav = 0, trace_prev_ins = 0;
     const uint32_t *lord = nullptr;  // level-major order of the current call's vertex records
     // clouds of the current call (one for dt_insert_points)
     uint32_t nclouds = 0;
@@ -389,18 +389,29 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     c->st.rounds++;
     if (c->trace) {
         uint32_t &prev_won = c->trace_prev_won;
-        if (prev_won > c->hctr->won) prev_won = 0, c->trace_prev_att = c->trace_prev_walk = 0;
+        if (prev_won > c->hctr->won) {
+            prev_won = c->trace_prev_conf = c->trace_prev_ovf = 0;
+            c->trace_prev_att = c->trace_prev_walk = c->trace_prev_cav = c->trace_prev_ins = 0;
+        }
         float a = 0.f, b = 0.f;
         if (c->opt.timing && max_cand) {
             hipEventElapsedTime(&a, c->ev[0], c->ev[1]);
             hipEventElapsedTime(&b, c->ev[1], c->ev[2]);
         }
-        fprintf(stderr, "round %llu cand<=%u won=%u tets=%u free=%u cavity_ms=%.3f ball_ms=%.3f att=%llu walk=%llu\n",
+        fprintf(stderr,
+                "round %llu cand<=%u won=%u tets=%u free=%u cavity_ms=%.3f ball_ms=%.3f att=%llu walk=%llu conf=%u "
+                "ovf=%u capC=%u cavw=%llu insph=%llu\n",
                 (unsigned long long)c->st.rounds, max_cand, c->hctr->won - prev_won, c->hctr->tet_count,
-                c->hctr->fl_n, a, b, c->hctr->attempts - c->trace_prev_att, c->hctr->walk_steps - c->trace_prev_walk);
+                c->hctr->fl_n, a, b, c->hctr->attempts - c->trace_prev_att, c->hctr->walk_steps - c->trace_prev_walk,
+                c->hctr->conflicts - c->trace_prev_conf, c->hctr->overflows - c->trace_prev_ovf, capC,
+                c->hctr->cav_tets - c->trace_prev_cav, c->hctr->insphere - c->trace_prev_ins);
         prev_won = c->hctr->won;
         c->trace_prev_att = c->hctr->attempts;
         c->trace_prev_walk = c->hctr->walk_steps;
+        c->trace_prev_conf = c->hctr->conflicts;
+        c->trace_prev_ovf = c->hctr->overflows;
+        c->trace_prev_cav = c->hctr->cav_tets;
+        c->trace_prev_ins = c->hctr->insphere;
     }
     return check_errors(c);
 }
@@ -417,19 +428,20 @@ int ensure_capacity_for(dt_ctx *c, uint32_t max_cand, uint32_t capF) {
 // Rounds for candidates whose cavities overflowed, in slices of the list in which each
 // insertion gets `need` buffer entries (first 1024, the wave-per-insertion kernel with its
 // queue in LDS, then the same kernel with queue and set in global memory); `need` grows
-// while a pass over the list inserts nothing.
+// after a pass over the list that inserts nothing or fewer points than overflow.  Large
+// cavities of nearby points overlap, so few of them win per round however many are tried:
+// a slice holds at most DRAIN_SLICE consecutive entries of the list (taking entries far
+// apart on the curve instead measured slower: more of them overflow or conflict).
 int drain_overflow(dt_ctx *c, uint64_t base, uint64_t n) {
     size_t need = std::max<size_t>(4 * (size_t)c->capC, 1024);
     while (c->hctr->list_count[2 + c->ovf_idx] > 0) {
         const int ci = 2 + c->ovf_idx, ni = 2 + (c->ovf_idx ^ 1);
         const uint32_t cnt = c->hctr->list_count[ci];
-        // large cavities overlap, so few of them win per round however many are tried:
-        // slices of at most DRAIN_SLICE keep the wasted attempts low
         const uint32_t chunk =
             (uint32_t)std::max<size_t>(1, std::min<size_t>(std::min<size_t>(cnt, DRAIN_SLICE), c->bufC / need));
         const uint32_t capC = (uint32_t)std::min<size_t>(std::min(c->bufC / chunk, need), 1u << 24);
         const uint32_t capF = (uint32_t)std::min<size_t>(std::min(c->bufF / chunk, 2 * need), 1u << 24);
-        const uint32_t won0 = c->hctr->won;
+        const uint32_t won0 = c->hctr->won, ovf0 = c->hctr->overflows;
         for (uint32_t off = 0; off < cnt; off += chunk) {
             const uint32_t k = std::min(chunk, cnt - off);
             int rc = ensure_capacity_for(c, k, capF);
@@ -446,6 +458,10 @@ int drain_overflow(dt_ctx *c, uint64_t base, uint64_t n) {
         if (c->hctr->won == won0) {
             if (chunk == 1 && need >= c->bufC)  // the whole buffer did not hold one cavity
                 return fail(c, DT_E_CAPACITY, "a cavity exceeds the per-insertion buffer (%u tetrahedra)", capC);
+            need *= 4;
+        } else if (c->hctr->overflows - ovf0 >= c->hctr->won - won0 && need < c->bufC) {
+            // more overflows than insertions: retrying them at this size wastes rounds, and
+            // their claims block the neighbouring candidates
             need *= 4;
         }
     }

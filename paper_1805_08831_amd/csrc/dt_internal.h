@@ -66,10 +66,10 @@ struct Ctr {
                          // unit u >= fl_n is pool slot tet_count + (u - fl_n)
     uint32_t fl_next;    // slots freed this round
     uint32_t tet_count;  // bump pointer of the tetrahedron pool
-    uint32_t won;        // insertions this round
-    uint32_t conflicts;  // conflicts this round
-    uint32_t overflows;  // overflows this round
-    uint32_t dups;       // duplicates found this round
+    uint32_t won;        // insertions so far (this and the other counters below: since the
+    uint32_t conflicts;  // last clear), conflicts,
+    uint32_t overflows;  // cavity buffer overflows,
+    uint32_t dups;       // duplicates found
     uint32_t error;      // ERR_* flags
     uint32_t init[4];    // sorted positions of the initial tetrahedron's vertices
     uint32_t bad_cloud;  // first cloud found degenerate by the initial-tetrahedron search

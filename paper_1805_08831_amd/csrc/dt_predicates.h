@@ -17,7 +17,15 @@
 // stays a multiple of 2^(-172 k) at degree k <= 5, far above the underflow threshold, and
 // far below overflow.
 //
-// Stage 2 (when the filter cannot decide): the coordinates are scaled by a common power
+// Stage 2a (when the filter cannot decide): the same fp64 evaluation is repeated with an
+// exactness certificate.  The rounding error of each product p = fl(x y) is fma(x, y, -p),
+// and that of each sum or difference is the remainder of Knuth's TwoSum; both are computed
+// without rounding.  If every one is zero, no operation rounded and the fp64 value is the
+// exact determinant, zero included.  This decides the degenerate configurations of inputs
+// with few significant bits (points of a lattice with a power-of-two spacing) without the
+// integer stage.  The input range above keeps every intermediate out of the subnormals.
+//
+// Stage 2b (when the certificate fails): the coordinates are scaled by a common power
 // of two into exact integers and the same determinant is evaluated in two's-complement
 // multi-limb integers modulo 2^(32 W).  W is chosen from the exponent spread of the call
 // so that every true intermediate value fits; the result is then exact.  This replaces
@@ -234,6 +242,75 @@ __device__ __noinline__ bool collinear_exact(P3 a, P3 b, P3 c) {
     return true;
 }
 
+// ------------------------------------------------------------------ certified fp64
+
+// a - b, clearing ok unless it is exact (TwoSum remainder zero)
+__device__ __forceinline__ double c_sub(double a, double b, bool &ok) {
+    const double x = a - b;
+    const double bv = a - x;
+    const double av = x + bv;
+    const double r = (a - av) + (bv - b);
+    ok = ok && r == 0.0;
+    return x;
+}
+
+__device__ __forceinline__ double c_add(double a, double b, bool &ok) {
+    const double x = a + b;
+    const double bv = x - a;
+    const double av = x - bv;
+    const double r = (a - av) + (b - bv);
+    ok = ok && r == 0.0;
+    return x;
+}
+
+__device__ __forceinline__ double c_mul(double a, double b, bool &ok) {
+    const double p = a * b;
+    ok = ok && fma(a, b, -p) == 0.0;
+    return p;
+}
+
+// sign of orient3d if the fp64 evaluation is certified exact, else 2
+__device__ __noinline__ int orient3d_cert(P3 a, P3 b, P3 c, P3 d) {
+    bool ok = true;
+    const double ux = c_sub(b.x, a.x, ok), uy = c_sub(b.y, a.y, ok), uz = c_sub(b.z, a.z, ok);
+    const double vx = c_sub(c.x, a.x, ok), vy = c_sub(c.y, a.y, ok), vz = c_sub(c.z, a.z, ok);
+    const double wx = c_sub(d.x, a.x, ok), wy = c_sub(d.y, a.y, ok), wz = c_sub(d.z, a.z, ok);
+    const double m0 = c_sub(c_mul(vy, wz, ok), c_mul(vz, wy, ok), ok);
+    const double m1 = c_sub(c_mul(vz, wx, ok), c_mul(vx, wz, ok), ok);
+    const double m2 = c_sub(c_mul(vx, wy, ok), c_mul(vy, wx, ok), ok);
+    const double det = c_add(c_add(c_mul(ux, m0, ok), c_mul(uy, m1, ok), ok), c_mul(uz, m2, ok), ok);
+    if (!ok) return 2;
+    return det > 0.0 ? 1 : (det < 0.0 ? -1 : 0);
+}
+
+// sign of the unperturbed lifted determinant (translated form) if certified exact, else 2
+__device__ __noinline__ int insphere_cert(P3 a, P3 b, P3 c, P3 d, P3 e) {
+    bool ok = true;
+    const double ax = c_sub(a.x, e.x, ok), ay = c_sub(a.y, e.y, ok), az = c_sub(a.z, e.z, ok);
+    const double bx = c_sub(b.x, e.x, ok), by = c_sub(b.y, e.y, ok), bz = c_sub(b.z, e.z, ok);
+    const double cx = c_sub(c.x, e.x, ok), cy = c_sub(c.y, e.y, ok), cz = c_sub(c.z, e.z, ok);
+    const double dx = c_sub(d.x, e.x, ok), dy = c_sub(d.y, e.y, ok), dz = c_sub(d.z, e.z, ok);
+    if (!ok) return 2;
+    const double ab = c_sub(c_mul(ax, by, ok), c_mul(bx, ay, ok), ok);
+    const double ac = c_sub(c_mul(ax, cy, ok), c_mul(cx, ay, ok), ok);
+    const double ad = c_sub(c_mul(ax, dy, ok), c_mul(dx, ay, ok), ok);
+    const double bc = c_sub(c_mul(bx, cy, ok), c_mul(cx, by, ok), ok);
+    const double bd = c_sub(c_mul(bx, dy, ok), c_mul(dx, by, ok), ok);
+    const double cd = c_sub(c_mul(cx, dy, ok), c_mul(dx, cy, ok), ok);
+    const double abc = c_add(c_sub(c_mul(az, bc, ok), c_mul(bz, ac, ok), ok), c_mul(cz, ab, ok), ok);
+    const double abd = c_add(c_sub(c_mul(az, bd, ok), c_mul(bz, ad, ok), ok), c_mul(dz, ab, ok), ok);
+    const double acd = c_add(c_sub(c_mul(az, cd, ok), c_mul(cz, ad, ok), ok), c_mul(dz, ac, ok), ok);
+    const double bcd = c_add(c_sub(c_mul(bz, cd, ok), c_mul(cz, bd, ok), ok), c_mul(dz, bc, ok), ok);
+    const double la = c_add(c_add(c_mul(ax, ax, ok), c_mul(ay, ay, ok), ok), c_mul(az, az, ok), ok);
+    const double lb = c_add(c_add(c_mul(bx, bx, ok), c_mul(by, by, ok), ok), c_mul(bz, bz, ok), ok);
+    const double lc = c_add(c_add(c_mul(cx, cx, ok), c_mul(cy, cy, ok), ok), c_mul(cz, cz, ok), ok);
+    const double ld = c_add(c_add(c_mul(dx, dx, ok), c_mul(dy, dy, ok), ok), c_mul(dz, dz, ok), ok);
+    const double det = c_add(c_sub(c_mul(ld, abc, ok), c_mul(lc, abd, ok), ok),
+                             c_sub(c_mul(lb, acd, ok), c_mul(la, bcd, ok), ok), ok);
+    if (!ok) return 2;
+    return det > 0.0 ? 1 : (det < 0.0 ? -1 : 0);
+}
+
 // ------------------------------------------------------------------ filtered predicates
 
 // sign of orient3d, or 2 when the fp64 filter cannot decide
@@ -256,6 +333,8 @@ __device__ __forceinline__ int orient3d(P3 a, P3 b, P3 c, P3 d, PredStats &st) {
     int s = orient3d_filter(a, b, c, d);
     if (s != 2) return s;
     st.orient_exact++;
+    s = orient3d_cert(a, b, c, d);
+    if (s != 2) return s;
     return orient3d_exact(a, b, c, d);
 }
 
@@ -294,6 +373,8 @@ __device__ __forceinline__ int insphere_raw(P3 a, P3 b, P3 c, P3 d, P3 e, PredSt
     int s = insphere_filter(a, b, c, d, e);
     if (s != 2) return s;
     st.insphere_exact++;
+    s = insphere_cert(a, b, c, d, e);
+    if (s != 2) return s;
     return insphere_exact(a, b, c, d, e);
 }
 
