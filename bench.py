@@ -87,8 +87,10 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick lanes per insertion, round fraction and cavity cap on a 2e6-point sample first")
     ap.add_argument("--workload", choices=["uniform", "batch", "mix"], default="uniform")
-    ap.add_argument("--train-seeds", type=str, default="9001,9002", help="mix: seeds of the plain runs logged for training")
-    ap.add_argument("--train-samples", type=int, default=4_000_000, help="mix: samples drawn from the logs")
+    ap.add_argument("--no-learned", action="store_true", help="uniform: skip the learned-scheduler comparison")
+    ap.add_argument("--train-seeds", type=str, default="9001,9002", help="seeds of the plain runs logged for training")
+    ap.add_argument("--train-samples", type=int, default=4_000_000, help="samples drawn from the logs")
+    ap.add_argument("--train-n", type=int, default=0, help="uniform: points per training run (0: min(n, 1e7))")
     ap.add_argument("--mix-scale", type=float, default=1.0, help="mix: fraction of the 1e7 points")
     ap.add_argument("--clouds", type=int, default=4096, help="batch: number of clouds")
     ap.add_argument("--chunk", type=int, default=1024, help="batch: clouds per dt_insert_batch call")
@@ -198,6 +200,23 @@ def main():
                 "bytes_per_attempt": round(b_unit, 1), "attempts_per_launch": round(agg["attempts"] / launches, 1),
                 "avg_launch_ms": round(avg_launch_ms, 4)}
 
+    learned = None
+    if not args.no_learned:
+        # the learned scheduler on the same input, trained on plain runs of other seeds
+        t_l = time.perf_counter()
+
+        def progress(msg):
+            print(f"[learned] {msg} ({time.perf_counter() - t_l:.1f} s)", file=sys.stderr, flush=True)
+
+        tn = args.train_n or min(args.n, 10_000_000)
+        seeds = [int(x) for x in args.train_seeds.split(",") if x]
+        model, training = train_scheduler(lambda s: uniform_points(tn, s), seeds, args.train_samples, progress)
+        # both schedulers timed the same way (insertion and tetrahedron count, no export)
+        res = {name: timed_runs(d_xyz, sched, model, args.steps, args.warmup, progress, name)
+               for name, sched in (("plain", 0), ("learned", 1))}
+        learned = dict(res["learned"], same_count=res["learned"]["tetrahedra"] == T,
+                       training=dict(training, points_per_run=tn), plain=res["plain"])
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -228,6 +247,7 @@ def main():
         "roofline": roofline if lanes == 8 and not args.round_fraction and not args.round_size else
         dict(roofline, traffic=None),
         "cpu_baseline": cpu,
+        "learned": learned,
         "detail": {"rounds_per_step": agg["rounds"] / args.steps, "attempts_per_point": agg["attempts"] / max(args.n * args.steps, 1),
                    "conflict_rate": agg["conflicts"] / att, "walk_steps_per_attempt": round(walk, 3),
                    "cavity_tets": round(C, 2), "boundary_facets": round(F, 2),
@@ -241,71 +261,92 @@ def main():
     tri.close()
 
 
-def run_mix(args):
-    """MIX (4e6 lattice nodes + 3e6 points in 50 Gaussian clusters + 3e6 points near the
-    unit sphere, shuffled), plain against learned scheduler on the same GPU.  The model is
-    trained on the point logs of plain runs on other seeds (outside the timed region)."""
+def train_scheduler(gen, seeds, samples, progress):
+    """Plain runs with point logs on the training seeds (other seeds than the timed input),
+    then the MLP trained on a random sample of the logged points.  Returns (model, info)."""
     import numpy as np
     import torch
 
-    from paper_1805_08831_amd import Triangulation, dt_get_point_log, dt_get_tets, dt_load_model, dt_train_model
-    from synth import mix_points
+    from paper_1805_08831_amd import Triangulation, dt_get_point_log, dt_train_model
 
-    seed = args.seed if args.seed != 1007 else 2007
+    t0 = time.perf_counter()
     stream = torch.cuda.current_stream()
-    sc = args.mix_scale
-    counts = (int(4_000_000 * sc), int(3_000_000 * sc), int(3_000_000 * sc))
-
-    def progress(msg):
-        print(f"[mix] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
-
-    t_start = time.perf_counter()
-    t_train = time.perf_counter()
     feats, costs, buckets = [], [], []
     rng = np.random.default_rng(1)
-    seeds = [int(x) for x in args.train_seeds.split(",") if x]
     with Triangulation(device=0, stream=stream.cuda_stream, log_points=True) as tri:
         for s in seeds:
             tri.clear()
-            pts = mix_points(s, *counts)
+            pts = gen(s)
             progress(f"training run, seed {s}: {len(pts)} points generated")
             tri.insert(torch.from_numpy(pts).cuda())
             progress(f"training run, seed {s}: triangulated, {tri.stats()['rounds']} rounds")
             f, c, b = dt_get_point_log(tri.ctx)
-            keep = rng.choice(len(c), min(len(c), args.train_samples // max(len(seeds), 1)), replace=False)
+            keep = rng.choice(len(c), min(len(c), samples // max(len(seeds), 1)), replace=False)
             feats.append(f[keep])
             costs.append(c[keep])
             buckets.append(b[keep])
         model = dt_train_model(tri.ctx, np.concatenate(feats), np.concatenate(costs), np.concatenate(buckets),
                                epochs=3, lr=1e-3, seed=1)
-    t_train = time.perf_counter() - t_train
+    info = {"seeds": list(seeds), "samples": int(sum(len(c) for c in costs)), "epochs": 3,
+            "seconds": round(time.perf_counter() - t0, 2)}
     progress("model trained")
+    return model, info
+
+
+def timed_runs(d_xyz, sched, model, steps, warmup, progress, name):
+    """`steps` timed triangulations of d_xyz with the given scheduler; per-step means."""
+    import torch
+
+    from paper_1805_08831_amd import Triangulation, dt_get_tets, dt_load_model
+
+    stream = torch.cuda.current_stream()
+    tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True, scheduler=sched)
+    if sched:
+        dt_load_model(tri.ctx, model)
+    for _ in range(warmup):
+        tri.clear()
+        tri.insert(d_xyz)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg = dict(rounds=0, attempts=0, conflicts=0, overflows=0, walk_steps=0, perturbed=0, insphere_exact=0,
+               orient_exact=0)
+    T = 0
+    for _ in range(steps):
+        tri.clear()
+        tri.insert(d_xyz)
+        T = dt_get_tets(tri.ctx)
+        st = tri.stats()
+        progress(f"{name}: step done, {T} tetrahedra, {st['rounds']} rounds")
+        for k in agg:
+            agg[k] += st[k]
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    tri.close()
+    return {"value": round(T / (ms / 1000.0), 1), "ms_per_step": round(ms, 3), "tetrahedra": T,
+            **{k: v / steps for k, v in agg.items()}}
+
+
+def run_mix(args):
+    """MIX (4e6 lattice nodes + 3e6 points in 50 Gaussian clusters + 3e6 points near the
+    unit sphere, shuffled), plain against learned scheduler on the same GPU.  The model is
+    trained on the point logs of plain runs on other seeds (outside the timed region)."""
+    import torch
+
+    from synth import mix_points
+
+    seed = args.seed if args.seed != 1007 else 2007
+    sc = args.mix_scale
+    counts = (int(4_000_000 * sc), int(3_000_000 * sc), int(3_000_000 * sc))
+    t_start = time.perf_counter()
+
+    def progress(msg):
+        print(f"[mix] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
+    seeds = [int(x) for x in args.train_seeds.split(",") if x]
+    model, training = train_scheduler(lambda s: mix_points(s, *counts), seeds, args.train_samples, progress)
     d_xyz = torch.from_numpy(mix_points(seed, *counts)).cuda()
-    res = {}
-    for name, sched in (("plain", 0), ("learned", 1)):
-        tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True, scheduler=sched)
-        if sched:
-            dt_load_model(tri.ctx, model)
-        for _ in range(args.warmup):
-            tri.clear()
-            tri.insert(d_xyz)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        agg = dict(rounds=0, attempts=0, conflicts=0, overflows=0, perturbed=0, insphere_exact=0, orient_exact=0)
-        T = 0
-        for _ in range(args.steps):
-            tri.clear()
-            tri.insert(d_xyz)
-            T = dt_get_tets(tri.ctx)
-            st = tri.stats()
-            progress(f"{name}: step done, {T} tetrahedra, {st['rounds']} rounds")
-            for k in agg:
-                agg[k] += st[k]
-        torch.cuda.synchronize()
-        ms = 1000.0 * (time.perf_counter() - t0) / args.steps
-        res[name] = {"value": round(T / (ms / 1000.0), 1), "ms_per_step": round(ms, 3), "tetrahedra": T,
-                     **{k: v / args.steps for k, v in agg.items()}}
-        tri.close()
+    res = {name: timed_runs(d_xyz, sched, model, args.steps, args.warmup, progress, name)
+           for name, sched in (("plain", 0), ("learned", 1))}
     line = {
         "metric": "tetrahedra/sec (exact 3D Delaunay, MIX: lattice + clusters + shell)",
         "value": res["plain"]["value"],
@@ -323,8 +364,7 @@ def run_mix(args):
                                f"clusters, {counts[2]} within 1e-4 of the unit sphere), seed {seed}",
                    "scheduler": "plain"},
         "learned": dict(res["learned"], same_count=res["learned"]["tetrahedra"] == res["plain"]["tetrahedra"],
-                        training={"seeds": seeds, "samples": int(sum(len(c) for c in costs)), "epochs": 3,
-                                  "seconds": round(t_train, 2)}),
+                        training=training),
         "plain": res["plain"],
     }
     print(json.dumps(line), flush=True)

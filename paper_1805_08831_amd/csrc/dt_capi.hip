@@ -29,7 +29,7 @@ constexpr uint32_t DEFAULT_CAVITY_CAP = 128;
 constexpr uint32_t DEFAULT_LANES = 8;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t ROUND_MIN = 64;
-constexpr uint32_t DRAIN_SLICE = 1024;  // candidates per round when draining overflowed cavities
+constexpr uint32_t DRAIN_SLICE = 4096;  // candidates per round when draining overflowed cavities
 
 uint64_t host_mix64(uint64_t z) {
     z += 0x9E3779B97F4A7C15ull;
@@ -776,7 +776,8 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
         L *= 2;
         compute_levels(hist, L, lv);
         if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
-        HIPCHK(launch_anchor(c->lord, d_start, L, c->V.p, base, n, c->anchor.p, c->stream));
+        // anchors stay those of the BRIO levels: a half level is a sparse and, by the cost
+        // prediction, uneven subset, and its records make far walk starts
     }
     c->logged = c->opt.log_points != 0;
     if (c->logged) {
@@ -1109,8 +1110,8 @@ int dt_get_point_log(dt_ctx *c, float *features, float *cost, uint8_t *bucket, u
         L = std::max(L, (int)brio_cum(c->h_off[k + 1] - c->h_off[k]).size());
     HIPCHK(launch_features(c->V.p, c->log_base, n, c->clouds.p, c->anchor.p, c->lev.p, L, c->feat.p, c->stream));
     // labels: cost in ypred (stride 1), bucket in wbucket
-    HIPCHK(launch_labels(c->V.p, c->log_base, n, c->clouds.p, c->anchor.p, c->log_att.p, c->ypred.p, c->wbucket.p,
-                         c->stream));
+    HIPCHK(launch_labels(c->V.p, c->log_base, n, c->clouds.p, c->anchor.p, c->lev.p, c->log_att.p, c->ypred.p,
+                         c->wbucket.p, c->stream));
     if (features)
         HIPCHK(hipMemcpyAsync(features, c->feat.p, n * NFEAT * sizeof(float), hipMemcpyDefault, c->stream));
     if (cost) HIPCHK(hipMemcpyAsync(cost, c->ypred.p, n * sizeof(float), hipMemcpyDefault, c->stream));

@@ -369,22 +369,21 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
         const P3 P = {pv.x, pv.y, pv.z};
         // start: near the nearest inserted point among GS / 2 records on either side of p on
         // the curve (in p's cloud), one probe per lane; else near the point's anchor (a
-        // record of a lower level); else the cloud's known live tetrahedron
+        // record of a lower level); else the cloud's known live tetrahedron.  A record's
+        // hint is a tetrahedron incident to it: the ball kernel renews the hints of all
+        // vertices of the tetrahedra it builds, which include every vertex of a removed one.
+        Cloud *cl = &a.clouds[pv.idx >> 32];
+        const uint32_t clo = cl->lo, chi = cl->hi;
         const uint32_t d = (gl >> 1) + 1;
         const uint32_t hp = (gl & 1) ? p + d : p - d;
         const bool inr = (gl & 1) ? (p + d < a.vhi) : (p >= a.vlo + d);
-        uint32_t ht = inr ? a.vtet[hp] : NONE;
+        const uint32_t ht = inr && hp >= clo && hp < chi ? a.vtet[hp] : NONE;
         const uint32_t q = a.anchor[p - a.vlo];
-        Cloud *cl = &a.clouds[pv.idx >> 32];
-        const uint32_t clo = cl->lo, chi = cl->hi;
-        if (hp < clo || hp >= chi) ht = NONE;
+        const uint32_t tq = q != NONE ? a.vtet[q] : NONE;
         const unsigned long long hm = __ballot(ht != NONE) & gmask;
-        uint32_t t = hm ? __shfl(ht, __ffsll((long long)hm) - 1) : (q != NONE ? a.vtet[q] : NONE);
-        if (a.wbucket && q != NONE && a.wbucket[p - a.vlo]) {
-            // the learned scheduler predicts the anchor to be the closer start
-            const uint32_t tq = a.vtet[q];
-            if (tq != NONE) t = tq;
-        }
+        uint32_t t = hm ? __shfl(ht, __ffsll((long long)hm) - 1) : tq;
+        // the learned scheduler predicts the anchor to be the closer start
+        if (a.wbucket && tq != NONE && a.wbucket[p - a.vlo]) t = tq;
         if (t == NONE) t = cl->any_live;
         uint4 w = a.T[t].v;
         if (w.x == DEAD) {

@@ -193,7 +193,8 @@ hipError_t launch_adam(float *w, float *grad, float *m1, float *m2, uint16_t *wb
 hipError_t launch_learned_keys(const float *y, const uint8_t *level, uint64_t n, uint64_t base, float thr,
                                unsigned long long *keys, uint32_t *vals, uint8_t *wbucket, hipStream_t s);
 hipError_t launch_labels(const Vert *V, uint64_t base, uint64_t n, const Cloud *clouds, const uint32_t *anchor,
-                         const uint32_t *attempts, float *cost, uint8_t *bucket, hipStream_t s);
+                         const uint8_t *level, const uint32_t *attempts, float *cost, uint8_t *bucket,
+                         hipStream_t s);
 
 // ---- launch wrappers (dt_insert.hip) ----
 // initial tetrahedron and four ghosts of each cloud c at slots 5 c0 + 5 c .. + 4 (c0: first)

@@ -259,10 +259,13 @@ hipError_t launch_learned_keys(const float *y, const uint8_t *level, uint64_t n,
 }
 
 // training labels of the records of a finished plain run: log2(1 + attempts), and bucket 1
-// when the anchor is closer to the point than both curve neighbours
+// when the anchor is closer to the point than each record within 4 places on the curve that
+// belongs to a lower BRIO level (the neighbours that are sure to be inserted before the
+// point, hence walk starts the default rule may take); 0 when there is no such record
 __global__ void k_labels(const Vert *__restrict__ V, uint64_t base, uint64_t n, const Cloud *__restrict__ clouds,
-                         const uint32_t *__restrict__ anchor, const uint32_t *__restrict__ attempts,
-                         float *__restrict__ cost, uint8_t *__restrict__ bucket) {
+                         const uint32_t *__restrict__ anchor, const uint8_t *__restrict__ level,
+                         const uint32_t *__restrict__ attempts, float *__restrict__ cost,
+                         uint8_t *__restrict__ bucket) {
     const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t p = (uint32_t)(base + i);
@@ -272,18 +275,21 @@ __global__ void k_labels(const Vert *__restrict__ V, uint64_t base, uint64_t n, 
     const uint32_t q = anchor[i];
     uint8_t b = 0;
     if (q != NONE) {
-        const float da = ldist(a, V, q, true, 1.0);
-        const float dn = fminf(p + 1 < cl.hi ? ldist(a, V, p + 1, true, 1.0) : 1e30f,
-                               p > cl.lo ? ldist(a, V, p - 1, true, 1.0) : 1e30f);
-        b = da < dn ? 1 : 0;
+        float dn = 1e30f;
+        for (uint32_t d = 1; d <= 4; ++d) {
+            if (p + d < cl.hi && level[i + d] < level[i]) dn = fminf(dn, ldist(a, V, p + d, true, 1.0));
+            if (p >= cl.lo + d && level[i - d] < level[i]) dn = fminf(dn, ldist(a, V, p - d, true, 1.0));
+        }
+        b = dn < 1e30f && ldist(a, V, q, true, 1.0) < dn ? 1 : 0;
     }
     bucket[i] = b;
 }
 
 hipError_t launch_labels(const Vert *V, uint64_t base, uint64_t n, const Cloud *clouds, const uint32_t *anchor,
-                         const uint32_t *attempts, float *cost, uint8_t *bucket, hipStream_t s) {
+                         const uint8_t *level, const uint32_t *attempts, float *cost, uint8_t *bucket,
+                         hipStream_t s) {
     if (n == 0) return hipSuccess;
-    k_labels<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V, base, n, clouds, anchor, attempts, cost, bucket);
+    k_labels<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V, base, n, clouds, anchor, level, attempts, cost, bucket);
     return hipGetLastError();
 }
 
