@@ -106,7 +106,7 @@ struct dt_ctx {
     DevBuf<uint32_t> vals, vals_tmp, hist, scan_tmp, small;
     DevBuf<uint64_t> small64;
     // output scratch
-    DevBuf<uint32_t> oflags, omap, otets;
+    DevBuf<uint32_t> oflags, omap, otets, ovid;
     DevBuf<int64_t> onbrs;
 
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -923,7 +923,10 @@ int dt_get_tets(dt_ctx *c, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets) {
         return fail(c, DT_E_ARG, "output buffers hold %llu tetrahedra, %u needed", (unsigned long long)*num_tets, T);
     }
     *num_tets = T;
-    const bool dev_t = tets && is_device_ptr(tets), dev_n = nbrs && is_device_ptr(nbrs);
+    // the export kernel stores 16-byte vectors: device buffers that are not 16-byte aligned
+    // are filled through the staging buffers, like host buffers
+    const bool dev_t = tets && is_device_ptr(tets) && ((uintptr_t)tets & 15u) == 0,
+               dev_n = nbrs && is_device_ptr(nbrs) && ((uintptr_t)nbrs & 15u) == 0;
     uint32_t *ot = tets;
     int64_t *on = nbrs;
     if (tets && !dev_t) {
@@ -934,11 +937,13 @@ int dt_get_tets(dt_ctx *c, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets) {
         if ((rc = ensure(c, c->onbrs, 4 * (size_t)T + 4))) return rc;
         on = c->onbrs.p;
     }
-    HIPCHK(launch_output(c->T, c->V.p, c->omap.p, count, ot, on, c->stream));
+    if ((rc = ensure(c, c->ovid, std::max<uint64_t>(c->nv, 1)))) return rc;
+    HIPCHK(launch_output(c->T, c->V.p, (uint32_t)c->nv, c->oflags.p, c->omap.p, c->ovid.p, count, ot, on,
+                         c->stream));
     if (tets && !dev_t)
-        HIPCHK(hipMemcpyAsync(tets, ot, 4 * (size_t)T * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(tets, ot, 4 * (size_t)T * sizeof(uint32_t), hipMemcpyDefault, c->stream));
     if (nbrs && !dev_n)
-        HIPCHK(hipMemcpyAsync(nbrs, on, 4 * (size_t)T * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(nbrs, on, 4 * (size_t)T * sizeof(int64_t), hipMemcpyDefault, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return DT_OK;
 }
@@ -995,7 +1000,10 @@ int dt_get_tets_batch(dt_ctx *c, uint32_t cloud, uint32_t *tets, int64_t *nbrs, 
                     (unsigned long long)T);
     }
     *num_tets = T;
-    const bool dev_t = tets && is_device_ptr(tets), dev_n = nbrs && is_device_ptr(nbrs);
+    // the export kernel stores 16-byte vectors: device buffers that are not 16-byte aligned
+    // are filled through the staging buffers, like host buffers
+    const bool dev_t = tets && is_device_ptr(tets) && ((uintptr_t)tets & 15u) == 0,
+               dev_n = nbrs && is_device_ptr(nbrs) && ((uintptr_t)nbrs & 15u) == 0;
     uint32_t *ot = tets;
     int64_t *on = nbrs;
     if (tets && !dev_t) {
@@ -1301,7 +1309,7 @@ int dt_destroy(dt_ctx *c) {
     f(c->okeys.p); f(c->osorted.p); f(c->omap2.p); f(c->dbgV.p); f(c->dbg_cloud.p);
     f(c->lev.p); f(c->wbucket.p); f(c->log_att.p); f(c->feat.p); f(c->ypred.p);
     f(c->w32.p); f(c->m1.p); f(c->m2.p); f(c->grad.p); f(c->loss.p); f(c->wbf.p);
-    f(c->oflags.p); f(c->omap.p); f(c->otets.p); f(c->onbrs.p);
+    f(c->oflags.p); f(c->omap.p); f(c->otets.p); f(c->onbrs.p); f(c->ovid.p);
     for (int k = 0; k < 3; ++k)
         if (c->ev[k]) hipEventDestroy(c->ev[k]);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);

@@ -1025,33 +1025,45 @@ hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hi
     return hipGetLastError();
 }
 
-__global__ void k_output(const Tet *__restrict__ T, const Vert *__restrict__ V,
+// Output position of each slot: map[t] (the exclusive scan of the live flags) for live finite
+// tetrahedra, NONE for ghosts and free slots; and the input index of each vertex record as a
+// compact 4-byte array.  The export kernel then gathers from these two small arrays (which
+// stay in the last-level caches far better than 64-byte tetrahedron rows and 32-byte vertex
+// records) instead of from the tetrahedron and vertex pools.
+__global__ void k_out_map(const uint32_t *__restrict__ flags, uint32_t count, uint32_t *__restrict__ map,
+                          const Vert *__restrict__ V, uint32_t nv, uint32_t *__restrict__ vid) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count && !flags[t]) map[t] = NONE;
+    if (t < nv) vid[t] = (uint32_t)V[t].idx;
+}
+
+__global__ void k_output(const Tet *__restrict__ T, const uint32_t *__restrict__ vid,
                          const uint32_t *__restrict__ map, uint32_t count, uint32_t *__restrict__ tets,
                          int64_t *__restrict__ nbrs) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
-    const uint4 w = T[t].v;
-    if (w.x == DEAD || w.w == GHOST) return;
     const uint32_t o = map[t];
+    if (o == NONE) return;
     if (tets) {
-        tets[4 * (size_t)o + 0] = (uint32_t)V[w.x].idx;
-        tets[4 * (size_t)o + 1] = (uint32_t)V[w.y].idx;
-        tets[4 * (size_t)o + 2] = (uint32_t)V[w.z].idx;
-        tets[4 * (size_t)o + 3] = (uint32_t)V[w.w].idx;
+        const uint4 w = T[t].v;
+        const uint4 out = make_uint4(vid[w.x], vid[w.y], vid[w.z], vid[w.w]);
+        *reinterpret_cast<uint4 *>(tets + 4 * (size_t)o) = out;
     }
     if (nbrs) {
         const uint4 nn = T[t].n;
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t nt = comp(nn, k) >> 2;
-            nbrs[4 * (size_t)o + k] = T[nt].v.w == GHOST ? -1 : (int64_t)map[nt];
-        }
+        const uint32_t m[4] = {map[nn.x >> 2], map[nn.y >> 2], map[nn.z >> 2], map[nn.w >> 2]};
+        longlong2 *dst = reinterpret_cast<longlong2 *>(nbrs + 4 * (size_t)o);
+        dst[0] = make_longlong2(m[0] == NONE ? -1ll : (long long)m[0], m[1] == NONE ? -1ll : (long long)m[1]);
+        dst[1] = make_longlong2(m[2] == NONE ? -1ll : (long long)m[2], m[3] == NONE ? -1ll : (long long)m[3]);
     }
 }
 
-hipError_t launch_output(const Tet *T, const Vert *V, const uint32_t *map, uint32_t count, uint32_t *tets,
-                         int64_t *nbrs, hipStream_t s) {
+hipError_t launch_output(const Tet *T, const Vert *V, uint32_t nv, const uint32_t *flags, uint32_t *map,
+                         uint32_t *vid, uint32_t count, uint32_t *tets, int64_t *nbrs, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    k_output<<<(count + 255) / 256, 256, 0, s>>>(T, V, map, count, tets, nbrs);
+    const uint32_t m = count > nv ? count : nv;
+    k_out_map<<<(m + 255) / 256, 256, 0, s>>>(flags, count, map, V, nv, vid);
+    k_output<<<(count + 255) / 256, 256, 0, s>>>(T, vid, map, count, tets, nbrs);
     return hipGetLastError();
 }
 

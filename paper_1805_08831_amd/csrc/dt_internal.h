@@ -207,8 +207,8 @@ hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, con
 hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s);
 hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s);
-hipError_t launch_output(const Tet *T, const Vert *V, const uint32_t *map, uint32_t count, uint32_t *tets,
-                         int64_t *nbrs, hipStream_t s);
+hipError_t launch_output(const Tet *T, const Vert *V, uint32_t nv, const uint32_t *flags, uint32_t *map,
+                         uint32_t *vid, uint32_t count, uint32_t *tets, int64_t *nbrs, hipStream_t s);
 // grouping of the live finite tetrahedra by cloud (see dt_get_tets_batch)
 hipError_t launch_tet_cloud(const Tet *T, const Vert *V, uint32_t count, uint32_t nclouds, unsigned long long *keys,
                             uint32_t *vals, hipStream_t s);

@@ -261,6 +261,21 @@ def test_device_buffers_through_torch(dtlib, oracle_mod):
         nb = nb.cpu().numpy()
     assert_parity(oracle_mod, xyz, t, "device buffers")
     check_invariants(xyz, t, nb, oracle_mod, expect_vertices=np.arange(len(xyz)))
+    # device buffers that are not 16-byte aligned (views one element in) give the same output
+    with dtlib.Triangulation(stream=torch.cuda.current_stream().cuda_stream) as tri:
+        tri.insert(d)
+        T = dtlib.dt_get_tets(tri.ctx)
+        bt = torch.full((T + 1, 4), -7, dtype=torch.int32, device="cuda")
+        bn = torch.full((T + 1, 4), -7, dtype=torch.int64, device="cuda")
+        vt = bt.view(-1)[1:1 + 4 * T]
+        vn = bn.view(-1)[1:1 + 4 * T]
+        assert vt.data_ptr() % 16 and vn.data_ptr() % 16
+        assert dtlib.dt_get_tets(tri.ctx, vt, vn, T) == T
+        t2, nb2 = tri.tets(device_tensors=True)  # aligned, same context: same order
+        torch.cuda.synchronize()
+        assert np.array_equal(vt.cpu().numpy().reshape(T, 4), t2.cpu().numpy())
+        assert np.array_equal(vn.cpu().numpy().reshape(T, 4), nb2.cpu().numpy())
+        assert bt.view(-1)[0].item() == -7 and bn.view(-1)[0].item() == -7
 
 
 # ------------------------------------------------------------------ batches of clouds
