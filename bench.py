@@ -244,8 +244,10 @@ def main():
         "config": {"workload": f"{args.n} i.i.d. uniform fp64 points in [0,1)^3, seed {args.seed}",
                    "points": args.n, "tetrahedra": T, "scheduler": "plain",
                    "launch": tuned if tuned else "defaults"},
-        "roofline": roofline if lanes == 8 and not args.round_fraction and not args.round_size else
-        dict(roofline, traffic=None),
+        # the counter summary was taken on this workload (1e7 points, seed 1007) at the default
+        # launch configuration; other launches have other per-launch traffic
+        "roofline": roofline if (lanes == 8 and not args.round_fraction and not args.round_size
+                                 and args.n == 10_000_000 and args.seed == 1007) else dict(roofline, traffic=None),
         "cpu_baseline": cpu,
         "learned": learned,
         "detail": {"rounds_per_step": agg["rounds"] / args.steps, "attempts_per_point": agg["attempts"] / max(args.n * args.steps, 1),

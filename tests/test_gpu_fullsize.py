@@ -1,0 +1,183 @@
+"""Checks at the benchmark's full sizes, in the launch configuration bench.py times (default
+options, device input and device outputs on torch's stream).
+
+A serial oracle run on 1e7 or 1e8 points would take minutes to hours, so the output is checked
+against the oracle on a sub-box, and by properties that hold at any size:
+
+* sub-box: every tetrahedron whose circumball lies inside a box B belongs to the Delaunay
+  tetrahedralization of all points iff it belongs to that of the points in B (its ball is
+  empty of the points in B, and holds no point outside B).  The oracle triangulates the points
+  in B; both outputs, filtered by one classifier (fp64 circumballs inside B shrunk by 1e-9),
+  must be equal;
+* every input point is a vertex;
+* adjacency: each neighbour link is mirrored and the two tetrahedra share three vertices;
+* the hull: V - E + F = 2 on the faces without neighbour, and the tetrahedra fill the volume of
+  the convex hull computed independently (scipy's Qhull);
+* local Delaunay (perturbed, exact, by the oracle) across a random sample of interior facets,
+  and positive orientation of the tetrahedra sampled.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from synth import uniform_points
+from test_gpu import dtlib, say  # noqa: F401  (fixture)
+
+pytestmark = pytest.mark.gpu
+
+
+def _triangulate(dtlib, xyz):
+    """Bench configuration: device input, default options, device outputs."""
+    import torch
+    d = torch.from_numpy(xyz).cuda()
+    stream = torch.cuda.current_stream()
+    tri = dtlib.Triangulation(device=0, stream=stream.cuda_stream, timing=True)
+    tri.insert(d)
+    T = dtlib.dt_get_tets(tri.ctx)
+    t = torch.empty((T, 4), dtype=torch.int32, device="cuda")
+    nb = torch.empty((T, 4), dtype=torch.int64, device="cuda")
+    assert dtlib.dt_get_tets(tri.ctx, t, nb, T) == T
+    torch.cuda.synchronize()
+    tri.close()
+    return t, nb
+
+
+def _circumballs(xyz, q):
+    a = xyz[q[:, 0]]
+    m = np.stack([xyz[q[:, k]] - a for k in (1, 2, 3)], axis=1)  # [k, 3, 3]
+    rhs = 0.5 * np.einsum("kij,kij->ki", m, m)
+    c = np.linalg.solve(m, rhs[:, :, None])[:, :, 0]
+    return a + c, np.sqrt(np.einsum("ki,ki->k", c, c))
+
+
+def _in_box(xyz, q, lo, hi, margin=1e-9):
+    cen, r = _circumballs(xyz, q)
+    return np.all(cen - r[:, None] > lo + margin, axis=1) & np.all(cen + r[:, None] < hi - margin, axis=1)
+
+
+def _subbox_check(oracle_mod, xyz, t_dev, lo, side):
+    import torch
+    hi = lo + side
+    inb = np.all((xyz >= lo) & (xyz < hi), axis=1)
+    sub_idx = np.nonzero(inb)[0]
+    say(f"sub-box [{lo}, {hi})^3: {len(sub_idx)} points")
+    # GPU tetrahedra with all four vertices in the box, then the circumball classifier
+    m = torch.from_numpy(inb).cuda()
+    keep = m[t_dev.long()].all(dim=1)
+    g = t_dev[keep].cpu().numpy().astype(np.int64)
+    g = g[_in_box(xyz, g, lo, hi)]
+    # the oracle on the points of the box (their input order kept: same perturbation order)
+    rc, ot, _, _ = oracle_mod.delaunay(xyz[sub_idx])
+    assert rc == 0
+    o = sub_idx[ot.astype(np.int64)]
+    o = o[_in_box(xyz, o, lo, hi)]
+    a, b = oracle_mod.canonical(g), oracle_mod.canonical(o)
+    say(f"sub-box: {len(a)} GPU and {len(b)} oracle tetrahedra with the ball inside")
+    assert len(a) > 0.5 * 6.5 * len(sub_idx)
+    assert a.shape == b.shape and np.array_equal(a, b)
+
+
+def _vertices_check(t_dev, n):
+    import torch
+    seen = torch.zeros(n, dtype=torch.bool, device="cuda")
+    seen[t_dev.reshape(-1).long()] = True
+    assert int(seen.sum()) == n
+
+
+def _adjacency_and_hull_check(t, nb):
+    """On the device (torch): mirrored links sharing a facet; V - E + F = 2 on the hull."""
+    import torch
+    T = t.shape[0]
+    chunk = 1 << 22
+    for s in range(0, T, chunk):
+        e = min(T, s + chunk)
+        ti = torch.arange(s, e, device="cuda").repeat_interleave(4)
+        nf = nb[s:e].reshape(-1)
+        ok = nf >= 0
+        back = nb[nf[ok]]
+        assert bool((back == ti[ok][:, None]).any(dim=1).all()), "neighbour link not mirrored"
+        va = t[ti[ok]]
+        vb = t[nf[ok]]
+        shared = (va[:, :, None] == vb[:, None, :]).any(dim=2).sum(dim=1)
+        assert bool((shared == 3).all()), "neighbours do not share a facet"
+    # hull faces: facet j of t without neighbour; V - E + F = 2 (a closed triangulated sphere)
+    hf = torch.nonzero(nb < 0)
+    F = hf.shape[0]
+    faces = torch.stack([t[hf[:, 0], (hf[:, 1] + k) % 4] for k in (1, 2, 3)], dim=1)
+    V = torch.unique(faces).numel()
+    assert F % 2 == 0 and V - (3 * F) // 2 + F == 2
+
+
+def _volume_check(xyz, t):
+    """Sum of the tetrahedra's volumes (fp64, on the device) against Qhull's hull volume."""
+    import torch
+    from scipy.spatial import ConvexHull
+    X = torch.from_numpy(xyz).cuda()
+    vol = 0.0
+    chunk = 1 << 22
+    for s in range(0, t.shape[0], chunk):
+        q = t[s:s + chunk].long()
+        a = X[q[:, 0]]
+        u, v, w = X[q[:, 1]] - a, X[q[:, 2]] - a, X[q[:, 3]] - a
+        vol += float((u * torch.cross(v, w, dim=1)).sum()) / 6.0
+    hull = ConvexHull(xyz).volume
+    say(f"volume: tetrahedra {vol:.12f}, hull {hull:.12f}")
+    assert abs(vol - hull) <= 1e-8 * hull
+
+
+def _local_delaunay_sample(oracle_mod, xyz, t, nb, k, seed):
+    rng = np.random.default_rng(seed)
+    T = len(t)
+    picks = []
+    while sum(len(p) for p in picks) < k:
+        r = rng.integers(0, T, size=k)
+        j = rng.integers(0, 4, size=k)
+        ok = nb[r, j] >= 0
+        picks.append(np.stack([r[ok], j[ok]], axis=1))
+    rj = np.concatenate(picks)[:k]
+    r, j = rj[:, 0], rj[:, 1]
+    q = t[r]
+    assert np.all(oracle_mod.orient3d(xyz[q]) > 0)
+    assert np.all(nb[r, j] >= 0)
+    u = t[nb[r, j]]
+    inq = (u[:, :, None] == q[:, None, :]).any(axis=2)
+    assert np.all(inq.sum(axis=1) == 3)
+    ap = u[~inq]  # the neighbour's vertex across the shared facet, one per row
+    pts = np.concatenate([xyz[q], xyz[ap][:, None, :]], axis=1)
+    idx = np.concatenate([q, ap[:, None]], axis=1)
+    s = oracle_mod.insphere_sos(pts, idx)
+    assert np.all(s > 0), "a neighbour's apex lies inside a circumsphere"
+
+
+def test_uniform_1e7_bench_config(dtlib, oracle_mod):
+    """The benchmark workload: 1e7 uniform points, seed 1007."""
+    n = 10_000_000
+    say("full size: uniform 1e7 (seed 1007), bench configuration")
+    xyz = uniform_points(n, 1007)
+    t_dev, nb_dev = _triangulate(dtlib, xyz)
+    say(f"{len(t_dev)} tetrahedra")
+    _subbox_check(oracle_mod, xyz, t_dev, 0.37, 0.2714)
+    _vertices_check(t_dev, n)
+    say("adjacency and hull")
+    _adjacency_and_hull_check(t_dev, nb_dev)
+    say("volume")
+    _volume_check(xyz, t_dev)
+    say("local Delaunay sample")
+    t = t_dev.cpu().numpy().astype(np.int64)
+    nb = nb_dev.cpu().numpy()
+    _local_delaunay_sample(oracle_mod, xyz, t, nb, 20000, 11)
+
+
+def test_uniform_1e8_subbox(dtlib, oracle_mod):
+    """1e8 uniform points (seed 1008): sub-box against the oracle, every point a vertex."""
+    import torch
+    n = 100_000_000
+    say("full size: uniform 1e8 (seed 1008), bench configuration")
+    xyz = uniform_points(n, 1008)
+    t_dev, nb_dev = _triangulate(dtlib, xyz)
+    say(f"{len(t_dev)} tetrahedra")
+    del nb_dev
+    torch.cuda.empty_cache()
+    _subbox_check(oracle_mod, xyz, t_dev, 0.61, 0.126)
+    _vertices_check(t_dev, n)
