@@ -56,7 +56,7 @@ def _in_box(xyz, q, lo, hi, margin=1e-9):
     return np.all(cen - r[:, None] > lo + margin, axis=1) & np.all(cen + r[:, None] < hi - margin, axis=1)
 
 
-def _subbox_check(oracle_mod, xyz, t_dev, lo, side):
+def _subbox_check(oracle_mod, xyz, t_dev, lo, side, min_tets=None):
     import torch
     hi = lo + side
     inb = np.all((xyz >= lo) & (xyz < hi), axis=1)
@@ -74,7 +74,7 @@ def _subbox_check(oracle_mod, xyz, t_dev, lo, side):
     o = o[_in_box(xyz, o, lo, hi)]
     a, b = oracle_mod.canonical(g), oracle_mod.canonical(o)
     say(f"sub-box: {len(a)} GPU and {len(b)} oracle tetrahedra with the ball inside")
-    assert len(a) > 0.5 * 6.5 * len(sub_idx)
+    assert len(a) > (0.5 * 6.5 * len(sub_idx) if min_tets is None else min_tets)
     assert a.shape == b.shape and np.array_equal(a, b)
 
 
@@ -181,3 +181,46 @@ def test_uniform_1e8_subbox(dtlib, oracle_mod):
     torch.cuda.empty_cache()
     _subbox_check(oracle_mod, xyz, t_dev, 0.61, 0.126)
     _vertices_check(t_dev, n)
+
+
+def test_mix_1e7_subboxes(dtlib, oracle_mod):
+    """MIX 1e7 (seed 2007, the benchmark's MIX input): sub-boxes in the lattice and in the
+    clusters against the oracle (the circumball argument holds under the perturbation: a ball
+    strictly inside B leaves every point outside B strictly outside), every point a vertex."""
+    from synth import mix_points
+    say("full size: MIX 1e7 (seed 2007), bench configuration")
+    xyz = mix_points(2007)
+    t_dev, nb_dev = _triangulate(dtlib, xyz)
+    say(f"{len(t_dev)} tetrahedra")
+    del nb_dev
+    # lattice nodes are odd multiples of 1/512; the box edges avoid them
+    _subbox_check(oracle_mod, xyz, t_dev, -0.0996, 0.06, min_tets=1000)
+    # a box around a cluster point (outside the lattice cube, inside r < 0.9)
+    r = np.linalg.norm(xyz, axis=1)
+    c = xyz[np.nonzero((r < 0.9) & (np.abs(xyz).max(axis=1) > 0.35))[0][0]]
+    _subbox_check(oracle_mod, xyz, t_dev, c - 0.015, 0.03, min_tets=1000)
+    _vertices_check(t_dev, len(xyz))
+
+
+def test_batch_bench_chunk(dtlib, oracle_mod):
+    """The benchmark's batch configuration: clouds 0..1023 of the 4096-cloud recipe in one
+    dt_insert_batch call; a sample of clouds (the smallest, the largest, and every 128th)
+    against the oracle run on that cloud alone."""
+    import torch
+    from synth import batch_clouds
+    say("full size: batch of 1024 clouds (seeds 3000..4023)")
+    xyz, off = batch_clouds(1024, seed_base=3000)
+    off = off.astype(np.int64)
+    stream = torch.cuda.current_stream()
+    with dtlib.Triangulation(device=0, stream=stream.cuda_stream, timing=True) as tri:
+        tri.insert_batch(torch.from_numpy(xyz).cuda(), off.astype(np.uint64))
+        sizes = np.diff(off)
+        pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes))] + list(range(0, 1024, 128))))
+        for k in pick:
+            pts = xyz[off[k]:off[k + 1]]
+            t, nb = tri.tets_batch(k)
+            rc, ot, _, _ = oracle_mod.delaunay(pts)
+            assert rc == 0
+            a, b = oracle_mod.canonical(t.astype(np.int64)), oracle_mod.canonical(ot)
+            assert a.shape == b.shape and np.array_equal(a, b), f"cloud {k}"
+        say(f"{len(pick)} clouds match, largest {int(sizes.max())} points")
