@@ -309,13 +309,17 @@ __device__ __forceinline__ int mem_find(uint32_t *mem, uint32_t hm, uint32_t t) 
     return -1;
 }
 
-// adds t with `kind`: 1 if this call added it, 0 if it was there, -1 if the set is full
-__device__ __forceinline__ int mem_insert(uint32_t *mem, uint32_t hm, uint32_t t, uint32_t kind) {
+// adds t with `kind`: 1 if this call added it (its entry is then mem[*at]), 0 if it was
+// there, -1 if the set is full
+__device__ __forceinline__ int mem_insert(uint32_t *mem, uint32_t hm, uint32_t t, uint32_t kind, uint32_t *at) {
     uint32_t h = mem_hash(t, hm);
     const uint32_t e = (t << 1) | kind;
     for (uint32_t probe = 0; probe < hm; ++probe) {
         const uint32_t old = atomicCAS(&mem[h], MEM_EMPTY, e);
-        if (old == MEM_EMPTY) return 1;
+        if (old == MEM_EMPTY) {
+            *at = h;
+            return 1;
+        }
         if ((old >> 1) == t) return 0;
         h = (h + 1) & (hm - 1);
     }
@@ -348,7 +352,9 @@ template <int GS, uint32_t CAPL, uint32_t HM, bool GLOBAL>
 __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
     constexpr uint32_t GPB = 256 / GS;  // insertions per 256-thread block
     constexpr uint32_t NP = GS / 4;     // cavity tetrahedra expanded per step
-    __shared__ uint32_t s_cav[GPB][GLOBAL ? 1 : CAPL];
+    // LDS queue entries: (slot of the tetrahedron's entry in the set << 2 | facet it was
+    // entered through), 16 bits; the global queue holds (tetrahedron << 2 | facet)
+    __shared__ uint16_t s_cav[GPB][GLOBAL ? 1 : CAPL];
     __shared__ uint32_t s_mem[GPB][GLOBAL ? 1 : HM];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t gl = threadIdx.x & (GS - 1);
@@ -435,7 +441,8 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
         const uint32_t capL = GLOBAL ? a.capC : min(a.capC, CAPL), capF = a.capF;
         uint32_t *bnd = a.bnd + (size_t)i * a.capF;
         uint32_t *outc = a.outc + (size_t)i * a.capF;
-        uint32_t *cavq = GLOBAL ? a.cav + (size_t)i * a.capC : s_cav[gi];
+        uint32_t *cavg = a.cav + (size_t)i * a.capC;
+        uint16_t *cavl = s_cav[gi];
         // the set in global memory: hms (a power of two, at most 4 capC) words of the
         // candidate's part of the ball scratch, which the ball kernel uses only later
         const uint32_t hms = GLOBAL ? a.hmg : HM;
@@ -452,8 +459,10 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 status = ST_CONFLICT;
             } else {
                 if (gl == 0) {
-                    cavq[0] = t << 2;
-                    mem_insert(mem, hms, t, 0u);
+                    uint32_t at = 0;
+                    mem_insert(mem, hms, t, 0u, &at);
+                    if (GLOBAL) cavg[0] = t << 2;
+                    else cavl[0] = (uint16_t)(at << 2);
                 }
                 ncav = 1;
             }
@@ -463,7 +472,15 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 const uint32_t slot = k0 + (gl >> 2);
                 const int f = jl;
                 const bool lv = slot < k0 + nproc;
-                const uint32_t code = lv ? cavq[slot] : 0u;
+                uint32_t code = 0u;
+                if (lv) {
+                    if (GLOBAL) {
+                        code = cavg[slot];
+                    } else {
+                        const uint32_t q = cavl[slot];
+                        code = ((mem[q >> 2] >> 1) << 2) | (q & 3u);
+                    }
+                }
                 const uint32_t c = code >> 2;
                 const int pf = slot == 0 ? -1 : (int)(code & 3u);
                 const bool act = lv && f != pf;
@@ -521,7 +538,8 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 // record u in the set; a tetrahedron reached through several facets in this
                 // step is queued (if inside) by the lane that records it
                 int ins = 0;
-                if (need) ins = mem_insert(mem, hms, u, inside ? 0u : 1u);
+                uint32_t at = 0;
+                if (need) ins = mem_insert(mem, hms, u, inside ? 0u : 1u, &at);
                 const bool first_in = ins == 1 && inside;
                 const bool outside = (act && kind == 1) || (need && !inside);  // boundary facet (c, f)
                 const unsigned long long mi = __ballot(first_in) & gmask;
@@ -532,7 +550,9 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                     break;
                 }
                 if (first_in) {
-                    cavq[ncav + __popcll(mi & below)] = ncode;
+                    const uint32_t pos = ncav + (uint32_t)__popcll(mi & below);
+                    if (GLOBAL) cavg[pos] = ncode;
+                    else cavl[pos] = (uint16_t)((at << 2) | (ncode & 3u));
                     atomicMin(&a.T[u].claim, S);
                 }
 
@@ -549,7 +569,10 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
             if (status == ST_NONE) status = ST_CAND;
         }
         if (!GLOBAL && status == ST_CAND)
-            for (uint32_t k = gl; k < ncav; k += GS) a.cav[(size_t)i * a.capC + k] = cavq[k];
+            for (uint32_t k = gl; k < ncav; k += GS) {
+                const uint32_t q = cavl[k];
+                cavg[k] = ((mem[q >> 2] >> 1) << 2) | (q & 3u);
+            }
         if (gl == 0) {
             a.status[i] = status;
             a.cnt[i] = ncav;
