@@ -2,22 +2,23 @@
 // concurrency rules of Sec. 3.2).
 //
 // A round is two kernels over the round's candidate points:
-//   k_cavity_g / k_cavity : Walk (visibility walk, Sec. 2.1) from a live tetrahedron of an
-//              already inserted neighbour on the space-filling curve, then Cavity (breadth-
-//              first search by perturbed insphere, ghosts by the half-space + circumdisk rule
-//              of Sec. 2.6), by a group of lanes (k_cavity_g) or one thread (k_cavity, for
-//              cavities beyond the LDS queue).  The attempt claims every tetrahedron it
-//              touches with atomicMin on the tetrahedron's 64-bit claim word: its stamp
-//              S = (round part, 2 rank) for cavity tetrahedra, S + 1 for tetrahedra found
-//              outside.  Meeting a lower claim that excludes it ends the attempt at once.
+//   k_cavity_g : Walk (visibility walk, Sec. 2.1) from a live tetrahedron of an already
+//              inserted neighbour on the space-filling curve, then Cavity (breadth-first
+//              search by perturbed insphere, ghosts by the half-space + circumdisk rule of
+//              Sec. 2.6), by a group of lanes per insertion.  The attempt claims every
+//              tetrahedron it touches, once it has tested it, with atomicMin on the
+//              tetrahedron's 64-bit claim word: its stamp S = (round part, 2 rank) for cavity
+//              tetrahedra, S + 1 for tetrahedra found outside.  Meeting a lower claim that
+//              excludes it ends the attempt (one search step later).
 //   k_ball   : an attempt wins iff no lower attempt claimed a tetrahedron of its cavity
 //              (either way) or has one of its outer tetrahedra in its cavity, so the cavities
 //              of winners are disjoint from each other and from each other's adjacent
 //              tetrahedra (rules 1a-1c and 2 of Sec. 3.2); the lowest rank in a
 //              round always wins, so every round makes progress.  A winner builds
 //              DelaunayBall (Sec. 2.5): one tetrahedron per boundary facet, glued a priori to
-//              the outer tetrahedron, and glued to its three sibling tetrahedra by pivoting
-//              around each boundary edge through copies of the cavity tetrahedra.  Freed
+//              the outer tetrahedron, and glued to its three sibling tetrahedra through an
+//              LDS table of boundary edges (pivoting around each boundary edge through copies
+//              of the cavity tetrahedra for large balls).  Freed
 //              slots are reused in later rounds (Sec. 2.5 end, Sec. 3.6).
 // Then k_compact queues losers for the next round with their rank, and overflowing
 // cavities for rounds with larger per-insertion buffers.
@@ -342,12 +343,12 @@ __device__ __forceinline__ void lane_fence() {
 // uniform within each group.  Cavity entries hold (tetrahedron << 2 | facet it was entered
 // through), which is skipped when the tetrahedron is expanded.
 //
-// Claims: every neighbour examined for the first time is claimed with S + 1 (S is the
-// attempt's stamp: round, then rank); a lower even value returned means a lower attempt has
-// it in its cavity, and this attempt loses.  A tetrahedron found inside is then claimed with
-// S; a lower odd value on it means a lower attempt has it outside its cavity, and this
-// attempt loses too.  The attempt's own tetrahedra are tracked in the set, so each is
-// claimed and tested once.  GLOBAL keeps queue and set in global memory (any capC).
+// Claims: every neighbour examined is tested first and then claimed once, with S if it is
+// inside (S is the attempt's stamp: round, then rank) and S + 1 if it is outside.  A lower
+// value returned on an inside tetrahedron, or a lower even value (a lower attempt's cavity)
+// on an outside one, loses the attempt.  The attempt's own tetrahedra are tracked in the
+// set, so each is claimed and tested once.  GLOBAL keeps queue and set in global memory
+// (any capC).
 template <int GS, uint32_t CAPL, uint32_t HM, bool GLOBAL>
 __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
     constexpr uint32_t GPB = 256 / GS;  // insertions per 256-thread block
@@ -467,6 +468,10 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 ncav = 1;
             }
             lane_fence<GLOBAL>();
+            // each step's claims are checked at the next step (or after the last), once that
+            // step's loads are in flight, so that the atomics' latency overlaps them
+            bool pneed = false, pinside = false;
+            unsigned long long po1 = ~0ull;
             for (uint32_t k0 = 0, nproc = 0; k0 < ncav && status == ST_NONE; k0 += nproc) {
                 nproc = min(NP, ncav - k0);  // entries expanded in this step
                 const uint32_t slot = k0 + (gl >> 2);
@@ -489,19 +494,19 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                     cv = a.T[c].v;
                     cn = a.T[c].n;
                 }
+                // the previous step's claims: a lower claim on a tetrahedron of this cavity,
+                // or a lower cavity claim (even) on one outside it, loses the attempt
+                if (__ballot(pneed && po1 < S && (pinside || !(po1 & 1ull))) & gmask) {
+                    status = ST_CONFLICT;
+                    break;
+                }
                 const uint32_t ncode = comp(cn, f);
                 const uint32_t u = ncode >> 2;
                 const int kind = act ? mem_find<GLOBAL>(mem, hms, u) : -1;  // 0: in this cavity, 1: outside it
                 const bool need = act && kind < 0;
-                unsigned long long o1 = ~0ull;
-                if (need) {
-                    o1 = atomicMin(&a.T[u].claim, S + 1);
-                    uw = a.T[u].v;
-                }
-                // a lower attempt has u in its cavity: this one loses either way
-                bool conflict = need && o1 < S && !(o1 & 1ull);
+                if (need) uw = a.T[u].v;
                 bool inside = false;
-                if (need && !conflict) {
+                if (need) {
                     const bool cghost = cv.w == GHOST;
                     const uint32_t apex = comp(uw, (int)(ncode & 3u));
                     if (!cghost && apex != GHOST) {
@@ -528,13 +533,11 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                     } else {
                         inside = tet_inside(a, u, P, pv.idx, st);
                     }
-                    // a lower attempt has u next to its cavity: it cannot be in this one
-                    conflict = inside && o1 < S;
                 }
-                if (__ballot(conflict) & gmask) {
-                    status = ST_CONFLICT;
-                    break;
-                }
+                // the one claim of u: S if inside, S + 1 if outside (a tetrahedron reached
+                // through several facets in this step gets the same claim from each lane)
+                unsigned long long o1 = ~0ull;
+                if (need) o1 = atomicMin(&a.T[u].claim, inside ? S : S + 1);
                 // record u in the set; a tetrahedron reached through several facets in this
                 // step is queued (if inside) by the lane that records it
                 int ins = 0;
@@ -553,9 +556,7 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                     const uint32_t pos = ncav + (uint32_t)__popcll(mi & below);
                     if (GLOBAL) cavg[pos] = ncode;
                     else cavl[pos] = (uint16_t)((at << 2) | (ncode & 3u));
-                    atomicMin(&a.T[u].claim, S);
                 }
-
                 if (outside) {
                     // boundary facet: (local index of c) << 2 | f, and the outer tetrahedron
                     const uint32_t pos = nbnd + (uint32_t)__popcll(mo & below);
@@ -564,8 +565,13 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 }
                 ncav += ni;
                 nbnd += no;
+                pneed = need;
+                pinside = inside;
+                po1 = o1;
                 lane_fence<GLOBAL>();
             }
+            if (status == ST_NONE && (__ballot(pneed && po1 < S && (pinside || !(po1 & 1ull))) & gmask))
+                status = ST_CONFLICT;
             if (status == ST_NONE) status = ST_CAND;
         }
         if (!GLOBAL && status == ST_CAND)
