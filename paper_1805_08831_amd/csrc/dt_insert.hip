@@ -453,25 +453,20 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
             // = (gl / 4, gl % 4).
             for (uint32_t h = gl; h < hms; h += GS) mem[h] = MEM_EMPTY;
             lane_fence<GLOBAL>();
-            unsigned long long o0 = 0;
-            if (gl == 0) o0 = atomicMin(&a.T[t].claim, S);
-            o0 = __shfl(o0, (int)gbase);
-            if (o0 < S) {
-                status = ST_CONFLICT;
-            } else {
-                if (gl == 0) {
-                    uint32_t at = 0;
-                    mem_insert(mem, hms, t, 0u, &at);
-                    if (GLOBAL) cavg[0] = t << 2;
-                    else cavl[0] = (uint16_t)(at << 2);
-                }
-                ncav = 1;
-            }
-            lane_fence<GLOBAL>();
             // each step's claims are checked at the next step (or after the last), once that
-            // step's loads are in flight, so that the atomics' latency overlaps them
-            bool pneed = false, pinside = false;
+            // step's loads are in flight, so that the atomics' latency overlaps them; the
+            // walk's tetrahedron is inside, its claim is checked with the first step's
+            bool pneed = gl == 0, pinside = true;
             unsigned long long po1 = ~0ull;
+            if (gl == 0) {
+                po1 = atomicMin(&a.T[t].claim, S);
+                uint32_t at = 0;
+                mem_insert(mem, hms, t, 0u, &at);
+                if (GLOBAL) cavg[0] = t << 2;
+                else cavl[0] = (uint16_t)(at << 2);
+            }
+            ncav = 1;
+            lane_fence<GLOBAL>();
             for (uint32_t k0 = 0, nproc = 0; k0 < ncav && status == ST_NONE; k0 += nproc) {
                 nproc = min(NP, ncav - k0);  // entries expanded in this step
                 const uint32_t slot = k0 + (gl >> 2);
