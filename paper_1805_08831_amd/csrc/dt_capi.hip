@@ -97,7 +97,8 @@ struct dt_ctx {
     uint8_t *status = nullptr;
 
     Ctr *ctr = nullptr;
-    Ctr *hctr = nullptr;  // pinned mirror
+    Ctr *hctr = nullptr;   // pinned: the counters after the last completed round (one of hring)
+    Ctr *hring = nullptr;  // three pinned snapshots: the host's and one per round in flight
     unsigned long long *stat = nullptr;  // spread work statistics (summed into ctr each round)
 
     // per-call scratch
@@ -109,9 +110,13 @@ struct dt_ctx {
     DevBuf<uint32_t> oflags, omap, otets, ovid;
     DevBuf<int64_t> onbrs;
 
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[3][3] = {};   // per snapshot slot: kernel timing events of its round
+    hipEvent_t evdone[3] = {};  // per snapshot slot: its copy has landed
+    uint32_t slot_cand[3] = {}, slot_capC[3] = {};
+    bool grow_pending = false;  // a round found the pool full: grow before the next one
     dt_stats st{};
     uint32_t trace_prev_won = 0, trace_prev_conf = 0, trace_prev_ovf = 0;
+    uint64_t trace_rounds = 0;
     unsigned long long trace_prev_att = 0, trace_prev_walk = 0, trace_prev_cav = 0, trace_prev_ins = 0;
     const uint32_t *lord = nullptr;  // level-major order of the current call's vertex records
     // clouds of the current call (one for dt_insert_points)
@@ -306,12 +311,12 @@ void apply_options(dt_ctx *c) {
 int check_errors(dt_ctx *c) {
     uint32_t e = c->hctr->error;
     if (e & ERR_POOL) {
-        // some insertions found the pool full and will retry: grow it now
+        // some insertions found the pool full and will retry: the pool grows before the next
+        // round is planned (once no round is in flight)
         HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
         c->hctr->error &= ~ERR_POOL;
         e &= ~ERR_POOL;
-        int rc = grow_tets(c, (uint64_t)c->tcap + c->tcap / 2 + 4096);
-        if (rc) return rc;
+        c->grow_pending = true;
     }
     if (!e) return DT_OK;
     if (e & ERR_CAPACITY) return fail(c, DT_E_CAPACITY, "tetrahedron pool exhausted inside a round");
@@ -319,11 +324,11 @@ int check_errors(dt_ctx *c) {
     return fail(c, DT_E_INTERNAL, "device error flags 0x%x", e);
 }
 
-void accumulate_timing(dt_ctx *c) {
+void accumulate_timing(dt_ctx *c, int slot) {
     if (!c->opt.timing) return;
     float a = 0.f, b = 0.f;
-    if (hipEventElapsedTime(&a, c->ev[0], c->ev[1]) == hipSuccess &&
-        hipEventElapsedTime(&b, c->ev[1], c->ev[2]) == hipSuccess) {
+    if (hipEventElapsedTime(&a, c->ev[slot][0], c->ev[slot][1]) == hipSuccess &&
+        hipEventElapsedTime(&b, c->ev[slot][1], c->ev[slot][2]) == hipSuccess) {
         c->st.ms_cavity_kernel += a;
         c->st.ms_ball_kernel += b;
         c->st.cavity_launches++;
@@ -333,10 +338,16 @@ void accumulate_timing(dt_ctx *c) {
     }
 }
 
-// one round over the candidate list `ci`; losers go to `ni`, overflows to `oi`
-// (slice: the candidates are entries off .. off + max_cand of list ci, not the whole list)
-int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t capC, uint32_t capF,
-                  uint64_t base, uint64_t n, bool slice = false, uint32_t off = 0) {
+// One round over the candidate list `ci`; losers go to `ni`, overflows to `oi` (slice: the
+// candidates are entries off .. off + max_cand of list ci, not the whole list).  The round
+// is launched with the copy of its counters into a free snapshot slot (neither the host's
+// nor one still in flight); complete_round waits for it.  max_cand bounds the candidates:
+// the kernels read the count itself from the device.
+int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t capC, uint32_t capF,
+                  uint64_t base, uint64_t n, int busy, int *slot_out, bool slice = false, uint32_t off = 0) {
+    const int host = (int)(c->hctr - c->hring);
+    int slot = 0;
+    while (slot == host || slot == busy) ++slot;
     Ctr *d = c->ctr;
     RoundArgs a{};
     a.V = c->V.p;
@@ -380,29 +391,41 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.hmg = 1u << (31 - __builtin_clz(std::min<uint32_t>(4u * std::min<uint32_t>(capC, 1u << 24), 1u << 30)));
     a.round_hi = (0xFFFFFFFFull - (c->round_counter & 0xFFFFFFFFull)) << 32;
     c->round_counter++;
-    HIPCHK(launch_round(a, max_cand, c->lanes, c->stream, c->opt.timing ? c->ev : nullptr));
+    HIPCHK(launch_round(a, max_cand, c->lanes, c->stream, c->opt.timing ? c->ev[slot] : nullptr));
     HIPCHK(launch_round_end(a, max_cand, c->stream));
     c->fl_idx ^= 1;
-    int rc = sync_ctr(c);
-    if (rc) return rc;
-    if (max_cand) accumulate_timing(c);
+    HIPCHK(hipMemcpyAsync(&c->hring[slot], c->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipEventRecord(c->evdone[slot], c->stream));
+    c->slot_cand[slot] = max_cand;
+    c->slot_capC[slot] = capC;
     c->st.rounds++;
+    *slot_out = slot;
+    return DT_OK;
+}
+
+// Waits for the round whose counters go to `slot`; they become the host's snapshot.
+int complete_round(dt_ctx *c, int slot) {
+    HIPCHK(hipEventSynchronize(c->evdone[slot]));
+    c->hctr = &c->hring[slot];
+    const uint32_t max_cand = c->slot_cand[slot], capC = c->slot_capC[slot];
+    if (max_cand) accumulate_timing(c, slot);
     if (c->trace) {
         uint32_t &prev_won = c->trace_prev_won;
         if (prev_won > c->hctr->won) {
             prev_won = c->trace_prev_conf = c->trace_prev_ovf = 0;
             c->trace_prev_att = c->trace_prev_walk = c->trace_prev_cav = c->trace_prev_ins = 0;
+            c->trace_rounds = 0;
         }
-        float a = 0.f, b = 0.f;
+        float ta = 0.f, tb = 0.f;
         if (c->opt.timing && max_cand) {
-            hipEventElapsedTime(&a, c->ev[0], c->ev[1]);
-            hipEventElapsedTime(&b, c->ev[1], c->ev[2]);
+            hipEventElapsedTime(&ta, c->ev[slot][0], c->ev[slot][1]);
+            hipEventElapsedTime(&tb, c->ev[slot][1], c->ev[slot][2]);
         }
         fprintf(stderr,
-                "round %llu cand<=%u won=%u tets=%u free=%u cavity_ms=%.3f ball_ms=%.3f att=%llu walk=%llu conf=%u "
-                "ovf=%u capC=%u cavw=%llu insph=%llu\n",
-                (unsigned long long)c->st.rounds, max_cand, c->hctr->won - prev_won, c->hctr->tet_count,
-                c->hctr->fl_n, a, b, c->hctr->attempts - c->trace_prev_att, c->hctr->walk_steps - c->trace_prev_walk,
+                "round %llu cand<=%u won=%u tets=%u free=%u cavity_ms=%.3f ball_ms=%.3f att=%llu walk=%llu "
+                "conf=%u ovf=%u capC=%u cavw=%llu insph=%llu\n",
+                (unsigned long long)++c->trace_rounds, max_cand, c->hctr->won - prev_won, c->hctr->tet_count, c->hctr->fl_n, ta, tb,
+                c->hctr->attempts - c->trace_prev_att, c->hctr->walk_steps - c->trace_prev_walk,
                 c->hctr->conflicts - c->trace_prev_conf, c->hctr->overflows - c->trace_prev_ovf, capC,
                 c->hctr->cav_tets - c->trace_prev_cav, c->hctr->insphere - c->trace_prev_ins);
         prev_won = c->hctr->won;
@@ -414,6 +437,23 @@ int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
         c->trace_prev_ins = c->hctr->insphere;
     }
     return check_errors(c);
+}
+
+// grows the pool when a round found it full (no round may be in flight)
+int grow_if_pending(dt_ctx *c) {
+    if (!c->grow_pending) return DT_OK;
+    c->grow_pending = false;
+    return grow_tets(c, (uint64_t)c->tcap + c->tcap / 2 + 4096);
+}
+
+// one round, waited for
+int run_one_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t capC, uint32_t capF,
+                  uint64_t base, uint64_t n, bool slice = false, uint32_t off = 0) {
+    int slot = -1;
+    int rc = enqueue_round(c, ci, ni, oi, max_cand, capC, capF, base, n, -1, &slot, slice, off);
+    if (rc) return rc;
+    if ((rc = complete_round(c, slot))) return rc;
+    return grow_if_pending(c);
 }
 
 // Grow the pool ahead of a round when the expected consumption would not fit; an
@@ -499,19 +539,82 @@ uint64_t plan_fill(const Levels &lv, uint64_t first, uint64_t W, FillPlan &plan)
     return r - first;
 }
 
+// The rounds of one call.  While new ranks remain, a round is planned and launched while
+// the previous one still runs: its size comes from the last completed round's counters,
+// with the running round's candidates as the bound on the losers that open the next list
+// (the kernels read the exact count on the device), so the GPU does not wait for the host
+// between rounds.  Drains, pool growth, the last rounds and anything the bounds cannot
+// guarantee run one round at a time.
 int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint32_t *d_size,
                const uint32_t *d_bits, const unsigned long long *d_rank_base, uint64_t base, uint64_t n) {
     const uint32_t rmax = c->list_cap;
     const double frac = c->opt.round_fraction > 0 ? c->opt.round_fraction : DEFAULT_ROUND_FRACTION;
     uint64_t next_rank = 0;
     uint64_t rounds_this_call = 0;
+    int fly = -1;            // snapshot slot of the round in flight, or -1
+    uint32_t fly_cand = 0;   // its candidates (exact)
+    double loss = 0.5;       // share of candidates lost by the last completed round
+    uint32_t won_seen = c->hctr->won;
+    auto target_size = [&]() {
+        uint64_t t = (uint64_t)std::llround(frac * (double)c->mesh_vertices);
+        if (c->opt.round_size) t = c->opt.round_size;
+        return std::min<uint64_t>(std::max<uint64_t>(t, ROUND_MIN), rmax);
+    };
+    // completes the round in flight: mesh size, loss share (a pool growth it asks for waits
+    // until no round is in flight)
+    auto land = [&]() -> int {
+        int rc = complete_round(c, fly);
+        if (rc) return rc;
+        const uint32_t won = c->hctr->won - won_seen;
+        won_seen = c->hctr->won;
+        c->mesh_vertices += won;
+        if (fly_cand) loss = 1.0 - (double)won / (double)fly_cand;
+        fly = -1;
+        return DT_OK;
+    };
     for (;;) {
         const int ci = c->list_idx, ni = ci ^ 1, oi = 2 + c->ovf_idx;
+        if (c->grow_pending) {
+            int rc = fly >= 0 ? land() : grow_if_pending(c);
+            if (rc) return rc;
+            continue;
+        }
+        if (fly >= 0) {
+            // plan the next round while the previous one runs
+            const uint64_t est = (uint64_t)std::llround(loss * (double)fly_cand);
+            const uint64_t target = target_size();
+            uint64_t W = 0;
+            if (next_rank < lv.total_ranks && target > est)
+                W = std::min<uint64_t>(target - est, lv.total_ranks - next_rank);
+            W = std::min<uint64_t>(W, rmax - fly_cand);
+            const uint64_t per = std::min<uint64_t>(c->capF, 48);
+            const uint64_t bound = fly_cand + W;
+            const bool ok = W > 0 && (!c->opt.max_rounds || rounds_this_call < c->opt.max_rounds) &&
+                            (uint64_t)c->hctr->list_count[oi] + fly_cand + bound <= rmax &&
+                            (uint64_t)c->hctr->tet_count + (fly_cand + bound) * per + 16 <= c->tcap;
+            if (ok) {
+                FillPlan plan;
+                const uint32_t w = (uint32_t)plan_fill(lv, next_rank, W, plan);
+                HIPCHK(launch_fill_list(plan, d_start, d_size, d_bits, d_rank_base, c->lord, c->dup.p, c->vtet.p,
+                                        c->lpt[ci], c->lrank[ci], &c->ctr->list_count[ci], c->stream));
+                next_rank += w;
+                int slot = -1;
+                int rc = enqueue_round(c, ci, ni, oi, fly_cand + w, c->capC, c->capF, base, n, fly, &slot);
+                if (rc) return rc;
+                c->list_idx = ni;
+                ++rounds_this_call;
+                if ((rc = land())) return rc;  // the previous round; its losers open this one
+                fly = slot;
+                fly_cand = c->hctr->list_count[ci] + w;
+                continue;
+            }
+            int rc = land();
+            if (rc) return rc;
+            continue;
+        }
+        // one round at a time, from exact counts
         const uint32_t nl = c->hctr->list_count[ci];
-        uint64_t target = (uint64_t)std::llround(frac * (double)c->mesh_vertices);
-        if (c->opt.round_size) target = c->opt.round_size;
-        target = std::max<uint64_t>(target, ROUND_MIN);
-        target = std::min<uint64_t>(target, rmax);
+        const uint64_t target = target_size();
         uint32_t W = 0;
         if (next_rank < lv.total_ranks && target > nl)
             W = (uint32_t)std::min<uint64_t>(target - nl, lv.total_ranks - next_rank);
@@ -519,6 +622,7 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint3
             if (c->hctr->list_count[oi] == 0) break;
             int rc = drain_overflow(c, base, n);
             if (rc) return rc;
+            won_seen = c->hctr->won;
             continue;
         }
         // overflowed candidates wait until the regular lists are done (by then their
@@ -527,6 +631,7 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint3
         if (c->hctr->list_count[oi] + nl + W > rmax) {
             int rc = drain_overflow(c, base, n);
             if (rc) return rc;
+            won_seen = c->hctr->won;
             continue;
         }
         if (c->opt.max_rounds && rounds_this_call >= c->opt.max_rounds)
@@ -539,10 +644,9 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint3
         const uint32_t max_cand = nl + W;
         int rc = ensure_capacity_for(c, max_cand, c->capF);
         if (rc) return rc;
-        const uint32_t won0 = c->hctr->won;
-        rc = run_one_round(c, ci, ni, oi, max_cand, c->capC, c->capF, base, n);
+        rc = enqueue_round(c, ci, ni, oi, max_cand, c->capC, c->capF, base, n, -1, &fly);
         if (rc) return rc;
-        c->mesh_vertices += c->hctr->won - won0;
+        fly_cand = max_cand;
         c->list_idx = ni;
         ++rounds_this_call;
     }
@@ -851,10 +955,14 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
     apply_options(c);
     if (!rc && (hipMalloc((void **)&c->ctr, sizeof(Ctr)) != hipSuccess ||
                 hipMalloc((void **)&c->stat, STAT_WORDS * sizeof(unsigned long long)) != hipSuccess ||
-                hipHostMalloc((void **)&c->hctr, sizeof(Ctr), hipHostMallocDefault) != hipSuccess))
+                hipHostMalloc((void **)&c->hring, 3 * sizeof(Ctr), hipHostMallocDefault) != hipSuccess))
         rc = DT_E_DEVICE;
-    for (int k = 0; k < 3 && !rc; ++k)
-        if (hipEventCreate(&c->ev[k]) != hipSuccess) rc = DT_E_DEVICE;
+    if (!rc) c->hctr = c->hring;
+    for (int k = 0; k < 3 && !rc; ++k) {
+        for (int j = 0; j < 3 && !rc; ++j)
+            if (hipEventCreate(&c->ev[k][j]) != hipSuccess) rc = DT_E_DEVICE;
+        if (!rc && hipEventCreateWithFlags(&c->evdone[k], hipEventDisableTiming) != hipSuccess) rc = DT_E_DEVICE;
+    }
     if (!rc && (hipMemsetAsync(c->ctr, 0, sizeof(Ctr), c->stream) != hipSuccess ||
                 hipMemsetAsync(c->stat, 0, STAT_WORDS * sizeof(unsigned long long), c->stream) != hipSuccess ||
                 hipStreamSynchronize(c->stream) != hipSuccess))
@@ -864,7 +972,7 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
         dt_destroy(c);
         return rc;
     }
-    std::memset(c->hctr, 0, sizeof(Ctr));
+    std::memset(c->hring, 0, 3 * sizeof(Ctr));
     *out = c;
     return DT_OK;
 }
@@ -1278,7 +1386,9 @@ int dt_clear(dt_ctx *c) {
     HIPCHK(hipMemsetAsync(c->ctr, 0, sizeof(Ctr), c->stream));
     HIPCHK(hipMemsetAsync(c->stat, 0, STAT_WORDS * sizeof(unsigned long long), c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    std::memset(c->hctr, 0, sizeof(Ctr));
+    std::memset(c->hring, 0, 3 * sizeof(Ctr));
+    c->hctr = c->hring;
+    c->grow_pending = false;
     c->npoints = c->nv = 0;
     c->have_mesh = false;
     c->mesh_vertices = 0;
@@ -1302,7 +1412,7 @@ int dt_destroy(dt_ctx *c) {
     f(c->scr_v); f(c->scr_n);
     f(c->ctr);
     f(c->stat);
-    if (c->hctr) hipHostFree(c->hctr);
+    if (c->hring) hipHostFree(c->hring);
     f(c->staging.p); f(c->keys.p); f(c->keys_tmp.p); f(c->table.p); f(c->vals.p); f(c->vals_tmp.p);
     f(c->hist.p); f(c->scan_tmp.p); f(c->small.p); f(c->small64.p);
     f(c->clouds.p); f(c->off.p); f(c->ch_start.p); f(c->ch_end.p); f(c->cloud_ch.p); f(c->partial.p);
@@ -1310,8 +1420,11 @@ int dt_destroy(dt_ctx *c) {
     f(c->lev.p); f(c->wbucket.p); f(c->log_att.p); f(c->feat.p); f(c->ypred.p);
     f(c->w32.p); f(c->m1.p); f(c->m2.p); f(c->grad.p); f(c->loss.p); f(c->wbf.p);
     f(c->oflags.p); f(c->omap.p); f(c->otets.p); f(c->onbrs.p); f(c->ovid.p);
-    for (int k = 0; k < 3; ++k)
-        if (c->ev[k]) hipEventDestroy(c->ev[k]);
+    for (int k = 0; k < 3; ++k) {
+        for (int j = 0; j < 3; ++j)
+            if (c->ev[k][j]) hipEventDestroy(c->ev[k][j]);
+        if (c->evdone[k]) hipEventDestroy(c->evdone[k]);
+    }
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     hipGetLastError();
     delete c;
