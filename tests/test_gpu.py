@@ -228,7 +228,8 @@ def test_append_and_clear(dtlib, oracle_mod):
                                   dict(round_size=1 << 16), dict(round_fraction=2.0), dict(seed=99),
                                   dict(lanes_per_insert=4), dict(lanes_per_insert=16),
                                   dict(lanes_per_insert=64), dict(lanes_per_insert=4, cavity_cap=200),
-                                  dict(cavity_cap=2048), dict(lanes_per_insert=16, cavity_cap=1500)])
+                                  dict(cavity_cap=2048), dict(lanes_per_insert=16, cavity_cap=1500),
+                                  dict(capacity_tets=4096)])
 def test_launch_options_do_not_change_result(dtlib, oracle_mod, opts):
     say(f"options {opts}")
     xyz = mix_small(51, 4000)
@@ -236,6 +237,8 @@ def test_launch_options_do_not_change_result(dtlib, oracle_mod, opts):
     assert_parity(oracle_mod, xyz, tets, str(opts))
     if opts.get("cavity_cap") == 4:
         assert st["overflows"] > 0
+    if "capacity_tets" in opts:  # the pool grew several times between rounds
+        assert len(tets) > 4 * opts["capacity_tets"]
 
 
 def test_round_limit(dtlib):
