@@ -157,7 +157,9 @@ int dt_autotune(dt_ctx *ctx, const double *xyz, uint64_t n, dt_options *best, do
    (log distances to its curve neighbours and anchor, BRIO level, position in the box) to a
    cost (predicted log2(1 + attempts)) and two walk-start logits (curve neighbour / anchor).
    With dt_options.scheduler = DT_SCHED_LEARNED each BRIO level is inserted in two halves,
-   the points predicted cheap first, and the walk starts where the MLP predicts. */
+   the points predicted cheap (cost at most the median training cost) first, and the walk
+   starts where the MLP predicts.  When the costly training points needed 3 attempts or
+   more on average, rounds over the costly halves are half the usual size. */
 
 /* After a dt_insert_points run with dt_options.log_points = 1: training samples of its
    points, in curve order - features (num_points x 16 fp32), cost target log2(1 + attempts)

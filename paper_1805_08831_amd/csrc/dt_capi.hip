@@ -29,7 +29,12 @@ constexpr uint32_t DEFAULT_CAVITY_CAP = 128;
 constexpr uint32_t DEFAULT_LANES = 8;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t ROUND_MIN = 64;
-constexpr uint32_t DRAIN_SLICE = 4096;  // candidates per round when draining overflowed cavities
+constexpr uint32_t DRAIN_SLICE = 4096;
+// learned order: where the points above the median training cost needed COSTLY_ATTEMPTS
+// attempts or more on average, rounds over the costly halves take COSTLY_ROUND_SCALE of the
+// usual size (fewer of these conflict-heavy points at once)
+constexpr uint32_t COSTLY_ATTEMPTS = 3;
+constexpr double COSTLY_ROUND_SCALE = 0.5;  // candidates per round when draining overflowed cavities
 
 uint64_t host_mix64(uint64_t z) {
     z += 0x9E3779B97F4A7C15ull;
@@ -140,6 +145,7 @@ struct dt_ctx {
     DevBuf<float> feat, ypred;
     bool have_model = false, logged = false;
     float thr = 0.0f;
+    float costly_scale = 1.0f;
     uint64_t log_base = 0, log_n = 0;
     DevBuf<float> w32, m1, m2, grad, loss;
     DevBuf<uint16_t> wbf;
@@ -274,6 +280,7 @@ struct Levels {
     std::vector<uint32_t> start, size, bits;  // start: offsets into the level-major order
     std::vector<unsigned long long> rank_base;
     uint64_t total_ranks = 0;
+    bool halves = false;  // learned order: level 2k + 1 holds the points of BRIO level k predicted costly
 };
 
 // device copies of the level tables live in c->small / c->small64
@@ -556,7 +563,14 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint3
     double loss = 0.5;       // share of candidates lost by the last completed round
     uint32_t won_seen = c->hctr->won;
     auto target_size = [&]() {
-        uint64_t t = (uint64_t)std::llround(frac * (double)c->mesh_vertices);
+        double f = frac;
+        if (lv.halves && next_rank < lv.total_ranks) {
+            // the points predicted costly conflict more: fewer of them per round
+            int k = 0;
+            while (k + 1 < lv.L && lv.rank_base[k + 1] <= next_rank) ++k;
+            if (k & 1) f *= c->costly_scale;
+        }
+        uint64_t t = (uint64_t)std::llround(f * (double)c->mesh_vertices);
         if (c->opt.round_size) t = c->opt.round_size;
         return std::min<uint64_t>(std::max<uint64_t>(t, ROUND_MIN), rmax);
     };
@@ -879,6 +893,7 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
         HIPCHK(hipStreamSynchronize(c->stream));
         L *= 2;
         compute_levels(hist, L, lv);
+        lv.halves = true;
         if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
         // anchors stay those of the BRIO levels: a half level is a sparse and, by the cost
         // prediction, uneven subset, and its records make far walk starts
@@ -1187,9 +1202,11 @@ int dt_autotune(dt_ctx *c, const double *xyz, uint64_t n, dt_options *best, doub
 namespace {
 
 constexpr uint32_t MODEL_MAGIC = 0x4C4D5444u;  // "DTML"
+// thr: cost above which a point goes to the costly half of its level; costly_scale: round
+// size factor for the costly halves
 struct ModelHeader {
     uint32_t magic, version, nfeat, nhid, nout, nparam;
-    float thr, loss;
+    float thr, costly_scale;
 };
 
 int model_buffers(dt_ctx *c) {
@@ -1307,14 +1324,23 @@ int dt_train_model(dt_ctx *c, const float *features, const float *cost, const ui
     hipFree(df.p);
     hipFree(dc.p);
     hipFree(db.p);
-    // split threshold of the scheduler: the median predicted cost of the training points
+    // split threshold of the scheduler: the median cost of the training points.  The rounds
+    // over the costly halves shrink only where the costly points are conflict-heavy: their
+    // mean cost in training reaches that of COSTLY_ATTEMPTS attempts
     std::vector<float> med(hc);
     std::nth_element(med.begin(), med.begin() + med.size() / 2, med.end());
-    ModelHeader h{MODEL_MAGIC, 1, NFEAT, NHID, NOUT, NPARAM, med[med.size() / 2], last};
+    const float thr = med[med.size() / 2];
+    double sum = 0.0;
+    uint64_t cnt = 0;
+    for (float v : hc)
+        if (v > thr) sum += v, ++cnt;
+    const bool heavy = cnt && sum / (double)cnt >= std::log2(1.0 + (double)COSTLY_ATTEMPTS);
+    ModelHeader h{MODEL_MAGIC, 2, NFEAT, NHID, NOUT, NPARAM, thr, heavy ? (float)COSTLY_ROUND_SCALE : 1.0f};
     std::memcpy(model, &h, sizeof h);
     std::memcpy((char *)model + sizeof h, w.data(), NPARAM * sizeof(float));
     *model_bytes = bytes;
     c->thr = h.thr;
+    c->costly_scale = h.costly_scale;
     c->have_model = true;
     return DT_OK;
 }
@@ -1324,7 +1350,7 @@ int dt_load_model(dt_ctx *c, const void *model, size_t bytes) {
     ModelHeader h;
     if (bytes < sizeof h) return fail(c, DT_E_ARG, "model too short");
     std::memcpy(&h, model, sizeof h);
-    if (h.magic != MODEL_MAGIC || h.version != 1 || h.nfeat != (uint32_t)NFEAT || h.nhid != (uint32_t)NHID ||
+    if (h.magic != MODEL_MAGIC || h.version != 2 || h.nfeat != (uint32_t)NFEAT || h.nhid != (uint32_t)NHID ||
         h.nout != (uint32_t)NOUT || h.nparam != (uint32_t)NPARAM || bytes < sizeof h + NPARAM * sizeof(float))
         return fail(c, DT_E_ARG, "not a model of this library (%u-%u-%u)", h.nfeat, h.nhid, h.nout);
     HIPCHK(hipSetDevice(c->device));
@@ -1335,6 +1361,7 @@ int dt_load_model(dt_ctx *c, const void *model, size_t bytes) {
     HIPCHK(launch_to_bf16(c->w32.p, c->wbf.p, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->thr = h.thr;
+    c->costly_scale = h.costly_scale;
     c->have_model = true;
     return DT_OK;
 }
