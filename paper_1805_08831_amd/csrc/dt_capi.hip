@@ -1307,17 +1307,12 @@ int dt_train_model(dt_ctx *c, const float *features, const float *cost, const ui
     HIPCHK(launch_to_bf16(c->w32.p, c->wbf.p, c->stream));
     constexpr uint32_t BATCH = 4096;
     int t = 0;
-    float last = 0.0f;
     for (uint32_t e = 0; e < epochs; ++e) {
-        HIPCHK(hipMemsetAsync(c->loss.p, 0, sizeof(float), c->stream));
         for (uint64_t b0 = 0; b0 < n; b0 += BATCH) {
             const uint32_t nb = (uint32_t)std::min<uint64_t>(BATCH, n - b0);
-            HIPCHK(launch_mlp_grad(c->wbf.p, df.p, dc.p, db.p, b0, nb, c->grad.p, c->loss.p, c->stream));
+            HIPCHK(launch_mlp_grad(c->wbf.p, df.p, dc.p, db.p, b0, nb, c->grad.p, nullptr, c->stream));
             HIPCHK(launch_adam(c->w32.p, c->grad.p, c->m1.p, c->m2.p, c->wbf.p, lr, ++t, c->stream));
         }
-        HIPCHK(hipMemcpyAsync(&last, c->loss.p, sizeof(float), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        last /= (float)n;
     }
     HIPCHK(hipMemcpyAsync(w.data(), c->w32.p, NPARAM * sizeof(float), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

@@ -69,10 +69,11 @@ __device__ __forceinline__ void add_stat(unsigned long long *stat, int id, unsig
 }
 
 // Reserves v units of the counter *count per thread with one atomic per block (the block is
-// 256 threads; every thread must call it): returns the first unit of this thread's range.
-// tmp: 5 words of LDS the block does not use meanwhile.
+// NW waves; every thread must call it): returns the first unit of this thread's range.
+// tmp: NW + 1 words of LDS the block does not use meanwhile.
+template <int NW = 4>
 __device__ __forceinline__ uint32_t block_reserve(uint32_t v, uint32_t *count, uint32_t *tmp) {
-    uint32_t *s_wave = tmp, &s_base = tmp[4];
+    uint32_t *s_wave = tmp, &s_base = tmp[NW];
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     uint32_t x = v;
     for (int o = 1; o < 64; o <<= 1) {
@@ -83,7 +84,7 @@ __device__ __forceinline__ uint32_t block_reserve(uint32_t v, uint32_t *count, u
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t t = 0;
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < NW; ++w) {
             const uint32_t c = s_wave[w];
             s_wave[w] = t;
             t += c;
@@ -614,6 +615,9 @@ constexpr uint32_t LOC_BOUNDARY = 0x80000000u;
 constexpr uint32_t HT = 128;             // edge table entries per candidate
 constexpr uint32_t HT_MAX_FACETS = 64;   // balls up to this size use the table (load <= 3/4)
 constexpr unsigned long long HT_EMPTY = ~0ull;
+// threads per block of the ball kernel: the slot reservation is one atomic per block on one
+// counter, so larger blocks contend less (at the cost of LDS occupancy)
+constexpr int BALL_BLOCK = 1024;
 
 // orders the memory accesses of one group (all in one wave) across phases
 __device__ __forceinline__ void group_fence() {
@@ -625,9 +629,9 @@ __device__ __forceinline__ uint32_t edge_hash(unsigned long long key) {
     return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits: HT = 128
 }
 
-template <int GL>
-__global__ __launch_bounds__(256) void k_ball(RoundArgs a) {
-    constexpr uint32_t GPB = 256 / GL;
+template <int GL, int BS>
+__global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
+    constexpr uint32_t GPB = BS / GL;
     __shared__ unsigned long long s_key[GPB][HT];
     __shared__ uint32_t s_val[GPB][HT][2];
     const uint32_t lane = threadIdx.x & 63u;
@@ -665,7 +669,7 @@ __global__ __launch_bounds__(256) void k_ball(RoundArgs a) {
     // the rest are fresh pool slots from tet_count on); C - F surplus cavity slots are freed
     const bool leader = win && gl == 0;
     const uint32_t need = leader && nb > nc ? nb - nc : 0u;
-    const uint32_t u0 = block_reserve(need, &a.ctr->fl_take, &s_val[0][0][0]);
+    const uint32_t u0 = block_reserve<BS / 64>(need, &a.ctr->fl_take, &s_val[0][0][0]);
     const uint32_t fln = a.ctr->fl_n, tc0 = a.ctr->tet_count;
     const bool full = need && u0 + need > fln && tc0 + (u0 + need - fln) > a.tcap;
     if (full) {
@@ -949,7 +953,7 @@ hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, h
         k_cavity_g<16, LCAPC, LHM, false><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
     }
     if (ev) hipEventRecord(ev[1], s);
-    k_ball<16><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
+    k_ball<16, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 16 - 1) / (BALL_BLOCK / 16), BALL_BLOCK, 0, s>>>(a);
     if (ev) hipEventRecord(ev[2], s);
     return hipGetLastError();
 }

@@ -202,10 +202,10 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const uint16_t *__restrict__ w
     __syncthreads();
     for (int k = threadIdx.x; k < NPARAM; k += blockDim.x)
         if (g[k] != 0.0f) atomicAdd(&grad[k], g[k]);
-    // loss sum (for monitoring)
+    // loss sum (for the gradient check; training passes no loss buffer)
     float s = my_loss;
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss, s);
+    if (loss && (threadIdx.x & 63) == 0) atomicAdd(loss, s);
 }
 
 hipError_t launch_mlp_grad(const uint16_t *wbf, const float *feat, const float *cost, const uint8_t *bucket,
