@@ -748,7 +748,6 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
             ol[b] = me;
             for (int q = 0; q < 4; ++q)
                 if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
-            if (b == 0) a.clouds[a.V[p].idx >> 32].any_live = slot;
             if (table) {
                 // the three facets through p: facet q holds p and the edge of the boundary
                 // facet without vertex q
@@ -853,11 +852,19 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
                 nref(a.T, slot, q) = res;
             }
         }
-        // E: cavity slots beyond the ball's size are freed
-        for (uint32_t k = nb + gl; k < nc; k += GL) {
-            const uint32_t c = cavl[k] >> 2;
-            a.T[c].v.x = DEAD;
-            a.fl_next[g_fb + (k - nb)] = c;
+        // E: cavity slots beyond the ball's size are freed.  The cloud's known live
+        // tetrahedron stays live unless it is one of them (the other cavity slots hold the
+        // new tetrahedra): then it moves to the ball's first tetrahedron.  Only this rare
+        // case writes it, so winners do not all store to one address.
+        if (nc > nb) {
+            Cloud *cl = &a.clouds[a.V[p].idx >> 32];
+            const uint32_t live = cl->any_live;
+            for (uint32_t k = nb + gl; k < nc; k += GL) {
+                const uint32_t c = cavl[k] >> 2;
+                a.T[c].v.x = DEAD;
+                a.fl_next[g_fb + (k - nb)] = c;
+                if (c == live) cl->any_live = cavl[0] >> 2;
+            }
         }
         if (gl == 0) {
             cav_w = nc;
