@@ -746,8 +746,10 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
             nref(a.T, slot, f) = oc;           // facet opposite p: the outer tetrahedron
             nref(a.T, oc >> 2, oc & 3u) = me;  // and back
             ol[b] = me;
+            // vertex hints: the cavity boundary's vertices from every new tetrahedron on them,
+            // the new point (vertex f of each) from the first only
             for (int q = 0; q < 4; ++q)
-                if (wv[q] != GHOST) a.vtet[wv[q]] = slot;
+                if (wv[q] != GHOST && (q != f || b == 0)) a.vtet[wv[q]] = slot;
             if (table) {
                 // the three facets through p: facet q holds p and the edge of the boundary
                 // facet without vertex q
