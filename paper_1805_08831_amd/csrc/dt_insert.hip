@@ -46,17 +46,6 @@ __device__ __forceinline__ uint32_t &nref(Tet *T, uint32_t t, uint32_t f) {
     return reinterpret_cast<uint32_t *>(&T[t].n)[f];
 }
 
-// appends the lanes with `keep` to a list at *count, in lane order, with one atomic per wave;
-// returns the position of this lane's entry (valid where keep)
-__device__ __forceinline__ uint32_t wave_append(bool keep, uint32_t *count) {
-    const unsigned long long m = __ballot(keep);
-    const uint32_t lane = threadIdx.x & 63u;
-    uint32_t base = 0;
-    if (lane == 0 && m) base = atomicAdd(count, (uint32_t)__popcll(m));
-    base = __shfl(base, 0);
-    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-}
-
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -218,7 +207,12 @@ hipError_t launch_init(const Vert *V, Cloud *clouds, uint32_t nclouds, uint32_t 
 // order of bitreverse_w of the rank's low bits: thread s takes l = a + bitreverse_w(s), so
 // the block's candidates come out in curve order.  A wave appends its valid candidates
 // with one atomic, in thread order.
-__global__ void k_fill(FillPlan plan, const uint32_t *__restrict__ lvl_start, const uint32_t *__restrict__ lvl_size,
+// Round-start and round-end kernels append to shared list counters with one atomic per
+// 1024-thread block: one address takes about one atomic per 12 ns, so per-wave appends from
+// a large round serialize for several microseconds.
+constexpr int FILL_BLOCK = 1024;
+
+__global__ __launch_bounds__(FILL_BLOCK) void k_fill(FillPlan plan, const uint32_t *__restrict__ lvl_start, const uint32_t *__restrict__ lvl_size,
                        const uint32_t *__restrict__ lvl_bits, const unsigned long long *__restrict__ rank_base,
                        const uint32_t *__restrict__ lord, const uint8_t *__restrict__ dup,
                        const uint32_t *__restrict__ vtet, uint32_t *__restrict__ cand_pt,
@@ -240,7 +234,8 @@ __global__ void k_fill(FillPlan plan, const uint32_t *__restrict__ lvl_start, co
             r = (uint32_t)(rank_base[k] + local);
         }
     }
-    const uint32_t pos = wave_append(ok, ncand);
+    __shared__ uint32_t s_tmp[FILL_BLOCK / 64 + 1];
+    const uint32_t pos = block_reserve<FILL_BLOCK / 64>(ok ? 1u : 0u, ncand, s_tmp);
     if (ok) {
         cand_pt[pos] = p;
         cand_rank[pos] = r;
@@ -253,7 +248,7 @@ hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, con
                             uint32_t *ncand, hipStream_t s) {
     const uint32_t count = plan.off[plan.nblk];
     if (count == 0) return hipSuccess;
-    k_fill<<<(count + 255) / 256, 256, 0, s>>>(plan, lvl_start, lvl_size, lvl_bits, rank_base, lord, dup, vtet,
+    k_fill<<<(count + FILL_BLOCK - 1) / FILL_BLOCK, FILL_BLOCK, 0, s>>>(plan, lvl_start, lvl_size, lvl_bits, rank_base, lord, dup, vtet,
                                                cand_pt, cand_rank, ncand);
     return hipGetLastError();
 }
@@ -879,15 +874,17 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
 
 // ------------------------------------------------------------------ round end
 
-__global__ void k_compact(RoundArgs a) {
+__global__ __launch_bounds__(FILL_BLOCK) void k_compact(RoundArgs a) {
+    constexpr int NW = FILL_BLOCK / 64;
+    __shared__ uint32_t s_tmp[NW + 1];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ncand = *a.ncand_ptr;
     const uint8_t s = i < ncand ? a.status[i] : (uint8_t)ST_NONE;
     const bool again = i < ncand && (s == ST_CONFLICT || s == ST_CAND);
     const bool ovf = i < ncand && s == ST_OVERFLOW;
     if (a.log_att && i < ncand) atomicAdd(&a.log_att[a.cand_pt[i] - a.vlo], 1u);
-    const uint32_t pn = wave_append(again, a.nnext_ptr);
-    const uint32_t po = wave_append(ovf, a.novf_ptr);
+    const uint32_t pn = block_reserve<NW>(again ? 1u : 0u, a.nnext_ptr, s_tmp);
+    const uint32_t po = block_reserve<NW>(ovf ? 1u : 0u, a.novf_ptr, s_tmp);
     if (again) {
         a.next_pt[pn] = a.cand_pt[i];
         a.next_rank[pn] = a.cand_rank[i];
@@ -896,16 +893,12 @@ __global__ void k_compact(RoundArgs a) {
         a.ovf_pt[po] = a.cand_pt[i];
         a.ovf_rank[po] = a.cand_rank[i];
     }
-    const unsigned n_again = wave_sum(again ? 1u : 0u), n_ovf = wave_sum(ovf ? 1u : 0u);
-    const unsigned n_won = wave_sum(i < ncand && s == ST_WON ? 1u : 0u);
-    const unsigned n_dup = wave_sum(i < ncand && s == ST_DUP ? 1u : 0u);
+    // the round's counts: one atomic per block and counter
+    block_reserve<NW>(again ? 1u : 0u, &a.ctr->conflicts, s_tmp);
+    block_reserve<NW>(ovf ? 1u : 0u, &a.ctr->overflows, s_tmp);
+    block_reserve<NW>(i < ncand && s == ST_WON ? 1u : 0u, &a.ctr->won, s_tmp);
+    block_reserve<NW>(i < ncand && s == ST_DUP ? 1u : 0u, &a.ctr->dups, s_tmp);
     const bool bad = i < ncand && !(again || ovf || s == ST_WON || s == ST_DUP);
-    if ((threadIdx.x & 63u) == 0) {
-        if (n_again) atomicAdd(&a.ctr->conflicts, n_again);
-        if (n_ovf) atomicAdd(&a.ctr->overflows, n_ovf);
-        if (n_won) atomicAdd(&a.ctr->won, n_won);
-        if (n_dup) atomicAdd(&a.ctr->dups, n_dup);
-    }
     if (bad) atomicOr(&a.ctr->error, ERR_WALK);
 }
 
@@ -968,7 +961,7 @@ hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, h
 }
 
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s) {
-    if (max_cand) k_compact<<<(max_cand + 255) / 256, 256, 0, s>>>(a);
+    if (max_cand) k_compact<<<(max_cand + FILL_BLOCK - 1) / FILL_BLOCK, FILL_BLOCK, 0, s>>>(a);
     k_freelist_carry<<<256, 256, 0, s>>>(a);
     k_roll<<<1, 64, 0, s>>>(a.ctr, const_cast<uint32_t *>(a.ncand_ptr), a.tcap, a.stat);
     return hipGetLastError();
