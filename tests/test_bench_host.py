@@ -1,0 +1,52 @@
+"""CPU checks of the benchmark's host logic: the algorithmic byte model, the gating of the
+measured HBM traffic on the kernel sources it was taken on, and the one-GPU guard."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench_host", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_cavity_byte_model():
+    b = load_bench()
+    # an attempt with no walk and an empty cavity still reads its candidate and point and the
+    # two initial vertex records of an empty boundary
+    assert b.cavity_bytes_per_attempt(0, 0, 0) == 48 + 32 * 2
+    # each term is linear in its count: walk steps 64 B, cavity tetrahedra 52 B, facets 56 B
+    base = b.cavity_bytes_per_attempt(0, 0, 0)
+    assert b.cavity_bytes_per_attempt(1, 0, 0) - base == 64
+    assert b.cavity_bytes_per_attempt(0, 1, 0) - base == 32 + 16 + 4
+    assert b.cavity_bytes_per_attempt(0, 0, 2) - base == 2 * (16 + 16 + 8) + 32
+    # the uniform workload's measured shape (W 5.7, C 20, F 26.8) is about 3 KB
+    assert 2900 < b.cavity_bytes_per_attempt(5.7, 20.04, 26.8) < 3100
+
+
+def test_traffic_is_used_only_for_matching_sources(tmp_path, monkeypatch):
+    b = load_bench()
+    summary = open(b.PMC_SUMMARY).read()
+    # the committed summary carries the hash of the committed kernel sources
+    assert b.measured_traffic() is not None and b.measured_traffic() > 1e8
+    # a summary taken on other sources is ignored
+    stale = summary.replace("kernel_source_sha256 = ", "kernel_source_sha256 = 0")
+    p = tmp_path / "stale.md"
+    p.write_text(stale)
+    monkeypatch.setattr(b, "PMC_SUMMARY", str(p))
+    assert b.measured_traffic() is None
+    # as is a missing one
+    monkeypatch.setattr(b, "PMC_SUMMARY", str(tmp_path / "missing.md"))
+    assert b.measured_traffic() is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
