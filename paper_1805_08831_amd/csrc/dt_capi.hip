@@ -29,12 +29,12 @@ constexpr uint32_t DEFAULT_CAVITY_CAP = 128;
 constexpr uint32_t DEFAULT_LANES = 8;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t ROUND_MIN = 64;
-constexpr uint32_t DRAIN_SLICE = 4096;
+constexpr uint32_t DRAIN_SLICE = 4096;  // candidates per round when draining overflowed cavities
 // learned order: where the points above the median training cost needed COSTLY_ATTEMPTS
 // attempts or more on average, rounds over the costly halves take COSTLY_ROUND_SCALE of the
 // usual size (fewer of these conflict-heavy points at once)
 constexpr uint32_t COSTLY_ATTEMPTS = 3;
-constexpr double COSTLY_ROUND_SCALE = 0.5;  // candidates per round when draining overflowed cavities
+constexpr double COSTLY_ROUND_SCALE = 0.5;
 
 uint64_t host_mix64(uint64_t z) {
     z += 0x9E3779B97F4A7C15ull;
