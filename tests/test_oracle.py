@@ -273,6 +273,54 @@ def test_moore_level(oracle_mod):
     assert oracle_mod.moore_level(2) == 1
 
 
+@pytest.mark.parametrize("m", [2, 5])
+def test_moore_keys_cells_by_construction(oracle_mod, m):
+    """Points placed at the centres of known cells of a 2^m grid; two corner points fix the
+    bounding box to [0, 2^m] on the long axes, so each point's cell is known without the
+    quantisation formula.  The short y axis (half the extent) shares the long axes' scale."""
+    g = 1 << m
+    r = np.random.default_rng(m)
+    cells = np.stack([r.integers(0, g, 500), r.integers(0, g // 2, 500), r.integers(0, g, 500)], axis=1)
+    xyz = np.vstack([cells + 0.5, [[0.0, 0.0, 0.0], [g, g / 2, g]]])
+    keys = oracle_mod.moore_keys(xyz, m)
+    want = [oracle_mod.moore_index(c, m) for c in cells]
+    assert np.array_equal(keys[:500], np.array(want, dtype=np.uint64))
+    # the low corner is cell (0, 0, 0); the high corner sits on the grid's far faces and
+    # belongs to the last cell along x and z, and to cell g/2 along y
+    assert keys[500] == oracle_mod.moore_index([0, 0, 0], m)
+    assert keys[501] == oracle_mod.moore_index([g - 1, g // 2, g - 1], m)
+
+
+def test_stable_sort_is_numpy_stable_argsort(oracle_mod):
+    """The oracle's sort is the stable sort: equal keys keep the input order."""
+    r = np.random.default_rng(7)
+    for n, hi in [(1, 5), (1000, 7), (50000, 1 << 40), (50000, 100)]:
+        keys = r.integers(0, hi, size=n, dtype=np.uint64)
+        assert np.array_equal(oracle_mod.stable_sort(keys), np.argsort(keys, kind="stable"))
+    keys = np.array([2 ** 64 - 1, 0, 2 ** 63, 2 ** 63 - 1, 0], dtype=np.uint64)
+    assert list(oracle_mod.stable_sort(keys)) == [1, 4, 3, 2, 0]
+
+
+def test_sort_reference_is_level_major_moore_order(oracle_mod):
+    """The insertion order: BRIO levels in turn (sizes as the level table gives them), each
+    level along the Moore curve, ties by input index."""
+    xyz = uniform_points(40000, 31)
+    keys, perm, m, cum = oracle_mod.sort_reference(xyz, 5)
+    assert np.array_equal(np.sort(perm), np.arange(len(xyz)))
+    lev = (keys >> np.uint64(3 * m)).astype(np.int64)
+    mk = keys & np.uint64((1 << (3 * m)) - 1)
+    assert np.array_equal(mk, oracle_mod.moore_keys(xyz, m))
+    lv, _ = oracle_mod.brio_levels(len(xyz), 5)
+    assert np.array_equal(lev, lv.astype(np.int64))
+    sl, sk = lev[perm], mk[perm]
+    assert np.all(np.diff(sl) >= 0)
+    same = sl[1:] == sl[:-1]
+    assert np.all(sk[1:][same] >= sk[:-1][same])
+    tie = same & (sk[1:] == sk[:-1])
+    assert np.all(perm[1:][tie] > perm[:-1][tie])
+    assert list(cum) == [2048, 14336, 40000]
+
+
 def test_brio_rounds_match_paper_table(oracle_mod):
     lines = [l.split() for l in open(os.path.join(GOLDEN, "brio_rounds_1e6.txt"))
              if l.strip() and not l.startswith("#")]
