@@ -59,3 +59,46 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(dt, "_lib", None)
     with pytest.raises(RuntimeError):
         dt.lib()
+
+
+def test_every_entry_point_rejects_a_null_context(libdt):
+    """Each entry point that takes a context returns DT_E_ARG for NULL, touching nothing."""
+    from paper_1805_08831_amd import dt
+    L = dt.lib()
+    n = None
+    calls = {
+        "dt_insert_points": (n, n, 0),
+        "dt_insert_batch": (n, n, n, 0),
+        "dt_get_tets": (n, n, n, n),
+        "dt_get_tets_batch": (n, 0, n, n, n),
+        "dt_autotune": (n, n, 0, n, n),
+        "dt_get_point_log": (n, n, n, n, n),
+        "dt_train_model": (n, n, n, n, 0, 0, 0.0, 0, n, n),
+        "dt_load_model": (n, n, 0),
+        "dt_debug_mlp": (n, n, 0, n),
+        "dt_debug_mlp_grad": (n, n, n, n, 0, n, n),
+        "dt_debug_sort": (n, n, 0, n, n, n),
+        "dt_debug_predicates": (n, 0, n, n, 0, n),
+        "dt_clear": (n,),
+        "dt_destroy": (n,),
+        "dt_get_stats": (n, n),
+    }
+    assert set(calls) | {"dt_default_options", "dt_create", "dt_last_error"} == set(declared_functions())
+    for name, args in calls.items():
+        assert getattr(L, name)(*args) == dt.DT_E_ARG, name
+
+
+def test_create_without_a_device_fails_cleanly(libdt):
+    """With valid options, dt_create either succeeds (a GPU is present) or returns
+    DT_E_DEVICE with the handle cleared; it never returns a half-built context."""
+    from paper_1805_08831_amd import dt
+    o = dt.dt_options()
+    dt.lib().dt_default_options(ctypes.byref(o))
+    o.device = 0
+    h = ctypes.c_void_p(1)
+    rc = dt.lib().dt_create(ctypes.byref(h), ctypes.byref(o))
+    if rc == dt.DT_OK:
+        assert h.value
+        assert dt.lib().dt_destroy(h) == dt.DT_OK
+    else:
+        assert rc == dt.DT_E_DEVICE and not h.value
