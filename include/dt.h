@@ -163,7 +163,9 @@ int dt_autotune(dt_ctx *ctx, const double *xyz, uint64_t n, dt_options *best, do
 
 /* After a dt_insert_points run with dt_options.log_points = 1: training samples of its
    points, in curve order - features (num_points x 16 fp32), cost target log2(1 + attempts)
-   and bucket label (1 when the anchor is closer to the point than both curve neighbours).
+   and bucket label (1 when the anchor is closer to the point than every curve neighbour
+   within 4 records that belongs to a lower BRIO level, and at least one such neighbour
+   exists; 0 otherwise).
    *num_points in/out as in dt_get_tets (NULL buffers: query).  Host or device pointers. */
 int dt_get_point_log(dt_ctx *ctx, float *features, float *cost, uint8_t *bucket, uint64_t *num_points);
 
