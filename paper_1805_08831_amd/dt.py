@@ -101,10 +101,45 @@ def _ptr(x):
     if x is None:
         return None
     if isinstance(x, np.ndarray):
-        assert x.flags["C_CONTIGUOUS"]
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array is not C-contiguous")
         return x.ctypes.data
-    assert x.is_contiguous()
+    if not x.is_contiguous():
+        raise ValueError("tensor is not contiguous")
     return x.data_ptr()
+
+
+def _dtype(x):
+    return str(x.dtype).replace("torch.", "")
+
+
+def _numel(x):
+    return int(x.size) if isinstance(x, np.ndarray) else int(x.numel())
+
+
+def _points(xyz, n=None):
+    """Checks an n x 3 float64 point buffer (the library reads 24 n bytes from it) and
+    returns (address, n)."""
+    if _dtype(xyz) != "float64":
+        raise ValueError(f"points must be float64, got {xyz.dtype}")
+    if n is None:
+        if len(xyz.shape) != 2 or int(xyz.shape[1]) != 3:
+            raise ValueError(f"points must have shape (n, 3), got {tuple(xyz.shape)}")
+        n = int(xyz.shape[0])
+    if _numel(xyz) < 3 * int(n):
+        raise ValueError(f"{int(n)} points need {3 * int(n)} values, the buffer holds {_numel(xyz)}")
+    return _ptr(xyz), int(n)
+
+
+def _out(buf, dtypes, count, what):
+    """Checks an output buffer of at least `count` elements of one of `dtypes`."""
+    if buf is None:
+        return None
+    if _dtype(buf) not in dtypes:
+        raise ValueError(f"{what} must be {' or '.join(dtypes)}, got {buf.dtype}")
+    if _numel(buf) < count:
+        raise ValueError(f"{what} holds {_numel(buf)} elements, {count} needed")
+    return _ptr(buf)
 
 
 # --------------------------------------------------------------------- C-ABI mirror
@@ -129,32 +164,43 @@ def _check(ctx, rc):
 
 
 def dt_insert_points(ctx, xyz, n=None):
-    n = int(xyz.shape[0]) if n is None else int(n)
-    _check(ctx, lib().dt_insert_points(ctx, _ptr(xyz), n))
+    p, n = _points(xyz, n)
+    _check(ctx, lib().dt_insert_points(ctx, p, n))
+
+
+_TET_TYPES, _NBR_TYPES = ("int32", "uint32"), ("int64",)
 
 
 def dt_get_tets(ctx, tets=None, nbrs=None, capacity=0):
     num = ctypes.c_uint64(capacity)
-    _check(ctx, lib().dt_get_tets(ctx, _ptr(tets), _ptr(nbrs), ctypes.byref(num)))
+    pt = _out(tets, _TET_TYPES, 4 * int(capacity), "tets")
+    pn = _out(nbrs, _NBR_TYPES, 4 * int(capacity), "nbrs")
+    _check(ctx, lib().dt_get_tets(ctx, pt, pn, ctypes.byref(num)))
     return int(num.value)
 
 
 def dt_insert_batch(ctx, xyz, offsets):
     """offsets: host array of num_clouds + 1 uint64 (numpy)."""
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
-    _check(ctx, lib().dt_insert_batch(ctx, _ptr(xyz), off.ctypes.data, int(len(off) - 1)))
+    if len(off) < 2:
+        raise ValueError("offsets must hold num_clouds + 1 >= 2 entries")
+    p, _ = _points(xyz, int(off[-1]))
+    _check(ctx, lib().dt_insert_batch(ctx, p, off.ctypes.data, int(len(off) - 1)))
 
 
 def dt_get_tets_batch(ctx, cloud, tets=None, nbrs=None, capacity=0):
     num = ctypes.c_uint64(capacity)
-    _check(ctx, lib().dt_get_tets_batch(ctx, int(cloud), _ptr(tets), _ptr(nbrs), ctypes.byref(num)))
+    pt = _out(tets, _TET_TYPES, 4 * int(capacity), "tets")
+    pn = _out(nbrs, _NBR_TYPES, 4 * int(capacity), "nbrs")
+    _check(ctx, lib().dt_get_tets_batch(ctx, int(cloud), pt, pn, ctypes.byref(num)))
     return int(num.value)
 
 
 def dt_autotune(ctx, xyz):
     """Returns (chosen dt_options, ms of the chosen configuration on the sample)."""
     best, ms = dt_options(), ctypes.c_double(0.0)
-    _check(ctx, lib().dt_autotune(ctx, _ptr(xyz), int(xyz.shape[0]), ctypes.byref(best), ctypes.byref(ms)))
+    p, n = _points(xyz)
+    _check(ctx, lib().dt_autotune(ctx, p, n, ctypes.byref(best), ctypes.byref(ms)))
     return best, float(ms.value)
 
 
@@ -222,19 +268,24 @@ def dt_get_stats(ctx):
 
 
 def dt_debug_sort(ctx, xyz):
-    n = int(xyz.shape[0])
+    p, n = _points(xyz)
     keys = np.empty(n, dtype=np.uint64)
     perm = np.empty(n, dtype=np.uint32)
     m = ctypes.c_int(0)
-    _check(ctx, lib().dt_debug_sort(ctx, _ptr(xyz), n, keys.ctypes.data, perm.ctypes.data, ctypes.byref(m)))
+    _check(ctx, lib().dt_debug_sort(ctx, p, n, keys.ctypes.data, perm.ctypes.data, ctypes.byref(m)))
     return keys, perm, int(m.value)
 
 
 def dt_debug_predicates(ctx, kind, pts, idx=None):
     pts = np.ascontiguousarray(pts, dtype=np.float64)
     k = int(pts.shape[0])
+    npts = 4 if int(kind) == 0 else 5
+    if pts.size != 3 * npts * k:
+        raise ValueError(f"kind {kind} needs {npts} points (x, y, z) per record, {3 * npts * k} values")
     out = np.empty(k, dtype=np.int8)
     idx = None if idx is None else np.ascontiguousarray(idx, dtype=np.int64)
+    if idx is not None and idx.size != 5 * k:
+        raise ValueError("idx must hold 5 input indices per record")
     _check(ctx, lib().dt_debug_predicates(ctx, int(kind), pts.ctypes.data, _ptr(idx), k, out.ctypes.data))
     return out
 
@@ -259,7 +310,6 @@ class Triangulation:
     def insert(self, xyz):
         if isinstance(xyz, np.ndarray):
             xyz = np.ascontiguousarray(xyz, dtype=np.float64)
-        assert xyz.ndim == 2 and xyz.shape[1] == 3
         dt_insert_points(self.ctx, xyz)
 
     def insert_batch(self, xyz, offsets):

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -102,3 +103,53 @@ def test_create_without_a_device_fails_cleanly(libdt):
         assert dt.lib().dt_destroy(h) == dt.DT_OK
     else:
         assert rc == dt.DT_E_DEVICE and not h.value
+
+
+def test_binding_checks_buffers_before_the_library(libdt):
+    """The binding rejects buffers the library would read or write out of bounds (wrong
+    dtype, shape or size, or not contiguous) with ValueError, before any library call; valid
+    buffers reach the library (here with no context: DT_E_ARG)."""
+    import torch
+    from paper_1805_08831_amd import dt
+    bad_points = [np.zeros((5, 3), np.float32), np.zeros((5, 2)), np.zeros((3, 5))[:, :3],
+                  torch.zeros((5, 3), dtype=torch.float32), np.zeros((5, 3, 1))]
+    for x in bad_points:
+        with pytest.raises(ValueError):
+            dt.dt_insert_points(None, x)
+        with pytest.raises(ValueError):
+            dt.dt_autotune(None, x)
+    with pytest.raises(ValueError):
+        dt.dt_insert_points(None, np.zeros(9), n=4)
+    with pytest.raises(ValueError):
+        dt.dt_insert_batch(None, np.zeros((10, 3)), [0, 5, 11])
+    with pytest.raises(ValueError):
+        dt.dt_insert_batch(None, np.zeros((10, 3)), [0])
+    for t, nb in [(np.zeros((3, 4), np.int64), None), (np.zeros((2, 4), np.int32), None),
+                  (None, np.zeros((3, 4), np.int32)), (None, np.zeros((2, 4), np.int64)),
+                  (torch.zeros((3, 4), dtype=torch.float32), None), (np.zeros((4, 3), np.int32).T, None)]:
+        with pytest.raises(ValueError):
+            dt.dt_get_tets(None, t, nb, 3)
+        with pytest.raises(ValueError):
+            dt.dt_get_tets_batch(None, 0, t, nb, 3)
+    with pytest.raises(ValueError):
+        dt.dt_debug_predicates(None, 1, np.zeros((4, 12)))
+    with pytest.raises(ValueError):
+        dt.dt_debug_predicates(None, 2, np.zeros((4, 15)), np.zeros((4, 4), np.int64))
+    # accepted forms: (n, 3) float64 arrays and tensors, flat or 2-D 4-byte and 8-byte
+    # outputs of at least 4 * capacity elements, offset views
+    good = [lambda: dt.dt_insert_points(None, np.zeros((5, 3))),
+            lambda: dt.dt_insert_points(None, torch.zeros((5, 3), dtype=torch.float64)),
+            lambda: dt.dt_insert_points(None, np.zeros((10, 3))[2:7]),
+            lambda: dt.dt_insert_batch(None, np.zeros((10, 3)), np.array([0, 4, 10], np.uint64)),
+            lambda: dt.dt_get_tets(None),
+            lambda: dt.dt_get_tets(None, np.zeros((3, 4), np.uint32), np.zeros((3, 4), np.int64), 3),
+            lambda: dt.dt_get_tets(None, torch.zeros(13, dtype=torch.int32)[1:13],
+                                   torch.zeros(13, dtype=torch.int64)[1:13], 3),
+            lambda: dt.dt_get_tets(None, torch.zeros((4, 4), dtype=torch.int32), None, 3),
+            lambda: dt.dt_get_tets_batch(None, 0, np.zeros((3, 4), np.uint32), np.zeros((3, 4), np.int64), 3),
+            lambda: dt.dt_debug_predicates(None, 0, np.zeros((4, 12))),
+            lambda: dt.dt_debug_predicates(None, 2, np.zeros((4, 15)), np.zeros((4, 5), np.int64))]
+    for call in good:
+        with pytest.raises(dt.DTError) as e:
+            call()
+        assert e.value.code == dt.DT_E_ARG
