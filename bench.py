@@ -72,6 +72,34 @@ def cavity_bytes_per_attempt(walk, C, F):
     return 48 + 64 * walk + 32 * C + 16 * F + 16 * (C + F) + 32 * (F / 2 + 2) + 4 * C + 8 * F
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(n, seed):
+    """The serial oracle (one thread) on n uniform points: tetrahedra per second."""
+    import oracle
+    from synth import uniform_points
+    sample = uniform_points(n, seed)
+    t0 = time.perf_counter()
+    rc, tets, _, _ = oracle.delaunay(sample)
+    dt = time.perf_counter() - t0
+    if rc != 0:
+        raise RuntimeError(f"oracle failed on the CPU sample (code {rc})")
+    return {"value": round(len(tets) / dt, 1), "unit": "tetrahedra/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} uniform points (seed {seed}), full serial triangulation in {dt:.2f} s, "
+                      f"{len(tets)} tetrahedra",
+            "cpu": host_cpu_model(), "host_threads": os.cpu_count()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,7 +184,8 @@ def main():
     times = []
     T = 0
     agg = dict(attempts=0, walk=0, cav=0, bnd=0, won=0, ms_cav=0.0, ms_ball=0.0, launches=0, rounds=0,
-               orient=0, orient_exact=0, insphere=0, insphere_exact=0, perturbed=0, conflicts=0)
+               orient=0, orient_exact=0, insphere=0, insphere_exact=0, perturbed=0, conflicts=0,
+               ms_sort=0.0, ms_insert=0.0)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -175,6 +204,8 @@ def main():
         agg["launches"] += s["cavity_launches"]
         agg["rounds"] += s["rounds"]
         agg["conflicts"] += s["conflicts"]
+        agg["ms_sort"] += s["ms_sort"]
+        agg["ms_insert"] += s["ms_insert"]
         for k in ("orient", "orient_exact", "insphere", "insphere_exact", "perturbed"):
             agg[k] += s[k + ("_calls" if k in ("orient", "insphere") else "")]
     torch.cuda.synchronize()
@@ -217,16 +248,7 @@ def main():
         learned = dict(res["learned"], same_count=res["learned"]["tetrahedra"] == T,
                        training=dict(training, points_per_run=tn), plain=res["plain"])
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        sample = uniform_points(args.cpu_sample, args.seed + 1)
-        t0 = time.perf_counter()
-        rc, tets, _, _ = oracle.delaunay(sample)
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(len(tets) / dt, 1), "unit": "tetrahedra/s", "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_sample} uniform points (seed {args.seed + 1}), full serial triangulation "
-                         f"in {dt:.2f} s, {len(tets)} tetrahedra"}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample, args.seed + 1)
 
     line = {
         "metric": "tetrahedra/sec (exact 3D Delaunay, uniform points)",
@@ -255,6 +277,12 @@ def main():
                    "cavity_tets": round(C, 2), "boundary_facets": round(F, 2),
                    "ms_cavity_kernel_per_step": round(agg["ms_cav"] / args.steps, 3),
                    "ms_ball_kernel_per_step": round(agg["ms_ball"] / args.steps, 3),
+                   # host clock inside dt_insert_points: sort phase and insertion rounds; the
+                   # paper's sequential timings leave the sort out
+                   "ms_sort_per_step": round(agg["ms_sort"] / args.steps, 3),
+                   "ms_insert_per_step": round(agg["ms_insert"] / args.steps, 3),
+                   "insertion_only_tets_per_s": round(T / (agg["ms_insert"] / args.steps / 1000.0), 1)
+                   if agg["ms_insert"] > 0 else None,
                    "orient_exact_rate": agg["orient_exact"] / max(agg["orient"], 1),
                    "insphere_exact_rate": agg["insphere_exact"] / max(agg["insphere"], 1),
                    "perturbed": agg["perturbed"], "step_ms": [round(1000 * t, 2) for t in times]},

@@ -50,3 +50,14 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_cpu_baseline_runs_the_oracle():
+    b = load_bench()
+    r = b.cpu_baseline(3000, 5)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "tetrahedra/s"
+    assert r["value"] > 0 and r["host_threads"] >= 1 and r["cpu"]
+    import oracle
+    from synth import uniform_points
+    rc, tets, _, _ = oracle.delaunay(uniform_points(3000, 5))
+    assert rc == 0 and f"{len(tets)} tetrahedra" in r["sample"]
