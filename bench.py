@@ -100,6 +100,29 @@ def cpu_baseline(n, seed):
             "cpu": host_cpu_model(), "host_threads": os.cpu_count()}
 
 
+def cpu_baseline_clouds(xyz, off, clouds, budget_s=15.0):
+    """The serial oracle (one thread) on the given clouds in turn, each triangulated alone,
+    until about budget_s seconds of work: tetrahedra per second over the clouds done."""
+    import oracle
+    t_all, tets, pts, done = 0.0, 0, 0, 0
+    for c in clouds:
+        p = xyz[int(off[c]):int(off[c + 1])]
+        t0 = time.perf_counter()
+        rc, t, _, _ = oracle.delaunay(p)
+        t_all += time.perf_counter() - t0
+        if rc != 0:
+            raise RuntimeError(f"oracle failed on cloud {c} (code {rc})")
+        tets += len(t)
+        pts += len(p)
+        done += 1
+        if t_all >= budget_s:
+            break
+    return {"value": round(tets / t_all, 1), "unit": "tetrahedra/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of the clouds ({pts} points, {tets} tetrahedra), each triangulated alone, "
+                      f"serially in {t_all:.2f} s",
+            "cpu": host_cpu_model(), "host_threads": os.cpu_count()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -418,13 +441,16 @@ def run_batch(args):
     chunks = [(c, min(c + args.chunk, args.clouds)) for c in range(0, args.clouds, args.chunk)]
 
     def step():
-        total = 0
+        """Every chunk once; returns (tetrahedra, rounds) summed over the chunks (each chunk
+        starts from a cleared context, which also resets the statistics)."""
+        total, rounds = 0, 0
         for c0, c1 in chunks:
             p0, p1 = int(off[c0]), int(off[c1])
             tri.clear()
             tri.insert_batch(d_xyz[p0:p1], (off[c0:c1 + 1] - p0).astype(np.uint64))
             total += tri.num_tets()
-        return total
+            rounds += tri.stats()["rounds"]
+        return total, rounds
 
     for _ in range(args.warmup):
         step()
@@ -433,8 +459,8 @@ def run_batch(args):
     T = 0
     rounds = 0
     for _ in range(args.steps):
-        T = step()
-        rounds += tri.stats()["rounds"]
+        T, r = step()
+        rounds += r
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / args.steps
     # the same clouds, one dt_insert_points call each, on a sample
@@ -469,6 +495,7 @@ def run_batch(args):
                    "calls_per_step": len(chunks), "rounds_per_step": rounds / max(args.steps, 1)},
         "loop_single": {"value": round(tt / tl, 1), "unit": "tetrahedra/s",
                         "sample": f"{len(sample)} of the clouds ({pts} points), one dt_insert_points call each"},
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_clouds(xyz, off, sample),
     }
     print(json.dumps(line), flush=True)
     tri.close()

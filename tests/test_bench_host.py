@@ -61,3 +61,18 @@ def test_cpu_baseline_runs_the_oracle():
     from synth import uniform_points
     rc, tets, _, _ = oracle.delaunay(uniform_points(3000, 5))
     assert rc == 0 and f"{len(tets)} tetrahedra" in r["sample"]
+
+
+def test_cpu_baseline_over_clouds_stops_at_its_budget():
+    b = load_bench()
+    import numpy as np
+    from synth import batch_clouds
+    xyz, off = batch_clouds(6, seed_base=3000, nmin=50, nmax=400)
+    off = off.astype(np.int64)
+    r = b.cpu_baseline_clouds(xyz, off, [0, 2, 4], budget_s=1e9)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["value"] > 0
+    assert r["sample"].startswith("3 of the clouds")
+    pts = sum(int(off[c + 1] - off[c]) for c in (0, 2, 4))
+    assert f"({pts} points" in r["sample"]
+    r = b.cpu_baseline_clouds(xyz, off, [0, 2, 4], budget_s=0.0)
+    assert r["sample"].startswith("1 of the clouds")
