@@ -84,20 +84,23 @@ def host_cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(n, seed):
-    """The serial oracle (one thread) on n uniform points: tetrahedra per second."""
+def cpu_baseline_points(sample, what):
+    """The serial oracle (one thread) on one point set: tetrahedra per second."""
     import oracle
-    from synth import uniform_points
-    sample = uniform_points(n, seed)
     t0 = time.perf_counter()
     rc, tets, _, _ = oracle.delaunay(sample)
     dt = time.perf_counter() - t0
     if rc != 0:
         raise RuntimeError(f"oracle failed on the CPU sample (code {rc})")
     return {"value": round(len(tets) / dt, 1), "unit": "tetrahedra/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} uniform points (seed {seed}), full serial triangulation in {dt:.2f} s, "
-                      f"{len(tets)} tetrahedra",
+            "sample": f"{what}, full serial triangulation in {dt:.2f} s, {len(tets)} tetrahedra",
             "cpu": host_cpu_model(), "host_threads": os.cpu_count()}
+
+
+def cpu_baseline(n, seed):
+    """The serial oracle on n uniform points (seed)."""
+    from synth import uniform_points
+    return cpu_baseline_points(uniform_points(n, seed), f"{n} uniform points (seed {seed})")
 
 
 def cpu_baseline_clouds(xyz, off, clouds, budget_s=15.0):
@@ -143,6 +146,8 @@ def main():
     ap.add_argument("--train-samples", type=int, default=4_000_000, help="samples drawn from the logs")
     ap.add_argument("--train-n", type=int, default=0, help="uniform: points per training run (0: min(n, 1e7))")
     ap.add_argument("--mix-scale", type=float, default=1.0, help="mix: fraction of the 1e7 points")
+    ap.add_argument("--cpu-mix-scale", type=float, default=0.05,
+                    help="mix: size of the oracle's CPU sample as a fraction of the timed input")
     ap.add_argument("--clouds", type=int, default=4096, help="batch: number of clouds")
     ap.add_argument("--chunk", type=int, default=1024, help="batch: clouds per dt_insert_batch call")
     ap.add_argument("--loop-sample", type=int, default=64, help="batch: clouds timed one call each")
@@ -419,6 +424,9 @@ def run_mix(args):
         "learned": dict(res["learned"], same_count=res["learned"]["tetrahedra"] == res["plain"]["tetrahedra"],
                         training=training),
         "plain": res["plain"],
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_points(
+            mix_points(seed + 1, *(int(c * args.cpu_mix_scale) for c in counts)),
+            f"MIX at {args.cpu_mix_scale} of the timed size (seed {seed + 1})"),
     }
     print(json.dumps(line), flush=True)
 
