@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 from synth import cluster_points, lattice_points, shell_points, uniform_points
-from validators import (brute_force_dt, check_invariants, det_exact, insphere_exact,
+from validators import (brute_force_dt, check_adjacency, check_hull_convex, check_invariants, det_exact,
+                        euler_counts, insphere_exact,
                         insphere_perturbed_poly, lifted_rows, orient3d_exact,
                         perturbed_sign_int, _int_scale)
 
@@ -191,6 +192,29 @@ def test_bruteforce_lattice_3x3x3(oracle_mod):
     canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
     assert np.array_equal(canon, brute_force_dt(xyz))
     check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(27))
+
+
+def test_hull_convexity_check_rejects_a_concave_complex(oracle_mod):
+    """The I4 check on its own: two tetrahedra glued on a facet, with the segment between
+    their apexes missing that facet, form a valid closed complex (I1-I3 hold) whose hull is
+    not convex; every oracle output above passes the check."""
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [2, 2, 1], [2, 2, -1]], dtype=np.float64)
+    tets = np.array([[0, 1, 2, 3], [0, 1, 2, 4]])
+    for t in tets:
+        if oracle_mod.orient3d(xyz[t][None])[0] < 0:
+            t[[1, 2]] = t[[2, 1]]
+    assert np.all(oracle_mod.orient3d(xyz[tets]) > 0)
+    nbrs = np.full((2, 4), -1)
+    nbrs[0, list(tets[0]).index(3)] = 1
+    nbrs[1, list(tets[1]).index(4)] = 0
+    check_adjacency(tets, nbrs)
+    V, E, F, T, Vh, Eh, Fh = euler_counts(tets, nbrs)
+    assert V - E + F - T == 1 and Vh - Eh + Fh == 2
+    with pytest.raises(AssertionError, match="not locally convex"):
+        check_hull_convex(xyz, tets, nbrs, oracle_mod)
+    # the Delaunay tetrahedralization of the same points is convex
+    rc, t2, n2, _ = oracle_mod.delaunay(xyz)
+    assert rc == 0 and check_hull_convex(xyz, t2, n2, oracle_mod) == 6
 
 
 # ------------------------------------------------------------------ edge cases

@@ -225,10 +225,45 @@ def euler_counts(tets, nbrs):
     return V, E, F, len(tets), Vh, Eh, len(hull)
 
 
+def check_hull_convex(xyz, tets, nbrs, oracle):
+    """I4: the hull is locally convex.  Each hull facet is oriented with its tetrahedron's
+    fourth vertex on the inner side (exact orient3d > 0); across every hull edge, the far
+    vertex of the other hull facet must lie on the inner side of this one or in its plane."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    tets = np.asarray(tets, dtype=np.int64)
+    t_idx, j_idx = np.nonzero(np.asarray(nbrs) < 0)
+    H = len(t_idx)
+    rest = np.array([[k for k in range(4) if k != j] for j in range(4)])
+    f = tets[t_idx[:, None], rest[j_idx]].copy()
+    inner = tets[t_idx, j_idx]
+    s = oracle.orient3d(xyz[np.concatenate([f, inner[:, None]], axis=1)])
+    assert np.all(s != 0), "flat tetrahedron on the hull"
+    neg = s < 0
+    tmp = f[neg, 1].copy()
+    f[neg, 1] = f[neg, 2]
+    f[neg, 2] = tmp
+    # hull edges: (sorted vertex pair, facet, far vertex of the facet)
+    E = np.stack([np.sort(np.stack([f[:, k], f[:, (k + 1) % 3]], axis=1), axis=1) for k in range(3)],
+                 axis=1).reshape(-1, 2)
+    W = np.stack([f[:, (k + 2) % 3] for k in range(3)], axis=1).reshape(-1)
+    face = np.repeat(np.arange(H), 3)
+    order = np.lexsort((E[:, 1], E[:, 0]))
+    assert len(order) % 2 == 0
+    a, b = order[0::2], order[1::2]
+    assert np.all(E[a] == E[b]), "a hull edge is not shared by exactly two hull facets"
+    if len(a) > 1:
+        assert np.all(np.any(E[a[1:]] != E[a[:-1]], axis=1)), "a hull edge is shared by more than two facets"
+    for x, y in ((a, b), (b, a)):
+        q = np.concatenate([f[face[x]], W[y][:, None]], axis=1)
+        assert np.all(oracle.orient3d(xyz[q]) >= 0), "hull not locally convex"
+    return H
+
+
 def check_invariants(xyz, tets, nbrs, oracle, expect_vertices=None, local_delaunay=True,
                      chunk=1 << 20):
-    """I1 orientation, I2 adjacency, I3 Euler characteristic, I5 vertex coverage,
-    I6 volume, I7 local Delaunay (perturbed).  Raises AssertionError on failure."""
+    """I1 orientation, I2 adjacency, I3 Euler characteristic, I4 local convexity of the hull,
+    I5 vertex coverage, I6 volume, I7 local Delaunay (perturbed).  Raises AssertionError on
+    failure."""
     xyz = np.asarray(xyz, dtype=np.float64)
     tets = np.asarray(tets, dtype=np.int64)
     nbrs = np.asarray(nbrs, dtype=np.int64)
@@ -244,6 +279,8 @@ def check_invariants(xyz, tets, nbrs, oracle, expect_vertices=None, local_delaun
     V, E, F, TT, Vh, Eh, Fh = euler_counts(tets, nbrs)
     assert V - E + F - TT == 1, "Euler characteristic of the complex"
     assert Vh - Eh + Fh == 2, "Euler characteristic of the hull surface"
+    # I4
+    check_hull_convex(xyz, tets, nbrs, oracle)
     # I5
     if expect_vertices is not None:
         assert np.array_equal(np.unique(tets), np.sort(np.asarray(expect_vertices)))
