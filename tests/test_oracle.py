@@ -9,8 +9,8 @@ import numpy as np
 import pytest
 
 from synth import cluster_points, lattice_points, shell_points, uniform_points
-from validators import (brute_force_dt, check_adjacency, check_hull_convex, check_invariants, det_exact,
-                        euler_counts, insphere_exact,
+from validators import (brute_force_dt, check_adjacency, check_hull_convex, check_invariants,
+                        check_volume_exact, det_exact, euler_counts, insphere_exact,
                         insphere_perturbed_poly, lifted_rows, orient3d_exact,
                         perturbed_sign_int, _int_scale)
 
@@ -215,6 +215,25 @@ def test_hull_convexity_check_rejects_a_concave_complex(oracle_mod):
     # the Delaunay tetrahedralization of the same points is convex
     rc, t2, n2, _ = oracle_mod.delaunay(xyz)
     assert rc == 0 and check_hull_convex(xyz, t2, n2, oracle_mod) == 6
+
+
+def test_exact_volume_check_rejects_a_folded_complex(oracle_mod):
+    """The exact I6 check on its own: two positive tetrahedra glued on a facet with both apexes
+    on the same side pass I1-I3, but the facet does not cancel in the divergence sum."""
+    # (off the origin: a facet whose plane holds the origin adds nothing to the divergence sum)
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0.25, 0.25, 1], [0.125, 0.25, 2]], dtype=np.float64) + 0.5
+    tets = np.array([[0, 1, 2, 3], [0, 1, 2, 4]])
+    assert np.all(oracle_mod.orient3d(xyz[tets]) > 0)
+    nbrs = np.full((2, 4), -1)
+    nbrs[0, 3] = 1
+    nbrs[1, 3] = 0
+    check_adjacency(tets, nbrs)
+    V, E, F, T, Vh, Eh, Fh = euler_counts(tets, nbrs)
+    assert V - E + F - T == 1 and Vh - Eh + Fh == 2
+    with pytest.raises(AssertionError, match="different volumes"):
+        check_volume_exact(xyz, tets, nbrs, oracle_mod)
+    rc, t2, n2, _ = oracle_mod.delaunay(xyz)
+    assert rc == 0 and check_volume_exact(xyz, t2, n2, oracle_mod) > 0
 
 
 # ------------------------------------------------------------------ edge cases

@@ -225,23 +225,53 @@ def euler_counts(tets, nbrs):
     return V, E, F, len(tets), Vh, Eh, len(hull)
 
 
-def check_hull_convex(xyz, tets, nbrs, oracle):
-    """I4: the hull is locally convex.  Each hull facet is oriented with its tetrahedron's
-    fourth vertex on the inner side (exact orient3d > 0); across every hull edge, the far
-    vertex of the other hull facet must lie on the inner side of this one or in its plane."""
-    xyz = np.asarray(xyz, dtype=np.float64)
+def hull_facets(xyz, tets, nbrs, oracle):
+    """The facets without neighbour, (H, 3) vertex indices, each ordered so that the fourth
+    vertex of its tetrahedron is on the positive side (exact orient3d > 0)."""
     tets = np.asarray(tets, dtype=np.int64)
     t_idx, j_idx = np.nonzero(np.asarray(nbrs) < 0)
-    H = len(t_idx)
     rest = np.array([[k for k in range(4) if k != j] for j in range(4)])
     f = tets[t_idx[:, None], rest[j_idx]].copy()
     inner = tets[t_idx, j_idx]
-    s = oracle.orient3d(xyz[np.concatenate([f, inner[:, None]], axis=1)])
+    s = oracle.orient3d(np.asarray(xyz, dtype=np.float64)[np.concatenate([f, inner[:, None]], axis=1)])
     assert np.all(s != 0), "flat tetrahedron on the hull"
     neg = s < 0
     tmp = f[neg, 1].copy()
     f[neg, 1] = f[neg, 2]
     f[neg, 2] = tmp
+    return f
+
+
+def check_volume_exact(xyz, tets, nbrs, oracle):
+    """I6, exact: with the coordinates scaled to integers, six times the summed volume of the
+    tetrahedra (the sum of their orient3d determinants) equals the divergence-theorem volume of
+    the hull facets, -sum det(a, b, c) over the facets ordered as in hull_facets.  The identity
+    holds for a complex whose shared facets cancel; two positive tetrahedra folded over a
+    shared facet break it, unless that facet's plane holds the origin (the reference point of
+    the divergence sum)."""
+    P = np.empty((len(xyz), 3), dtype=object)
+    P[:, :] = _int_scale(xyz)
+    t = np.asarray(tets, dtype=np.int64)
+    a = P[t[:, 0]]
+    u, v, w = P[t[:, 1]] - a, P[t[:, 2]] - a, P[t[:, 3]] - a
+    vol6 = (u[:, 0] * (v[:, 1] * w[:, 2] - v[:, 2] * w[:, 1]) - u[:, 1] * (v[:, 0] * w[:, 2] - v[:, 2] * w[:, 0])
+            + u[:, 2] * (v[:, 0] * w[:, 1] - v[:, 1] * w[:, 0]))
+    f = hull_facets(xyz, tets, nbrs, oracle)
+    A, B, C = P[f[:, 0]], P[f[:, 1]], P[f[:, 2]]
+    div6 = (A[:, 0] * (B[:, 1] * C[:, 2] - B[:, 2] * C[:, 1]) - A[:, 1] * (B[:, 0] * C[:, 2] - B[:, 2] * C[:, 0])
+            + A[:, 2] * (B[:, 0] * C[:, 1] - B[:, 1] * C[:, 0]))
+    total, hull = int(vol6.sum()), -int(div6.sum())
+    assert total == hull, "tetrahedra and hull facets enclose different volumes"
+    return total
+
+
+def check_hull_convex(xyz, tets, nbrs, oracle):
+    """I4: the hull is locally convex.  Each hull facet is oriented with its tetrahedron's
+    fourth vertex on the inner side (exact orient3d > 0); across every hull edge, the far
+    vertex of the other hull facet must lie on the inner side of this one or in its plane."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    f = hull_facets(xyz, tets, nbrs, oracle)
+    H = len(f)
     # hull edges: (sorted vertex pair, facet, far vertex of the facet)
     E = np.stack([np.sort(np.stack([f[:, k], f[:, (k + 1) % 3]], axis=1), axis=1) for k in range(3)],
                  axis=1).reshape(-1, 2)
@@ -260,7 +290,7 @@ def check_hull_convex(xyz, tets, nbrs, oracle):
 
 
 def check_invariants(xyz, tets, nbrs, oracle, expect_vertices=None, local_delaunay=True,
-                     chunk=1 << 20):
+                     chunk=1 << 20, exact_volume=True):
     """I1 orientation, I2 adjacency, I3 Euler characteristic, I4 local convexity of the hull,
     I5 vertex coverage, I6 volume, I7 local Delaunay (perturbed).  Raises AssertionError on
     failure."""
@@ -284,7 +314,10 @@ def check_invariants(xyz, tets, nbrs, oracle, expect_vertices=None, local_delaun
     # I5
     if expect_vertices is not None:
         assert np.array_equal(np.unique(tets), np.sort(np.asarray(expect_vertices)))
-    # I6: summed volumes against an independent hull (tolerance: float)
+    # I6: exact, the tetrahedra against the hull facets of the output; then the summed volumes
+    # against an independent hull (tolerance: float)
+    if exact_volume:
+        check_volume_exact(xyz, tets, nbrs, oracle)
     p = xyz[tets]
     vol = np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0])).sum() / 6.0
     try:
