@@ -122,6 +122,52 @@ def test_perturbed_insphere_matches_eps_polynomial(oracle_mod):
     assert np.count_nonzero(raw == 0) > 40
 
 
+def test_ghost_rule_is_intrinsic(oracle_mod):
+    """Reading R4: for p coplanar with a hull facet abc, the decision falls to the perturbed
+    insphere of (a, b, c, x, p) with x the finite neighbour's apex; its sign must not depend
+    on x (position on the inner side, or input index).  Cube faces (p on the circumcircle of
+    abc: the perturbation decides), generic points of the plane, and tilted lattice planes."""
+    r = np.random.default_rng(77)
+    lat = lattice_points(216, 9, side=6)
+    cases = []
+    sq = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], dtype=np.float64)
+    for _ in range(40):
+        cases.append(sq[r.permutation(4)])  # three corners of a square face and the fourth
+    for _ in range(40):
+        abc = np.c_[r.integers(-8, 9, size=(3, 2)) / 8.0, np.zeros(3)]
+        p = np.array([r.integers(-8, 9) / 8.0, r.integers(-8, 9) / 8.0, 0.0])
+        cases.append(np.vstack([abc, p]))
+    while len(cases) < 200:  # coplanar lattice quadruples in tilted planes
+        q = lat[r.choice(len(lat), 4, replace=False)]
+        if oracle_mod.orient3d(q[None])[0] == 0:
+            cases.append(q)
+    checked, ties = 0, 0
+    for q in cases:
+        a, b, c, p = q
+        if oracle_mod.orient3d(np.array([[a, b, c, p]]))[0] != 0:
+            continue
+        n = np.cross(b - a, c - a)
+        if not np.any(n):
+            continue  # collinear facet
+        signs = []
+        base = 100 + r.permutation(1000)[:5]  # indices of a, b, c, (x), p; only x's varies below
+        srt = np.sort(base[[0, 1, 2, 4]])
+        for k in range(6):
+            x = a + n * (0.25 + r.random() * 3) + (b - a) * r.normal() + (c - a) * r.normal()
+            abcx = np.array([a, b, c, x])  # x is on the side of (b - a) x (c - a): positive
+            assert oracle_mod.orient3d(abcx[None])[0] > 0
+            idx = base.copy()
+            # the apex's index: before, after or between the others in the index order
+            mid = (int(srt[1]) + int(srt[2])) // 2
+            idx[3] = [int(srt[0]) - 1 - k, int(srt[-1]) + 1 + k,
+                      mid if mid not in (srt[1], srt[2]) else int(srt[-1]) + 50 + k][k % 3]
+            signs.append(oracle_mod.insphere_sos(np.vstack([abcx, p])[None], idx[None])[0])
+        assert len(set(signs)) == 1 and signs[0] != 0, (q, signs)
+        checked += 1
+        ties += int(oracle_mod.insphere(np.vstack([abcx, p])[None])[0] == 0)
+    assert checked > 150 and ties > 40  # many decided by the perturbation alone
+
+
 def test_bruteforce_cofactor_sign_matches_eps_polynomial():
     """The brute-force helper's tie-break agrees with the eps-polynomial definition."""
     cube = np.array(list(itertools.product([0.0, 1.0], repeat=3)))
@@ -298,7 +344,7 @@ def test_invariants(oracle_mod, kind):
 
 # ------------------------------------------------------------------ Moore curve, BRIO
 
-@pytest.mark.parametrize("m", [1, 2, 3, 4])
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5])
 def test_moore_curve_closed_and_adjacent(oracle_mod, m):
     n = 1 << m
     cells = np.array(list(itertools.product(range(n), repeat=3)), dtype=np.uint32)
