@@ -14,6 +14,14 @@
  * Symbolic perturbation (reading of Sec. 2.4 item 3): the lifted coordinate of point i is
  * |p_i|^2 + eps^(delta_i) with delta strictly decreasing in the input index, so the
  * highest index dominates; orient3d is never perturbed.
+ *
+ * What pins each part (tests, CPU only): the predicate signs against exact rational
+ * determinants; the perturbation against the eps-polynomial of its definition, and the ghost
+ * rule's tie-break against its independence of the apex; Moore keys by brute-force curve
+ * properties and cells placed by construction; the sort against a library stable sort; the
+ * level sizes against the paper's table of insertion steps; the triangulation against
+ * brute-force enumeration on tiny inputs and invariants I1-I7 on larger ones.  The work
+ * counters in oracle_stats are reported only: parity unpinned.
  */
 #ifndef DT_ORACLE_H
 #define DT_ORACLE_H
