@@ -126,6 +126,21 @@ def cpu_baseline_clouds(xyz, off, clouds, budget_s=15.0):
             "cpu": host_cpu_model(), "host_threads": os.cpu_count()}
 
 
+# Algorithmic bytes of the ball kernel (winner test + DelaunayBall) per launch, from the
+# counters.  Every candidate reads its point, rank, two list lengths and status (20 B) and,
+# for the winner test, each cavity and outer entry of its lists with that tetrahedron's claim
+# word (4 + 8 B each).  A winner also reads its cavity tetrahedra's vertex rows and writes
+# their copies (16 + 16 B each), writes one new tetrahedron per boundary facet (vertices and
+# neighbours, 32 B), the back-pointer in the outer tetrahedron (4 B), the facet's list entries
+# (boundary entry read, outer code read and rewritten, slot index: 16 B), and the vertex
+# hints of the boundary's F/2 + 2 vertices (4 B each).  Losers are counted with the winners'
+# mean cavity and boundary sizes.
+def ball_bytes(C, F, candidates, winners):
+    per_candidate = 20 + 12 * (C + F)
+    per_winner = 32 * C + 32 * F + 4 * F + 16 * F + 4 * (F / 2 + 2)
+    return candidates * per_candidate + winners * per_winner
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,7 +228,7 @@ def main():
     T = 0
     agg = dict(attempts=0, walk=0, cav=0, bnd=0, won=0, ms_cav=0.0, ms_ball=0.0, launches=0, rounds=0,
                orient=0, orient_exact=0, insphere=0, insphere_exact=0, perturbed=0, conflicts=0,
-               ms_sort=0.0, ms_insert=0.0)
+               ms_sort=0.0, ms_insert=0.0, ball_launches=0)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -233,6 +248,7 @@ def main():
         agg["rounds"] += s["rounds"]
         agg["conflicts"] += s["conflicts"]
         agg["ms_sort"] += s["ms_sort"]
+        agg["ball_launches"] += s["ball_launches"]
         agg["ms_insert"] += s["ms_insert"]
         for k in ("orient", "orient_exact", "insphere", "insphere_exact", "perturbed"):
             agg[k] += s[k + ("_calls" if k in ("orient", "insphere") else "")]
@@ -258,6 +274,14 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / peak, 5), "traffic": measured_traffic(),
                 "bytes_per_attempt": round(b_unit, 1), "attempts_per_launch": round(agg["attempts"] / launches, 1),
                 "avg_launch_ms": round(avg_launch_ms, 4)}
+
+    # the ball kernel's algorithmic rate (a detail; the cavity kernel is the dominant one)
+    ball_total = ball_bytes(C, F, agg["attempts"], agg["won"])
+    ball = {"bound": "hbm", "kernel": "k_ball<16, 1024>", "unit": "GB/s", "peak": peak,
+            "achieved": round(ball_total / (agg["ms_ball"] / 1000.0) / 1e9, 2) if agg["ms_ball"] > 0 else 0.0,
+            "bytes_per_insertion": round(ball_total / won, 1),
+            "avg_launch_ms": round(agg["ms_ball"] / max(agg["ball_launches"], 1), 4)}
+    ball["frac"] = round(ball["achieved"] / peak, 5)
 
     learned = None
     if not args.no_learned:
@@ -305,6 +329,7 @@ def main():
                    "cavity_tets": round(C, 2), "boundary_facets": round(F, 2),
                    "ms_cavity_kernel_per_step": round(agg["ms_cav"] / args.steps, 3),
                    "ms_ball_kernel_per_step": round(agg["ms_ball"] / args.steps, 3),
+                   "ball_roofline": ball,
                    # host clock inside dt_insert_points: sort phase and insertion rounds; the
                    # paper's sequential timings leave the sort out
                    "ms_sort_per_step": round(agg["ms_sort"] / args.steps, 3),

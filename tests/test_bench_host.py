@@ -76,3 +76,19 @@ def test_cpu_baseline_over_clouds_stops_at_its_budget():
     assert f"({pts} points" in r["sample"]
     r = b.cpu_baseline_clouds(xyz, off, [0, 2, 4], budget_s=0.0)
     assert r["sample"].startswith("1 of the clouds")
+
+
+def test_ball_byte_model():
+    b = load_bench()
+    # a candidate with empty lists still reads its point, rank, lengths and status
+    assert b.ball_bytes(0, 0, 1, 0) == 20
+    # each cavity or outer entry costs its list entry and claim word
+    assert b.ball_bytes(1, 0, 1, 0) - 20 == 12 and b.ball_bytes(0, 1, 1, 0) - 20 == 12
+    # a winner's part: cavity rows 32 B each, boundary facets 52 B each, boundary vertex hints
+    base = b.ball_bytes(0, 0, 0, 1)
+    assert base == 4 * 2
+    assert b.ball_bytes(1, 0, 0, 1) - base == 32
+    assert b.ball_bytes(0, 2, 0, 1) - base == 2 * 52 + 4
+    # the uniform 1e7 shape: about 2.9 KB per insertion
+    per = b.ball_bytes(20.04, 26.8, 1.3469e7, 1e7) / 1e7
+    assert 2800 < per < 3000
