@@ -112,8 +112,8 @@ int dt_create(dt_ctx **out, const dt_options *opt);
    leaves the context empty.  After DT_E_ARG, DT_E_INPUT or DT_E_DEGENERATE the context
    is as it was before the call; after DT_E_CAPACITY, DT_E_INCOMPLETE, DT_E_DEVICE or
    DT_E_INTERNAL only dt_clear, dt_get_stats, dt_last_error and dt_destroy are
-   meaningful.  Limits: fewer than 2^30 points per call and 2^31 in all (DT_E_CAPACITY),
-   and fewer than 2^30 tetrahedra slots. */
+   meaningful.  n = 0 does nothing and returns DT_OK.  Limits: fewer than 2^30 points per
+   call and 2^31 in all (DT_E_CAPACITY), and fewer than 2^30 tetrahedra slots. */
 int dt_insert_points(dt_ctx *ctx, const double *xyz, uint64_t n);
 
 /* Export the finite tetrahedra.  *num_tets is in/out: on input the capacity of the
@@ -131,8 +131,8 @@ int dt_get_tets(dt_ctx *ctx, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
    at least 4 points per cloud) are not retained.  Each cloud gets the Delaunay
    tetrahedralization of its own points (Algorithm 1), exactly as if it were inserted alone
    into a fresh context.  The context must be empty (new or after dt_clear), and
-   dt_insert_points is refused until the next dt_clear.  Errors as dt_insert_points;
-   DT_E_DEGENERATE names the first degenerate cloud in dt_last_error.  Limits: fewer than 2^30
+   dt_insert_points is refused until the next dt_clear, also after a failed call.  Errors as
+   dt_insert_points; DT_E_DEGENERATE names the first degenerate cloud in dt_last_error.  Limits: fewer than 2^30
    points in all, fewer than 2^30 tetrahedron slots in all. */
 int dt_insert_batch(dt_ctx *ctx, const double *xyz, const uint64_t *offsets, uint32_t num_clouds);
 
