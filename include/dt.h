@@ -133,9 +133,9 @@ int dt_get_tets(dt_ctx *ctx, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
    into a fresh context.  The context must be empty (new or after dt_clear), and
    dt_insert_points is refused until the next dt_clear, also after a call that fails past
    its argument checks (DT_E_ARG for NULL pointers, bad offsets or too few points in a cloud
-   leaves the context untouched).  Errors as
-   dt_insert_points; DT_E_DEGENERATE names the first degenerate cloud in dt_last_error.  Limits: fewer than 2^30
-   points in all, fewer than 2^30 tetrahedron slots in all. */
+   leaves the context untouched).  Errors as dt_insert_points; DT_E_DEGENERATE names the
+   first degenerate cloud in dt_last_error.  Limits: fewer than 2^30 points in all, fewer
+   than 2^30 tetrahedron slots in all. */
 int dt_insert_batch(dt_ctx *ctx, const double *xyz, const uint64_t *offsets, uint32_t num_clouds);
 
 /* Export the finite tetrahedra of one cloud of the context (cloud 0 after dt_insert_points),
