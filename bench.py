@@ -72,6 +72,20 @@ def cavity_bytes_per_attempt(walk, C, F):
     return 48 + 64 * walk + 32 * C + 16 * F + 16 * (C + F) + 32 * (F / 2 + 2) + 4 * C + 8 * F
 
 
+# The paper's CPU figures for uniform points (other hardware: context, not a target):
+# 3e9 tetrahedra in 53 s on two 32-core AMD EPYC 7551 (abstract, Sec. 3.7), and its figure of
+# rates against n for the same machine.
+PAPER_RATE_BY_N = {10_000_000: 31.32e6, 100_000_000: 64.40e6}
+
+
+def paper_context(n):
+    ctx = {"headline": "3e9 tetrahedra in 53 s (56.6 M tets/s), 2x AMD EPYC 7551, 64 cores",
+           "unit": "tetrahedra/s", "note": "the paper's CPU; other hardware, context only"}
+    if n in PAPER_RATE_BY_N:
+        ctx["value_at_this_n"] = PAPER_RATE_BY_N[n]
+    return ctx
+
+
 def host_cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -323,6 +337,7 @@ def main():
         "roofline": roofline if (lanes == 8 and not args.round_fraction and not args.round_size
                                  and args.n == 10_000_000 and args.seed == 1007) else dict(roofline, traffic=None),
         "cpu_baseline": cpu,
+        "paper_context": paper_context(args.n),
         "learned": learned,
         "detail": {"rounds_per_step": agg["rounds"] / args.steps, "attempts_per_point": agg["attempts"] / max(args.n * args.steps, 1),
                    "conflict_rate": agg["conflicts"] / att, "walk_steps_per_attempt": round(walk, 3),

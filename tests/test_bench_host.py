@@ -92,3 +92,11 @@ def test_ball_byte_model():
     # the uniform 1e7 shape: about 2.9 KB per insertion
     per = b.ball_bytes(20.04, 26.8, 1.3469e7, 1e7) / 1e7
     assert 2800 < per < 3000
+
+
+def test_paper_context_is_quoted_only_where_the_paper_has_the_size():
+    b = load_bench()
+    assert b.paper_context(10_000_000)["value_at_this_n"] == 31.32e6
+    assert b.paper_context(100_000_000)["value_at_this_n"] == 64.40e6
+    assert "value_at_this_n" not in b.paper_context(1_000_000)
+    assert "context" in b.paper_context(1)["note"]
