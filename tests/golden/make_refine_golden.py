@@ -1,0 +1,43 @@
+"""Writes refine_golden.txt: the refinement oracle's result on fixed seeded inputs (final point
+count, steps as candidates/kept, and SHA-256 of the canonical tetrahedra and of the final
+coordinates).  Calls only the oracle package and the input generators.
+
+Run from the repository root: python tests/golden/make_refine_golden.py
+"""
+import hashlib
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+CASES = [("uniform", 600, 7, 0.08), ("uniform", 2000, 11, 0.05), ("clusters", 800, 8, 0.03)]
+
+
+def run_case(kind, n, seed, h):
+    import oracle
+    from oracle import refine
+    from synth import cluster_points, uniform_points
+    xyz = uniform_points(n, seed) if kind == "uniform" else cluster_points(n, seed, clusters=4)
+    pts, tets, nbrs, steps = refine.refine(xyz, h)
+    canon = oracle.canonical(tets).astype(np.int64)
+    return (len(pts), ";".join(f"{a}/{b}" for a, b in steps),
+            hashlib.sha256(canon.tobytes()).hexdigest(),
+            hashlib.sha256(np.ascontiguousarray(pts, dtype=np.float64).tobytes()).hexdigest())
+
+
+def main():
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "refine_golden.txt")
+    with open(out, "w") as fh:
+        fh.write("# refinement oracle results (written by make_refine_golden.py)\n")
+        fh.write("# kind n seed h | points steps(candidates/kept) sha256(canonical tets) sha256(points)\n")
+        for kind, n, seed, h in CASES:
+            npts, steps, ht, hp = run_case(kind, n, seed, h)
+            fh.write(f"{kind} {n} {seed} {h} | {npts} {steps} {ht} {hp}\n")
+    print(out)
+
+
+if __name__ == "__main__":
+    main()

@@ -130,3 +130,22 @@ def test_refined_mesh_properties(R, oracle_mod, kind, h):
     # the hull is the input's: inserted points are strictly inside it
     f0 = R.hull_facets(xyz, *oracle_mod.delaunay(xyz)[1:3])
     assert R.strictly_inside(pts[n0:], xyz, f0).all()
+
+
+def test_refine_matches_stored_results(R):
+    """Regression: the oracle reproduces tests/golden/refine_golden.txt, which
+    tests/golden/make_refine_golden.py wrote from this oracle.  A change to the oracle's
+    arithmetic must come with a rewritten file and the passage that justifies it."""
+    import os
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    import make_refine_golden as mk
+    rows = [l.split("|") for l in open(os.path.join(here, "golden", "refine_golden.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == len(mk.CASES)
+    for (lhs, rhs), case in zip(rows, mk.CASES):
+        kind, n, seed, h = lhs.split()
+        assert (kind, int(n), int(seed), float(h)) == case
+        npts, steps, ht, hp = rhs.split()
+        assert mk.run_case(*case) == (int(npts), steps, ht, hp)
