@@ -75,11 +75,12 @@ def hull_facets(xyz, tets, nbrs):
     return f
 
 
-def strictly_inside(q, xyz, facets, chunk=4096):
+def strictly_inside(q, xyz, facets, quads_per_batch=1 << 19):
     """Exact test: q is on the positive side of every oriented hull facet."""
     q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
     P = np.asarray(xyz, dtype=np.float64)[facets]  # H, 3, 3
     out = np.ones(len(q), dtype=bool)
+    chunk = max(1, quads_per_batch // max(len(P), 1))
     for s in range(0, len(q), chunk):
         qq = q[s:s + chunk]
         quad = np.concatenate([np.broadcast_to(P[None], (len(qq),) + P.shape),
@@ -96,7 +97,9 @@ def greedy_filter(cand, order, vertices, h):
     reach = FILTER * h * (1.0 + 1e-6)
     tree = cKDTree(vertices)
     near_v = tree.query_ball_point(cand[order], reach)
-    cell = FILTER * h
+    # grid cells a little wider than the threshold, so that two candidates closer than it
+    # always fall in neighbouring cells despite the rounding of c / cell
+    cell = FILTER * h * (1.0 + 1e-9)
     grid = {}
     kept = []
     for k, i in enumerate(order):
