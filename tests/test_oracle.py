@@ -284,6 +284,21 @@ def test_exact_volume_check_rejects_a_folded_complex(oracle_mod):
 
 # ------------------------------------------------------------------ edge cases
 
+def test_input_domain_boundaries(oracle_mod):
+    """Accepted coordinates: 0, or magnitude in [2^-120, 2^120).  The edges of the interval,
+    one ulp either side, in either sign."""
+    base = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0.25, 0.25, 0.25]], dtype=np.float64)
+    big, tiny = 2.0 ** 120, 2.0 ** -120
+    cases = [(np.nextafter(big, 0), True), (big, False), (tiny, True), (np.nextafter(tiny, 0), False),
+             (np.inf, False), (np.nan, False)]
+    for v, ok in cases:
+        for sign in (1.0, -1.0):
+            x = base.copy()
+            x[4, 1] = sign * v
+            rc = oracle_mod.delaunay(x)[0]
+            assert (rc == oracle_mod.OK) == ok and (ok or rc == oracle_mod.E_INPUT), (v, sign, rc)
+
+
 def test_errors_and_duplicates(oracle_mod):
     assert oracle_mod.delaunay(np.zeros((3, 3)))[0] == oracle_mod.E_DEGENERATE
     plane = np.c_[uniform_points(50, 3)[:, :2], np.zeros(50)]
