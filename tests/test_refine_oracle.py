@@ -105,6 +105,26 @@ def test_cube_closed_form(R, h, inserted):
         assert steps == [(0, 0)]
 
 
+def test_lattice_closed_form(R, oracle_mod):
+    """5 x 5 x 5 lattice, spacing 1/4 (co-spherical everywhere).  Each of the 64 cells has
+    circumradius sqrt(3)/8 = 0.2165.  h = 0.2 (r / h = 1.08) inserts nothing.  h = 0.12
+    (r / h = 1.80) proposes the centre of every cell six times (once per tetrahedron of the
+    cell) and keeps it once: centres are 1/4 apart and sqrt(3)/8 from the corners, both above
+    0.7 h.  The lattice plus the centres is body-centred cubic, whose Delaunay tetrahedra have
+    circumradius sqrt(5)/16 = 0.1398 (r / h = 1.16); the tetrahedra on a hull face have their
+    circumcentres outside the hull.  So refinement stops with exactly the 64 centres added."""
+    lat = np.array(list(itertools.product(np.arange(5.0) / 4, repeat=3)))
+    pts, tets, nbrs, steps = R.refine(lat, 0.2)
+    assert len(pts) == 125 and steps == [(0, 0)]
+    pts, tets, nbrs, steps = R.refine(lat, 0.12)
+    assert steps == [(384, 64), (0, 0)]
+    centres = np.array(list(itertools.product((np.arange(4.0) + 0.5) / 4, repeat=3)))
+    got = pts[125:]
+    assert len(got) == 64
+    assert np.array_equal(got[np.lexsort(got.T[::-1])], centres[np.lexsort(centres.T[::-1])])
+    check_invariants(pts, tets, nbrs, oracle_mod, expect_vertices=np.arange(len(pts)))
+
+
 @pytest.mark.parametrize("kind,h", [("uniform", 0.08), ("uniform", 0.05), ("clusters", 0.03)])
 def test_refined_mesh_properties(R, oracle_mod, kind, h):
     """What the rule fixes at the end: the result is the Delaunay tetrahedralization of its
