@@ -162,7 +162,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--seed", type=int, default=1007)
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=2_500_000,
+                    help="uniform: points of the oracle's CPU sample (about 10 s on one core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--round-fraction", type=float, default=0.0)
     ap.add_argument("--round-size", type=int, default=0)
