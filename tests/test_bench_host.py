@@ -100,3 +100,70 @@ def test_paper_context_is_quoted_only_where_the_paper_has_the_size():
     assert b.paper_context(100_000_000)["value_at_this_n"] == 64.40e6
     assert "value_at_this_n" not in b.paper_context(1_000_000)
     assert "context" in b.paper_context(1)["note"]
+
+
+def test_bench_line_contract(monkeypatch, capsys):
+    """bench.main() on stand-ins for the device (no GPU here): the one JSON line carries every
+    field of the output contract, with value = tetrahedra / (ms_per_step / 1000)."""
+    import json
+
+    import torch
+
+    import paper_1805_08831_amd as pkg
+    from paper_1805_08831_amd import dt
+
+    class Stream:
+        cuda_stream = 0
+
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    monkeypatch.setattr(torch.cuda, "current_stream", lambda *a, **k: Stream())
+    monkeypatch.setattr(torch.Tensor, "cuda", lambda self, *a, **k: self)
+    real_empty = torch.empty
+    monkeypatch.setattr(torch, "empty", lambda *a, **k: real_empty(*a, **{x: y for x, y in k.items() if x != "device"}))
+    stats = {n: 0 for n, _ in dt.dt_stats._fields_}
+    stats.update(attempts=1350, walk_steps=7700, cavity_tets=20000, boundary_facets=26800, inserted=1000,
+                 ms_cavity_kernel=12.0, ms_ball_kernel=7.0, cavity_launches=50, ball_launches=50, rounds=50,
+                 ms_sort=3.0, ms_insert=20.0)
+
+    class Tri:
+        def __init__(self, **k):
+            self.ctx = 1
+
+        def clear(self):
+            pass
+
+        def insert(self, x):
+            dt._points(x)
+
+        def stats(self):
+            return dict(stats)
+
+        def close(self):
+            pass
+
+    def get_tets(ctx, t=None, nb=None, cap=0):
+        dt._out(t, dt._TET_TYPES, 4 * cap, "tets")
+        dt._out(nb, dt._NBR_TYPES, 4 * cap, "nbrs")
+        return 6700
+
+    monkeypatch.setattr(pkg, "Triangulation", Tri)
+    monkeypatch.setattr(pkg, "dt_get_tets", get_tets)
+    b = load_bench()
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--n", "2000", "--steps", "2", "--warmup", "1", "--no-learned",
+                                      "--cpu-sample", "1000"])
+    b.main()
+    line = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in line, k
+    assert line["n_gpus"] == 1 and line["steps"] == 2 and line["warmup"] == 1
+    assert line["higher_is_better"] is True and line["vs_baseline"] is None and line["data"] == "synthetic"
+    assert line["dtype"] == "f64" and "workload" in line["config"]
+    # ms_per_step is printed to 3 decimals: allow that rounding
+    assert abs(line["value"] * line["ms_per_step"] / 1000.0 - 6700) <= 6700 * (0.0006 / line["ms_per_step"] + 1e-6)
+    r = line["roofline"]
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-4 and "traffic" in r
+    assert r["traffic"] is None  # the counters were taken on the 1e7 workload only
+    c = line["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] == 1 and c["value"] > 0 and "sample" in c
