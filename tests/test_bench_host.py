@@ -102,11 +102,10 @@ def test_paper_context_is_quoted_only_where_the_paper_has_the_size():
     assert "context" in b.paper_context(1)["note"]
 
 
-def test_bench_line_contract(monkeypatch, capsys):
-    """bench.main() on stand-ins for the device (no GPU here): the one JSON line carries every
-    field of the output contract, with value = tetrahedra / (ms_per_step / 1000)."""
-    import json
-
+def _stand_ins(monkeypatch):
+    """Replaces the device (torch.cuda, the library's Triangulation and exports) with host
+    stand-ins that check the buffers the binding would pass and return fixed statistics."""
+    import numpy as np
     import torch
 
     import paper_1805_08831_amd as pkg
@@ -135,10 +134,22 @@ def test_bench_line_contract(monkeypatch, capsys):
         def insert(self, x):
             dt._points(x)
 
+        def insert_batch(self, x, off):
+            dt._points(x, int(off[-1]))
+
+        def num_tets(self):
+            return 6700
+
         def stats(self):
             return dict(stats)
 
         def close(self):
+            pass
+
+        def __enter__(self):
+            return self
+
+        def __exit__(self, *a):
             pass
 
     def get_tets(ctx, t=None, nb=None, cap=0):
@@ -148,17 +159,36 @@ def test_bench_line_contract(monkeypatch, capsys):
 
     monkeypatch.setattr(pkg, "Triangulation", Tri)
     monkeypatch.setattr(pkg, "dt_get_tets", get_tets)
+    monkeypatch.setattr(pkg, "dt_get_point_log", lambda ctx: (np.zeros((100, 16), np.float32),
+                                                              np.zeros(100, np.float32), np.zeros(100, np.uint8)))
+    monkeypatch.setattr(pkg, "dt_train_model", lambda *a, **k: b"model")
+    monkeypatch.setattr(pkg, "dt_load_model", lambda ctx, m: None)
+
+
+CONTRACT_KEYS = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                 "scaling", "vs_baseline", "dtype", "data", "config")
+
+
+def _run_bench(monkeypatch, capsys, args):
+    import json
     b = load_bench()
-    monkeypatch.setattr(sys, "argv", ["bench.py", "--n", "2000", "--steps", "2", "--warmup", "1", "--no-learned",
-                                      "--cpu-sample", "1000"])
+    monkeypatch.setattr(sys, "argv", ["bench.py"] + args)
     b.main()
     line = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
-    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
-              "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+    for k in CONTRACT_KEYS:
         assert k in line, k
-    assert line["n_gpus"] == 1 and line["steps"] == 2 and line["warmup"] == 1
-    assert line["higher_is_better"] is True and line["vs_baseline"] is None and line["data"] == "synthetic"
-    assert line["dtype"] == "f64" and "workload" in line["config"]
+    assert line["n_gpus"] == 1 and line["higher_is_better"] is True and line["vs_baseline"] is None
+    assert line["data"] == "synthetic" and line["dtype"] == "f64" and "workload" in line["config"]
+    return line
+
+
+def test_bench_line_contract(monkeypatch, capsys):
+    """bench.main() on stand-ins for the device (no GPU here): the one JSON line carries every
+    field of the output contract, with value = tetrahedra / (ms_per_step / 1000)."""
+    _stand_ins(monkeypatch)
+    line = _run_bench(monkeypatch, capsys, ["--n", "2000", "--steps", "2", "--warmup", "1", "--no-learned",
+                                            "--cpu-sample", "1000"])
+    assert line["steps"] == 2 and line["warmup"] == 1
     # ms_per_step is printed to 3 decimals: allow that rounding
     assert abs(line["value"] * line["ms_per_step"] / 1000.0 - 6700) <= 6700 * (0.0006 / line["ms_per_step"] + 1e-6)
     r = line["roofline"]
@@ -167,3 +197,15 @@ def test_bench_line_contract(monkeypatch, capsys):
     assert r["traffic"] is None  # the counters were taken on the 1e7 workload only
     c = line["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] == 1 and c["value"] > 0 and "sample" in c
+
+
+def test_bench_line_contract_batch_and_mix(monkeypatch, capsys):
+    _stand_ins(monkeypatch)
+    line = _run_bench(monkeypatch, capsys, ["--workload", "batch", "--clouds", "8", "--chunk", "4",
+                                            "--loop-sample", "2", "--steps", "1", "--warmup", "0",
+                                            "--no-cpu-baseline"])
+    assert line["config"]["calls_per_step"] == 2 and line["config"]["rounds_per_step"] == 100
+    assert line["cpu_baseline"] is None
+    line = _run_bench(monkeypatch, capsys, ["--workload", "mix", "--mix-scale", "0.001", "--train-samples", "100",
+                                            "--steps", "1", "--warmup", "0", "--cpu-mix-scale", "0.05"])
+    assert line["learned"]["same_count"] and line["cpu_baseline"]["kind"] == "oracle"
