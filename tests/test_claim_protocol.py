@@ -40,9 +40,10 @@ def _cavities(oracle_mod, xyz, tets, nbrs, new_idx):
 
 
 def _round(oracle_mod, seed, claim_outer=True):
-    """One round of 500 new points on the triangulation of 2500: returns (attempts with their
-    ranks, winners, number of winner pairs whose cavity meets the other's outer tetrahedra,
-    whether all winners applied at once give the oracle's triangulation)."""
+    """One round on the triangulation of 2500 points, attempted by the next 500 points that lie
+    in [0.15, 0.85]^3 (about 170): returns (attempts, ranks, winners, number of winner pairs
+    whose cavities meet, whether all winners applied at once give the oracle's
+    triangulation)."""
     xyz = uniform_points(3000, 900 + seed)
     n0 = 2500
     # the new points away from the hull, so that no cavity reaches a ghost
