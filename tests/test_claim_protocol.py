@@ -113,28 +113,28 @@ def test_rounds_until_every_point_is_in(oracle_mod):
     give the oracle's triangulation of the points inserted so far."""
     xyz = uniform_points(2400, 907)
     n0 = 2000
-    todo = [i for i in range(n0, 2400) if np.all((xyz[i] > 0.15) & (xyz[i] < 0.85))]
-    rank = {p: r for r, p in enumerate(np.random.default_rng(7).permutation(todo))}
+    pending = [i for i in range(n0, 2400) if np.all((xyz[i] > 0.15) & (xyz[i] < 0.85))]
+    rank = {p: r for r, p in enumerate(np.random.default_rng(7).permutation(pending))}
     done = list(range(n0))
     rounds = 0
-    while todo:
+    while pending:
         rounds += 1
         sub = np.array(sorted(done))
         rc, tets, nbrs, _ = oracle_mod.delaunay(xyz[sub])
         assert rc == 0
         tets, nbrs = sub[tets.astype(np.int64)], nbrs.astype(np.int64)  # global point indices
-        cavs = _cavities(oracle_mod, xyz, tets, nbrs, todo)
+        cavs = _cavities(oracle_mod, xyz, tets, nbrs, pending)
         assert all(c is not None for c in cavs)
         claim = {}
-        for p, (cav, outer) in zip(todo, cavs):
+        for p, (cav, outer) in zip(pending, cavs):
             S = 2 * rank[p]
             for t in cav:
                 claim[t] = min(claim.get(t, S), S)
             for t in outer:
                 claim[t] = min(claim.get(t, S + 1), S + 1)
-        won = [(p, cav) for p, (cav, outer) in zip(todo, cavs)
+        won = [(p, cav) for p, (cav, outer) in zip(pending, cavs)
                if all(claim[t] == 2 * rank[p] for t in cav) and all(claim[t] % 2 == 1 for t in outer)]
-        assert min(todo, key=rank.get) in {p for p, _ in won}
+        assert min(pending, key=rank.get) in {p for p, _ in won}
         keep = np.ones(len(tets), dtype=bool)
         balls = []
         for p, cav in won:
@@ -143,7 +143,7 @@ def test_rounds_until_every_point_is_in(oracle_mod):
                       for t in cav for j in range(4) if nbrs[t, j] not in cav]
         built = np.vstack([tets[keep], np.array(balls, dtype=np.int64)])
         done += [p for p, _ in won]
-        todo = [p for p in todo if p not in {q for q, _ in won}]
+        pending = [p for p in pending if p not in {q for q, _ in won}]
         sub = np.array(sorted(done))
         pos = {int(g): k for k, g in enumerate(sub)}
         rc, ref, _, _ = oracle_mod.delaunay(xyz[sub])
