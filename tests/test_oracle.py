@@ -195,7 +195,8 @@ def _oracle_canon(oracle_mod, xyz, order="brio"):
     return oracle_mod.canonical(tets), tets, nbrs
 
 
-@pytest.mark.parametrize("n,seed", [(4, 1), (5, 2), (5, 3), (6, 4), (8, 5), (10, 6), (12, 7), (12, 8)])
+@pytest.mark.parametrize("n,seed", [(4, 1), (5, 2), (5, 3), (6, 4), (8, 5), (10, 6), (12, 7), (12, 8),
+                                    (20, 60), (32, 72), (40, 80)])
 def test_bruteforce_uniform(oracle_mod, n, seed):
     xyz = uniform_points(n, seed)
     canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
@@ -230,6 +231,14 @@ def test_bruteforce_coplanar_hull(oracle_mod):
         canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
         assert np.array_equal(canon, brute_force_dt(xyz))
         check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(len(xyz)))
+
+
+def test_bruteforce_lattice_40(oracle_mod):
+    """40 distinct nodes of a 4^3 lattice: co-spherical everywhere, the perturbation decides."""
+    xyz = lattice_points(40, 5, side=4)
+    canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
+    assert np.array_equal(canon, brute_force_dt(xyz))
+    check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(40))
 
 
 def test_bruteforce_lattice_3x3x3(oracle_mod):
