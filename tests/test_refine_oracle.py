@@ -169,3 +169,48 @@ def test_refine_matches_stored_results(R):
         assert (kind, int(n), int(seed), float(h)) == case
         npts, steps, ht, hp = rhs.split()
         assert mk.run_case(*case) == (int(npts), steps, ht, hp)
+
+
+def _filter_in_rounds(R, cand, order, vertices, h):
+    """The filter as parallel rounds (the form a GPU would run): drop candidates too close to a
+    vertex; then, each round, every undecided candidate whose lower-ranked conflicting
+    candidates are all decided is kept iff none of them was kept.  Returns (kept in rank
+    order, rounds)."""
+    from scipy.spatial import cKDTree
+    lim = (0.7 * h) * (0.7 * h)
+    rank = np.empty(len(cand), dtype=np.int64)
+    rank[order] = np.arange(len(order))
+    near = cKDTree(vertices).query_ball_point(cand, 0.7 * h * 1.000001)
+    alive = np.array([not (nb and np.any(R.sq_dist(vertices[nb], cand[i]) < lim)) for i, nb in enumerate(near)])
+    tree = cKDTree(cand)
+    lower = []
+    for i in range(len(cand)):
+        nb = [j for j in tree.query_ball_point(cand[i], 0.7 * h * 1.000001)
+              if j != i and alive[j] and rank[j] < rank[i] and R.sq_dist(cand[j], cand[i]) < lim]
+        lower.append(nb)
+    state = np.where(alive, 0, -1)  # 0 undecided, 1 kept, -1 dropped
+    rounds = 0
+    while np.any(state == 0):
+        rounds += 1
+        ready = [i for i in np.nonzero(state == 0)[0] if all(state[j] != 0 for j in lower[i])]
+        new = {i: (1 if all(state[j] != 1 for j in lower[i]) else -1) for i in ready}
+        for i, v in new.items():
+            state[i] = v
+    kept = [i for i in order if state[i] == 1]
+    return kept, rounds
+
+
+def test_filter_rounds_equal_greedy(R, oracle_mod):
+    """The parallel-round form of the filter keeps exactly the greedy filter's candidates, for
+    random ranks and for the Moore-curve ranks the oracle uses; a few rounds suffice."""
+    r = np.random.default_rng(5)
+    for h, k, moore in [(0.1, 600, False), (0.05, 3000, False), (0.05, 3000, True)]:
+        verts = r.random((200, 3))
+        cand = r.random((k, 3))
+        if moore:
+            order = np.argsort(oracle_mod.moore_keys(cand, oracle_mod.moore_level(k)), kind="stable")
+        else:
+            order = r.permutation(k)
+        kept, rounds = _filter_in_rounds(R, cand, order, verts, h)
+        assert kept == list(R.greedy_filter(cand, order, verts, h))
+        assert 1 <= rounds < 20
