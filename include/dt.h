@@ -6,9 +6,9 @@
  * Marot, Pellerin and Remacle, "One machine, one minute, three billion tetrahedra",
  * Sec. 2.1, Eq. (1) and Algorithm 1), with thousands of insertions per round on the GPU.
  *
- * Problem statement (Sec. 1): for a set S of n points the output is a set of
- * non-overlapping tetrahedra that covers the convex hull of S, uses every distinct point
- * of S as a vertex, and whose circumspheres contain no point of S.  Points in
+ * Problem (Sec. 1): given n points S, the output tetrahedra have pairwise disjoint
+ * interiors and their union is the convex hull of S; every distinct point of S is a
+ * vertex, and no point of S lies strictly inside any output circumsphere.  Points in
  * non-general position are resolved by symbolic perturbation (Sec. 2.4, item 3): the
  * lifted coordinate |p_i|^2 of the point with input index i is perturbed by eps^delta_i,
  * delta strictly decreasing in i.  The result is therefore unique and does not depend on
@@ -63,8 +63,9 @@ typedef struct {
                                0: automatic                                              */
     uint32_t lanes_per_insert; /* lanes of a wavefront cooperating on one insertion in the
                                   walk and cavity search: 4, 8, 16 or 64; 0: automatic   */
-    int scheduler;          /* DT_SCHED_PLAIN (0) or DT_SCHED_LEARNED (1, needs a model:
-                               dt_load_model or dt_train_model)                          */
+    int scheduler;          /* DT_SCHED_PLAIN (0) or DT_SCHED_LEARNED (1: uses the model of
+                               dt_load_model or dt_train_model; without one the call runs
+                               the plain order and counts dt_stats.sched_fallbacks)      */
     int log_points;         /* 1: record the attempts of every point (dt_get_point_log)  */
 } dt_options;
 
@@ -94,6 +95,8 @@ typedef struct {
     uint64_t cavity_launches, ball_launches;
     double ms_cavity_kernel, ms_ball_kernel;
     uint64_t cavity_units, ball_units; /* attempts processed / insertions completed   */
+    uint64_t sched_fallbacks; /* calls with DT_SCHED_LEARNED but no model loaded, run in the
+                                 plain order instead                                     */
 } dt_stats;
 
 /* Fill *opt with the defaults (device 0, library stream, automatic sizes, seed 0x5EED). */
@@ -211,6 +214,11 @@ const char *dt_last_error(const dt_ctx *ctx);
    the point at each sorted position; *moore_m receives m.  Device or host outputs. */
 int dt_debug_sort(dt_ctx *ctx, const double *xyz, uint64_t n, uint64_t *keys, uint32_t *perm,
                   int *moore_m);
+
+/* Sets the context's round counter (the stamp of the next round's claims).  Claim stamps
+   take the low 32 bits of the counter; when they wrap, the library resets every claim word
+   before the round.  Lets a test cross the wrap without 2^32 rounds. */
+int dt_debug_set_round_counter(dt_ctx *ctx, uint64_t rounds);
 
 /* Predicates (Sec. 2.4): for k records evaluates, per record r,
    kind 0: orient3d sign of pts[12r .. 12r+11] (four points);

@@ -144,6 +144,7 @@ struct dt_ctx {
     DevBuf<uint32_t> log_att;
     DevBuf<float> feat, ypred;
     bool have_model = false, logged = false;
+    bool learned_active = false;  // this call runs the learned order (scheduler set and a model loaded)
     float thr = 0.0f;
     float costly_scale = 1.0f;
     uint64_t log_base = 0, log_n = 0;
@@ -367,7 +368,7 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.anchor = c->anchor.p;
     a.clouds = c->clouds.p;
     a.log_att = c->logged ? c->log_att.p : nullptr;
-    a.wbucket = c->opt.scheduler == DT_SCHED_LEARNED ? c->wbucket.p : nullptr;
+    a.wbucket = c->learned_active ? c->wbucket.p : nullptr;
     a.cand_pt = c->lpt[ci] + off;
     a.cand_rank = c->lrank[ci] + off;
     a.next_pt = c->lpt[ni];
@@ -396,6 +397,12 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.capF = capF;
     a.tcap = c->tcap;
     a.hmg = 1u << (31 - __builtin_clz(std::min<uint32_t>(4u * std::min<uint32_t>(capC, 1u << 24), 1u << 30)));
+    // Claim words are never reset between rounds: later rounds stamp lower.  When the low 32
+    // bits of the round counter wrap, every claim left in the pool would outrank the new
+    // stamps, so the claim words are reset to the empty value first (the kernels of earlier
+    // rounds are ahead of the reset on the same stream).
+    if ((c->round_counter & 0xFFFFFFFFull) == 0 && c->round_counter != 0 && c->tcap)
+        HIPCHK(launch_reset_claims(c->T, c->tcap, c->stream));
     a.round_hi = (0xFFFFFFFFull - (c->round_counter & 0xFFFFFFFFull)) << 32;
     c->round_counter++;
     HIPCHK(launch_round(a, max_cand, c->lanes, c->stream, c->opt.timing ? c->ev[slot] : nullptr));
@@ -869,11 +876,14 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
     if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
     HIPCHK(launch_anchor(lord, d_start, L, c->V.p, base, n, c->anchor.p, c->stream));
     c->lord = lord;
-    const bool learned = c->opt.scheduler == DT_SCHED_LEARNED;
+    // without a model the learned scheduler falls back to the plain order (counted in the
+    // statistics); the triangulation is the same either way
+    const bool learned = c->opt.scheduler == DT_SCHED_LEARNED && c->have_model;
+    if (c->opt.scheduler == DT_SCHED_LEARNED && !c->have_model) c->st.sched_fallbacks++;
+    c->learned_active = learned;
     if (learned) {
         // learned order: each BRIO level split into the points predicted cheap, then the
         // costly ones; walk-start buckets from the same MLP pass
-        if (!c->have_model) return fail(c, DT_E_ARG, "the learned scheduler needs a model (dt_load_model)");
         if ((rc = ensure(c, c->feat, (size_t)n * NFEAT)) || (rc = ensure(c, c->ypred, (size_t)n * NOUT)) ||
             (rc = ensure(c, c->wbucket, n)))
             return rc;
@@ -1139,10 +1149,11 @@ int dt_get_tets_batch(dt_ctx *c, uint32_t cloud, uint32_t *tets, int64_t *nbrs, 
     }
     HIPCHK(launch_output_cloud(c->T, c->V.p, c->osorted_live, c->omap2.p, tb, te, c->h_off[cloud], ot, on,
                                c->stream));
+    // the destination is host memory or an unaligned device buffer
     if (tets && !dev_t)
-        HIPCHK(hipMemcpyAsync(tets, ot, 4 * T * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(tets, ot, 4 * T * sizeof(uint32_t), hipMemcpyDefault, c->stream));
     if (nbrs && !dev_n)
-        HIPCHK(hipMemcpyAsync(nbrs, on, 4 * T * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(nbrs, on, 4 * T * sizeof(int64_t), hipMemcpyDefault, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return DT_OK;
 }
@@ -1528,6 +1539,12 @@ int dt_debug_sort(dt_ctx *c, const double *xyz, uint64_t n, uint64_t *keys, uint
         HIPCHK(hipMemcpy(perm, ph.data(), n * sizeof(uint32_t), hipMemcpyDefault));
     }
     if (moore_m) *moore_m = mmax;
+    return DT_OK;
+}
+
+int dt_debug_set_round_counter(dt_ctx *c, uint64_t rounds) {
+    if (!c) return DT_E_ARG;
+    c->round_counter = rounds;
     return DT_OK;
 }
 

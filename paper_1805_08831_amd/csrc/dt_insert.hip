@@ -967,6 +967,19 @@ hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s
     return hipGetLastError();
 }
 
+// Claim words back to the empty value (above every stamp), for the round after the round
+// counter's low 32 bits wrap.  A fill kernel rather than a strided memset.
+__global__ void k_reset_claims(Tet *__restrict__ T, uint32_t tcap) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < tcap; t += gridDim.x * blockDim.x)
+        T[t].claim = ~0ull;
+}
+
+hipError_t launch_reset_claims(Tet *T, uint32_t tcap, hipStream_t s) {
+    if (tcap == 0) return hipSuccess;
+    k_reset_claims<<<2048, 256, 0, s>>>(T, tcap);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ output
 
 __global__ void k_out_flags(const Tet *__restrict__ T, uint32_t count, uint32_t *__restrict__ flags) {

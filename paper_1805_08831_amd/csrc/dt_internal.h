@@ -206,6 +206,7 @@ hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, con
                             uint32_t *ncand, hipStream_t s);
 hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s);
+hipError_t launch_reset_claims(Tet *T, uint32_t tcap, hipStream_t s);
 hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s);
 hipError_t launch_output(const Tet *T, const Vert *V, uint32_t nv, const uint32_t *flags, uint32_t *map,
                          uint32_t *vid, uint32_t count, uint32_t *tets, int64_t *nbrs, hipStream_t s);

@@ -43,7 +43,8 @@ class dt_stats(ctypes.Structure):
                 [("ms_total", ctypes.c_double), ("ms_sort", ctypes.c_double), ("ms_insert", ctypes.c_double),
                  ("cavity_launches", ctypes.c_uint64), ("ball_launches", ctypes.c_uint64),
                  ("ms_cavity_kernel", ctypes.c_double), ("ms_ball_kernel", ctypes.c_double),
-                 ("cavity_units", ctypes.c_uint64), ("ball_units", ctypes.c_uint64)])
+                 ("cavity_units", ctypes.c_uint64), ("ball_units", ctypes.c_uint64),
+                 ("sched_fallbacks", ctypes.c_uint64)])
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -88,9 +89,11 @@ def lib():
         L.dt_debug_mlp_grad.argtypes = [vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
         L.dt_debug_sort.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(i32)]
         L.dt_debug_predicates.argtypes = [vp, i32, vp, vp, u64, vp]
+        L.dt_debug_set_round_counter.argtypes = [vp, u64]
         for f in ("dt_create", "dt_insert_points", "dt_get_tets", "dt_clear", "dt_destroy", "dt_get_stats",
                   "dt_insert_batch", "dt_get_tets_batch", "dt_autotune", "dt_get_point_log", "dt_train_model",
-                  "dt_load_model", "dt_debug_mlp", "dt_debug_mlp_grad", "dt_debug_sort", "dt_debug_predicates"):
+                  "dt_load_model", "dt_debug_mlp", "dt_debug_mlp_grad", "dt_debug_sort", "dt_debug_predicates",
+                  "dt_debug_set_round_counter"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -274,6 +277,10 @@ def dt_debug_sort(ctx, xyz):
     m = ctypes.c_int(0)
     _check(ctx, lib().dt_debug_sort(ctx, p, n, keys.ctypes.data, perm.ctypes.data, ctypes.byref(m)))
     return keys, perm, int(m.value)
+
+
+def dt_debug_set_round_counter(ctx, rounds):
+    _check(ctx, lib().dt_debug_set_round_counter(ctx, int(rounds)))
 
 
 def dt_debug_predicates(ctx, kind, pts, idx=None):

@@ -327,6 +327,45 @@ def test_batch_mixed_clouds(dtlib, oracle_mod):
         assert_parity(oracle_mod, uniform_points(1000, 13), t.astype(np.int64), "single cloud after clear")
 
 
+def test_batch_export_to_unaligned_device_buffers(dtlib, oracle_mod):
+    """dt_get_tets_batch into device buffers that are not 16-byte aligned goes through the
+    staging buffers and must give what the aligned export gives."""
+    say("batch: export into unaligned device buffers")
+    import torch
+    xyz, off = batch_clouds(6, seed_base=7100, nmin=500, nmax=3000)
+    with dtlib.Triangulation(stream=torch.cuda.current_stream().cuda_stream) as tri:
+        tri.insert_batch(xyz, off)
+        for k in range(6):
+            T = dtlib.dt_get_tets_batch(tri.ctx, k)
+            bt = torch.full((T + 1, 4), -7, dtype=torch.int32, device="cuda")
+            bn = torch.full((T + 1, 4), -7, dtype=torch.int64, device="cuda")
+            vt = bt.view(-1)[1:1 + 4 * T]
+            vn = bn.view(-1)[1:1 + 4 * T]
+            assert vt.data_ptr() % 16 and vn.data_ptr() % 16
+            assert dtlib.dt_get_tets_batch(tri.ctx, k, vt, vn, T) == T
+            torch.cuda.synchronize()
+            t, nb = tri.tets_batch(k)
+            assert np.array_equal(vt.cpu().numpy().reshape(T, 4), t.astype(np.int32))
+            assert np.array_equal(vn.cpu().numpy().reshape(T, 4), nb)
+            assert bt.view(-1)[0].item() == -7 and bn.view(-1)[0].item() == -7
+            assert_parity(oracle_mod, xyz[off[k]:off[k + 1]], t.astype(np.int64), f"cloud {k}")
+
+
+def test_claim_stamps_across_the_round_counter_wrap(dtlib, oracle_mod):
+    """Claim stamps take the low 32 bits of the round counter; the rounds of this insert
+    cross the wrap (the library resets the claim words there), and the result is unchanged."""
+    say("round counter wrap")
+    xyz = uniform_points(30000, 81)
+    with dtlib.Triangulation() as tri:
+        tri.insert(uniform_points(2000, 80))  # claims left in the pool by earlier rounds
+        tri.clear()
+        dtlib.dt_debug_set_round_counter(tri.ctx, (1 << 32) - 7)
+        tri.insert(xyz)
+        assert tri.stats()["rounds"] > 7
+        t, nb = tri.tets()
+        assert_parity(oracle_mod, xyz, t.astype(np.int64), "across the wrap")
+
+
 def test_batch_degenerate_cloud(dtlib):
     say("batch: a coplanar cloud is reported by index")
     flat = np.array([[x, y, 0.0] for x in range(3) for y in range(3)], dtype=np.float64)
@@ -386,7 +425,7 @@ def test_mlp_matches_cpu_reference(dtlib):
     say("mlp: inference and gradient vs CPU reference, training fit")
     f, cost, bucket = _synthetic_samples(16384, 5)
     with dtlib.Triangulation() as tri:
-        model = dtlib.dt_train_model(tri.ctx, f, cost, bucket, epochs=10, lr=3e-3, seed=7)
+        model = dtlib.dt_train_model(tri.ctx, f, cost, bucket, epochs=40, lr=3e-3, seed=7)
         ps = [torch.tensor(_bf16(p)).requires_grad_(True) for p in _unpack(model)]
 
         def forward(x):
@@ -406,8 +445,8 @@ def test_mlp_matches_cpu_reference(dtlib):
         np.testing.assert_allclose(g, gr, rtol=2e-3, atol=2e-6)
         assert abs(loss / n - ref.item()) < 1e-3 * (1.0 + ref.item())
         yall = dtlib.dt_debug_mlp(tri.ctx, f)
-        assert np.corrcoef(yall[:, 0], cost)[0, 1] > 0.85
-        assert ((yall[:, 2] > yall[:, 1]) == (bucket == 1)).mean() > 0.85
+        assert np.corrcoef(yall[:, 0], cost)[0, 1] > 0.9
+        assert ((yall[:, 2] > yall[:, 1]) == (bucket == 1)).mean() > 0.9
 
 
 def test_learned_scheduler_keeps_result(dtlib, oracle_mod):
@@ -423,10 +462,12 @@ def test_learned_scheduler_keeps_result(dtlib, oracle_mod):
         assert (c < 1.0).sum() == 4 and c.mean() > 1.0
         model = dtlib.dt_train_model(tri.ctx, f, c, b, epochs=4, seed=3)
     xyz = mix_small(62, 7000)
+    # without a model the learned scheduler falls back to the plain order
     with dtlib.Triangulation(scheduler=dtlib.DT_SCHED_LEARNED) as tri:
-        with pytest.raises(dtlib.DTError) as e:
-            tri.insert(xyz)
-        assert e.value.code == dtlib.DT_E_ARG
+        tri.insert(xyz)
+        assert tri.stats()["sched_fallbacks"] == 1
+        t, _ = tri.tets()
+        assert_parity(oracle_mod, xyz, t.astype(np.int64), "learned scheduler without a model")
     with dtlib.Triangulation(scheduler=dtlib.DT_SCHED_LEARNED) as tri:
         dtlib.dt_load_model(tri.ctx, model)
         tri.insert(xyz)

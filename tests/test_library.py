@@ -80,6 +80,7 @@ def test_every_entry_point_rejects_a_null_context(libdt):
         "dt_debug_mlp_grad": (n, n, n, n, 0, n, n),
         "dt_debug_sort": (n, n, 0, n, n, n),
         "dt_debug_predicates": (n, 0, n, n, 0, n),
+        "dt_debug_set_round_counter": (n, 0),
         "dt_clear": (n,),
         "dt_destroy": (n,),
         "dt_get_stats": (n, n),
