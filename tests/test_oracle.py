@@ -74,6 +74,141 @@ def test_insphere_matches_rational(oracle_mod):
     assert np.count_nonzero(want == 0) > 20
 
 
+# ------------------------------------------------------------------ the accepted domain's edges
+# Coordinates are 0 or have magnitude in [2^-120, 2^120).  The exact stage turns every
+# coordinate into an integer multiple of 2^-(120 + 52), so one determinant can hold terms
+# 2^239 apart; these cases put such extremes into one call, with exact zeros and one-ulp
+# nudges, and compare with rational arithmetic.
+
+_WIDE_RNG = np.random.default_rng(2024)
+
+
+def _wide(shape, lo=-120, hi=119):
+    """Coordinates sign * (1 + u) * 2^e, e uniform in [lo, hi] (inside the accepted domain)."""
+    m = 1.0 + _WIDE_RNG.random(shape)
+    e = _WIDE_RNG.integers(lo, hi + 1, size=shape)
+    sgn = np.where(_WIDE_RNG.random(shape) < 0.5, -1.0, 1.0)
+    out = np.ldexp(sgn * m, e)
+    return np.where(np.abs(out) >= 2.0 ** 120, np.ldexp(sgn * 1.5, 119), out)
+
+
+def _scaled(points, k):
+    return np.ldexp(np.asarray(points, dtype=np.float64), k)
+
+
+def _wide_orient_cases():
+    cases = [_wide((4, 3)) for _ in range(120)]
+    # the extremes only: every coordinate is +-2^-120, +-2^119 or 0
+    ext = np.array([2.0 ** -120, -2.0 ** -120, 2.0 ** 119, -2.0 ** 119, 0.0])
+    cases += [ext[_WIDE_RNG.integers(0, 5, size=(4, 3))] for _ in range(80)]
+    # coplanar: equal z (any x, y spread) -> exactly 0; one z nudged by an ulp -> tiny
+    for t in range(120):
+        c = _wide((4, 3))
+        c[:, 2] = c[0, 2]
+        if t % 2:
+            k = int(_WIDE_RNG.integers(0, 4))
+            c[k, 2] = nudge(c[k, 2], 1 if t % 4 == 1 else -1)
+        cases.append(c)
+    # a small plane far from the origin: lattice quadruples scaled by 2^-110 and 2^100
+    lat = lattice_points(100, 7, side=5)
+    for t in range(80):
+        q = lat[_WIDE_RNG.choice(len(lat), 4, replace=False)]
+        q = _scaled(q, -110 if t % 2 else 100)
+        if t % 3 == 0:
+            q[3, 0] = nudge(q[3, 0], 1) if q[3, 0] != 0 else 2.0 ** -120
+        cases.append(q)
+    return np.array(cases)
+
+
+def test_orient3d_matches_rational_at_the_domain_edges(oracle_mod):
+    pts = _wide_orient_cases()
+    assert np.all((pts == 0) | ((np.abs(pts) >= 2.0 ** -120) & (np.abs(pts) < 2.0 ** 120)))
+    got = oracle_mod.orient3d(pts)
+    want = np.array([orient3d_exact(*c) for c in pts])
+    assert np.array_equal(got, want)
+    assert np.count_nonzero(want == 0) > 40 and np.count_nonzero(want != 0) > 200
+
+
+def _wide_insphere_cases():
+    cases = [_wide((5, 3)) for _ in range(100)]
+    ext = np.array([2.0 ** -120, -2.0 ** -120, 2.0 ** 119, -2.0 ** 119, 0.0])
+    cases += [ext[_WIDE_RNG.integers(0, 5, size=(5, 3))] for _ in range(60)]
+    sph = sphere50_points() / 8.0
+    for t in range(160):
+        # cospherical at scales 2^-115 .. 2^115 (exact), some nudged by an ulp
+        k = int(_WIDE_RNG.integers(-115, 116))
+        c = _scaled(sph[_WIDE_RNG.choice(len(sph), 5, replace=False)], k)
+        if t % 2:
+            j = int(np.flatnonzero(c[4])[0])
+            c[4, j] = nudge(c[4, j], 1 if t % 4 == 1 else -1)
+        cases.append(c)
+    for t in range(60):
+        # a tiny sphere next to a huge coordinate: the sum rounds, the rational reference
+        # takes the doubles as they are
+        c = _scaled(sph[_WIDE_RNG.choice(len(sph), 5, replace=False)], -100)
+        c[:, 0] += 2.0 ** int(_WIDE_RNG.integers(-60, 110))
+        cases.append(c)
+    return np.array(cases)
+
+
+def test_insphere_matches_rational_at_the_domain_edges(oracle_mod):
+    pts = _wide_insphere_cases()
+    assert np.all((pts == 0) | ((np.abs(pts) >= 2.0 ** -120) & (np.abs(pts) < 2.0 ** 120)))
+    got = oracle_mod.insphere(pts)
+    want = np.array([insphere_exact(c) for c in pts])
+    assert np.array_equal(got, want)
+    assert np.count_nonzero(want == 0) > 60 and np.count_nonzero(want != 0) > 150
+
+
+def test_perturbed_insphere_matches_eps_polynomial_at_the_domain_edges(oracle_mod):
+    """The perturbation cascade on degenerate sets scaled to the domain's edges and on
+    mixed-magnitude points, against the eps-polynomial."""
+    sph = sphere50_points() / 8.0
+    cube = np.array(list(itertools.product([0.0, 1.0], repeat=3)))
+    lat = lattice_points(64, 3, side=4)
+    pts, idxs = [], []
+    trial = 0
+    while len(pts) < 150:
+        src = [sph, cube, lat][trial % 3]
+        k = [-117, 116, int(_WIDE_RNG.integers(-110, 110))][trial % 3]
+        trial += 1
+        c = _scaled(src[_WIDE_RNG.choice(len(src), 5, replace=False)], k)
+        if trial % 5 == 0:
+            c[4] = _wide((3,))  # a fifth point of any magnitude
+        if orient3d_exact(*c[:4]) == 0:
+            continue
+        c[:4] = _positive(c[:4])
+        pts.append(c)
+        idxs.append(_WIDE_RNG.permutation(1000)[:5])
+    pts, idxs = np.array(pts), np.array(idxs)
+    got = oracle_mod.insphere_sos(pts, idxs)
+    want = np.array([insphere_perturbed_poly(p, i) for p, i in zip(pts, idxs)])
+    assert np.all(want != 0)
+    assert np.array_equal(got, want)
+    raw = np.array([insphere_exact(p) for p in pts])
+    assert np.count_nonzero(raw == 0) > 30
+
+
+def test_bruteforce_at_the_domain_edges(oracle_mod):
+    """Whole triangulations at the edges of the domain: a cospherical set scaled by 2^-117,
+    a lattice scaled by 2^116, and a mixed cloud (a few points of magnitude 2^100 around a
+    cluster of magnitude 2^-100), each against brute force."""
+    sph = sphere50_points() / 8.0
+    xyz = _scaled(sph[np.random.default_rng(3).choice(len(sph), 12, replace=False)], -117)
+    assert np.array_equal(_oracle_canon(oracle_mod, xyz)[0], brute_force_dt(xyz))
+    xyz = _scaled(np.random.default_rng(4).permutation(
+        np.array(list(itertools.product([0.0, 0.5, 1.0], repeat=3))))[:16], 116)
+    canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
+    assert np.array_equal(canon, brute_force_dt(xyz))
+    check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(16))
+    big = _scaled(np.array(list(itertools.product([-1.0, 1.0], repeat=3))), 100)
+    small = _scaled(uniform_points(8, 91) - 0.5, -100)
+    xyz = np.random.default_rng(5).permutation(np.vstack([big, small]))
+    canon, tets, nbrs = _oracle_canon(oracle_mod, xyz)
+    assert np.array_equal(canon, brute_force_dt(xyz))
+    check_invariants(xyz, tets, nbrs, oracle_mod, expect_vertices=np.arange(16))
+
+
 def test_insphere_closed_forms(oracle_mod):
     """Hand-worked determinant values (tests/golden/insphere_closed_forms.txt)."""
     rows = [l.split() for l in open(os.path.join(GOLDEN, "insphere_closed_forms.txt"))
