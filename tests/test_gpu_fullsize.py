@@ -1,28 +1,32 @@
 """Checks at the benchmark's full sizes, in the launch configuration bench.py times (default
 options, device input and device outputs on torch's stream).
 
-A serial oracle run on 1e7 or 1e8 points would take minutes to hours, so the output is checked
-against the oracle on a sub-box, and by properties that hold at any size:
-
-* sub-box: every tetrahedron whose circumball lies inside a box B belongs to the Delaunay
-  tetrahedralization of all points iff it belongs to that of the points in B (its ball is
-  empty of the points in B, and holds no point outside B).  The oracle triangulates the points
-  in B; both outputs, filtered by one classifier (fp64 circumballs inside B shrunk by 1e-9),
-  must be equal;
-* every input point is a vertex;
-* adjacency: each neighbour link is mirrored and the two tetrahedra share three vertices;
-* the hull: V - E + F = 2 on the faces without neighbour, and the tetrahedra fill the volume of
-  the convex hull computed independently (scipy's Qhull);
-* local Delaunay (perturbed, exact, by the oracle) across a random sample of interior facets,
-  and positive orientation of the tetrahedra sampled.
+* whole-output equality with the oracle where the oracle's result is stored: uniform 1e6 and
+  1e7 and MIX 1e7 (tests/golden/fullsize_golden.txt holds the count and SHA-256 of the
+  oracle's canonical tetrahedra, written by make_fullsize_golden.py from the oracle alone);
+  the GPU output is canonicalized on the device and hashed;
+* at 1e8 (no stored oracle result: the serial oracle needs about 100 GB and most of an hour),
+  a complete certificate: every tetrahedron positive, every neighbour link mirrored on the
+  same facet, no two neighbours overlapping, every interior facet locally Delaunay under the
+  perturbation (fullcheck.c, the oracle's exact predicates), the hull facets one closed
+  locally convex surface and every point a vertex.  By Delaunay's lemma this is the unique
+  perturbed Delaunay tetrahedralization, the oracle's result.  A sub-box is also compared
+  with the oracle directly: a tetrahedron whose circumball lies inside a box B belongs to the
+  tetrahedralization of all points iff it belongs to that of the points in B;
+* the adjacency, hull and volume checks on the device at 1e7.
 """
 from __future__ import annotations
 
 import numpy as np
 import pytest
 
+import os
+
+from canon import canonical_hash_torch, read_golden
 from synth import uniform_points
 from test_gpu import dtlib, say  # noqa: F401  (fixture)
+
+GOLDEN = read_golden(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_golden.txt"))
 
 pytestmark = pytest.mark.gpu
 
@@ -78,13 +82,6 @@ def _subbox_check(oracle_mod, xyz, t_dev, lo, side, min_tets=None):
     assert a.shape == b.shape and np.array_equal(a, b)
 
 
-def _vertices_check(t_dev, n):
-    import torch
-    seen = torch.zeros(n, dtype=torch.bool, device="cuda")
-    seen[t_dev.reshape(-1).long()] = True
-    assert int(seen.sum()) == n
-
-
 def _adjacency_and_hull_check(t, nb):
     """On the device (torch): mirrored links sharing a facet; V - E + F = 2 on the hull."""
     import torch
@@ -126,80 +123,78 @@ def _volume_check(xyz, t):
     assert abs(vol - hull) <= 1e-8 * hull
 
 
-def _local_delaunay_sample(oracle_mod, xyz, t, nb, k, seed):
-    rng = np.random.default_rng(seed)
-    T = len(t)
-    picks = []
-    while sum(len(p) for p in picks) < k:
-        r = rng.integers(0, T, size=k)
-        j = rng.integers(0, 4, size=k)
-        ok = nb[r, j] >= 0
-        picks.append(np.stack([r[ok], j[ok]], axis=1))
-    rj = np.concatenate(picks)[:k]
-    r, j = rj[:, 0], rj[:, 1]
-    q = t[r]
-    assert np.all(oracle_mod.orient3d(xyz[q]) > 0)
-    assert np.all(nb[r, j] >= 0)
-    u = t[nb[r, j]]
-    inq = (u[:, :, None] == q[:, None, :]).any(axis=2)
-    assert np.all(inq.sum(axis=1) == 3)
-    ap = u[~inq]  # the neighbour's vertex across the shared facet, one per row
-    pts = np.concatenate([xyz[q], xyz[ap][:, None, :]], axis=1)
-    idx = np.concatenate([q, ap[:, None]], axis=1)
-    s = oracle_mod.insphere_sos(pts, idx)
-    assert np.all(s > 0), "a neighbour's apex lies inside a circumsphere"
+def _hash_check(t_dev, name):
+    g = GOLDEN[name]
+    count, digest = canonical_hash_torch(t_dev)
+    say(f"{name}: GPU {count} tetrahedra sha256 {digest[:16]}..; oracle {g['tets']} {g['sha256'][:16]}..")
+    assert count == int(g["tets"]) and digest == g["sha256"], f"{name}: output differs from the oracle's"
+
+
+def _full_certificate(oracle_mod, xyz, t_dev, nb_dev):
+    import fullcheck
+    t = t_dev.cpu().numpy().view(np.uint32)
+    nb = nb_dev.cpu().numpy()
+    say("every tetrahedron and facet (I1, I2, folds, I7)")
+    T, interior, hull = fullcheck.check_all_facets(xyz, t, nb)
+    say(f"{T} tetrahedra, {interior} interior facets locally Delaunay, {hull} hull facets")
+    assert 2 * interior + hull == 4 * T
+    assert fullcheck.check_hull_and_vertices(xyz, t, nb, oracle_mod, n_expect=len(xyz)) == hull
+
+
+def test_uniform_1e6_whole_output(dtlib):
+    """1e6 uniform points (seed 1006): the whole output equals the oracle's."""
+    say("full size: uniform 1e6 (seed 1006)")
+    t_dev, _ = _triangulate(dtlib, uniform_points(1_000_000, 1006))
+    _hash_check(t_dev, "uniform_1e6")
 
 
 def test_uniform_1e7_bench_config(dtlib, oracle_mod):
-    """The benchmark workload: 1e7 uniform points, seed 1007."""
+    """The benchmark workload: 1e7 uniform points, seed 1007.  The whole output equals the
+    oracle's; the certificate and the device-side checks run on it too."""
     n = 10_000_000
     say("full size: uniform 1e7 (seed 1007), bench configuration")
     xyz = uniform_points(n, 1007)
     t_dev, nb_dev = _triangulate(dtlib, xyz)
     say(f"{len(t_dev)} tetrahedra")
-    _subbox_check(oracle_mod, xyz, t_dev, 0.37, 0.2714)
-    _vertices_check(t_dev, n)
+    _hash_check(t_dev, "uniform_1e7")
     say("adjacency and hull")
     _adjacency_and_hull_check(t_dev, nb_dev)
     say("volume")
     _volume_check(xyz, t_dev)
-    say("local Delaunay sample")
-    t = t_dev.cpu().numpy().astype(np.int64)
-    nb = nb_dev.cpu().numpy()
-    _local_delaunay_sample(oracle_mod, xyz, t, nb, 20000, 11)
+    _full_certificate(oracle_mod, xyz, t_dev, nb_dev)
 
 
-def test_uniform_1e8_subbox(dtlib, oracle_mod):
-    """1e8 uniform points (seed 1008): sub-box against the oracle, every point a vertex."""
+def test_uniform_1e8_certificate(dtlib, oracle_mod):
+    """1e8 uniform points (seed 1008): the complete certificate on every facet, and a sub-box
+    against the oracle."""
     import torch
     n = 100_000_000
     say("full size: uniform 1e8 (seed 1008), bench configuration")
     xyz = uniform_points(n, 1008)
     t_dev, nb_dev = _triangulate(dtlib, xyz)
     say(f"{len(t_dev)} tetrahedra")
-    del nb_dev
-    torch.cuda.empty_cache()
     _subbox_check(oracle_mod, xyz, t_dev, 0.61, 0.126)
-    _vertices_check(t_dev, n)
+    _full_certificate(oracle_mod, xyz, t_dev, nb_dev)
+    del t_dev, nb_dev
+    torch.cuda.empty_cache()
 
 
-def test_mix_1e7_subboxes(dtlib, oracle_mod):
-    """MIX 1e7 (seed 2007, the benchmark's MIX input): sub-boxes in the lattice and in the
-    clusters against the oracle (the circumball argument holds under the perturbation: a ball
-    strictly inside B leaves every point outside B strictly outside), every point a vertex."""
+def test_mix_1e7_whole_output(dtlib, oracle_mod):
+    """MIX 1e7 (seed 2007, the benchmark's MIX input): the whole output equals the oracle's,
+    and sub-boxes in the lattice and in the clusters against the oracle directly."""
     from synth import mix_points
     say("full size: MIX 1e7 (seed 2007), bench configuration")
     xyz = mix_points(2007)
     t_dev, nb_dev = _triangulate(dtlib, xyz)
     say(f"{len(t_dev)} tetrahedra")
     del nb_dev
+    _hash_check(t_dev, "mix_1e7")
     # lattice nodes are odd multiples of 1/512; the box edges avoid them
     _subbox_check(oracle_mod, xyz, t_dev, -0.0996, 0.06, min_tets=1000)
     # a box around a cluster point (outside the lattice cube, inside r < 0.9)
     r = np.linalg.norm(xyz, axis=1)
     c = xyz[np.nonzero((r < 0.9) & (np.abs(xyz).max(axis=1) > 0.35))[0][0]]
     _subbox_check(oracle_mod, xyz, t_dev, c - 0.015, 0.03, min_tets=1000)
-    _vertices_check(t_dev, len(xyz))
 
 
 def test_batch_bench_chunk(dtlib, oracle_mod):
