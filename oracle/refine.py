@@ -12,7 +12,9 @@ Readings (the paper gives the rule, not these details):
   facet, the facet ordered with its tetrahedron's fourth vertex on the positive side.
   Inserted points are strictly inside, so the hull facets never change.
 * Size: one constant h.  A tetrahedron is refined when r^2 > (1.4 h)^2, with the
-  circumcentre and r^2 evaluated in fp64 by the fixed formula of `circumcentres`.
+  circumcentre and r^2 evaluated in fp64 by the fixed formula of `circumcentres`, which takes
+  the four vertices in ascending input index (so the rounded values depend on the
+  tetrahedron only, not on how a triangulation stores it).
 * Filter: the candidates of a step are taken in the order of their Moore key (the input
   cloud's grid) and then of their tetrahedron's sorted vertex indices.  A candidate is kept
   iff its squared distance (fp64, fixed formula) to every current vertex and to every
@@ -34,11 +36,11 @@ GROW, FILTER = 1.4, 0.7
 
 
 def circumcentres(xyz: np.ndarray, tets: np.ndarray):
-    """fp64 circumcentre c and squared radius |c - a|^2 of each tetrahedron (a, b, c, d):
-    with u = b - a, v = c - a, w = d - a,
+    """fp64 circumcentre c and squared radius |c - a|^2 of each tetrahedron, its vertices
+    (a, b, c, d) in ascending input index: with u = b - a, v = c - a, w = d - a,
     c - a = (|u|^2 (v x w) + |v|^2 (w x u) + |w|^2 (u x v)) / (2 u . (v x w)),
     evaluated left to right as written, no fused operations."""
-    p = np.asarray(xyz, dtype=np.float64)[np.asarray(tets, dtype=np.int64)]
+    p = np.asarray(xyz, dtype=np.float64)[np.sort(np.asarray(tets, dtype=np.int64), axis=1)]
     a = p[:, 0]
     u, v, w = p[:, 1] - a, p[:, 2] - a, p[:, 3] - a
 
