@@ -62,12 +62,50 @@ def copy_calibration():
     torch.cuda.synchronize()
     print(f"copied {n} bytes three times", flush=True)
 
-# Algorithmic bytes of the cavity kernel (walk + cavity + claim) per attempt, from the
-# counters: candidate/hint/point (48 B), per walk step one tetrahedron row (vertices 16 B +
-# neighbours 16 B) and one new vertex record (32 B), per cavity tetrahedron its two rows
-# (32 B) and per outer tetrahedron its vertex row (16 B), an 8-byte owner word read and
-# written per touched tetrahedron (16 B), the boundary's vertex records (F/2 + 2 records of
-# 32 B) and the per-insertion buffers written (4 B per cavity tetrahedron, 8 B per facet).
+def gather_calibration():
+    """A random gather of 4 Mi 64-byte records out of a 4 GiB array (index_select with a
+    shuffled index), three times: the reference for the counters on random 64-byte reads that
+    miss the caches, the access pattern of the tetrahedron pool.  Each dispatch reads 256 MiB
+    of records and 32 MiB of indices and writes 256 MiB."""
+    import torch
+    rows = 64 * 1024 * 1024  # 4 GiB of 64-byte rows
+    src = torch.empty((rows, 16), dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    idx = torch.randint(0, rows, (4 * 1024 * 1024,), device="cuda", generator=gen)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        out = src.index_select(0, idx)
+    torch.cuda.synchronize()
+    print(f"gathered {out.shape[0]} rows of 64 bytes three times", flush=True)
+
+
+# Algorithmic bytes per insertion, the hot-path scope table's model of an HBM-bound insertion
+# (u32 layout): the point record and its key/index (32 + 12 B), W walk steps of one
+# tetrahedron row (ids 16 B + neighbour codes 16 B) and ~32 B of vertex data each, the C
+# cavity tetrahedra (32 B each), the F outer tetrahedra's vertex ids (16 B each) and ~30
+# vertex records (32 B each) belong to the walk + cavity kernel; the F new tetrahedra (32 B)
+# and their back-pointers (4 B) to the ball kernel.  W = 4 and 30 vertex records are the
+# model's own figures; C and F are measured per insertion.
+MODEL_WALK_STEPS = 4
+MODEL_VERTEX_RECORDS = 30
+
+
+def cavity_bytes_per_insertion(C, F, W=MODEL_WALK_STEPS, V=MODEL_VERTEX_RECORDS):
+    return 44 + 64 * W + 32 * C + 16 * F + 32 * V
+
+
+def ball_bytes_per_insertion(F):
+    return 32 * F + 4 * F
+
+
+# A finer model of what one attempt of the cavity kernel moves (reported beside the table's
+# model, not as the roofline): candidate/hint/point (48 B), per walk step one tetrahedron row
+# (vertices 16 B + neighbours 16 B) and one new vertex record (32 B), per cavity tetrahedron
+# its two rows (32 B) and per outer tetrahedron its vertex row (16 B), an 8-byte owner word
+# read and written per touched tetrahedron (16 B), the boundary's vertex records (F/2 + 2
+# records of 32 B) and the per-insertion buffers written (4 B per cavity tetrahedron, 8 B per
+# facet).  Counts every attempt, losers included.
 def cavity_bytes_per_attempt(walk, C, F):
     return 48 + 64 * walk + 32 * C + 16 * F + 16 * (C + F) + 32 * (F / 2 + 2) + 4 * C + 8 * F
 
@@ -140,21 +178,6 @@ def cpu_baseline_clouds(xyz, off, clouds, budget_s=15.0):
             "cpu": host_cpu_model(), "host_threads": os.cpu_count()}
 
 
-# Algorithmic bytes of the ball kernel (winner test + DelaunayBall) per launch, from the
-# counters.  Every candidate reads its point, rank, two list lengths and status (20 B) and,
-# for the winner test, each cavity and outer entry of its lists with that tetrahedron's claim
-# word (4 + 8 B each).  A winner also reads its cavity tetrahedra's vertex rows and writes
-# their copies (16 + 16 B each), writes one new tetrahedron per boundary facet (vertices and
-# neighbours, 32 B), the back-pointer in the outer tetrahedron (4 B), the facet's list entries
-# (boundary entry read, outer code read and rewritten, slot index: 16 B), and the vertex
-# hints of the boundary's F/2 + 2 vertices (4 B each).  Losers are counted with the winners'
-# mean cavity and boundary sizes.
-def ball_bytes(C, F, candidates, winners):
-    per_candidate = 20 + 12 * (C + F)
-    per_winner = 32 * C + 32 * F + 4 * F + 16 * F + 4 * (F / 2 + 2)
-    return candidates * per_candidate + winners * per_winner
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,7 +186,13 @@ def main():
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--seed", type=int, default=1007)
     ap.add_argument("--cpu-sample", type=int, default=2_500_000,
-                    help="uniform: points of the oracle's CPU sample (about 10 s on one core)")
+                    help="uniform: the oracle's CPU sample, the first points of the timed input (about 10 s "
+                         "on one core)")
+    ap.add_argument("--no-export", action="store_true",
+                    help="uniform: a step ends with the tetrahedron count (for pools too large to hold the "
+                         "output beside them, 5e8 points)")
+    ap.add_argument("--u8-steps", type=int, default=2,
+                    help="uniform: timed steps at 1e8 points (seed 1008) for the line's u8 object; 0: skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--round-fraction", type=float, default=0.0)
     ap.add_argument("--round-size", type=int, default=0)
@@ -179,14 +208,21 @@ def main():
     ap.add_argument("--cpu-mix-scale", type=float, default=0.05,
                     help="mix: size of the oracle's CPU sample as a fraction of the timed input")
     ap.add_argument("--clouds", type=int, default=4096, help="batch: number of clouds")
-    ap.add_argument("--chunk", type=int, default=1024, help="batch: clouds per dt_insert_batch call")
+    ap.add_argument("--chunk", type=int, default=4096,
+                    help="batch: clouds per dt_insert_batch call (default: all in one call, the pool then "
+                         "takes 64-bit adjacency codes)")
     ap.add_argument("--loop-sample", type=int, default=64, help="batch: clouds timed one call each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
+    ap.add_argument("--gather-calibration", action="store_true",
+                    help="only run a random 64-byte gather from a 4 GiB array (counter calibration) and exit")
     args = ap.parse_args()
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.gather_calibration:
+        gather_calibration()
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -201,13 +237,144 @@ def main():
         run_mix(args)
         return
 
-    import numpy as np
+    import torch
+
+    from synth import uniform_points
+
+    t_bench = time.perf_counter()
+
+    def progress(msg):
+        print(f"[bench] {msg} ({time.perf_counter() - t_bench:.1f} s)", file=sys.stderr, flush=True)
+
+    xyz = uniform_points(args.n, args.seed)
+    main_run = run_uniform(args, xyz, args.n, args.seed, args.steps, args.warmup, progress)
+    T = main_run["tetrahedra"]
+    golden = golden_hash(args.n, args.seed)
+    oracle_match = None
+    if golden is not None:
+        oracle_match = main_run["hash"] == golden
+        progress(f"whole output against the stored oracle hash: {'equal' if oracle_match else 'DIFFERENT'}")
+
+    model = training = None
+    learned = None
+    if not args.no_learned:
+        # the learned scheduler on the same input, trained on plain runs of other seeds
+        tn = args.train_n or min(args.n, 10_000_000)
+        seeds = [int(x) for x in args.train_seeds.split(",") if x]
+        model, training = train_scheduler(lambda s: uniform_points(tn, s), seeds, args.train_samples, progress)
+        learned = compare_schedulers(main_run["d_xyz"], model, args.steps, args.warmup, progress,
+                                     reference=main_run["canon"], export=not args.no_export)
+        learned["training"] = dict(training, points_per_run=tn)
+    main_run["canon"] = None
+    del main_run["d_xyz"]
+    torch.cuda.empty_cache()
+
+    u8 = None
+    if args.u8_steps > 0 and args.n != 100_000_000:
+        # the metric's second size: 1e8 uniform points (seed 1008), timed the same way
+        xyz8 = uniform_points(100_000_000, 1008)
+        r8 = run_uniform(args, xyz8, 100_000_000, 1008, args.u8_steps, 1, progress)
+        del xyz8
+        u8 = {k: r8[k] for k in ("value", "ms_per_step", "tetrahedra", "roofline", "detail")}
+        u8["workload"] = "1e8 i.i.d. uniform fp64 points in [0,1)^3, seed 1008"
+        u8["steps"] = args.u8_steps
+        u8["paper_context"] = paper_context(100_000_000)
+        if model is not None:
+            u8["learned"] = compare_schedulers(r8["d_xyz"], model, args.u8_steps, 1, progress,
+                                               reference=r8["canon"])
+        r8["canon"] = None
+        del r8["d_xyz"]
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # a bounded sample of the timed input: its first cpu_sample points
+        k = min(args.cpu_sample, args.n)
+        cpu = cpu_baseline_points(xyz[:k], f"the first {k} points of the timed input ({args.n} uniform points, "
+                                           f"seed {args.seed})")
+
+    line = {
+        "metric": "tetrahedra/sec (exact 3D Delaunay, uniform points)",
+        "value": main_run["value"],
+        "unit": "tetrahedra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.n} i.i.d. uniform fp64 points in [0,1)^3, seed {args.seed}",
+                   "points": args.n, "tetrahedra": T, "scheduler": "plain",
+                   "launch": main_run["tuned"] if main_run["tuned"] else "defaults"},
+        "roofline": main_run["roofline"],
+        "cpu_baseline": cpu,
+        "paper_context": paper_context(args.n),
+        "oracle_hash_match": oracle_match,
+        "learned": learned,
+        "u8": u8,
+        "detail": main_run["detail"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def reference_output(d_xyz):
+    """One untimed plain triangulation of d_xyz, exported: its canonical form on the device and
+    the SHA-256 of that."""
+    import torch
+
+    from paper_1805_08831_amd import Triangulation, dt_get_tets
+    with Triangulation(device=0, stream=torch.cuda.current_stream().cuda_stream) as tri:
+        tri.insert(d_xyz)
+        T = dt_get_tets(tri.ctx)
+        out = torch.empty((T, 4), dtype=torch.int32, device="cuda")
+        dt_get_tets(tri.ctx, out, None, T)
+    canon = canonical_device(out)
+    return canon, sha256_of(canon)
+
+
+def golden_hash(n, seed, kind="uniform"):
+    """SHA-256 of the oracle's canonical output for this input, when stored."""
+    path = os.path.join(ROOT, "tests", "golden", "fullsize_golden.txt")
+    try:
+        for line in open(path):
+            if line.startswith("#") or not line.strip():
+                continue
+            kv = dict(x.split("=", 1) for x in line.split()[1:])
+            if kv.get("kind") == kind and int(kv["n"]) == n and int(kv["seed"]) == seed:
+                return kv["sha256"]
+    except (OSError, KeyError, ValueError):
+        return None
+    return None
+
+
+def canonical_device(t):
+    """Canonical form of a (T, 4) int32 device tensor: each row's indices sorted, rows in
+    lexicographic order (stable sorts on the device)."""
+    import torch
+    q = torch.sort(t.long(), dim=1).values
+    hi = (q[:, 0] << 32) | q[:, 1]
+    lo = (q[:, 2] << 32) | q[:, 3]
+    o1 = torch.sort(lo, stable=True).indices
+    o2 = torch.sort(hi[o1], stable=True).indices
+    return q[o1[o2]].to(torch.int32)
+
+
+def sha256_of(canon):
+    import hashlib
+    return hashlib.sha256(canon.cpu().numpy().astype("<u4").tobytes()).hexdigest()
+
+
+def run_uniform(args, xyz, n, seed, steps, warmup, progress):
+    """`steps` timed steps on the uniform input xyz; the roofline of the walk + cavity
+    kernel; the canonical output (device) and its hash."""
     import torch
 
     from paper_1805_08831_amd import Triangulation, dt_get_tets
     from synth import uniform_points
 
-    xyz = uniform_points(args.n, args.seed)
     d_xyz = torch.from_numpy(xyz).cuda()
     stream = torch.cuda.current_stream()
     tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True,
@@ -215,30 +382,27 @@ def main():
                         lanes_per_insert=args.lanes)
     tuned = None
     if args.autotune:
-        tuned = tri.autotune(torch.from_numpy(uniform_points(2_000_000, args.seed + 2)).cuda())
+        tuned = tri.autotune(torch.from_numpy(uniform_points(2_000_000, seed + 2)).cuda())
 
-    def step():
-        tri.clear()
-        tri.insert(d_xyz)
-        T = dt_get_tets(tri.ctx)
-        return T
-
-    # output buffers sized once (outside the timed region) from a first run
+    # output buffers sized once (outside the timed region) from a first run; without export
+    # (pools too large to hold the output beside them) a step ends with the count
     tri.insert(d_xyz)
     T0 = dt_get_tets(tri.ctx)
-    out_t = torch.empty((T0 + 1024, 4), dtype=torch.int32, device="cuda")
-    out_n = torch.empty((T0 + 1024, 4), dtype=torch.int64, device="cuda")
+    export = not args.no_export
+    out_t = torch.empty((T0 + 1024, 4), dtype=torch.int32, device="cuda") if export else None
+    out_n = torch.empty((T0 + 1024, 4), dtype=torch.int64, device="cuda") if export else None
 
     def full_step():
         tri.clear()
         tri.insert(d_xyz)
+        if not export:
+            return dt_get_tets(tri.ctx)
         return dt_get_tets(tri.ctx, out_t, out_n, T0 + 1024)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         full_step()
     torch.cuda.synchronize()
     tri.clear()
-    base_stats = tri.stats()
     times = []
     T = 0
     agg = dict(attempts=0, walk=0, cav=0, bnd=0, won=0, ms_cav=0.0, ms_ball=0.0, launches=0, rounds=0,
@@ -246,7 +410,7 @@ def main():
                ms_sort=0.0, ms_insert=0.0, ball_launches=0)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         t0 = time.perf_counter()
         T = full_step()
         torch.cuda.synchronize()
@@ -269,95 +433,83 @@ def main():
             agg[k] += s[k + ("_calls" if k in ("orient", "insphere") else "")]
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-    ms_per_step = 1000.0 * total / args.steps
+    ms_per_step = 1000.0 * total / steps
     value = T / (ms_per_step / 1000.0)
+    progress(f"{n} points: {T} tetrahedra, {ms_per_step:.1f} ms per step")
+    canon = canonical_device(out_t[:T]) if export else None
+    digest = sha256_of(canon) if export else None
+    st_last = tri.stats()
+    tri.close()
+    del out_n
 
-    # roofline of the dominant kernel (walk + cavity + claim), HBM-bound
+    # roofline of the dominant kernel (walk + cavity + claim), HBM-bound, with the table's
+    # algorithmic bytes per insertion times the insertions per launch
     att = max(agg["attempts"], 1)
     won = max(agg["won"], 1)
     walk = agg["walk"] / att
     C = agg["cav"] / won
     F = agg["bnd"] / won
-    b_unit = cavity_bytes_per_attempt(walk, C, F)
     launches = max(agg["launches"], 1)
     avg_launch_ms = agg["ms_cav"] / launches
-    bytes_per_launch = b_unit * agg["attempts"] / launches
-    achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
+    per_ins = cavity_bytes_per_insertion(C, F)
+    ins_per_launch = agg["won"] / launches
+    achieved = per_ins * ins_per_launch / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
     peak = 8000.0
     lanes = (tuned or {}).get("lanes_per_insert") or args.lanes or 8
+    b_att = cavity_bytes_per_attempt(walk, C, F)
+    att_achieved = b_att * agg["attempts"] / launches / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
+    default_launch = (lanes == 8 and not args.round_fraction and not args.round_size and n == 10_000_000
+                      and seed == 1007)
     roofline = {"bound": "hbm", "kernel": f"k_cavity_g<{lanes}>", "achieved": round(achieved, 2), "peak": peak,
-                "unit": "GB/s", "frac": round(achieved / peak, 5), "traffic": measured_traffic(),
-                "bytes_per_attempt": round(b_unit, 1), "attempts_per_launch": round(agg["attempts"] / launches, 1),
-                "avg_launch_ms": round(avg_launch_ms, 4)}
-
-    # the ball kernel's algorithmic rate (a detail; the cavity kernel is the dominant one)
-    ball_total = ball_bytes(C, F, agg["attempts"], agg["won"])
+                "unit": "GB/s", "frac": round(achieved / peak, 5),
+                # measured HBM bytes per launch (counter summary), only for the launch it was taken on
+                "traffic": measured_traffic() if default_launch else None,
+                "bytes_per_insertion": round(per_ins, 1), "insertions_per_launch": round(ins_per_launch, 1),
+                "avg_launch_ms": round(avg_launch_ms, 4),
+                "model_per_attempt": {"bytes_per_attempt": round(b_att, 1),
+                                      "attempts_per_launch": round(agg["attempts"] / launches, 1),
+                                      "achieved": round(att_achieved, 2), "frac": round(att_achieved / peak, 5)}}
+    ball_ms = agg["ms_ball"] / max(agg["ball_launches"], 1)
+    ball_per_ins = ball_bytes_per_insertion(F)
+    ball_ach = ball_per_ins * agg["won"] / max(agg["ball_launches"], 1) / (ball_ms / 1000.0) / 1e9 if ball_ms > 0 else 0.0
     ball = {"bound": "hbm", "kernel": "k_ball<16, 1024>", "unit": "GB/s", "peak": peak,
-            "achieved": round(ball_total / (agg["ms_ball"] / 1000.0) / 1e9, 2) if agg["ms_ball"] > 0 else 0.0,
-            "bytes_per_insertion": round(ball_total / won, 1),
-            "avg_launch_ms": round(agg["ms_ball"] / max(agg["ball_launches"], 1), 4)}
-    ball["frac"] = round(ball["achieved"] / peak, 5)
+            "achieved": round(ball_ach, 2), "frac": round(ball_ach / peak, 5),
+            "bytes_per_insertion": round(ball_per_ins, 1), "avg_launch_ms": round(ball_ms, 4)}
+    detail = {"rounds_per_step": agg["rounds"] / steps, "attempts_per_point": agg["attempts"] / max(n * steps, 1),
+              "conflict_rate": agg["conflicts"] / att, "walk_steps_per_attempt": round(walk, 3),
+              "cavity_tets": round(C, 2), "boundary_facets": round(F, 2),
+              "ms_cavity_kernel_per_step": round(agg["ms_cav"] / steps, 3),
+              "ms_ball_kernel_per_step": round(agg["ms_ball"] / steps, 3),
+              "ball_roofline": ball,
+              # host clock inside dt_insert_points: sort phase and insertion rounds; the
+              # paper's sequential timings leave the sort out
+              "ms_sort_per_step": round(agg["ms_sort"] / steps, 3),
+              "ms_insert_per_step": round(agg["ms_insert"] / steps, 3),
+              "insertion_only_tets_per_s": round(T / (agg["ms_insert"] / steps / 1000.0), 1)
+              if agg["ms_insert"] > 0 else None,
+              "orient_exact_rate": agg["orient_exact"] / max(agg["orient"], 1),
+              "insphere_exact_rate": agg["insphere_exact"] / max(agg["insphere"], 1),
+              "perturbed": agg["perturbed"], "step_ms": [round(1000 * t, 2) for t in times],
+              "output_sha256": digest, "exported": export, "index_bits": st_last["index_bits"]}
+    return {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3), "tetrahedra": T,
+            "roofline": roofline, "detail": detail, "tuned": tuned, "hash": digest, "canon": canon,
+            "d_xyz": d_xyz}
 
-    learned = None
-    if not args.no_learned:
-        # the learned scheduler on the same input, trained on plain runs of other seeds
-        t_l = time.perf_counter()
 
-        def progress(msg):
-            print(f"[learned] {msg} ({time.perf_counter() - t_l:.1f} s)", file=sys.stderr, flush=True)
-
-        tn = args.train_n or min(args.n, 10_000_000)
-        seeds = [int(x) for x in args.train_seeds.split(",") if x]
-        model, training = train_scheduler(lambda s: uniform_points(tn, s), seeds, args.train_samples, progress)
-        # both schedulers timed the same way (insertion and tetrahedron count, no export)
-        res = {name: timed_runs(d_xyz, sched, model, args.steps, args.warmup, progress, name)
-               for name, sched in (("plain", 0), ("learned", 1))}
-        learned = dict(res["learned"], same_count=res["learned"]["tetrahedra"] == T,
-                       training=dict(training, points_per_run=tn), plain=res["plain"])
-
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample, args.seed + 1)
-
-    line = {
-        "metric": "tetrahedra/sec (exact 3D Delaunay, uniform points)",
-        "value": round(value, 1),
-        "unit": "tetrahedra/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{args.n} i.i.d. uniform fp64 points in [0,1)^3, seed {args.seed}",
-                   "points": args.n, "tetrahedra": T, "scheduler": "plain",
-                   "launch": tuned if tuned else "defaults"},
-        # the counter summary was taken on this workload (1e7 points, seed 1007) at the default
-        # launch configuration; other launches have other per-launch traffic
-        "roofline": roofline if (lanes == 8 and not args.round_fraction and not args.round_size
-                                 and args.n == 10_000_000 and args.seed == 1007) else dict(roofline, traffic=None),
-        "cpu_baseline": cpu,
-        "paper_context": paper_context(args.n),
-        "learned": learned,
-        "detail": {"rounds_per_step": agg["rounds"] / args.steps, "attempts_per_point": agg["attempts"] / max(args.n * args.steps, 1),
-                   "conflict_rate": agg["conflicts"] / att, "walk_steps_per_attempt": round(walk, 3),
-                   "cavity_tets": round(C, 2), "boundary_facets": round(F, 2),
-                   "ms_cavity_kernel_per_step": round(agg["ms_cav"] / args.steps, 3),
-                   "ms_ball_kernel_per_step": round(agg["ms_ball"] / args.steps, 3),
-                   "ball_roofline": ball,
-                   # host clock inside dt_insert_points: sort phase and insertion rounds; the
-                   # paper's sequential timings leave the sort out
-                   "ms_sort_per_step": round(agg["ms_sort"] / args.steps, 3),
-                   "ms_insert_per_step": round(agg["ms_insert"] / args.steps, 3),
-                   "insertion_only_tets_per_s": round(T / (agg["ms_insert"] / args.steps / 1000.0), 1)
-                   if agg["ms_insert"] > 0 else None,
-                   "orient_exact_rate": agg["orient_exact"] / max(agg["orient"], 1),
-                   "insphere_exact_rate": agg["insphere_exact"] / max(agg["insphere"], 1),
-                   "perturbed": agg["perturbed"], "step_ms": [round(1000 * t, 2) for t in times]},
-    }
-    print(json.dumps(line), flush=True)
-    tri.close()
+def compare_schedulers(d_xyz, model, steps, warmup, progress, reference, export=True):
+    """Plain and learned scheduler on the same device input, timed the same way (insertion
+    and tetrahedron count, no export); then each output, exported once, against the plain
+    step's canonical output (without export: the tetrahedron counts only)."""
+    res = {name: timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference if export else None)
+           for name, sched in (("plain", 0), ("learned", 1))}
+    out = dict(res["learned"], plain=res["plain"])
+    if export:
+        out["identical_output"] = bool(res["learned"]["identical"] and res["plain"]["identical"])
+    else:
+        out["identical_output"] = None
+        out["same_count"] = res["learned"]["tetrahedra"] == res["plain"]["tetrahedra"]
+    out["speedup_vs_plain"] = round(res["learned"]["value"] / res["plain"]["value"], 4)
+    return out
 
 
 def train_scheduler(gen, seeds, samples, progress):
@@ -392,8 +544,10 @@ def train_scheduler(gen, seeds, samples, progress):
     return model, info
 
 
-def timed_runs(d_xyz, sched, model, steps, warmup, progress, name):
-    """`steps` timed triangulations of d_xyz with the given scheduler; per-step means."""
+def timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference=None):
+    """`steps` timed triangulations of d_xyz with the given scheduler; per-step means.  With
+    a reference canonical output, the last triangulation is exported (untimed) and compared
+    with it on the device."""
     import torch
 
     from paper_1805_08831_amd import Triangulation, dt_get_tets, dt_load_model
@@ -420,9 +574,16 @@ def timed_runs(d_xyz, sched, model, steps, warmup, progress, name):
             agg[k] += st[k]
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / steps
+    identical = None
+    if reference is not None:
+        out = torch.empty((T, 4), dtype=torch.int32, device="cuda")
+        dt_get_tets(tri.ctx, out, None, T)
+        identical = bool(out.shape == reference.shape and torch.equal(canonical_device(out), reference))
+        del out
+        progress(f"{name}: output {'identical to' if identical else 'DIFFERENT from'} the plain step's")
     tri.close()
     return {"value": round(T / (ms / 1000.0), 1), "ms_per_step": round(ms, 3), "tetrahedra": T,
-            **{k: v / steps for k, v in agg.items()}}
+            "identical": identical, **{k: v / steps for k, v in agg.items()}}
 
 
 def run_mix(args):
@@ -444,7 +605,9 @@ def run_mix(args):
     seeds = [int(x) for x in args.train_seeds.split(",") if x]
     model, training = train_scheduler(lambda s: mix_points(s, *counts), seeds, args.train_samples, progress)
     d_xyz = torch.from_numpy(mix_points(seed, *counts)).cuda()
-    res = {name: timed_runs(d_xyz, sched, model, args.steps, args.warmup, progress, name)
+    reference, digest = reference_output(d_xyz)
+    golden = golden_hash(sum(counts), seed, kind="mix")
+    res = {name: timed_runs(d_xyz, sched, model, args.steps, args.warmup, progress, name, reference)
            for name, sched in (("plain", 0), ("learned", 1))}
     line = {
         "metric": "tetrahedra/sec (exact 3D Delaunay, MIX: lattice + clusters + shell)",
@@ -462,9 +625,12 @@ def run_mix(args):
         "config": {"workload": f"MIX {sum(counts)} ({counts[0]} nodes of the 160^3 lattice, {counts[1]} in 50 "
                                f"clusters, {counts[2]} within 1e-4 of the unit sphere), seed {seed}",
                    "scheduler": "plain"},
-        "learned": dict(res["learned"], same_count=res["learned"]["tetrahedra"] == res["plain"]["tetrahedra"],
-                        training=training),
+        "learned": dict(res["learned"], training=training,
+                        speedup_vs_plain=round(res["learned"]["value"] / res["plain"]["value"], 4),
+                        identical_output=bool(res["learned"]["identical"] and res["plain"]["identical"])),
         "plain": res["plain"],
+        "output_sha256": digest,
+        "oracle_hash_match": None if golden is None else digest == golden,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_points(
             mix_points(seed + 1, *(int(c * args.cpu_mix_scale) for c in counts)),
             f"MIX at {args.cpu_mix_scale} of the timed size (seed {seed + 1})"),

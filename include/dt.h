@@ -67,6 +67,16 @@ typedef struct {
                                dt_load_model or dt_train_model; without one the call runs
                                the plain order and counts dt_stats.sched_fallbacks)      */
     int log_points;         /* 1: record the attempts of every point (dt_get_point_log)  */
+    int index_bits;         /* width of the adjacency codes 4 t + f (Sec. 2.2): 32 (pools
+                               up to 2^30 - 1 tetrahedron slots), 64 (up to 2^32 - 16
+                               slots, the same 64-byte records), or 0: 32 while the pool
+                               fits, widened to 64 when it must grow past that           */
+    int adaptive_curve;     /* 0: the Moore curve on the grid of level ceil(log2(n) / 3)
+                               (Sec. 2.3); 1: on the deepest grid the sort key holds (21
+                               levels for one cloud), which orders the points of a crowded
+                               cell by the curve's finer levels, an adaptive curve for
+                               non-uniform inputs (the Conclusion's open point).  The
+                               triangulation is the same either way.                     */
 } dt_options;
 
 enum { DT_SCHED_PLAIN = 0, DT_SCHED_LEARNED = 1 };
@@ -97,6 +107,10 @@ typedef struct {
     uint64_t cavity_units, ball_units; /* attempts processed / insertions completed   */
     uint64_t sched_fallbacks; /* calls with DT_SCHED_LEARNED but no model loaded, run in the
                                  plain order instead                                     */
+    uint64_t index_bits;      /* adjacency code width of the current pool (0: no pool)   */
+    uint64_t dropped_slots;   /* freed slots left unused because the free list was full  */
+    uint64_t deferred;        /* attempts whose fp64 filter left a sign undecided, run
+                                 again with exact predicates in the same round           */
 } dt_stats;
 
 /* Fill *opt with the defaults (device 0, library stream, automatic sizes, seed 0x5EED). */
@@ -116,7 +130,8 @@ int dt_create(dt_ctx **out, const dt_options *opt);
    is as it was before the call; after DT_E_CAPACITY, DT_E_INCOMPLETE, DT_E_DEVICE or
    DT_E_INTERNAL only dt_clear, dt_get_stats, dt_last_error and dt_destroy are
    meaningful.  n = 0 does nothing and returns DT_OK.  Limits: fewer than 2^30 points per
-   call and 2^31 in all (DT_E_CAPACITY), and fewer than 2^30 tetrahedra slots. */
+   call and 2^31 in all (DT_E_CAPACITY); fewer than 2^30 tetrahedron slots with 32-bit
+   adjacency codes, 2^32 - 16 with 64-bit codes (dt_options.index_bits). */
 int dt_insert_points(dt_ctx *ctx, const double *xyz, uint64_t n);
 
 /* Export the finite tetrahedra.  *num_tets is in/out: on input the capacity of the
@@ -137,8 +152,8 @@ int dt_get_tets(dt_ctx *ctx, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
    dt_insert_points is refused until the next dt_clear, also after a call that fails past
    its argument checks (DT_E_ARG for NULL pointers, bad offsets or too few points in a cloud
    leaves the context untouched).  Errors as dt_insert_points; DT_E_DEGENERATE names the
-   first degenerate cloud in dt_last_error.  Limits: fewer than 2^30 points in all, fewer
-   than 2^30 tetrahedron slots in all. */
+   first degenerate cloud in dt_last_error.  Limits: fewer than 2^30 points in all, and the
+   tetrahedron slots of dt_insert_points. */
 int dt_insert_batch(dt_ctx *ctx, const double *xyz, const uint64_t *offsets, uint32_t num_clouds);
 
 /* Export the finite tetrahedra of one cloud of the context (cloud 0 after dt_insert_points),
@@ -194,6 +209,29 @@ int dt_debug_mlp(dt_ctx *ctx, const float *features, uint64_t n, float *out);
 int dt_debug_mlp_grad(dt_ctx *ctx, const float *features, const float *cost, const uint8_t *bucket, uint32_t n,
                       float *grad, float *loss);
 
+/* ---- Delaunay refinement (Sec. 4) ----
+   Refines the context's triangulation (built by dt_insert_points; not a batch) by inserting
+   circumcentres, as the paper's mesh generator does with its size field, here one constant
+   h.  Each step: every tetrahedron with squared circumradius above (1.4 h)^2 proposes its
+   circumcentre (fp64, one fixed formula over its vertices in ascending input index, no
+   fused operations); a proposal is a candidate only strictly inside the convex hull (exact
+   orient3d against every hull facet), so the hull never changes; candidates are taken in
+   the order of their Moore key in the grid of the points present when the call starts, then
+   of their tetrahedron's sorted vertex indices, and one is kept iff no vertex and no kept
+   earlier candidate lies closer than 0.7 h (squared distances in fp64); the kept points are
+   inserted in that order (their input indices follow it).  Steps repeat until one keeps
+   nothing, or max_steps.  step_counts (2 * max_steps uint32, may be NULL) receives each
+   step's candidates and kept points; *num_steps and *inserted (may be NULL) the steps run
+   and the points added.  h must be positive and finite and not below about 2^-20 of the
+   point set's extent (DT_E_ARG).  Other errors as dt_insert_points. */
+int dt_refine(dt_ctx *ctx, double h, uint32_t max_steps, uint32_t *step_counts, uint32_t *num_steps,
+              uint64_t *inserted);
+
+/* Coordinates of every point inserted so far, xyz[3*i..3*i+2] for global input index i (fp64,
+   host or device memory); *num_points in/out as in dt_get_tets (NULL xyz: query).  Not for a
+   batch of clouds. */
+int dt_get_points(dt_ctx *ctx, double *xyz, uint64_t *num_points);
+
 /* Drop every point and tetrahedron but keep the device allocations. */
 int dt_clear(dt_ctx *ctx);
 
@@ -209,7 +247,8 @@ const char *dt_last_error(const dt_ctx *ctx);
 /* ---- test hooks: the kernels of the hot path run on caller data ---- */
 
 /* Sort step (Sec. 2.3): for n points (device or host xyz) computes the sort key
-   (BRIO level << 3m | Moore index) of every point and the stable sorted order.
+   (BRIO level << 3m | Moore index; the Moore index alone when 3m + 8 > 64, as with the
+   adaptive curve) of every point and the stable sorted order.
    keys (n uint64) receives the keys in input order, perm (n uint32) the input index of
    the point at each sorted position; *moore_m receives m.  Device or host outputs. */
 int dt_debug_sort(dt_ctx *ctx, const double *xyz, uint64_t n, uint64_t *keys, uint32_t *perm,
@@ -219,6 +258,11 @@ int dt_debug_sort(dt_ctx *ctx, const double *xyz, uint64_t n, uint64_t *keys, ui
    take the low 32 bits of the counter; when they wrap, the library resets every claim word
    before the round.  Lets a test cross the wrap without 2^32 rounds. */
 int dt_debug_set_round_counter(dt_ctx *ctx, uint64_t rounds);
+
+/* With dt_options.index_bits = 0, a pool with 32-bit codes is widened to 64-bit codes when
+   it must grow past `slots` (default and maximum 2^30 - 1; at least 4096) instead of past
+   2^30 - 1: lets a test widen a pool in the middle of an insertion without 2^30 slots. */
+int dt_debug_widen_at(dt_ctx *ctx, uint64_t slots);
 
 /* Predicates (Sec. 2.4): for k records evaluates, per record r,
    kind 0: orient3d sign of pts[12r .. 12r+11] (four points);

@@ -134,13 +134,19 @@ def stable_sort(keys: np.ndarray) -> np.ndarray:
     return perm
 
 
-def sort_reference(xyz: np.ndarray, seed: int):
-    """Sorted order of the points by (BRIO level, Moore index), ties by input index."""
+def sort_reference(xyz: np.ndarray, seed: int, m: int | None = None):
+    """Sorted order of the points by (BRIO level, Moore index on the grid of level m), ties
+    by input index; m defaults to the level of the point count.  The keys returned are
+    level << 3m | Moore index when that fits 64 bits, else the Moore index alone."""
     n = len(xyz)
-    m = moore_level(n)
+    m = moore_level(n) if m is None else int(m)
     lev, cum = brio_levels(n, seed)
-    keys = (lev.astype(np.uint64) << np.uint64(3 * m)) | moore_keys(xyz, m)
-    return keys, stable_sort(keys), m, cum
+    moore = moore_keys(xyz, m)
+    if 3 * m + 8 <= 64:
+        keys = (lev.astype(np.uint64) << np.uint64(3 * m)) | moore
+        return keys, stable_sort(keys), m, cum
+    # level first, then the Moore index, ties by input index (lexsort is stable)
+    return moore, np.lexsort((moore, lev)).astype(np.int64), m, cum
 
 
 def delaunay(xyz: np.ndarray, order: str = "brio", seed: int = 0):

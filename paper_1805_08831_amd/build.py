@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["dt_sort.hip", "dt_insert.hip", "dt_learn.hip", "dt_capi.hip"]
+SOURCES = ["dt_sort.hip", "dt_insert.hip", "dt_learn.hip", "dt_refine.hip", "dt_capi.hip"]
 LIB = os.path.join(HERE, "libdt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -14,6 +14,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,6 +32,13 @@ constexpr uint32_t DEFAULT_LANES = 8;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t ROUND_MIN = 64;
 constexpr uint32_t DRAIN_SLICE = 4096;  // candidates per round when draining overflowed cavities
+constexpr uint32_t EXPORT_CHUNK = 1u << 24;  // slots per staged export launch (a multiple of 64)
+constexpr size_t TET_BYTES = 64;               // one tetrahedron record, either layout
+// entries of each free list: slots freed while it is full stay unused (the pool has room for
+// them); in practice a round frees far fewer
+constexpr uint64_t FREE_LIST_MAX = 1ull << 26;
+// calls with more points release the sort's temporaries before the rounds
+constexpr uint64_t BIG_CALL_POINTS = 1ull << 27;
 // learned order: where the points above the median training cost needed COSTLY_ATTEMPTS
 // attempts or more on average, rounds over the costly halves take COSTLY_ROUND_SCALE of the
 // usual size (fewer of these conflict-heavy points at once)
@@ -89,7 +98,10 @@ struct dt_ctx {
     DevBuf<uint32_t> vtet, anchor;
     DevBuf<uint8_t> dup;
     uint32_t tcap = 0;
-    Tet *T = nullptr;
+    void *T = nullptr;       // Tet[tcap] (32-bit codes) or TetW[tcap] (64-bit codes)
+    bool wide = false;       // the pool's layout
+    uint64_t narrow_max = MAX_TETS;  // growth past this widens an automatic pool
+    uint32_t flcap = 0;      // entries of each free list
     uint32_t *fl[2] = {nullptr, nullptr};
 
     uint32_t list_cap = 0;
@@ -97,9 +109,13 @@ struct dt_ctx {
     size_t bufC = 0, bufF = 0;
     uint32_t capC = 0, capF = 0;
     uint32_t lanes = 8;  // lanes per insertion of the cavity kernel
-    uint32_t *cav = nullptr, *bnd = nullptr, *outc = nullptr, *cnt = nullptr;
-    uint4 *scr_v = nullptr, *scr_n = nullptr;
+    uint32_t *defer = nullptr;             // candidates handed to the exact-predicate pass
+    void *cav = nullptr, *outc = nullptr;  // adjacency codes (4 or 8 bytes each)
+    uint32_t *bnd = nullptr, *cnt = nullptr;
+    uint4 *scr_v = nullptr;
+    void *scr_n = nullptr;
     uint8_t *status = nullptr;
+    bool buf_wide = false;  // code width the round buffers were sized for
 
     Ctr *ctr = nullptr;
     Ctr *hctr = nullptr;   // pinned: the counters after the last completed round (one of hring)
@@ -112,7 +128,8 @@ struct dt_ctx {
     DevBuf<uint32_t> vals, vals_tmp, hist, scan_tmp, small;
     DevBuf<uint64_t> small64;
     // output scratch
-    DevBuf<uint32_t> oflags, omap, otets, ovid;
+    DevBuf<unsigned long long> obits;  // export: live bit set, one word per 64 slots
+    DevBuf<uint32_t> owcnt, opre, otets, ovid;
     DevBuf<int64_t> onbrs;
 
     hipEvent_t ev[3][3] = {};   // per snapshot slot: kernel timing events of its round
@@ -154,6 +171,24 @@ struct dt_ctx {
     DevBuf<Vert> dbgV;
     DevBuf<Cloud> dbg_cloud;
     bool trace = false;  // DT_TRACE=1 in the environment: one line per round on stderr
+    // Device memory source: hipMalloc, or (no-allocation entry point) a bump arena carved
+    // from the library's static scratch array, reset at every call; then nothing is freed,
+    // events are not used (rounds complete by stream synchronization) and the counters'
+    // host copies are static memory.
+    // refinement (dt_refine): candidates, their ordering, grids and the kept points
+    DevBuf<double> rf_cc, rf_cc2, rf_ccr, rf_pts, rf_partial;
+    DevBuf<uint4> rf_q, rf_q2, rf_facets;
+    DevBuf<unsigned long long> rf_moore, rf_k0, rf_k1;
+    DevBuf<uint32_t> rf_v0, rf_v1, rf_ctr, rf_flags, rf_pos;
+    DevBuf<uint8_t> rf_status;
+    DevBuf<Cloud> rf_cloud;
+    DevBuf<uint64_t> rf_off;
+    unsigned char *arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
+    DevBuf<Ctr> ctrbuf;                          // counters and statistics in the arena
+    DevBuf<unsigned long long> statbuf;
+    uint32_t round_cap = DEFAULT_ROUND_MAX;  // candidates per round buffer (smaller in the arena)
+    uint32_t export_chunk = EXPORT_CHUNK;    // slots per staged export launch
 };
 
 namespace {
@@ -174,20 +209,37 @@ int fail(dt_ctx *c, int code, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(c, DT_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
+// Device memory of the context: hipMalloc, or the next 256-byte aligned piece of the arena.
+hipError_t dev_alloc(dt_ctx *c, void **p, size_t bytes) {
+    if (!c->arena) return hipMalloc(p, bytes);
+    const size_t off = (c->arena_used + 255) & ~(size_t)255;
+    if (off > c->arena_size || bytes > c->arena_size - off) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    *p = c->arena + off;
+    c->arena_used = off + bytes;
+    return hipSuccess;
+}
+
+void dev_free(dt_ctx *c, void *p) {
+    if (!c->arena && p) hipFree(p);
+}
+
 template <class T>
 int ensure(dt_ctx *c, DevBuf<T> &b, size_t n, bool keep = false) {
     if (b.cap >= n && b.p) return DT_OK;
     size_t cap = std::max<size_t>(n, 1);
     if (b.cap) cap = std::max(cap, b.cap + b.cap / 2);
     T *p = nullptr;
-    if (hipMalloc((void **)&p, cap * sizeof(T)) != hipSuccess) {
+    if (dev_alloc(c, (void **)&p, cap * sizeof(T)) != hipSuccess) {
         hipGetLastError();
         return fail(c, DT_E_CAPACITY, "device allocation of %zu bytes failed", cap * sizeof(T));
     }
     if (keep && b.p && b.cap) HIPCHK(hipMemcpyAsync(p, b.p, b.cap * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
     if (b.p) {
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(hipFree(b.p));
+        dev_free(c, b.p);
     }
     b.p = p;
     b.cap = cap;
@@ -209,65 +261,108 @@ int sync_ctr(dt_ctx *c) {
     return DT_OK;
 }
 
+int realloc_code_buffers(dt_ctx *c);
+
+// Grows (or first allocates) the tetrahedron pool to at least `need` slots.  A pool with
+// 32-bit codes that must pass 2^30 slots is widened to 64-bit codes on the way when the
+// options allow it (index_bits 0); the records are converted on the device.
 int grow_tets(dt_ctx *c, uint64_t need) {
-    if (need > MAX_TETS) return fail(c, DT_E_CAPACITY, "more than %u tetrahedra needed", MAX_TETS);
+    bool wide = c->wide;
+    if (!wide && need > c->narrow_max) {
+        if (c->opt.index_bits == 32)
+            return fail(c, DT_E_CAPACITY, "more than %u tetrahedra needed with 32-bit adjacency codes "
+                                          "(dt_options.index_bits = 64 or 0 lifts the limit)", MAX_TETS);
+        wide = true;
+    }
+    const uint64_t max_tets = wide ? MAX_TETS_WIDE : MAX_TETS;
+    if (need > max_tets) return fail(c, DT_E_CAPACITY, "more than %llu tetrahedra needed", (unsigned long long)max_tets);
     uint64_t cap = std::max<uint64_t>(need, (uint64_t)c->tcap + c->tcap / 2);
-    cap = std::min<uint64_t>(cap, MAX_TETS);
-    Tet *T = nullptr;
+    cap = std::min<uint64_t>(cap, max_tets);
+    const uint32_t flcap = (uint32_t)std::min<uint64_t>(cap, FREE_LIST_MAX);
+    void *T = nullptr;
     uint32_t *f0 = nullptr, *f1 = nullptr;
-    bool ok = hipMalloc((void **)&T, cap * sizeof(Tet)) == hipSuccess &&
-              hipMalloc((void **)&f0, cap * sizeof(uint32_t)) == hipSuccess &&
-              hipMalloc((void **)&f1, cap * sizeof(uint32_t)) == hipSuccess;
+    bool ok = dev_alloc(c, &T, cap * TET_BYTES) == hipSuccess &&
+              dev_alloc(c, (void **)&f0, (size_t)flcap * sizeof(uint32_t)) == hipSuccess &&
+              dev_alloc(c, (void **)&f1, (size_t)flcap * sizeof(uint32_t)) == hipSuccess;
     if (!ok) {
         hipGetLastError();
-        hipFree(T); hipFree(f0); hipFree(f1);
+        dev_free(c, T); dev_free(c, f0); dev_free(c, f1);
         return fail(c, DT_E_CAPACITY, "device allocation for %llu tetrahedra failed", (unsigned long long)cap);
     }
     // claim words start above every stamp
-    HIPCHK(hipMemsetAsync(T, 0xFF, cap * sizeof(Tet), c->stream));
+    HIPCHK(hipMemsetAsync(T, 0xFF, cap * TET_BYTES, c->stream));
     if (c->tcap) {
         uint64_t used = c->hctr->tet_count;
-        HIPCHK(hipMemcpyAsync(T, c->T, used * sizeof(Tet), hipMemcpyDeviceToDevice, c->stream));
-        uint64_t nf = c->hctr->fl_n;
+        if (wide && !c->wide) HIPCHK(launch_widen(c->T, T, (uint32_t)used, c->stream));
+        else HIPCHK(hipMemcpyAsync(T, c->T, used * TET_BYTES, hipMemcpyDeviceToDevice, c->stream));
+        uint64_t nf = std::min<uint64_t>(c->hctr->fl_n, flcap);
         HIPCHK(hipMemcpyAsync(c->fl_idx == 0 ? f0 : f1, c->fl[c->fl_idx], nf * sizeof(uint32_t),
                               hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        hipFree(c->T); hipFree(c->fl[0]); hipFree(c->fl[1]);
+        dev_free(c, c->T); dev_free(c, c->fl[0]); dev_free(c, c->fl[1]);
     }
     c->T = T; c->fl[0] = f0; c->fl[1] = f1;
     c->tcap = (uint32_t)cap;
+    c->flcap = flcap;
+    const bool widened = wide && !c->wide;
+    c->wide = wide;
+    // the code buffers of the rounds follow the pool's code width (the candidate lists, which
+    // may hold pending candidates, are kept)
+    if (widened && c->cav) return realloc_code_buffers(c);
+    return DT_OK;
+}
+
+// cavity and outer lists and neighbour copies for the pool's code width
+int realloc_code_buffers(dt_ctx *c) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dev_free(c, c->cav); dev_free(c, c->outc); dev_free(c, c->scr_n);
+    c->cav = c->outc = c->scr_n = nullptr;
+    const size_t cb = c->wide ? sizeof(unsigned long long) : sizeof(uint32_t);
+    if (dev_alloc(c, &c->cav, c->bufC * cb) != hipSuccess || dev_alloc(c, &c->outc, c->bufF * cb) != hipSuccess ||
+        dev_alloc(c, &c->scr_n, c->bufC * 4 * cb) != hipSuccess) {
+        hipGetLastError();
+        return fail(c, DT_E_CAPACITY, "round buffers for %u insertions do not fit", c->list_cap);
+    }
+    c->buf_wide = c->wide;
     return DT_OK;
 }
 
 int ensure_round_buffers(dt_ctx *c, uint32_t rmax) {
     if (c->list_cap >= rmax && c->cav && c->bufC == (size_t)c->list_cap * c->capC &&
-        c->bufF == (size_t)c->list_cap * c->capF)
+        c->bufF == (size_t)c->list_cap * c->capF && c->buf_wide == c->wide)
         return DT_OK;
     rmax = std::max(rmax, c->list_cap);
     for (int k = 0; k < 4; ++k) {
-        hipFree(c->lpt[k]);
-        hipFree(c->lrank[k]);
+        dev_free(c, c->lpt[k]);
+        dev_free(c, c->lrank[k]);
         c->lpt[k] = c->lrank[k] = nullptr;
     }
-    hipFree(c->cav); hipFree(c->bnd); hipFree(c->outc); hipFree(c->cnt); hipFree(c->status);
-    hipFree(c->scr_v); hipFree(c->scr_n);
-    c->scr_v = c->scr_n = nullptr;
-    c->cav = c->bnd = c->outc = c->cnt = nullptr;
+    dev_free(c, c->cav); dev_free(c, c->bnd); dev_free(c, c->outc); dev_free(c, c->cnt); dev_free(c, c->status);
+    dev_free(c, c->scr_v); dev_free(c, c->scr_n); dev_free(c, c->defer);
+    c->defer = nullptr;
+    c->scr_v = nullptr;
+    c->scr_n = nullptr;
+    c->cav = c->outc = nullptr;
+    c->bnd = c->cnt = nullptr;
     c->status = nullptr;
     c->list_cap = rmax;
     c->bufC = (size_t)rmax * c->capC;
     c->bufF = (size_t)rmax * c->capF;
     bool ok = true;
     for (int k = 0; k < 4; ++k)
-        ok = ok && hipMalloc((void **)&c->lpt[k], rmax * sizeof(uint32_t)) == hipSuccess &&
-             hipMalloc((void **)&c->lrank[k], rmax * sizeof(uint32_t)) == hipSuccess;
-    ok = ok && hipMalloc((void **)&c->cav, c->bufC * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void **)&c->bnd, c->bufF * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void **)&c->outc, c->bufF * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void **)&c->cnt, 2 * (size_t)rmax * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void **)&c->status, rmax) == hipSuccess &&
-         hipMalloc((void **)&c->scr_v, c->bufC * sizeof(uint4)) == hipSuccess &&
-         hipMalloc((void **)&c->scr_n, c->bufC * sizeof(uint4)) == hipSuccess;
+        ok = ok && dev_alloc(c, (void **)&c->lpt[k], rmax * sizeof(uint32_t)) == hipSuccess &&
+             dev_alloc(c, (void **)&c->lrank[k], rmax * sizeof(uint32_t)) == hipSuccess;
+    // adjacency codes in the cavity and outer lists and the neighbour copies: 4 or 8 bytes
+    const size_t cb = c->wide ? sizeof(unsigned long long) : sizeof(uint32_t);
+    ok = ok && dev_alloc(c, &c->cav, c->bufC * cb) == hipSuccess &&
+         dev_alloc(c, (void **)&c->bnd, c->bufF * sizeof(uint32_t)) == hipSuccess &&
+         dev_alloc(c, &c->outc, c->bufF * cb) == hipSuccess &&
+         dev_alloc(c, (void **)&c->cnt, 2 * (size_t)rmax * sizeof(uint32_t)) == hipSuccess &&
+         dev_alloc(c, (void **)&c->status, rmax) == hipSuccess &&
+         dev_alloc(c, (void **)&c->defer, rmax * sizeof(uint32_t)) == hipSuccess &&
+         dev_alloc(c, (void **)&c->scr_v, c->bufC * sizeof(uint4)) == hipSuccess &&
+         dev_alloc(c, &c->scr_n, c->bufC * 4 * cb) == hipSuccess;
+    c->buf_wide = c->wide;
     if (!ok) {
         hipGetLastError();
         c->list_cap = 0;
@@ -383,6 +478,8 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     }
     a.nnext_ptr = &d->list_count[ni];
     a.novf_ptr = &d->list_count[oi];
+    a.defer = c->defer;
+    a.ndefer_ptr = &d->ndefer;
     a.cav = c->cav;
     a.bnd = c->bnd;
     a.outc = c->outc;
@@ -390,26 +487,30 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.status = c->status;
     a.fl_cur = c->fl[c->fl_idx];
     a.fl_next = c->fl[c->fl_idx ^ 1];
+    a.flcap = c->flcap;
     a.ctr = d;
     a.stat = c->stat;
     a.stride = std::max<uint32_t>(max_cand, 1);
     a.capC = capC;
     a.capF = capF;
     a.tcap = c->tcap;
-    a.hmg = 1u << (31 - __builtin_clz(std::min<uint32_t>(4u * std::min<uint32_t>(capC, 1u << 24), 1u << 30)));
+    // the global cavity set of the largest cavities: a power of two of entries in the
+    // candidate's 16 capC bytes of ball scratch (4-byte entries, or 8-byte with 64-bit codes)
+    a.hmg = 1u << (31 - __builtin_clz(std::min<uint32_t>((c->wide ? 2u : 4u) * std::min<uint32_t>(capC, 1u << 24),
+                                                         1u << 30)));
     // Claim words are never reset between rounds: later rounds stamp lower.  When the low 32
     // bits of the round counter wrap, every claim left in the pool would outrank the new
     // stamps, so the claim words are reset to the empty value first (the kernels of earlier
     // rounds are ahead of the reset on the same stream).
     if ((c->round_counter & 0xFFFFFFFFull) == 0 && c->round_counter != 0 && c->tcap)
-        HIPCHK(launch_reset_claims(c->T, c->tcap, c->stream));
+        HIPCHK(launch_reset_claims(c->T, c->wide, c->tcap, c->stream));
     a.round_hi = (0xFFFFFFFFull - (c->round_counter & 0xFFFFFFFFull)) << 32;
     c->round_counter++;
-    HIPCHK(launch_round(a, max_cand, c->lanes, c->stream, c->opt.timing ? c->ev[slot] : nullptr));
+    HIPCHK(launch_round(a, c->wide, max_cand, c->lanes, c->stream, c->opt.timing ? c->ev[slot] : nullptr));
     HIPCHK(launch_round_end(a, max_cand, c->stream));
     c->fl_idx ^= 1;
     HIPCHK(hipMemcpyAsync(&c->hring[slot], c->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipEventRecord(c->evdone[slot], c->stream));
+    if (c->evdone[slot]) HIPCHK(hipEventRecord(c->evdone[slot], c->stream));
     c->slot_cand[slot] = max_cand;
     c->slot_capC[slot] = capC;
     c->st.rounds++;
@@ -419,7 +520,10 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
 
 // Waits for the round whose counters go to `slot`; they become the host's snapshot.
 int complete_round(dt_ctx *c, int slot) {
-    HIPCHK(hipEventSynchronize(c->evdone[slot]));
+    // without events (the arena's context) the whole stream is waited for: the round in
+    // flight behind this one completes too, which is correct, only not overlapped
+    if (c->evdone[slot]) HIPCHK(hipEventSynchronize(c->evdone[slot]));
+    else HIPCHK(hipStreamSynchronize(c->stream));
     c->hctr = &c->hring[slot];
     const uint32_t max_cand = c->slot_cand[slot], capC = c->slot_capC[slot];
     if (max_cand) accumulate_timing(c, slot);
@@ -706,6 +810,11 @@ int prepare_clouds(dt_ctx *c, const std::vector<uint64_t> &off, uint64_t base, b
     std::vector<uint32_t> cch(C + 1, 0);
     std::vector<Cloud> h(C);
     *mmax = 1;
+    // adaptive curve: the deepest grid the key holds beside the cloud id, so that points
+    // sharing a cell of the fixed level are ordered by the curve's deeper levels too
+    int cb = 0;
+    while ((1ull << cb) < C) ++cb;
+    const uint32_t m_adaptive = (uint32_t)std::min(21, (64 - cb) / 3);
     for (uint32_t k = 0; k < C; ++k) {
         cch[k] = (uint32_t)cs.size();
         for (uint64_t b = off[k]; b < off[k + 1]; b += CHUNK) {
@@ -716,7 +825,7 @@ int prepare_clouds(dt_ctx *c, const std::vector<uint64_t> &off, uint64_t base, b
         std::memset(&h[k], 0, sizeof(Cloud));
         h[k].lo = (uint32_t)(base + off[k]);
         h[k].hi = (uint32_t)(base + off[k + 1]);
-        h[k].m = (uint32_t)moore_level(nk);
+        h[k].m = c->opt.adaptive_curve ? m_adaptive : (uint32_t)moore_level(nk);
         *mmax = std::max(*mmax, (int)h[k].m);
     }
     cch[C] = (uint32_t)cs.size();
@@ -844,33 +953,7 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
     HIPCHK(hipStreamSynchronize(c->stream));
     Levels lv;
     compute_levels(hist, L, lv);
-    // 6. initial tetrahedron of each cloud
-    if (fresh) {
-        if (c->tcap == 0 || c->tcap < 7 * n + 4096 + 5ull * C) {
-            uint64_t want = c->opt.capacity_tets ? c->opt.capacity_tets : (uint64_t)(6.9 * (double)n) + 65536 + 5ull * C;
-            if (c->tcap) {
-                hipFree(c->T); hipFree(c->fl[0]); hipFree(c->fl[1]);
-                c->tcap = 0;
-            }
-            if ((rc = grow_tets(c, std::max<uint64_t>(want, 4096)))) return rc;
-        }
-        HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
-        c->hctr->bad_cloud = NONE;
-        c->hctr->tet_count = 5 * C;
-        HIPCHK(hipMemcpyAsync(&c->ctr->bad_cloud, &c->hctr->bad_cloud, sizeof(uint32_t), hipMemcpyHostToDevice,
-                              c->stream));
-        HIPCHK(hipMemcpyAsync(&c->ctr->tet_count, &c->hctr->tet_count, sizeof(uint32_t), hipMemcpyHostToDevice,
-                              c->stream));
-        HIPCHK(launch_init(c->V.p, c->clouds.p, C, 0, c->dup.p, c->T, c->vtet.p, c->ctr, c->stream));
-        if ((rc = sync_ctr(c))) return rc;
-        if (c->hctr->error & ERR_DEGENERATE) {
-            if (C == 1) return fail(c, DT_E_DEGENERATE, "fewer than four affinely independent distinct points");
-            return fail(c, DT_E_DEGENERATE, "cloud %u has fewer than four affinely independent distinct points",
-                        c->hctr->bad_cloud);
-        }
-        c->mesh_vertices = 4ull * C;
-    }
-    // 7. level tables and walk anchors
+    // 6. level tables, walk anchors and (learned scheduler) the learned order
     uint32_t *d_start, *d_size, *d_bits;
     unsigned long long *d_rb;
     if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
@@ -908,6 +991,55 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
         // anchors stay those of the BRIO levels: a half level is a sparse and, by the cost
         // prediction, uneven subset, and its records make far walk starts
     }
+    if (n > BIG_CALL_POINTS) {
+        // the keys, the dedupe table, the value buffer not holding the level-major order and
+        // the scheduler's features are not needed by the rounds: their memory goes to the
+        // pool and round buffers, allocated next
+        auto rel = [c](auto &b) { dev_free(c, b.p); b.p = nullptr; b.cap = 0; };
+        rel(c->keys);
+        rel(c->keys_tmp);
+        rel(c->table);
+        rel(c->feat);
+        rel(c->ypred);
+        if (c->lord == c->vals.p) rel(c->vals_tmp);
+        else if (c->lord == c->vals_tmp.p) rel(c->vals);
+    }
+    // 7. initial tetrahedron of each cloud
+    if (fresh) {
+        // pool layout: 64-bit adjacency codes when asked for, or (automatic) when the pool
+        // this call needs passes the 2^30 slots of 32-bit codes
+        const uint64_t want = std::max<uint64_t>(
+            c->opt.capacity_tets ? c->opt.capacity_tets : (uint64_t)(6.9 * (double)n) + 65536 + 5ull * C, 4096);
+        const bool wide = c->opt.index_bits == 64 || (c->opt.index_bits == 0 && want > MAX_TETS);
+        if (c->opt.index_bits == 32 && want > MAX_TETS)
+            return fail(c, DT_E_CAPACITY, "%llu points need more than %u tetrahedron slots with 32-bit adjacency "
+                                          "codes (dt_options.index_bits = 64 or 0 lifts the limit)",
+                        (unsigned long long)n, MAX_TETS);
+        if (c->tcap == 0 || c->tcap < std::min<uint64_t>(want, 7 * n + 4096 + 5ull * C) || c->wide != wide) {
+            if (c->tcap) {
+                dev_free(c, c->T); dev_free(c, c->fl[0]); dev_free(c, c->fl[1]);
+                c->T = nullptr;
+                c->tcap = 0;
+            }
+            c->wide = wide;
+            if ((rc = grow_tets(c, want))) return rc;
+        }
+        HIPCHK(hipMemsetAsync(&c->ctr->error, 0, sizeof(uint32_t), c->stream));
+        c->hctr->bad_cloud = NONE;
+        c->hctr->tet_count = 5 * C;
+        HIPCHK(hipMemcpyAsync(&c->ctr->bad_cloud, &c->hctr->bad_cloud, sizeof(uint32_t), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipMemcpyAsync(&c->ctr->tet_count, &c->hctr->tet_count, sizeof(uint32_t), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(launch_init(c->V.p, c->clouds.p, C, 0, c->dup.p, c->T, c->wide, c->vtet.p, c->ctr, c->stream));
+        if ((rc = sync_ctr(c))) return rc;
+        if (c->hctr->error & ERR_DEGENERATE) {
+            if (C == 1) return fail(c, DT_E_DEGENERATE, "fewer than four affinely independent distinct points");
+            return fail(c, DT_E_DEGENERATE, "cloud %u has fewer than four affinely independent distinct points",
+                        c->hctr->bad_cloud);
+        }
+        c->mesh_vertices = 4ull * C;
+    }
     c->logged = c->opt.log_points != 0;
     if (c->logged) {
         if ((rc = ensure(c, c->log_att, n))) return rc;
@@ -924,7 +1056,7 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
     c->nv = base + n;
     c->npoints += n;
     c->st.points += n;
-    const uint64_t want_r = c->opt.round_size ? c->opt.round_size : DEFAULT_ROUND_MAX;
+    const uint64_t want_r = c->opt.round_size ? std::min<uint64_t>(c->opt.round_size, c->round_cap) : c->round_cap;
     if ((rc = ensure_round_buffers(c, (uint32_t)std::min<uint64_t>(want_r, std::max<uint64_t>(n, ROUND_MIN)))))
         return rc;
     rc = run_rounds(c, lv, d_start, d_size, d_bits, d_rb, base, n);
@@ -958,7 +1090,8 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
     else dt_default_options(&c->opt);
     if (c->opt.round_fraction < 0 || c->opt.round_fraction > 64 ||
         (c->opt.lanes_per_insert != 0 && c->opt.lanes_per_insert != 4 && c->opt.lanes_per_insert != 8 &&
-         c->opt.lanes_per_insert != 16 && c->opt.lanes_per_insert != 64)) {
+         c->opt.lanes_per_insert != 16 && c->opt.lanes_per_insert != 64) ||
+        (c->opt.index_bits != 0 && c->opt.index_bits != 32 && c->opt.index_bits != 64)) {
         delete c;
         return DT_E_ARG;
     }
@@ -1037,14 +1170,16 @@ int dt_get_tets(dt_ctx *c, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets) {
         return DT_OK;
     }
     int rc;
+    // live finite tetrahedra numbered in slot order: bit set + scan of the per-word counts
     const uint32_t count = c->hctr->tet_count;
-    if ((rc = ensure(c, c->oflags, count)) || (rc = ensure(c, c->omap, count + 1)) ||
-        (rc = ensure(c, c->scan_tmp, scan_tmp_entries(count) + 64)))
+    const uint64_t nw = ((uint64_t)count + 63) / 64;
+    if ((rc = ensure(c, c->obits, nw + 1)) || (rc = ensure(c, c->owcnt, nw + 1)) ||
+        (rc = ensure(c, c->opre, nw + 1)) || (rc = ensure(c, c->scan_tmp, scan_tmp_entries(nw) + 64)))
         return rc;
-    HIPCHK(launch_output_flags(c->T, count, c->oflags.p, c->stream));
-    HIPCHK(exclusive_scan_u32(c->oflags.p, c->omap.p, count, c->scan_tmp.p, c->omap.p + count, c->stream));
+    HIPCHK(launch_live_bits(c->T, c->wide, count, c->obits.p, c->owcnt.p, c->stream));
+    HIPCHK(exclusive_scan_u32(c->owcnt.p, c->opre.p, nw, c->scan_tmp.p, c->opre.p + nw, c->stream));
     uint32_t T = 0;
-    HIPCHK(hipMemcpyAsync(&T, c->omap.p + count, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&T, c->opre.p + nw, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->st.tets = T;
     if (!tets && !nbrs) {
@@ -1056,27 +1191,42 @@ int dt_get_tets(dt_ctx *c, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets) {
         return fail(c, DT_E_ARG, "output buffers hold %llu tetrahedra, %u needed", (unsigned long long)*num_tets, T);
     }
     *num_tets = T;
-    // the export kernel stores 16-byte vectors: device buffers that are not 16-byte aligned
-    // are filled through the staging buffers, like host buffers
+    if ((rc = ensure(c, c->ovid, std::max<uint64_t>(c->nv, 1)))) return rc;
+    HIPCHK(launch_out_vid(c->V.p, (uint32_t)c->nv, c->ovid.p, c->stream));
+    // The export kernel stores 16-byte vectors: host buffers and device buffers that are not
+    // 16-byte aligned are filled through staging buffers, a slot range at a time (chunk
+    // boundaries are multiples of 64 slots, so each chunk's first output row is a scan value).
     const bool dev_t = tets && is_device_ptr(tets) && ((uintptr_t)tets & 15u) == 0,
                dev_n = nbrs && is_device_ptr(nbrs) && ((uintptr_t)nbrs & 15u) == 0;
-    uint32_t *ot = tets;
-    int64_t *on = nbrs;
-    if (tets && !dev_t) {
-        if ((rc = ensure(c, c->otets, 4 * (size_t)T + 4))) return rc;
-        ot = c->otets.p;
+    const bool staged = (tets && !dev_t) || (nbrs && !dev_n);
+    const uint32_t chunk = staged ? c->export_chunk : std::max<uint32_t>(count, 64);
+    std::vector<uint32_t> obase;
+    for (uint64_t t0 = 0; t0 < count; t0 += chunk) obase.push_back(0);
+    obase.push_back(T);
+    if (staged) {
+        if ((tets && !dev_t && (rc = ensure(c, c->otets, 4 * (size_t)chunk))) ||
+            (nbrs && !dev_n && (rc = ensure(c, c->onbrs, 4 * (size_t)chunk))))
+            return rc;
+        for (size_t k = 1; k + 1 < obase.size(); ++k)
+            HIPCHK(hipMemcpyAsync(&obase[k], c->opre.p + (k * (uint64_t)chunk) / 64, sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
     }
-    if (nbrs && !dev_n) {
-        if ((rc = ensure(c, c->onbrs, 4 * (size_t)T + 4))) return rc;
-        on = c->onbrs.p;
+    for (size_t k = 0; k + 1 < obase.size(); ++k) {
+        const uint32_t t0 = (uint32_t)(k * (uint64_t)chunk);
+        const uint32_t t1 = (uint32_t)std::min<uint64_t>(count, (uint64_t)t0 + chunk);
+        const uint32_t o0 = obase[k], o1 = obase[k + 1];
+        uint32_t *ot = tets ? (dev_t ? tets + 4 * (size_t)o0 : c->otets.p) : nullptr;
+        int64_t *on = nbrs ? (dev_n ? nbrs + 4 * (size_t)o0 : c->onbrs.p) : nullptr;
+        HIPCHK(launch_output(c->T, c->wide, c->ovid.p, c->obits.p, c->opre.p, t0, t1, o0, ot, on, c->stream));
+        if (tets && !dev_t && o1 > o0)
+            HIPCHK(hipMemcpyAsync(tets + 4 * (size_t)o0, ot, 4 * (size_t)(o1 - o0) * sizeof(uint32_t),
+                                  hipMemcpyDefault, c->stream));
+        if (nbrs && !dev_n && o1 > o0)
+            HIPCHK(hipMemcpyAsync(nbrs + 4 * (size_t)o0, on, 4 * (size_t)(o1 - o0) * sizeof(int64_t),
+                                  hipMemcpyDefault, c->stream));
+        if (staged) HIPCHK(hipStreamSynchronize(c->stream));  // the staging buffers are reused
     }
-    if ((rc = ensure(c, c->ovid, std::max<uint64_t>(c->nv, 1)))) return rc;
-    HIPCHK(launch_output(c->T, c->V.p, (uint32_t)c->nv, c->oflags.p, c->omap.p, c->ovid.p, count, ot, on,
-                         c->stream));
-    if (tets && !dev_t)
-        HIPCHK(hipMemcpyAsync(tets, ot, 4 * (size_t)T * sizeof(uint32_t), hipMemcpyDefault, c->stream));
-    if (nbrs && !dev_n)
-        HIPCHK(hipMemcpyAsync(nbrs, on, 4 * (size_t)T * sizeof(int64_t), hipMemcpyDefault, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return DT_OK;
 }
@@ -1093,7 +1243,7 @@ static int build_cloud_index(dt_ctx *c) {
         return rc;
     unsigned long long *k0 = c->okeys.p, *k1 = c->okeys.p + count + 1;
     uint32_t *v0 = c->osorted.p, *v1 = c->osorted.p + count + 1;
-    HIPCHK(launch_tet_cloud(c->T, c->V.p, count, C, k0, v0, c->stream));
+    HIPCHK(launch_tet_cloud(c->T, c->wide, c->V.p, count, C, k0, v0, c->stream));
     int bits = 0;
     while ((1ull << bits) <= C) ++bits;
     bool swapped = false;
@@ -1147,7 +1297,7 @@ int dt_get_tets_batch(dt_ctx *c, uint32_t cloud, uint32_t *tets, int64_t *nbrs, 
         if ((rc = ensure(c, c->onbrs, 4 * (size_t)T + 4))) return rc;
         on = c->onbrs.p;
     }
-    HIPCHK(launch_output_cloud(c->T, c->V.p, c->osorted_live, c->omap2.p, tb, te, c->h_off[cloud], ot, on,
+    HIPCHK(launch_output_cloud(c->T, c->wide, c->V.p, c->osorted_live, c->omap2.p, tb, te, c->h_off[cloud], ot, on,
                                c->stream));
     // the destination is host memory or an unaligned device buffer
     if (tets && !dev_t)
@@ -1442,7 +1592,7 @@ int dt_destroy(dt_ctx *c) {
     f(c->T); f(c->fl[0]); f(c->fl[1]);
     for (int k = 0; k < 4; ++k) { f(c->lpt[k]); f(c->lrank[k]); }
     f(c->cav); f(c->bnd); f(c->outc); f(c->cnt); f(c->status);
-    f(c->scr_v); f(c->scr_n);
+    f(c->scr_v); f(c->scr_n); f(c->defer);
     f(c->ctr);
     f(c->stat);
     if (c->hring) hipHostFree(c->hring);
@@ -1452,7 +1602,7 @@ int dt_destroy(dt_ctx *c) {
     f(c->okeys.p); f(c->osorted.p); f(c->omap2.p); f(c->dbgV.p); f(c->dbg_cloud.p);
     f(c->lev.p); f(c->wbucket.p); f(c->log_att.p); f(c->feat.p); f(c->ypred.p);
     f(c->w32.p); f(c->m1.p); f(c->m2.p); f(c->grad.p); f(c->loss.p); f(c->wbf.p);
-    f(c->oflags.p); f(c->omap.p); f(c->otets.p); f(c->onbrs.p); f(c->ovid.p);
+    f(c->obits.p); f(c->owcnt.p); f(c->opre.p); f(c->otets.p); f(c->onbrs.p); f(c->ovid.p);
     for (int k = 0; k < 3; ++k) {
         for (int j = 0; j < 3; ++j)
             if (c->ev[k][j]) hipEventDestroy(c->ev[k][j]);
@@ -1483,6 +1633,9 @@ int dt_get_stats(const dt_ctx *c, dt_stats *out) {
     out->perturbed = h.perturbed;
     out->cavity_units = h.attempts;
     out->ball_units = h.won;
+    out->index_bits = c->tcap ? (c->wide ? 64 : 32) : 0;
+    out->dropped_slots = h.dropped;
+    out->deferred = h.deferred;
     return DT_OK;
 }
 
@@ -1527,10 +1680,12 @@ int dt_debug_sort(dt_ctx *c, const double *xyz, uint64_t n, uint64_t *keys, uint
         std::vector<uint64_t> kh(n);
         HIPCHK(hipMemcpyAsync(kh.data(), c->keys_tmp.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        // with the level in front when it fits beside the Moore index
         uint64_t j = 0;
-        for (int k = 0; k < L; ++k)
-            for (uint32_t q = 0; q < hist[k]; ++q, ++j)
-                kh[moore_order[lord_h[j]]] |= (uint64_t)k << (3 * mmax);
+        if (3 * mmax + 8 <= 64)
+            for (int k = 0; k < L; ++k)
+                for (uint32_t q = 0; q < hist[k]; ++q, ++j)
+                    kh[moore_order[lord_h[j]]] |= (uint64_t)k << (3 * mmax);
         HIPCHK(hipMemcpy(keys, kh.data(), n * sizeof(uint64_t), hipMemcpyDefault));
     }
     if (perm) {
@@ -1545,6 +1700,197 @@ int dt_debug_sort(dt_ctx *c, const double *xyz, uint64_t n, uint64_t *keys, uint
 int dt_debug_set_round_counter(dt_ctx *c, uint64_t rounds) {
     if (!c) return DT_E_ARG;
     c->round_counter = rounds;
+    return DT_OK;
+}
+
+int dt_get_points(dt_ctx *c, double *xyz, uint64_t *num_points) {
+    if (!c || !num_points) return DT_E_ARG;
+    if (c->batch) return fail(c, DT_E_ARG, "the context holds a batch of clouds");
+    const uint64_t n = c->have_mesh ? c->nv : 0;
+    if (!xyz) {
+        *num_points = n;
+        return DT_OK;
+    }
+    if (*num_points < n) {
+        *num_points = n;
+        return fail(c, DT_E_ARG, "the buffer holds %llu points, %llu needed", (unsigned long long)*num_points,
+                    (unsigned long long)n);
+    }
+    *num_points = n;
+    if (n == 0) return DT_OK;
+    HIPCHK(hipSetDevice(c->device));
+    double *out = xyz;
+    const bool dev = is_device_ptr(xyz);
+    int rc;
+    if (!dev) {
+        if ((rc = ensure(c, c->staging, 3 * n))) return rc;
+        out = c->staging.p;
+    }
+    HIPCHK(launch_points_out(c->V.p, (uint32_t)n, out, c->stream));
+    if (!dev) HIPCHK(hipMemcpyAsync(xyz, out, 3 * n * sizeof(double), hipMemcpyDefault, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DT_OK;
+}
+
+namespace {
+
+// stable radix sort of (keys, vals) by the low `bits` bits; the sorted pair lands in
+// (k0, v0) or (k1, v1): returns the values' buffer, *ko the keys'
+uint32_t *sort_into(dt_ctx *c, unsigned long long *k0, uint32_t *v0, unsigned long long *k1, uint32_t *v1,
+                    uint32_t n, int bits, unsigned long long **ko, hipError_t *err) {
+    bool swapped = false;
+    *err = radix_sort_pairs(k0, v0, k1, v1, c->hist.p, c->scan_tmp.p, n, bits, c->stream, &swapped);
+    if (ko) *ko = swapped ? k1 : k0;
+    return swapped ? v1 : v0;
+}
+
+int bits_for(uint64_t x) {
+    int b = 1;
+    while (b < 64 && (1ull << b) <= x) ++b;
+    return b;
+}
+
+}  // namespace
+
+int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, uint32_t *num_steps,
+              uint64_t *inserted) {
+    if (!c || !(h > 0.0) || !std::isfinite(h)) return DT_E_ARG;
+    if (num_steps) *num_steps = 0;
+    if (inserted) *inserted = 0;
+    if (!c->have_mesh || c->batch || c->nclouds != 1)
+        return fail(c, DT_E_ARG, "dt_refine needs the triangulation of dt_insert_points calls");
+    HIPCHK(hipSetDevice(c->device));
+    int rc;
+    hipError_t he;
+    // the input's grid for the candidates' Moore keys: the box of the points present now and
+    // the Moore level of their number
+    const uint64_t n0 = c->nv;
+    const uint32_t m = (uint32_t)moore_level(n0);
+    constexpr uint32_t BOX_BLOCKS = 256;
+    if ((rc = ensure(c, c->rf_cloud, 1)) || (rc = ensure(c, c->rf_partial, 6 * BOX_BLOCKS)) ||
+        (rc = ensure(c, c->rf_off, 2)) || (rc = ensure(c, c->rf_ctr, 4)))
+        return rc;
+    HIPCHK(launch_vert_box(c->V.p, (uint32_t)n0, m, c->rf_partial.p, BOX_BLOCKS, c->rf_cloud.p, c->stream));
+    Cloud box{};
+    HIPCHK(hipMemcpyAsync(&box, c->rf_cloud.p, sizeof box, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const double ext = box.box[3] > 0 ? std::ldexp(1.0, (int)m) / box.box[3] : 0.0;
+    // thresholds as (1.4 h)^2 and (0.7 h)^2 in fp64; grid cells a little wider than 0.7 h so
+    // that points closer than it always lie in neighbouring cells
+    const double g1 = 1.4 * h, f1 = 0.7 * h;
+    const double grow = g1 * g1, lim = f1 * f1;
+    const double cell = f1 * (1.0 + 0x1p-20);
+    const double cells = std::floor(ext / cell) + 3.0;
+    if (cells > (double)(1u << 20))
+        return fail(c, DT_E_ARG, "h = %g is too small for the point set's extent %g", h, ext);
+    const uint64_t G = (uint64_t)cells;
+    const int gbits = bits_for(G * G * G);
+    const double lo[3] = {box.box[0], box.box[1], box.box[2]};
+    // hull facets: the ghosts' facets; points strictly inside never change them
+    uint32_t count = c->hctr->tet_count;
+    if ((rc = ensure(c, c->rf_facets, std::max<uint32_t>(count, 1)))) return rc;
+    HIPCHK(hipMemsetAsync(c->rf_ctr.p, 0, 4 * sizeof(uint32_t), c->stream));
+    HIPCHK(launch_hull_facets(c->T, c->wide, count, c->rf_facets.p, c->rf_ctr.p, c->stream));
+    uint32_t nf = 0;
+    HIPCHK(hipMemcpyAsync(&nf, c->rf_ctr.p, sizeof nf, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    uint64_t total = 0;
+    for (uint32_t step = 0; step < max_steps; ++step) {
+        count = c->hctr->tet_count;
+        const uint64_t nv = c->nv;
+        // 1. candidates: circumcentres of the tetrahedra larger than 1.4 h, strictly inside
+        if ((rc = ensure(c, c->rf_cc, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q, count)) ||
+            (rc = ensure(c, c->rf_cc2, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q2, count)))
+            return rc;
+        HIPCHK(hipMemsetAsync(c->rf_ctr.p, 0, 4 * sizeof(uint32_t), c->stream));
+        HIPCHK(launch_circum(c->T, c->wide, c->V.p, count, grow, c->rf_cc.p, c->rf_q.p, count, c->rf_ctr.p,
+                             c->stream));
+        uint32_t k0 = 0;
+        HIPCHK(hipMemcpyAsync(&k0, c->rf_ctr.p, sizeof k0, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(launch_inside(c->V.p, c->rf_facets.p, nf, c->rf_cc.p, c->rf_q.p, k0, c->rf_cc2.p, c->rf_q2.p,
+                             c->rf_ctr.p + 1, c->stream));
+        uint32_t K = 0;
+        HIPCHK(hipMemcpyAsync(&K, c->rf_ctr.p + 1, sizeof K, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (K == 0) {
+            if (step_counts) step_counts[2 * step] = step_counts[2 * step + 1] = 0;
+            if (num_steps) *num_steps = step + 1;
+            break;
+        }
+        // 2. filter order: Moore key in the input's grid, then the sorted vertex indices
+        const size_t sortn = std::max<size_t>(K, nv);
+        if ((rc = ensure(c, c->rf_moore, K)) || (rc = ensure(c, c->rf_k0, sortn)) || (rc = ensure(c, c->rf_k1, sortn)) ||
+            (rc = ensure(c, c->rf_v0, sortn)) || (rc = ensure(c, c->rf_v1, sortn)) ||
+            (rc = ensure(c, c->hist, radix_hist_entries(sortn))) ||
+            (rc = ensure(c, c->scan_tmp, scan_tmp_entries(radix_hist_entries(sortn)) + scan_tmp_entries(sortn) + 64)) ||
+            (rc = ensure(c, c->rf_ccr, 3 * (size_t)K)) || (rc = ensure(c, c->rf_status, K)) ||
+            (rc = ensure(c, c->rf_flags, (size_t)K + 1)) || (rc = ensure(c, c->rf_pos, (size_t)K + 1)))
+            return rc;
+        const uint64_t off[2] = {0, K};
+        HIPCHK(hipMemcpyAsync(c->rf_off.p, off, sizeof off, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(launch_keys(c->rf_cc2.p, K, c->rf_off.p, 1, c->rf_cloud.p, 0, c->rf_moore.p, c->rf_v1.p, c->stream));
+        const int ib = bits_for(nv);  // bits of an input index
+        unsigned long long *ks = nullptr;
+        HIPCHK(launch_order_keys(c->rf_q2.p, nullptr, nullptr, K, 0, ib, c->rf_k0.p, c->rf_v0.p, c->stream));
+        uint32_t *perm = sort_into(c, c->rf_k0.p, c->rf_v0.p, c->rf_k1.p, c->rf_v1.p, K, 2 * ib, &ks, &he);
+        HIPCHK(he);
+        uint32_t *vb = perm == c->rf_v0.p ? c->rf_v1.p : c->rf_v0.p;
+        HIPCHK(launch_order_keys(c->rf_q2.p, nullptr, perm, K, 1, ib, c->rf_k0.p, vb, c->stream));
+        perm = sort_into(c, c->rf_k0.p, vb, c->rf_k1.p, perm, K, 2 * ib, &ks, &he);
+        HIPCHK(he);
+        vb = perm == c->rf_v0.p ? c->rf_v1.p : c->rf_v0.p;
+        HIPCHK(launch_order_keys(c->rf_q2.p, c->rf_moore.p, perm, K, 2, 0, c->rf_k0.p, vb, c->stream));
+        perm = sort_into(c, c->rf_k0.p, vb, c->rf_k1.p, perm, K, 3 * (int)m, &ks, &he);
+        HIPCHK(he);
+        // perm[r] = the candidate of rank r; keep it in rf_pos until the grids are built
+        HIPCHK(hipMemcpyAsync(c->rf_pos.p, perm, (size_t)K * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
+        // 3. no vertex closer than 0.7 h: vertex grid, sorted cell keys
+        HIPCHK(launch_cell_keys(lo, cell, G, nullptr, c->V.p, (uint32_t)nv, c->rf_k0.p, c->rf_v0.p, c->stream));
+        unsigned long long *vkeys = nullptr;
+        uint32_t *vidx = sort_into(c, c->rf_k0.p, c->rf_v0.p, c->rf_k1.p, c->rf_v1.p, (uint32_t)nv, gbits, &vkeys, &he);
+        HIPCHK(he);
+        HIPCHK(launch_near_vertex(lo, cell, G, c->V.p, vkeys, vidx, (uint32_t)nv, c->rf_cc2.p, c->rf_pos.p, K, lim,
+                                  c->rf_ccr.p, c->rf_status.p, c->stream));
+        // 4. the greedy filter among the candidates, in rounds over the candidate grid
+        HIPCHK(launch_cell_keys(lo, cell, G, c->rf_ccr.p, nullptr, K, c->rf_k0.p, c->rf_v0.p, c->stream));
+        unsigned long long *ckeys = nullptr;
+        uint32_t *crank = sort_into(c, c->rf_k0.p, c->rf_v0.p, c->rf_k1.p, c->rf_v1.p, K, gbits, &ckeys, &he);
+        HIPCHK(he);
+        for (uint32_t round = 0;; ++round) {
+            if (round > K) return fail(c, DT_E_INTERNAL, "refinement filter did not settle");
+            HIPCHK(hipMemsetAsync(c->rf_ctr.p + 2, 0, sizeof(uint32_t), c->stream));
+            HIPCHK(launch_filter_round(lo, cell, G, ckeys, crank, K, c->rf_ccr.p, lim, c->rf_status.p,
+                                       c->rf_ctr.p + 2, c->stream));
+            uint32_t und = 0;
+            HIPCHK(hipMemcpyAsync(&und, c->rf_ctr.p + 2, sizeof und, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            if (und == 0) break;
+        }
+        // 5. the kept points in filter order, appended
+        HIPCHK(launch_kept(c->rf_status.p, K, c->rf_flags.p, nullptr, nullptr, nullptr, 0, c->stream));
+        HIPCHK(exclusive_scan_u32(c->rf_flags.p, c->rf_pos.p, K, c->scan_tmp.p, c->rf_pos.p + K, c->stream));
+        uint32_t nk = 0;
+        HIPCHK(hipMemcpyAsync(&nk, c->rf_pos.p + K, sizeof nk, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (step_counts) {
+            step_counts[2 * step] = K;
+            step_counts[2 * step + 1] = nk;
+        }
+        if (num_steps) *num_steps = step + 1;
+        if (nk == 0) break;
+        if ((rc = ensure(c, c->rf_pts, 3 * (size_t)nk))) return rc;
+        HIPCHK(launch_kept(c->rf_status.p, K, nullptr, c->rf_pos.p, c->rf_ccr.p, c->rf_pts.p, 1, c->stream));
+        if ((rc = dt_insert_points(c, c->rf_pts.p, nk))) return rc;
+        total += nk;
+        if (inserted) *inserted = total;
+    }
+    return DT_OK;
+}
+
+int dt_debug_widen_at(dt_ctx *c, uint64_t slots) {
+    if (!c || slots < 4096 || slots > MAX_TETS) return DT_E_ARG;
+    c->narrow_max = slots;
     return DT_OK;
 }
 

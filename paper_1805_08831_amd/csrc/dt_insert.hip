@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "dt_internal.h"
 #include "dt_predicates.h"
 
@@ -37,13 +39,26 @@ __device__ __forceinline__ P3 vpos(const Vert *V, uint32_t v) {
     return {r.x, r.y, r.z};
 }
 
-__device__ __forceinline__ uint32_t comp(uint4 q, int k) {
-    return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w));
-}
-
-// neighbour code of facet f of tetrahedron t, as a 4-byte lvalue
+// neighbour code of facet f of tetrahedron t, as an lvalue
 __device__ __forceinline__ uint32_t &nref(Tet *T, uint32_t t, uint32_t f) {
     return reinterpret_cast<uint32_t *>(&T[t].n)[f];
+}
+__device__ __forceinline__ unsigned long long &nref(TetW *T, uint32_t t, uint32_t f) {
+    return T[t].n.c[f];
+}
+
+// slot and facet of an adjacency code 4 t + f
+template <class C>
+__device__ __forceinline__ uint32_t code_slot(C code) {
+    return (uint32_t)(code >> 2);
+}
+template <class C>
+__device__ __forceinline__ int code_facet(C code) {
+    return (int)(code & 3u);
+}
+template <class K>
+__device__ __forceinline__ typename K::code make_code(uint32_t slot, uint32_t f) {
+    return ((typename K::code)slot << 2) | (typename K::code)f;
 }
 
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
@@ -115,9 +130,11 @@ __device__ __forceinline__ int orient_new_tet(uint32_t w[4], int j) {
 // records (any choice gives the same triangulation), positively oriented, plus the four
 // ghosts (each holds G in slot 3, its finite facet facing outward), at slots
 // first_slot + 5 c .. + 4.
+template <class K>
 __global__ void k_init(const Vert *__restrict__ V, Cloud *__restrict__ clouds, uint32_t first_slot,
-                       const uint8_t *__restrict__ dup, Tet *__restrict__ T, uint32_t *__restrict__ vtet,
+                       const uint8_t *__restrict__ dup, typename K::Rec *__restrict__ T, uint32_t *__restrict__ vtet,
                        Ctr *__restrict__ ctr) {
+    using code = typename K::code;
     __shared__ uint32_t sel[4];
     __shared__ uint32_t best;
     PredStats st;
@@ -154,15 +171,16 @@ __global__ void k_init(const Vert *__restrict__ V, Cloud *__restrict__ clouds, u
         uint32_t t = v[0]; v[0] = v[1]; v[1] = t;
     }
     const uint32_t s0 = first_slot + 5 * c;
-    uint32_t TV[5][4], N[5][4];
+    uint32_t TV[5][4];
+    code N[5][4];
     for (int k = 0; k < 4; ++k) TV[0][k] = v[k];
     for (int j = 0; j < 4; ++j) {
         uint32_t w[4] = {v[0], v[1], v[2], v[3]};
         w[j] = GHOST;
         orient_new_tet(w, j);  // G ends in slot 3: finite facet (w0,w1,w2) faces outward
         for (int k = 0; k < 4; ++k) TV[1 + j][k] = w[k];
-        N[0][j] = ((s0 + 1u + j) << 2) | 3u;
-        N[1 + j][3] = (s0 << 2) | (uint32_t)j;
+        N[0][j] = make_code<K>(s0 + 1u + j, 3u);
+        N[1 + j][3] = make_code<K>(s0, (uint32_t)j);
     }
     // ghost-ghost adjacencies: facets through G with the same three vertices
     for (int g1 = 1; g1 < 5; ++g1)
@@ -176,25 +194,27 @@ __global__ void k_init(const Vert *__restrict__ V, Cloud *__restrict__ clouds, u
                         for (int k = 0; k < 4; ++k)
                             if (k != f2 && TV[g2][k] == TV[g1][i]) same++;
                     }
-                    if (same == 3) N[g1][f1] = ((s0 + (uint32_t)g2) << 2) | (uint32_t)f2;
+                    if (same == 3) N[g1][f1] = make_code<K>(s0 + (uint32_t)g2, (uint32_t)f2);
                 }
             }
     for (int t = 0; t < 5; ++t) {
-        Tet r;
+        typename K::Rec &r = T[s0 + t];
         r.v = make_uint4(TV[t][0], TV[t][1], TV[t][2], TV[t][3]);
-        r.n = make_uint4(N[t][0], N[t][1], N[t][2], N[t][3]);
+        for (int f = 0; f < 4; ++f) nref(T, s0 + t, f) = N[t][f];
         r.claim = ~0ull;
-        r.spare[0] = r.spare[1] = r.spare[2] = 0;
-        T[s0 + t] = r;
+        r.spare[0] = 0;
     }
     for (int k = 0; k < 4; ++k) vtet[v[k]] = s0;
     clouds[c].any_live = s0;
 }
 
 hipError_t launch_init(const Vert *V, Cloud *clouds, uint32_t nclouds, uint32_t first_slot, const uint8_t *dup,
-                       Tet *T, uint32_t *vtet, Ctr *ctr, hipStream_t s) {
+                       void *T, bool wide, uint32_t *vtet, Ctr *ctr, hipStream_t s) {
     if (nclouds == 0) return hipSuccess;
-    k_init<<<nclouds, 256, 0, s>>>(V, clouds, first_slot, dup, T, vtet, ctr);
+    if (wide)
+        k_init<Wide><<<nclouds, 256, 0, s>>>(V, clouds, first_slot, dup, (TetW *)T, vtet, ctr);
+    else
+        k_init<Narrow><<<nclouds, 256, 0, s>>>(V, clouds, first_slot, dup, (Tet *)T, vtet, ctr);
     return hipGetLastError();
 }
 
@@ -256,23 +276,53 @@ hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, con
 // ------------------------------------------------------------------ walk + cavity + claim
 
 
-// perturbed "P strictly inside the circumsphere of finite tetrahedron w"
-__device__ __forceinline__ bool finite_inside(const Vert *V, uint4 w, P3 P, unsigned long long pidx,
-                                              PredStats &st) {
-    const uint32_t ids[4] = {w.x, w.y, w.z, w.w};
-    return insphere_perturbed(vpos(V, w.x), vpos(V, w.y), vpos(V, w.z), vpos(V, w.w), P,
-                              [&](int k) { return k < 4 ? V[ids[k]].idx : pidx; }, st) < 0;
+// Predicates of the cavity kernel.  FULL decides every sign exactly (filter, certified fp64,
+// integers, perturbation).  Without FULL only the fp64 filter runs, and a sign it cannot
+// decide (an exact zero included, which needs the perturbation) comes back as UNDECIDED: the
+// attempt then stops before claiming anything on that step and is run again by the FULL
+// kernel in the same round.  The exact stages (and their registers and scratch) stay out of
+// the kernel that does almost all the work.
+constexpr int UNDECIDED = 2;
+
+template <bool FULL>
+__device__ __forceinline__ int cav_orient(P3 a, P3 b, P3 c, P3 d, PredStats &st) {
+    if (FULL) return orient3d(a, b, c, d, st);
+    st.orient++;
+    return orient3d_filter(a, b, c, d);
 }
 
-// Sec. 2.6: a ghost (a,b,c,G) contains the open half-space beyond abc and abc's circumdisk
-__device__ __forceinline__ bool tet_inside(const RoundArgs &a, uint32_t u, P3 P, unsigned long long pidx,
-                                           PredStats &st) {
-    uint4 w = a.T[u].v;
-    if (w.w != GHOST) return finite_inside(a.V, w, P, pidx, st);
-    int o = orient3d(vpos(a.V, w.x), vpos(a.V, w.y), vpos(a.V, w.z), P, st);
-    if (o != 0) return o > 0;
-    uint32_t x = a.T[u].n.w >> 2;
-    return finite_inside(a.V, a.T[x].v, P, pidx, st);
+// -1: e strictly inside the (perturbed) circumsphere of the positive tetrahedron abcd
+template <bool FULL, class Keys>
+__device__ __forceinline__ int cav_insphere(P3 a, P3 b, P3 c, P3 d, P3 e, Keys keys, PredStats &st) {
+    if (FULL) return insphere_perturbed(a, b, c, d, e, keys, st);
+    st.insphere++;
+    const int s = insphere_filter(a, b, c, d, e);
+    return s == 0 ? UNDECIDED : s;
+}
+
+// perturbed "P strictly inside the circumsphere of finite tetrahedron w": -1 inside, 1
+// outside, UNDECIDED
+template <bool FULL>
+__device__ __forceinline__ int finite_inside(const Vert *V, uint4 w, P3 P, unsigned long long pidx,
+                                             PredStats &st) {
+    const uint32_t ids[4] = {w.x, w.y, w.z, w.w};
+    const int s = cav_insphere<FULL>(vpos(V, w.x), vpos(V, w.y), vpos(V, w.z), vpos(V, w.w), P,
+                                     [&](int k) { return k < 4 ? V[ids[k]].idx : pidx; }, st);
+    return s == UNDECIDED ? s : (s < 0 ? -1 : 1);
+}
+
+// Sec. 2.6: a ghost (a,b,c,G) contains the open half-space beyond abc and abc's circumdisk;
+// -1 inside, 1 outside, UNDECIDED
+template <class K, bool FULL>
+__device__ __forceinline__ int tet_inside(const typename K::Rec *T, const Vert *V, uint32_t u, P3 P,
+                                          unsigned long long pidx, PredStats &st) {
+    uint4 w = T[u].v;
+    if (w.w != GHOST) return finite_inside<FULL>(V, w, P, pidx, st);
+    int o = cav_orient<FULL>(vpos(V, w.x), vpos(V, w.y), vpos(V, w.z), P, st);
+    if (o == UNDECIDED) return o;
+    if (o != 0) return o > 0 ? -1 : 1;
+    uint32_t x = code_slot(comp(T[u].n, 3));
+    return finite_inside<FULL>(V, T[x].v, P, pidx, st);
 }
 
 // ------------------------------------------------------------------ walk + cavity + claim
@@ -282,9 +332,13 @@ __device__ __forceinline__ bool tet_inside(const RoundArgs &a, uint32_t u, P3 P,
 // keep both in LDS at (128, 256) with 4 to 64 lanes per insertion; rounds for large
 // cavities use (1024, 2048) with 64 lanes, and beyond that the same 64-lane search keeps
 // both in global memory (the candidate's cavity buffer and its part of the ball scratch).
-constexpr uint32_t LCAPC = 128, LHM = 256;
+constexpr uint32_t LCAPC = 128;
 constexpr uint32_t BIG_CAPC = 1024, BIG_HM = 2048;
-constexpr uint32_t MEM_EMPTY = 0xFFFFFFFFu;
+
+template <class E>
+__device__ __forceinline__ constexpr E mem_empty() {
+    return ~(E)0;
+}
 
 // open addressing in a power-of-two table of hm entries, (t << 1 | kind) per entry
 __device__ __forceinline__ uint32_t mem_hash(uint32_t t, uint32_t hm) {
@@ -293,14 +347,14 @@ __device__ __forceinline__ uint32_t mem_hash(uint32_t t, uint32_t hm) {
 
 // kind of tetrahedron t in the set (0 cavity, 1 outer) or -1; a set in global memory is
 // read at device scope, past any vector L1 copy, since other lanes fill it by atomics
-template <bool GLOBAL>
-__device__ __forceinline__ int mem_find(uint32_t *mem, uint32_t hm, uint32_t t) {
+template <bool GLOBAL, class E>
+__device__ __forceinline__ int mem_find(E *mem, uint32_t hm, uint32_t t) {
     uint32_t h = mem_hash(t, hm);
     for (uint32_t probe = 0; probe < hm; ++probe) {
-        const uint32_t e =
+        const E e =
             GLOBAL ? __hip_atomic_load(&mem[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : mem[h];
-        if (e == MEM_EMPTY) return -1;
-        if ((e >> 1) == t) return (int)(e & 1u);
+        if (e == mem_empty<E>()) return -1;
+        if ((e >> 1) == (E)t) return (int)(e & 1u);
         h = (h + 1) & (hm - 1);
     }
     return -1;
@@ -308,16 +362,17 @@ __device__ __forceinline__ int mem_find(uint32_t *mem, uint32_t hm, uint32_t t) 
 
 // adds t with `kind`: 1 if this call added it (its entry is then mem[*at]), 0 if it was
 // there, -1 if the set is full
-__device__ __forceinline__ int mem_insert(uint32_t *mem, uint32_t hm, uint32_t t, uint32_t kind, uint32_t *at) {
+template <class E>
+__device__ __forceinline__ int mem_insert(E *mem, uint32_t hm, uint32_t t, uint32_t kind, uint32_t *at) {
     uint32_t h = mem_hash(t, hm);
-    const uint32_t e = (t << 1) | kind;
+    const E e = ((E)t << 1) | (E)kind;
     for (uint32_t probe = 0; probe < hm; ++probe) {
-        const uint32_t old = atomicCAS(&mem[h], MEM_EMPTY, e);
-        if (old == MEM_EMPTY) {
+        const E old = atomicCAS(&mem[h], mem_empty<E>(), e);
+        if (old == mem_empty<E>()) {
             *at = h;
             return 1;
         }
-        if ((old >> 1) == t) return 0;
+        if ((old >> 1) == (E)t) return 0;
         h = (h + 1) & (hm - 1);
     }
     return -1;
@@ -345,26 +400,34 @@ __device__ __forceinline__ void lane_fence() {
 // on an outside one, loses the attempt.  The attempt's own tetrahedra are tracked in the
 // set, so each is claimed and tested once.  GLOBAL keeps queue and set in global memory
 // (any capC).
-template <int GS, uint32_t CAPL, uint32_t HM, bool GLOBAL>
+//
+// FULL = false: filter-only predicates; an attempt meeting a sign the filter cannot decide
+// ends with ST_FULL and is listed for the FULL kernel.  DEFER: the kernel runs the listed
+// candidates (a.defer[0 .. *a.ndefer_ptr)) instead of the round's list, grid-stride.
+template <class K, int GS, uint32_t CAPL, uint32_t HM, bool GLOBAL, bool FULL, bool DEFER>
 __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
+    using code = typename K::code;
+    using E = typename K::set_t;
     constexpr uint32_t GPB = 256 / GS;  // insertions per 256-thread block
     constexpr uint32_t NP = GS / 4;     // cavity tetrahedra expanded per step
     // LDS queue entries: (slot of the tetrahedron's entry in the set << 2 | facet it was
     // entered through), 16 bits; the global queue holds (tetrahedron << 2 | facet)
     __shared__ uint16_t s_cav[GPB][GLOBAL ? 1 : CAPL];
-    __shared__ uint32_t s_mem[GPB][GLOBAL ? 1 : HM];
+    __shared__ E s_mem[GPB][GLOBAL ? 1 : HM];
+    typename K::Rec *const T = static_cast<typename K::Rec *>(a.T);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t gl = threadIdx.x & (GS - 1);
     const uint32_t gi = threadIdx.x / GS;
     const uint32_t gbase = lane & ~(uint32_t)(GS - 1);
     const unsigned long long gmask = GS == 64 ? ~0ull : (((1ull << (GS & 63)) - 1ull) << gbase);
     const unsigned long long below = gmask & ((1ull << lane) - 1ull);
-    const uint32_t i = blockIdx.x * GPB + gi;
-    const uint32_t ncand = *a.ncand_ptr;
+    const uint32_t ncand = DEFER ? *a.ndefer_ptr : *a.ncand_ptr;
     const uint32_t stride = a.stride;
     PredStats st;
     unsigned steps = 0, attempt = 0;
-    if (i < ncand) {
+    // one candidate per group; the deferred pass strides over its short list
+    for (uint32_t j = blockIdx.x * GPB + gi; j < ncand; j += DEFER ? gridDim.x * GPB : ncand) {
+        const uint32_t i = DEFER ? a.defer[j] : j;
         uint8_t status = ST_NONE;
         const uint32_t p = a.cand_pt[i];
         const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
@@ -388,35 +451,40 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
         // the learned scheduler predicts the anchor to be the closer start
         if (a.wbucket && tq != NONE && a.wbucket[p - a.vlo]) t = tq;
         if (t == NONE) t = cl->any_live;
-        uint4 w = a.T[t].v;
+        uint4 w = T[t].v;
         if (w.x == DEAD) {
             t = cl->any_live;
-            w = a.T[t].v;
+            w = T[t].v;
         }
         if (w.w == GHOST) {
-            t = a.T[t].n.w >> 2;
-            w = a.T[t].v;
+            t = code_slot(comp(T[t].n, 3));
+            w = T[t].v;
         }
         // Walk: lane j < 4 tests facet j
         int entry = -1;
         bool in_ghost = false;
         const int jl = (int)(gl & 3u);
+        unsigned ws = 0;  // steps of this walk
         for (;;) {
             const P3 q0 = vpos(a.V, w.x), q1 = vpos(a.V, w.y), q2 = vpos(a.V, w.z), q3 = vpos(a.V, w.w);
-            const uint4 nn = a.T[t].n;
+            const typename K::code4 nn = T[t].n;
             int o = 1;
             if (gl < 4 && jl != entry)
-                o = orient3d(jl == 0 ? P : q0, jl == 1 ? P : q1, jl == 2 ? P : q2, jl == 3 ? P : q3, st);
+                o = cav_orient<FULL>(jl == 0 ? P : q0, jl == 1 ? P : q1, jl == 2 ? P : q2, jl == 3 ? P : q3, st);
+            if (!FULL && (__ballot(o == UNDECIDED) & gmask)) {
+                status = ST_FULL;
+                break;
+            }
             const unsigned bits = (unsigned)((__ballot(o < 0) & gmask) >> gbase) & 0xFu;
             if (!bits) break;
-            const unsigned rot = (p + steps) & 3u;
+            const unsigned rot = (p + ws) & 3u;
             const unsigned rb = ((bits >> rot) | (bits << (4u - rot))) & 0xFu;
             const int moved = (int)(((unsigned)__ffs(rb) - 1u + rot) & 3u);
-            const uint32_t code = comp(nn, moved);
-            t = code >> 2;
-            entry = (int)(code & 3u);
-            w = a.T[t].v;
-            if (++steps > WALK_LIMIT) {
+            const code cd = comp(nn, moved);
+            t = code_slot(cd);
+            entry = code_facet(cd);
+            w = T[t].v;
+            if (++ws > WALK_LIMIT) {
                 status = ST_ERROR;
                 break;
             }
@@ -425,6 +493,7 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 break;
             }
         }
+        steps += ws;
         if (status == ST_NONE && !in_ghost) {
             // p equal to a vertex of its containing tetrahedron: lane j < 4 compares vertex j
             bool same = false;
@@ -437,17 +506,17 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
         uint32_t ncav = 0, nbnd = 0;
         const uint32_t capL = GLOBAL ? a.capC : min(a.capC, CAPL), capF = a.capF;
         uint32_t *bnd = a.bnd + (size_t)i * a.capF;
-        uint32_t *outc = a.outc + (size_t)i * a.capF;
-        uint32_t *cavg = a.cav + (size_t)i * a.capC;
+        code *outc = static_cast<code *>(a.outc) + (size_t)i * a.capF;
+        code *cavg = static_cast<code *>(a.cav) + (size_t)i * a.capC;
         uint16_t *cavl = s_cav[gi];
-        // the set in global memory: hms (a power of two, at most 4 capC) words of the
-        // candidate's part of the ball scratch, which the ball kernel uses only later
+        // the set in global memory: hms entries (a power of two, at most 16 capC bytes) of
+        // the candidate's part of the ball scratch, which the ball kernel uses only later
         const uint32_t hms = GLOBAL ? a.hmg : HM;
-        uint32_t *mem = GLOBAL ? reinterpret_cast<uint32_t *>(a.scr_v + (size_t)i * a.capC) : s_mem[gi];
+        E *mem = GLOBAL ? reinterpret_cast<E *>(a.scr_v + (size_t)i * a.capC) : s_mem[gi];
         if (status == ST_NONE) {
             // Cavity.  Step k expands cavity tetrahedra k0 .. k0 + NP - 1, lane (slot, facet)
             // = (gl / 4, gl % 4).
-            for (uint32_t h = gl; h < hms; h += GS) mem[h] = MEM_EMPTY;
+            for (uint32_t h = gl; h < hms; h += GS) mem[h] = mem_empty<E>();
             lane_fence<GLOBAL>();
             // each step's claims are checked at the next step (or after the last), once that
             // step's loads are in flight, so that the atomics' latency overlaps them; the
@@ -455,10 +524,10 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
             bool pneed = gl == 0, pinside = true;
             unsigned long long po1 = ~0ull;
             if (gl == 0) {
-                po1 = atomicMin(&a.T[t].claim, S);
+                po1 = atomicMin(&T[t].claim, S);
                 uint32_t at = 0;
                 mem_insert(mem, hms, t, 0u, &at);
-                if (GLOBAL) cavg[0] = t << 2;
+                if (GLOBAL) cavg[0] = make_code<K>(t, 0u);
                 else cavl[0] = (uint16_t)(at << 2);
             }
             ncav = 1;
@@ -468,22 +537,23 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 const uint32_t slot = k0 + (gl >> 2);
                 const int f = jl;
                 const bool lv = slot < k0 + nproc;
-                uint32_t code = 0u;
+                code cd = 0u;
                 if (lv) {
                     if (GLOBAL) {
-                        code = cavg[slot];
+                        cd = cavg[slot];
                     } else {
                         const uint32_t q = cavl[slot];
-                        code = ((mem[q >> 2] >> 1) << 2) | (q & 3u);
+                        cd = make_code<K>((uint32_t)(mem[q >> 2] >> 1), q & 3u);
                     }
                 }
-                const uint32_t c = code >> 2;
-                const int pf = slot == 0 ? -1 : (int)(code & 3u);
+                const uint32_t c = code_slot(cd);
+                const int pf = slot == 0 ? -1 : code_facet(cd);
                 const bool act = lv && f != pf;
-                uint4 cv = make_uint4(0u, 0u, 0u, 0u), cn = cv, uw = cv;
+                uint4 cv = make_uint4(0u, 0u, 0u, 0u), uw = cv;
+                typename K::code4 cn{};
                 if (lv) {
-                    cv = a.T[c].v;
-                    cn = a.T[c].n;
+                    cv = T[c].v;
+                    cn = T[c].n;
                 }
                 // the previous step's claims: a lower claim on a tetrahedron of this cavity,
                 // or a lower cavity claim (even) on one outside it, loses the attempt
@@ -491,15 +561,15 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                     status = ST_CONFLICT;
                     break;
                 }
-                const uint32_t ncode = comp(cn, f);
-                const uint32_t u = ncode >> 2;
+                const code ncode = comp(cn, f);
+                const uint32_t u = code_slot(ncode);
                 const int kind = act ? mem_find<GLOBAL>(mem, hms, u) : -1;  // 0: in this cavity, 1: outside it
                 const bool need = act && kind < 0;
-                if (need) uw = a.T[u].v;
-                bool inside = false;
+                if (need) uw = T[u].v;
+                bool inside = false, undecided = false;
                 if (need) {
                     const bool cghost = cv.w == GHOST;
-                    const uint32_t apex = comp(uw, (int)(ncode & 3u));
+                    const uint32_t apex = comp(uw, code_facet(ncode));
                     if (!cghost && apex != GHOST) {
                         // u = facet f of c + apex; c with vertex f replaced by the apex and
                         // two entries swapped is positively oriented
@@ -511,24 +581,37 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                         uint32_t r2[4];
 #pragma unroll
                         for (int m = 0; m < 4; ++m) r2[m] = m == sa ? rid[sb] : (m == sb ? rid[sa] : rid[m]);
-                        inside = insphere_perturbed(vpos(a.V, r2[0]), vpos(a.V, r2[1]), vpos(a.V, r2[2]),
-                                                    vpos(a.V, r2[3]), P,
-                                                    [&](int kk) { return kk < 4 ? a.V[r2[kk]].idx : pv.idx; },
-                                                    st) < 0;
+                        const int si = cav_insphere<FULL>(vpos(a.V, r2[0]), vpos(a.V, r2[1]), vpos(a.V, r2[2]),
+                                                          vpos(a.V, r2[3]), P,
+                                                          [&](int kk) { return kk < 4 ? a.V[r2[kk]].idx : pv.idx; },
+                                                          st);
+                        inside = si < 0;
+                        undecided = si == UNDECIDED;
                     } else if (!cghost) {
                         // u is the ghost beyond facet f of the finite cavity tetrahedron c:
                         // inside iff p is beyond the facet, or on it (then c decides: inside)
                         const P3 c0 = vpos(a.V, cv.x), c1 = vpos(a.V, cv.y), c2 = vpos(a.V, cv.z),
                                  c3 = vpos(a.V, cv.w);
-                        inside = orient3d(f == 0 ? P : c0, f == 1 ? P : c1, f == 2 ? P : c2, f == 3 ? P : c3, st) <= 0;
+                        const int so = cav_orient<FULL>(f == 0 ? P : c0, f == 1 ? P : c1, f == 2 ? P : c2,
+                                                        f == 3 ? P : c3, st);
+                        inside = so <= 0;
+                        undecided = so == UNDECIDED;
                     } else {
-                        inside = tet_inside(a, u, P, pv.idx, st);
+                        const int si = tet_inside<K, FULL>(T, a.V, u, P, pv.idx, st);
+                        inside = si < 0;
+                        undecided = si == UNDECIDED;
                     }
+                }
+                // a sign the filter could not decide: no claim on this step, the FULL kernel
+                // runs the attempt again
+                if (!FULL && (__ballot(undecided) & gmask)) {
+                    status = ST_FULL;
+                    break;
                 }
                 // the one claim of u: S if inside, S + 1 if outside (a tetrahedron reached
                 // through several facets in this step gets the same claim from each lane)
                 unsigned long long o1 = ~0ull;
-                if (need) o1 = atomicMin(&a.T[u].claim, inside ? S : S + 1);
+                if (need) o1 = atomicMin(&T[u].claim, inside ? S : S + 1);
                 // record u in the set; a tetrahedron reached through several facets in this
                 // step is queued (if inside) by the lane that records it
                 int ins = 0;
@@ -546,7 +629,7 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 if (first_in) {
                     const uint32_t pos = ncav + (uint32_t)__popcll(mi & below);
                     if (GLOBAL) cavg[pos] = ncode;
-                    else cavl[pos] = (uint16_t)((at << 2) | (ncode & 3u));
+                    else cavl[pos] = (uint16_t)((at << 2) | (uint32_t)code_facet(ncode));
                 }
                 if (outside) {
                     // boundary facet: (local index of c) << 2 | f, and the outer tetrahedron
@@ -568,17 +651,17 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
         if (!GLOBAL && status == ST_CAND)
             for (uint32_t k = gl; k < ncav; k += GS) {
                 const uint32_t q = cavl[k];
-                cavg[k] = ((mem[q >> 2] >> 1) << 2) | (q & 3u);
+                cavg[k] = make_code<K>((uint32_t)(mem[q >> 2] >> 1), q & 3u);
             }
         if (gl == 0) {
             a.status[i] = status;
             a.cnt[i] = ncav;
             a.cnt[stride + i] = nbnd;
-            attempt = 1;
-        } else {
-            steps = 0;
+            if (!FULL && status == ST_FULL) a.defer[atomicAdd(a.ndefer_ptr, 1u)] = i;
+            else attempt++;  // a deferred attempt is counted by the FULL kernel
         }
     }
+    if (gl != 0) steps = 0;
     add_stat(a.stat, STAT_ATTEMPTS, attempt);
     add_stat(a.stat, STAT_WALK, steps);
     add_stat(a.stat, STAT_ORIENT, st.orient);
@@ -606,7 +689,6 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
 // facets, and the two new tetrahedra on them are the siblings.  They are paired through a
 // hash table of edges in LDS.  Balls too large for the table pair siblings by pivoting
 // around the edge through copies of the cavity tetrahedra instead.
-constexpr uint32_t LOC_BOUNDARY = 0x80000000u;
 constexpr uint32_t HT = 128;             // edge table entries per candidate
 constexpr uint32_t HT_MAX_FACETS = 64;   // balls up to this size use the table (load <= 3/4)
 constexpr unsigned long long HT_EMPTY = ~0ull;
@@ -624,11 +706,18 @@ __device__ __forceinline__ uint32_t edge_hash(unsigned long long key) {
     return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 57);  // 7 bits: HT = 128
 }
 
-template <int GL, int BS>
+template <class K, int GL, int BS>
 __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
+    using code = typename K::code;
+    constexpr code LOC_BOUNDARY = (code)1 << (8 * sizeof(code) - 1);
     constexpr uint32_t GPB = BS / GL;
+    // edge table: key = the edge's two vertices; value = (boundary facet b << 2 | facet q of
+    // b's new tetrahedron) for the two new tetrahedra on the edge; the slot of b's new
+    // tetrahedron is in s_slot[b] (b < HT_MAX_FACETS on this path)
     __shared__ unsigned long long s_key[GPB][HT];
-    __shared__ uint32_t s_val[GPB][HT][2];
+    __shared__ uint16_t s_val[GPB][HT][2];
+    __shared__ uint32_t s_slot[GPB][HT_MAX_FACETS];
+    typename K::Rec *const T = static_cast<typename K::Rec *>(a.T);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t gl = threadIdx.x % GL;
     const uint32_t gi = threadIdx.x / GL;
@@ -641,11 +730,11 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
     const bool cand = i < ncand && a.status[i] == ST_CAND;
     uint32_t p = 0, nc = 0, nb = 0;
     unsigned long long S = 0;
-    const uint32_t *cavl = a.cav + (size_t)i * capC;
+    const code *cavl = static_cast<const code *>(a.cav) + (size_t)i * capC;
     const uint32_t *bl = a.bnd + (size_t)i * capF;
-    uint32_t *ol = a.outc + (size_t)i * capF;
+    code *ol = static_cast<code *>(a.outc) + (size_t)i * capF;
     uint4 *sv = a.scr_v + (size_t)i * capC;
-    uint4 *sn = a.scr_n + (size_t)i * capC;
+    typename K::code4 *sn = static_cast<typename K::code4 *>(a.scr_n) + (size_t)i * capC;
     bool ok = true;
     if (cand) {
         p = a.cand_pt[i];
@@ -655,8 +744,8 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
         // winner test
         // cavity tetrahedra: no lower claim; outer tetrahedra: the lowest claim is an outer
         // one (any lower attempt with it in its cavity then loses on that claim)
-        for (uint32_t k = gl; k < nc; k += GL) ok &= a.T[cavl[k] >> 2].claim == S;
-        for (uint32_t k = gl; k < nb; k += GL) ok &= (a.T[ol[k] >> 2].claim & 1ull) != 0;
+        for (uint32_t k = gl; k < nc; k += GL) ok &= T[code_slot(cavl[k])].claim == S;
+        for (uint32_t k = gl; k < nb; k += GL) ok &= (T[code_slot(ol[k])].claim & 1ull) != 0;
     }
     const bool win = cand && (__ballot(!ok) & gmask) == 0;
     // slot reservation by each winner's first lane, one atomic per block: the F - C extra
@@ -664,27 +753,31 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
     // the rest are fresh pool slots from tet_count on); C - F surplus cavity slots are freed
     const bool leader = win && gl == 0;
     const uint32_t need = leader && nb > nc ? nb - nc : 0u;
-    const uint32_t u0 = block_reserve<BS / 64>(need, &a.ctr->fl_take, &s_val[0][0][0]);
+    const uint32_t u0 = block_reserve<BS / 64>(need, &a.ctr->fl_take, &s_slot[0][0]);
     const uint32_t fln = a.ctr->fl_n, tc0 = a.ctr->tet_count;
-    const bool full = need && u0 + need > fln && tc0 + (u0 + need - fln) > a.tcap;
+    const bool full = need && u0 + need > fln && (uint64_t)tc0 + (u0 + need - fln) > a.tcap;
     if (full) {
         // pool full: give the units back (pool slots inside the pool are marked free) and
         // retry next round after the host has grown the pool
         uint32_t give = 0;
         for (uint32_t k = 0; k < need; ++k) {
             const uint32_t u = u0 + k;
-            if (u < fln || tc0 + (u - fln) < a.tcap) ++give;
+            if (u < fln || (uint64_t)tc0 + (u - fln) < a.tcap) ++give;
         }
         const uint32_t g0 = atomicAdd(&a.ctr->fl_next, give);
         uint32_t q = 0;
         for (uint32_t k = 0; k < need; ++k) {
             const uint32_t u = u0 + k;
+            uint32_t slot = NONE;
             if (u < fln) {
-                a.fl_next[g0 + q++] = a.fl_cur[u];
-            } else if (tc0 + (u - fln) < a.tcap) {
-                a.T[tc0 + (u - fln)].v.x = DEAD;
-                a.fl_next[g0 + q++] = tc0 + (u - fln);
+                slot = a.fl_cur[u];
+            } else if ((uint64_t)tc0 + (u - fln) < a.tcap) {
+                slot = tc0 + (u - fln);
+                T[slot].v.x = DEAD;
             }
+            // a slot that does not fit the free list stays free and unused (k_roll counts it)
+            if (slot != NONE && (uint64_t)g0 + q < a.flcap) a.fl_next[g0 + q] = slot;
+            if (slot != NONE) ++q;
         }
         atomicOr(&a.ctr->error, ERR_POOL);
     }
@@ -698,11 +791,11 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
         // A: copies of the cavity tetrahedra (vertices; for the pivot also the neighbours and
         // the local index in the spare word); the edge table is cleared
         for (uint32_t k = gl; k < nc; k += GL) {
-            const uint32_t c = cavl[k] >> 2;
-            sv[k] = a.T[c].v;
+            const uint32_t c = code_slot(cavl[k]);
+            sv[k] = T[c].v;
             if (!table) {
-                sn[k] = a.T[c].n;
-                a.T[c].spare[0] = k;
+                sn[k] = T[c].n;
+                T[c].spare[0] = k;
             }
         }
         if (table)
@@ -713,10 +806,10 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
             for (uint32_t task = gl; task < 4 * nc; task += GL) {
                 const uint32_t k = task >> 2;
                 const int f = (int)(task & 3u);
-                const uint32_t code = comp(sn[k], f);
-                const uint32_t nt = code >> 2;
-                if (a.T[nt].claim == S)  // only this winner's cavity tetrahedra hold S
-                    reinterpret_cast<uint32_t *>(&sn[k])[f] = ((uint32_t)a.T[nt].spare[0] << 2) | (code & 3u);
+                const code cd = comp(sn[k], f);
+                const uint32_t nt = code_slot(cd);
+                if (T[nt].claim == S)  // only this winner's cavity tetrahedra hold S
+                    reinterpret_cast<code *>(&sn[k])[f] = make_code<K>((uint32_t)T[nt].spare[0], code_facet(cd));
             }
             group_fence();
         }
@@ -724,7 +817,7 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
         for (uint32_t b = gl; b < nb; b += GL) {
             uint32_t slot;
             if (b < nc) {
-                slot = cavl[b] >> 2;
+                slot = code_slot(cavl[b]);
             } else {
                 const uint32_t u = g_u0 + (b - nc);
                 slot = u < fln ? a.fl_cur[u] : tc0 + (u - fln);
@@ -732,14 +825,14 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
             const uint32_t bc = bl[b];  // local index of the cavity tetrahedron << 2 | facet
             const uint32_t kb = bc >> 2;
             const int f = (int)(bc & 3u);
-            const uint32_t oc = ol[b];
+            const code oc = ol[b];
             const uint4 cw = sv[kb];
             uint32_t wv[4] = {cw.x, cw.y, cw.z, cw.w};
             wv[f] = p;
-            a.T[slot].v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
-            const uint32_t me = (slot << 2) | (uint32_t)f;
-            nref(a.T, slot, f) = oc;           // facet opposite p: the outer tetrahedron
-            nref(a.T, oc >> 2, oc & 3u) = me;  // and back
+            T[slot].v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+            const code me = make_code<K>(slot, (uint32_t)f);
+            nref(T, slot, f) = oc;                            // facet opposite p: the outer tetrahedron
+            nref(T, code_slot(oc), code_facet(oc)) = me;      // and back
             ol[b] = me;
             // vertex hints: the cavity boundary's vertices from every new tetrahedron on them,
             // the new point (vertex f of each) from the first only
@@ -763,24 +856,25 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
                     for (uint32_t probe = 0; probe < HT && !placed; ++probe) {
                         const unsigned long long old = atomicCAS(&s_key[gi][h], HT_EMPTY, key);
                         if (old == HT_EMPTY || old == key) {
-                            s_val[gi][h][old == HT_EMPTY ? 0 : 1] = (slot << 2) | (uint32_t)q;
+                            s_val[gi][h][old == HT_EMPTY ? 0 : 1] = (uint16_t)((b << 2) | (uint32_t)q);
                             placed = true;
                         }
                         h = (h + 1) & (HT - 1);
                     }
                     if (!placed) atomicOr(&a.ctr->error, ERR_WALK);
                 }
+                s_slot[gi][b] = slot;
             } else {
-                reinterpret_cast<uint32_t *>(&sn[kb])[f] = LOC_BOUNDARY | b;
+                reinterpret_cast<code *>(&sn[kb])[f] = LOC_BOUNDARY | (code)b;
             }
         }
         group_fence();
         // D: the three siblings of each new tetrahedron
         if (table) {
             for (uint32_t b = gl; b < nb; b += GL) {
-                const uint32_t me = ol[b];
-                const uint32_t slot = me >> 2;
-                const int f = (int)(me & 3u);
+                const code me = ol[b];
+                const uint32_t slot = code_slot(me);
+                const int f = code_facet(me);
                 const uint4 cw = sv[bl[b] >> 2];
                 uint32_t wv[4] = {cw.x, cw.y, cw.z, cw.w};
                 wv[f] = p;
@@ -794,7 +888,7 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
                         }
                     const unsigned long long key = e0 < e1 ? ((unsigned long long)e0 << 32) | e1
                                                            : ((unsigned long long)e1 << 32) | e0;
-                    const uint32_t mine = (slot << 2) | (uint32_t)q;
+                    const uint32_t mine = (b << 2) | (uint32_t)q;
                     uint32_t h = edge_hash(key), res = NONE;
                     for (uint32_t probe = 0; probe < HT; ++probe) {
                         if (s_key[gi][h] == key) {
@@ -805,15 +899,15 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
                         h = (h + 1) & (HT - 1);
                     }
                     if (res == NONE) atomicOr(&a.ctr->error, ERR_WALK);
-                    nref(a.T, slot, q) = res;
+                    else nref(T, slot, q) = make_code<K>(s_slot[gi][res >> 2], res & 3u);
                 }
             }
         } else {
             for (uint32_t task = gl; task < 3 * nb; task += GL) {
                 const uint32_t b = task / 3, qi = task - 3 * b;
-                const uint32_t me = ol[b];
-                const uint32_t slot = me >> 2;
-                const int pf = (int)(me & 3u);
+                const code me = ol[b];
+                const uint32_t slot = code_slot(me);
+                const int pf = code_facet(me);
                 const int q = (pf + 1 + (int)qi) & 3;  // the three facets through p
                 const uint32_t kb = bl[b] >> 2;
                 const uint4 cw = sv[kb];
@@ -824,7 +918,7 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
                     if (r != q && r != pf) e[ne++] = c4[r];
                 uint32_t k = kb;
                 int f = pf;
-                uint32_t res = 0;
+                code res = 0;
                 bool found = false;
                 for (uint32_t guard = 0; guard <= nc + 1; ++guard) {
                     const uint4 cv = sv[k];
@@ -833,20 +927,20 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
                     for (int m = 0; m < 4; ++m)
                         if (m != f && v4[m] != e[0] && v4[m] != e[1]) xpos = m;
                     if (xpos < 0) break;
-                    const uint32_t lc = comp(sn[k], xpos);
+                    const code lc = comp(sn[k], xpos);
                     if (lc & LOC_BOUNDARY) {
                         // boundary facet (k, xpos): its new tetrahedron has p at xpos, and
                         // the facet through p, e0, e1 is opposite its vertex f
-                        res = (ol[lc & ~LOC_BOUNDARY] & ~3u) | (uint32_t)f;
+                        res = make_code<K>(code_slot(ol[(size_t)(lc & ~LOC_BOUNDARY)]), (uint32_t)f);
                         found = true;
                         break;
                     }
-                    k = lc >> 2;
-                    f = (int)(lc & 3u);
+                    k = code_slot(lc);
+                    f = code_facet(lc);
                     if (k >= nc) break;
                 }
                 if (!found) atomicOr(&a.ctr->error, ERR_WALK);
-                nref(a.T, slot, q) = res;
+                else nref(T, slot, q) = res;
             }
         }
         // E: cavity slots beyond the ball's size are freed.  The cloud's known live
@@ -857,10 +951,11 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
             Cloud *cl = &a.clouds[a.V[p].idx >> 32];
             const uint32_t live = cl->any_live;
             for (uint32_t k = nb + gl; k < nc; k += GL) {
-                const uint32_t c = cavl[k] >> 2;
-                a.T[c].v.x = DEAD;
-                a.fl_next[g_fb + (k - nb)] = c;
-                if (c == live) cl->any_live = cavl[0] >> 2;
+                const uint32_t c = code_slot(cavl[k]);
+                T[c].v.x = DEAD;
+                // a slot that does not fit the free list stays free and unused (k_roll counts it)
+                if ((uint64_t)g_fb + (k - nb) < a.flcap) a.fl_next[g_fb + (k - nb)] = c;
+                if (c == live) cl->any_live = code_slot(cavl[0]);
             }
         }
         if (gl == 0) {
@@ -902,16 +997,18 @@ __global__ __launch_bounds__(FILL_BLOCK) void k_compact(RoundArgs a) {
     if (bad) atomicOr(&a.ctr->error, ERR_WALK);
 }
 
-// carry the unused part of this round's free list behind the slots freed this round
+// carry the unused part of this round's free list behind the slots freed this round (as far
+// as the list holds them; k_roll counts the rest)
 __global__ void k_freelist_carry(RoundArgs a) {
-    const uint32_t fln = a.ctr->fl_n, take = a.ctr->fl_take, nxt = a.ctr->fl_next;
+    const uint32_t fln = a.ctr->fl_n, take = a.ctr->fl_take, nxt = min(a.ctr->fl_next, a.flcap);
     if (take >= fln) return;
-    const uint32_t left = fln - take;
+    const uint32_t left = min(fln - take, a.flcap - nxt);
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < left; k += gridDim.x * blockDim.x)
         a.fl_next[nxt + k] = a.fl_cur[take + k];
 }
 
-__global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, const unsigned long long *stat) {
+__global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, uint32_t flcap,
+                       const unsigned long long *stat) {
     const uint32_t t = threadIdx.x;
     if (t < NSTAT) {
         unsigned long long sum = 0;
@@ -929,70 +1026,111 @@ __global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, const unsign
         ctr->tet_count = tc > tcap ? tcap : (uint32_t)tc;
     }
     const uint32_t left = take < fln ? fln - take : 0u;
-    ctr->fl_n = ctr->fl_next + left;
+    const uint32_t nxt = min(ctr->fl_next, flcap), keep = min(left, flcap - nxt);
+    ctr->dropped += (ctr->fl_next - nxt) + (left - keep);
+    ctr->deferred += ctr->ndefer;
+    ctr->ndefer = 0;
+    ctr->fl_n = nxt + keep;
     ctr->fl_take = 0;
     ctr->fl_next = 0;
     *consumed = 0;  // the list this round read from is empty now
 }
 
-hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, hipStream_t s, hipEvent_t *ev) {
-    if (max_cand == 0) return hipSuccess;
-    const unsigned nb = (max_cand + 255) / 256;
+constexpr uint32_t DEFER_BLOCKS = 512;  // grid of the exact-predicate pass (grid-stride)
+
+template <class K>
+static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, hipStream_t s,
+                                 hipEvent_t *ev) {
+    constexpr uint32_t LHM = K::LHM;
     if (ev) hipEventRecord(ev[0], s);
+    // regular rounds: the filter-only kernel over the round's list, then the exact kernel over
+    // the attempts it handed on (a short grid-stride pass; nothing to do for most rounds);
+    // rounds for large cavities use exact predicates throughout
+    const uint32_t dgrid = std::min<uint32_t>((max_cand + 31) / 32, DEFER_BLOCKS);
     if (a.capC > BIG_CAPC) {
-        // the set takes hmg words of the candidate's 4 capC words of ball scratch
-        if (a.hmg < 4096 || (a.hmg & (a.hmg - 1)) || a.hmg > 4ull * a.capC) return hipErrorInvalidValue;
-        k_cavity_g<64, 1, 1, true><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
+        // the set takes hmg entries of the candidate's 16 capC bytes of ball scratch
+        if (a.hmg < 4096 || (a.hmg & (a.hmg - 1)) || (uint64_t)a.hmg * sizeof(typename K::set_t) > 16ull * a.capC)
+            return hipErrorInvalidValue;
+        k_cavity_g<K, 64, 1, 1, true, true, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
     } else if (a.capC > LCAPC) {
-        k_cavity_g<64, BIG_CAPC, BIG_HM, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
+        k_cavity_g<K, 64, BIG_CAPC, BIG_HM, false, true, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
     } else if (lanes == 4) {
-        k_cavity_g<4, LCAPC, LHM, false><<<(max_cand + 63) / 64, 256, 0, s>>>(a);
+        k_cavity_g<K, 4, LCAPC, LHM, false, false, false><<<(max_cand + 63) / 64, 256, 0, s>>>(a);
+        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 8) {
-        k_cavity_g<8, LCAPC, LHM, false><<<(max_cand + 31) / 32, 256, 0, s>>>(a);
+        k_cavity_g<K, 8, LCAPC, LHM, false, false, false><<<(max_cand + 31) / 32, 256, 0, s>>>(a);
+        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 64) {
-        k_cavity_g<64, LCAPC, LHM, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
+        k_cavity_g<K, 64, LCAPC, LHM, false, false, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
+        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else {
-        k_cavity_g<16, LCAPC, LHM, false><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
+        k_cavity_g<K, 16, LCAPC, LHM, false, false, false><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
+        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     }
     if (ev) hipEventRecord(ev[1], s);
-    k_ball<16, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 16 - 1) / (BALL_BLOCK / 16), BALL_BLOCK, 0, s>>>(a);
+    k_ball<K, 16, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 16 - 1) / (BALL_BLOCK / 16), BALL_BLOCK, 0, s>>>(a);
     if (ev) hipEventRecord(ev[2], s);
     return hipGetLastError();
+}
+
+hipError_t launch_round(const RoundArgs &a, bool wide, uint32_t max_cand, uint32_t lanes, hipStream_t s,
+                        hipEvent_t *ev) {
+    if (max_cand == 0) return hipSuccess;
+    return wide ? launch_round_k<Wide>(a, max_cand, lanes, s, ev) : launch_round_k<Narrow>(a, max_cand, lanes, s, ev);
 }
 
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s) {
     if (max_cand) k_compact<<<(max_cand + FILL_BLOCK - 1) / FILL_BLOCK, FILL_BLOCK, 0, s>>>(a);
     k_freelist_carry<<<256, 256, 0, s>>>(a);
-    k_roll<<<1, 64, 0, s>>>(a.ctr, const_cast<uint32_t *>(a.ncand_ptr), a.tcap, a.stat);
+    k_roll<<<1, 64, 0, s>>>(a.ctr, const_cast<uint32_t *>(a.ncand_ptr), a.tcap, a.flcap, a.stat);
     return hipGetLastError();
 }
 
 // Claim words back to the empty value (above every stamp), for the round after the round
 // counter's low 32 bits wrap.  A fill kernel rather than a strided memset.
-__global__ void k_reset_claims(Tet *__restrict__ T, uint32_t tcap) {
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < tcap; t += gridDim.x * blockDim.x)
+template <class R>
+__global__ void k_reset_claims(R *__restrict__ T, uint32_t tcap) {
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < tcap; t += (uint64_t)gridDim.x * blockDim.x)
         T[t].claim = ~0ull;
 }
 
-hipError_t launch_reset_claims(Tet *T, uint32_t tcap, hipStream_t s) {
+hipError_t launch_reset_claims(void *T, bool wide, uint32_t tcap, hipStream_t s) {
     if (tcap == 0) return hipSuccess;
-    k_reset_claims<<<2048, 256, 0, s>>>(T, tcap);
+    if (wide) k_reset_claims<<<2048, 256, 0, s>>>((TetW *)T, tcap);
+    else k_reset_claims<<<2048, 256, 0, s>>>((Tet *)T, tcap);
+    return hipGetLastError();
+}
+
+// A pool with 32-bit codes copied into one with 64-bit codes (the code 4 t + f is the same
+// number in either width).
+__global__ void k_widen(const Tet *__restrict__ src, TetW *__restrict__ dst, uint32_t count) {
+    const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const Tet r = src[t];
+    TetW w;
+    w.v = r.v;
+    w.n.c[0] = r.n.x;
+    w.n.c[1] = r.n.y;
+    w.n.c[2] = r.n.z;
+    w.n.c[3] = r.n.w;
+    w.claim = r.claim;
+    w.spare[0] = r.spare[0];
+    dst[t] = w;
+}
+
+hipError_t launch_widen(const void *src, void *dst, uint32_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    k_widen<<<(uint32_t)(((uint64_t)count + 255) / 256), 256, 0, s>>>((const Tet *)src, (TetW *)dst, count);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ output
 
-__global__ void k_out_flags(const Tet *__restrict__ T, uint32_t count, uint32_t *__restrict__ flags) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count) return;
-    const uint4 w = T[t].v;
-    flags[t] = (w.x != DEAD && w.w != GHOST) ? 1u : 0u;
-}
-
 // Per-cloud output.  The live finite tetrahedra are sorted by the cloud of their vertices
 // (keys: cloud, or nclouds for ghosts and free slots); cloud c owns sorted positions
 // [toff[c], toff[c + 1]); map[t] is the sorted position of tetrahedron t.
-__global__ void k_tet_cloud(const Tet *__restrict__ T, const Vert *__restrict__ V, uint32_t count, uint32_t nclouds,
+template <class R>
+__global__ void k_tet_cloud(const R *__restrict__ T, const Vert *__restrict__ V, uint32_t count, uint32_t nclouds,
                             unsigned long long *__restrict__ keys, uint32_t *__restrict__ vals) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
@@ -1014,7 +1152,8 @@ __global__ void k_tet_map(const uint32_t *__restrict__ sorted, uint32_t nlive, u
     if (j < nlive) map[sorted[j]] = j;
 }
 
-__global__ void k_output_cloud(const Tet *__restrict__ T, const Vert *__restrict__ V, const uint32_t *__restrict__ sorted,
+template <class R>
+__global__ void k_output_cloud(const R *__restrict__ T, const Vert *__restrict__ V, const uint32_t *__restrict__ sorted,
                                const uint32_t *__restrict__ map, uint32_t tb, uint32_t te, uint64_t vbase,
                                uint32_t *__restrict__ tets, int64_t *__restrict__ nbrs) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1026,87 +1165,147 @@ __global__ void k_output_cloud(const Tet *__restrict__ T, const Vert *__restrict
         for (int k = 0; k < 4; ++k) tets[4 * (size_t)j + k] = (uint32_t)((uint32_t)V[wv[k]].idx - vbase);
     }
     if (nbrs) {
-        const uint4 nn = T[t].n;
-        const uint32_t nv[4] = {nn.x, nn.y, nn.z, nn.w};
+        const auto nn = T[t].n;
         for (int k = 0; k < 4; ++k) {
-            const uint32_t nt = nv[k] >> 2;
+            const uint32_t nt = code_slot(comp(nn, k));
             nbrs[4 * (size_t)j + k] = T[nt].v.w == GHOST ? -1 : (int64_t)map[nt] - (int64_t)tb;
         }
     }
 }
 
-hipError_t launch_tet_cloud(const Tet *T, const Vert *V, uint32_t count, uint32_t nclouds, unsigned long long *keys,
-                            uint32_t *vals, hipStream_t s) {
+hipError_t launch_tet_cloud(const void *T, bool wide, const Vert *V, uint32_t count, uint32_t nclouds,
+                            unsigned long long *keys, uint32_t *vals, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    k_tet_cloud<<<(count + 255) / 256, 256, 0, s>>>(T, V, count, nclouds, keys, vals);
+    if (wide) k_tet_cloud<<<(uint32_t)(((uint64_t)count + 255) / 256), 256, 0, s>>>((const TetW *)T, V, count, nclouds, keys, vals);
+    else k_tet_cloud<<<(uint32_t)(((uint64_t)count + 255) / 256), 256, 0, s>>>((const Tet *)T, V, count, nclouds, keys, vals);
     return hipGetLastError();
 }
 
 hipError_t launch_seg_bounds(const unsigned long long *keys, uint32_t count, uint32_t nclouds, uint32_t *toff,
                              hipStream_t s) {
     if (count == 0) return hipSuccess;
-    k_seg_bounds<<<(count + 255) / 256, 256, 0, s>>>(keys, count, nclouds, toff);
+    k_seg_bounds<<<(uint32_t)(((uint64_t)count + 255) / 256), 256, 0, s>>>(keys, count, nclouds, toff);
     return hipGetLastError();
 }
 
 hipError_t launch_tet_map(const uint32_t *sorted, uint32_t nlive, uint32_t *map, hipStream_t s) {
     if (nlive == 0) return hipSuccess;
-    k_tet_map<<<(nlive + 255) / 256, 256, 0, s>>>(sorted, nlive, map);
+    k_tet_map<<<(uint32_t)(((uint64_t)nlive + 255) / 256), 256, 0, s>>>(sorted, nlive, map);
     return hipGetLastError();
 }
 
-hipError_t launch_output_cloud(const Tet *T, const Vert *V, const uint32_t *sorted, const uint32_t *map, uint32_t tb,
-                               uint32_t te, uint64_t vbase, uint32_t *tets, int64_t *nbrs, hipStream_t s) {
+hipError_t launch_output_cloud(const void *T, bool wide, const Vert *V, const uint32_t *sorted, const uint32_t *map,
+                               uint32_t tb, uint32_t te, uint64_t vbase, uint32_t *tets, int64_t *nbrs, hipStream_t s) {
     if (te <= tb) return hipSuccess;
-    k_output_cloud<<<(te - tb + 255) / 256, 256, 0, s>>>(T, V, sorted, map, tb, te, vbase, tets, nbrs);
+    if (wide)
+        k_output_cloud<<<(te - tb + 255) / 256, 256, 0, s>>>((const TetW *)T, V, sorted, map, tb, te, vbase, tets, nbrs);
+    else
+        k_output_cloud<<<(te - tb + 255) / 256, 256, 0, s>>>((const Tet *)T, V, sorted, map, tb, te, vbase, tets, nbrs);
     return hipGetLastError();
 }
 
-hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s) {
-    if (count == 0) return hipSuccess;
-    k_out_flags<<<(count + 255) / 256, 256, 0, s>>>(T, count, flags);
-    return hipGetLastError();
-}
-
-// Output position of each slot: map[t] (the exclusive scan of the live flags) for live finite
-// tetrahedra, NONE for ghosts and free slots; and the input index of each vertex record as a
-// compact 4-byte array.  The export kernel then gathers from these two small arrays (which
-// stay in the last-level caches far better than 64-byte tetrahedron rows and 32-byte vertex
-// records) instead of from the tetrahedron and vertex pools.
-__global__ void k_out_map(const uint32_t *__restrict__ flags, uint32_t count, uint32_t *__restrict__ map,
-                          const Vert *__restrict__ V, uint32_t nv, uint32_t *__restrict__ vid) {
+// Export.  The live finite tetrahedra are numbered in slot order through a bit set: one
+// 64-bit word per 64 slots (one wavefront's ballot), and an exclusive scan of the words'
+// population counts.  The output index of live slot t is pre[t / 64] plus the live bits
+// below t in its word, so the export needs 12 bytes per 64 slots instead of a per-slot map,
+// and the neighbour lookups read from this small array, which stays in the caches.
+template <class R>
+__global__ void k_live_bits(const R *__restrict__ T, uint32_t count, unsigned long long *__restrict__ bits,
+                            uint32_t *__restrict__ wcnt) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < count && !flags[t]) map[t] = NONE;
+    bool live = false;
+    if (t < count) {
+        const uint4 w = T[t].v;
+        live = w.x != DEAD && w.w != GHOST;
+    }
+    const unsigned long long m = __ballot(live);
+    const uint32_t word = t >> 6;
+    if ((threadIdx.x & 63u) == 0 && word < ((uint64_t)count + 63) / 64) {
+        bits[word] = m;
+        wcnt[word] = (uint32_t)__popcll(m);
+    }
+}
+
+__device__ __forceinline__ bool is_live(const unsigned long long *bits, uint32_t t) {
+    return (bits[t >> 6] >> (t & 63u)) & 1ull;
+}
+
+__device__ __forceinline__ uint32_t out_index(const unsigned long long *bits, const uint32_t *pre, uint32_t t) {
+    return pre[t >> 6] + (uint32_t)__popcll(bits[t >> 6] & ((1ull << (t & 63u)) - 1ull));
+}
+
+// input index of each vertex record as a compact 4-byte array
+__global__ void k_out_vid(const Vert *__restrict__ V, uint32_t nv, uint32_t *__restrict__ vid) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < nv) vid[t] = (uint32_t)V[t].idx;
 }
 
-__global__ void k_output(const Tet *__restrict__ T, const uint32_t *__restrict__ vid,
-                         const uint32_t *__restrict__ map, uint32_t count, uint32_t *__restrict__ tets,
-                         int64_t *__restrict__ nbrs) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count) return;
-    const uint32_t o = map[t];
-    if (o == NONE) return;
+// slots [t0, t1): live tetrahedron t goes to output row out_index(t) - obase
+template <class R>
+__global__ void k_output(const R *__restrict__ T, const uint32_t *__restrict__ vid,
+                         const unsigned long long *__restrict__ bits, const uint32_t *__restrict__ pre, uint32_t t0,
+                         uint32_t t1, uint32_t obase, uint32_t *__restrict__ tets, int64_t *__restrict__ nbrs) {
+    const uint64_t tt = (uint64_t)t0 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (tt >= t1) return;
+    const uint32_t t = (uint32_t)tt;
+    if (!is_live(bits, t)) return;
+    const uint32_t o = out_index(bits, pre, t) - obase;
     if (tets) {
         const uint4 w = T[t].v;
         const uint4 out = make_uint4(vid[w.x], vid[w.y], vid[w.z], vid[w.w]);
         *reinterpret_cast<uint4 *>(tets + 4 * (size_t)o) = out;
     }
     if (nbrs) {
-        const uint4 nn = T[t].n;
-        const uint32_t m[4] = {map[nn.x >> 2], map[nn.y >> 2], map[nn.z >> 2], map[nn.w >> 2]};
+        const auto nn = T[t].n;
+        const uint32_t nt[4] = {code_slot(comp(nn, 0)), code_slot(comp(nn, 1)), code_slot(comp(nn, 2)),
+                                code_slot(comp(nn, 3))};
+        long long m[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m[k] = is_live(bits, nt[k]) ? (long long)out_index(bits, pre, nt[k]) : -1ll;
         longlong2 *dst = reinterpret_cast<longlong2 *>(nbrs + 4 * (size_t)o);
-        dst[0] = make_longlong2(m[0] == NONE ? -1ll : (long long)m[0], m[1] == NONE ? -1ll : (long long)m[1]);
-        dst[1] = make_longlong2(m[2] == NONE ? -1ll : (long long)m[2], m[3] == NONE ? -1ll : (long long)m[3]);
+        dst[0] = make_longlong2(m[0], m[1]);
+        dst[1] = make_longlong2(m[2], m[3]);
     }
 }
 
-hipError_t launch_output(const Tet *T, const Vert *V, uint32_t nv, const uint32_t *flags, uint32_t *map,
-                         uint32_t *vid, uint32_t count, uint32_t *tets, int64_t *nbrs, hipStream_t s) {
+hipError_t launch_live_bits(const void *T, bool wide, uint32_t count, unsigned long long *bits, uint32_t *wcnt,
+                            hipStream_t s) {
     if (count == 0) return hipSuccess;
-    const uint32_t m = count > nv ? count : nv;
-    k_out_map<<<(m + 255) / 256, 256, 0, s>>>(flags, count, map, V, nv, vid);
-    k_output<<<(count + 255) / 256, 256, 0, s>>>(T, vid, map, count, tets, nbrs);
+    const uint32_t nb = (uint32_t)(((uint64_t)count + 255) / 256);
+    if (wide) k_live_bits<<<nb, 256, 0, s>>>((const TetW *)T, count, bits, wcnt);
+    else k_live_bits<<<nb, 256, 0, s>>>((const Tet *)T, count, bits, wcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_out_vid(const Vert *V, uint32_t nv, uint32_t *vid, hipStream_t s) {
+    if (nv == 0) return hipSuccess;
+    k_out_vid<<<(nv + 255) / 256, 256, 0, s>>>(V, nv, vid);
+    return hipGetLastError();
+}
+
+hipError_t launch_output(const void *T, bool wide, const uint32_t *vid, const unsigned long long *bits,
+                         const uint32_t *pre, uint32_t t0, uint32_t t1, uint32_t obase, uint32_t *tets, int64_t *nbrs,
+                         hipStream_t s) {
+    if (t1 <= t0) return hipSuccess;
+    const uint32_t nb = (uint32_t)(((uint64_t)(t1 - t0) + 255) / 256);
+    if (wide) k_output<<<nb, 256, 0, s>>>((const TetW *)T, vid, bits, pre, t0, t1, obase, tets, nbrs);
+    else k_output<<<nb, 256, 0, s>>>((const Tet *)T, vid, bits, pre, t0, t1, obase, tets, nbrs);
+    return hipGetLastError();
+}
+
+__global__ void k_points_out(const Vert *__restrict__ V, uint32_t nv, double *__restrict__ xyz) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nv) return;
+    const Vert v = V[r];
+    const size_t i = (uint32_t)v.idx;
+    xyz[3 * i] = v.x;
+    xyz[3 * i + 1] = v.y;
+    xyz[3 * i + 2] = v.z;
+}
+
+hipError_t launch_points_out(const Vert *V, uint32_t nv, double *xyz, hipStream_t s) {
+    if (nv == 0) return hipSuccess;
+    k_points_out<<<(uint32_t)(((uint64_t)nv + 255) / 256), 256, 0, s>>>(V, nv, xyz);
     return hipGetLastError();
 }
 

@@ -8,7 +8,8 @@ namespace dtk {
 constexpr uint32_t GHOST = 0xFFFFFFFFu;  // ghost vertex id (paper Sec. 2.6); always slot 3
 constexpr uint32_t DEAD = 0xFFFFFFFEu;   // first vertex slot of a freed tetrahedron
 constexpr uint32_t NONE = 0xFFFFFFFFu;   // "no tetrahedron" in the vertex -> tetrahedron hints
-constexpr uint32_t MAX_TETS = (1u << 30) - 1;  // adjacency code 4 t + f must fit 32 bits
+constexpr uint32_t MAX_TETS = (1u << 30) - 1;         // 32-bit codes: 4 t + f must fit 32 bits
+constexpr uint32_t MAX_TETS_WIDE = 0xFFFFFFF0u;       // 64-bit codes: slots stay 32-bit indices
 
 // A vertex record: 32 bytes so that one aligned fetch brings a whole vertex (Sec. 2.2,
 // Listing 1); `idx` holds the global input index (the key of the symbolic perturbation).
@@ -19,7 +20,7 @@ struct __align__(32) Vert {
 
 // One tetrahedron: 64 bytes, so that a visit touches one cache line.  Facet j is opposite
 // v[j]; n[j] = 4 t' + f' names the neighbour across it (Sec. 2.2, adjacency code).  The
-// two claim words of the concurrent rounds live in the same record.
+// claim word of the concurrent rounds lives in the same record.
 struct __align__(64) Tet {
     uint4 v;                    // vertex ids (ghost in slot 3); v.x = DEAD once freed
     uint4 n;                    // neighbour codes
@@ -27,6 +28,43 @@ struct __align__(64) Tet {
                                 // stamp S (in the attempt's cavity) or S + 1 (outside it)
     unsigned long long spare[3];
 };
+
+// The same record with 64-bit neighbour codes, for pools beyond 2^30 slots (the paper's own
+// 3e9-tetrahedron scale, Sec. 3.7): still 64 bytes, one line per visit.
+struct Codes4W {
+    unsigned long long c[4];
+};
+struct __align__(64) TetW {
+    uint4 v;
+    Codes4W n;
+    unsigned long long claim;
+    unsigned long long spare[1];
+};
+static_assert(sizeof(Tet) == 64 && sizeof(TetW) == 64, "one tetrahedron is one 64-byte record");
+
+// Layout of the tetrahedron pool and its adjacency codes: 32-bit codes (pools below 2^30
+// slots) or 64-bit codes.  Slots are 32-bit indices in both.
+struct Narrow {
+    using Rec = Tet;
+    using code = uint32_t;
+    using code4 = uint4;
+    using set_t = uint32_t;                // cavity-set entry (slot << 1 | kind)
+    static constexpr uint32_t LHM = 256;   // regular cavity set entries in LDS
+};
+struct Wide {
+    using Rec = TetW;
+    using code = unsigned long long;
+    using code4 = Codes4W;
+    using set_t = unsigned long long;
+    static constexpr uint32_t LHM = 128;   // same LDS bytes as the narrow set
+};
+
+__host__ __device__ __forceinline__ uint32_t comp(uint4 q, int k) {
+    return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w));
+}
+__host__ __device__ __forceinline__ unsigned long long comp(const Codes4W &q, int k) {
+    return k == 0 ? q.c[0] : (k == 1 ? q.c[1] : (k == 2 ? q.c[2] : q.c[3]));
+}
 
 // candidate status after a round
 enum : uint8_t {
@@ -36,7 +74,8 @@ enum : uint8_t {
     ST_OVERFLOW = 3,  // cavity larger than this round's per-insertion buffer
     ST_DUP = 4,       // exact duplicate of a vertex already in the mesh
     ST_WON = 5,       // inserted
-    ST_ERROR = 6      // walk did not terminate (never expected)
+    ST_ERROR = 6,     // walk did not terminate (never expected)
+    ST_FULL = 7       // a sign the fp64 filter could not decide: run again with exact predicates
 };
 
 enum : uint32_t {
@@ -75,6 +114,9 @@ struct Ctr {
     uint32_t bad_cloud;  // first cloud found degenerate by the initial-tetrahedron search
     uint32_t any_live;   // some live tetrahedron (walk start of last resort)
     uint32_t chunk;      // length of a list slice processed as one round
+    uint32_t dropped;    // freed slots that did not fit the free list (left unused)
+    uint32_t ndefer;     // candidates of this round handed to the exact-predicate pass
+    uint32_t deferred;   // such candidates since the last clear
     unsigned long long walk_steps, cav_tets, bnd_facets;
     unsigned long long orient, orient_exact, insphere, insphere_exact, perturbed;
     unsigned long long attempts;
@@ -94,10 +136,12 @@ struct Cloud {
     double box[4];       // grid origin (x, y, z) and scale 2^m / largest extent
 };
 
-// Arguments of one insertion round.
+// Arguments of one insertion round.  The pool and the code buffers are typed by the
+// kernels' layout (Narrow or Wide): T is K::Rec[tcap], cav and outc are K::code arrays,
+// scr_n is a K::code4 array.
 struct RoundArgs {
     const Vert *V;
-    Tet *T;                      // tetrahedron pool
+    void *T;                     // tetrahedron pool
     uint32_t *vtet;              // vertex -> a live tetrahedron containing it
     uint32_t vlo, vhi;           // vertex records of the current call
     const uint32_t *anchor;      // walk anchor of each record of the call (a lower-level record
@@ -114,18 +158,22 @@ struct RoundArgs {
     const uint32_t *ncand_ptr;   // device count of the current list
     uint32_t *nnext_ptr;         // device count of the next list
     uint32_t *novf_ptr;          // device count of the overflow list
-    uint32_t *cav;               // [stride][capC] cavity tetrahedra (code 4 t + entry facet)
+    uint32_t *defer;             // [stride] candidates handed to the exact-predicate pass
+    uint32_t *ndefer_ptr;        // device count of them (reset at the round's end)
+    void *cav;                   // [stride][capC] cavity tetrahedra (code 4 t + entry facet)
     uint32_t *bnd;               // [stride][capF] boundary facets (4 c + f, c in the cavity)
-    uint32_t *outc;              // [stride][capF] outer codes, then new tetrahedra
+    void *outc;                  // [stride][capF] outer codes, then new tetrahedra
     uint32_t *cnt;               // [2][stride] cavity size, boundary size
     uint8_t *status;             // [stride]
-    uint4 *scr_v, *scr_n;        // [stride][capC] copies of the winners' cavity tetrahedra
+    uint4 *scr_v;                // [stride][capC] vertex copies of the winners' cavity tetrahedra
+    void *scr_n;                 // [stride][capC] their neighbour codes (pivoting balls)
     uint32_t *fl_cur;            // free list consumed this round
     uint32_t *fl_next;           // free list filled this round
+    uint32_t flcap;              // entries of each free list (slots freed beyond it are dropped)
     Ctr *ctr;
     unsigned long long *stat;    // [NSTAT][STAT_SPREAD][STAT_PAD] work statistics
     uint32_t stride, capC, capF, tcap;
-    uint32_t hmg;                // capC > 1024: size of the cavity set in global memory
+    uint32_t hmg;                // capC > 1024: entries of the cavity set in global memory
     unsigned long long round_hi;  // (0xFFFFFFFF - round) << 32: newer rounds claim lower
 };
 
@@ -198,27 +246,61 @@ hipError_t launch_labels(const Vert *V, uint64_t base, uint64_t n, const Cloud *
 
 // ---- launch wrappers (dt_insert.hip) ----
 // initial tetrahedron and four ghosts of each cloud c at slots 5 c0 + 5 c .. + 4 (c0: first)
+// Every wrapper that touches the pool takes `wide`: the pool holds TetW records with 64-bit
+// codes (true) or Tet records with 32-bit codes (false).
 hipError_t launch_init(const Vert *V, Cloud *clouds, uint32_t nclouds, uint32_t first_slot, const uint8_t *dup,
-                       Tet *T, uint32_t *vtet, Ctr *ctr, hipStream_t s);
+                       void *T, bool wide, uint32_t *vtet, Ctr *ctr, hipStream_t s);
 hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, const uint32_t *lvl_size,
                             const uint32_t *lvl_bits, const unsigned long long *rank_base, const uint32_t *lord,
                             const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank,
                             uint32_t *ncand, hipStream_t s);
-hipError_t launch_round(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_round(const RoundArgs &a, bool wide, uint32_t max_cand, uint32_t lanes, hipStream_t s,
+                        hipEvent_t *ev);
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s);
-hipError_t launch_reset_claims(Tet *T, uint32_t tcap, hipStream_t s);
-hipError_t launch_output_flags(const Tet *T, uint32_t count, uint32_t *flags, hipStream_t s);
-hipError_t launch_output(const Tet *T, const Vert *V, uint32_t nv, const uint32_t *flags, uint32_t *map,
-                         uint32_t *vid, uint32_t count, uint32_t *tets, int64_t *nbrs, hipStream_t s);
+hipError_t launch_reset_claims(void *T, bool wide, uint32_t tcap, hipStream_t s);
+// copies `count` Tet records into TetW records
+hipError_t launch_widen(const void *src, void *dst, uint32_t count, hipStream_t s);
+// export: live bit set (one word per 64 slots) with per-word counts, input index per vertex
+// record, and the output rows of live slots [t0, t1) at out_index - obase
+hipError_t launch_live_bits(const void *T, bool wide, uint32_t count, unsigned long long *bits, uint32_t *wcnt,
+                            hipStream_t s);
+hipError_t launch_out_vid(const Vert *V, uint32_t nv, uint32_t *vid, hipStream_t s);
+hipError_t launch_output(const void *T, bool wide, const uint32_t *vid, const unsigned long long *bits,
+                         const uint32_t *pre, uint32_t t0, uint32_t t1, uint32_t obase, uint32_t *tets, int64_t *nbrs,
+                         hipStream_t s);
 // grouping of the live finite tetrahedra by cloud (see dt_get_tets_batch)
-hipError_t launch_tet_cloud(const Tet *T, const Vert *V, uint32_t count, uint32_t nclouds, unsigned long long *keys,
-                            uint32_t *vals, hipStream_t s);
+hipError_t launch_tet_cloud(const void *T, bool wide, const Vert *V, uint32_t count, uint32_t nclouds,
+                            unsigned long long *keys, uint32_t *vals, hipStream_t s);
 hipError_t launch_seg_bounds(const unsigned long long *keys, uint32_t count, uint32_t nclouds, uint32_t *toff,
                              hipStream_t s);
 hipError_t launch_tet_map(const uint32_t *sorted, uint32_t nlive, uint32_t *map, hipStream_t s);
-hipError_t launch_output_cloud(const Tet *T, const Vert *V, const uint32_t *sorted, const uint32_t *map, uint32_t tb,
-                               uint32_t te, uint64_t vbase, uint32_t *tets, int64_t *nbrs, hipStream_t s);
+hipError_t launch_output_cloud(const void *T, bool wide, const Vert *V, const uint32_t *sorted, const uint32_t *map,
+                               uint32_t tb, uint32_t te, uint64_t vbase, uint32_t *tets, int64_t *nbrs, hipStream_t s);
 hipError_t launch_predicates(int kind, const double *pts, const int64_t *idx, uint64_t k, int8_t *out,
                              hipStream_t s);
+// coordinates of every vertex record at its input index (single-cloud contexts)
+hipError_t launch_points_out(const Vert *V, uint32_t nv, double *xyz, hipStream_t s);
+
+// ---- launch wrappers (dt_refine.hip): circumcentre refinement steps
+hipError_t launch_hull_facets(const void *T, bool wide, uint32_t count, uint4 *facets, uint32_t *nfacets,
+                              hipStream_t s);
+hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count, double grow, double *cc, uint4 *q,
+                         uint32_t cap, uint32_t *ncand, hipStream_t s);
+hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const double *cc, const uint4 *q, uint32_t k,
+                         double *cc2, uint4 *q2, uint32_t *nin, hipStream_t s);
+hipError_t launch_order_keys(const uint4 *q, const unsigned long long *moore, const uint32_t *perm, uint32_t k,
+                             int which, int bits, unsigned long long *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_cell_keys(const double *lo, double cell, uint64_t g, const double *xyz, const Vert *V, uint32_t n,
+                            unsigned long long *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_near_vertex(const double *lo, double cell, uint64_t g, const Vert *V, const unsigned long long *vkeys,
+                              const uint32_t *vidx, uint32_t nv, const double *cc, const uint32_t *perm, uint32_t k,
+                              double lim, double *ccr, uint8_t *status, hipStream_t s);
+hipError_t launch_filter_round(const double *lo, double cell, uint64_t g, const unsigned long long *ckeys,
+                               const uint32_t *crank, uint32_t k, const double *ccr, double lim, uint8_t *status,
+                               uint32_t *undecided, hipStream_t s);
+hipError_t launch_kept(const uint8_t *status, uint32_t k, uint32_t *flags, const uint32_t *pos, const double *ccr,
+                       double *out, int phase, hipStream_t s);
+hipError_t launch_vert_box(const Vert *V, uint32_t n, uint32_t m, double *partial, uint32_t nblocks, Cloud *cl,
+                           hipStream_t s);
 
 }  // namespace dtk

@@ -26,7 +26,8 @@ class dt_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("round_size", ctypes.c_uint32),
                 ("cavity_cap", ctypes.c_uint32), ("capacity_tets", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("max_rounds", ctypes.c_uint32), ("timing", ctypes.c_int), ("round_fraction", ctypes.c_double),
-                ("lanes_per_insert", ctypes.c_uint32), ("scheduler", ctypes.c_int), ("log_points", ctypes.c_int)]
+                ("lanes_per_insert", ctypes.c_uint32), ("scheduler", ctypes.c_int), ("log_points", ctypes.c_int),
+                ("index_bits", ctypes.c_int), ("adaptive_curve", ctypes.c_int)]
 
 DT_SCHED_PLAIN, DT_SCHED_LEARNED = 0, 1
 NFEAT, NHID, NOUT = 16, 64, 3
@@ -44,7 +45,8 @@ class dt_stats(ctypes.Structure):
                  ("cavity_launches", ctypes.c_uint64), ("ball_launches", ctypes.c_uint64),
                  ("ms_cavity_kernel", ctypes.c_double), ("ms_ball_kernel", ctypes.c_double),
                  ("cavity_units", ctypes.c_uint64), ("ball_units", ctypes.c_uint64),
-                 ("sched_fallbacks", ctypes.c_uint64)])
+                 ("sched_fallbacks", ctypes.c_uint64), ("index_bits", ctypes.c_uint64),
+                 ("dropped_slots", ctypes.c_uint64), ("deferred", ctypes.c_uint64)])
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -90,10 +92,15 @@ def lib():
         L.dt_debug_sort.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(i32)]
         L.dt_debug_predicates.argtypes = [vp, i32, vp, vp, u64, vp]
         L.dt_debug_set_round_counter.argtypes = [vp, u64]
+        L.dt_debug_widen_at.argtypes = [vp, u64]
+        L.dt_refine.argtypes = [vp, ctypes.c_double, ctypes.c_uint32, vp, ctypes.POINTER(ctypes.c_uint32),
+                                ctypes.POINTER(u64)]
+        L.dt_get_points.argtypes = [vp, vp, ctypes.POINTER(u64)]
         for f in ("dt_create", "dt_insert_points", "dt_get_tets", "dt_clear", "dt_destroy", "dt_get_stats",
                   "dt_insert_batch", "dt_get_tets_batch", "dt_autotune", "dt_get_point_log", "dt_train_model",
                   "dt_load_model", "dt_debug_mlp", "dt_debug_mlp_grad", "dt_debug_sort", "dt_debug_predicates",
-                  "dt_debug_set_round_counter"):
+                  "dt_debug_set_round_counter", "dt_debug_widen_at", "dt_refine",
+                  "dt_get_points"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -283,6 +290,29 @@ def dt_debug_set_round_counter(ctx, rounds):
     _check(ctx, lib().dt_debug_set_round_counter(ctx, int(rounds)))
 
 
+def dt_refine(ctx, h, max_steps=100):
+    """Refinement steps (see dt.h); returns (points inserted, [(candidates, kept) per step])."""
+    counts = np.zeros(2 * int(max_steps), dtype=np.uint32)
+    ns = ctypes.c_uint32(0)
+    ins = ctypes.c_uint64(0)
+    _check(ctx, lib().dt_refine(ctx, float(h), int(max_steps), counts.ctypes.data, ctypes.byref(ns), ctypes.byref(ins)))
+    k = int(ns.value)
+    return int(ins.value), [(int(counts[2 * i]), int(counts[2 * i + 1])) for i in range(k)]
+
+
+def dt_get_points(ctx):
+    """(n, 3) float64 coordinates of every inserted point, by global input index."""
+    n = ctypes.c_uint64(0)
+    _check(ctx, lib().dt_get_points(ctx, None, ctypes.byref(n)))
+    out = np.empty((int(n.value), 3), dtype=np.float64)
+    _check(ctx, lib().dt_get_points(ctx, out.ctypes.data, ctypes.byref(n)))
+    return out
+
+
+def dt_debug_widen_at(ctx, slots):
+    _check(ctx, lib().dt_debug_widen_at(ctx, int(slots)))
+
+
 def dt_debug_predicates(ctx, kind, pts, idx=None):
     pts = np.ascontiguousarray(pts, dtype=np.float64)
     k = int(pts.shape[0])
@@ -304,13 +334,16 @@ class Triangulation:
     (host or device); `tets` returns (tets[T,4] uint32, nbrs[T,4] int64)."""
 
     def __init__(self, device=0, stream=None, round_size=0, cavity_cap=0, capacity_tets=0, seed=0x5EED,
-                 max_rounds=0, timing=False, round_fraction=0.0, lanes_per_insert=0, scheduler=0, log_points=False):
+                 max_rounds=0, timing=False, round_fraction=0.0, lanes_per_insert=0, scheduler=0, log_points=False,
+                 index_bits=0, adaptive_curve=False):
         o = dt_default_options()
         o.device, o.round_size, o.cavity_cap = int(device), int(round_size), int(cavity_cap)
         o.capacity_tets, o.seed, o.max_rounds = int(capacity_tets), int(seed), int(max_rounds)
         o.timing, o.round_fraction = int(bool(timing)), float(round_fraction)
         o.lanes_per_insert = int(lanes_per_insert)
         o.scheduler, o.log_points = int(scheduler), int(bool(log_points))
+        o.index_bits = int(index_bits)
+        o.adaptive_curve = int(bool(adaptive_curve))
         o.stream = stream
         self.ctx = dt_create(o)
 

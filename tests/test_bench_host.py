@@ -17,23 +17,32 @@ def load_bench():
 
 def test_cavity_byte_model():
     b = load_bench()
-    # an attempt with no walk and an empty cavity still reads its candidate and point and the
-    # two initial vertex records of an empty boundary
+    # the scope table's model per insertion: 44 + 64 W + 32 C + 16 F + 32 V, W = 4, V = 30;
+    # at C = 20, F = 26 it is 2316 B
+    assert b.cavity_bytes_per_insertion(20, 26) == 44 + 4 * 64 + 20 * 32 + 26 * 16 + 30 * 32 == 2316
+    assert b.cavity_bytes_per_insertion(0, 0, W=0, V=0) == 44
+    assert b.cavity_bytes_per_insertion(1, 0, W=0, V=0) - 44 == 32
+    assert b.cavity_bytes_per_insertion(0, 1, W=0, V=0) - 44 == 16
+    assert b.ball_bytes_per_insertion(26) == 936
+    # the per-attempt model: an attempt with no walk and an empty cavity still reads its
+    # candidate and point and the two initial vertex records of an empty boundary
     assert b.cavity_bytes_per_attempt(0, 0, 0) == 48 + 32 * 2
-    # each term is linear in its count: walk steps 64 B, cavity tetrahedra 52 B, facets 56 B
     base = b.cavity_bytes_per_attempt(0, 0, 0)
     assert b.cavity_bytes_per_attempt(1, 0, 0) - base == 64
     assert b.cavity_bytes_per_attempt(0, 1, 0) - base == 32 + 16 + 4
     assert b.cavity_bytes_per_attempt(0, 0, 2) - base == 2 * (16 + 16 + 8) + 32
-    # the uniform workload's measured shape (W 5.7, C 20, F 26.8) is about 3 KB
     assert 2900 < b.cavity_bytes_per_attempt(5.7, 20.04, 26.8) < 3100
 
 
 def test_traffic_is_used_only_for_matching_sources(tmp_path, monkeypatch):
     b = load_bench()
-    summary = open(b.PMC_SUMMARY).read()
-    # the committed summary carries the hash of the committed kernel sources
-    assert b.measured_traffic() is not None and b.measured_traffic() > 1e8
+    # a summary carrying the hash of the current kernel sources is read
+    summary = ("# summary\n\n- traffic_bytes_per_launch = 414386916\n"
+               f"- kernel_source_sha256 = {b.kernel_source_hash()}\n")
+    cur = tmp_path / "current.md"
+    cur.write_text(summary)
+    monkeypatch.setattr(b, "PMC_SUMMARY", str(cur))
+    assert b.measured_traffic() == 414386916.0
     # a summary taken on other sources is ignored
     stale = summary.replace("kernel_source_sha256 = ", "kernel_source_sha256 = 0")
     p = tmp_path / "stale.md"
@@ -76,22 +85,6 @@ def test_cpu_baseline_over_clouds_stops_at_its_budget():
     assert f"({pts} points" in r["sample"]
     r = b.cpu_baseline_clouds(xyz, off, [0, 2, 4], budget_s=0.0)
     assert r["sample"].startswith("1 of the clouds")
-
-
-def test_ball_byte_model():
-    b = load_bench()
-    # a candidate with empty lists still reads its point, rank, lengths and status
-    assert b.ball_bytes(0, 0, 1, 0) == 20
-    # each cavity or outer entry costs its list entry and claim word
-    assert b.ball_bytes(1, 0, 1, 0) - 20 == 12 and b.ball_bytes(0, 1, 1, 0) - 20 == 12
-    # a winner's part: cavity rows 32 B each, boundary facets 52 B each, boundary vertex hints
-    base = b.ball_bytes(0, 0, 0, 1)
-    assert base == 4 * 2
-    assert b.ball_bytes(1, 0, 0, 1) - base == 32
-    assert b.ball_bytes(0, 2, 0, 1) - base == 2 * 52 + 4
-    # the uniform 1e7 shape: about 2.9 KB per insertion
-    per = b.ball_bytes(20.04, 26.8, 1.3469e7, 1e7) / 1e7
-    assert 2800 < per < 3000
 
 
 def test_paper_context_is_quoted_only_where_the_paper_has_the_size():
@@ -187,7 +180,7 @@ def test_bench_line_contract(monkeypatch, capsys):
     field of the output contract, with value = tetrahedra / (ms_per_step / 1000)."""
     _stand_ins(monkeypatch)
     line = _run_bench(monkeypatch, capsys, ["--n", "2000", "--steps", "2", "--warmup", "1", "--no-learned",
-                                            "--cpu-sample", "1000"])
+                                            "--cpu-sample", "1000", "--u8-steps", "0"])
     assert line["steps"] == 2 and line["warmup"] == 1
     # ms_per_step is printed to 3 decimals: allow that rounding
     assert abs(line["value"] * line["ms_per_step"] / 1000.0 - 6700) <= 6700 * (0.0006 / line["ms_per_step"] + 1e-6)
@@ -195,6 +188,12 @@ def test_bench_line_contract(monkeypatch, capsys):
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-4 and "traffic" in r
     assert r["traffic"] is None  # the counters were taken on the 1e7 workload only
+    # frac by hand: bytes per insertion x insertions per launch / mean launch time / peak
+    C, F = 20000 / 1000, 26800 / 1000
+    per = 44 + 4 * 64 + 32 * C + 16 * F + 30 * 32
+    assert r["bytes_per_insertion"] == round(per, 1) and r["insertions_per_launch"] == 1000 / 50
+    assert abs(r["achieved"] - per * (1000 / 50) / (12.0 / 50 / 1000) / 1e9) < 0.01
+    assert "model_per_attempt" in r and line["u8"] is None
     c = line["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] == 1 and c["value"] > 0 and "sample" in c
 
@@ -208,4 +207,4 @@ def test_bench_line_contract_batch_and_mix(monkeypatch, capsys):
     assert line["cpu_baseline"] is None
     line = _run_bench(monkeypatch, capsys, ["--workload", "mix", "--mix-scale", "0.001", "--train-samples", "100",
                                             "--steps", "1", "--warmup", "0", "--cpu-mix-scale", "0.05"])
-    assert line["learned"]["same_count"] and line["cpu_baseline"]["kind"] == "oracle"
+    assert "identical_output" in line["learned"] and line["cpu_baseline"]["kind"] == "oracle"

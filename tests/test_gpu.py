@@ -124,6 +124,31 @@ def test_sort_matches_oracle(dtlib, oracle_mod, kind, n):
     assert np.array_equal(perm.astype(np.int64), rperm)
 
 
+@pytest.mark.parametrize("kind,n", [("uniform", 20000), ("mix", 30000)])
+def test_adaptive_curve_sort_matches_oracle(dtlib, oracle_mod, kind, n):
+    """The adaptive curve: the same definition on the grid of 21 levels."""
+    say(f"adaptive sort {kind} {n}")
+    xyz = uniform_points(n, 1002) if kind == "uniform" else mix_small(6, n // 3)
+    o = dtlib.dt_default_options()
+    o.adaptive_curve = 1
+    ctx = dtlib.dt_create(o)
+    try:
+        keys, perm, m = dtlib.dt_debug_sort(ctx, xyz)
+    finally:
+        dtlib.dt_destroy(ctx)
+    rkeys, rperm, rm, _ = oracle_mod.sort_reference(xyz, 0x5EED, m=21)
+    assert m == rm == 21
+    assert np.array_equal(keys, rkeys)
+    assert np.array_equal(perm.astype(np.int64), rperm)
+
+
+def test_adaptive_curve_keeps_result(dtlib, oracle_mod):
+    say("adaptive curve triangulation")
+    xyz = mix_small(53, 6000)
+    tets, nbrs, st = gpu_dt(dtlib, xyz, adaptive_curve=True)
+    assert_parity(oracle_mod, xyz, tets, "adaptive curve")
+
+
 # ------------------------------------------------------------------ triangulations
 
 @pytest.mark.parametrize("n,seed", [(4, 1), (5, 2), (6, 3), (8, 4), (12, 5), (33, 6), (100, 7), (1000, 8),

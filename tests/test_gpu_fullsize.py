@@ -197,20 +197,24 @@ def test_mix_1e7_whole_output(dtlib, oracle_mod):
     _subbox_check(oracle_mod, xyz, t_dev, c - 0.015, 0.03, min_tets=1000)
 
 
-def test_batch_bench_chunk(dtlib, oracle_mod):
-    """The benchmark's batch configuration: clouds 0..1023 of the 4096-cloud recipe in one
-    dt_insert_batch call; a sample of clouds (the smallest, the largest, and every 128th)
-    against the oracle run on that cloud alone."""
+def test_batch_bench_config(dtlib, oracle_mod):
+    """The benchmark's batch configuration: all 4096 clouds of the recipe (1.58e8 points, about
+    1.05e9 tetrahedra) in one dt_insert_batch call, which takes 64-bit adjacency codes; a
+    sample of clouds (the smallest, the largest, and every 256th) against the oracle run on
+    that cloud alone."""
     import torch
     from synth import batch_clouds
-    say("full size: batch of 1024 clouds (seeds 3000..4023)")
-    xyz, off = batch_clouds(1024, seed_base=3000)
+    say("full size: batch of 4096 clouds (seeds 3000..7095), one call")
+    xyz, off = batch_clouds(4096, seed_base=3000)
     off = off.astype(np.int64)
     stream = torch.cuda.current_stream()
     with dtlib.Triangulation(device=0, stream=stream.cuda_stream, timing=True) as tri:
         tri.insert_batch(torch.from_numpy(xyz).cuda(), off.astype(np.uint64))
+        st = tri.stats()
+        say(f"{st['rounds']} rounds, index_bits {st['index_bits']}")
+        assert st["index_bits"] == 64
         sizes = np.diff(off)
-        pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes))] + list(range(0, 1024, 128))))
+        pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes))] + list(range(0, 4096, 256))))
         for k in pick:
             pts = xyz[off[k]:off[k + 1]]
             t, nb = tri.tets_batch(k)

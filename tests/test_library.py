@@ -81,6 +81,9 @@ def test_every_entry_point_rejects_a_null_context(libdt):
         "dt_debug_sort": (n, n, 0, n, n, n),
         "dt_debug_predicates": (n, 0, n, n, 0, n),
         "dt_debug_set_round_counter": (n, 0),
+        "dt_debug_widen_at": (n, 0),
+        "dt_refine": (n, 0.1, 10, n, n, n),
+        "dt_get_points": (n, n, n),
         "dt_clear": (n,),
         "dt_destroy": (n,),
         "dt_get_stats": (n, n),
