@@ -232,6 +232,25 @@ int dt_refine(dt_ctx *ctx, double h, uint32_t max_steps, uint32_t *step_counts, 
    batch of clouds. */
 int dt_get_points(dt_ctx *ctx, double *xyz, uint64_t *num_points);
 
+/* ---- triangulation without device allocation ----
+   For callers that cannot allocate device memory: code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc.  Triangulates the n points at xyz (fp64
+   AoS, host or device memory) on `device` and the given hipStream_t (NULL: the null
+   stream), exactly as dt_create + dt_insert_points + dt_get_tets would (same unique
+   result), and returns when done.  Every device buffer comes from a static array of
+   DT_NOALLOC_SCRATCH_BYTES that each GPU the call runs on holds until the process ends; the
+   call makes no hipMalloc, hipFree or other allocating call (the first call on a device only
+   looks up the array's address).  The caller owns xyz and the outputs: tets (4*T uint32),
+   nbrs (4*T int64), each may be NULL, host or device memory; *num_tets is in/out as in
+   dt_get_tets (both NULL: the count only, after triangulating).  n above
+   DT_NOALLOC_MAX_POINTS, or a result that does not fit the array, returns DT_E_CAPACITY;
+   other errors as dt_insert_points.  Calls on one device share the array: calls that
+   overlap on one device race.  No context, no statistics. */
+#define DT_NOALLOC_MAX_POINTS 65536u
+#define DT_NOALLOC_SCRATCH_BYTES (128u << 20)
+int dt_triangulate_noalloc(int device, void *stream, const double *xyz, uint64_t n, uint32_t *tets,
+                           int64_t *nbrs, uint64_t *num_tets);
+
 /* Drop every point and tetrahedron but keep the device allocations. */
 int dt_clear(dt_ctx *ctx);
 

@@ -1703,6 +1703,109 @@ int dt_debug_set_round_counter(dt_ctx *c, uint64_t rounds) {
     return DT_OK;
 }
 
+// ---- triangulation without device allocation ----
+//
+// Every buffer of the call comes from `scratch`, a static device array each GPU holds for the
+// life of the process.  Its address on a device is taken once, with that device current, by
+// hipGetSymbolAddress; host code then uses that address only (the array's name is a host
+// stand-in).  Calls on one device share the array and its context, so calls that overlap on
+// one device race.
+
+}  // extern "C"
+
+static __device__ __align__(256) unsigned char scratch[DT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+constexpr uint32_t NOALLOC_ROUND_CAP = 4096;      // candidates per round
+constexpr uint32_t NOALLOC_EXPORT_CHUNK = 1u << 16;
+
+struct NoallocDevice {
+    std::once_flag once;
+    int status = DT_OK;             // result of the set-up
+    unsigned char *ptr = nullptr;   // device address of `scratch` on this device
+    dt_ctx *ctx = nullptr;          // host state, rebuilt in place at every call
+    Ctr ring[3];                    // host copies of the counters (static: no pinned allocation)
+};
+NoallocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+
+// once per device, with the device current: the array's device address and the context
+void noalloc_setup(int device, NoallocDevice &d) {
+    if (hipSetDevice(device) != hipSuccess) {
+        hipGetLastError();
+        d.status = DT_E_DEVICE;
+        return;
+    }
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        hipGetLastError();
+        d.status = DT_E_DEVICE;
+        return;
+    }
+    d.ptr = static_cast<unsigned char *>(p);
+    d.ctx = new (std::nothrow) dt_ctx();
+    d.status = d.ctx ? DT_OK : DT_E_CAPACITY;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dt_triangulate_noalloc(int device, void *stream, const double *xyz, uint64_t n, uint32_t *tets, int64_t *nbrs,
+                           uint64_t *num_tets) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES || !num_tets || (n && !xyz)) return DT_E_ARG;
+    if (n > DT_NOALLOC_MAX_POINTS) return DT_E_CAPACITY;
+    NoallocDevice &d = g_noalloc[device];
+    std::call_once(d.once, noalloc_setup, device, std::ref(d));
+    if (d.status != DT_OK) return d.status;
+    if (hipSetDevice(device) != hipSuccess) {
+        hipGetLastError();
+        return DT_E_DEVICE;
+    }
+    // a fresh context over the arena: options at their defaults, no events, static counters
+    dt_ctx *c = d.ctx;
+    *c = dt_ctx();
+    dt_default_options(&c->opt);
+    c->opt.device = device;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->arena = d.ptr;
+    c->arena_size = DT_NOALLOC_SCRATCH_BYTES;
+    c->round_cap = NOALLOC_ROUND_CAP;
+    c->export_chunk = NOALLOC_EXPORT_CHUNK;
+    c->hring = d.ring;
+    c->hctr = d.ring;
+    std::memset(d.ring, 0, sizeof d.ring);
+    // the pool is sized once for the whole call: besides the tetrahedra of n points it keeps
+    // the headroom the rounds check for (48 slots per candidate of a full round), so it never
+    // grows (growth in the arena would leave the old pool behind)
+    c->opt.capacity_tets = 7 * n + 65536 + 48ull * NOALLOC_ROUND_CAP;
+    apply_options(c);
+    int rc;
+    if ((rc = ensure(c, c->ctrbuf, 1)) || (rc = ensure(c, c->statbuf, STAT_WORDS))) return rc;
+    c->ctr = c->ctrbuf.p;
+    c->stat = c->statbuf.p;
+    HIPCHK(hipMemsetAsync(c->ctr, 0, sizeof(Ctr), c->stream));
+    HIPCHK(hipMemsetAsync(c->stat, 0, STAT_WORDS * sizeof(unsigned long long), c->stream));
+    if (n == 0) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        *num_tets = 0;
+        return DT_OK;
+    }
+    c->h_off = {0, n};
+    if ((rc = insert_clouds(c, xyz, n, c->h_off))) return rc;
+    if (!tets && !nbrs) {
+        // count only
+        rc = dt_get_tets(c, nullptr, nullptr, num_tets);
+    } else {
+        rc = dt_get_tets(c, tets, nbrs, num_tets);
+    }
+    c->ctr = nullptr;
+    c->stat = nullptr;
+    return rc;
+}
+
 int dt_get_points(dt_ctx *c, double *xyz, uint64_t *num_points) {
     if (!c || !num_points) return DT_E_ARG;
     if (c->batch) return fail(c, DT_E_ARG, "the context holds a batch of clouds");

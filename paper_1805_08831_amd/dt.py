@@ -93,13 +93,14 @@ def lib():
         L.dt_debug_predicates.argtypes = [vp, i32, vp, vp, u64, vp]
         L.dt_debug_set_round_counter.argtypes = [vp, u64]
         L.dt_debug_widen_at.argtypes = [vp, u64]
+        L.dt_triangulate_noalloc.argtypes = [i32, vp, vp, u64, vp, vp, ctypes.POINTER(u64)]
         L.dt_refine.argtypes = [vp, ctypes.c_double, ctypes.c_uint32, vp, ctypes.POINTER(ctypes.c_uint32),
                                 ctypes.POINTER(u64)]
         L.dt_get_points.argtypes = [vp, vp, ctypes.POINTER(u64)]
         for f in ("dt_create", "dt_insert_points", "dt_get_tets", "dt_clear", "dt_destroy", "dt_get_stats",
                   "dt_insert_batch", "dt_get_tets_batch", "dt_autotune", "dt_get_point_log", "dt_train_model",
                   "dt_load_model", "dt_debug_mlp", "dt_debug_mlp_grad", "dt_debug_sort", "dt_debug_predicates",
-                  "dt_debug_set_round_counter", "dt_debug_widen_at", "dt_refine",
+                  "dt_debug_set_round_counter", "dt_debug_widen_at", "dt_triangulate_noalloc", "dt_refine",
                   "dt_get_points"):
             getattr(L, f).restype = i32
         _lib = L
@@ -288,6 +289,19 @@ def dt_debug_sort(ctx, xyz):
 
 def dt_debug_set_round_counter(ctx, rounds):
     _check(ctx, lib().dt_debug_set_round_counter(ctx, int(rounds)))
+
+
+def dt_triangulate_noalloc(xyz, tets=None, nbrs=None, capacity=0, device=0, stream=None):
+    """The no-allocation entry point: triangulates xyz (n x 3 float64, host or device) with
+    the library's static scratch memory; fills tets / nbrs (may be None) and returns T."""
+    p, n = _points(xyz)
+    _out(tets, _TET_TYPES, 4 * int(capacity), "tets")
+    _out(nbrs, _NBR_TYPES, 4 * int(capacity), "nbrs")
+    cnt = ctypes.c_uint64(int(capacity))
+    rc = lib().dt_triangulate_noalloc(int(device), stream, p, n, _ptr(tets), _ptr(nbrs), ctypes.byref(cnt))
+    if rc != DT_OK:
+        raise DTError(rc, f"dt_triangulate_noalloc returned {ERROR_NAMES.get(rc, rc)} (needs {cnt.value} tetrahedra)")
+    return int(cnt.value)
 
 
 def dt_refine(ctx, h, max_steps=100):

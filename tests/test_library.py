@@ -88,9 +88,13 @@ def test_every_entry_point_rejects_a_null_context(libdt):
         "dt_destroy": (n,),
         "dt_get_stats": (n, n),
     }
-    assert set(calls) | {"dt_default_options", "dt_create", "dt_last_error"} == set(declared_functions())
+    assert set(calls) | {"dt_default_options", "dt_create", "dt_last_error", "dt_triangulate_noalloc"} == \
+        set(declared_functions())
     for name, args in calls.items():
         assert getattr(L, name)(*args) == dt.DT_E_ARG, name
+    # the context-free entry point checks its arguments before touching a device
+    assert L.dt_triangulate_noalloc(0, None, None, 0, None, None, None) == dt.DT_E_ARG
+    assert L.dt_triangulate_noalloc(-1, None, None, 0, None, None, None) == dt.DT_E_ARG
 
 
 def test_create_without_a_device_fails_cleanly(libdt):
