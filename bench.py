@@ -188,6 +188,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2_500_000,
                     help="uniform: the oracle's CPU sample, the first points of the timed input (about 10 s "
                          "on one core)")
+    ap.add_argument("--subdet-cache", action="store_true",
+                    help="cache four sub-determinants per tetrahedron (the paper's Sec. 2.4 optimization)")
+    ap.add_argument("--adaptive-curve", action="store_true",
+                    help="Moore curve on the deepest grid the key holds (adaptive order for non-uniform inputs)")
     ap.add_argument("--no-export", action="store_true",
                     help="uniform: a step ends with the tetrahedron count (for pools too large to hold the "
                          "output beside them, 5e8 points)")
@@ -196,7 +200,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--round-fraction", type=float, default=0.0)
     ap.add_argument("--round-size", type=int, default=0)
-    ap.add_argument("--lanes", type=int, default=0, help="lanes per insertion (4, 8, 16, 64; 0: automatic)")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per insertion (4, 8, 16, 32, 64; 0: automatic)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick lanes per insertion, round fraction and cavity cap on a 2e6-point sample first")
     ap.add_argument("--workload", choices=["uniform", "batch", "mix"], default="uniform")
@@ -308,7 +312,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.n} i.i.d. uniform fp64 points in [0,1)^3, seed {args.seed}",
                    "points": args.n, "tetrahedra": T, "scheduler": "plain",
-                   "launch": main_run["tuned"] if main_run["tuned"] else "defaults"},
+                   "launch": main_run["tuned"] if main_run["tuned"] else "defaults",
+                   "subdet_cache": bool(args.subdet_cache), "adaptive_curve": bool(args.adaptive_curve)},
         "roofline": main_run["roofline"],
         "cpu_baseline": cpu,
         "paper_context": paper_context(args.n),
@@ -379,7 +384,8 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     stream = torch.cuda.current_stream()
     tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True,
                         round_fraction=args.round_fraction, round_size=args.round_size,
-                        lanes_per_insert=args.lanes)
+                        lanes_per_insert=args.lanes, subdet_cache=args.subdet_cache,
+                        adaptive_curve=args.adaptive_curve)
     tuned = None
     if args.autotune:
         tuned = tri.autotune(torch.from_numpy(uniform_points(2_000_000, seed + 2)).cuda())
@@ -455,11 +461,11 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     ins_per_launch = agg["won"] / launches
     achieved = per_ins * ins_per_launch / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
     peak = 8000.0
-    lanes = (tuned or {}).get("lanes_per_insert") or args.lanes or 8
+    lanes = (tuned or {}).get("lanes_per_insert") or args.lanes or 16
     b_att = cavity_bytes_per_attempt(walk, C, F)
     att_achieved = b_att * agg["attempts"] / launches / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
-    default_launch = (lanes == 8 and not args.round_fraction and not args.round_size and n == 10_000_000
-                      and seed == 1007)
+    default_launch = (lanes == 16 and not args.round_fraction and not args.round_size and n == 10_000_000
+                      and seed == 1007 and not args.subdet_cache and not args.adaptive_curve)
     roofline = {"bound": "hbm", "kernel": f"k_cavity_g<{lanes}>", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "GB/s", "frac": round(achieved / peak, 5),
                 # measured HBM bytes per launch (counter summary), only for the launch it was taken on
@@ -544,7 +550,7 @@ def train_scheduler(gen, seeds, samples, progress):
     return model, info
 
 
-def timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference=None):
+def timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference=None, adaptive_curve=False):
     """`steps` timed triangulations of d_xyz with the given scheduler; per-step means.  With
     a reference canonical output, the last triangulation is exported (untimed) and compared
     with it on the device."""
@@ -553,7 +559,8 @@ def timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference=Non
     from paper_1805_08831_amd import Triangulation, dt_get_tets, dt_load_model
 
     stream = torch.cuda.current_stream()
-    tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True, scheduler=sched)
+    tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True, scheduler=sched,
+                        adaptive_curve=adaptive_curve)
     if sched:
         dt_load_model(tri.ctx, model)
     for _ in range(warmup):
@@ -609,6 +616,9 @@ def run_mix(args):
     golden = golden_hash(sum(counts), seed, kind="mix")
     res = {name: timed_runs(d_xyz, sched, model, args.steps, args.warmup, progress, name, reference)
            for name, sched in (("plain", 0), ("learned", 1))}
+    # the adaptive Moore curve (plain scheduler) on the same input
+    res["adaptive"] = timed_runs(d_xyz, 0, model, args.steps, args.warmup, progress, "adaptive curve", reference,
+                                 adaptive_curve=True)
     line = {
         "metric": "tetrahedra/sec (exact 3D Delaunay, MIX: lattice + clusters + shell)",
         "value": res["plain"]["value"],
@@ -629,6 +639,8 @@ def run_mix(args):
                         speedup_vs_plain=round(res["learned"]["value"] / res["plain"]["value"], 4),
                         identical_output=bool(res["learned"]["identical"] and res["plain"]["identical"])),
         "plain": res["plain"],
+        "adaptive_curve": dict(res["adaptive"],
+                               speedup_vs_plain=round(res["adaptive"]["value"] / res["plain"]["value"], 4)),
         "output_sha256": digest,
         "oracle_hash_match": None if golden is None else digest == golden,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_points(

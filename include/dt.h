@@ -62,7 +62,8 @@ typedef struct {
     double round_fraction;  /* round size as a fraction of the current vertex count;
                                0: automatic                                              */
     uint32_t lanes_per_insert; /* lanes of a wavefront cooperating on one insertion in the
-                                  walk and cavity search: 4, 8, 16 or 64; 0: automatic   */
+                                  walk and cavity search: 4, 8, 16, 32 or 64; 0:
+                                  automatic (16)                                         */
     int scheduler;          /* DT_SCHED_PLAIN (0) or DT_SCHED_LEARNED (1: uses the model of
                                dt_load_model or dt_train_model; without one the call runs
                                the plain order and counts dt_stats.sched_fallbacks)      */
@@ -77,6 +78,13 @@ typedef struct {
                                cell by the curve's finer levels, an adaptive curve for
                                non-uniform inputs (the Conclusion's open point).  The
                                triangulation is the same either way.                     */
+    int subdet_cache;       /* 1: keep four sub-determinants per tetrahedron and the
+                               largest of its edge-vector coordinates (40 bytes) so that
+                               the cavity search's insphere test is a dot product that
+                               reads one vertex (Sec. 2.4); each new tetrahedron pays for
+                               them in the DelaunayBall step.  Signs the cached filter
+                               cannot decide go to the exact predicates; the result is the
+                               same.                                                     */
 } dt_options;
 
 enum { DT_SCHED_PLAIN = 0, DT_SCHED_LEARNED = 1 };

@@ -28,12 +28,13 @@ namespace {
 
 constexpr uint32_t DEFAULT_ROUND_MAX = 1u << 20;
 constexpr uint32_t DEFAULT_CAVITY_CAP = 128;
-constexpr uint32_t DEFAULT_LANES = 8;
+constexpr uint32_t DEFAULT_LANES = 16;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t ROUND_MIN = 64;
 constexpr uint32_t DRAIN_SLICE = 4096;  // candidates per round when draining overflowed cavities
 constexpr uint32_t EXPORT_CHUNK = 1u << 24;  // slots per staged export launch (a multiple of 64)
 constexpr size_t TET_BYTES = 64;               // one tetrahedron record, either layout
+constexpr size_t SUBD_BYTES = 40;              // its cached sub-determinants (dt_options.subdet_cache)
 // entries of each free list: slots freed while it is full stay unused (the pool has room for
 // them); in practice a round frees far fewer
 constexpr uint64_t FREE_LIST_MAX = 1ull << 26;
@@ -99,6 +100,7 @@ struct dt_ctx {
     DevBuf<uint8_t> dup;
     uint32_t tcap = 0;
     void *T = nullptr;       // Tet[tcap] (32-bit codes) or TetW[tcap] (64-bit codes)
+    void *subd = nullptr;    // dt_options.subdet_cache: SubD[tcap], the cached sub-determinants
     bool wide = false;       // the pool's layout
     uint64_t narrow_max = MAX_TETS;  // growth past this widens an automatic pool
     uint32_t flcap = 0;      // entries of each free list
@@ -279,14 +281,15 @@ int grow_tets(dt_ctx *c, uint64_t need) {
     uint64_t cap = std::max<uint64_t>(need, (uint64_t)c->tcap + c->tcap / 2);
     cap = std::min<uint64_t>(cap, max_tets);
     const uint32_t flcap = (uint32_t)std::min<uint64_t>(cap, FREE_LIST_MAX);
-    void *T = nullptr;
+    void *T = nullptr, *sd = nullptr;
     uint32_t *f0 = nullptr, *f1 = nullptr;
     bool ok = dev_alloc(c, &T, cap * TET_BYTES) == hipSuccess &&
               dev_alloc(c, (void **)&f0, (size_t)flcap * sizeof(uint32_t)) == hipSuccess &&
-              dev_alloc(c, (void **)&f1, (size_t)flcap * sizeof(uint32_t)) == hipSuccess;
+              dev_alloc(c, (void **)&f1, (size_t)flcap * sizeof(uint32_t)) == hipSuccess &&
+              (!c->opt.subdet_cache || dev_alloc(c, &sd, cap * SUBD_BYTES) == hipSuccess);
     if (!ok) {
         hipGetLastError();
-        dev_free(c, T); dev_free(c, f0); dev_free(c, f1);
+        dev_free(c, T); dev_free(c, f0); dev_free(c, f1); dev_free(c, sd);
         return fail(c, DT_E_CAPACITY, "device allocation for %llu tetrahedra failed", (unsigned long long)cap);
     }
     // claim words start above every stamp
@@ -298,10 +301,12 @@ int grow_tets(dt_ctx *c, uint64_t need) {
         uint64_t nf = std::min<uint64_t>(c->hctr->fl_n, flcap);
         HIPCHK(hipMemcpyAsync(c->fl_idx == 0 ? f0 : f1, c->fl[c->fl_idx], nf * sizeof(uint32_t),
                               hipMemcpyDeviceToDevice, c->stream));
+        if (sd && c->subd) HIPCHK(hipMemcpyAsync(sd, c->subd, used * SUBD_BYTES, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        dev_free(c, c->T); dev_free(c, c->fl[0]); dev_free(c, c->fl[1]);
+        dev_free(c, c->T); dev_free(c, c->fl[0]); dev_free(c, c->fl[1]); dev_free(c, c->subd);
     }
     c->T = T; c->fl[0] = f0; c->fl[1] = f1;
+    c->subd = sd;
     c->tcap = (uint32_t)cap;
     c->flcap = flcap;
     const bool widened = wide && !c->wide;
@@ -480,6 +485,7 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.novf_ptr = &d->list_count[oi];
     a.defer = c->defer;
     a.ndefer_ptr = &d->ndefer;
+    a.subd = c->subd;
     a.cav = c->cav;
     a.bnd = c->bnd;
     a.outc = c->outc;
@@ -1015,10 +1021,12 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
             return fail(c, DT_E_CAPACITY, "%llu points need more than %u tetrahedron slots with 32-bit adjacency "
                                           "codes (dt_options.index_bits = 64 or 0 lifts the limit)",
                         (unsigned long long)n, MAX_TETS);
-        if (c->tcap == 0 || c->tcap < std::min<uint64_t>(want, 7 * n + 4096 + 5ull * C) || c->wide != wide) {
+        if (c->tcap == 0 || c->tcap < std::min<uint64_t>(want, 7 * n + 4096 + 5ull * C) || c->wide != wide ||
+            (c->opt.subdet_cache != 0) != (c->subd != nullptr)) {
             if (c->tcap) {
-                dev_free(c, c->T); dev_free(c, c->fl[0]); dev_free(c, c->fl[1]);
+                dev_free(c, c->T); dev_free(c, c->fl[0]); dev_free(c, c->fl[1]); dev_free(c, c->subd);
                 c->T = nullptr;
+                c->subd = nullptr;
                 c->tcap = 0;
             }
             c->wide = wide;
@@ -1031,7 +1039,8 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
                               c->stream));
         HIPCHK(hipMemcpyAsync(&c->ctr->tet_count, &c->hctr->tet_count, sizeof(uint32_t), hipMemcpyHostToDevice,
                               c->stream));
-        HIPCHK(launch_init(c->V.p, c->clouds.p, C, 0, c->dup.p, c->T, c->wide, c->vtet.p, c->ctr, c->stream));
+        HIPCHK(launch_init(c->V.p, c->clouds.p, C, 0, c->dup.p, c->T, c->wide, c->vtet.p, c->ctr, c->subd,
+                           c->stream));
         if ((rc = sync_ctr(c))) return rc;
         if (c->hctr->error & ERR_DEGENERATE) {
             if (C == 1) return fail(c, DT_E_DEGENERATE, "fewer than four affinely independent distinct points");
@@ -1090,7 +1099,7 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
     else dt_default_options(&c->opt);
     if (c->opt.round_fraction < 0 || c->opt.round_fraction > 64 ||
         (c->opt.lanes_per_insert != 0 && c->opt.lanes_per_insert != 4 && c->opt.lanes_per_insert != 8 &&
-         c->opt.lanes_per_insert != 16 && c->opt.lanes_per_insert != 64) ||
+         c->opt.lanes_per_insert != 16 && c->opt.lanes_per_insert != 32 && c->opt.lanes_per_insert != 64) ||
         (c->opt.index_bits != 0 && c->opt.index_bits != 32 && c->opt.index_bits != 64)) {
         delete c;
         return DT_E_ARG;
@@ -1589,7 +1598,7 @@ int dt_destroy(dt_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     auto f = [](void *p) { if (p) hipFree(p); };
     f(c->V.p); f(c->vtet.p); f(c->anchor.p); f(c->dup.p);
-    f(c->T); f(c->fl[0]); f(c->fl[1]);
+    f(c->T); f(c->fl[0]); f(c->fl[1]); f(c->subd);
     for (int k = 0; k < 4; ++k) { f(c->lpt[k]); f(c->lrank[k]); }
     f(c->cav); f(c->bnd); f(c->outc); f(c->cnt); f(c->status);
     f(c->scr_v); f(c->scr_n); f(c->defer);

@@ -130,10 +130,12 @@ __device__ __forceinline__ int orient_new_tet(uint32_t w[4], int j) {
 // records (any choice gives the same triangulation), positively oriented, plus the four
 // ghosts (each holds G in slot 3, its finite facet facing outward), at slots
 // first_slot + 5 c .. + 4.
+static_assert(sizeof(SubD) == 40, "the host sizes the sub-determinant cache at 40 bytes per tetrahedron");
+
 template <class K>
 __global__ void k_init(const Vert *__restrict__ V, Cloud *__restrict__ clouds, uint32_t first_slot,
                        const uint8_t *__restrict__ dup, typename K::Rec *__restrict__ T, uint32_t *__restrict__ vtet,
-                       Ctr *__restrict__ ctr) {
+                       Ctr *__restrict__ ctr, SubD *__restrict__ subd) {
     using code = typename K::code;
     __shared__ uint32_t sel[4];
     __shared__ uint32_t best;
@@ -205,16 +207,17 @@ __global__ void k_init(const Vert *__restrict__ V, Cloud *__restrict__ clouds, u
         r.spare[0] = 0;
     }
     for (int k = 0; k < 4; ++k) vtet[v[k]] = s0;
+    if (subd) subd[s0] = subdets(vpos(V, v[0]), vpos(V, v[1]), vpos(V, v[2]), vpos(V, v[3]));
     clouds[c].any_live = s0;
 }
 
 hipError_t launch_init(const Vert *V, Cloud *clouds, uint32_t nclouds, uint32_t first_slot, const uint8_t *dup,
-                       void *T, bool wide, uint32_t *vtet, Ctr *ctr, hipStream_t s) {
+                       void *T, bool wide, uint32_t *vtet, Ctr *ctr, void *subd, hipStream_t s) {
     if (nclouds == 0) return hipSuccess;
     if (wide)
-        k_init<Wide><<<nclouds, 256, 0, s>>>(V, clouds, first_slot, dup, (TetW *)T, vtet, ctr);
+        k_init<Wide><<<nclouds, 256, 0, s>>>(V, clouds, first_slot, dup, (TetW *)T, vtet, ctr, (SubD *)subd);
     else
-        k_init<Narrow><<<nclouds, 256, 0, s>>>(V, clouds, first_slot, dup, (Tet *)T, vtet, ctr);
+        k_init<Narrow><<<nclouds, 256, 0, s>>>(V, clouds, first_slot, dup, (Tet *)T, vtet, ctr, (SubD *)subd);
     return hipGetLastError();
 }
 
@@ -388,7 +391,7 @@ __device__ __forceinline__ void lane_fence() {
 }
 
 // Walk (Sec. 2.3) and cavity search (Sec. 2.4) of one candidate per group of GS lanes
-// (4, 8, 16 or 64): the walk tests the four facets of the current tetrahedron on four lanes
+// (4, 8, 16, 32 or 64): the walk tests the four facets of the current tetrahedron on four lanes
 // at once, and the cavity search expands GS / 4 cavity tetrahedra (four facets each) per
 // step, appending cavity and boundary entries by ballot prefix counts.  Control flow is
 // uniform within each group.  Cavity entries hold (tetrahedron << 2 | facet it was entered
@@ -581,10 +584,17 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                         uint32_t r2[4];
 #pragma unroll
                         for (int m = 0; m < 4; ++m) r2[m] = m == sa ? rid[sb] : (m == sb ? rid[sa] : rid[m]);
-                        const int si = cav_insphere<FULL>(vpos(a.V, r2[0]), vpos(a.V, r2[1]), vpos(a.V, r2[2]),
-                                                          vpos(a.V, r2[3]), P,
-                                                          [&](int kk) { return kk < 4 ? a.V[r2[kk]].idx : pv.idx; },
-                                                          st);
+                        int si;
+                        if (!FULL && a.subd) {
+                            // cached sub-determinants of u (its stored vertex order is positive too,
+                            // an even permutation of r2, so the sign is the same)
+                            st.insphere++;
+                            si = insphere_cached(static_cast<const SubD *>(a.subd)[u], vpos(a.V, uw.x), P);
+                        } else {
+                            si = cav_insphere<FULL>(vpos(a.V, r2[0]), vpos(a.V, r2[1]), vpos(a.V, r2[2]),
+                                                    vpos(a.V, r2[3]), P,
+                                                    [&](int kk) { return kk < 4 ? a.V[r2[kk]].idx : pv.idx; }, st);
+                        }
                         inside = si < 0;
                         undecided = si == UNDECIDED;
                     } else if (!cghost) {
@@ -830,6 +840,9 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
             uint32_t wv[4] = {cw.x, cw.y, cw.z, cw.w};
             wv[f] = p;
             T[slot].v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+            if (a.subd && wv[3] != GHOST)
+                static_cast<SubD *>(a.subd)[slot] =
+                    subdets(vpos(a.V, wv[0]), vpos(a.V, wv[1]), vpos(a.V, wv[2]), vpos(a.V, wv[3]));
             const code me = make_code<K>(slot, (uint32_t)f);
             nref(T, slot, f) = oc;                            // facet opposite p: the outer tetrahedron
             nref(T, code_slot(oc), code_facet(oc)) = me;      // and back
@@ -1059,6 +1072,9 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
         k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 8) {
         k_cavity_g<K, 8, LCAPC, LHM, false, false, false><<<(max_cand + 31) / 32, 256, 0, s>>>(a);
+        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+    } else if (lanes == 32) {
+        k_cavity_g<K, 32, LCAPC, LHM, false, false, false><<<(max_cand + 7) / 8, 256, 0, s>>>(a);
         k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 64) {
         k_cavity_g<K, 64, LCAPC, LHM, false, false, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);

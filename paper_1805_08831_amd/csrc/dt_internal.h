@@ -158,6 +158,7 @@ struct RoundArgs {
     const uint32_t *ncand_ptr;   // device count of the current list
     uint32_t *nnext_ptr;         // device count of the next list
     uint32_t *novf_ptr;          // device count of the overflow list
+    void *subd;                  // if set: [tcap] cached sub-determinants (SubD) of each finite tetrahedron
     uint32_t *defer;             // [stride] candidates handed to the exact-predicate pass
     uint32_t *ndefer_ptr;        // device count of them (reset at the round's end)
     void *cav;                   // [stride][capC] cavity tetrahedra (code 4 t + entry facet)
@@ -249,7 +250,7 @@ hipError_t launch_labels(const Vert *V, uint64_t base, uint64_t n, const Cloud *
 // Every wrapper that touches the pool takes `wide`: the pool holds TetW records with 64-bit
 // codes (true) or Tet records with 32-bit codes (false).
 hipError_t launch_init(const Vert *V, Cloud *clouds, uint32_t nclouds, uint32_t first_slot, const uint8_t *dup,
-                       void *T, bool wide, uint32_t *vtet, Ctr *ctr, hipStream_t s);
+                       void *T, bool wide, uint32_t *vtet, Ctr *ctr, void *subd, hipStream_t s);
 hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, const uint32_t *lvl_size,
                             const uint32_t *lvl_bits, const unsigned long long *rank_base, const uint32_t *lord,
                             const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank,

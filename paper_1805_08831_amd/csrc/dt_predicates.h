@@ -411,6 +411,59 @@ __device__ __forceinline__ int insphere_perturbed(P3 a, P3 b, P3 c, P3 d, P3 e, 
     return insphere_perturbed_tail(a, b, c, d, e, key, &st);
 }
 
+// ------------------------------------------------------------------ cached sub-determinants
+
+// Sec. 2.4 caches four sub-determinants per tetrahedron so that insphere becomes a dot
+// product.  For a positive tetrahedron (a, b, c, d) with u = b - a, v = c - a, w = d - a and
+// the lifts |u|^2, |v|^2, |w|^2, the lifted 5x5 determinant with a fifth point e is
+// det = x . C with x = (e - a, |e - a|^2) and C = (-M1, M2, -M3, M4), Mk the 3x3 minor of
+// [u |u|^2; v |v|^2; w |w|^2] without column k (M4 = orient3d(a, b, c, d)).  The record also
+// keeps m, the largest magnitude of the nine rounded differences, which the filter's error
+// bound needs; a query then reads a and the record, not b, c and d.
+struct SubD {
+    double c[4];
+    double m;
+};
+
+__device__ __forceinline__ double det3r(double p0, double p1, double p2, double q0, double q1, double q2, double r0,
+                                        double r1, double r2) {
+    return p0 * (q1 * r2 - q2 * r1) - p1 * (q0 * r2 - q2 * r0) + p2 * (q0 * r1 - q1 * r0);
+}
+
+__device__ __forceinline__ SubD subdets(P3 a, P3 b, P3 c, P3 d) {
+    const double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
+    const double vx = c.x - a.x, vy = c.y - a.y, vz = c.z - a.z;
+    const double wx = d.x - a.x, wy = d.y - a.y, wz = d.z - a.z;
+    const double lu = ux * ux + uy * uy + uz * uz, lv = vx * vx + vy * vy + vz * vz, lw = wx * wx + wy * wy + wz * wz;
+    SubD r;
+    r.c[0] = -det3r(uy, uz, lu, vy, vz, lv, wy, wz, lw);
+    r.c[1] = det3r(ux, uz, lu, vx, vz, lv, wx, wz, lw);
+    r.c[2] = -det3r(ux, uy, lu, vx, vy, lv, wx, wy, lw);
+    r.c[3] = det3r(ux, uy, uz, vx, vy, vz, wx, wy, wz);
+    r.m = fmax(fmax(fmax(fabs(ux), fabs(uy)), fmax(fabs(uz), fabs(vx))),
+               fmax(fmax(fmax(fabs(vy), fabs(vz)), fmax(fabs(wx), fabs(wy))), fabs(wz)));
+    return r;
+}
+
+// Sign of the lifted determinant of (a, b, c, d, e) from the cached record of (a, b, c, d), or
+// 2 when the fp64 filter cannot decide.  Error bound: each cached minor's monomials (two
+// rounded differences and one rounded lift) carry at most 13 roundings, so with M the largest
+// magnitude of the rounded differences b - a, c - a, d - a, e - a, |C1..3| <= 18 M^4 and
+// |C4| <= 6 M^3 are off by at most gamma_13 of that; the query's differences add one rounding
+// and its lift five; the dot product seven.  The sum stays below 1400 u M^5 < 2^-42 M^5; the
+// filter uses 2^-40 M^5.
+__device__ __forceinline__ int insphere_cached(const SubD &C, P3 a, P3 e) {
+    const double x0 = e.x - a.x, x1 = e.y - a.y, x2 = e.z - a.z;
+    const double x3 = x0 * x0 + x1 * x1 + x2 * x2;
+    const double det = ((x0 * C.c[0] + x1 * C.c[1]) + x2 * C.c[2]) + x3 * C.c[3];
+    const double M = fmax(fmax(C.m, fabs(x0)), fmax(fabs(x1), fabs(x2)));
+    const double M2 = M * M;
+    const double bound = (M2 * M2) * M * 0x1p-40;
+    if (det > bound) return 1;
+    if (-det > bound) return -1;
+    return 2;
+}
+
 // filtered orient2d-free collinearity test used only by the initial tetrahedron search
 __device__ __forceinline__ bool collinear(P3 a, P3 b, P3 c) {
     double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;

@@ -27,7 +27,7 @@ class dt_options(ctypes.Structure):
                 ("cavity_cap", ctypes.c_uint32), ("capacity_tets", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("max_rounds", ctypes.c_uint32), ("timing", ctypes.c_int), ("round_fraction", ctypes.c_double),
                 ("lanes_per_insert", ctypes.c_uint32), ("scheduler", ctypes.c_int), ("log_points", ctypes.c_int),
-                ("index_bits", ctypes.c_int), ("adaptive_curve", ctypes.c_int)]
+                ("index_bits", ctypes.c_int), ("adaptive_curve", ctypes.c_int), ("subdet_cache", ctypes.c_int)]
 
 DT_SCHED_PLAIN, DT_SCHED_LEARNED = 0, 1
 NFEAT, NHID, NOUT = 16, 64, 3
@@ -349,7 +349,7 @@ class Triangulation:
 
     def __init__(self, device=0, stream=None, round_size=0, cavity_cap=0, capacity_tets=0, seed=0x5EED,
                  max_rounds=0, timing=False, round_fraction=0.0, lanes_per_insert=0, scheduler=0, log_points=False,
-                 index_bits=0, adaptive_curve=False):
+                 index_bits=0, adaptive_curve=False, subdet_cache=False):
         o = dt_default_options()
         o.device, o.round_size, o.cavity_cap = int(device), int(round_size), int(cavity_cap)
         o.capacity_tets, o.seed, o.max_rounds = int(capacity_tets), int(seed), int(max_rounds)
@@ -358,6 +358,7 @@ class Triangulation:
         o.scheduler, o.log_points = int(scheduler), int(bool(log_points))
         o.index_bits = int(index_bits)
         o.adaptive_curve = int(bool(adaptive_curve))
+        o.subdet_cache = int(bool(subdet_cache))
         o.stream = stream
         self.ctx = dt_create(o)
 

@@ -142,6 +142,36 @@ def test_adaptive_curve_sort_matches_oracle(dtlib, oracle_mod, kind, n):
     assert np.array_equal(perm.astype(np.int64), rperm)
 
 
+@pytest.mark.parametrize("case", ["uniform", "mix", "lattice6", "sphere", "widened"])
+def test_subdet_cache_keeps_result(dtlib, oracle_mod, case):
+    """Cached sub-determinants (Sec. 2.4): the cavity search's insphere as a dot product with a
+    filter bound of its own; undecided signs go to the exact predicates.  Same triangulation;
+    the pool grows (the cache is copied) and is widened in one case."""
+    say(f"sub-determinant cache, {case}")
+    xyz = {
+        "uniform": lambda: uniform_points(30000, 401),
+        "mix": lambda: mix_small(402, 6000),
+        "lattice6": lambda: np.random.default_rng(3).permutation(
+            np.array(list(itertools.product(np.arange(6.0) / 8, repeat=3)))),
+        "sphere": lambda: sphere50(),
+        "widened": lambda: uniform_points(20000, 403),
+    }[case]()
+    opts = dict(subdet_cache=True)
+    if case in ("uniform", "widened"):
+        opts["capacity_tets"] = 4096  # grows several times
+    with dtlib.Triangulation(**opts) as tri:
+        if case == "widened":
+            dtlib.dt_debug_widen_at(tri.ctx, 40000)
+        tri.insert(np.ascontiguousarray(xyz, dtype=np.float64))
+        t, nb = tri.tets()
+        st = tri.stats()
+    assert_parity(oracle_mod, xyz, t.astype(np.int64), f"subdet cache {case}")
+    if case == "widened":
+        assert st["index_bits"] == 64
+    if len(xyz) < 10000:
+        check_invariants(xyz, t.astype(np.int64), nb, oracle_mod, expect_vertices=np.arange(len(xyz)))
+
+
 def test_adaptive_curve_keeps_result(dtlib, oracle_mod):
     say("adaptive curve triangulation")
     xyz = mix_small(53, 6000)
@@ -252,7 +282,8 @@ def test_append_and_clear(dtlib, oracle_mod):
 @pytest.mark.parametrize("opts", [dict(cavity_cap=4), dict(cavity_cap=12), dict(round_size=64),
                                   dict(round_size=1 << 16), dict(round_fraction=2.0), dict(seed=99),
                                   dict(lanes_per_insert=4), dict(lanes_per_insert=16),
-                                  dict(lanes_per_insert=64), dict(lanes_per_insert=4, cavity_cap=200),
+                                  dict(lanes_per_insert=32), dict(lanes_per_insert=64),
+                                  dict(lanes_per_insert=4, cavity_cap=200),
                                   dict(cavity_cap=2048), dict(lanes_per_insert=16, cavity_cap=1500),
                                   dict(capacity_tets=4096)])
 def test_launch_options_do_not_change_result(dtlib, oracle_mod, opts):
@@ -405,7 +436,7 @@ def test_autotune_keeps_results(dtlib, oracle_mod):
     say("autotune on a 20000-point sample, then a triangulation with the chosen options")
     with dtlib.Triangulation() as tri:
         best = tri.autotune(uniform_points(20000, 31))
-        assert best["lanes_per_insert"] in (4, 8, 16, 64) and best["cavity_cap"] in (64, 128)
+        assert best["lanes_per_insert"] in (4, 8, 16, 32, 64) and best["cavity_cap"] in (64, 128)
         assert best["round_fraction"] in (1 / 32, 1 / 16, 1 / 8) and best["ms"] > 0
         assert tri.stats()["points"] == 0
         xyz = uniform_points(5000, 32)

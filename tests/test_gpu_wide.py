@@ -13,7 +13,7 @@ from validators import check_invariants
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("opts", [dict(), dict(lanes_per_insert=4), dict(lanes_per_insert=16),
+@pytest.mark.parametrize("opts", [dict(), dict(lanes_per_insert=4), dict(lanes_per_insert=16), dict(lanes_per_insert=32),
                                   dict(lanes_per_insert=64), dict(cavity_cap=12),
                                   dict(lanes_per_insert=4, cavity_cap=200), dict(cavity_cap=2048),
                                   dict(capacity_tets=4096), dict(round_size=64)])
