@@ -188,10 +188,14 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2_500_000,
                     help="uniform: the oracle's CPU sample, the first points of the timed input (about 10 s "
                          "on one core)")
+    ap.add_argument("--walk-cap", type=int, default=0,
+                    help="walk steps after which a regular round's attempt resumes next round (0: automatic, -1: none)")
     ap.add_argument("--subdet-cache", action="store_true",
                     help="cache four sub-determinants per tetrahedron (the paper's Sec. 2.4 optimization)")
     ap.add_argument("--adaptive-curve", action="store_true",
                     help="Moore curve on the deepest grid the key holds (adaptive order for non-uniform inputs)")
+    ap.add_argument("--phase-clocks", action="store_true",
+                    help="after the timed steps, one instrumented step: per-attempt clocks of the cavity kernel")
     ap.add_argument("--no-export", action="store_true",
                     help="uniform: a step ends with the tetrahedron count (for pools too large to hold the "
                          "output beside them, 5e8 points)")
@@ -259,6 +263,10 @@ def main():
         oracle_match = main_run["hash"] == golden
         progress(f"whole output against the stored oracle hash: {'equal' if oracle_match else 'DIFFERENT'}")
 
+    clocks = None
+    if args.phase_clocks:
+        clocks = phase_clocks(main_run["d_xyz"], args.lanes, progress)
+
     model = training = None
     learned = None
     if not args.no_learned:
@@ -322,6 +330,8 @@ def main():
         "u8": u8,
         "detail": main_run["detail"],
     }
+    if clocks is not None:
+        line["phase_clocks"] = clocks
     print(json.dumps(line), flush=True)
 
 
@@ -385,10 +395,13 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     tri = Triangulation(device=0, stream=stream.cuda_stream, timing=True,
                         round_fraction=args.round_fraction, round_size=args.round_size,
                         lanes_per_insert=args.lanes, subdet_cache=args.subdet_cache,
-                        adaptive_curve=args.adaptive_curve)
+                        adaptive_curve=args.adaptive_curve,
+                        walk_cap=0xFFFFFFFF if args.walk_cap < 0 else args.walk_cap)
     tuned = None
     if args.autotune:
-        tuned = tri.autotune(torch.from_numpy(uniform_points(2_000_000, seed + 2)).cuda())
+        # tuned at the timed size, on another seed (the choice is kept for that size class)
+        tuned = tri.autotune(torch.from_numpy(uniform_points(n, seed + 2)).cuda())
+        progress(f"autotuned at {n} points: {tuned}")
 
     # output buffers sized once (outside the timed region) from a first run; without export
     # (pools too large to hold the output beside them) a step ends with the count
@@ -412,7 +425,7 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     times = []
     T = 0
     agg = dict(attempts=0, walk=0, cav=0, bnd=0, won=0, ms_cav=0.0, ms_ball=0.0, launches=0, rounds=0,
-               orient=0, orient_exact=0, insphere=0, insphere_exact=0, perturbed=0, conflicts=0,
+               orient=0, orient_exact=0, insphere=0, insphere_exact=0, perturbed=0, conflicts=0, walk_caps=0,
                ms_sort=0.0, ms_insert=0.0, ball_launches=0)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -432,6 +445,7 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
         agg["launches"] += s["cavity_launches"]
         agg["rounds"] += s["rounds"]
         agg["conflicts"] += s["conflicts"]
+        agg["walk_caps"] += s["walk_caps"]
         agg["ms_sort"] += s["ms_sort"]
         agg["ball_launches"] += s["ball_launches"]
         agg["ms_insert"] += s["ms_insert"]
@@ -445,6 +459,18 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     canon = canonical_device(out_t[:T]) if export else None
     digest = sha256_of(canon) if export else None
     st_last = tri.stats()
+    if tuned:
+        # the same steps with the default launch configuration, for comparison
+        tri.autotune_reset()
+        full_step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            full_step()
+        torch.cuda.synchronize()
+        tuned = dict(tuned, defaults_ms_per_step=round(1000.0 * (time.perf_counter() - t1) / steps, 3),
+                     tuned_ms_per_step=round(ms_per_step, 3))
+        progress(f"defaults: {tuned['defaults_ms_per_step']} ms per step")
     tri.close()
     del out_n
 
@@ -465,7 +491,7 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     b_att = cavity_bytes_per_attempt(walk, C, F)
     att_achieved = b_att * agg["attempts"] / launches / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
     default_launch = (lanes == 16 and not args.round_fraction and not args.round_size and n == 10_000_000
-                      and seed == 1007 and not args.subdet_cache and not args.adaptive_curve)
+                      and seed == 1007 and not args.subdet_cache and not args.adaptive_curve and not args.walk_cap)
     roofline = {"bound": "hbm", "kernel": f"k_cavity_g<{lanes}>", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "GB/s", "frac": round(achieved / peak, 5),
                 # measured HBM bytes per launch (counter summary), only for the launch it was taken on
@@ -483,6 +509,8 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
             "bytes_per_insertion": round(ball_per_ins, 1), "avg_launch_ms": round(ball_ms, 4)}
     detail = {"rounds_per_step": agg["rounds"] / steps, "attempts_per_point": agg["attempts"] / max(n * steps, 1),
               "conflict_rate": agg["conflicts"] / att, "walk_steps_per_attempt": round(walk, 3),
+              # attempts stopped by the walk cap (among the conflicts: they retry next round)
+              "walk_cap_rate": agg["walk_caps"] / att,
               "cavity_tets": round(C, 2), "boundary_facets": round(F, 2),
               "ms_cavity_kernel_per_step": round(agg["ms_cav"] / steps, 3),
               "ms_ball_kernel_per_step": round(agg["ms_ball"] / steps, 3),
@@ -500,6 +528,104 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     return {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3), "tetrahedra": T,
             "roofline": roofline, "detail": detail, "tuned": tuned, "hash": digest, "canon": canon,
             "d_xyz": d_xyz}
+
+
+def phase_clocks(d_xyz, lanes, progress):
+    """One untimed step of the plain path with the library's trace level 2: per round, the
+    filter pass's per-attempt wall clocks (walk, cavity, whole attempt, launch span), read back
+    after every round.  Summarised over the step: the launch spans add up to the filter pass's
+    time; the median attempt against the span shows how much of a launch is its tail."""
+    import tempfile
+
+    import torch
+
+    from paper_1805_08831_amd import Triangulation
+
+    old = os.environ.get("DT_TRACE")
+    os.environ["DT_TRACE"] = "2"
+    sys.stderr.flush()
+    saved = os.dup(2)
+    with tempfile.TemporaryFile(mode="w+") as fh:
+        try:
+            os.dup2(fh.fileno(), 2)
+            stream = torch.cuda.current_stream()
+            with Triangulation(device=0, stream=stream.cuda_stream, lanes_per_insert=lanes) as tri:
+                tri.insert(d_xyz)
+                torch.cuda.synchronize()
+        finally:
+            os.dup2(saved, 2)
+            os.close(saved)
+            if old is None:
+                del os.environ["DT_TRACE"]
+            else:
+                os.environ["DT_TRACE"] = old
+        fh.seek(0)
+        lines = [ln for ln in fh if ln.startswith(("clocks ", "ballclocks "))]
+    out = summarise_clocks(lines)
+    if out is not None:
+        progress(f"phase clocks: {out}")
+    return out
+
+
+def summarise_clocks(lines):
+    """Summary of the library's per-round `clocks` and `ballclocks` trace lines (see
+    phase_clocks)."""
+    import re
+    balls = []
+    for ln in lines:
+        if ln.startswith("ballclocks "):
+            kv = dict(re.findall(r"(\w+)=([\d./]+)", ln))
+            balls.append({k: [float(x) for x in v.split("/")] for k, v in kv.items()})
+    lines = [ln for ln in lines if ln.startswith("clocks ")]
+    rows = []
+    for ln in lines:
+        kv = dict(re.findall(r"(\w+)=([\d./]+)", ln))
+        q = {k: [float(x) for x in v.split("/")] for k, v in kv.items()}
+        rows.append(q)
+    if not rows:
+        return None
+    span = sum(r["span_us"][0] for r in rows)
+    att50 = sum(r["att_us"][0] for r in rows)
+    att90 = sum(r["att_us"][1] for r in rows)
+    walk50 = sum(r["walk_us"][0] for r in rows)
+    cav50 = sum(r["cav_us"][0] for r in rows)
+    n = sum(r["n"][0] for r in rows)
+    big = [r for r in rows if r["n"][0] >= 4096]
+    out = {
+        "rounds": len(rows), "attempts": int(n),
+        "sum_span_ms": round(span / 1000, 3),
+        # per round: the median attempt, the 90th percentile and the span, summed over rounds
+        "sum_att_p50_ms": round(att50 / 1000, 3), "sum_att_p90_ms": round(att90 / 1000, 3),
+        "median_attempt_share_of_span": round(att50 / span, 4),
+        "walk_share_of_median_attempt": round(walk50 / max(walk50 + cav50, 1e-9), 4),
+        "walk_steps_per_attempt": round(sum(r["walk_steps"][0] * r["n"][0] for r in rows) / n, 3),
+        "cavity_steps_per_attempt": round(sum(r["cav_steps"][0] * r["n"][0] for r in rows) / n, 3),
+        "rounds_4096_or_more": {
+            "rounds": len(big),
+            "sum_span_ms": round(sum(r["span_us"][0] for r in big) / 1000, 3),
+            "att_us_p50_p90_p99_max_mean": [round(sum(r["att_us"][k] for r in big) / max(len(big), 1), 2)
+                                            for k in range(4)],
+            "walk_us_p50_mean": round(sum(r["walk_us"][0] for r in big) / max(len(big), 1), 2),
+            "cav_us_p50_mean": round(sum(r["cav_us"][0] for r in big) / max(len(big), 1), 2),
+            "span_us_mean": round(sum(r["span_us"][0] for r in big) / max(len(big), 1), 2)},
+        "rounds_below_4096": {
+            "rounds": len(rows) - len(big),
+            "sum_span_ms": round(sum(r["span_us"][0] for r in rows if r["n"][0] < 4096) / 1000, 3)},
+    }
+    if balls:
+        bb = [b for b in balls if b["n"][0] >= 4096]
+        mean = lambda key, k: round(sum(b[key][k] for b in bb) / max(len(bb), 1), 2)  # noqa: E731
+        out["ball"] = {
+            "rounds": len(balls), "sum_span_ms": round(sum(b["span_us"][0] for b in balls) / 1000, 3),
+            "rounds_4096_or_more": {
+                "rounds": len(bb), "span_us_mean": mean("span_us", 0),
+                # winner test + slot reservation, cavity copies, building: median and 90th
+                # percentile per round, averaged over the rounds
+                "test_us_p50_p90": [mean("test_us", 0), mean("test_us", 1)],
+                "copy_us_p50_p90": [mean("copy_us", 0), mean("copy_us", 1)],
+                "build_us_p50_p90": [mean("build_us", 0), mean("build_us", 1)],
+                "ball_us_p50_p90_p99_max": [mean("ball_us", k) for k in range(4)]}}
+    return out
 
 
 def compare_schedulers(d_xyz, model, steps, warmup, progress, reference, export=True):
@@ -569,7 +695,7 @@ def timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference=Non
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     agg = dict(rounds=0, attempts=0, conflicts=0, overflows=0, walk_steps=0, perturbed=0, insphere_exact=0,
-               orient_exact=0)
+               orient_exact=0, walk_caps=0)
     T = 0
     for _ in range(steps):
         tri.clear()

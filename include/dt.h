@@ -85,6 +85,11 @@ typedef struct {
                                them in the DelaunayBall step.  Signs the cached filter
                                cannot decide go to the exact predicates; the result is the
                                same.                                                     */
+    uint32_t walk_cap;      /* walk steps after which an attempt of a regular round stops;
+                               its point retries in the next round, resuming the walk from
+                               where it stopped (a launch then ends with its typical
+                               attempts, not with one long walk).  0: automatic (16);
+                               UINT32_MAX: no cap.  The result never depends on it.      */
 } dt_options;
 
 enum { DT_SCHED_PLAIN = 0, DT_SCHED_LEARNED = 1 };
@@ -119,6 +124,8 @@ typedef struct {
     uint64_t dropped_slots;   /* freed slots left unused because the free list was full  */
     uint64_t deferred;        /* attempts whose fp64 filter left a sign undecided, run
                                  again with exact predicates in the same round           */
+    uint64_t walk_caps;       /* attempts stopped by dt_options.walk_cap (counted among
+                                 the conflicts too: they retry in the next round)        */
 } dt_stats;
 
 /* Fill *opt with the defaults (device 0, library stream, automatic sizes, seed 0x5EED). */
@@ -172,13 +179,19 @@ int dt_insert_batch(dt_ctx *ctx, const double *xyz, const uint64_t *offsets, uin
 int dt_get_tets_batch(dt_ctx *ctx, uint32_t cloud, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
 
 /* Autotuner: triangulates the n sample points (host or device memory) once per launch
-   configuration - lanes per insertion {4, 8, 16, 64} (64: one wavefront per insertion),
-   round fraction {1/32, 1/16, 1/8}, cavity cap {64, 128} - after one warm-up run, and keeps
-   the fastest (host wall time of dt_insert_points) in the context's options.  *best (may be
-   NULL) receives the chosen options, *best_ms (may be NULL) its time.  The context must be
-   empty and is empty again on return; the statistics are reset.  Results never depend on
-   these options. */
+   configuration - lanes per insertion {8, 16, 32, 64} (64: one wavefront per insertion),
+   round fraction {3/64, 1/16, 3/32}, cavity cap {64, 128} - after one warm-up run, and keeps
+   the fastest (host wall time of dt_insert_points) for the sample's size class,
+   floor(log2 n).  Later insertions use the choice of the tuned class nearest to their own
+   point count (ties to the larger class); with no class tuned, dt_options decide.  Tune at
+   the size that will be run: choices do not carry over between sizes.  *best (may be NULL)
+   receives the chosen options, *best_ms (may be NULL) its time.  The context must be empty
+   and is empty again on return; the statistics are reset.  Results never depend on these
+   options. */
 int dt_autotune(dt_ctx *ctx, const double *xyz, uint64_t n, dt_options *best, double *best_ms);
+
+/* Forgets every choice of dt_autotune; insertions use dt_options again. */
+int dt_autotune_reset(dt_ctx *ctx);
 
 /* ---- learned insertion scheduler (not in the paper; the output never depends on it) ----
    An MLP 16 -> 64 -> 64 -> 3 (BF16 weights, FP32 accumulation) maps features of each point

@@ -30,6 +30,7 @@ constexpr uint32_t DEFAULT_ROUND_MAX = 1u << 20;
 constexpr uint32_t DEFAULT_CAVITY_CAP = 128;
 constexpr uint32_t DEFAULT_LANES = 16;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
+constexpr uint32_t DEFAULT_WALK_CAP = 16;
 constexpr uint32_t ROUND_MIN = 64;
 constexpr uint32_t DRAIN_SLICE = 4096;  // candidates per round when draining overflowed cavities
 constexpr uint32_t EXPORT_CHUNK = 1u << 24;  // slots per staged export launch (a multiple of 64)
@@ -96,7 +97,7 @@ struct dt_ctx {
     int ovf_idx = 0;
 
     DevBuf<Vert> V;
-    DevBuf<uint32_t> vtet, anchor;
+    DevBuf<uint32_t> vtet, anchor, lastt;
     DevBuf<uint8_t> dup;
     uint32_t tcap = 0;
     void *T = nullptr;       // Tet[tcap] (32-bit codes) or TetW[tcap] (64-bit codes)
@@ -111,6 +112,16 @@ struct dt_ctx {
     size_t bufC = 0, bufF = 0;
     uint32_t capC = 0, capF = 0;
     uint32_t lanes = 8;  // lanes per insertion of the cavity kernel
+    double frac = 0;     // round size as a fraction of the mesh's vertices
+    uint32_t call_clouds = 1;  // clouds of the insertion call in progress
+    // dt_autotune's choices by size class (floor(log2 n) of the sample): an insertion takes
+    // the choice of the nearest tuned class; without any, the options decide
+    struct Tuned {
+        bool set = false;
+        uint32_t lanes = 0, cap = 0;
+        double frac = 0;
+        double ms = 0;
+    } tuned[64];
     uint32_t *defer = nullptr;             // candidates handed to the exact-predicate pass
     void *cav = nullptr, *outc = nullptr;  // adjacency codes (4 or 8 bytes each)
     uint32_t *bnd = nullptr, *cnt = nullptr;
@@ -172,7 +183,12 @@ struct dt_ctx {
     // scratch of dt_debug_sort (kept apart from the mesh's own buffers)
     DevBuf<Vert> dbgV;
     DevBuf<Cloud> dbg_cloud;
-    bool trace = false;  // DT_TRACE=1 in the environment: one line per round on stderr
+    // DT_TRACE=1 in the environment: one line per round on stderr; DT_TRACE=2 adds the
+    // distribution of the filter pass's per-attempt clocks (walk, cavity, launch span)
+    int trace = 0;
+    unsigned long long *clk[3] = {nullptr, nullptr, nullptr};  // per snapshot slot
+    uint32_t clk_cap[3] = {0, 0, 0};
+    std::vector<unsigned long long> clk_host;
     // Device memory source: hipMalloc, or (no-allocation entry point) a bump arena carved
     // from the library's static scratch array, reset at every call; then nothing is freed,
     // events are not used (rounds complete by stream synchronization) and the counters'
@@ -413,6 +429,27 @@ int grow_tets(dt_ctx *c, uint64_t need);
 void apply_options(dt_ctx *c) {
     c->capC = c->opt.cavity_cap ? c->opt.cavity_cap : DEFAULT_CAVITY_CAP;
     c->lanes = c->opt.lanes_per_insert ? c->opt.lanes_per_insert : DEFAULT_LANES;
+    c->frac = c->opt.round_fraction > 0 ? c->opt.round_fraction : DEFAULT_ROUND_FRACTION;
+    c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
+}
+
+int size_class(uint64_t n) { return n ? 63 - __builtin_clzll(n) : 0; }
+
+// The launch configuration of an insertion of n points: the autotuner's choice for the
+// nearest tuned size class (ties to the larger), else the options.
+void select_launch(dt_ctx *c, uint64_t n) {
+    apply_options(c);
+    const int k = size_class(n);
+    int best = -1;
+    for (int j = 0; j < 64; ++j)
+        if (c->tuned[j].set && (best < 0 || std::abs(j - k) < std::abs(best - k) ||
+                                (std::abs(j - k) == std::abs(best - k) && j > best)))
+            best = j;
+    if (best < 0) return;
+    const dt_ctx::Tuned &t = c->tuned[best];
+    c->lanes = t.lanes;
+    c->capC = t.cap;
+    c->frac = t.frac;
     c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
 }
 
@@ -466,6 +503,9 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     a.vlo = (uint32_t)base;
     a.vhi = (uint32_t)(base + n);
     a.anchor = c->anchor.p;
+    a.lastt = c->lastt.p;
+    a.multi = c->call_clouds > 1 ? 1u : 0u;
+    a.walk_cap = c->opt.walk_cap ? c->opt.walk_cap : DEFAULT_WALK_CAP;
     a.clouds = c->clouds.p;
     a.log_att = c->logged ? c->log_att.p : nullptr;
     a.wbucket = c->learned_active ? c->wbucket.p : nullptr;
@@ -511,6 +551,18 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     if ((c->round_counter & 0xFFFFFFFFull) == 0 && c->round_counter != 0 && c->tcap)
         HIPCHK(launch_reset_claims(c->T, c->wide, c->tcap, c->stream));
     a.round_hi = (0xFFFFFFFFull - (c->round_counter & 0xFFFFFFFFull)) << 32;
+    a.clk = nullptr;
+    if (c->trace >= 2 && max_cand) {
+        if (c->clk_cap[slot] < max_cand) {
+            if (c->clk[slot]) hipFree(c->clk[slot]);
+            c->clk[slot] = nullptr;
+            c->clk_cap[slot] = 0;
+            HIPCHK(hipMalloc((void **)&c->clk[slot], 8ull * max_cand * sizeof(unsigned long long)));
+            c->clk_cap[slot] = max_cand;
+        }
+        HIPCHK(hipMemsetAsync(c->clk[slot], 0, 8ull * max_cand * sizeof(unsigned long long), c->stream));
+        a.clk = c->clk[slot];
+    }
     c->round_counter++;
     HIPCHK(launch_round(a, c->wide, max_cand, c->lanes, c->stream, c->opt.timing ? c->ev[slot] : nullptr));
     HIPCHK(launch_round_end(a, max_cand, c->stream));
@@ -522,6 +574,68 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     c->st.rounds++;
     *slot_out = slot;
     return DT_OK;
+}
+
+// Trace mode 2: the filter pass's per-attempt clocks of the round in `slot` (10 ns ticks),
+// summarised on stderr as quantiles of the walk, cavity and whole-attempt durations, the
+// launch span (first start to last end) and the mean walk and cavity steps.
+void trace_clocks(dt_ctx *c, int slot, uint32_t max_cand) {
+    std::vector<unsigned long long> &h = c->clk_host;
+    h.resize(8ull * max_cand);
+    if (hipMemcpy(h.data(), c->clk[slot], h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+        hipGetLastError();
+        return;
+    }
+    std::vector<double> walk, cav, att;
+    unsigned long long lo = ~0ull, hi = 0;
+    double ws = 0, cs = 0;
+    std::vector<double> test, copy, build, ball;
+    unsigned long long blo = ~0ull, bhi = 0;
+    for (uint32_t i = 0; i < max_cand; ++i) {
+        const unsigned long long *b = &h[8ull * i + 4];
+        if (b[0] && b[1] >= b[0]) {
+            test.push_back(0.01 * (double)(b[1] - b[0]));
+            blo = std::min(blo, b[0]);
+            bhi = std::max(bhi, b[1]);
+            if (b[2] >= b[1] && b[3] >= b[2] && b[3]) {
+                copy.push_back(0.01 * (double)(b[2] - b[1]));
+                build.push_back(0.01 * (double)(b[3] - b[2]));
+                ball.push_back(0.01 * (double)(b[3] - b[0]));
+                bhi = std::max(bhi, b[3]);
+            }
+        }
+    }
+    for (uint32_t i = 0; i < max_cand; ++i) {
+        const unsigned long long *r = &h[8ull * i];
+        if (r[0] == 0 || r[2] < r[0] || r[1] < r[0]) continue;  // not run (slot of a shorter list)
+        walk.push_back(0.01 * (double)(r[1] - r[0]));
+        cav.push_back(0.01 * (double)(r[2] - r[1]));
+        att.push_back(0.01 * (double)(r[2] - r[0]));
+        lo = std::min(lo, r[0]);
+        hi = std::max(hi, r[2]);
+        ws += (double)(r[3] & 0xFFFFu);
+        cs += (double)((r[3] >> 16) & 0xFFFFu);
+    }
+    if (att.empty()) return;
+    auto q = [](std::vector<double> &v, double f) {
+        const size_t k = std::min(v.size() - 1, (size_t)(f * (double)(v.size() - 1)));
+        std::nth_element(v.begin(), v.begin() + k, v.end());
+        return v[k];
+    };
+    const double n = (double)att.size();
+    fprintf(stderr,
+            "clocks n=%zu span_us=%.2f walk_us=%.2f/%.2f/%.2f cav_us=%.2f/%.2f/%.2f att_us=%.2f/%.2f/%.2f/%.2f "
+            "walk_steps=%.2f cav_steps=%.2f\n",
+            att.size(), 0.01 * (double)(hi - lo), q(walk, 0.5), q(walk, 0.9), q(walk, 1.0), q(cav, 0.5), q(cav, 0.9),
+            q(cav, 1.0), q(att, 0.5), q(att, 0.9), q(att, 0.99), q(att, 1.0), ws / n, cs / n);
+    if (!ball.empty())
+        fprintf(stderr,
+                "ballclocks n=%zu built=%zu span_us=%.2f test_us=%.2f/%.2f/%.2f copy_us=%.2f/%.2f/%.2f "
+                "build_us=%.2f/%.2f/%.2f ball_us=%.2f/%.2f/%.2f/%.2f\n",
+                test.size(), ball.size(), 0.01 * (double)(bhi - blo), q(test, 0.5), q(test, 0.9), q(test, 1.0),
+                q(copy, 0.5), q(copy, 0.9), q(copy, 1.0), q(build, 0.5), q(build, 0.9), q(build, 1.0), q(ball, 0.5),
+                q(ball, 0.9), q(ball, 0.99), q(ball, 1.0));
 }
 
 // Waits for the round whose counters go to `slot`; they become the host's snapshot.
@@ -553,6 +667,7 @@ int complete_round(dt_ctx *c, int slot) {
                 c->hctr->conflicts - c->trace_prev_conf, c->hctr->overflows - c->trace_prev_ovf, capC,
                 c->hctr->cav_tets - c->trace_prev_cav, c->hctr->insphere - c->trace_prev_ins);
         prev_won = c->hctr->won;
+        if (c->trace >= 2 && max_cand && c->clk[slot] && c->clk_cap[slot] >= max_cand) trace_clocks(c, slot, max_cand);
         c->trace_prev_att = c->hctr->attempts;
         c->trace_prev_walk = c->hctr->walk_steps;
         c->trace_prev_conf = c->hctr->conflicts;
@@ -672,7 +787,7 @@ uint64_t plan_fill(const Levels &lv, uint64_t first, uint64_t W, FillPlan &plan)
 int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint32_t *d_size,
                const uint32_t *d_bits, const unsigned long long *d_rank_base, uint64_t base, uint64_t n) {
     const uint32_t rmax = c->list_cap;
-    const double frac = c->opt.round_fraction > 0 ? c->opt.round_fraction : DEFAULT_ROUND_FRACTION;
+    const double frac = c->frac;
     uint64_t next_rank = 0;
     uint64_t rounds_this_call = 0;
     int fly = -1;            // snapshot slot of the round in flight, or -1
@@ -924,8 +1039,9 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
     }
     const uint64_t base = c->nv;
     const bool fresh = !c->have_mesh;
+    select_launch(c, n);
     if ((rc = ensure(c, c->V, base + n, true)) || (rc = ensure(c, c->vtet, base + n, true)) ||
-        (rc = ensure(c, c->dup, base + n, true)) || (rc = ensure(c, c->anchor, n)))
+        (rc = ensure(c, c->dup, base + n, true)) || (rc = ensure(c, c->anchor, n)) || (rc = ensure(c, c->lastt, n)))
         return rc;
     c->out_index = false;
     // 1-2. clouds, validation, boxes, keys, sort
@@ -964,6 +1080,8 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
     unsigned long long *d_rb;
     if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
     HIPCHK(launch_anchor(lord, d_start, L, c->V.p, base, n, c->anchor.p, c->stream));
+    HIPCHK(hipMemsetAsync(c->lastt.p, 0xFF, n * sizeof(uint32_t), c->stream));
+    c->call_clouds = C;
     c->lord = lord;
     // without a model the learned scheduler falls back to the plain order (counted in the
     // statistics); the triangulation is the same either way
@@ -1105,7 +1223,7 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
         return DT_E_ARG;
     }
     c->device = c->opt.device;
-    c->trace = getenv("DT_TRACE") && getenv("DT_TRACE")[0] == '1';
+    c->trace = getenv("DT_TRACE") ? atoi(getenv("DT_TRACE")) : 0;
     if (hipSetDevice(c->device) != hipSuccess) {
         hipGetLastError();
         delete c;
@@ -1330,18 +1448,24 @@ int dt_autotune(dt_ctx *c, const double *xyz, uint64_t n, dt_options *best, doub
         HIPCHK(hipMemcpyAsync(sample.p, xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
         dxyz = sample.p;
     }
-    static const uint32_t lanes[] = {4, 8, 16, 64};
-    static const double fracs[] = {1.0 / 32, 1.0 / 16, 1.0 / 8};
+    static const uint32_t lanes[] = {8, 16, 32, 64};
+    static const double fracs[] = {3.0 / 64, 1.0 / 16, 3.0 / 32};
     static const uint32_t caps[] = {64, 128};
+    constexpr int NL = 4, NF = 3, NC = 2;
+    const int cls = size_class(n);
     const dt_options saved = c->opt;
+    const dt_ctx::Tuned saved_entry = c->tuned[cls];
     dt_options bo = saved;
     double bms = 1e300;
     rc = DT_OK;
-    for (int warm = 1, k = 0; k < 4 * 3 * 2 && rc == DT_OK; warm = 0) {
-        c->opt.lanes_per_insert = lanes[k / 6];
-        c->opt.round_fraction = fracs[(k / 2) % 3];
-        c->opt.cavity_cap = caps[k % 2];
-        apply_options(c);
+    // the configuration under test is the only tuned entry while the loop runs
+    dt_ctx::Tuned keep[64];
+    std::copy(std::begin(c->tuned), std::end(c->tuned), keep);
+    for (auto &t : c->tuned) t.set = false;
+    for (int warm = 1, k = 0; k < NL * NF * NC && rc == DT_OK; warm = 0) {
+        c->opt.lanes_per_insert = lanes[k / (NF * NC)];
+        c->opt.round_fraction = fracs[(k / NC) % NF];
+        c->opt.cavity_cap = caps[k % NC];
         auto t0 = std::chrono::steady_clock::now();
         rc = dt_insert_points(c, dxyz, n);
         if (rc == DT_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = DT_E_DEVICE;
@@ -1359,11 +1483,29 @@ int dt_autotune(dt_ctx *c, const double *xyz, uint64_t n, dt_options *best, doub
         hipStreamSynchronize(c->stream);
         hipFree(sample.p);
     }
-    c->opt = rc == DT_OK ? bo : saved;
+    std::copy(std::begin(keep), std::end(keep), c->tuned);
+    c->opt = saved;
+    if (rc != DT_OK) {
+        c->tuned[cls] = saved_entry;
+        apply_options(c);
+        return rc;
+    }
+    dt_ctx::Tuned &t = c->tuned[cls];
+    t.set = true;
+    t.lanes = bo.lanes_per_insert;
+    t.frac = bo.round_fraction;
+    t.cap = bo.cavity_cap;
+    t.ms = bms;
     apply_options(c);
-    if (rc != DT_OK) return rc;
     if (best) *best = bo;
     if (best_ms) *best_ms = bms;
+    return DT_OK;
+}
+
+int dt_autotune_reset(dt_ctx *c) {
+    if (!c) return DT_E_ARG;
+    for (auto &t : c->tuned) t.set = false;
+    apply_options(c);
     return DT_OK;
 }
 
@@ -1597,8 +1739,9 @@ int dt_destroy(dt_ctx *c) {
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
     auto f = [](void *p) { if (p) hipFree(p); };
-    f(c->V.p); f(c->vtet.p); f(c->anchor.p); f(c->dup.p);
+    f(c->V.p); f(c->vtet.p); f(c->anchor.p); f(c->lastt.p); f(c->dup.p);
     f(c->T); f(c->fl[0]); f(c->fl[1]); f(c->subd);
+    for (int k = 0; k < 3; ++k) f(c->clk[k]);
     for (int k = 0; k < 4; ++k) { f(c->lpt[k]); f(c->lrank[k]); }
     f(c->cav); f(c->bnd); f(c->outc); f(c->cnt); f(c->status);
     f(c->scr_v); f(c->scr_n); f(c->defer);
@@ -1645,6 +1788,7 @@ int dt_get_stats(const dt_ctx *c, dt_stats *out) {
     out->index_bits = c->tcap ? (c->wide ? 64 : 32) : 0;
     out->dropped_slots = h.dropped;
     out->deferred = h.deferred;
+    out->walk_caps = h.walk_caps;
     return DT_OK;
 }
 

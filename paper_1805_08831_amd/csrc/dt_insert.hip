@@ -436,6 +436,8 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
         const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
         const Vert pv = a.V[p];
         const P3 P = {pv.x, pv.y, pv.z};
+        const bool clocked = !FULL && !DEFER && a.clk != nullptr;
+        const unsigned long long tc0 = clocked ? (unsigned long long)wall_clock64() : 0ull;
         // start: near the nearest inserted point among GS / 2 records on either side of p on
         // the curve (in p's cloud), one probe per lane; else near the point's anchor (a
         // record of a lower level); else the cloud's known live tetrahedron.  A record's
@@ -449,12 +451,26 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
         const uint32_t ht = inr && hp >= clo && hp < chi ? a.vtet[hp] : NONE;
         const uint32_t q = a.anchor[p - a.vlo];
         const uint32_t tq = q != NONE ? a.vtet[q] : NONE;
+        const uint32_t tl = a.lastt[p - a.vlo];
         const unsigned long long hm = __ballot(ht != NONE) & gmask;
         uint32_t t = hm ? __shfl(ht, __ffsll((long long)hm) - 1) : tq;
         // the learned scheduler predicts the anchor to be the closer start
         if (a.wbucket && tq != NONE && a.wbucket[p - a.vlo]) t = tq;
         if (t == NONE) t = cl->any_live;
-        uint4 w = T[t].v;
+        // a retry starts where the last attempt located p: that tetrahedron, or the one the
+        // ball of a winner built in its slot, is near p unless the slot went to another
+        // cloud of the call
+        uint4 w;
+        bool from_last = false;
+        if (tl != NONE) {
+            w = T[tl].v;
+            from_last = w.x != DEAD && (!a.multi || (a.V[w.x].idx >> 32) == (pv.idx >> 32));
+        }
+        if (from_last) {
+            t = tl;
+        } else {
+            w = T[t].v;
+        }
         if (w.x == DEAD) {
             t = cl->any_live;
             w = T[t].v;
@@ -495,8 +511,15 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 in_ghost = true;
                 break;
             }
+            if (!FULL && ws >= a.walk_cap) {
+                status = ST_WALK;
+                break;
+            }
         }
         steps += ws;
+        if (gl == 0 && status != ST_ERROR) a.lastt[p - a.vlo] = t;
+        const unsigned long long tc1 = clocked ? (unsigned long long)wall_clock64() : 0ull;
+        unsigned cav_steps = 0;
         if (status == ST_NONE && !in_ghost) {
             // p equal to a vertex of its containing tetrahedron: lane j < 4 compares vertex j
             bool same = false;
@@ -537,6 +560,7 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
             lane_fence<GLOBAL>();
             for (uint32_t k0 = 0, nproc = 0; k0 < ncav && status == ST_NONE; k0 += nproc) {
                 nproc = min(NP, ncav - k0);  // entries expanded in this step
+                ++cav_steps;
                 const uint32_t slot = k0 + (gl >> 2);
                 const int f = jl;
                 const bool lv = slot < k0 + nproc;
@@ -663,6 +687,14 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 const uint32_t q = cavl[k];
                 cavg[k] = make_code<K>((uint32_t)(mem[q >> 2] >> 1), q & 3u);
             }
+        if (clocked && gl == 0) {
+            unsigned long long *r = a.clk + 8ull * i;
+            r[0] = tc0;
+            r[1] = tc1;
+            r[2] = (unsigned long long)wall_clock64();
+            r[3] = (unsigned long long)min(ws, 0xFFFFu) | ((unsigned long long)min(cav_steps, 0xFFFFu) << 16) |
+                   ((unsigned long long)min(ncav, 0xFFFFu) << 32) | ((unsigned long long)status << 48);
+        }
         if (gl == 0) {
             a.status[i] = status;
             a.cnt[i] = ncav;
@@ -737,6 +769,7 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
     const uint32_t ncand = *a.ncand_ptr;
     const uint32_t stride = a.stride, capC = a.capC, capF = a.capF;
     unsigned cav_w = 0, bnd_w = 0;
+    const unsigned long long tb0 = a.clk ? (unsigned long long)wall_clock64() : 0ull;
     const bool cand = i < ncand && a.status[i] == ST_CAND;
     uint32_t p = 0, nc = 0, nb = 0;
     unsigned long long S = 0;
@@ -796,6 +829,8 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
     if (cand && gl == 0) a.status[i] = lbuilt ? ST_WON : ST_CONFLICT;
     const bool built = __shfl((int)lbuilt, (int)gbase) != 0;
     const uint32_t g_u0 = __shfl(u0, (int)gbase), g_fb = __shfl(fb, (int)gbase);
+    const unsigned long long tb1 = a.clk ? (unsigned long long)wall_clock64() : 0ull;
+    unsigned long long tb2 = tb1;
     if (built) {
         const bool table = nb <= HT_MAX_FACETS;
         // A: copies of the cavity tetrahedra (vertices; for the pivot also the neighbours and
@@ -811,6 +846,7 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
         if (table)
             for (uint32_t h = gl; h < HT; h += GL) s_key[gi][h] = HT_EMPTY;
         group_fence();
+        if (a.clk) tb2 = (unsigned long long)wall_clock64();
         if (!table) {
             // B (pivot only): facets between two cavity tetrahedra -> local codes
             for (uint32_t task = gl; task < 4 * nc; task += GL) {
@@ -976,6 +1012,13 @@ __global__ __launch_bounds__(BS) void k_ball(RoundArgs a) {
             bnd_w = nb;
         }
     }
+    if (a.clk && cand && gl == 0) {
+        unsigned long long *r = a.clk + 8ull * i + 4;
+        r[0] = tb0;
+        r[1] = tb1;
+        r[2] = built ? tb2 : 0ull;
+        r[3] = built ? (unsigned long long)wall_clock64() : 0ull;
+    }
     add_stat(a.stat, STAT_CAV_TETS, cav_w);
     add_stat(a.stat, STAT_BND_FACETS, bnd_w);
 }
@@ -988,7 +1031,7 @@ __global__ __launch_bounds__(FILL_BLOCK) void k_compact(RoundArgs a) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ncand = *a.ncand_ptr;
     const uint8_t s = i < ncand ? a.status[i] : (uint8_t)ST_NONE;
-    const bool again = i < ncand && (s == ST_CONFLICT || s == ST_CAND);
+    const bool again = i < ncand && (s == ST_CONFLICT || s == ST_CAND || s == ST_WALK);
     const bool ovf = i < ncand && s == ST_OVERFLOW;
     if (a.log_att && i < ncand) atomicAdd(&a.log_att[a.cand_pt[i] - a.vlo], 1u);
     const uint32_t pn = block_reserve<NW>(again ? 1u : 0u, a.nnext_ptr, s_tmp);
@@ -1006,6 +1049,7 @@ __global__ __launch_bounds__(FILL_BLOCK) void k_compact(RoundArgs a) {
     block_reserve<NW>(ovf ? 1u : 0u, &a.ctr->overflows, s_tmp);
     block_reserve<NW>(i < ncand && s == ST_WON ? 1u : 0u, &a.ctr->won, s_tmp);
     block_reserve<NW>(i < ncand && s == ST_DUP ? 1u : 0u, &a.ctr->dups, s_tmp);
+    block_reserve<NW>(i < ncand && s == ST_WALK ? 1u : 0u, &a.ctr->walk_caps, s_tmp);
     const bool bad = i < ncand && !(again || ovf || s == ST_WON || s == ST_DUP);
     if (bad) atomicOr(&a.ctr->error, ERR_WALK);
 }
@@ -1084,7 +1128,12 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
         k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     }
     if (ev) hipEventRecord(ev[1], s);
-    k_ball<K, 16, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 16 - 1) / (BALL_BLOCK / 16), BALL_BLOCK, 0, s>>>(a);
+    // rounds for large cavities build large balls (their siblings found by pivoting): a
+    // wavefront per candidate
+    if (a.capC > LCAPC)
+        k_ball<K, 64, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 64 - 1) / (BALL_BLOCK / 64), BALL_BLOCK, 0, s>>>(a);
+    else
+        k_ball<K, 16, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 16 - 1) / (BALL_BLOCK / 16), BALL_BLOCK, 0, s>>>(a);
     if (ev) hipEventRecord(ev[2], s);
     return hipGetLastError();
 }

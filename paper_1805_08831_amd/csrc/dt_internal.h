@@ -75,7 +75,8 @@ enum : uint8_t {
     ST_DUP = 4,       // exact duplicate of a vertex already in the mesh
     ST_WON = 5,       // inserted
     ST_ERROR = 6,     // walk did not terminate (never expected)
-    ST_FULL = 7       // a sign the fp64 filter could not decide: run again with exact predicates
+    ST_FULL = 7,      // a sign the fp64 filter could not decide: run again with exact predicates
+    ST_WALK = 8       // walk stopped at the round's cap: retried next round from where it stopped
 };
 
 enum : uint32_t {
@@ -117,6 +118,7 @@ struct Ctr {
     uint32_t dropped;    // freed slots that did not fit the free list (left unused)
     uint32_t ndefer;     // candidates of this round handed to the exact-predicate pass
     uint32_t deferred;   // such candidates since the last clear
+    uint32_t walk_caps;  // attempts stopped at the walk cap since the last clear
     unsigned long long walk_steps, cav_tets, bnd_facets;
     unsigned long long orient, orient_exact, insphere, insphere_exact, perturbed;
     unsigned long long attempts;
@@ -146,6 +148,10 @@ struct RoundArgs {
     uint32_t vlo, vhi;           // vertex records of the current call
     const uint32_t *anchor;      // walk anchor of each record of the call (a lower-level record
                                  // of the same cloud), indexed by record - vlo
+    uint32_t *lastt;             // where the record's last attempt located it (NONE before the
+                                 // first), indexed by record - vlo: the start of its next walk
+    uint32_t multi;              // 1: the call has several clouds (slots move between them)
+    uint32_t walk_cap;           // filter pass: walk steps after which an attempt stops (ST_WALK)
     Cloud *clouds;               // the call's clouds (walk bounds, live tetrahedron)
     uint32_t *log_att;           // if set: attempts per record of the call (record - vlo)
     const uint8_t *wbucket;      // if set: 1 = start the walk at the anchor (record - vlo)
@@ -176,6 +182,11 @@ struct RoundArgs {
     uint32_t stride, capC, capF, tcap;
     uint32_t hmg;                // capC > 1024: entries of the cavity set in global memory
     unsigned long long round_hi;  // (0xFFFFFFFF - round) << 32: newer rounds claim lower
+    // if set (trace mode): [stride][8] per attempt.  Filter pass: wall clock (100 MHz) at its
+    // start, at the walk's end and at its end, then walk steps | cavity steps << 16 | cavity
+    // size << 32 | status << 48.  Ball kernel: clock at its start, after the winner test and
+    // slot reservation, after the cavity copies and at its end.
+    unsigned long long *clk;
 };
 
 // New candidates of one round: a window of ranks split into aligned power-of-two blocks,

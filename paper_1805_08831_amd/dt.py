@@ -27,7 +27,7 @@ class dt_options(ctypes.Structure):
                 ("cavity_cap", ctypes.c_uint32), ("capacity_tets", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("max_rounds", ctypes.c_uint32), ("timing", ctypes.c_int), ("round_fraction", ctypes.c_double),
                 ("lanes_per_insert", ctypes.c_uint32), ("scheduler", ctypes.c_int), ("log_points", ctypes.c_int),
-                ("index_bits", ctypes.c_int), ("adaptive_curve", ctypes.c_int), ("subdet_cache", ctypes.c_int)]
+                ("index_bits", ctypes.c_int), ("adaptive_curve", ctypes.c_int), ("subdet_cache", ctypes.c_int), ("walk_cap", ctypes.c_uint32)]
 
 DT_SCHED_PLAIN, DT_SCHED_LEARNED = 0, 1
 NFEAT, NHID, NOUT = 16, 64, 3
@@ -46,7 +46,8 @@ class dt_stats(ctypes.Structure):
                  ("ms_cavity_kernel", ctypes.c_double), ("ms_ball_kernel", ctypes.c_double),
                  ("cavity_units", ctypes.c_uint64), ("ball_units", ctypes.c_uint64),
                  ("sched_fallbacks", ctypes.c_uint64), ("index_bits", ctypes.c_uint64),
-                 ("dropped_slots", ctypes.c_uint64), ("deferred", ctypes.c_uint64)])
+                 ("dropped_slots", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
+                 ("walk_caps", ctypes.c_uint64)])
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -83,6 +84,7 @@ def lib():
         L.dt_insert_batch.argtypes = [vp, vp, vp, ctypes.c_uint32]
         L.dt_get_tets_batch.argtypes = [vp, ctypes.c_uint32, vp, vp, ctypes.POINTER(u64)]
         L.dt_autotune.argtypes = [vp, vp, u64, ctypes.POINTER(dt_options), ctypes.POINTER(ctypes.c_double)]
+        L.dt_autotune_reset.argtypes = [vp]
         L.dt_get_point_log.argtypes = [vp, vp, vp, vp, ctypes.POINTER(u64)]
         L.dt_train_model.argtypes = [vp, vp, vp, vp, u64, ctypes.c_uint32, ctypes.c_float, u64, vp,
                                      ctypes.POINTER(ctypes.c_size_t)]
@@ -98,7 +100,8 @@ def lib():
                                 ctypes.POINTER(u64)]
         L.dt_get_points.argtypes = [vp, vp, ctypes.POINTER(u64)]
         for f in ("dt_create", "dt_insert_points", "dt_get_tets", "dt_clear", "dt_destroy", "dt_get_stats",
-                  "dt_insert_batch", "dt_get_tets_batch", "dt_autotune", "dt_get_point_log", "dt_train_model",
+                  "dt_insert_batch", "dt_get_tets_batch", "dt_autotune", "dt_autotune_reset", "dt_get_point_log",
+                  "dt_train_model",
                   "dt_load_model", "dt_debug_mlp", "dt_debug_mlp_grad", "dt_debug_sort", "dt_debug_predicates",
                   "dt_debug_set_round_counter", "dt_debug_widen_at", "dt_triangulate_noalloc", "dt_refine",
                   "dt_get_points"):
@@ -213,6 +216,10 @@ def dt_autotune(ctx, xyz):
     p, n = _points(xyz)
     _check(ctx, lib().dt_autotune(ctx, p, n, ctypes.byref(best), ctypes.byref(ms)))
     return best, float(ms.value)
+
+
+def dt_autotune_reset(ctx):
+    _check(ctx, lib().dt_autotune_reset(ctx))
 
 
 def dt_get_point_log(ctx):
@@ -349,7 +356,7 @@ class Triangulation:
 
     def __init__(self, device=0, stream=None, round_size=0, cavity_cap=0, capacity_tets=0, seed=0x5EED,
                  max_rounds=0, timing=False, round_fraction=0.0, lanes_per_insert=0, scheduler=0, log_points=False,
-                 index_bits=0, adaptive_curve=False, subdet_cache=False):
+                 index_bits=0, adaptive_curve=False, subdet_cache=False, walk_cap=0):
         o = dt_default_options()
         o.device, o.round_size, o.cavity_cap = int(device), int(round_size), int(cavity_cap)
         o.capacity_tets, o.seed, o.max_rounds = int(capacity_tets), int(seed), int(max_rounds)
@@ -359,6 +366,7 @@ class Triangulation:
         o.index_bits = int(index_bits)
         o.adaptive_curve = int(bool(adaptive_curve))
         o.subdet_cache = int(bool(subdet_cache))
+        o.walk_cap = int(walk_cap)
         o.stream = stream
         self.ctx = dt_create(o)
 
@@ -381,8 +389,12 @@ class Triangulation:
         dt_get_tets_batch(self.ctx, cloud, tets, nbrs, T)
         return tets, nbrs
 
+    def autotune_reset(self):
+        dt_autotune_reset(self.ctx)
+
     def autotune(self, xyz):
-        """Picks lanes per insertion, round fraction and cavity cap on a sample (see dt.h)."""
+        """Picks lanes per insertion, round fraction and cavity cap for the sample's size
+        class (see dt.h)."""
         if isinstance(xyz, np.ndarray):
             xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         best, ms = dt_autotune(self.ctx, xyz)

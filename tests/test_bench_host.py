@@ -208,3 +208,29 @@ def test_bench_line_contract_batch_and_mix(monkeypatch, capsys):
     line = _run_bench(monkeypatch, capsys, ["--workload", "mix", "--mix-scale", "0.001", "--train-samples", "100",
                                             "--steps", "1", "--warmup", "0", "--cpu-mix-scale", "0.05"])
     assert "identical_output" in line["learned"] and line["cpu_baseline"]["kind"] == "oracle"
+
+
+def test_clock_summary_reads_the_trace_lines():
+    """The phase-clock summary adds the rounds' spans and medians and splits large rounds."""
+    import bench
+    lines = [
+        "clocks n=5000 span_us=200.00 walk_us=10.00/20.00/30.00 cav_us=30.00/40.00/90.00 "
+        "att_us=40.00/60.00/100.00/150.00 walk_steps=5.00 cav_steps=6.00\n",
+        "clocks n=100 span_us=50.00 walk_us=5.00/6.00/7.00 cav_us=15.00/20.00/30.00 "
+        "att_us=20.00/25.00/30.00/40.00 walk_steps=3.00 cav_steps=4.00\n",
+    ]
+    s = bench.summarise_clocks(lines)
+    assert s["rounds"] == 2 and s["attempts"] == 5100
+    assert s["sum_span_ms"] == 0.25 and s["sum_att_p50_ms"] == 0.06
+    assert s["median_attempt_share_of_span"] == round(60 / 250, 4)
+    assert s["walk_share_of_median_attempt"] == round(15 / 60, 4)
+    assert s["walk_steps_per_attempt"] == round((5 * 5000 + 3 * 100) / 5100, 3)
+    assert s["rounds_4096_or_more"]["rounds"] == 1 and s["rounds_below_4096"]["sum_span_ms"] == 0.05
+    assert s["rounds_4096_or_more"]["att_us_p50_p90_p99_max_mean"] == [40.0, 60.0, 100.0, 150.0]
+    assert bench.summarise_clocks([]) is None
+    ball = ("ballclocks n=5000 built=3700 span_us=120.00 test_us=20.00/30.00/50.00 copy_us=5.00/8.00/9.00 "
+            "build_us=30.00/40.00/60.00 ball_us=55.00/70.00/90.00/110.00\n")
+    s = bench.summarise_clocks(lines + [ball])
+    assert s["rounds"] == 2 and s["ball"]["rounds"] == 1 and s["ball"]["sum_span_ms"] == 0.12
+    assert s["ball"]["rounds_4096_or_more"]["test_us_p50_p90"] == [20.0, 30.0]
+    assert s["ball"]["rounds_4096_or_more"]["ball_us_p50_p90_p99_max"] == [55.0, 70.0, 90.0, 110.0]

@@ -285,7 +285,8 @@ def test_append_and_clear(dtlib, oracle_mod):
                                   dict(lanes_per_insert=32), dict(lanes_per_insert=64),
                                   dict(lanes_per_insert=4, cavity_cap=200),
                                   dict(cavity_cap=2048), dict(lanes_per_insert=16, cavity_cap=1500),
-                                  dict(capacity_tets=4096)])
+                                  dict(capacity_tets=4096), dict(walk_cap=1), dict(walk_cap=3),
+                                  dict(walk_cap=0xFFFFFFFF)])
 def test_launch_options_do_not_change_result(dtlib, oracle_mod, opts):
     say(f"options {opts}")
     xyz = mix_small(51, 4000)
@@ -295,6 +296,10 @@ def test_launch_options_do_not_change_result(dtlib, oracle_mod, opts):
         assert st["overflows"] > 0
     if "capacity_tets" in opts:  # the pool grew several times between rounds
         assert len(tets) > 4 * opts["capacity_tets"]
+    if opts.get("walk_cap") in (1, 3):  # walks stopped and resumed in later rounds
+        assert st["walk_caps"] > 0
+    if opts.get("walk_cap") == 0xFFFFFFFF:
+        assert st["walk_caps"] == 0
 
 
 def test_round_limit(dtlib):
@@ -433,16 +438,24 @@ def test_batch_degenerate_cloud(dtlib):
 
 
 def test_autotune_keeps_results(dtlib, oracle_mod):
-    say("autotune on a 20000-point sample, then a triangulation with the chosen options")
+    say("autotune at two sizes, then triangulations of sizes near each and between them")
     with dtlib.Triangulation() as tri:
-        best = tri.autotune(uniform_points(20000, 31))
-        assert best["lanes_per_insert"] in (4, 8, 16, 32, 64) and best["cavity_cap"] in (64, 128)
-        assert best["round_fraction"] in (1 / 32, 1 / 16, 1 / 8) and best["ms"] > 0
-        assert tri.stats()["points"] == 0
-        xyz = uniform_points(5000, 32)
+        for size, seed in ((20000, 31), (3000, 33)):
+            best = tri.autotune(uniform_points(size, seed))
+            assert best["lanes_per_insert"] in (8, 16, 32, 64) and best["cavity_cap"] in (64, 128)
+            assert best["round_fraction"] in (3 / 64, 1 / 16, 3 / 32) and best["ms"] > 0
+            assert tri.stats()["points"] == 0
+        for n, seed in ((5000, 32), (2500, 34), (40000, 35)):
+            xyz = uniform_points(n, seed)
+            tri.insert(xyz)
+            t, _ = tri.tets()
+            assert_parity(oracle_mod, xyz, t.astype(np.int64), f"tuned, {n} points")
+            tri.clear()
+        tri.autotune_reset()
+        xyz = uniform_points(4000, 36)
         tri.insert(xyz)
         t, _ = tri.tets()
-        assert_parity(oracle_mod, xyz, t.astype(np.int64), f"tuned {best}")
+        assert_parity(oracle_mod, xyz, t.astype(np.int64), "after the reset")
 
 
 # ------------------------------------------------------------------ learned scheduler

@@ -73,6 +73,7 @@ def test_every_entry_point_rejects_a_null_context(libdt):
         "dt_get_tets": (n, n, n, n),
         "dt_get_tets_batch": (n, 0, n, n, n),
         "dt_autotune": (n, n, 0, n, n),
+        "dt_autotune_reset": (n,),
         "dt_get_point_log": (n, n, n, n, n),
         "dt_train_model": (n, n, n, n, 0, 0, 0.0, 0, n, n),
         "dt_load_model": (n, n, 0),
