@@ -58,7 +58,9 @@ typedef struct {
     uint64_t capacity_tets; /* initial tetrahedron pool (grown on demand); 0: automatic   */
     uint64_t seed;          /* seed of the randomized insertion levels (BRIO, Sec. 2.3)  */
     uint32_t max_rounds;    /* 0: unlimited; otherwise DT_E_INCOMPLETE beyond it          */
-    int timing;             /* 1: time the insertion kernels with HIP events              */
+    int timing;             /* 1: time the two insertion kernels with HIP events (three
+                               per round); 2: the cavity kernel only (two per round: an
+                               event record leaves the GPU idle for a few microseconds)  */
     double round_fraction;  /* round size as a fraction of the current vertex count;
                                0: automatic                                              */
     uint32_t lanes_per_insert; /* lanes of a wavefront cooperating on one insertion in the

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -133,6 +134,12 @@ struct dt_ctx {
     Ctr *ctr = nullptr;
     Ctr *hctr = nullptr;   // pinned: the counters after the last completed round (one of hring)
     Ctr *hring = nullptr;  // three pinned snapshots: the host's and one per round in flight
+    // pinned ring: the round-end kernel writes each snapshot there and then sets hseq[slot]
+    // to the round's tag (else a copy and an event per round)
+    bool ring_direct = false;
+    unsigned long long *hseq = nullptr;
+    unsigned long long tag_counter = 0;
+    unsigned long long slot_tag[3] = {0, 0, 0};
     unsigned long long *stat = nullptr;  // spread work statistics (summed into ctr each round)
 
     // per-call scratch
@@ -471,13 +478,17 @@ int check_errors(dt_ctx *c) {
 
 void accumulate_timing(dt_ctx *c, int slot) {
     if (!c->opt.timing) return;
+    const bool ball = c->opt.timing == 1;
     float a = 0.f, b = 0.f;
-    if (hipEventElapsedTime(&a, c->ev[slot][0], c->ev[slot][1]) == hipSuccess &&
-        hipEventElapsedTime(&b, c->ev[slot][1], c->ev[slot][2]) == hipSuccess) {
+    if (hipEventSynchronize(c->ev[slot][ball ? 2 : 1]) == hipSuccess &&
+        hipEventElapsedTime(&a, c->ev[slot][0], c->ev[slot][1]) == hipSuccess &&
+        (!ball || hipEventElapsedTime(&b, c->ev[slot][1], c->ev[slot][2]) == hipSuccess)) {
         c->st.ms_cavity_kernel += a;
-        c->st.ms_ball_kernel += b;
         c->st.cavity_launches++;
-        c->st.ball_launches++;
+        if (ball) {
+            c->st.ms_ball_kernel += b;
+            c->st.ball_launches++;
+        }
     } else {
         hipGetLastError();
     }
@@ -564,11 +575,19 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
         a.clk = c->clk[slot];
     }
     c->round_counter++;
-    HIPCHK(launch_round(a, c->wide, max_cand, c->lanes, c->stream, c->opt.timing ? c->ev[slot] : nullptr));
-    HIPCHK(launch_round_end(a, max_cand, c->stream));
+    // timing 1: events around both kernels; 2: around the cavity kernel only (each event
+    // record leaves the GPU idle for a few microseconds)
+    hipEvent_t evs[3] = {c->ev[slot][0], c->ev[slot][1], c->opt.timing == 1 ? c->ev[slot][2] : nullptr};
+    HIPCHK(launch_round(a, c->wide, max_cand, c->lanes, c->stream, c->opt.timing ? evs : nullptr));
     c->fl_idx ^= 1;
-    HIPCHK(hipMemcpyAsync(&c->hring[slot], c->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, c->stream));
-    if (c->evdone[slot]) HIPCHK(hipEventRecord(c->evdone[slot], c->stream));
+    if (c->ring_direct) {
+        c->slot_tag[slot] = ++c->tag_counter;
+        HIPCHK(launch_round_end(a, max_cand, c->stream, &c->hring[slot], &c->hseq[slot], c->slot_tag[slot]));
+    } else {
+        HIPCHK(launch_round_end(a, max_cand, c->stream, nullptr, nullptr, 0));
+        HIPCHK(hipMemcpyAsync(&c->hring[slot], c->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, c->stream));
+        if (c->evdone[slot]) HIPCHK(hipEventRecord(c->evdone[slot], c->stream));
+    }
     c->slot_cand[slot] = max_cand;
     c->slot_capC[slot] = capC;
     c->st.rounds++;
@@ -640,10 +659,30 @@ void trace_clocks(dt_ctx *c, int slot, uint32_t max_cand) {
 
 // Waits for the round whose counters go to `slot`; they become the host's snapshot.
 int complete_round(dt_ctx *c, int slot) {
-    // without events (the arena's context) the whole stream is waited for: the round in
-    // flight behind this one completes too, which is correct, only not overlapped
-    if (c->evdone[slot]) HIPCHK(hipEventSynchronize(c->evdone[slot]));
-    else HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->ring_direct) {
+        // the round-end kernel sets the slot's tag after writing its snapshot; the stream is
+        // queried now and then so that a failed launch ends the wait
+        const volatile unsigned long long *seq = &c->hseq[slot];
+        const unsigned long long want = c->slot_tag[slot];
+        for (uint64_t spin = 1; *seq != want; ++spin) {
+            if ((spin & 4095) == 0) {
+                const hipError_t e = hipStreamQuery(c->stream);
+                if (e == hipSuccess && *seq != want)
+                    return fail(c, DT_E_INTERNAL, "round counters did not arrive (stream idle)");
+                if (e != hipSuccess && e != hipErrorNotReady) {
+                    hipGetLastError();
+                    return fail(c, DT_E_DEVICE, "device error while waiting for a round (%s)", hipGetErrorString(e));
+                }
+            }
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
+    } else if (c->evdone[slot]) {
+        HIPCHK(hipEventSynchronize(c->evdone[slot]));
+    } else {
+        // without events (the arena's context) the whole stream is waited for: the round in
+        // flight behind this one completes too, which is correct, only not overlapped
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
     c->hctr = &c->hring[slot];
     const uint32_t max_cand = c->slot_cand[slot], capC = c->slot_capC[slot];
     if (max_cand) accumulate_timing(c, slot);
@@ -657,7 +696,7 @@ int complete_round(dt_ctx *c, int slot) {
         float ta = 0.f, tb = 0.f;
         if (c->opt.timing && max_cand) {
             hipEventElapsedTime(&ta, c->ev[slot][0], c->ev[slot][1]);
-            hipEventElapsedTime(&tb, c->ev[slot][1], c->ev[slot][2]);
+            if (c->opt.timing == 1) hipEventElapsedTime(&tb, c->ev[slot][1], c->ev[slot][2]);
         }
         fprintf(stderr,
                 "round %llu cand<=%u won=%u tets=%u free=%u cavity_ms=%.3f ball_ms=%.3f att=%llu walk=%llu "
@@ -1240,9 +1279,14 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
     apply_options(c);
     if (!rc && (hipMalloc((void **)&c->ctr, sizeof(Ctr)) != hipSuccess ||
                 hipMalloc((void **)&c->stat, STAT_WORDS * sizeof(unsigned long long)) != hipSuccess ||
-                hipHostMalloc((void **)&c->hring, 3 * sizeof(Ctr), hipHostMallocDefault) != hipSuccess))
+                hipHostMalloc((void **)&c->hring, 3 * sizeof(Ctr) + 3 * sizeof(unsigned long long),
+                              hipHostMallocDefault) != hipSuccess))
         rc = DT_E_DEVICE;
-    if (!rc) c->hctr = c->hring;
+    if (!rc) {
+        c->hctr = c->hring;
+        c->hseq = reinterpret_cast<unsigned long long *>(c->hring + 3);
+        c->ring_direct = true;
+    }
     for (int k = 0; k < 3 && !rc; ++k) {
         for (int j = 0; j < 3 && !rc; ++j)
             if (hipEventCreate(&c->ev[k][j]) != hipSuccess) rc = DT_E_DEVICE;
@@ -1257,7 +1301,7 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
         dt_destroy(c);
         return rc;
     }
-    std::memset(c->hring, 0, 3 * sizeof(Ctr));
+    std::memset(c->hring, 0, 3 * sizeof(Ctr) + 3 * sizeof(unsigned long long));
     *out = c;
     return DT_OK;
 }

@@ -713,6 +713,258 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
     add_stat(a.stat, STAT_PERTURBED, st.perturbed);
 }
 
+// Walk and cavity search of one candidate per 256-thread block, for rounds of large
+// cavities (exact predicates throughout).  The four waves walk the same path independently
+// (the walk reads nothing that changes during the kernel, so they arrive at the same
+// tetrahedron); the cavity search then expands 64 cavity tetrahedra per step, thread
+// (slot, facet) = (tid / 4, tid % 4), with block-wide prefix counts for the appends and a
+// barrier between steps.  Queue and set are in LDS (CAPL and HM entries) or, with GLOBAL, in
+// global memory as in k_cavity_g.  Claims, set and status follow k_cavity_g.
+template <class K, uint32_t CAPL, uint32_t HM, bool GLOBAL>
+__global__ __launch_bounds__(256) void k_cavity_b(RoundArgs a) {
+    using code = typename K::code;
+    using E = typename K::set_t;
+    __shared__ uint16_t s_cav[GLOBAL ? 1 : CAPL];
+    __shared__ E s_mem[GLOBAL ? 1 : HM];
+    __shared__ uint32_t s_cnt[2][4];
+    __shared__ int s_flag;
+    typename K::Rec *const T = static_cast<typename K::Rec *>(a.T);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wid = tid >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const uint32_t i = blockIdx.x;
+    if (i >= *a.ncand_ptr) return;  // uniform over the block
+    PredStats st;
+    uint8_t status = ST_NONE;
+    const uint32_t p = a.cand_pt[i];
+    const unsigned long long S = a.round_hi | (2ull * a.cand_rank[i]);
+    const Vert pv = a.V[p];
+    const P3 P = {pv.x, pv.y, pv.z};
+    // start as in k_cavity_g, probing 32 records on either side of p
+    Cloud *cl = &a.clouds[pv.idx >> 32];
+    const uint32_t clo = cl->lo, chi = cl->hi;
+    const uint32_t d = (lane >> 1) + 1;
+    const uint32_t hp = (lane & 1) ? p + d : p - d;
+    const bool inr = (lane & 1) ? (p + d < a.vhi) : (p >= a.vlo + d);
+    const uint32_t ht = inr && hp >= clo && hp < chi ? a.vtet[hp] : NONE;
+    const uint32_t q = a.anchor[p - a.vlo];
+    const uint32_t tq = q != NONE ? a.vtet[q] : NONE;
+    const uint32_t tl = a.lastt[p - a.vlo];
+    const unsigned long long hmask = __ballot(ht != NONE);
+    uint32_t t = hmask ? __shfl(ht, __ffsll((long long)hmask) - 1) : tq;
+    if (a.wbucket && tq != NONE && a.wbucket[p - a.vlo]) t = tq;
+    if (t == NONE) t = cl->any_live;
+    uint4 w;
+    bool from_last = false;
+    if (tl != NONE) {
+        w = T[tl].v;
+        from_last = w.x != DEAD && (!a.multi || (a.V[w.x].idx >> 32) == (pv.idx >> 32));
+    }
+    if (from_last) {
+        t = tl;
+    } else {
+        w = T[t].v;
+    }
+    if (w.x == DEAD) {
+        t = cl->any_live;
+        w = T[t].v;
+    }
+    if (w.w == GHOST) {
+        t = code_slot(comp(T[t].n, 3));
+        w = T[t].v;
+    }
+    // walk: lane j < 4 of each wave tests facet j
+    int entry = -1;
+    bool in_ghost = false;
+    const int jl = (int)(lane & 3u);
+    unsigned ws = 0;
+    for (;;) {
+        const P3 q0 = vpos(a.V, w.x), q1 = vpos(a.V, w.y), q2 = vpos(a.V, w.z), q3 = vpos(a.V, w.w);
+        const typename K::code4 nn = T[t].n;
+        int o = 1;
+        if (lane < 4 && jl != entry)
+            o = cav_orient<true>(jl == 0 ? P : q0, jl == 1 ? P : q1, jl == 2 ? P : q2, jl == 3 ? P : q3, st);
+        const unsigned bits = (unsigned)__ballot(o < 0) & 0xFu;
+        if (!bits) break;
+        const unsigned rot = (p + ws) & 3u;
+        const unsigned rb = ((bits >> rot) | (bits << (4u - rot))) & 0xFu;
+        const int moved = (int)(((unsigned)__ffs(rb) - 1u + rot) & 3u);
+        const code cd = comp(nn, moved);
+        t = code_slot(cd);
+        entry = code_facet(cd);
+        w = T[t].v;
+        if (++ws > WALK_LIMIT) {
+            status = ST_ERROR;
+            break;
+        }
+        if (w.w == GHOST) {
+            in_ghost = true;
+            break;
+        }
+    }
+    if (tid == 0 && status != ST_ERROR) a.lastt[p - a.vlo] = t;
+    const uint32_t walk_or = st.orient, walk_orx = st.orient_exact;
+    if (status == ST_NONE && !in_ghost) {
+        bool same = false;
+        if (lane < 4) {
+            const P3 v = vpos(a.V, comp(w, jl));
+            same = v.x == P.x && v.y == P.y && v.z == P.z;
+        }
+        if (__ballot(same)) status = ST_DUP;
+    }
+    uint32_t ncav = 0, nbnd = 0;
+    const uint32_t capL = GLOBAL ? a.capC : min(a.capC, CAPL), capF = a.capF;
+    uint32_t *bnd = a.bnd + (size_t)i * a.capF;
+    code *outc = static_cast<code *>(a.outc) + (size_t)i * a.capF;
+    code *cavg = static_cast<code *>(a.cav) + (size_t)i * a.capC;
+    const uint32_t hms = GLOBAL ? a.hmg : HM;
+    E *mem = GLOBAL ? reinterpret_cast<E *>(a.scr_v + (size_t)i * a.capC) : s_mem;
+    if (status == ST_NONE) {
+        for (uint32_t h = tid; h < hms; h += 256) mem[h] = mem_empty<E>();
+        if (GLOBAL) __threadfence_block();
+        __syncthreads();
+        bool pneed = tid == 0, pinside = true;
+        unsigned long long po1 = ~0ull;
+        if (tid == 0) {
+            po1 = atomicMin(&T[t].claim, S);
+            uint32_t at = 0;
+            mem_insert(mem, hms, t, 0u, &at);
+            if (GLOBAL) cavg[0] = make_code<K>(t, 0u);
+            else s_cav[0] = (uint16_t)(at << 2);
+        }
+        ncav = 1;
+        if (GLOBAL) __threadfence_block();
+        __syncthreads();
+        for (uint32_t k0 = 0, nproc = 0; k0 < ncav && status == ST_NONE; k0 += nproc) {
+            nproc = min(64u, ncav - k0);
+            const uint32_t slot = k0 + (tid >> 2);
+            const int f = (int)(tid & 3u);
+            const bool lv = slot < k0 + nproc;
+            code cd = 0u;
+            if (lv) {
+                if (GLOBAL) {
+                    cd = cavg[slot];
+                } else {
+                    const uint32_t qe = s_cav[slot];
+                    cd = make_code<K>((uint32_t)(mem[qe >> 2] >> 1), qe & 3u);
+                }
+            }
+            const uint32_t c = code_slot(cd);
+            const int pf = slot == 0 ? -1 : code_facet(cd);
+            const bool act = lv && f != pf;
+            uint4 cv = make_uint4(0u, 0u, 0u, 0u), uw = cv;
+            typename K::code4 cn{};
+            if (lv) {
+                cv = T[c].v;
+                cn = T[c].n;
+            }
+            // the previous step's claims (as in k_cavity_g)
+            if (__syncthreads_or(pneed && po1 < S && (pinside || !(po1 & 1ull)))) {
+                status = ST_CONFLICT;
+                break;
+            }
+            const code ncode = comp(cn, f);
+            const uint32_t u = code_slot(ncode);
+            const int kind = act ? mem_find<GLOBAL>(mem, hms, u) : -1;
+            const bool need = act && kind < 0;
+            if (need) uw = T[u].v;
+            bool inside = false;
+            if (need) {
+                const bool cghost = cv.w == GHOST;
+                const uint32_t apex = comp(uw, code_facet(ncode));
+                if (!cghost && apex != GHOST) {
+                    const uint32_t cid[4] = {cv.x, cv.y, cv.z, cv.w};
+                    uint32_t rid[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) rid[m] = m == f ? apex : cid[m];
+                    const int sa = (f + 1) & 3, sb = (f + 2) & 3;
+                    uint32_t r2[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) r2[m] = m == sa ? rid[sb] : (m == sb ? rid[sa] : rid[m]);
+                    inside = cav_insphere<true>(vpos(a.V, r2[0]), vpos(a.V, r2[1]), vpos(a.V, r2[2]),
+                                                vpos(a.V, r2[3]), P,
+                                                [&](int kk) { return kk < 4 ? a.V[r2[kk]].idx : pv.idx; }, st) < 0;
+                } else if (!cghost) {
+                    const P3 c0 = vpos(a.V, cv.x), c1 = vpos(a.V, cv.y), c2 = vpos(a.V, cv.z), c3 = vpos(a.V, cv.w);
+                    inside = cav_orient<true>(f == 0 ? P : c0, f == 1 ? P : c1, f == 2 ? P : c2, f == 3 ? P : c3,
+                                              st) <= 0;
+                } else {
+                    inside = tet_inside<K, true>(T, a.V, u, P, pv.idx, st) < 0;
+                }
+            }
+            unsigned long long o1 = ~0ull;
+            if (need) o1 = atomicMin(&T[u].claim, inside ? S : S + 1);
+            int ins = 0;
+            uint32_t at = 0;
+            if (need) ins = mem_insert(mem, hms, u, inside ? 0u : 1u, &at);
+            const bool first_in = ins == 1 && inside;
+            const bool outside = (act && kind == 1) || (need && !inside);
+            const unsigned long long mi = __ballot(first_in), mo = __ballot(outside);
+            const unsigned long long mf = __ballot(ins < 0);
+            if (lane == 0) {
+                s_cnt[0][wid] = (uint32_t)__popcll(mi);
+                s_cnt[1][wid] = (uint32_t)__popcll(mo);
+            }
+            if (tid == 0) s_flag = 0;
+            __syncthreads();
+            if (lane == 0 && mf) s_flag = 1;
+            uint32_t bi = 0, bo = 0, ni = 0, no = 0;
+#pragma unroll
+            for (uint32_t v = 0; v < 4; ++v) {
+                if (v < wid) {
+                    bi += s_cnt[0][v];
+                    bo += s_cnt[1][v];
+                }
+                ni += s_cnt[0][v];
+                no += s_cnt[1][v];
+            }
+            __syncthreads();
+            if (ncav + ni > capL || nbnd + no > capF || s_flag) {
+                status = ST_OVERFLOW;
+                break;
+            }
+            if (first_in) {
+                const uint32_t pos = ncav + bi + (uint32_t)__popcll(mi & below);
+                if (GLOBAL) cavg[pos] = ncode;
+                else s_cav[pos] = (uint16_t)((at << 2) | (uint32_t)code_facet(ncode));
+            }
+            if (outside) {
+                const uint32_t pos = nbnd + bo + (uint32_t)__popcll(mo & below);
+                bnd[pos] = (slot << 2) | (uint32_t)f;
+                outc[pos] = ncode;
+            }
+            ncav += ni;
+            nbnd += no;
+            pneed = need;
+            pinside = inside;
+            po1 = o1;
+            if (GLOBAL) __threadfence_block();
+            __syncthreads();
+        }
+        if (status == ST_NONE && __syncthreads_or(pneed && po1 < S && (pinside || !(po1 & 1ull))))
+            status = ST_CONFLICT;
+        if (status == ST_NONE) status = ST_CAND;
+    }
+    if (!GLOBAL && status == ST_CAND)
+        for (uint32_t k = tid; k < ncav; k += 256) {
+            const uint32_t qe = s_cav[k];
+            cavg[k] = make_code<K>((uint32_t)(mem[qe >> 2] >> 1), qe & 3u);
+        }
+    if (tid == 0) {
+        a.status[i] = status;
+        a.cnt[i] = ncav;
+        a.cnt[a.stride + i] = nbnd;
+    }
+    add_stat(a.stat, STAT_ATTEMPTS, tid == 0 ? 1u : 0u);
+    add_stat(a.stat, STAT_WALK, tid == 0 ? ws : 0u);
+    // the four waves repeated the walk's orientation tests: wave 0's count them
+    add_stat(a.stat, STAT_ORIENT, wid == 0 ? st.orient : st.orient - walk_or);
+    add_stat(a.stat, STAT_ORIENT_EXACT, wid == 0 ? st.orient_exact : st.orient_exact - walk_orx);
+    add_stat(a.stat, STAT_INSPHERE, st.insphere);
+    add_stat(a.stat, STAT_INSPHERE_EXACT, st.insphere_exact);
+    add_stat(a.stat, STAT_PERTURBED, st.perturbed);
+}
+
 // Winner test, slot reservation and DelaunayBall (Sec. 2.5), GL lanes per candidate, all in
 // one wave.  An attempt wins iff no lower attempt touched a tetrahedron of its cavity (the
 // claim word still holds its stamp) and the lowest claim on each of its outer tetrahedra is
@@ -1064,8 +1316,12 @@ __global__ void k_freelist_carry(RoundArgs a) {
         a.fl_next[nxt + k] = a.fl_cur[take + k];
 }
 
-__global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, uint32_t flcap,
-                       const unsigned long long *stat) {
+// Round end: statistics summed, the pool's counters advanced.  With `snap` (pinned host
+// memory), the counters are then written there and `seq` (host memory too) is set to `tag`
+// after them with a release at system scope: the host waits for that value instead of for a
+// copy and an event.
+__global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, uint32_t flcap, const unsigned long long *stat,
+                       Ctr *snap, unsigned long long *seq, unsigned long long tag) {
     const uint32_t t = threadIdx.x;
     if (t < NSTAT) {
         unsigned long long sum = 0;
@@ -1075,7 +1331,8 @@ __global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, uint32_t flc
                                          &ctr->cav_tets, &ctr->bnd_facets};
         *dst[t] = sum;
     }
-    if (t != 0) return;
+    __syncthreads();
+    if (t == 0) {
     const uint32_t fln = ctr->fl_n, take = ctr->fl_take;
     if (take > fln) {
         // units beyond the free list were fresh pool slots (beyond the pool: never used)
@@ -1091,6 +1348,17 @@ __global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, uint32_t flc
     ctr->fl_take = 0;
     ctr->fl_next = 0;
     *consumed = 0;  // the list this round read from is empty now
+    }
+    if (!snap) return;
+    __threadfence_block();
+    __syncthreads();
+    static_assert(sizeof(Ctr) % sizeof(uint32_t) == 0, "the snapshot is copied in words");
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(ctr);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(snap);
+    for (uint32_t k = t; k < sizeof(Ctr) / sizeof(uint32_t); k += blockDim.x) dst[k] = src[k];
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) __hip_atomic_store(seq, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 constexpr uint32_t DEFER_BLOCKS = 512;  // grid of the exact-predicate pass (grid-stride)
@@ -1104,7 +1372,14 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
     // the attempts it handed on (a short grid-stride pass; nothing to do for most rounds);
     // rounds for large cavities use exact predicates throughout
     const uint32_t dgrid = std::min<uint32_t>((max_cand + 31) / 32, DEFER_BLOCKS);
-    if (a.capC > BIG_CAPC) {
+    static const bool blk = getenv("DT_LARGE_BLOCK") && getenv("DT_LARGE_BLOCK")[0] == '1';
+    if (blk && a.capC > BIG_CAPC) {
+        if (a.hmg < 4096 || (a.hmg & (a.hmg - 1)) || (uint64_t)a.hmg * sizeof(typename K::set_t) > 16ull * a.capC)
+            return hipErrorInvalidValue;
+        k_cavity_b<K, 1, 1, true><<<max_cand, 256, 0, s>>>(a);
+    } else if (blk && a.capC > LCAPC) {
+        k_cavity_b<K, BIG_CAPC, BIG_HM, false><<<max_cand, 256, 0, s>>>(a);
+    } else if (a.capC > BIG_CAPC) {
         // the set takes hmg entries of the candidate's 16 capC bytes of ball scratch
         if (a.hmg < 4096 || (a.hmg & (a.hmg - 1)) || (uint64_t)a.hmg * sizeof(typename K::set_t) > 16ull * a.capC)
             return hipErrorInvalidValue;
@@ -1134,7 +1409,7 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
         k_ball<K, 64, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 64 - 1) / (BALL_BLOCK / 64), BALL_BLOCK, 0, s>>>(a);
     else
         k_ball<K, 16, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 16 - 1) / (BALL_BLOCK / 16), BALL_BLOCK, 0, s>>>(a);
-    if (ev) hipEventRecord(ev[2], s);
+    if (ev && ev[2]) hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 
@@ -1144,10 +1419,11 @@ hipError_t launch_round(const RoundArgs &a, bool wide, uint32_t max_cand, uint32
     return wide ? launch_round_k<Wide>(a, max_cand, lanes, s, ev) : launch_round_k<Narrow>(a, max_cand, lanes, s, ev);
 }
 
-hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s) {
+hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s, Ctr *snap,
+                            unsigned long long *seq, unsigned long long tag) {
     if (max_cand) k_compact<<<(max_cand + FILL_BLOCK - 1) / FILL_BLOCK, FILL_BLOCK, 0, s>>>(a);
     k_freelist_carry<<<256, 256, 0, s>>>(a);
-    k_roll<<<1, 64, 0, s>>>(a.ctr, const_cast<uint32_t *>(a.ncand_ptr), a.tcap, a.flcap, a.stat);
+    k_roll<<<1, 64, 0, s>>>(a.ctr, const_cast<uint32_t *>(a.ncand_ptr), a.tcap, a.flcap, a.stat, snap, seq, tag);
     return hipGetLastError();
 }
 

@@ -268,7 +268,8 @@ hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, con
                             uint32_t *ncand, hipStream_t s);
 hipError_t launch_round(const RoundArgs &a, bool wide, uint32_t max_cand, uint32_t lanes, hipStream_t s,
                         hipEvent_t *ev);
-hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s);
+hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s, Ctr *snap,
+                            unsigned long long *seq, unsigned long long tag);
 hipError_t launch_reset_claims(void *T, bool wide, uint32_t tcap, hipStream_t s);
 // copies `count` Tet records into TetW records
 hipError_t launch_widen(const void *src, void *dst, uint32_t count, hipStream_t s);

@@ -360,7 +360,7 @@ class Triangulation:
         o = dt_default_options()
         o.device, o.round_size, o.cavity_cap = int(device), int(round_size), int(cavity_cap)
         o.capacity_tets, o.seed, o.max_rounds = int(capacity_tets), int(seed), int(max_rounds)
-        o.timing, o.round_fraction = int(bool(timing)), float(round_fraction)
+        o.timing, o.round_fraction = int(timing), float(round_fraction)
         o.lanes_per_insert = int(lanes_per_insert)
         o.scheduler, o.log_points = int(scheduler), int(bool(log_points))
         o.index_bits = int(index_bits)

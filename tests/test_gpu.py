@@ -543,3 +543,22 @@ def test_learned_scheduler_keeps_result(dtlib, oracle_mod):
         t, nb = tri.tets()
         assert_parity(oracle_mod, xyz, t.astype(np.int64), "learned scheduler")
         check_invariants(xyz, t.astype(np.int64), nb, oracle_mod, expect_vertices=None)
+
+
+@pytest.mark.parametrize("timing", [0, 1, 2])
+def test_timing_modes(dtlib, oracle_mod, timing):
+    """Timing 1 times both insertion kernels per round, 2 the cavity kernel only, 0 neither;
+    the result is the same."""
+    say(f"timing {timing}")
+    xyz = uniform_points(30000, 41)
+    with dtlib.Triangulation(timing=timing) as tri:
+        tri.insert(xyz)
+        t, _ = tri.tets()
+        st = tri.stats()
+    assert_parity(oracle_mod, xyz, t.astype(np.int64), f"timing {timing}")
+    if timing == 0:
+        assert st["cavity_launches"] == 0 and st["ball_launches"] == 0
+    else:
+        assert 0 < st["cavity_launches"] <= st["rounds"] and st["ms_cavity_kernel"] > 0
+        assert (st["ball_launches"] == st["cavity_launches"] and st["ms_ball_kernel"] > 0) if timing == 1 else \
+            (st["ball_launches"] == 0 and st["ms_ball_kernel"] == 0)
