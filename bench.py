@@ -204,7 +204,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--round-fraction", type=float, default=0.0)
     ap.add_argument("--round-size", type=int, default=0)
-    ap.add_argument("--lanes", type=int, default=0, help="lanes per insertion (4, 8, 16, 32, 64; 0: automatic)")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per insertion in every round (4, 8, 16, 32, 64; 0: automatic)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick lanes per insertion, round fraction and cavity cap on a 2e6-point sample first")
     ap.add_argument("--workload", choices=["uniform", "batch", "mix"], default="uniform")
@@ -481,7 +481,7 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     # one untimed step with events around both kernels: the ball kernel's time
     if tuned:
         launch_opts.update(lanes_per_insert=tuned["lanes_per_insert"], round_fraction=tuned["round_fraction"],
-                           cavity_cap=tuned["cavity_cap"])
+                           cavity_cap=tuned["cavity_cap"], large_lanes=tuned["large_lanes"])
     with Triangulation(device=0, stream=stream.cuda_stream, timing=1, **launch_opts) as tb:
         tb.insert(d_xyz)
         torch.cuda.synchronize()
@@ -503,12 +503,14 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     ins_per_launch = agg["won"] / launches
     achieved = per_ins * ins_per_launch / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
     peak = 8000.0
-    lanes = (tuned or {}).get("lanes_per_insert") or args.lanes or 16
+    lanes = (tuned or {}).get("lanes_per_insert") if tuned else args.lanes
     b_att = cavity_bytes_per_attempt(walk, C, F)
     att_achieved = b_att * agg["attempts"] / launches / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
-    default_launch = (lanes == 16 and not args.round_fraction and not args.round_size and n == 10_000_000
+    default_launch = (not lanes and not args.round_fraction and not args.round_size and n == 10_000_000
                       and seed == 1007 and not args.subdet_cache and not args.adaptive_curve and not args.walk_cap)
-    roofline = {"bound": "hbm", "kernel": f"k_cavity_g<{lanes}>", "achieved": round(achieved, 2), "peak": peak,
+    kname = (f"k_cavity_g filter pass, {lanes} lanes" if lanes else
+             "k_cavity_g filter pass, 64 lanes in rounds below 32768 candidates, 16 above")
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": peak,
                 "unit": "GB/s", "frac": round(achieved / peak, 5),
                 # measured HBM bytes per launch (counter summary), only for the launch it was taken on
                 "traffic": measured_traffic() if default_launch else None,
@@ -520,7 +522,10 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     ball_ms = agg["ms_ball"] / max(agg["ball_launches"], 1)
     ball_per_ins = ball_bytes_per_insertion(F)
     ball_ach = ball_per_ins * agg["won"] / max(agg["ball_launches"], 1) / (ball_ms / 1000.0) / 1e9 if ball_ms > 0 else 0.0
-    ball = {"bound": "hbm", "kernel": "k_ball<16, 1024>", "unit": "GB/s", "peak": peak,
+    ball = {"bound": "hbm", "unit": "GB/s", "peak": peak,
+            "kernel": ("k_ball, 1024-thread blocks, " + ("64 lanes per candidate in rounds below 32768 candidates, "
+                                                        "16 above" if not lanes else
+                                                        f"{64 if lanes == 64 else 16} lanes per candidate")),
             "achieved": round(ball_ach, 2), "frac": round(ball_ach / peak, 5),
             "bytes_per_insertion": round(ball_per_ins, 1), "avg_launch_ms": round(ball_ms, 4)}
     detail = {"rounds_per_step": agg["rounds"] / steps, "attempts_per_point": agg["attempts"] / max(n * steps, 1),

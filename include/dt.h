@@ -64,8 +64,10 @@ typedef struct {
     double round_fraction;  /* round size as a fraction of the current vertex count;
                                0: automatic                                              */
     uint32_t lanes_per_insert; /* lanes of a wavefront cooperating on one insertion in the
-                                  walk and cavity search: 4, 8, 16, 32 or 64; 0:
-                                  automatic (16)                                         */
+                                  walk and cavity search: 4, 8, 16, 32 or 64 in every
+                                  round; 0: automatic (64 in rounds of fewer than 32768
+                                  candidates, whose time is their slowest insertion's,
+                                  16 in larger ones)                                     */
     int scheduler;          /* DT_SCHED_PLAIN (0) or DT_SCHED_LEARNED (1: uses the model of
                                dt_load_model or dt_train_model; without one the call runs
                                the plain order and counts dt_stats.sched_fallbacks)      */
@@ -92,6 +94,10 @@ typedef struct {
                                where it stopped (a launch then ends with its typical
                                attempts, not with one long walk).  0: automatic (16);
                                UINT32_MAX: no cap.  The result never depends on it.      */
+    uint32_t large_lanes;   /* lanes per insertion in rounds for cavities beyond the
+                               regular rounds' 128-entry buffers: 64 (one wavefront,
+                               16 cavity tetrahedra per breadth-first step) or 256 (a
+                               256-thread block, 64 per step); 0: automatic (256)        */
 } dt_options;
 
 enum { DT_SCHED_PLAIN = 0, DT_SCHED_LEARNED = 1 };
@@ -181,8 +187,9 @@ int dt_insert_batch(dt_ctx *ctx, const double *xyz, const uint64_t *offsets, uin
 int dt_get_tets_batch(dt_ctx *ctx, uint32_t cloud, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
 
 /* Autotuner: triangulates the n sample points (host or device memory) once per launch
-   configuration - lanes per insertion {8, 16, 32, 64} (64: one wavefront per insertion),
-   round fraction {3/64, 1/16, 3/32}, cavity cap {64, 128} - after one warm-up run, and keeps
+   configuration - lanes per insertion {automatic, 8, 16, 32}, round fraction {3/64, 1/16, 3/32},
+   cavity cap {64, 128}, lanes per insertion for large cavities {64, 256} (a wavefront or a
+   256-thread block) - after one warm-up run, and keeps
    the fastest (host wall time of dt_insert_points) for the sample's size class,
    floor(log2 n).  Later insertions use the choice of the tuned class nearest to their own
    point count (ties to the larger class); with no class tuned, dt_options decide.  Tune at

@@ -32,6 +32,9 @@ constexpr uint32_t DEFAULT_CAVITY_CAP = 128;
 constexpr uint32_t DEFAULT_LANES = 16;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t DEFAULT_WALK_CAP = 16;
+constexpr uint32_t DEFAULT_LARGE_LANES = 256;
+// automatic lanes: rounds of fewer candidates than this use 64 lanes per insertion
+constexpr uint32_t SMALL_ROUND = 32768;
 constexpr uint32_t ROUND_MIN = 64;
 constexpr uint32_t DRAIN_SLICE = 4096;  // candidates per round when draining overflowed cavities
 constexpr uint32_t EXPORT_CHUNK = 1u << 24;  // slots per staged export launch (a multiple of 64)
@@ -113,13 +116,15 @@ struct dt_ctx {
     size_t bufC = 0, bufF = 0;
     uint32_t capC = 0, capF = 0;
     uint32_t lanes = 8;  // lanes per insertion of the cavity kernel
+    bool lanes_auto = true;  // lanes_per_insert 0: 64 lanes in rounds below SMALL_ROUND
+    uint32_t large_lanes = 256;  // the same in rounds for large cavities (64 or 256)
     double frac = 0;     // round size as a fraction of the mesh's vertices
     uint32_t call_clouds = 1;  // clouds of the insertion call in progress
     // dt_autotune's choices by size class (floor(log2 n) of the sample): an insertion takes
     // the choice of the nearest tuned class; without any, the options decide
     struct Tuned {
         bool set = false;
-        uint32_t lanes = 0, cap = 0;
+        uint32_t lanes = 0, cap = 0, large = 0;
         double frac = 0;
         double ms = 0;
     } tuned[64];
@@ -436,6 +441,8 @@ int grow_tets(dt_ctx *c, uint64_t need);
 void apply_options(dt_ctx *c) {
     c->capC = c->opt.cavity_cap ? c->opt.cavity_cap : DEFAULT_CAVITY_CAP;
     c->lanes = c->opt.lanes_per_insert ? c->opt.lanes_per_insert : DEFAULT_LANES;
+    c->lanes_auto = c->opt.lanes_per_insert == 0;
+    c->large_lanes = c->opt.large_lanes ? c->opt.large_lanes : DEFAULT_LARGE_LANES;
     c->frac = c->opt.round_fraction > 0 ? c->opt.round_fraction : DEFAULT_ROUND_FRACTION;
     c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
 }
@@ -454,7 +461,9 @@ void select_launch(dt_ctx *c, uint64_t n) {
             best = j;
     if (best < 0) return;
     const dt_ctx::Tuned &t = c->tuned[best];
-    c->lanes = t.lanes;
+    c->lanes = t.lanes ? t.lanes : DEFAULT_LANES;
+    c->lanes_auto = t.lanes == 0;
+    c->large_lanes = t.large;
     c->capC = t.cap;
     c->frac = t.frac;
     c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
@@ -578,7 +587,10 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     // timing 1: events around both kernels; 2: around the cavity kernel only (each event
     // record leaves the GPU idle for a few microseconds)
     hipEvent_t evs[3] = {c->ev[slot][0], c->ev[slot][1], c->opt.timing == 1 ? c->ev[slot][2] : nullptr};
-    HIPCHK(launch_round(a, c->wide, max_cand, c->lanes, c->stream, c->opt.timing ? evs : nullptr));
+    // automatic lanes: a wavefront per insertion in short rounds, which wait on their slowest
+    // candidate, c->lanes in the rest
+    const uint32_t lanes = c->lanes_auto && max_cand < SMALL_ROUND ? 64u : c->lanes;
+    HIPCHK(launch_round(a, c->wide, max_cand, lanes, c->large_lanes, c->stream, c->opt.timing ? evs : nullptr));
     c->fl_idx ^= 1;
     if (c->ring_direct) {
         c->slot_tag[slot] = ++c->tag_counter;
@@ -1257,7 +1269,8 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
     if (c->opt.round_fraction < 0 || c->opt.round_fraction > 64 ||
         (c->opt.lanes_per_insert != 0 && c->opt.lanes_per_insert != 4 && c->opt.lanes_per_insert != 8 &&
          c->opt.lanes_per_insert != 16 && c->opt.lanes_per_insert != 32 && c->opt.lanes_per_insert != 64) ||
-        (c->opt.index_bits != 0 && c->opt.index_bits != 32 && c->opt.index_bits != 64)) {
+        (c->opt.index_bits != 0 && c->opt.index_bits != 32 && c->opt.index_bits != 64) ||
+        (c->opt.large_lanes != 0 && c->opt.large_lanes != 64 && c->opt.large_lanes != 256)) {
         delete c;
         return DT_E_ARG;
     }
@@ -1492,10 +1505,11 @@ int dt_autotune(dt_ctx *c, const double *xyz, uint64_t n, dt_options *best, doub
         HIPCHK(hipMemcpyAsync(sample.p, xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
         dxyz = sample.p;
     }
-    static const uint32_t lanes[] = {8, 16, 32, 64};
+    static const uint32_t lanes[] = {0, 8, 16, 32};  // 0: automatic
     static const double fracs[] = {3.0 / 64, 1.0 / 16, 3.0 / 32};
     static const uint32_t caps[] = {64, 128};
-    constexpr int NL = 4, NF = 3, NC = 2;
+    static const uint32_t larges[] = {64, 256};
+    constexpr int NL = 4, NF = 3, NC = 2, NB = 2;
     const int cls = size_class(n);
     const dt_options saved = c->opt;
     const dt_ctx::Tuned saved_entry = c->tuned[cls];
@@ -1506,10 +1520,11 @@ int dt_autotune(dt_ctx *c, const double *xyz, uint64_t n, dt_options *best, doub
     dt_ctx::Tuned keep[64];
     std::copy(std::begin(c->tuned), std::end(c->tuned), keep);
     for (auto &t : c->tuned) t.set = false;
-    for (int warm = 1, k = 0; k < NL * NF * NC && rc == DT_OK; warm = 0) {
-        c->opt.lanes_per_insert = lanes[k / (NF * NC)];
-        c->opt.round_fraction = fracs[(k / NC) % NF];
-        c->opt.cavity_cap = caps[k % NC];
+    for (int warm = 1, k = 0; k < NL * NF * NC * NB && rc == DT_OK; warm = 0) {
+        c->opt.lanes_per_insert = lanes[k / (NF * NC * NB)];
+        c->opt.round_fraction = fracs[(k / (NC * NB)) % NF];
+        c->opt.cavity_cap = caps[(k / NB) % NC];
+        c->opt.large_lanes = larges[k % NB];
         auto t0 = std::chrono::steady_clock::now();
         rc = dt_insert_points(c, dxyz, n);
         if (rc == DT_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = DT_E_DEVICE;
@@ -1539,6 +1554,7 @@ int dt_autotune(dt_ctx *c, const double *xyz, uint64_t n, dt_options *best, doub
     t.lanes = bo.lanes_per_insert;
     t.frac = bo.round_fraction;
     t.cap = bo.cavity_cap;
+    t.large = bo.large_lanes;
     t.ms = bms;
     apply_options(c);
     if (best) *best = bo;

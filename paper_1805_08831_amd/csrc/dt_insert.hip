@@ -1364,15 +1364,15 @@ __global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, uint32_t flc
 constexpr uint32_t DEFER_BLOCKS = 512;  // grid of the exact-predicate pass (grid-stride)
 
 template <class K>
-static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, hipStream_t s,
-                                 hipEvent_t *ev) {
+static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, uint32_t large_lanes,
+                                 hipStream_t s, hipEvent_t *ev) {
     constexpr uint32_t LHM = K::LHM;
     if (ev) hipEventRecord(ev[0], s);
     // regular rounds: the filter-only kernel over the round's list, then the exact kernel over
     // the attempts it handed on (a short grid-stride pass; nothing to do for most rounds);
     // rounds for large cavities use exact predicates throughout
     const uint32_t dgrid = std::min<uint32_t>((max_cand + 31) / 32, DEFER_BLOCKS);
-    static const bool blk = getenv("DT_LARGE_BLOCK") && getenv("DT_LARGE_BLOCK")[0] == '1';
+    const bool blk = large_lanes != 64;
     if (blk && a.capC > BIG_CAPC) {
         if (a.hmg < 4096 || (a.hmg & (a.hmg - 1)) || (uint64_t)a.hmg * sizeof(typename K::set_t) > 16ull * a.capC)
             return hipErrorInvalidValue;
@@ -1403,9 +1403,9 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
         k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     }
     if (ev) hipEventRecord(ev[1], s);
-    // rounds for large cavities build large balls (their siblings found by pivoting): a
-    // wavefront per candidate
-    if (a.capC > LCAPC)
+    // rounds for large cavities build large balls (their siblings found by pivoting), and
+    // short rounds wait on their slowest candidate: a wavefront per candidate
+    if (a.capC > LCAPC || lanes == 64)
         k_ball<K, 64, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 64 - 1) / (BALL_BLOCK / 64), BALL_BLOCK, 0, s>>>(a);
     else
         k_ball<K, 16, BALL_BLOCK><<<(max_cand + BALL_BLOCK / 16 - 1) / (BALL_BLOCK / 16), BALL_BLOCK, 0, s>>>(a);
@@ -1413,10 +1413,11 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_round(const RoundArgs &a, bool wide, uint32_t max_cand, uint32_t lanes, hipStream_t s,
-                        hipEvent_t *ev) {
+hipError_t launch_round(const RoundArgs &a, bool wide, uint32_t max_cand, uint32_t lanes, uint32_t large_lanes,
+                        hipStream_t s, hipEvent_t *ev) {
     if (max_cand == 0) return hipSuccess;
-    return wide ? launch_round_k<Wide>(a, max_cand, lanes, s, ev) : launch_round_k<Narrow>(a, max_cand, lanes, s, ev);
+    return wide ? launch_round_k<Wide>(a, max_cand, lanes, large_lanes, s, ev)
+                : launch_round_k<Narrow>(a, max_cand, lanes, large_lanes, s, ev);
 }
 
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s, Ctr *snap,

@@ -27,7 +27,8 @@ class dt_options(ctypes.Structure):
                 ("cavity_cap", ctypes.c_uint32), ("capacity_tets", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("max_rounds", ctypes.c_uint32), ("timing", ctypes.c_int), ("round_fraction", ctypes.c_double),
                 ("lanes_per_insert", ctypes.c_uint32), ("scheduler", ctypes.c_int), ("log_points", ctypes.c_int),
-                ("index_bits", ctypes.c_int), ("adaptive_curve", ctypes.c_int), ("subdet_cache", ctypes.c_int), ("walk_cap", ctypes.c_uint32)]
+                ("index_bits", ctypes.c_int), ("adaptive_curve", ctypes.c_int), ("subdet_cache", ctypes.c_int), ("walk_cap", ctypes.c_uint32),
+                ("large_lanes", ctypes.c_uint32)]
 
 DT_SCHED_PLAIN, DT_SCHED_LEARNED = 0, 1
 NFEAT, NHID, NOUT = 16, 64, 3
@@ -356,7 +357,7 @@ class Triangulation:
 
     def __init__(self, device=0, stream=None, round_size=0, cavity_cap=0, capacity_tets=0, seed=0x5EED,
                  max_rounds=0, timing=False, round_fraction=0.0, lanes_per_insert=0, scheduler=0, log_points=False,
-                 index_bits=0, adaptive_curve=False, subdet_cache=False, walk_cap=0):
+                 index_bits=0, adaptive_curve=False, subdet_cache=False, walk_cap=0, large_lanes=0):
         o = dt_default_options()
         o.device, o.round_size, o.cavity_cap = int(device), int(round_size), int(cavity_cap)
         o.capacity_tets, o.seed, o.max_rounds = int(capacity_tets), int(seed), int(max_rounds)
@@ -367,6 +368,7 @@ class Triangulation:
         o.adaptive_curve = int(bool(adaptive_curve))
         o.subdet_cache = int(bool(subdet_cache))
         o.walk_cap = int(walk_cap)
+        o.large_lanes = int(large_lanes)
         o.stream = stream
         self.ctx = dt_create(o)
 
@@ -399,7 +401,7 @@ class Triangulation:
             xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         best, ms = dt_autotune(self.ctx, xyz)
         return {"lanes_per_insert": best.lanes_per_insert, "round_fraction": best.round_fraction,
-                "cavity_cap": best.cavity_cap, "ms": ms}
+                "cavity_cap": best.cavity_cap, "large_lanes": best.large_lanes, "ms": ms}
 
     def num_tets(self):
         return dt_get_tets(self.ctx)

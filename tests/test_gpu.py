@@ -286,7 +286,8 @@ def test_append_and_clear(dtlib, oracle_mod):
                                   dict(lanes_per_insert=4, cavity_cap=200),
                                   dict(cavity_cap=2048), dict(lanes_per_insert=16, cavity_cap=1500),
                                   dict(capacity_tets=4096), dict(walk_cap=1), dict(walk_cap=3),
-                                  dict(walk_cap=0xFFFFFFFF)])
+                                  dict(walk_cap=0xFFFFFFFF), dict(large_lanes=64, cavity_cap=4),
+                                  dict(large_lanes=256, cavity_cap=4), dict(large_lanes=64, cavity_cap=12)])
 def test_launch_options_do_not_change_result(dtlib, oracle_mod, opts):
     say(f"options {opts}")
     xyz = mix_small(51, 4000)
@@ -442,7 +443,8 @@ def test_autotune_keeps_results(dtlib, oracle_mod):
     with dtlib.Triangulation() as tri:
         for size, seed in ((20000, 31), (3000, 33)):
             best = tri.autotune(uniform_points(size, seed))
-            assert best["lanes_per_insert"] in (8, 16, 32, 64) and best["cavity_cap"] in (64, 128)
+            assert best["lanes_per_insert"] in (0, 8, 16, 32) and best["cavity_cap"] in (64, 128)
+            assert best["large_lanes"] in (64, 256)
             assert best["round_fraction"] in (3 / 64, 1 / 16, 3 / 32) and best["ms"] > 0
             assert tri.stats()["points"] == 0
         for n, seed in ((5000, 32), (2500, 34), (40000, 35)):

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("opts", [dict(), dict(lanes_per_insert=4), dict(lanes_per_insert=16), dict(lanes_per_insert=32),
                                   dict(lanes_per_insert=64), dict(cavity_cap=12),
                                   dict(lanes_per_insert=4, cavity_cap=200), dict(cavity_cap=2048),
-                                  dict(capacity_tets=4096), dict(round_size=64)])
+                                  dict(capacity_tets=4096), dict(round_size=64), dict(large_lanes=64, cavity_cap=12)])
 def test_wide_codes_launch_options(dtlib, oracle_mod, opts):
     say(f"64-bit codes, options {opts}")
     xyz = mix_small(52, 4000)
