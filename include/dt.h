@@ -58,9 +58,11 @@ typedef struct {
     uint64_t capacity_tets; /* initial tetrahedron pool (grown on demand); 0: automatic   */
     uint64_t seed;          /* seed of the randomized insertion levels (BRIO, Sec. 2.3)  */
     uint32_t max_rounds;    /* 0: unlimited; otherwise DT_E_INCOMPLETE beyond it          */
-    int timing;             /* 1: time the two insertion kernels with HIP events (three
-                               per round); 2: the cavity kernel only (two per round: an
-                               event record leaves the GPU idle for a few microseconds)  */
+    int timing;             /* 1: time the two insertion kernels of every round with HIP
+                               events (three per round); 2: the cavity kernel of rounds of
+                               at least 32768 candidates only (two per such round: an
+                               event record leaves the GPU idle for a few microseconds,
+                               which short rounds feel most)                             */
     double round_fraction;  /* round size as a fraction of the current vertex count;
                                0: automatic                                              */
     uint32_t lanes_per_insert; /* lanes of a wavefront cooperating on one insertion in the
@@ -134,6 +136,8 @@ typedef struct {
                                  again with exact predicates in the same round           */
     uint64_t walk_caps;       /* attempts stopped by dt_options.walk_cap (counted among
                                  the conflicts too: they retry in the next round)        */
+    uint64_t timed_attempts, timed_insertions; /* attempts and insertions of the rounds
+                                 timed by dt_options.timing (cavity_launches of them)    */
 } dt_stats;
 
 /* Fill *opt with the defaults (device 0, library stream, automatic sizes, seed 0x5EED). */

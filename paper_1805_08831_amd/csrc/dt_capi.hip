@@ -160,6 +160,7 @@ struct dt_ctx {
     hipEvent_t ev[3][3] = {};   // per snapshot slot: kernel timing events of its round
     hipEvent_t evdone[3] = {};  // per snapshot slot: its copy has landed
     uint32_t slot_cand[3] = {}, slot_capC[3] = {};
+    bool slot_timed[3] = {};  // the round in the slot recorded timing events
     bool grow_pending = false;  // a round found the pool full: grow before the next one
     dt_stats st{};
     uint32_t trace_prev_won = 0, trace_prev_conf = 0, trace_prev_ovf = 0;
@@ -584,13 +585,16 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
         a.clk = c->clk[slot];
     }
     c->round_counter++;
-    // timing 1: events around both kernels; 2: around the cavity kernel only (each event
-    // record leaves the GPU idle for a few microseconds)
+    // timing 1: events around both kernels in every round; 2: around the cavity kernel in
+    // rounds of at least SMALL_ROUND candidates (each event record leaves the GPU idle for a
+    // few microseconds, which the short rounds would feel most)
     hipEvent_t evs[3] = {c->ev[slot][0], c->ev[slot][1], c->opt.timing == 1 ? c->ev[slot][2] : nullptr};
+    const bool timed = c->opt.timing == 1 || (c->opt.timing == 2 && max_cand >= SMALL_ROUND);
+    c->slot_timed[slot] = timed;
     // automatic lanes: a wavefront per insertion in short rounds, which wait on their slowest
     // candidate, c->lanes in the rest
     const uint32_t lanes = c->lanes_auto && max_cand < SMALL_ROUND ? 64u : c->lanes;
-    HIPCHK(launch_round(a, c->wide, max_cand, lanes, c->large_lanes, c->stream, c->opt.timing ? evs : nullptr));
+    HIPCHK(launch_round(a, c->wide, max_cand, lanes, c->large_lanes, c->stream, timed ? evs : nullptr));
     c->fl_idx ^= 1;
     if (c->ring_direct) {
         c->slot_tag[slot] = ++c->tag_counter;
@@ -695,9 +699,15 @@ int complete_round(dt_ctx *c, int slot) {
         // flight behind this one completes too, which is correct, only not overlapped
         HIPCHK(hipStreamSynchronize(c->stream));
     }
+    const uint32_t won_before = c->hctr->won;
+    const unsigned long long att_before = c->hctr->attempts;
     c->hctr = &c->hring[slot];
     const uint32_t max_cand = c->slot_cand[slot], capC = c->slot_capC[slot];
-    if (max_cand) accumulate_timing(c, slot);
+    if (max_cand && c->slot_timed[slot]) {
+        accumulate_timing(c, slot);
+        c->st.timed_insertions += c->hctr->won - won_before;
+        c->st.timed_attempts += c->hctr->attempts - att_before;
+    }
     if (c->trace) {
         uint32_t &prev_won = c->trace_prev_won;
         if (prev_won > c->hctr->won) {
@@ -707,7 +717,7 @@ int complete_round(dt_ctx *c, int slot) {
         }
         float ta = 0.f, tb = 0.f;
         if (c->opt.timing && max_cand) {
-            hipEventElapsedTime(&ta, c->ev[slot][0], c->ev[slot][1]);
+            if (c->slot_timed[slot]) hipEventElapsedTime(&ta, c->ev[slot][0], c->ev[slot][1]);
             if (c->opt.timing == 1) hipEventElapsedTime(&tb, c->ev[slot][1], c->ev[slot][2]);
         }
         fprintf(stderr,

@@ -48,7 +48,8 @@ class dt_stats(ctypes.Structure):
                  ("cavity_units", ctypes.c_uint64), ("ball_units", ctypes.c_uint64),
                  ("sched_fallbacks", ctypes.c_uint64), ("index_bits", ctypes.c_uint64),
                  ("dropped_slots", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
-                 ("walk_caps", ctypes.c_uint64)])
+                 ("walk_caps", ctypes.c_uint64), ("timed_attempts", ctypes.c_uint64),
+                 ("timed_insertions", ctypes.c_uint64)])
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

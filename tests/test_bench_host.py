@@ -115,7 +115,7 @@ def _stand_ins(monkeypatch):
     stats = {n: 0 for n, _ in dt.dt_stats._fields_}
     stats.update(attempts=1350, walk_steps=7700, cavity_tets=20000, boundary_facets=26800, inserted=1000,
                  ms_cavity_kernel=12.0, ms_ball_kernel=7.0, cavity_launches=50, ball_launches=50, rounds=50,
-                 ms_sort=3.0, ms_insert=20.0)
+                 ms_sort=3.0, ms_insert=20.0, timed_insertions=1000, timed_attempts=1350)
 
     class Tri:
         def __init__(self, **k):

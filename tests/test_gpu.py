@@ -549,8 +549,8 @@ def test_learned_scheduler_keeps_result(dtlib, oracle_mod):
 
 @pytest.mark.parametrize("timing", [0, 1, 2])
 def test_timing_modes(dtlib, oracle_mod, timing):
-    """Timing 1 times both insertion kernels per round, 2 the cavity kernel only, 0 neither;
-    the result is the same."""
+    """Timing 1 times both insertion kernels of every round, 2 the cavity kernel of rounds of
+    at least 32768 candidates (none at this size), 0 neither; the result is the same."""
     say(f"timing {timing}")
     xyz = uniform_points(30000, 41)
     with dtlib.Triangulation(timing=timing) as tri:
@@ -558,9 +558,27 @@ def test_timing_modes(dtlib, oracle_mod, timing):
         t, _ = tri.tets()
         st = tri.stats()
     assert_parity(oracle_mod, xyz, t.astype(np.int64), f"timing {timing}")
-    if timing == 0:
-        assert st["cavity_launches"] == 0 and st["ball_launches"] == 0
-    else:
+    if timing == 1:
         assert 0 < st["cavity_launches"] <= st["rounds"] and st["ms_cavity_kernel"] > 0
-        assert (st["ball_launches"] == st["cavity_launches"] and st["ms_ball_kernel"] > 0) if timing == 1 else \
-            (st["ball_launches"] == 0 and st["ms_ball_kernel"] == 0)
+        assert st["ball_launches"] == st["cavity_launches"] and st["ms_ball_kernel"] > 0
+        assert st["timed_insertions"] == st["inserted"] and st["timed_attempts"] == st["attempts"]
+    else:
+        assert st["cavity_launches"] == 0 and st["ball_launches"] == 0 and st["timed_insertions"] == 0
+
+
+def test_timing_large_rounds(dtlib):
+    """Timing 2 on 2e6 points times the rounds of at least 32768 candidates: some but not all
+    rounds, the counts of their insertions and attempts; the output equals an untimed run's."""
+    from canon import canonical_hash
+    say("timing 2 on 2e6 points")
+    xyz = uniform_points(2_000_000, 43)
+    out = {}
+    for timing in (0, 2):
+        with dtlib.Triangulation(timing=timing) as tri:
+            tri.insert(xyz)
+            t, _ = tri.tets()
+            out[timing] = (canonical_hash(t), tri.stats())
+    assert out[0][0] == out[2][0]
+    st = out[2][1]
+    assert 0 < st["cavity_launches"] < st["rounds"] and st["ms_cavity_kernel"] > 0 and st["ball_launches"] == 0
+    assert 0 < st["timed_insertions"] < st["inserted"] and st["timed_insertions"] <= st["timed_attempts"]
