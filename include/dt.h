@@ -64,7 +64,8 @@ typedef struct {
                                event record leaves the GPU idle for a few microseconds,
                                which short rounds feel most)                             */
     double round_fraction;  /* round size as a fraction of the current vertex count;
-                               0: automatic                                              */
+                               0: automatic (1/16, and 3/32 for rounds that stay below
+                               32768 candidates)                                         */
     uint32_t lanes_per_insert; /* lanes of a wavefront cooperating on one insertion in the
                                   walk and cavity search: 4, 8, 16, 32 or 64 in every
                                   round; 0: automatic (64 in rounds of fewer than 32768
@@ -191,7 +192,8 @@ int dt_insert_batch(dt_ctx *ctx, const double *xyz, const uint64_t *offsets, uin
 int dt_get_tets_batch(dt_ctx *ctx, uint32_t cloud, uint32_t *tets, int64_t *nbrs, uint64_t *num_tets);
 
 /* Autotuner: triangulates the n sample points (host or device memory) once per launch
-   configuration - lanes per insertion {automatic, 8, 16, 32}, round fraction {3/64, 1/16, 3/32},
+   configuration - lanes per insertion {automatic, 8, 16, 32}, round fraction {automatic, 3/64,
+   3/32},
    cavity cap {64, 128}, lanes per insertion for large cavities {64, 256} (a wavefront or a
    256-thread block) - after one warm-up run, and keeps
    the fastest (host wall time of dt_insert_points) for the sample's size class,

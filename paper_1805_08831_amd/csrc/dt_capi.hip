@@ -33,8 +33,10 @@ constexpr uint32_t DEFAULT_LANES = 16;
 constexpr double DEFAULT_ROUND_FRACTION = 1.0 / 16.0;
 constexpr uint32_t DEFAULT_WALK_CAP = 16;
 constexpr uint32_t DEFAULT_LARGE_LANES = 256;
-// automatic lanes: rounds of fewer candidates than this use 64 lanes per insertion
+// automatic lanes: rounds of fewer candidates than this use 64 lanes per insertion; with the
+// automatic round fraction they take 1.5 times the usual share of the mesh's vertices
 constexpr uint32_t SMALL_ROUND = 32768;
+constexpr double SHORT_ROUND_FRACTION_SCALE = 1.5;
 constexpr uint32_t ROUND_MIN = 64;
 constexpr uint32_t DRAIN_SLICE = 4096;  // candidates per round when draining overflowed cavities
 constexpr uint32_t EXPORT_CHUNK = 1u << 24;  // slots per staged export launch (a multiple of 64)
@@ -119,6 +121,7 @@ struct dt_ctx {
     bool lanes_auto = true;  // lanes_per_insert 0: 64 lanes in rounds below SMALL_ROUND
     uint32_t large_lanes = 256;  // the same in rounds for large cavities (64 or 256)
     double frac = 0;     // round size as a fraction of the mesh's vertices
+    bool frac_auto = true;  // round_fraction 0: short rounds take SHORT_ROUND_FRACTION_SCALE times more
     uint32_t call_clouds = 1;  // clouds of the insertion call in progress
     // dt_autotune's choices by size class (floor(log2 n) of the sample): an insertion takes
     // the choice of the nearest tuned class; without any, the options decide
@@ -445,6 +448,7 @@ void apply_options(dt_ctx *c) {
     c->lanes_auto = c->opt.lanes_per_insert == 0;
     c->large_lanes = c->opt.large_lanes ? c->opt.large_lanes : DEFAULT_LARGE_LANES;
     c->frac = c->opt.round_fraction > 0 ? c->opt.round_fraction : DEFAULT_ROUND_FRACTION;
+    c->frac_auto = !(c->opt.round_fraction > 0);
     c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
 }
 
@@ -466,7 +470,8 @@ void select_launch(dt_ctx *c, uint64_t n) {
     c->lanes_auto = t.lanes == 0;
     c->large_lanes = t.large;
     c->capC = t.cap;
-    c->frac = t.frac;
+    c->frac = t.frac > 0 ? t.frac : DEFAULT_ROUND_FRACTION;
+    c->frac_auto = !(t.frac > 0);
     c->capF = std::max<uint32_t>(4, (5 * c->capC) / 3);
 }
 
@@ -864,6 +869,11 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint3
             if (k & 1) f *= c->costly_scale;
         }
         uint64_t t = (uint64_t)std::llround(f * (double)c->mesh_vertices);
+        // automatic fraction: short rounds, which last as long as their slowest insertion
+        // whatever their size, take a larger share (up to SMALL_ROUND candidates)
+        if (c->frac_auto && t < SMALL_ROUND)
+            t = std::min<uint64_t>(SMALL_ROUND, (uint64_t)std::llround(f * SHORT_ROUND_FRACTION_SCALE *
+                                                                     (double)c->mesh_vertices));
         if (c->opt.round_size) t = c->opt.round_size;
         return std::min<uint64_t>(std::max<uint64_t>(t, ROUND_MIN), rmax);
     };
@@ -1516,7 +1526,7 @@ int dt_autotune(dt_ctx *c, const double *xyz, uint64_t n, dt_options *best, doub
         dxyz = sample.p;
     }
     static const uint32_t lanes[] = {0, 8, 16, 32};  // 0: automatic
-    static const double fracs[] = {3.0 / 64, 1.0 / 16, 3.0 / 32};
+    static const double fracs[] = {0.0, 3.0 / 64, 3.0 / 32};  // 0: automatic
     static const uint32_t caps[] = {64, 128};
     static const uint32_t larges[] = {64, 256};
     constexpr int NL = 4, NF = 3, NC = 2, NB = 2;
