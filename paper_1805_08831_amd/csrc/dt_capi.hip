@@ -37,7 +37,7 @@ constexpr uint32_t DEFAULT_LARGE_LANES = 256;
 // automatic round fraction they take 1.5 times the usual share of the mesh's vertices
 constexpr uint32_t SMALL_ROUND = 32768;
 constexpr double SHORT_ROUND_FRACTION_SCALE = 1.5;
-constexpr uint32_t ROUND_MIN = 64;
+constexpr uint32_t ROUND_MIN = 256;
 constexpr uint32_t DRAIN_SLICE = 4096;  // candidates per round when draining overflowed cavities
 constexpr uint32_t EXPORT_CHUNK = 1u << 24;  // slots per staged export launch (a multiple of 64)
 constexpr size_t TET_BYTES = 64;               // one tetrahedron record, either layout
@@ -874,7 +874,7 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint3
         if (c->frac_auto && t < SMALL_ROUND)
             t = std::min<uint64_t>(SMALL_ROUND, (uint64_t)std::llround(f * SHORT_ROUND_FRACTION_SCALE *
                                                                      (double)c->mesh_vertices));
-        if (c->opt.round_size) t = c->opt.round_size;
+        if (c->opt.round_size) return std::min<uint64_t>(c->opt.round_size, rmax);
         return std::min<uint64_t>(std::max<uint64_t>(t, ROUND_MIN), rmax);
     };
     // completes the round in flight: mesh size, loss share (a pool growth it asks for waits
