@@ -207,7 +207,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per insertion in every round (4, 8, 16, 32, 64; 0: automatic)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick lanes per insertion, round fraction and cavity cap on a 2e6-point sample first")
-    ap.add_argument("--workload", choices=["uniform", "batch", "mix"], default="uniform")
+    ap.add_argument("--workload", choices=["uniform", "batch", "mix", "refine"], default="uniform")
     ap.add_argument("--no-learned", action="store_true", help="uniform: skip the learned-scheduler comparison")
     ap.add_argument("--train-seeds", type=str, default="9001,9002", help="seeds of the plain runs logged for training")
     ap.add_argument("--train-samples", type=int, default=4_000_000, help="samples drawn from the logs")
@@ -220,6 +220,12 @@ def main():
                     help="batch: clouds per dt_insert_batch call (default: all in one call, the pool then "
                          "takes 64-bit adjacency codes)")
     ap.add_argument("--loop-sample", type=int, default=64, help="batch: clouds timed one call each")
+    ap.add_argument("--refine-n", type=int, default=250_000, help="refine: uniform input points (seed 4007)")
+    ap.add_argument("--refine-h", type=float, default=0.0064,
+                    help="refine: target size h (circumcentres of tetrahedra with r > 1.4 h, none closer "
+                         "than 0.7 h)")
+    ap.add_argument("--cpu-refine-points", type=int, default=15_000,
+                    help="refine: input points of the oracle's CPU sample (a corner cube of the input)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
     ap.add_argument("--gather-calibration", action="store_true",
@@ -243,6 +249,9 @@ def main():
         return
     if args.workload == "mix":
         run_mix(args)
+        return
+    if args.workload == "refine":
+        run_refine(args)
         return
 
     import torch
@@ -875,6 +884,132 @@ def run_batch(args):
         "loop_single": {"value": round(tt / tl, 1), "unit": "tetrahedra/s",
                         "sample": f"{len(sample)} of the clouds ({pts} points), one dt_insert_points call each"},
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_clouds(xyz, off, sample),
+    }
+    print(json.dumps(line), flush=True)
+    tri.close()
+
+
+def cpu_baseline_refine(xyz, n, h, sample_points):
+    """The refinement oracle (one thread) on the input's points in the corner cube [0, s)^3
+    that holds about sample_points of them, with the same h: tetrahedra of its final mesh per
+    second of refinement (the input's triangulation included: the oracle retriangulates every
+    step)."""
+    import numpy as np
+
+    from oracle.refine import refine
+    s = (sample_points / n) ** (1.0 / 3.0)
+    sub = xyz[np.all(xyz < s, axis=1)]
+    t0 = time.perf_counter()
+    pts, tets, _, steps = refine(sub, h)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(tets) / dt, 1), "unit": "tetrahedra/s", "cores": 1, "kind": "oracle",
+            "sample": f"the {len(sub)} input points in [0, {s:.4f})^3, refined with the same h to {len(pts)} "
+                      f"points and {len(tets)} tetrahedra in {len(steps)} steps, serially in {dt:.2f} s",
+            "cpu": host_cpu_model(), "host_threads": os.cpu_count()}
+
+
+def run_refine(args):
+    """Delaunay refinement by circumcentre insertion (paper Sec. 4, the sample / filter /
+    insert loop of its mesh generator) over the convex hull of a uniform cloud.  A step
+    triangulates the input (not timed) and then refines it with dt_refine: circumcentres of
+    the tetrahedra with r > 1.4 h that lie strictly inside the hull, none within 0.7 h of a
+    vertex or of a point kept before it, inserted through the same rounds, until a pass keeps
+    none.  The timed part is the refinement alone, as the paper's refinement column leaves
+    out the initial mesh; the value is the final mesh's tetrahedra per second of it."""
+    import numpy as np
+    import torch
+
+    from paper_1805_08831_amd import Triangulation, dt_get_tets
+    from paper_1805_08831_amd.dt import dt_refine
+    from synth import uniform_points
+
+    t_bench = time.perf_counter()
+
+    def progress(msg):
+        print(f"[bench] {msg} ({time.perf_counter() - t_bench:.1f} s)", file=sys.stderr, flush=True)
+
+    n, h, seed = args.refine_n, args.refine_h, 4007
+    xyz = uniform_points(n, seed)
+    d_xyz = torch.from_numpy(xyz).cuda()
+    stream = torch.cuda.current_stream()
+    tri = Triangulation(device=0, stream=stream.cuda_stream, timing=2, lanes_per_insert=args.lanes,
+                        round_fraction=args.round_fraction, round_size=args.round_size)
+    keys = ("attempts", "walk_steps", "cavity_tets", "boundary_facets", "inserted", "ms_cavity_kernel",
+            "cavity_launches", "rounds", "conflicts", "timed_insertions", "timed_attempts", "ms_sort", "ms_insert",
+            "walk_caps", "deferred", "orient_calls", "orient_exact", "insphere_calls", "insphere_exact", "perturbed",
+            "overflows")
+
+    def step():
+        tri.clear()
+        tri.insert(d_xyz)
+        T0 = dt_get_tets(tri.ctx)
+        torch.cuda.synchronize()
+        s0 = tri.stats()
+        t0 = time.perf_counter()
+        added, steps = dt_refine(tri.ctx, h)
+        T = dt_get_tets(tri.ctx)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s1 = tri.stats()
+        return dt, T0, T, added, steps, {k: s1[k] - s0[k] for k in keys}
+
+    for _ in range(args.warmup):
+        step()
+    runs = [step() for _ in range(args.steps)]
+    ms = 1000.0 * sum(r[0] for r in runs) / len(runs)
+    dt, T0, T, added, steps, d = runs[-1]
+    if any(r[2] != T or r[3] != added or r[4] != steps for r in runs):
+        raise RuntimeError("refinement runs differ")
+    progress(f"refined {n} points to {n + added} ({T} tetrahedra) in {ms:.1f} ms, steps {steps}")
+    agg = {k: sum(r[5][k] for r in runs) for k in keys}
+    att, won = max(agg["attempts"], 1), max(agg["inserted"], 1)
+    C, F = agg["cavity_tets"] / won, agg["boundary_facets"] / won
+    launches = max(agg["cavity_launches"], 1)
+    avg_launch_ms = agg["ms_cavity_kernel"] / launches
+    per_ins = cavity_bytes_per_insertion(C, F)
+    ins_per_launch = agg["timed_insertions"] / launches
+    achieved = per_ins * ins_per_launch / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
+    ms_insert = agg["ms_sort"] / len(runs) + agg["ms_insert"] / len(runs)
+    line = {
+        "metric": "tetrahedra/sec (Delaunay refinement by circumcentre insertion, final mesh)",
+        "value": round(T / (ms / 1000.0), 1),
+        "unit": "tetrahedra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"refinement of {n} i.i.d. uniform fp64 points in [0,1)^3 (seed {seed}), "
+                               f"h = {h}, convex hull as the domain",
+                   "input_tetrahedra": T0, "points_added": added, "final_points": n + added,
+                   "tetrahedra": T, "passes": [list(s) for s in steps]},
+        "roofline": {"bound": "hbm", "kernel": "k_cavity_g filter and exact passes of the refinement's "
+                                               "insertion rounds of 32768 candidates or more",
+                     "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(achieved / 8000.0, 5), "traffic": None,
+                     "bytes_per_insertion": round(per_ins, 1), "insertions_per_launch": round(ins_per_launch, 1),
+                     "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": round(launches / len(runs), 1)},
+        "detail": {"points_added_per_s": round(added / (ms / 1000.0), 1),
+                   # host clock inside the insertion calls; the rest is candidates, sorts and filter
+                   "ms_insertion_per_step": round(ms_insert, 3),
+                   "ms_selection_per_step": round(ms - ms_insert, 3),
+                   "rounds_per_step": agg["rounds"] / len(runs),
+                   "attempts_per_point": agg["attempts"] / max(agg["inserted"], 1),
+                   "conflict_rate": agg["conflicts"] / att,
+                   "walk_steps_per_attempt": round(agg["walk_steps"] / att, 3),
+                   "cavity_tets": round(C, 2), "boundary_facets": round(F, 2),
+                   # attempts stopped by the walk cap, handed to the exact pass, overflowed
+                   "walk_cap_rate": agg["walk_caps"] / att, "deferred_rate": agg["deferred"] / att,
+                   "overflow_rate": agg["overflows"] / att,
+                   "orient_exact_rate": agg["orient_exact"] / max(agg["orient_calls"], 1),
+                   "insphere_exact_rate": agg["insphere_exact"] / max(agg["insphere_calls"], 1),
+                   "perturbed_per_step": agg["perturbed"] / len(runs),
+                   "step_ms": [round(1000 * r[0], 2) for r in runs]},
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_refine(xyz, n, h, args.cpu_refine_points),
     }
     print(json.dumps(line), flush=True)
     tri.close()

@@ -214,6 +214,7 @@ struct dt_ctx {
     DevBuf<uint4> rf_q, rf_q2, rf_facets;
     DevBuf<unsigned long long> rf_moore, rf_k0, rf_k1;
     DevBuf<uint32_t> rf_v0, rf_v1, rf_ctr, rf_flags, rf_pos;
+    DevBuf<uint32_t> rf_src, rf_src2, rf_srcr, rf_hint;  // candidates' tetrahedron vertex records
     DevBuf<uint8_t> rf_status;
     DevBuf<Cloud> rf_cloud;
     DevBuf<uint64_t> rf_off;
@@ -1097,7 +1098,10 @@ int level_order(dt_ctx *c, uint32_t *svals, const Vert *V, uint64_t n, uint64_t 
 }
 
 // Inserts the n points at xyz, split into clouds by off (C + 1 offsets, off[0] = 0).
-int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<uint64_t> &off) {
+// hint (device, optional, one entry per input point of a single cloud): a vertex record
+// near the point, where its walk starts (its anchor)
+int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<uint64_t> &off,
+                  const uint32_t *hint = nullptr) {
     const uint32_t C = (uint32_t)(off.size() - 1);
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(hipSetDevice(c->device));
@@ -1151,6 +1155,7 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
     unsigned long long *d_rb;
     if ((rc = upload_levels(c, lv, &d_start, &d_size, &d_bits, &d_rb))) return rc;
     HIPCHK(launch_anchor(lord, d_start, L, c->V.p, base, n, c->anchor.p, c->stream));
+    if (hint) HIPCHK(launch_hint_anchor(c->V.p, base, n, c->npoints, hint, c->anchor.p, c->stream));
     HIPCHK(hipMemsetAsync(c->lastt.p, 0xFF, n * sizeof(uint32_t), c->stream));
     c->call_clouds = C;
     c->lord = lord;
@@ -1835,6 +1840,11 @@ int dt_destroy(dt_ctx *c) {
     f(c->lev.p); f(c->wbucket.p); f(c->log_att.p); f(c->feat.p); f(c->ypred.p);
     f(c->w32.p); f(c->m1.p); f(c->m2.p); f(c->grad.p); f(c->loss.p); f(c->wbf.p);
     f(c->obits.p); f(c->owcnt.p); f(c->opre.p); f(c->otets.p); f(c->onbrs.p); f(c->ovid.p);
+    f(c->rf_cc.p); f(c->rf_cc2.p); f(c->rf_ccr.p); f(c->rf_pts.p); f(c->rf_partial.p);
+    f(c->rf_q.p); f(c->rf_q2.p); f(c->rf_facets.p); f(c->rf_moore.p); f(c->rf_k0.p); f(c->rf_k1.p);
+    f(c->rf_v0.p); f(c->rf_v1.p); f(c->rf_ctr.p); f(c->rf_flags.p); f(c->rf_pos.p);
+    f(c->rf_src.p); f(c->rf_src2.p); f(c->rf_srcr.p); f(c->rf_hint.p);
+    f(c->rf_status.p); f(c->rf_cloud.p); f(c->rf_off.p);
     for (int k = 0; k < 3; ++k) {
         for (int j = 0; j < 3; ++j)
             if (c->ev[k][j]) hipEventDestroy(c->ev[k][j]);
@@ -2136,16 +2146,17 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         const uint64_t nv = c->nv;
         // 1. candidates: circumcentres of the tetrahedra larger than 1.4 h, strictly inside
         if ((rc = ensure(c, c->rf_cc, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q, count)) ||
-            (rc = ensure(c, c->rf_cc2, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q2, count)))
+            (rc = ensure(c, c->rf_cc2, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q2, count)) ||
+            (rc = ensure(c, c->rf_src, count)) || (rc = ensure(c, c->rf_src2, count)))
             return rc;
         HIPCHK(hipMemsetAsync(c->rf_ctr.p, 0, 4 * sizeof(uint32_t), c->stream));
-        HIPCHK(launch_circum(c->T, c->wide, c->V.p, count, grow, c->rf_cc.p, c->rf_q.p, count, c->rf_ctr.p,
-                             c->stream));
+        HIPCHK(launch_circum(c->T, c->wide, c->V.p, count, grow, c->rf_cc.p, c->rf_q.p, c->rf_src.p, count,
+                             c->rf_ctr.p, c->stream));
         uint32_t k0 = 0;
         HIPCHK(hipMemcpyAsync(&k0, c->rf_ctr.p, sizeof k0, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(launch_inside(c->V.p, c->rf_facets.p, nf, c->rf_cc.p, c->rf_q.p, k0, c->rf_cc2.p, c->rf_q2.p,
-                             c->rf_ctr.p + 1, c->stream));
+        HIPCHK(launch_inside(c->V.p, c->rf_facets.p, nf, c->rf_cc.p, c->rf_q.p, c->rf_src.p, k0, c->rf_cc2.p,
+                             c->rf_q2.p, c->rf_src2.p, c->rf_ctr.p + 1, c->stream));
         uint32_t K = 0;
         HIPCHK(hipMemcpyAsync(&K, c->rf_ctr.p + 1, sizeof K, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -2161,6 +2172,7 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
             (rc = ensure(c, c->hist, radix_hist_entries(sortn))) ||
             (rc = ensure(c, c->scan_tmp, scan_tmp_entries(radix_hist_entries(sortn)) + scan_tmp_entries(sortn) + 64)) ||
             (rc = ensure(c, c->rf_ccr, 3 * (size_t)K)) || (rc = ensure(c, c->rf_status, K)) ||
+            (rc = ensure(c, c->rf_srcr, K)) ||
             (rc = ensure(c, c->rf_flags, (size_t)K + 1)) || (rc = ensure(c, c->rf_pos, (size_t)K + 1)))
             return rc;
         const uint64_t off[2] = {0, K};
@@ -2186,8 +2198,8 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         unsigned long long *vkeys = nullptr;
         uint32_t *vidx = sort_into(c, c->rf_k0.p, c->rf_v0.p, c->rf_k1.p, c->rf_v1.p, (uint32_t)nv, gbits, &vkeys, &he);
         HIPCHK(he);
-        HIPCHK(launch_near_vertex(lo, cell, G, c->V.p, vkeys, vidx, (uint32_t)nv, c->rf_cc2.p, c->rf_pos.p, K, lim,
-                                  c->rf_ccr.p, c->rf_status.p, c->stream));
+        HIPCHK(launch_near_vertex(lo, cell, G, c->V.p, vkeys, vidx, (uint32_t)nv, c->rf_cc2.p, c->rf_src2.p,
+                                  c->rf_pos.p, K, lim, c->rf_ccr.p, c->rf_srcr.p, c->rf_status.p, c->stream));
         // 4. the greedy filter among the candidates, in rounds over the candidate grid
         HIPCHK(launch_cell_keys(lo, cell, G, c->rf_ccr.p, nullptr, K, c->rf_k0.p, c->rf_v0.p, c->stream));
         unsigned long long *ckeys = nullptr;
@@ -2204,7 +2216,8 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
             if (und == 0) break;
         }
         // 5. the kept points in filter order, appended
-        HIPCHK(launch_kept(c->rf_status.p, K, c->rf_flags.p, nullptr, nullptr, nullptr, 0, c->stream));
+        HIPCHK(launch_kept(c->rf_status.p, K, c->rf_flags.p, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                           c->stream));
         HIPCHK(exclusive_scan_u32(c->rf_flags.p, c->rf_pos.p, K, c->scan_tmp.p, c->rf_pos.p + K, c->stream));
         uint32_t nk = 0;
         HIPCHK(hipMemcpyAsync(&nk, c->rf_pos.p + K, sizeof nk, hipMemcpyDeviceToHost, c->stream));
@@ -2215,9 +2228,15 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         }
         if (num_steps) *num_steps = step + 1;
         if (nk == 0) break;
-        if ((rc = ensure(c, c->rf_pts, 3 * (size_t)nk))) return rc;
-        HIPCHK(launch_kept(c->rf_status.p, K, nullptr, c->rf_pos.p, c->rf_ccr.p, c->rf_pts.p, 1, c->stream));
-        if ((rc = dt_insert_points(c, c->rf_pts.p, nk))) return rc;
+        if ((rc = ensure(c, c->rf_pts, 3 * (size_t)nk)) || (rc = ensure(c, c->rf_hint, nk))) return rc;
+        HIPCHK(launch_kept(c->rf_status.p, K, nullptr, c->rf_pos.p, c->rf_ccr.p, c->rf_srcr.p, c->rf_pts.p,
+                           c->rf_hint.p, 1, c->stream));
+        // inserted as one call's cloud; each point's walk starts at a vertex of the tetrahedron
+        // whose circumcentre it is (the mesher inserts a circumcentre from its tetrahedron)
+        if (c->nv + nk >= (1ull << 31) || c->npoints + nk >= (1ull << 32) - 2 || nk >= (1ull << 30))
+            return fail(c, DT_E_CAPACITY, "too many points (limits: 2^30 per call, 2^31 in all)");
+        c->h_off = {0, nk};
+        if ((rc = insert_clouds(c, c->rf_pts.p, nk, c->h_off, c->rf_hint.p))) return rc;
         total += nk;
         if (inserted) *inserted = total;
     }

@@ -480,9 +480,14 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
             t = code_slot(comp(T[t].n, 3));
             w = T[t].v;
         }
-        // Walk: lane j < 4 tests facet j
+        // Walk: lane j < 4 tests facet j.  The walk moves through a facet whose sign is
+        // negative; a facet the filter cannot decide is not crossed.  If the walk stops at a
+        // tetrahedron with such a facet (p within rounding of its plane), that tetrahedron
+        // still starts the cavity when the filter puts p strictly inside its circumsphere
+        // (the cavity is connected, any of its tetrahedra starts it); else the FULL kernel
+        // runs the attempt.
         int entry = -1;
-        bool in_ghost = false;
+        bool in_ghost = false, unsure = false;
         const int jl = (int)(gl & 3u);
         unsigned ws = 0;  // steps of this walk
         for (;;) {
@@ -491,12 +496,11 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
             int o = 1;
             if (gl < 4 && jl != entry)
                 o = cav_orient<FULL>(jl == 0 ? P : q0, jl == 1 ? P : q1, jl == 2 ? P : q2, jl == 3 ? P : q3, st);
-            if (!FULL && (__ballot(o == UNDECIDED) & gmask)) {
-                status = ST_FULL;
+            const unsigned bits = (unsigned)((__ballot(o < 0) & gmask) >> gbase) & 0xFu;
+            if (!bits) {
+                unsure = !FULL && (__ballot(o == UNDECIDED) & gmask);
                 break;
             }
-            const unsigned bits = (unsigned)((__ballot(o < 0) & gmask) >> gbase) & 0xFu;
-            if (!bits) break;
             const unsigned rot = (p + ws) & 3u;
             const unsigned rb = ((bits >> rot) | (bits << (4u - rot))) & 0xFu;
             const int moved = (int)(((unsigned)__ffs(rb) - 1u + rot) & 3u);
@@ -529,6 +533,10 @@ __global__ __launch_bounds__(256) void k_cavity_g(RoundArgs a) {
                 same = v.x == P.x && v.y == P.y && v.z == P.z;
             }
             if (__ballot(same) & gmask) status = ST_DUP;
+        }
+        if (!FULL && unsure && status == ST_NONE && !in_ghost) {
+            const int si = gl == 0 ? finite_inside<FULL>(a.V, w, P, pv.idx, st) : -1;
+            if (__ballot(si != -1) & gmask) status = ST_FULL;
         }
         uint32_t ncav = 0, nbnd = 0;
         const uint32_t capL = GLOBAL ? a.capC : min(a.capC, CAPL), capF = a.capF;

@@ -219,6 +219,8 @@ hipError_t launch_level_hist(const unsigned long long *keys, uint64_t n, int shi
 hipError_t launch_levels(const uint32_t *src, const Vert *V, uint64_t n, uint64_t base, const uint64_t *off,
                          const Cloud *clouds, uint64_t salt, unsigned long long *keys, uint32_t *vals,
                          uint8_t *lev_out, hipStream_t s);
+hipError_t launch_hint_anchor(const Vert *V, uint64_t base, uint64_t n, uint64_t idx_offset, const uint32_t *hint,
+                              uint32_t *anchor, hipStream_t s);
 hipError_t launch_anchor(const uint32_t *lord, const uint32_t *start, int L, const Vert *V, uint64_t base,
                          uint64_t n, uint32_t *anchor, hipStream_t s);
 hipError_t launch_dedupe(const Vert *V, uint64_t base, uint64_t n, unsigned long long *table,
@@ -298,21 +300,23 @@ hipError_t launch_points_out(const Vert *V, uint32_t nv, double *xyz, hipStream_
 hipError_t launch_hull_facets(const void *T, bool wide, uint32_t count, uint4 *facets, uint32_t *nfacets,
                               hipStream_t s);
 hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count, double grow, double *cc, uint4 *q,
-                         uint32_t cap, uint32_t *ncand, hipStream_t s);
-hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const double *cc, const uint4 *q, uint32_t k,
-                         double *cc2, uint4 *q2, uint32_t *nin, hipStream_t s);
+                         uint32_t *src, uint32_t cap, uint32_t *ncand, hipStream_t s);
+hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const double *cc, const uint4 *q,
+                         const uint32_t *src, uint32_t k, double *cc2, uint4 *q2, uint32_t *src2, uint32_t *nin,
+                         hipStream_t s);
 hipError_t launch_order_keys(const uint4 *q, const unsigned long long *moore, const uint32_t *perm, uint32_t k,
                              int which, int bits, unsigned long long *keys, uint32_t *vals, hipStream_t s);
 hipError_t launch_cell_keys(const double *lo, double cell, uint64_t g, const double *xyz, const Vert *V, uint32_t n,
                             unsigned long long *keys, uint32_t *vals, hipStream_t s);
 hipError_t launch_near_vertex(const double *lo, double cell, uint64_t g, const Vert *V, const unsigned long long *vkeys,
-                              const uint32_t *vidx, uint32_t nv, const double *cc, const uint32_t *perm, uint32_t k,
-                              double lim, double *ccr, uint8_t *status, hipStream_t s);
+                              const uint32_t *vidx, uint32_t nv, const double *cc, const uint32_t *src,
+                              const uint32_t *perm, uint32_t k, double lim, double *ccr, uint32_t *srcr,
+                              uint8_t *status, hipStream_t s);
 hipError_t launch_filter_round(const double *lo, double cell, uint64_t g, const unsigned long long *ckeys,
                                const uint32_t *crank, uint32_t k, const double *ccr, double lim, uint8_t *status,
                                uint32_t *undecided, hipStream_t s);
 hipError_t launch_kept(const uint8_t *status, uint32_t k, uint32_t *flags, const uint32_t *pos, const double *ccr,
-                       double *out, int phase, hipStream_t s);
+                       const uint32_t *srcr, double *out, uint32_t *hint, int phase, hipStream_t s);
 hipError_t launch_vert_box(const Vert *V, uint32_t n, uint32_t m, double *partial, uint32_t nblocks, Cloud *cl,
                            hipStream_t s);
 

@@ -148,8 +148,240 @@ __device__ inline int ei_load(const double *v, int cnt, uint32_t (*X)[12], int w
     return emax - emin + 54;
 }
 
+// ------------------------------------------------------------------ exact integers, fixed width
+// The same integer arithmetic with widths fixed at compile time, for inputs whose exponent
+// spread is small (every coordinate an integer of at most SMALL_BITS bits after the common
+// scaling): with every loop unrolled the limbs stay in registers.  The general routines
+// above index their limbs with run-time widths, which puts them in per-lane scratch memory,
+// where each limb operation waits on a memory round trip.
+
+constexpr int SMALL_BITS = 80;
+
+template <int WA>
+__device__ __forceinline__ uint32_t fx_at(const uint32_t (&a)[WA], int k) {
+    return k < WA ? a[k] : (uint32_t)((int32_t)a[WA - 1] >> 31);
+}
+
+// r = a - b or a + b modulo 2^(32 W); r may alias a
+template <int W, int WA, int WB>
+__device__ __forceinline__ void fx_addsub(uint32_t (&r)[W], const uint32_t (&a)[WA], const uint32_t (&b)[WB],
+                                          bool sub) {
+    unsigned long long c = sub ? 1ull : 0ull;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const uint32_t bi = sub ? ~fx_at(b, i) : fx_at(b, i);
+        const unsigned long long t = (unsigned long long)fx_at(a, i) + bi + c;
+        r[i] = (uint32_t)t;
+        c = t >> 32;
+    }
+}
+
+// r = a * b modulo 2^(32 W); r must not alias a or b
+template <int W, int WA, int WB>
+__device__ __forceinline__ void fx_mul(uint32_t (&r)[W], const uint32_t (&a)[WA], const uint32_t (&b)[WB]) {
+#pragma unroll
+    for (int i = 0; i < W; ++i) r[i] = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const uint32_t ai = fx_at(a, i);
+        unsigned long long c = 0;
+#pragma unroll
+        for (int j = 0; i + j < W; ++j) {
+            const unsigned long long t = (unsigned long long)ai * fx_at(b, j) + r[i + j] + c;
+            r[i + j] = (uint32_t)t;
+            c = t >> 32;
+        }
+    }
+}
+
+template <int W>
+__device__ __forceinline__ int fx_sign(const uint32_t (&a)[W]) {
+    if (a[W - 1] >> 31) return -1;
+    uint32_t any = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) any |= a[i];
+    return any ? 1 : 0;
+}
+
+// the N coordinates as three-limb integers m 2^(e - emin); false when the spread needs more
+// than SMALL_BITS bits
+template <int N>
+__device__ __forceinline__ bool fx_load(const double (&v)[N], uint32_t (&X)[N][3]) {
+    Dyadic d[N];
+    int emin = 1 << 20, emax = -(1 << 20);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        d[i] = split_dyadic(v[i]);
+        if (d[i].m != 0) {
+            emin = min(emin, d[i].e);
+            emax = max(emax, d[i].e);
+        }
+    }
+    if (emax < emin) emin = emax = 0;
+    if (emax - emin + 54 > SMALL_BITS) return false;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const unsigned long long mag = d[i].m < 0 ? (unsigned long long)(-d[i].m) : (unsigned long long)d[i].m;
+        const int sh = d[i].m ? d[i].e - emin : 0;  // 0 .. SMALL_BITS - 54
+        const unsigned long long lo = mag << sh;
+        const uint32_t hi = sh ? (uint32_t)(mag >> (64 - sh)) : 0u;
+        uint32_t r[3] = {(uint32_t)lo, (uint32_t)(lo >> 32), hi};
+        if (d[i].m < 0) {
+            unsigned long long c = 1;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const unsigned long long t = (unsigned long long)(uint32_t)~r[k] + c;
+                r[k] = (uint32_t)t;
+                c = t >> 32;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) X[i][k] = r[k];
+    }
+    return true;
+}
+
+// exact sign of orient3d for coordinates within SMALL_BITS (false: not within)
+__device__ __forceinline__ bool orient3d_small(P3 a, P3 b, P3 c, P3 d, int *sign) {
+    const double v[12] = {a.x, a.y, a.z, b.x, b.y, b.z, c.x, c.y, c.z, d.x, d.y, d.z};
+    uint32_t X[12][3];
+    if (!fx_load(v, X)) return false;
+    // widths for SMALL_BITS = 80: differences 4 limbs, 2x2 minors 7, 3x3 determinant 9
+    uint32_t D[9][4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fx_addsub(D[3 * r + k], X[3 * (r + 1) + k], X[k], true);
+    uint32_t acc[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) acc[i] = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int i = q, j = (q + 1) % 3, k = (q + 2) % 3;
+        uint32_t t1[7], t2[7], m[7], t3[9];
+        fx_mul(t1, D[3 + j], D[6 + k]);
+        fx_mul(t2, D[3 + k], D[6 + j]);
+        fx_addsub(m, t1, t2, true);
+        fx_mul(t3, D[i], m);
+        fx_addsub(acc, acc, t3, false);
+    }
+    *sign = fx_sign(acc);
+    return true;
+}
+
+// the common exponent of the N values (the smallest dyadic exponent of a non-zero one); false
+// when the spread needs more than SMALL_BITS bits
+template <int N>
+__device__ __forceinline__ bool fx_range(const double (&v)[N], int *emin_out) {
+    int emin = 1 << 20, emax = -(1 << 20);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int ex = (int)(((unsigned long long)__double_as_longlong(v[i]) >> 52) & 0x7FF);
+        if (ex != 0) {
+            emin = min(emin, ex - 1075);
+            emax = max(emax, ex - 1075);
+        }
+    }
+    if (emax < emin) emin = emax = 0;
+    *emin_out = emin;
+    return emax - emin + 54 <= SMALL_BITS;
+}
+
+// x as a three-limb integer scaled by 2^-emin (the spread checked by fx_range)
+__device__ __forceinline__ void fx_int(double x, int emin, uint32_t (&r)[3]) {
+    const Dyadic d = split_dyadic(x);
+    const unsigned long long mag = d.m < 0 ? (unsigned long long)(-d.m) : (unsigned long long)d.m;
+    const int sh = d.m ? d.e - emin : 0;
+    const unsigned long long lo = mag << sh;
+    r[0] = (uint32_t)lo;
+    r[1] = (uint32_t)(lo >> 32);
+    r[2] = sh ? (uint32_t)(mag >> (64 - sh)) : 0u;
+    if (d.m < 0) {
+        unsigned long long c = 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const unsigned long long t = (unsigned long long)(uint32_t)~r[k] + c;
+            r[k] = (uint32_t)t;
+            c = t >> 32;
+        }
+    }
+}
+
+// exact sign of the lifted determinant (translated by e) for coordinates within SMALL_BITS.
+// With rows p - e (p = a, b, c, d), the six 2x2 minors of their x and y columns serve all four
+// 3x3 determinants, as in the fp64 filter.
+__device__ __forceinline__ bool insphere_small(P3 a, P3 b, P3 c, P3 d, P3 e, int *sign) {
+    const double v[15] = {a.x, a.y, a.z, b.x, b.y, b.z, c.x, c.y, c.z, d.x, d.y, d.z, e.x, e.y, e.z};
+    int emin;
+    if (!fx_range(v, &emin)) return false;
+    // widths for SMALL_BITS = 80: differences 4 limbs, minors and lifts 7, 3x3 determinants 9,
+    // the final sum 14
+    uint32_t Dx[4][4], Dy[4][4], Dz[4][4];
+    {
+        uint32_t E[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fx_int(v[12 + k], emin, E[k]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            uint32_t X[3];
+            fx_int(v[3 * r], emin, X);
+            fx_addsub(Dx[r], X, E[0], true);
+            fx_int(v[3 * r + 1], emin, X);
+            fx_addsub(Dy[r], X, E[1], true);
+            fx_int(v[3 * r + 2], emin, X);
+            fx_addsub(Dz[r], X, E[2], true);
+        }
+    }
+    uint32_t L[4][7];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        uint32_t t[7];
+        fx_mul(L[r], Dx[r], Dx[r]);
+        fx_mul(t, Dy[r], Dy[r]);
+        fx_addsub(L[r], L[r], t, false);
+        fx_mul(t, Dz[r], Dz[r]);
+        fx_addsub(L[r], L[r], t, false);
+    }
+    // minors m(p, q) = p_x q_y - q_x p_y for the pairs 01 02 03 12 13 23
+    uint32_t M[6][7];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int p = k < 3 ? 0 : (k < 5 ? 1 : 2);
+        const int q = k < 3 ? k + 1 : (k < 5 ? k - 1 : 3);
+        uint32_t t1[7], t2[7];
+        fx_mul(t1, Dx[p], Dy[q]);
+        fx_mul(t2, Dx[q], Dy[p]);
+        fx_addsub(M[k], t1, t2, true);
+    }
+    // det = l_d det3(a,b,c) - l_c det3(a,b,d) + l_b det3(a,c,d) - l_a det3(b,c,d), with
+    // det3(p,q,s) = p_z m(q,s) - q_z m(p,s) + s_z m(p,q)
+    uint32_t acc[14];
+#pragma unroll
+    for (int i = 0; i < 14; ++i) acc[i] = 0;
+#pragma unroll
+    for (int row = 0; row < 4; ++row) {
+        const int p = row == 0 ? 1 : 0, q = row <= 1 ? 2 : 1, s = row <= 2 ? 3 : 2;
+        // pair indices of (q, s), (p, s), (p, q)
+        const int mqs = q == 1 ? 3 + (s - 2) : (q == 2 ? 5 : 0), mps = p == 0 ? s - 1 : 3 + (s - 2),
+                  mpq = p == 0 ? q - 1 : 3;
+        uint32_t det3[9], t[9];
+        fx_mul(det3, Dz[p], M[mqs]);
+        fx_mul(t, Dz[q], M[mps]);
+        fx_addsub(det3, det3, t, true);
+        fx_mul(t, Dz[s], M[mpq]);
+        fx_addsub(det3, det3, t, false);
+        uint32_t prod[14];
+        fx_mul(prod, L[row], det3);
+        fx_addsub(acc, acc, prod, row == 0 || row == 2);
+    }
+    *sign = fx_sign(acc);
+    return true;
+}
+
 // exact sign of orient3d(a,b,c,d)
 __device__ __noinline__ int orient3d_exact(P3 a, P3 b, P3 c, P3 d) {
+    int sign;
+    if (orient3d_small(a, b, c, d, &sign)) return sign;
     double v[12] = {a.x, a.y, a.z, b.x, b.y, b.z, c.x, c.y, c.z, d.x, d.y, d.z};
     uint32_t X[12][12];
     // coordinates: bits <= 53 + 239 + 1 (sign) -> at most 10 limbs
@@ -180,6 +412,8 @@ __device__ __noinline__ int orient3d_exact(P3 a, P3 b, P3 c, P3 d) {
 
 // exact sign of the lifted determinant, translated by e
 __device__ __noinline__ int insphere_exact(P3 a, P3 b, P3 c, P3 d, P3 e) {
+    int sign;
+    if (insphere_small(a, b, c, d, e, &sign)) return sign;
     double v[15] = {a.x, a.y, a.z, b.x, b.y, b.z, c.x, c.y, c.z, d.x, d.y, d.z, e.x, e.y, e.z};
     uint32_t X[15][12];
     int bits = ei_load(v, 15, X, 10);

@@ -75,7 +75,8 @@ __device__ __forceinline__ void circumcentre(const double p[4][3], double *cc, d
 // live finite tetrahedra with r^2 > grow: candidate (circumcentre, sorted vertex input indices)
 template <class R>
 __global__ void k_circum(const R *__restrict__ T, const Vert *__restrict__ V, uint32_t count, double grow,
-                         double *__restrict__ cc, uint4 *__restrict__ q, uint32_t cap, uint32_t *__restrict__ ncand) {
+                         double *__restrict__ cc, uint4 *__restrict__ q, uint32_t *__restrict__ src, uint32_t cap,
+                         uint32_t *__restrict__ ncand) {
     const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     if (t >= count) return;
     const uint4 w = T[t].v;
@@ -104,13 +105,17 @@ __global__ void k_circum(const R *__restrict__ T, const Vert *__restrict__ V, ui
     cc[3 * (size_t)i + 1] = c[1];
     cc[3 * (size_t)i + 2] = c[2];
     q[i] = make_uint4(id[0], id[1], id[2], id[3]);
+    // a vertex of the tetrahedron: within its circumradius of the candidate, where the
+    // candidate's insertion starts its walk
+    src[i] = rec[0];
 }
 
 // strictly inside the hull: orient3d(a, b, c, x) < 0 for every hull facet; the inside ones
 // are appended (compacted) to cc2 / q2
 __global__ void k_inside(const Vert *__restrict__ V, const uint4 *__restrict__ facets, uint32_t nf,
-                         const double *__restrict__ cc, const uint4 *__restrict__ q, uint32_t k,
-                         double *__restrict__ cc2, uint4 *__restrict__ q2, uint32_t *__restrict__ nin) {
+                         const double *__restrict__ cc, const uint4 *__restrict__ q, const uint32_t *__restrict__ src,
+                         uint32_t k, double *__restrict__ cc2, uint4 *__restrict__ q2, uint32_t *__restrict__ src2,
+                         uint32_t *__restrict__ nin) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= k) return;
     const P3 x = {cc[3 * (size_t)i], cc[3 * (size_t)i + 1], cc[3 * (size_t)i + 2]};
@@ -127,6 +132,7 @@ __global__ void k_inside(const Vert *__restrict__ V, const uint4 *__restrict__ f
     cc2[3 * (size_t)j + 1] = x.y;
     cc2[3 * (size_t)j + 2] = x.z;
     q2[j] = q[i];
+    src2[j] = src[i];
 }
 
 // sort keys in the order of perm: (q.z, q.w) (which = 0), (q.x, q.y) (which = 1), or the
@@ -198,15 +204,18 @@ __device__ __forceinline__ double sq_dist(double ax, double ay, double az, doubl
     return dx * dx + dy * dy + dz * dz;
 }
 
-// The candidates in filter order: rank r is candidate perm[r]; ccr (rank order) gets its
-// point; status 0 (undecided) unless a vertex is closer than the limit (2: dropped).
+// The candidates in filter order: rank r is candidate perm[r]; ccr and srcr (rank order) get
+// its point and its tetrahedron's vertex record; status 0 (undecided) unless a vertex is
+// closer than the limit (2: dropped).
 __global__ void k_near_vertex(Grid G, const Vert *__restrict__ V, const unsigned long long *__restrict__ vkeys,
                               const uint32_t *__restrict__ vidx, uint32_t nv, const double *__restrict__ cc,
-                              const uint32_t *__restrict__ perm, uint32_t k, double lim, double *__restrict__ ccr,
+                              const uint32_t *__restrict__ src, const uint32_t *__restrict__ perm, uint32_t k,
+                              double lim, double *__restrict__ ccr, uint32_t *__restrict__ srcr,
                               uint8_t *__restrict__ status) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= k) return;
     const uint32_t i = perm[r];
+    srcr[r] = src[i];
     const double x = cc[3 * (size_t)i], y = cc[3 * (size_t)i + 1], z = cc[3 * (size_t)i + 2];
     ccr[3 * (size_t)r] = x;
     ccr[3 * (size_t)r + 1] = y;
@@ -276,11 +285,13 @@ __global__ void k_kept_flags(const uint8_t *__restrict__ status, uint32_t k, uin
 }
 
 __global__ void k_kept_points(const uint8_t *__restrict__ status, const uint32_t *__restrict__ pos, uint32_t k,
-                              const double *__restrict__ ccr, double *__restrict__ out) {
+                              const double *__restrict__ ccr, const uint32_t *__restrict__ srcr,
+                              double *__restrict__ out, uint32_t *__restrict__ hint) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= k || status[r] != 1) return;
     const uint32_t j = pos[r];
     for (int c = 0; c < 3; ++c) out[3 * (size_t)j + c] = ccr[3 * (size_t)r + c];
+    hint[j] = srcr[r];
 }
 
 // bounding box of the vertex records [0, n): per-block partial boxes, then one thread folds
@@ -349,17 +360,18 @@ hipError_t launch_hull_facets(const void *T, bool wide, uint32_t count, uint4 *f
 }
 
 hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count, double grow, double *cc, uint4 *q,
-                         uint32_t cap, uint32_t *ncand, hipStream_t s) {
+                         uint32_t *src, uint32_t cap, uint32_t *ncand, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    if (wide) k_circum<<<blocks256(count), 256, 0, s>>>((const TetW *)T, V, count, grow, cc, q, cap, ncand);
-    else k_circum<<<blocks256(count), 256, 0, s>>>((const Tet *)T, V, count, grow, cc, q, cap, ncand);
+    if (wide) k_circum<<<blocks256(count), 256, 0, s>>>((const TetW *)T, V, count, grow, cc, q, src, cap, ncand);
+    else k_circum<<<blocks256(count), 256, 0, s>>>((const Tet *)T, V, count, grow, cc, q, src, cap, ncand);
     return hipGetLastError();
 }
 
-hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const double *cc, const uint4 *q, uint32_t k,
-                         double *cc2, uint4 *q2, uint32_t *nin, hipStream_t s) {
+hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const double *cc, const uint4 *q,
+                         const uint32_t *src, uint32_t k, double *cc2, uint4 *q2, uint32_t *src2, uint32_t *nin,
+                         hipStream_t s) {
     if (k == 0) return hipSuccess;
-    k_inside<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, k, cc2, q2, nin);
+    k_inside<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, src, k, cc2, q2, src2, nin);
     return hipGetLastError();
 }
 
@@ -380,11 +392,12 @@ hipError_t launch_cell_keys(const double *lo, double cell, uint64_t g, const dou
 }
 
 hipError_t launch_near_vertex(const double *lo, double cell, uint64_t g, const Vert *V, const unsigned long long *vkeys,
-                              const uint32_t *vidx, uint32_t nv, const double *cc, const uint32_t *perm, uint32_t k,
-                              double lim, double *ccr, uint8_t *status, hipStream_t s) {
+                              const uint32_t *vidx, uint32_t nv, const double *cc, const uint32_t *src,
+                              const uint32_t *perm, uint32_t k, double lim, double *ccr, uint32_t *srcr,
+                              uint8_t *status, hipStream_t s) {
     if (k == 0) return hipSuccess;
     const Grid G = {{lo[0], lo[1], lo[2]}, cell, g};
-    k_near_vertex<<<blocks256(k), 256, 0, s>>>(G, V, vkeys, vidx, nv, cc, perm, k, lim, ccr, status);
+    k_near_vertex<<<blocks256(k), 256, 0, s>>>(G, V, vkeys, vidx, nv, cc, src, perm, k, lim, ccr, srcr, status);
     return hipGetLastError();
 }
 
@@ -398,10 +411,10 @@ hipError_t launch_filter_round(const double *lo, double cell, uint64_t g, const 
 }
 
 hipError_t launch_kept(const uint8_t *status, uint32_t k, uint32_t *flags, const uint32_t *pos, const double *ccr,
-                       double *out, int phase, hipStream_t s) {
+                       const uint32_t *srcr, double *out, uint32_t *hint, int phase, hipStream_t s) {
     if (k == 0) return hipSuccess;
     if (phase == 0) k_kept_flags<<<blocks256(k), 256, 0, s>>>(status, k, flags);
-    else k_kept_points<<<blocks256(k), 256, 0, s>>>(status, pos, k, ccr, out);
+    else k_kept_points<<<blocks256(k), 256, 0, s>>>(status, pos, k, ccr, srcr, out, hint);
     return hipGetLastError();
 }
 

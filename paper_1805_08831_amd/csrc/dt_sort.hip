@@ -285,6 +285,23 @@ hipError_t launch_anchor(const uint32_t *lord, const uint32_t *start, int L, con
     return hipGetLastError();
 }
 
+// Walk anchors given by the caller: input point i of the call (record base + j with input
+// index idx_offset + i) starts its walk near record hint[i], an inserted vertex.
+__global__ void k_hint_anchor(const Vert *__restrict__ V, uint64_t base, uint64_t n, uint64_t idx_offset,
+                              const uint32_t *__restrict__ hint, uint32_t *__restrict__ anchor) {
+    const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint64_t i = (uint32_t)V[base + j].idx - idx_offset;
+    anchor[j] = i < n ? hint[i] : 0xFFFFFFFFu;
+}
+
+hipError_t launch_hint_anchor(const Vert *V, uint64_t base, uint64_t n, uint64_t idx_offset, const uint32_t *hint,
+                              uint32_t *anchor, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_hint_anchor<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V, base, n, idx_offset, hint, anchor);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ scan
 
 constexpr int SCAN_TILE = 1024;  // 256 threads x 4 items

@@ -14,7 +14,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 CASES = [("uniform", 600, 7, 0.08), ("uniform", 2000, 11, 0.05), ("clusters", 800, 8, 0.03),
-         ("uniform", 20000, 5, 0.03)]
+         ("uniform", 20000, 5, 0.03),
+         # deep refinement: h n^(1/3) about 0.4, as in the benchmark workload (about six times
+         # the input points)
+         ("uniform", 10000, 13, 0.0185)]
 
 
 def run_case(kind, n, seed, h):

@@ -49,3 +49,32 @@ def test_refine_matches_the_oracle(dtlib, oracle_mod, case):
     assert hashlib.sha256(canon.tobytes()).hexdigest() == ht
     if npts < 5000:
         check_invariants(pts, t.astype(np.int64), nb, oracle_mod, expect_vertices=np.arange(npts))
+
+
+def test_refine_benchmark_size(dtlib, oracle_mod):
+    """The benchmark's refinement workload (2.5e5 uniform points, seed 4007, h = 0.0064; about
+    1.5e6 final points), checked by what holds at any size: the final tetrahedralization is
+    the oracle's Delaunay tetrahedralization of the final point set, every added point lies
+    at least 0.7 h from every other vertex, the passes' kept counts sum to the points added,
+    and the last pass keeps none."""
+    from scipy.spatial import cKDTree
+    n, h = 250_000, 0.0064
+    say(f"refine uniform n={n} seed=4007 h={h}")
+    xyz = uniform_points(n, 4007)
+    with dtlib.Triangulation() as tri:
+        tri.insert(xyz)
+        added, steps = dtlib.dt_refine(tri.ctx, h)
+        pts = dtlib.dt_get_points(tri.ctx)
+        t, _ = tri.tets()
+    say(f"steps {steps}, {added} points added, {len(t)} tetrahedra")
+    assert added > 4 * n and len(pts) == n + added
+    assert np.array_equal(pts[:n], xyz)
+    assert sum(k for _, k in steps) == added and steps[-1][1] == 0
+    d, _ = cKDTree(pts).query(pts[n:], k=2)
+    assert d[:, 1].min() >= 0.7 * h * (1 - 1e-12)
+    rc, ot, _, _ = oracle_mod.delaunay(pts, order="brio", seed=0)
+    assert rc == 0
+    assert len(ot) == len(t)
+    got = oracle_mod.canonical(t.astype(np.int64))
+    want = oracle_mod.canonical(ot.astype(np.int64))
+    assert np.array_equal(got, want)
