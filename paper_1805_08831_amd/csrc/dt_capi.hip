@@ -215,7 +215,7 @@ struct dt_ctx {
     DevBuf<unsigned long long> rf_moore, rf_k0, rf_k1;
     DevBuf<uint32_t> rf_v0, rf_v1, rf_ctr, rf_flags, rf_pos;
     DevBuf<uint32_t> rf_src, rf_src2, rf_srcr, rf_hint;  // candidates' tetrahedron vertex records
-    DevBuf<uint8_t> rf_status;
+    DevBuf<uint8_t> rf_status, rf_flag;
     DevBuf<Cloud> rf_cloud;
     DevBuf<uint64_t> rf_off;
     unsigned char *arena = nullptr;
@@ -1844,7 +1844,7 @@ int dt_destroy(dt_ctx *c) {
     f(c->rf_q.p); f(c->rf_q2.p); f(c->rf_facets.p); f(c->rf_moore.p); f(c->rf_k0.p); f(c->rf_k1.p);
     f(c->rf_v0.p); f(c->rf_v1.p); f(c->rf_ctr.p); f(c->rf_flags.p); f(c->rf_pos.p);
     f(c->rf_src.p); f(c->rf_src2.p); f(c->rf_srcr.p); f(c->rf_hint.p);
-    f(c->rf_status.p); f(c->rf_cloud.p); f(c->rf_off.p);
+    f(c->rf_status.p); f(c->rf_flag.p); f(c->rf_cloud.p); f(c->rf_off.p);
     for (int k = 0; k < 3; ++k) {
         for (int j = 0; j < 3; ++j)
             if (c->ev[k][j]) hipEventDestroy(c->ev[k][j]);
@@ -2147,7 +2147,8 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         // 1. candidates: circumcentres of the tetrahedra larger than 1.4 h, strictly inside
         if ((rc = ensure(c, c->rf_cc, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q, count)) ||
             (rc = ensure(c, c->rf_cc2, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q2, count)) ||
-            (rc = ensure(c, c->rf_src, count)) || (rc = ensure(c, c->rf_src2, count)))
+            (rc = ensure(c, c->rf_src, count)) || (rc = ensure(c, c->rf_src2, count)) ||
+            (rc = ensure(c, c->rf_flag, count)))
             return rc;
         HIPCHK(hipMemsetAsync(c->rf_ctr.p, 0, 4 * sizeof(uint32_t), c->stream));
         HIPCHK(launch_circum(c->T, c->wide, c->V.p, count, grow, c->rf_cc.p, c->rf_q.p, c->rf_src.p, count,
@@ -2155,8 +2156,8 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         uint32_t k0 = 0;
         HIPCHK(hipMemcpyAsync(&k0, c->rf_ctr.p, sizeof k0, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(launch_inside(c->V.p, c->rf_facets.p, nf, c->rf_cc.p, c->rf_q.p, c->rf_src.p, k0, c->rf_cc2.p,
-                             c->rf_q2.p, c->rf_src2.p, c->rf_ctr.p + 1, c->stream));
+        HIPCHK(launch_inside(c->V.p, c->rf_facets.p, nf, c->rf_cc.p, c->rf_q.p, c->rf_src.p, k0, c->rf_flag.p,
+                             c->rf_cc2.p, c->rf_q2.p, c->rf_src2.p, c->rf_ctr.p + 1, c->stream));
         uint32_t K = 0;
         HIPCHK(hipMemcpyAsync(&K, c->rf_ctr.p + 1, sizeof K, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));

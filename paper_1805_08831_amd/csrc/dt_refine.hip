@@ -38,6 +38,19 @@ __global__ void k_hull_facets(const R *__restrict__ T, uint32_t count, uint4 *__
     facets[atomicAdd(nfacets, 1u)] = make_uint4(w.x, w.y, w.z, 0u);
 }
 
+// slot of this lane in a list appended to by the lanes with `want` set: one atomic per
+// wavefront (every lane of the wavefront calls it)
+__device__ __forceinline__ uint32_t wave_append(bool want, uint32_t *count) {
+    const unsigned long long m = __ballot(want);
+    if (!m) return 0u;
+    const uint32_t lane = threadIdx.x & 63u;
+    const int first = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if ((int)lane == first) base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = __shfl(base, first);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 __device__ __forceinline__ double dot3(const double *x, const double *y) {
     return x[0] * y[0] + x[1] * y[1] + x[2] * y[2];
 }
@@ -78,29 +91,34 @@ __global__ void k_circum(const R *__restrict__ T, const Vert *__restrict__ V, ui
                          double *__restrict__ cc, uint4 *__restrict__ q, uint32_t *__restrict__ src, uint32_t cap,
                          uint32_t *__restrict__ ncand) {
     const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (t >= count) return;
-    const uint4 w = T[t].v;
-    if (w.x == DEAD || w.w == GHOST) return;
-    uint32_t rec[4] = {w.x, w.y, w.z, w.w}, id[4];
-    for (int k = 0; k < 4; ++k) id[k] = (uint32_t)V[rec[k]].idx;
-    // ascending input index (insertion sort of four)
-    for (int i = 1; i < 4; ++i)
-        for (int j = i; j > 0 && id[j - 1] > id[j]; --j) {
-            uint32_t x = id[j]; id[j] = id[j - 1]; id[j - 1] = x;
-            x = rec[j]; rec[j] = rec[j - 1]; rec[j - 1] = x;
+    uint4 w = make_uint4(DEAD, 0u, 0u, 0u);
+    if (t < count) w = T[t].v;
+    const bool live = w.x != DEAD && w.w != GHOST;
+    double c[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+    uint32_t rec[4] = {w.x, w.y, w.z, w.w}, id[4] = {0u, 0u, 0u, 0u};
+    if (live) {
+        // the four records, read once, in ascending input index (insertion sort of four)
+        double p[4][3];
+        for (int k = 0; k < 4; ++k) {
+            const Vert r = V[rec[k]];
+            id[k] = (uint32_t)r.idx;
+            p[k][0] = r.x;
+            p[k][1] = r.y;
+            p[k][2] = r.z;
         }
-    double p[4][3];
-    for (int k = 0; k < 4; ++k) {
-        const Vert r = V[rec[k]];
-        p[k][0] = r.x;
-        p[k][1] = r.y;
-        p[k][2] = r.z;
+        for (int i = 1; i < 4; ++i)
+            for (int j = i; j > 0 && id[j - 1] > id[j]; --j) {
+                uint32_t x = id[j]; id[j] = id[j - 1]; id[j - 1] = x;
+                x = rec[j]; rec[j] = rec[j - 1]; rec[j - 1] = x;
+                for (int k = 0; k < 3; ++k) {
+                    const double y = p[j][k]; p[j][k] = p[j - 1][k]; p[j - 1][k] = y;
+                }
+            }
+        circumcentre(p, c, &r2);
     }
-    double c[3], r2;
-    circumcentre(p, c, &r2);
-    if (!(r2 > grow)) return;
-    const uint32_t i = atomicAdd(ncand, 1u);
-    if (i >= cap) return;  // the host sizes cap to the live tetrahedra
+    const bool want = live && r2 > grow;
+    const uint32_t i = wave_append(want, ncand);
+    if (!want || i >= cap) return;  // the host sizes cap to the live tetrahedra
     cc[3 * (size_t)i] = c[0];
     cc[3 * (size_t)i + 1] = c[1];
     cc[3 * (size_t)i + 2] = c[2];
@@ -110,29 +128,80 @@ __global__ void k_circum(const R *__restrict__ T, const Vert *__restrict__ V, ui
     src[i] = rec[0];
 }
 
-// strictly inside the hull: orient3d(a, b, c, x) < 0 for every hull facet; the inside ones
-// are appended (compacted) to cc2 / q2
-__global__ void k_inside(const Vert *__restrict__ V, const uint4 *__restrict__ facets, uint32_t nf,
-                         const double *__restrict__ cc, const uint4 *__restrict__ q, const uint32_t *__restrict__ src,
-                         uint32_t k, double *__restrict__ cc2, uint4 *__restrict__ q2, uint32_t *__restrict__ src2,
-                         uint32_t *__restrict__ nin) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= k) return;
-    const P3 x = {cc[3 * (size_t)i], cc[3 * (size_t)i + 1], cc[3 * (size_t)i + 2]};
-    PredStats st;
-    bool in = true;
-    for (uint32_t f = 0; f < nf && in; ++f) {
-        const uint4 fa = facets[f];
-        const Vert a = V[fa.x], b = V[fa.y], c = V[fa.z];
-        in = orient3d({a.x, a.y, a.z}, {b.x, b.y, b.z}, {c.x, c.y, c.z}, x, st) < 0;
-    }
+// strictly inside the hull: orient3d(a, b, c, x) < 0 for every hull facet.  The fp64 filter
+// decides almost every test; a candidate it leaves undecided on some facet gets flag 2 and
+// k_inside_exact settles it with the exact predicate (kept out of this kernel, whose
+// registers it would take).  Candidates found inside are appended (compacted) to cc2 / q2 /
+// src2.  The facets' corners pass through LDS in tiles shared by the block's candidates.
+constexpr uint32_t INSIDE_TILE = 512;  // facets per tile: 512 x 9 doubles = 36 KB
+
+__device__ __forceinline__ void inside_append(uint32_t i, bool in, P3 x, const uint4 *__restrict__ q,
+                                              const uint32_t *__restrict__ src, double *__restrict__ cc2,
+                                              uint4 *__restrict__ q2, uint32_t *__restrict__ src2,
+                                              uint32_t *__restrict__ nin) {
+    const uint32_t j = wave_append(in, nin);
     if (!in) return;
-    const uint32_t j = atomicAdd(nin, 1u);
     cc2[3 * (size_t)j] = x.x;
     cc2[3 * (size_t)j + 1] = x.y;
     cc2[3 * (size_t)j + 2] = x.z;
     q2[j] = q[i];
     src2[j] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_inside(const Vert *__restrict__ V, const uint4 *__restrict__ facets,
+                                                uint32_t nf, const double *__restrict__ cc,
+                                                const uint4 *__restrict__ q, const uint32_t *__restrict__ src,
+                                                uint32_t k, uint8_t *__restrict__ flag, double *__restrict__ cc2,
+                                                uint4 *__restrict__ q2, uint32_t *__restrict__ src2,
+                                                uint32_t *__restrict__ nin) {
+    __shared__ double s_f[INSIDE_TILE][9];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    P3 x = {0.0, 0.0, 0.0};
+    if (i < k) x = {cc[3 * (size_t)i], cc[3 * (size_t)i + 1], cc[3 * (size_t)i + 2]};
+    bool in = i < k, unsure = false;
+    for (uint32_t f0 = 0; f0 < nf; f0 += INSIDE_TILE) {
+        const uint32_t nt = min(INSIDE_TILE, nf - f0);
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < nt; j += blockDim.x) {
+            const uint4 fa = facets[f0 + j];
+            const Vert a = V[fa.x], b = V[fa.y], c = V[fa.z];
+            s_f[j][0] = a.x; s_f[j][1] = a.y; s_f[j][2] = a.z;
+            s_f[j][3] = b.x; s_f[j][4] = b.y; s_f[j][5] = b.z;
+            s_f[j][6] = c.x; s_f[j][7] = c.y; s_f[j][8] = c.z;
+        }
+        __syncthreads();
+        if (__syncthreads_or(in) == 0) break;
+        for (uint32_t j = 0; j < nt && in; ++j) {
+            const int o = orient3d_filter({s_f[j][0], s_f[j][1], s_f[j][2]}, {s_f[j][3], s_f[j][4], s_f[j][5]},
+                                          {s_f[j][6], s_f[j][7], s_f[j][8]}, x);
+            if (o == 2) unsure = true;
+            else in = o < 0;
+        }
+    }
+    if (i < k) flag[i] = in && unsure ? 2 : 0;
+    inside_append(i, in && !unsure, x, q, src, cc2, q2, src2, nin);
+}
+
+// the candidates k_inside left undecided, with exact orient3d
+__global__ __launch_bounds__(256) void k_inside_exact(const Vert *__restrict__ V, const uint4 *__restrict__ facets,
+                                                      uint32_t nf, const double *__restrict__ cc,
+                                                      const uint4 *__restrict__ q, const uint32_t *__restrict__ src,
+                                                      uint32_t k, const uint8_t *__restrict__ flag,
+                                                      double *__restrict__ cc2, uint4 *__restrict__ q2,
+                                                      uint32_t *__restrict__ src2, uint32_t *__restrict__ nin) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool in = i < k && flag[i] == 2;
+    P3 x = {0.0, 0.0, 0.0};
+    if (in) {
+        x = {cc[3 * (size_t)i], cc[3 * (size_t)i + 1], cc[3 * (size_t)i + 2]};
+        PredStats st;
+        for (uint32_t f = 0; f < nf && in; ++f) {
+            const uint4 fa = facets[f];
+            const Vert a = V[fa.x], b = V[fa.y], c = V[fa.z];
+            in = orient3d({a.x, a.y, a.z}, {b.x, b.y, b.z}, {c.x, c.y, c.z}, x, st) < 0;
+        }
+    }
+    inside_append(i, in, x, q, src, cc2, q2, src2, nin);
 }
 
 // sort keys in the order of perm: (q.z, q.w) (which = 0), (q.x, q.y) (which = 1), or the
@@ -368,10 +437,11 @@ hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count
 }
 
 hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const double *cc, const uint4 *q,
-                         const uint32_t *src, uint32_t k, double *cc2, uint4 *q2, uint32_t *src2, uint32_t *nin,
-                         hipStream_t s) {
+                         const uint32_t *src, uint32_t k, uint8_t *flag, double *cc2, uint4 *q2, uint32_t *src2,
+                         uint32_t *nin, hipStream_t s) {
     if (k == 0) return hipSuccess;
-    k_inside<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, src, k, cc2, q2, src2, nin);
+    k_inside<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, src, k, flag, cc2, q2, src2, nin);
+    k_inside_exact<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, src, k, flag, cc2, q2, src2, nin);
     return hipGetLastError();
 }
 
