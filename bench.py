@@ -209,6 +209,8 @@ def main():
                     help="pick lanes per insertion, round fraction and cavity cap on a 2e6-point sample first")
     ap.add_argument("--workload", choices=["uniform", "batch", "mix", "refine"], default="uniform")
     ap.add_argument("--no-learned", action="store_true", help="uniform: skip the learned-scheduler comparison")
+    ap.add_argument("--no-graph-compare", action="store_true",
+                    help="uniform: skip the comparison of graph-launched rounds with separate launches")
     ap.add_argument("--train-seeds", type=str, default="9001,9002", help="seeds of the plain runs logged for training")
     ap.add_argument("--train-samples", type=int, default=4_000_000, help="samples drawn from the logs")
     ap.add_argument("--train-n", type=int, default=0, help="uniform: points per training run (0: min(n, 1e7))")
@@ -286,6 +288,11 @@ def main():
         learned = compare_schedulers(main_run["d_xyz"], model, args.steps, args.warmup, progress,
                                      reference=main_run["canon"], export=not args.no_export)
         learned["training"] = dict(training, points_per_run=tn)
+    graph = None
+    if not args.no_graph_compare:
+        graph = compare_graph_rounds(main_run["d_xyz"], args.steps, args.warmup, progress,
+                                     reference=main_run["canon"])
+        progress(f"graph rounds: {graph}")
     main_run["canon"] = None
     del main_run["d_xyz"]
     torch.cuda.empty_cache()
@@ -336,6 +343,7 @@ def main():
         "paper_context": paper_context(args.n),
         "oracle_hash_match": oracle_match,
         "learned": learned,
+        "graph_rounds": graph,
         "u8": u8,
         "detail": main_run["detail"],
     }
@@ -679,6 +687,19 @@ def compare_schedulers(d_xyz, model, steps, warmup, progress, reference, export=
     return out
 
 
+def compare_graph_rounds(d_xyz, steps, warmup, progress, reference):
+    """Regular rounds launched as one HIP graph each against separate kernel launches, both
+    without events (timing 0), on the same device input; outputs compared with the main
+    step's canonical output."""
+    res = {name: timed_runs(d_xyz, 0, None, steps, warmup, progress, name, reference, timing=0, graph_rounds=g)
+           for name, g in (("separate launches", False), ("graph rounds", True))}
+    sep, gr = res["separate launches"], res["graph rounds"]
+    return {"separate_ms_per_step": sep["ms_per_step"], "graph_ms_per_step": gr["ms_per_step"],
+            "speedup": round(sep["ms_per_step"] / gr["ms_per_step"], 4), "rounds": gr["rounds"],
+            "graph_launched_rounds": gr["graph_rounds"],
+            "identical_output": None if reference is None else bool(sep["identical"] and gr["identical"])}
+
+
 def train_scheduler(gen, seeds, samples, progress):
     """Plain runs with point logs on the training seeds (other seeds than the timed input),
     then the MLP trained on a random sample of the logged points.  Returns (model, info)."""
@@ -711,7 +732,8 @@ def train_scheduler(gen, seeds, samples, progress):
     return model, info
 
 
-def timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference=None, adaptive_curve=False):
+def timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference=None, adaptive_curve=False,
+               timing=2, graph_rounds=False):
     """`steps` timed triangulations of d_xyz with the given scheduler; per-step means.  With
     a reference canonical output, the last triangulation is exported (untimed) and compared
     with it on the device."""
@@ -720,8 +742,8 @@ def timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference=Non
     from paper_1805_08831_amd import Triangulation, dt_get_tets, dt_load_model
 
     stream = torch.cuda.current_stream()
-    tri = Triangulation(device=0, stream=stream.cuda_stream, timing=2, scheduler=sched,
-                        adaptive_curve=adaptive_curve)
+    tri = Triangulation(device=0, stream=stream.cuda_stream, timing=timing, scheduler=sched,
+                        adaptive_curve=adaptive_curve, graph_rounds=graph_rounds)
     if sched:
         dt_load_model(tri.ctx, model)
     for _ in range(warmup):
@@ -730,7 +752,7 @@ def timed_runs(d_xyz, sched, model, steps, warmup, progress, name, reference=Non
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     agg = dict(rounds=0, attempts=0, conflicts=0, overflows=0, walk_steps=0, perturbed=0, insphere_exact=0,
-               orient_exact=0, walk_caps=0)
+               orient_exact=0, walk_caps=0, graph_rounds=0)
     T = 0
     for _ in range(steps):
         tri.clear()

@@ -101,6 +101,12 @@ typedef struct {
                                regular rounds' 128-entry buffers: 64 (one wavefront,
                                16 cavity tetrahedra per breadth-first step) or 256 (a
                                256-thread block, 64 per step); 0: automatic (256)        */
+    int graph_rounds;       /* 1: launch each regular round (the candidate fill, both cavity
+                               passes, the DelaunayBall kernel and the three round-end
+                               kernels) as one HIP graph, built once per launch shape and
+                               given each round's arguments and grids; rounds for large
+                               cavities, timed rounds and traced rounds stay separate
+                               launches.  0: separate launches.  The result is the same.  */
 } dt_options;
 
 enum { DT_SCHED_PLAIN = 0, DT_SCHED_LEARNED = 1 };
@@ -139,6 +145,7 @@ typedef struct {
                                  the conflicts too: they retry in the next round)        */
     uint64_t timed_attempts, timed_insertions; /* attempts and insertions of the rounds
                                  timed by dt_options.timing (cavity_launches of them)    */
+    uint64_t graph_rounds;    /* rounds launched as one HIP graph (dt_options.graph_rounds) */
 } dt_stats;
 
 /* Fill *opt with the defaults (device 0, library stream, automatic sizes, seed 0x5EED). */

@@ -215,6 +215,7 @@ struct dt_ctx {
     DevBuf<unsigned long long> rf_moore, rf_k0, rf_k1;
     DevBuf<uint32_t> rf_v0, rf_v1, rf_ctr, rf_flags, rf_pos;
     DevBuf<uint32_t> rf_src, rf_src2, rf_srcr, rf_hint;  // candidates' tetrahedron vertex records
+    RoundGraph graphs[ROUND_GRAPH_SHAPES];              // graph-launched rounds, one per launch shape
     DevBuf<uint8_t> rf_status, rf_flag;
     DevBuf<Cloud> rf_cloud;
     DevBuf<uint64_t> rf_off;
@@ -516,7 +517,8 @@ void accumulate_timing(dt_ctx *c, int slot) {
 // nor one still in flight); complete_round waits for it.  max_cand bounds the candidates:
 // the kernels read the count itself from the device.
 int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t capC, uint32_t capF,
-                  uint64_t base, uint64_t n, int busy, int *slot_out, bool slice = false, uint32_t off = 0) {
+                  uint64_t base, uint64_t n, int busy, int *slot_out, bool slice = false, uint32_t off = 0,
+                  const FillPlan *plan = nullptr, const FillArgs *fa = nullptr) {
     const int host = (int)(c->hctr - c->hring);
     int slot = 0;
     while (slot == host || slot == busy) ++slot;
@@ -600,6 +602,28 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     // automatic lanes: a wavefront per insertion in short rounds, which wait on their slowest
     // candidate, c->lanes in the rest
     const uint32_t lanes = c->lanes_auto && max_cand < SMALL_ROUND ? 64u : c->lanes;
+    // graph-launched: regular rounds with the snapshot written by the round-end kernel,
+    // neither timed nor clocked (their events and clearing stay outside graphs)
+    const bool graph = c->opt.graph_rounds && c->ring_direct && !slice && !timed && !a.clk && max_cand &&
+                       capC <= DEFAULT_CAVITY_CAP;
+    if (graph) {
+        const FillPlan none{};
+        const FillArgs nofill{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, nullptr, &d->list_count[ci]};
+        c->fl_idx ^= 1;
+        c->slot_tag[slot] = ++c->tag_counter;
+        HIPCHK(launch_round_graph(c->graphs, plan ? *plan : none, fa ? *fa : nofill, a, c->wide, max_cand, lanes,
+                                  &c->hring[slot], &c->hseq[slot], c->slot_tag[slot], c->stream));
+        c->slot_cand[slot] = max_cand;
+        c->slot_capC[slot] = capC;
+        c->st.rounds++;
+        c->st.graph_rounds++;
+        *slot_out = slot;
+        return DT_OK;
+    }
+    if (plan)
+        HIPCHK(launch_fill_list(*plan, fa->lvl_start, fa->lvl_size, fa->lvl_bits, fa->rank_base, fa->lord, fa->dup,
+                                fa->vtet, fa->cand_pt, fa->cand_rank, fa->ncand, c->stream));
     HIPCHK(launch_round(a, c->wide, max_cand, lanes, c->large_lanes, c->stream, timed ? evs : nullptr));
     c->fl_idx ^= 1;
     if (c->ring_direct) {
@@ -913,11 +937,12 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint3
             if (ok) {
                 FillPlan plan;
                 const uint32_t w = (uint32_t)plan_fill(lv, next_rank, W, plan);
-                HIPCHK(launch_fill_list(plan, d_start, d_size, d_bits, d_rank_base, c->lord, c->dup.p, c->vtet.p,
-                                        c->lpt[ci], c->lrank[ci], &c->ctr->list_count[ci], c->stream));
+                const FillArgs fa{d_start, d_size, d_bits, d_rank_base, c->lord, c->dup.p, c->vtet.p,
+                                  c->lpt[ci], c->lrank[ci], &c->ctr->list_count[ci]};
                 next_rank += w;
                 int slot = -1;
-                int rc = enqueue_round(c, ci, ni, oi, fly_cand + w, c->capC, c->capF, base, n, fly, &slot);
+                int rc = enqueue_round(c, ci, ni, oi, fly_cand + w, c->capC, c->capF, base, n, fly, &slot, false, 0,
+                                       &plan, &fa);
                 if (rc) return rc;
                 c->list_idx = ni;
                 ++rounds_this_call;
@@ -956,13 +981,13 @@ int run_rounds(dt_ctx *c, const Levels &lv, const uint32_t *d_start, const uint3
             return fail(c, DT_E_INCOMPLETE, "round limit %u reached", c->opt.max_rounds);
         FillPlan plan;
         W = (uint32_t)plan_fill(lv, next_rank, W, plan);
-        HIPCHK(launch_fill_list(plan, d_start, d_size, d_bits, d_rank_base, c->lord, c->dup.p, c->vtet.p,
-                                c->lpt[ci], c->lrank[ci], &c->ctr->list_count[ci], c->stream));
+        const FillArgs fa{d_start, d_size, d_bits, d_rank_base, c->lord, c->dup.p, c->vtet.p,
+                          c->lpt[ci], c->lrank[ci], &c->ctr->list_count[ci]};
         next_rank += W;
         const uint32_t max_cand = nl + W;
         int rc = ensure_capacity_for(c, max_cand, c->capF);
         if (rc) return rc;
-        rc = enqueue_round(c, ci, ni, oi, max_cand, c->capC, c->capF, base, n, -1, &fly);
+        rc = enqueue_round(c, ci, ni, oi, max_cand, c->capC, c->capF, base, n, -1, &fly, false, 0, &plan, &fa);
         if (rc) return rc;
         fly_cand = max_cand;
         c->list_idx = ni;
@@ -1295,7 +1320,8 @@ int dt_create(dt_ctx **out, const dt_options *opt) {
         (c->opt.lanes_per_insert != 0 && c->opt.lanes_per_insert != 4 && c->opt.lanes_per_insert != 8 &&
          c->opt.lanes_per_insert != 16 && c->opt.lanes_per_insert != 32 && c->opt.lanes_per_insert != 64) ||
         (c->opt.index_bits != 0 && c->opt.index_bits != 32 && c->opt.index_bits != 64) ||
-        (c->opt.large_lanes != 0 && c->opt.large_lanes != 64 && c->opt.large_lanes != 256)) {
+        (c->opt.large_lanes != 0 && c->opt.large_lanes != 64 && c->opt.large_lanes != 256) ||
+        (c->opt.graph_rounds != 0 && c->opt.graph_rounds != 1)) {
         delete c;
         return DT_E_ARG;
     }
@@ -1850,6 +1876,7 @@ int dt_destroy(dt_ctx *c) {
             if (c->ev[k][j]) hipEventDestroy(c->ev[k][j]);
         if (c->evdone[k]) hipEventDestroy(c->evdone[k]);
     }
+    destroy_round_graphs(c->graphs);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     hipGetLastError();
     delete c;

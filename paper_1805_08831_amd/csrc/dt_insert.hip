@@ -1437,6 +1437,104 @@ hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ graph-launched rounds
+
+namespace {
+
+template <class K>
+void *cavity_filter_kernel(uint32_t lanes) {
+    constexpr uint32_t LHM = K::LHM;
+    switch (lanes) {
+    case 4: return (void *)k_cavity_g<K, 4, LCAPC, LHM, false, false, false>;
+    case 8: return (void *)k_cavity_g<K, 8, LCAPC, LHM, false, false, false>;
+    case 32: return (void *)k_cavity_g<K, 32, LCAPC, LHM, false, false, false>;
+    case 64: return (void *)k_cavity_g<K, 64, LCAPC, LHM, false, false, false>;
+    default: return (void *)k_cavity_g<K, 16, LCAPC, LHM, false, false, false>;
+    }
+}
+
+int lanes_index(uint32_t lanes) {
+    switch (lanes) {
+    case 4: return 0;
+    case 8: return 1;
+    case 32: return 3;
+    case 64: return 4;
+    default: return 2;
+    }
+}
+
+}  // namespace
+
+// The kernels and grids are those of launch_fill_list, launch_round (regular rounds) and
+// launch_round_end; an empty fill plan runs one block that appends nothing.
+hipError_t launch_round_graph(RoundGraph *graphs, const FillPlan &plan, const FillArgs &fa, const RoundArgs &a,
+                              bool wide, uint32_t max_cand, uint32_t lanes, Ctr *snap, unsigned long long *seq,
+                              unsigned long long tag, hipStream_t s) {
+    if (max_cand == 0 || a.capC > LCAPC) return hipErrorInvalidValue;
+    const uint32_t L = lanes == 4 || lanes == 8 || lanes == 32 || lanes == 64 ? lanes : 16u;
+    RoundGraph &g = graphs[(wide ? 5 : 0) + lanes_index(L)];
+    const uint32_t fill_count = plan.off[plan.nblk];
+    const uint32_t gl_ball = L == 64 ? 64u : 16u;
+    void *k_cav = wide ? cavity_filter_kernel<Wide>(L) : cavity_filter_kernel<Narrow>(L);
+    void *k_exact = wide ? (void *)k_cavity_g<Wide, 8, LCAPC, Wide::LHM, false, true, true>
+                         : (void *)k_cavity_g<Narrow, 8, LCAPC, Narrow::LHM, false, true, true>;
+    void *k_b = wide ? (gl_ball == 64 ? (void *)k_ball<Wide, 64, BALL_BLOCK> : (void *)k_ball<Wide, 16, BALL_BLOCK>)
+                     : (gl_ball == 64 ? (void *)k_ball<Narrow, 64, BALL_BLOCK> : (void *)k_ball<Narrow, 16, BALL_BLOCK>);
+    // arguments (copied into the graph when set)
+    FillPlan pl = plan;
+    FillArgs f = fa;
+    RoundArgs ra = a;
+    Ctr *ctr = a.ctr;
+    uint32_t *consumed = const_cast<uint32_t *>(a.ncand_ptr);
+    uint32_t tcap = a.tcap, flcap = a.flcap;
+    const unsigned long long *stat = a.stat;
+    void *fill_args[] = {&pl, &f.lvl_start, &f.lvl_size, &f.lvl_bits, &f.rank_base, &f.lord, &f.dup, &f.vtet,
+                         &f.cand_pt, &f.cand_rank, &f.ncand};
+    void *round_args[] = {&ra};
+    void *roll_args[] = {&ctr, &consumed, &tcap, &flcap, &stat, &snap, &seq, &tag};
+    hipKernelNodeParams p[7] = {};
+    auto set = [&](int k, void *fn, uint32_t grid, uint32_t block, void **args) {
+        p[k].func = fn;
+        p[k].gridDim = dim3(grid ? grid : 1u);
+        p[k].blockDim = dim3(block);
+        p[k].sharedMemBytes = 0;
+        p[k].kernelParams = args;
+        p[k].extra = nullptr;
+    };
+    const uint32_t gpb = 256 / L;
+    set(0, (void *)k_fill, (fill_count + FILL_BLOCK - 1) / FILL_BLOCK, FILL_BLOCK, fill_args);
+    set(1, k_cav, (max_cand + gpb - 1) / gpb, 256, round_args);
+    set(2, k_exact, std::min<uint32_t>((max_cand + 31) / 32, DEFER_BLOCKS), 256, round_args);
+    set(3, k_b, (max_cand + BALL_BLOCK / gl_ball - 1) / (BALL_BLOCK / gl_ball), BALL_BLOCK, round_args);
+    set(4, (void *)k_compact, (max_cand + FILL_BLOCK - 1) / FILL_BLOCK, FILL_BLOCK, round_args);
+    set(5, (void *)k_freelist_carry, 256, 256, round_args);
+    set(6, (void *)k_roll, 1, 64, roll_args);
+    hipError_t e;
+    if (!g.exec) {
+        if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return e;
+        for (int k = 0; k < 7; ++k) {
+            e = hipGraphAddKernelNode(&g.node[k], g.graph, k ? &g.node[k - 1] : nullptr, k ? 1 : 0, &p[k]);
+            if (e != hipSuccess) return e;
+        }
+        if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) {
+            g.exec = nullptr;
+            return e;
+        }
+    } else {
+        for (int k = 0; k < 7; ++k)
+            if ((e = hipGraphExecKernelNodeSetParams(g.exec, g.node[k], &p[k])) != hipSuccess) return e;
+    }
+    return hipGraphLaunch(g.exec, s);
+}
+
+void destroy_round_graphs(RoundGraph *graphs) {
+    for (int k = 0; k < ROUND_GRAPH_SHAPES; ++k) {
+        if (graphs[k].exec) hipGraphExecDestroy(graphs[k].exec);
+        if (graphs[k].graph) hipGraphDestroy(graphs[k].graph);
+        graphs[k] = RoundGraph{};
+    }
+}
+
 // Claim words back to the empty value (above every stamp), for the round after the round
 // counter's low 32 bits wrap.  A fill kernel rather than a strided memset.
 template <class R>

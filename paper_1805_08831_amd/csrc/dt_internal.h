@@ -272,6 +272,28 @@ hipError_t launch_round(const RoundArgs &a, bool wide, uint32_t max_cand, uint32
                         hipStream_t s, hipEvent_t *ev);
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s, Ctr *snap,
                             unsigned long long *seq, unsigned long long tag);
+// A regular round (cavity buffers of the regular size) as one HIP graph: the fill, the two
+// cavity passes, the DelaunayBall kernel and the three round-end kernels as a chain of kernel
+// nodes.  The graph is built and instantiated once per launch shape (pool layout, lanes per
+// insertion); each later round of that shape only updates the nodes' arguments and grids.
+struct FillArgs {
+    const uint32_t *lvl_start, *lvl_size, *lvl_bits;
+    const unsigned long long *rank_base;
+    const uint32_t *lord;
+    const uint8_t *dup;
+    const uint32_t *vtet;
+    uint32_t *cand_pt, *cand_rank, *ncand;
+};
+struct RoundGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node[7] = {};
+};
+constexpr int ROUND_GRAPH_SHAPES = 10;  // pool layout (2) x lanes per insertion (4, 8, 16, 32, 64)
+hipError_t launch_round_graph(RoundGraph *graphs, const FillPlan &plan, const FillArgs &fa, const RoundArgs &a,
+                              bool wide, uint32_t max_cand, uint32_t lanes, Ctr *snap, unsigned long long *seq,
+                              unsigned long long tag, hipStream_t s);
+void destroy_round_graphs(RoundGraph *graphs);
 hipError_t launch_reset_claims(void *T, bool wide, uint32_t tcap, hipStream_t s);
 // copies `count` Tet records into TetW records
 hipError_t launch_widen(const void *src, void *dst, uint32_t count, hipStream_t s);

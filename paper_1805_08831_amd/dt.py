@@ -28,7 +28,7 @@ class dt_options(ctypes.Structure):
                 ("max_rounds", ctypes.c_uint32), ("timing", ctypes.c_int), ("round_fraction", ctypes.c_double),
                 ("lanes_per_insert", ctypes.c_uint32), ("scheduler", ctypes.c_int), ("log_points", ctypes.c_int),
                 ("index_bits", ctypes.c_int), ("adaptive_curve", ctypes.c_int), ("subdet_cache", ctypes.c_int), ("walk_cap", ctypes.c_uint32),
-                ("large_lanes", ctypes.c_uint32)]
+                ("large_lanes", ctypes.c_uint32), ("graph_rounds", ctypes.c_int)]
 
 DT_SCHED_PLAIN, DT_SCHED_LEARNED = 0, 1
 NFEAT, NHID, NOUT = 16, 64, 3
@@ -49,7 +49,7 @@ class dt_stats(ctypes.Structure):
                  ("sched_fallbacks", ctypes.c_uint64), ("index_bits", ctypes.c_uint64),
                  ("dropped_slots", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
                  ("walk_caps", ctypes.c_uint64), ("timed_attempts", ctypes.c_uint64),
-                 ("timed_insertions", ctypes.c_uint64)])
+                 ("timed_insertions", ctypes.c_uint64), ("graph_rounds", ctypes.c_uint64)])
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -358,7 +358,8 @@ class Triangulation:
 
     def __init__(self, device=0, stream=None, round_size=0, cavity_cap=0, capacity_tets=0, seed=0x5EED,
                  max_rounds=0, timing=False, round_fraction=0.0, lanes_per_insert=0, scheduler=0, log_points=False,
-                 index_bits=0, adaptive_curve=False, subdet_cache=False, walk_cap=0, large_lanes=0):
+                 index_bits=0, adaptive_curve=False, subdet_cache=False, walk_cap=0, large_lanes=0,
+                 graph_rounds=False):
         o = dt_default_options()
         o.device, o.round_size, o.cavity_cap = int(device), int(round_size), int(cavity_cap)
         o.capacity_tets, o.seed, o.max_rounds = int(capacity_tets), int(seed), int(max_rounds)
@@ -370,6 +371,7 @@ class Triangulation:
         o.subdet_cache = int(bool(subdet_cache))
         o.walk_cap = int(walk_cap)
         o.large_lanes = int(large_lanes)
+        o.graph_rounds = int(bool(graph_rounds))
         o.stream = stream
         self.ctx = dt_create(o)
 

@@ -582,3 +582,43 @@ def test_timing_large_rounds(dtlib):
     st = out[2][1]
     assert 0 < st["cavity_launches"] < st["rounds"] and st["ms_cavity_kernel"] > 0 and st["ball_launches"] == 0
     assert 0 < st["timed_insertions"] < st["inserted"] and st["timed_insertions"] <= st["timed_attempts"]
+
+
+@pytest.mark.parametrize("case", ["mix", "lanes16", "wide", "grown", "batch", "large"])
+def test_graph_rounds_keep_result(dtlib, oracle_mod, case):
+    """Regular rounds launched as one HIP graph each (dt_options.graph_rounds) give the
+    oracle's result: with drains of overflowed candidates between graph rounds (small cavity
+    cap), with 16 lanes, on a pool of 64-bit codes, across pool growth, for a batch of clouds,
+    and on 2e6 points (graphs of both lane counts, compared with the separate launches)."""
+    from canon import canonical_hash
+    say(f"graph rounds: {case}")
+    if case == "batch":
+        xyz, off = batch_clouds(24, seed_base=7300, nmin=4, nmax=3000)
+        with dtlib.Triangulation(graph_rounds=True) as tri:
+            tri.insert_batch(xyz, off)
+            assert tri.stats()["graph_rounds"] > 0
+            for k in range(0, 24, 3):
+                t, _ = tri.tets_batch(k)
+                assert_parity(oracle_mod, xyz[off[k]:off[k + 1]], t.astype(np.int64), f"cloud {k}")
+        return
+    if case == "large":
+        xyz = uniform_points(2_000_000, 47)
+        out = {}
+        for graph in (False, True):
+            with dtlib.Triangulation(graph_rounds=graph) as tri:
+                tri.insert(xyz)
+                t, _ = tri.tets()
+                out[graph] = (canonical_hash(t), tri.stats())
+        assert out[True][0] == out[False][0]
+        assert out[True][1]["graph_rounds"] > 0 and out[False][1]["graph_rounds"] == 0
+        return
+    opts = {"mix": dict(cavity_cap=12), "lanes16": dict(lanes_per_insert=16), "wide": dict(index_bits=64),
+            "grown": dict(capacity_tets=4096)}[case]
+    xyz = mix_small(53, 4000) if case in ("mix", "grown") else uniform_points(60000, 59)
+    tets, nbrs, st = gpu_dt(dtlib, xyz, graph_rounds=True, **opts)
+    assert_parity(oracle_mod, xyz, tets, case)
+    assert 0 < st["graph_rounds"] <= st["rounds"]
+    if case == "mix":
+        assert st["overflows"] > 0
+    if case == "grown":
+        assert len(tets) > 4 * 4096

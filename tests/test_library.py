@@ -48,7 +48,7 @@ def test_default_options_and_argument_errors(libdt):
     # invalid options are rejected before any device work
     h = ctypes.c_void_p()
     for field, bad in [("lanes_per_insert", 5), ("lanes_per_insert", 128), ("round_fraction", -1.0),
-                       ("large_lanes", 128)]:
+                       ("large_lanes", 128), ("graph_rounds", 2)]:
         o2 = dt.dt_options()
         dt.lib().dt_default_options(ctypes.byref(o2))
         setattr(o2, field, bad)
