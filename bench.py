@@ -873,6 +873,30 @@ def run_batch(args):
         rounds += r
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    graph = None
+    if not args.no_graph_compare:
+        # the same steps without events, with separate launches and with every regular round
+        # launched as one HIP graph
+        timed = {}
+        for name, g in (("separate", False), ("graph", True)):
+            tri.close()
+            tri = Triangulation(device=0, stream=stream.cuda_stream, timing=0, lanes_per_insert=args.lanes,
+                                graph_rounds=g)
+            step()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                Tg, _ = step()
+            torch.cuda.synchronize()
+            timed[name] = (1000.0 * (time.perf_counter() - t1) / args.steps, Tg, tri.stats()["graph_rounds"])
+        graph = {"separate_ms_per_step": round(timed["separate"][0], 3),
+                 "graph_ms_per_step": round(timed["graph"][0], 3),
+                 "speedup": round(timed["separate"][0] / timed["graph"][0], 4),
+                 "graph_launched_rounds_last_call": timed["graph"][2],
+                 "same_count": timed["graph"][1] == T and timed["separate"][1] == T}
+        print(f"[batch] graph rounds: {graph}", file=sys.stderr, flush=True)
+        tri.close()
+        tri = Triangulation(device=0, stream=stream.cuda_stream, timing=2, lanes_per_insert=args.lanes)
     # the same clouds, one dt_insert_points call each, on a sample
     sample = list(range(0, args.clouds, max(1, args.clouds // args.loop_sample)))[:args.loop_sample]
     tl, tt, pts = 0.0, 0, 0
@@ -903,6 +927,7 @@ def run_batch(args):
                                f"seeds 3000 + cloud",
                    "points": int(off[-1]), "tetrahedra": T, "clouds_per_call": args.chunk,
                    "calls_per_step": len(chunks), "rounds_per_step": rounds / max(args.steps, 1)},
+        "graph_rounds": graph,
         "loop_single": {"value": round(tt / tl, 1), "unit": "tetrahedra/s",
                         "sample": f"{len(sample)} of the clouds ({pts} points), one dt_insert_points call each"},
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_clouds(xyz, off, sample),
