@@ -226,7 +226,7 @@ def main():
     ap.add_argument("--refine-h", type=float, default=0.0064,
                     help="refine: target size h (circumcentres of tetrahedra with r > 1.4 h, none closer "
                          "than 0.7 h)")
-    ap.add_argument("--cpu-refine-points", type=int, default=15_000,
+    ap.add_argument("--cpu-refine-points", type=int, default=30_000,
                     help="refine: input points of the oracle's CPU sample (a corner cube of the input)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
