@@ -1370,7 +1370,11 @@ __global__ void k_roll(Ctr *ctr, uint32_t *consumed, uint32_t tcap, uint32_t flc
     if (t == 0) __hip_atomic_store(seq, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-constexpr uint32_t DEFER_BLOCKS = 512;  // grid of the exact-predicate pass (grid-stride)
+// The exact-predicate pass: 16 lanes per attempt (its attempts are whole walks and cavity
+// searches with the exact stages), grid-stride over the attempts the filter pass handed on
+// with up to 16384 of them in flight
+constexpr uint32_t EXACT_LANES = 16;
+constexpr uint32_t DEFER_BLOCKS = 1024;
 
 template <class K>
 static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, uint32_t large_lanes,
@@ -1380,7 +1384,7 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
     // regular rounds: the filter-only kernel over the round's list, then the exact kernel over
     // the attempts it handed on (a short grid-stride pass; nothing to do for most rounds);
     // rounds for large cavities use exact predicates throughout
-    const uint32_t dgrid = std::min<uint32_t>((max_cand + 31) / 32, DEFER_BLOCKS);
+    const uint32_t dgrid = std::min<uint32_t>((max_cand + 256 / EXACT_LANES - 1) / (256 / EXACT_LANES), DEFER_BLOCKS);
     const bool blk = large_lanes != 64;
     if (blk && a.capC > BIG_CAPC) {
         if (a.hmg < 4096 || (a.hmg & (a.hmg - 1)) || (uint64_t)a.hmg * sizeof(typename K::set_t) > 16ull * a.capC)
@@ -1397,19 +1401,19 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
         k_cavity_g<K, 64, BIG_CAPC, BIG_HM, false, true, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
     } else if (lanes == 4) {
         k_cavity_g<K, 4, LCAPC, LHM, false, false, false><<<(max_cand + 63) / 64, 256, 0, s>>>(a);
-        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 8) {
         k_cavity_g<K, 8, LCAPC, LHM, false, false, false><<<(max_cand + 31) / 32, 256, 0, s>>>(a);
-        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 32) {
         k_cavity_g<K, 32, LCAPC, LHM, false, false, false><<<(max_cand + 7) / 8, 256, 0, s>>>(a);
-        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 64) {
         k_cavity_g<K, 64, LCAPC, LHM, false, false, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
-        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else {
         k_cavity_g<K, 16, LCAPC, LHM, false, false, false><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
-        k_cavity_g<K, 8, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     }
     if (ev) hipEventRecord(ev[1], s);
     // rounds for large cavities build large balls (their siblings found by pivoting), and
@@ -1476,8 +1480,8 @@ hipError_t launch_round_graph(RoundGraph *graphs, const FillPlan &plan, const Fi
     const uint32_t fill_count = plan.off[plan.nblk];
     const uint32_t gl_ball = L == 64 ? 64u : 16u;
     void *k_cav = wide ? cavity_filter_kernel<Wide>(L) : cavity_filter_kernel<Narrow>(L);
-    void *k_exact = wide ? (void *)k_cavity_g<Wide, 8, LCAPC, Wide::LHM, false, true, true>
-                         : (void *)k_cavity_g<Narrow, 8, LCAPC, Narrow::LHM, false, true, true>;
+    void *k_exact = wide ? (void *)k_cavity_g<Wide, EXACT_LANES, LCAPC, Wide::LHM, false, true, true>
+                         : (void *)k_cavity_g<Narrow, EXACT_LANES, LCAPC, Narrow::LHM, false, true, true>;
     void *k_b = wide ? (gl_ball == 64 ? (void *)k_ball<Wide, 64, BALL_BLOCK> : (void *)k_ball<Wide, 16, BALL_BLOCK>)
                      : (gl_ball == 64 ? (void *)k_ball<Narrow, 64, BALL_BLOCK> : (void *)k_ball<Narrow, 16, BALL_BLOCK>);
     // arguments (copied into the graph when set)
@@ -1504,7 +1508,7 @@ hipError_t launch_round_graph(RoundGraph *graphs, const FillPlan &plan, const Fi
     const uint32_t gpb = 256 / L;
     set(0, (void *)k_fill, (fill_count + FILL_BLOCK - 1) / FILL_BLOCK, FILL_BLOCK, fill_args);
     set(1, k_cav, (max_cand + gpb - 1) / gpb, 256, round_args);
-    set(2, k_exact, std::min<uint32_t>((max_cand + 31) / 32, DEFER_BLOCKS), 256, round_args);
+    set(2, k_exact, std::min<uint32_t>((max_cand + 256 / EXACT_LANES - 1) / (256 / EXACT_LANES), DEFER_BLOCKS), 256, round_args);
     set(3, k_b, (max_cand + BALL_BLOCK / gl_ball - 1) / (BALL_BLOCK / gl_ball), BALL_BLOCK, round_args);
     set(4, (void *)k_compact, (max_cand + FILL_BLOCK - 1) / FILL_BLOCK, FILL_BLOCK, round_args);
     set(5, (void *)k_freelist_carry, 256, 256, round_args);
