@@ -216,7 +216,8 @@ struct dt_ctx {
     DevBuf<uint32_t> rf_v0, rf_v1, rf_ctr, rf_flags, rf_pos;
     DevBuf<uint32_t> rf_src, rf_src2, rf_srcr, rf_hint;  // candidates' tetrahedron vertex records
     RoundGraph graphs[ROUND_GRAPH_SHAPES];              // graph-launched rounds, one per launch shape
-    DevBuf<uint8_t> rf_status, rf_flag;
+    DevBuf<uint8_t> rf_status, rf_flag, rf_pbig;
+    DevBuf<uint4> rf_prev;  // each slot's vertices at the last refinement pass
     DevBuf<Cloud> rf_cloud;
     DevBuf<uint64_t> rf_off;
     unsigned char *arena = nullptr;
@@ -1870,7 +1871,7 @@ int dt_destroy(dt_ctx *c) {
     f(c->rf_q.p); f(c->rf_q2.p); f(c->rf_facets.p); f(c->rf_moore.p); f(c->rf_k0.p); f(c->rf_k1.p);
     f(c->rf_v0.p); f(c->rf_v1.p); f(c->rf_ctr.p); f(c->rf_flags.p); f(c->rf_pos.p);
     f(c->rf_src.p); f(c->rf_src2.p); f(c->rf_srcr.p); f(c->rf_hint.p);
-    f(c->rf_status.p); f(c->rf_flag.p); f(c->rf_cloud.p); f(c->rf_off.p);
+    f(c->rf_status.p); f(c->rf_flag.p); f(c->rf_pbig.p); f(c->rf_prev.p); f(c->rf_cloud.p); f(c->rf_off.p);
     for (int k = 0; k < 3; ++k) {
         for (int j = 0; j < 3; ++j)
             if (c->ev[k][j]) hipEventDestroy(c->ev[k][j]);
@@ -2168,6 +2169,7 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
     HIPCHK(hipMemcpyAsync(&nf, c->rf_ctr.p, sizeof nf, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     uint64_t total = 0;
+    uint32_t known = 0;  // slots whose last-pass vertices and size flag rf_prev / rf_pbig hold
     for (uint32_t step = 0; step < max_steps; ++step) {
         count = c->hctr->tet_count;
         const uint64_t nv = c->nv;
@@ -2175,11 +2177,13 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         if ((rc = ensure(c, c->rf_cc, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q, count)) ||
             (rc = ensure(c, c->rf_cc2, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q2, count)) ||
             (rc = ensure(c, c->rf_src, count)) || (rc = ensure(c, c->rf_src2, count)) ||
-            (rc = ensure(c, c->rf_flag, count)))
+            (rc = ensure(c, c->rf_flag, count)) || (rc = ensure(c, c->rf_prev, count, true)) ||
+            (rc = ensure(c, c->rf_pbig, count, true)))
             return rc;
         HIPCHK(hipMemsetAsync(c->rf_ctr.p, 0, 4 * sizeof(uint32_t), c->stream));
-        HIPCHK(launch_circum(c->T, c->wide, c->V.p, count, grow, c->rf_cc.p, c->rf_q.p, c->rf_src.p, count,
-                             c->rf_ctr.p, c->stream));
+        HIPCHK(launch_circum(c->T, c->wide, c->V.p, count, grow, c->rf_prev.p, c->rf_pbig.p, known, c->rf_cc.p,
+                             c->rf_q.p, c->rf_src.p, count, c->rf_ctr.p, c->stream));
+        known = count;
         uint32_t k0 = 0;
         HIPCHK(hipMemcpyAsync(&k0, c->rf_ctr.p, sizeof k0, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));

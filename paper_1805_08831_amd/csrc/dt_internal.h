@@ -321,8 +321,11 @@ hipError_t launch_points_out(const Vert *V, uint32_t nv, double *xyz, hipStream_
 // ---- launch wrappers (dt_refine.hip): circumcentre refinement steps
 hipError_t launch_hull_facets(const void *T, bool wide, uint32_t count, uint4 *facets, uint32_t *nfacets,
                               hipStream_t s);
-hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count, double grow, double *cc, uint4 *q,
-                         uint32_t *src, uint32_t cap, uint32_t *ncand, hipStream_t s);
+// prev / pbig (count entries): each slot's vertices and "larger than 1.4 h" at the last pass,
+// valid for the first `known` slots; rewritten for the next pass
+hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count, double grow, uint4 *prev,
+                         uint8_t *pbig, uint32_t known, double *cc, uint4 *q, uint32_t *src, uint32_t cap,
+                         uint32_t *ncand, hipStream_t s);
 hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const double *cc, const uint4 *q,
                          const uint32_t *src, uint32_t k, uint8_t *flag, double *cc2, uint4 *q2, uint32_t *src2,
                          uint32_t *nin, hipStream_t s);

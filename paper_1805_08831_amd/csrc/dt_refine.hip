@@ -5,7 +5,8 @@
 // One step over the current triangulation (the host driver in dt_capi.hip loops the steps):
 //   k_circum     : every live finite tetrahedron with r^2 > (1.4 h)^2 proposes its
 //                  circumcentre (one fixed fp64 formula, vertices in ascending input index,
-//                  no contraction), with its sorted vertex indices as the tie-break;
+//                  no contraction), with its sorted vertex indices as the tie-break; a
+//                  tetrahedron unchanged since the last pass and not larger then is skipped;
 //   k_inside     : the candidate is kept only strictly inside the convex hull: exact
 //                  orient3d against every hull facet (the facets of the ghost tetrahedra);
 //   (sort)       : candidates ordered by the Moore key of the point in the input's grid,
@@ -88,15 +89,27 @@ __device__ __forceinline__ void circumcentre(const double p[4][3], double *cc, d
 // live finite tetrahedra with r^2 > grow: candidate (circumcentre, sorted vertex input indices)
 template <class R>
 __global__ void k_circum(const R *__restrict__ T, const Vert *__restrict__ V, uint32_t count, double grow,
+                         uint4 *__restrict__ prev, uint8_t *__restrict__ pbig, uint32_t known,
                          double *__restrict__ cc, uint4 *__restrict__ q, uint32_t *__restrict__ src, uint32_t cap,
                          uint32_t *__restrict__ ncand) {
     const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     uint4 w = make_uint4(DEAD, 0u, 0u, 0u);
     if (t < count) w = T[t].v;
     const bool live = w.x != DEAD && w.w != GHOST;
+    // a slot holding the same four vertices as at the last pass holds the same tetrahedron
+    // (a destroyed tetrahedron never returns: a later point lies inside its circumsphere);
+    // one that was not larger than 1.4 h then is not now, and its vertices are not read
+    bool keep_small = false;
+    if (t < count) {
+        if (t < known) {
+            const uint4 pw = prev[t];
+            keep_small = live && pw.x == w.x && pw.y == w.y && pw.z == w.z && pw.w == w.w && pbig[t] == 0;
+        }
+        prev[t] = w;
+    }
     double c[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
     uint32_t rec[4] = {w.x, w.y, w.z, w.w}, id[4] = {0u, 0u, 0u, 0u};
-    if (live) {
+    if (live && !keep_small) {
         // the four records, read once, in ascending input index (insertion sort of four)
         double p[4][3];
         for (int k = 0; k < 4; ++k) {
@@ -116,7 +129,8 @@ __global__ void k_circum(const R *__restrict__ T, const Vert *__restrict__ V, ui
             }
         circumcentre(p, c, &r2);
     }
-    const bool want = live && r2 > grow;
+    const bool want = live && !keep_small && r2 > grow;
+    if (t < count) pbig[t] = want ? 1 : 0;
     const uint32_t i = wave_append(want, ncand);
     if (!want || i >= cap) return;  // the host sizes cap to the live tetrahedra
     cc[3 * (size_t)i] = c[0];
@@ -428,11 +442,16 @@ hipError_t launch_hull_facets(const void *T, bool wide, uint32_t count, uint4 *f
     return hipGetLastError();
 }
 
-hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count, double grow, double *cc, uint4 *q,
-                         uint32_t *src, uint32_t cap, uint32_t *ncand, hipStream_t s) {
+hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count, double grow, uint4 *prev,
+                         uint8_t *pbig, uint32_t known, double *cc, uint4 *q, uint32_t *src, uint32_t cap,
+                         uint32_t *ncand, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    if (wide) k_circum<<<blocks256(count), 256, 0, s>>>((const TetW *)T, V, count, grow, cc, q, src, cap, ncand);
-    else k_circum<<<blocks256(count), 256, 0, s>>>((const Tet *)T, V, count, grow, cc, q, src, cap, ncand);
+    if (wide)
+        k_circum<<<blocks256(count), 256, 0, s>>>((const TetW *)T, V, count, grow, prev, pbig, known, cc, q, src, cap,
+                                                  ncand);
+    else
+        k_circum<<<blocks256(count), 256, 0, s>>>((const Tet *)T, V, count, grow, prev, pbig, known, cc, q, src, cap,
+                                                  ncand);
     return hipGetLastError();
 }
 

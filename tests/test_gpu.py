@@ -107,6 +107,42 @@ def test_predicates_match_oracle(dtlib, oracle_mod):
         dtlib.dt_destroy(ctx)
 
 
+def test_exact_stage_widths_match_oracle(dtlib, oracle_mod):
+    """Near-degenerate orient3d and insphere cases whose coordinates span 2^-s .. 1, for s
+    around 26 bits: the integer stage's fixed-width form in registers takes spreads up to 26
+    bits and the general form the wider ones; both must give the oracle's signs."""
+    say("exact stage widths")
+    rng = np.random.default_rng(11)
+    cases4, cases5 = [], []
+    for s in (20, 24, 25, 26, 27, 28, 32, 40):
+        for k in range(150):
+            p = uniform_points(3, 50000 + 1000 * s + k) + 0.25
+            p[k % 3, k % 2] = np.ldexp(0.5 + 0.5 * rng.random(), -s)  # one tiny coordinate
+            u, v = rng.random(2)
+            q = p[0] + u * (p[1] - p[0]) + v * (p[2] - p[0])
+            q[1] = np.nextafter(q[1], np.inf if k % 2 else -np.inf)
+            cases4.append(np.vstack([p, q]))
+            a = uniform_points(4, 60000 + 1000 * s + k) + 0.25
+            a[k % 4, 2] = np.ldexp(0.5 + 0.5 * rng.random(), -s)
+            # a fifth point on the circumsphere of the four, up to rounding
+            A = 2.0 * (a[1:] - a[0])
+            bvec = (a[1:] ** 2).sum(1) - (a[0] ** 2).sum()
+            c = np.linalg.solve(A, bvec)
+            d = rng.normal(size=3)
+            e = c + np.linalg.norm(a[0] - c) * d / np.linalg.norm(d)
+            cases5.append(np.vstack([a, e]))
+    p4, p5 = np.array(cases4), np.array(cases5)
+    want4, want5 = oracle_mod.orient3d(p4), oracle_mod.insphere(p5)
+    ctx = dtlib.dt_create()
+    try:
+        assert np.array_equal(dtlib.dt_debug_predicates(ctx, 0, p4.reshape(len(p4), -1)), want4)
+        assert np.array_equal(dtlib.dt_debug_predicates(ctx, 1, p5.reshape(len(p5), -1)), want5)
+    finally:
+        dtlib.dt_destroy(ctx)
+    # both signs occur: the cases are near, not on, the degenerate configurations
+    assert set(np.unique(want4)) >= {-1, 1} and set(np.unique(want5)) >= {-1, 1}
+
+
 # ------------------------------------------------------------------ sort
 
 @pytest.mark.parametrize("kind,n", [("uniform", 1017), ("uniform", 100000), ("mix", 30000)])
