@@ -39,17 +39,29 @@ __global__ void k_hull_facets(const R *__restrict__ T, uint32_t count, uint4 *__
     facets[atomicAdd(nfacets, 1u)] = make_uint4(w.x, w.y, w.z, 0u);
 }
 
-// slot of this lane in a list appended to by the lanes with `want` set: one atomic per
-// wavefront (every lane of the wavefront calls it)
-__device__ __forceinline__ uint32_t wave_append(bool want, uint32_t *count) {
+// Slot of this thread in a list appended to by the threads with `want` set: one atomic per
+// block, whose NW waves all call it (LDS: NW + 1 words).  Candidates are sparse but spread
+// over the whole pool, and one counter takes about one atomic per 12 ns, so per-wave appends
+// from a pass over ten million slots serialize for most of a millisecond.
+template <int NW>
+__device__ __forceinline__ uint32_t block_append(bool want, uint32_t *count, uint32_t *s_tmp) {
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     const unsigned long long m = __ballot(want);
-    if (!m) return 0u;
-    const uint32_t lane = threadIdx.x & 63u;
-    const int first = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if ((int)lane == first) base = atomicAdd(count, (uint32_t)__popcll(m));
-    base = __shfl(base, first);
-    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_tmp[wid] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c = s_tmp[w];
+            s_tmp[w] = t;
+            t += c;
+        }
+        s_tmp[NW] = t ? atomicAdd(count, t) : 0u;
+    }
+    __syncthreads();
+    const uint32_t r = s_tmp[NW] + s_tmp[wid] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    __syncthreads();  // s_tmp may be reused after
+    return r;
 }
 
 __device__ __forceinline__ double dot3(const double *x, const double *y) {
@@ -87,8 +99,10 @@ __device__ __forceinline__ void circumcentre(const double p[4][3], double *cc, d
 }
 
 // live finite tetrahedra with r^2 > grow: candidate (circumcentre, sorted vertex input indices)
+constexpr int CIRCUM_BLOCK = 1024;
+
 template <class R>
-__global__ void k_circum(const R *__restrict__ T, const Vert *__restrict__ V, uint32_t count, double grow,
+__global__ __launch_bounds__(CIRCUM_BLOCK) void k_circum(const R *__restrict__ T, const Vert *__restrict__ V, uint32_t count, double grow,
                          uint4 *__restrict__ prev, uint8_t *__restrict__ pbig, uint32_t known,
                          double *__restrict__ cc, uint4 *__restrict__ q, uint32_t *__restrict__ src, uint32_t cap,
                          uint32_t *__restrict__ ncand) {
@@ -131,7 +145,8 @@ __global__ void k_circum(const R *__restrict__ T, const Vert *__restrict__ V, ui
     }
     const bool want = live && !keep_small && r2 > grow;
     if (t < count) pbig[t] = want ? 1 : 0;
-    const uint32_t i = wave_append(want, ncand);
+    __shared__ uint32_t s_tmp[CIRCUM_BLOCK / 64 + 1];
+    const uint32_t i = block_append<CIRCUM_BLOCK / 64>(want, ncand, s_tmp);
     if (!want || i >= cap) return;  // the host sizes cap to the live tetrahedra
     cc[3 * (size_t)i] = c[0];
     cc[3 * (size_t)i + 1] = c[1];
@@ -153,7 +168,8 @@ __device__ __forceinline__ void inside_append(uint32_t i, bool in, P3 x, const u
                                               const uint32_t *__restrict__ src, double *__restrict__ cc2,
                                               uint4 *__restrict__ q2, uint32_t *__restrict__ src2,
                                               uint32_t *__restrict__ nin) {
-    const uint32_t j = wave_append(in, nin);
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
+    const uint32_t j = block_append<256 / 64>(in, nin, s_tmp);
     if (!in) return;
     cc2[3 * (size_t)j] = x.x;
     cc2[3 * (size_t)j + 1] = x.y;
@@ -324,41 +340,45 @@ __global__ void k_near_vertex(Grid G, const Vert *__restrict__ V, const unsigned
 // decided) looks at the earlier candidates r' < r closer than the limit that are not dropped:
 // any kept one drops r; none undecided keeps r; otherwise r waits.  Decisions never change,
 // and a decision reads only earlier ranks, so reading a neighbour decided in this same round
-// or the round before gives the same result.  *undecided counts the ones left.
-__global__ void k_filter_round(Grid G, const unsigned long long *__restrict__ ckeys, const uint32_t *__restrict__ crank,
-                               uint32_t k, const double *__restrict__ ccr, double lim, uint8_t *status,
-                               uint32_t *__restrict__ undecided) {
+// or the round before gives the same result.  *undecided becomes non-zero if any is left.
+__global__ __launch_bounds__(256) void k_filter_round(Grid G, const unsigned long long *__restrict__ ckeys,
+                                                      const uint32_t *__restrict__ crank, uint32_t k,
+                                                      const double *__restrict__ ccr, double lim, uint8_t *status,
+                                                      uint32_t *__restrict__ undecided) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= k) return;
-    if (__hip_atomic_load(&status[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-    const double x = ccr[3 * (size_t)r], y = ccr[3 * (size_t)r + 1], z = ccr[3 * (size_t)r + 2];
-    const long long cx = cell_of(G, x, 0), cy = cell_of(G, y, 1), cz = cell_of(G, z, 2);
-    bool kept_near = false, pending = false;
-    for (long long dz = -1; dz <= 1 && !kept_near; ++dz)
-        for (long long dy = -1; dy <= 1 && !kept_near; ++dy) {
-            const long long yy = cy + dy, zz = cz + dz;
-            if (yy < 0 || zz < 0 || yy >= (long long)G.g || zz >= (long long)G.g) continue;
-            const long long x0 = cx > 0 ? cx - 1 : 0, x1 = cx + 1 < (long long)G.g ? cx + 1 : (long long)G.g - 1;
-            uint32_t a = lower_bound(ckeys, k, cell_key(G, x0, yy, zz));
-            const unsigned long long kend = cell_key(G, x1, yy, zz);
-            for (; a < k && ckeys[a] <= kend && !kept_near; ++a) {
-                const uint32_t o = crank[a];
-                if (o >= r) continue;
-                const uint8_t so = __hip_atomic_load(&status[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (so == 2) continue;
-                if (sq_dist(ccr[3 * (size_t)o], ccr[3 * (size_t)o + 1], ccr[3 * (size_t)o + 2], x, y, z) < lim) {
-                    if (so == 1) kept_near = true;
-                    else pending = true;
+    bool pending = false;
+    if (r < k && __hip_atomic_load(&status[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        const double x = ccr[3 * (size_t)r], y = ccr[3 * (size_t)r + 1], z = ccr[3 * (size_t)r + 2];
+        const long long cx = cell_of(G, x, 0), cy = cell_of(G, y, 1), cz = cell_of(G, z, 2);
+        bool kept_near = false;
+        for (long long dz = -1; dz <= 1 && !kept_near; ++dz)
+            for (long long dy = -1; dy <= 1 && !kept_near; ++dy) {
+                const long long yy = cy + dy, zz = cz + dz;
+                if (yy < 0 || zz < 0 || yy >= (long long)G.g || zz >= (long long)G.g) continue;
+                const long long x0 = cx > 0 ? cx - 1 : 0, x1 = cx + 1 < (long long)G.g ? cx + 1 : (long long)G.g - 1;
+                uint32_t a = lower_bound(ckeys, k, cell_key(G, x0, yy, zz));
+                const unsigned long long kend = cell_key(G, x1, yy, zz);
+                for (; a < k && ckeys[a] <= kend && !kept_near; ++a) {
+                    const uint32_t o = crank[a];
+                    if (o >= r) continue;
+                    const uint8_t so = __hip_atomic_load(&status[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (so == 2) continue;
+                    if (sq_dist(ccr[3 * (size_t)o], ccr[3 * (size_t)o + 1], ccr[3 * (size_t)o + 2], x, y, z) < lim) {
+                        if (so == 1) kept_near = true;
+                        else pending = true;
+                    }
                 }
             }
+        if (kept_near) {
+            pending = false;
+            __hip_atomic_store(&status[r], (uint8_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (!pending) {
+            __hip_atomic_store(&status[r], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-    if (kept_near) {
-        __hip_atomic_store(&status[r], (uint8_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else if (!pending) {
-        __hip_atomic_store(&status[r], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        atomicAdd(undecided, 1u);
     }
+    // one flag per block: the host only asks whether any candidate is left undecided (one
+    // counter takes about one atomic per 12 ns, and a first round leaves many)
+    if (__syncthreads_or(pending) && threadIdx.x == 0) atomicOr(undecided, 1u);
 }
 
 // kept candidates in rank order: flag for the scan, then the points at their scanned positions
@@ -446,12 +466,13 @@ hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count
                          uint8_t *pbig, uint32_t known, double *cc, uint4 *q, uint32_t *src, uint32_t cap,
                          uint32_t *ncand, hipStream_t s) {
     if (count == 0) return hipSuccess;
+    const uint32_t nb = (uint32_t)((count + CIRCUM_BLOCK - 1) / CIRCUM_BLOCK);
     if (wide)
-        k_circum<<<blocks256(count), 256, 0, s>>>((const TetW *)T, V, count, grow, prev, pbig, known, cc, q, src, cap,
-                                                  ncand);
+        k_circum<<<nb, CIRCUM_BLOCK, 0, s>>>((const TetW *)T, V, count, grow, prev, pbig, known, cc, q, src, cap,
+                                             ncand);
     else
-        k_circum<<<blocks256(count), 256, 0, s>>>((const Tet *)T, V, count, grow, prev, pbig, known, cc, q, src, cap,
-                                                  ncand);
+        k_circum<<<nb, CIRCUM_BLOCK, 0, s>>>((const Tet *)T, V, count, grow, prev, pbig, known, cc, q, src, cap,
+                                             ncand);
     return hipGetLastError();
 }
 
