@@ -2237,13 +2237,16 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         unsigned long long *ckeys = nullptr;
         uint32_t *crank = sort_into(c, c->rf_k0.p, c->rf_v0.p, c->rf_k1.p, c->rf_v1.p, K, gbits, &ckeys, &he);
         HIPCHK(he);
-        for (uint32_t round = 0;; ++round) {
+        // two rounds per look at the flags: a round after the last deciding one is a pass that
+        // changes nothing, cheaper than a wait for the host
+        for (uint32_t round = 0;; round += 2) {
             if (round > K) return fail(c, DT_E_INTERNAL, "refinement filter did not settle");
-            HIPCHK(hipMemsetAsync(c->rf_ctr.p + 2, 0, sizeof(uint32_t), c->stream));
-            HIPCHK(launch_filter_round(lo, cell, G, ckeys, crank, K, c->rf_ccr.p, lim, c->rf_status.p,
-                                       c->rf_ctr.p + 2, c->stream));
+            HIPCHK(hipMemsetAsync(c->rf_ctr.p + 2, 0, 2 * sizeof(uint32_t), c->stream));
+            for (int r2 = 0; r2 < 2; ++r2)
+                HIPCHK(launch_filter_round(lo, cell, G, ckeys, crank, K, c->rf_ccr.p, lim, c->rf_status.p,
+                                           c->rf_ctr.p + 2 + r2, c->stream));
             uint32_t und = 0;
-            HIPCHK(hipMemcpyAsync(&und, c->rf_ctr.p + 2, sizeof und, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipMemcpyAsync(&und, c->rf_ctr.p + 3, sizeof und, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
             if (und == 0) break;
         }
