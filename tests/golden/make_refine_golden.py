@@ -3,6 +3,8 @@ count, steps as candidates/kept, and SHA-256 of the canonical tetrahedra and of 
 coordinates).  Calls only the oracle package and the input generators.
 
 Run from the repository root: python tests/golden/make_refine_golden.py
+With --fullsize it writes refine_fullsize_golden.txt instead: the same for the benchmark's
+refinement workload (2.5e5 points, h = 0.0064; about five minutes on one core).
 """
 import hashlib
 import os
@@ -19,6 +21,9 @@ CASES = [("uniform", 600, 7, 0.08), ("uniform", 2000, 11, 0.05), ("clusters", 80
          # the input points)
          ("uniform", 10000, 13, 0.0185)]
 
+# the benchmark's refinement workload (bench.py --workload refine)
+FULLSIZE_CASES = [("uniform", 250000, 4007, 0.0064)]
+
 
 def run_case(kind, n, seed, h):
     import oracle
@@ -33,11 +38,13 @@ def run_case(kind, n, seed, h):
 
 
 def main():
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "refine_golden.txt")
+    full = "--fullsize" in sys.argv[1:]
+    name = "refine_fullsize_golden.txt" if full else "refine_golden.txt"
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     with open(out, "w") as fh:
-        fh.write("# refinement oracle results (written by make_refine_golden.py)\n")
+        fh.write("# refinement oracle results (written by make_refine_golden.py%s)\n" % (" --fullsize" if full else ""))
         fh.write("# kind n seed h | points steps(candidates/kept) sha256(canonical tets) sha256(points)\n")
-        for kind, n, seed, h in CASES:
+        for kind, n, seed, h in (FULLSIZE_CASES if full else CASES):
             npts, steps, ht, hp = run_case(kind, n, seed, h)
             fh.write(f"{kind} {n} {seed} {h} | {npts} {steps} {ht} {hp}\n")
     print(out)

@@ -51,30 +51,35 @@ def test_refine_matches_the_oracle(dtlib, oracle_mod, case):
         check_invariants(pts, t.astype(np.int64), nb, oracle_mod, expect_vertices=np.arange(npts))
 
 
+FULLSIZE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "refine_fullsize_golden.txt")
+
+
 def test_refine_benchmark_size(dtlib, oracle_mod):
     """The benchmark's refinement workload (2.5e5 uniform points, seed 4007, h = 0.0064; about
-    1.5e6 final points), checked by what holds at any size: the final tetrahedralization is
-    the oracle's Delaunay tetrahedralization of the final point set, every added point lies
-    at least 0.7 h from every other vertex, the passes' kept counts sum to the points added,
-    and the last pass keeps none."""
+    1.5e6 final points) against the oracle's stored result for it
+    (tests/golden/refine_fullsize_golden.txt, written by make_refine_golden.py --fullsize from
+    the oracle alone): the same passes (candidates and kept points), the same final points bit
+    for bit and the same tetrahedra; and, by what holds at any size, every added point lies
+    at least 0.7 h from every other vertex."""
     from scipy.spatial import cKDTree
-    n, h = 250_000, 0.0064
-    say(f"refine uniform n={n} seed=4007 h={h}")
-    xyz = uniform_points(n, 4007)
+    rows = [l.split("|") for l in open(FULLSIZE) if l.strip() and not l.startswith("#")]
+    (kind, n, seed, h), (npts, steps, ht, hp) = rows[0][0].split(), rows[0][1].split()
+    n, seed, h, npts = int(n), int(seed), float(h), int(npts)
+    steps = [tuple(int(x) for x in st.split("/")) for st in steps.split(";")]
+    assert (kind, n, seed, h) == ("uniform", 250_000, 4007, 0.0064)
+    say(f"refine uniform n={n} seed={seed} h={h}")
+    xyz = uniform_points(n, seed)
     with dtlib.Triangulation() as tri:
         tri.insert(xyz)
-        added, steps = dtlib.dt_refine(tri.ctx, h)
+        added, got_steps = dtlib.dt_refine(tri.ctx, h)
         pts = dtlib.dt_get_points(tri.ctx)
         t, _ = tri.tets()
-    say(f"steps {steps}, {added} points added, {len(t)} tetrahedra")
-    assert added > 4 * n and len(pts) == n + added
+    say(f"steps {got_steps}, {added} points added, {len(t)} tetrahedra")
+    assert got_steps == steps
+    assert len(pts) == npts and added == npts - n
     assert np.array_equal(pts[:n], xyz)
-    assert sum(k for _, k in steps) == added and steps[-1][1] == 0
+    assert hashlib.sha256(np.ascontiguousarray(pts).tobytes()).hexdigest() == hp
+    canon = oracle_mod.canonical(t.astype(np.int64)).astype(np.int64)
+    assert hashlib.sha256(canon.tobytes()).hexdigest() == ht
     d, _ = cKDTree(pts).query(pts[n:], k=2)
     assert d[:, 1].min() >= 0.7 * h * (1 - 1e-12)
-    rc, ot, _, _ = oracle_mod.delaunay(pts, order="brio", seed=0)
-    assert rc == 0
-    assert len(ot) == len(t)
-    got = oracle_mod.canonical(t.astype(np.int64))
-    want = oracle_mod.canonical(ot.astype(np.int64))
-    assert np.array_equal(got, want)
