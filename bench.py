@@ -529,8 +529,8 @@ def run_uniform(args, xyz, n, seed, steps, warmup, progress):
     att_achieved = b_att * agg["timed_att"] / launches / (avg_launch_ms / 1000.0) / 1e9 if avg_launch_ms > 0 else 0.0
     default_launch = (not lanes and not args.round_fraction and not args.round_size and n == 10_000_000
                       and seed == 1007 and not args.subdet_cache and not args.adaptive_curve and not args.walk_cap)
-    kname = (f"k_cavity_g filter and exact passes, {lanes} lanes, rounds of 32768 candidates or more" if lanes else
-             "k_cavity_g filter and exact passes, 16 lanes, rounds of 32768 candidates or more")
+    kname = (f"k_cavity_g filter pass (and exact pass once launched), {lanes} lanes, rounds of 32768 candidates or more" if lanes else
+             "k_cavity_g filter pass (and exact pass once launched), 16 lanes, rounds of 32768 candidates or more")
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": peak,
                 "unit": "GB/s", "frac": round(achieved / peak, 5),
                 # measured HBM bytes per launch (counter summary), only for the launch it was taken on
@@ -1034,7 +1034,7 @@ def run_refine(args):
                                f"h = {h}, convex hull as the domain",
                    "input_tetrahedra": T0, "points_added": added, "final_points": n + added,
                    "tetrahedra": T, "passes": [list(s) for s in steps]},
-        "roofline": {"bound": "hbm", "kernel": "k_cavity_g filter and exact passes of the refinement's "
+        "roofline": {"bound": "hbm", "kernel": "k_cavity_g filter pass (and exact pass once launched) of the refinement's "
                                                "insertion rounds of 32768 candidates or more",
                      "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
                      "frac": round(achieved / 8000.0, 5), "traffic": None,

@@ -119,6 +119,11 @@ struct dt_ctx {
     uint32_t capC = 0, capF = 0;
     uint32_t lanes = 8;  // lanes per insertion of the cavity kernel
     bool lanes_auto = true;  // lanes_per_insert 0: 64 lanes in rounds below SMALL_ROUND
+    // exact-predicate pass: launched in the regular rounds once the call's filter passes have
+    // handed on an attempt (counted in Ctr::deferred, which stood at deferred_base when the
+    // call began); inputs whose fp64 filter decides everything never launch it
+    bool exact_needed = false;
+    unsigned long long deferred_base = 0;
     uint32_t large_lanes = 256;  // the same in rounds for large cavities (64 or 256)
     double frac = 0;     // round size as a fraction of the mesh's vertices
     bool frac_auto = true;  // round_fraction 0: short rounds take SHORT_ROUND_FRACTION_SCALE times more
@@ -625,7 +630,8 @@ int enqueue_round(dt_ctx *c, int ci, int ni, int oi, uint32_t max_cand, uint32_t
     if (plan)
         HIPCHK(launch_fill_list(*plan, fa->lvl_start, fa->lvl_size, fa->lvl_bits, fa->rank_base, fa->lord, fa->dup,
                                 fa->vtet, fa->cand_pt, fa->cand_rank, fa->ncand, c->stream));
-    HIPCHK(launch_round(a, c->wide, max_cand, lanes, c->large_lanes, c->stream, timed ? evs : nullptr));
+    HIPCHK(launch_round(a, c->wide, max_cand, lanes, c->large_lanes, c->exact_needed, c->stream,
+                        timed ? evs : nullptr));
     c->fl_idx ^= 1;
     if (c->ring_direct) {
         c->slot_tag[slot] = ++c->tag_counter;
@@ -733,6 +739,9 @@ int complete_round(dt_ctx *c, int slot) {
     const uint32_t won_before = c->hctr->won;
     const unsigned long long att_before = c->hctr->attempts;
     c->hctr = &c->hring[slot];
+    // from the first attempt the filter handed on, every later round of the call runs the
+    // exact pass (the rounds launched before it was seen retry theirs)
+    if (c->hctr->deferred != c->deferred_base) c->exact_needed = true;
     const uint32_t max_cand = c->slot_cand[slot], capC = c->slot_capC[slot];
     if (max_cand && c->slot_timed[slot]) {
         accumulate_timing(c, slot);
@@ -1185,6 +1194,8 @@ int insert_clouds(dt_ctx *c, const double *xyz, uint64_t n, const std::vector<ui
     HIPCHK(hipMemsetAsync(c->lastt.p, 0xFF, n * sizeof(uint32_t), c->stream));
     c->call_clouds = C;
     c->lord = lord;
+    c->exact_needed = false;
+    c->deferred_base = c->hctr->deferred;
     // without a model the learned scheduler falls back to the plain order (counted in the
     // statistics); the triangulation is the same either way
     const bool learned = c->opt.scheduler == DT_SCHED_LEARNED && c->have_model;

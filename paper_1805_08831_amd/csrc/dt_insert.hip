@@ -1292,7 +1292,8 @@ __global__ __launch_bounds__(FILL_BLOCK) void k_compact(RoundArgs a) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ncand = *a.ncand_ptr;
     const uint8_t s = i < ncand ? a.status[i] : (uint8_t)ST_NONE;
-    const bool again = i < ncand && (s == ST_CONFLICT || s == ST_CAND || s == ST_WALK);
+    // ST_FULL left by a round whose exact pass was not launched: the attempt retries
+    const bool again = i < ncand && (s == ST_CONFLICT || s == ST_CAND || s == ST_WALK || s == ST_FULL);
     const bool ovf = i < ncand && s == ST_OVERFLOW;
     if (a.log_att && i < ncand) atomicAdd(&a.log_att[a.cand_pt[i] - a.vlo], 1u);
     const uint32_t pn = block_reserve<NW>(again ? 1u : 0u, a.nnext_ptr, s_tmp);
@@ -1378,7 +1379,7 @@ constexpr uint32_t DEFER_BLOCKS = 1024;
 
 template <class K>
 static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t lanes, uint32_t large_lanes,
-                                 hipStream_t s, hipEvent_t *ev) {
+                                 bool exact, hipStream_t s, hipEvent_t *ev) {
     constexpr uint32_t LHM = K::LHM;
     if (ev) hipEventRecord(ev[0], s);
     // regular rounds: the filter-only kernel over the round's list, then the exact kernel over
@@ -1401,19 +1402,19 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
         k_cavity_g<K, 64, BIG_CAPC, BIG_HM, false, true, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
     } else if (lanes == 4) {
         k_cavity_g<K, 4, LCAPC, LHM, false, false, false><<<(max_cand + 63) / 64, 256, 0, s>>>(a);
-        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        if (exact) k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 8) {
         k_cavity_g<K, 8, LCAPC, LHM, false, false, false><<<(max_cand + 31) / 32, 256, 0, s>>>(a);
-        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        if (exact) k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 32) {
         k_cavity_g<K, 32, LCAPC, LHM, false, false, false><<<(max_cand + 7) / 8, 256, 0, s>>>(a);
-        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        if (exact) k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else if (lanes == 64) {
         k_cavity_g<K, 64, LCAPC, LHM, false, false, false><<<(max_cand + 3) / 4, 256, 0, s>>>(a);
-        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        if (exact) k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     } else {
         k_cavity_g<K, 16, LCAPC, LHM, false, false, false><<<(max_cand + 15) / 16, 256, 0, s>>>(a);
-        k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
+        if (exact) k_cavity_g<K, EXACT_LANES, LCAPC, LHM, false, true, true><<<dgrid, 256, 0, s>>>(a);
     }
     if (ev) hipEventRecord(ev[1], s);
     // rounds for large cavities build large balls (their siblings found by pivoting), and
@@ -1427,10 +1428,10 @@ static hipError_t launch_round_k(const RoundArgs &a, uint32_t max_cand, uint32_t
 }
 
 hipError_t launch_round(const RoundArgs &a, bool wide, uint32_t max_cand, uint32_t lanes, uint32_t large_lanes,
-                        hipStream_t s, hipEvent_t *ev) {
+                        bool exact, hipStream_t s, hipEvent_t *ev) {
     if (max_cand == 0) return hipSuccess;
-    return wide ? launch_round_k<Wide>(a, max_cand, lanes, large_lanes, s, ev)
-                : launch_round_k<Narrow>(a, max_cand, lanes, large_lanes, s, ev);
+    return wide ? launch_round_k<Wide>(a, max_cand, lanes, large_lanes, exact, s, ev)
+                : launch_round_k<Narrow>(a, max_cand, lanes, large_lanes, exact, s, ev);
 }
 
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s, Ctr *snap,

@@ -268,8 +268,10 @@ hipError_t launch_fill_list(const FillPlan &plan, const uint32_t *lvl_start, con
                             const uint32_t *lvl_bits, const unsigned long long *rank_base, const uint32_t *lord,
                             const uint8_t *dup, const uint32_t *vtet, uint32_t *cand_pt, uint32_t *cand_rank,
                             uint32_t *ncand, hipStream_t s);
+// exact: launch the exact-predicate pass after the filter pass of a regular round (without
+// it, attempts the filter hands on retry in the next round)
 hipError_t launch_round(const RoundArgs &a, bool wide, uint32_t max_cand, uint32_t lanes, uint32_t large_lanes,
-                        hipStream_t s, hipEvent_t *ev);
+                        bool exact, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_round_end(const RoundArgs &a, uint32_t max_cand, hipStream_t s, Ctr *snap,
                             unsigned long long *seq, unsigned long long tag);
 // A regular round (cavity buffers of the regular size) as one HIP graph: the fill, the two
