@@ -219,7 +219,7 @@ struct dt_ctx {
     DevBuf<uint4> rf_q, rf_q2, rf_facets;
     DevBuf<unsigned long long> rf_moore, rf_k0, rf_k1;
     DevBuf<uint32_t> rf_v0, rf_v1, rf_ctr, rf_flags, rf_pos;
-    DevBuf<uint32_t> rf_src, rf_src2, rf_srcr, rf_hint;  // candidates' tetrahedron vertex records
+    DevBuf<uint32_t> rf_src, rf_src2, rf_srcr, rf_hint, rf_rest;  // candidates' tetrahedron vertex records
     RoundGraph graphs[ROUND_GRAPH_SHAPES];              // graph-launched rounds, one per launch shape
     DevBuf<uint8_t> rf_status, rf_flag, rf_pbig;
     DevBuf<uint4> rf_prev;  // each slot's vertices at the last refinement pass
@@ -1881,7 +1881,7 @@ int dt_destroy(dt_ctx *c) {
     f(c->rf_cc.p); f(c->rf_cc2.p); f(c->rf_ccr.p); f(c->rf_pts.p); f(c->rf_partial.p);
     f(c->rf_q.p); f(c->rf_q2.p); f(c->rf_facets.p); f(c->rf_moore.p); f(c->rf_k0.p); f(c->rf_k1.p);
     f(c->rf_v0.p); f(c->rf_v1.p); f(c->rf_ctr.p); f(c->rf_flags.p); f(c->rf_pos.p);
-    f(c->rf_src.p); f(c->rf_src2.p); f(c->rf_srcr.p); f(c->rf_hint.p);
+    f(c->rf_src.p); f(c->rf_src2.p); f(c->rf_srcr.p); f(c->rf_hint.p); f(c->rf_rest.p);
     f(c->rf_status.p); f(c->rf_flag.p); f(c->rf_pbig.p); f(c->rf_prev.p); f(c->rf_cloud.p); f(c->rf_off.p);
     for (int k = 0; k < 3; ++k) {
         for (int j = 0; j < 3; ++j)
@@ -2137,6 +2137,67 @@ int bits_for(uint64_t x) {
 
 }  // namespace
 
+// The inner box of the hull test: the points' box [lo, hi] shrunk on every side by a fraction
+// of its extent, the largest of a few candidates whose eight corners the hull test (exact)
+// finds strictly inside.  None (lo > hi) when no candidate passes.
+static int find_inner_box(dt_ctx *c, uint32_t nf, const double lo[3], const double hi[3], InnerBox *out) {
+    *out = InnerBox{{1.0, 1.0, 1.0}, {0.0, 0.0, 0.0}};
+    if (nf == 0) return DT_OK;
+    constexpr int NBOX = 7;
+    constexpr uint32_t NP = 8 * NBOX;
+    const double shrink[NBOX] = {0x1p-10, 0x1p-8, 0x1p-6, 0x1p-5, 0x1p-4, 0x1p-3, 0x1p-2};
+    InnerBox boxes[NBOX];
+    double pts[3 * NP];
+    uint4 ids[NP];
+    for (int b = 0; b < NBOX; ++b) {
+        for (int k = 0; k < 3; ++k) {
+            const double e = hi[k] - lo[k];
+            boxes[b].lo[k] = lo[k] + shrink[b] * e;
+            boxes[b].hi[k] = hi[k] - shrink[b] * e;
+        }
+        for (uint32_t q = 0; q < 8; ++q) {
+            const uint32_t j = 8 * b + q;
+            for (int k = 0; k < 3; ++k) pts[3 * j + k] = (q >> k) & 1u ? boxes[b].hi[k] : boxes[b].lo[k];
+            ids[j] = make_uint4(j, 0, 0, 0);
+        }
+    }
+    int rc;
+    if ((rc = ensure(c, c->rf_cc, 3 * (size_t)NP)) || (rc = ensure(c, c->rf_q, NP)) ||
+        (rc = ensure(c, c->rf_src, NP)) || (rc = ensure(c, c->rf_flag, NP)) ||
+        (rc = ensure(c, c->rf_cc2, 3 * (size_t)NP)) || (rc = ensure(c, c->rf_q2, NP)) ||
+        (rc = ensure(c, c->rf_src2, NP)) || (rc = ensure(c, c->rf_rest, NP)))
+        return rc;
+    HIPCHK(hipMemcpyAsync(c->rf_cc.p, pts, sizeof pts, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->rf_q.p, ids, sizeof ids, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemsetAsync(c->rf_src.p, 0, NP * sizeof(uint32_t), c->stream));
+    HIPCHK(hipMemsetAsync(c->rf_ctr.p + 1, 0, 2 * sizeof(uint32_t), c->stream));
+    HIPCHK(launch_inside(c->V.p, c->rf_facets.p, nf, c->rf_cc.p, c->rf_q.p, c->rf_src.p, NP, *out, c->rf_rest.p,
+                         c->rf_ctr.p + 2, c->rf_flag.p, c->rf_cc2.p, c->rf_q2.p, c->rf_src2.p, c->rf_ctr.p + 1,
+                         c->stream));
+    uint32_t nin = 0;
+    uint4 got[NP];
+    HIPCHK(hipMemcpyAsync(&nin, c->rf_ctr.p + 1, sizeof nin, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (nin > NP) return fail(c, DT_E_INTERNAL, "inner box test returned %u of %u corners", nin, NP);
+    if (nin) {
+        HIPCHK(hipMemcpyAsync(got, c->rf_q2.p, nin * sizeof(uint4), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    bool inside[NP] = {};
+    for (uint32_t j = 0; j < nin; ++j)
+        if (got[j].x < NP) inside[got[j].x] = true;
+    for (int b = 0; b < NBOX; ++b) {
+        bool ok = true;
+        for (uint32_t q = 0; q < 8; ++q) ok = ok && inside[8 * b + q];
+        for (int k = 0; k < 3; ++k) ok = ok && boxes[b].lo[k] <= boxes[b].hi[k];
+        if (ok) {
+            *out = boxes[b];
+            break;
+        }
+    }
+    return DT_OK;
+}
+
 int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, uint32_t *num_steps,
               uint64_t *inserted) {
     if (!c || !(h > 0.0) || !std::isfinite(h)) return DT_E_ARG;
@@ -2157,8 +2218,18 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         return rc;
     HIPCHK(launch_vert_box(c->V.p, (uint32_t)n0, m, c->rf_partial.p, BOX_BLOCKS, c->rf_cloud.p, c->stream));
     Cloud box{};
+    std::vector<double> part(6 * BOX_BLOCKS);
     HIPCHK(hipMemcpyAsync(&box, c->rf_cloud.p, sizeof box, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(part.data(), c->rf_partial.p, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    // the points' box per axis, from the per-block partial boxes
+    double plo[3] = {INFINITY, INFINITY, INFINITY}, phi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t b = 0; b < BOX_BLOCKS; ++b)
+        for (int k = 0; k < 3; ++k) {
+            plo[k] = std::fmin(plo[k], part[6 * b + k]);
+            phi[k] = std::fmax(phi[k], part[6 * b + 3 + k]);
+        }
     const double ext = box.box[3] > 0 ? std::ldexp(1.0, (int)m) / box.box[3] : 0.0;
     // thresholds as (1.4 h)^2 and (0.7 h)^2 in fp64; grid cells a little wider than 0.7 h so
     // that points closer than it always lie in neighbouring cells
@@ -2179,6 +2250,8 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
     uint32_t nf = 0;
     HIPCHK(hipMemcpyAsync(&nf, c->rf_ctr.p, sizeof nf, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    InnerBox ibox;
+    if ((rc = find_inner_box(c, nf, plo, phi, &ibox))) return rc;
     uint64_t total = 0;
     uint32_t known = 0;  // slots whose last-pass vertices and size flag rf_prev / rf_pbig hold
     for (uint32_t step = 0; step < max_steps; ++step) {
@@ -2188,6 +2261,7 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         if ((rc = ensure(c, c->rf_cc, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q, count)) ||
             (rc = ensure(c, c->rf_cc2, 3 * (size_t)count)) || (rc = ensure(c, c->rf_q2, count)) ||
             (rc = ensure(c, c->rf_src, count)) || (rc = ensure(c, c->rf_src2, count)) ||
+            (rc = ensure(c, c->rf_rest, count)) ||
             (rc = ensure(c, c->rf_flag, count)) || (rc = ensure(c, c->rf_prev, count, true)) ||
             (rc = ensure(c, c->rf_pbig, count, true)))
             return rc;
@@ -2198,8 +2272,11 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         uint32_t k0 = 0;
         HIPCHK(hipMemcpyAsync(&k0, c->rf_ctr.p, sizeof k0, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(launch_inside(c->V.p, c->rf_facets.p, nf, c->rf_cc.p, c->rf_q.p, c->rf_src.p, k0, c->rf_flag.p,
-                             c->rf_cc2.p, c->rf_q2.p, c->rf_src2.p, c->rf_ctr.p + 1, c->stream));
+        // rf_ctr[2] counts the candidates outside the inner box here (the filter rounds below
+        // clear it before they use it)
+        HIPCHK(launch_inside(c->V.p, c->rf_facets.p, nf, c->rf_cc.p, c->rf_q.p, c->rf_src.p, k0, ibox,
+                             c->rf_rest.p, c->rf_ctr.p + 2, c->rf_flag.p, c->rf_cc2.p, c->rf_q2.p, c->rf_src2.p,
+                             c->rf_ctr.p + 1, c->stream));
         uint32_t K = 0;
         HIPCHK(hipMemcpyAsync(&K, c->rf_ctr.p + 1, sizeof K, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));

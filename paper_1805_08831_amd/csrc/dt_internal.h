@@ -328,9 +328,16 @@ hipError_t launch_hull_facets(const void *T, bool wide, uint32_t count, uint4 *f
 hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count, double grow, uint4 *prev,
                          uint8_t *pbig, uint32_t known, double *cc, uint4 *q, uint32_t *src, uint32_t cap,
                          uint32_t *ncand, hipStream_t s);
+// a closed axis-aligned box whose eight corners are strictly inside the convex hull, so every
+// point of it is (the hull is convex); lo > hi on an axis for none
+struct InnerBox {
+    double lo[3], hi[3];
+};
+// candidates in `box` are inside without the facet tests; the others are listed in rest[k]
+// (*nrest zero on entry) for them
 hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const double *cc, const uint4 *q,
-                         const uint32_t *src, uint32_t k, uint8_t *flag, double *cc2, uint4 *q2, uint32_t *src2,
-                         uint32_t *nin, hipStream_t s);
+                         const uint32_t *src, uint32_t k, const InnerBox &box, uint32_t *rest, uint32_t *nrest,
+                         uint8_t *flag, double *cc2, uint4 *q2, uint32_t *src2, uint32_t *nin, hipStream_t s);
 hipError_t launch_order_keys(const uint4 *q, const unsigned long long *moore, const uint32_t *perm, uint32_t k,
                              int which, int bits, unsigned long long *keys, uint32_t *vals, hipStream_t s);
 hipError_t launch_cell_keys(const double *lo, double cell, uint64_t g, const double *xyz, const Vert *V, uint32_t n,

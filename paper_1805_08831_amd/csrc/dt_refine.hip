@@ -157,11 +157,15 @@ __global__ __launch_bounds__(CIRCUM_BLOCK) void k_circum(const R *__restrict__ T
     src[i] = rec[0];
 }
 
-// strictly inside the hull: orient3d(a, b, c, x) < 0 for every hull facet.  The fp64 filter
-// decides almost every test; a candidate it leaves undecided on some facet gets flag 2 and
-// k_inside_exact settles it with the exact predicate (kept out of this kernel, whose
-// registers it would take).  Candidates found inside are appended (compacted) to cc2 / q2 /
-// src2.  The facets' corners pass through LDS in tiles shared by the block's candidates.
+// strictly inside the hull: orient3d(a, b, c, x) < 0 for every hull facet.  k_inside_box
+// takes the candidates in the inner box (a box whose corners were found strictly inside; the
+// hull is convex) as inside without a test and lists the others, so that k_inside runs the
+// facet tests over a compact list (the candidates come in slot order, which is spatially
+// mixed: nearly every block would hold one outside the box).  The fp64 filter decides almost
+// every test; a candidate it leaves undecided on some facet gets flag 2 and k_inside_exact
+// settles it with the exact predicate (kept out of this kernel, whose registers it would
+// take).  Candidates found inside are appended (compacted) to cc2 / q2 / src2.  The facets'
+// corners pass through LDS in tiles shared by the block's candidates.
 constexpr uint32_t INSIDE_TILE = 512;  // facets per tile: 512 x 9 doubles = 36 KB
 
 __device__ __forceinline__ void inside_append(uint32_t i, bool in, P3 x, const uint4 *__restrict__ q,
@@ -178,20 +182,43 @@ __device__ __forceinline__ void inside_append(uint32_t i, bool in, P3 x, const u
     src2[j] = src[i];
 }
 
-__global__ __launch_bounds__(256) void k_inside(const Vert *__restrict__ V, const uint4 *__restrict__ facets,
-                                                uint32_t nf, const double *__restrict__ cc,
-                                                const uint4 *__restrict__ q, const uint32_t *__restrict__ src,
-                                                uint32_t k, uint8_t *__restrict__ flag, double *__restrict__ cc2,
-                                                uint4 *__restrict__ q2, uint32_t *__restrict__ src2,
-                                                uint32_t *__restrict__ nin) {
-    __shared__ double s_f[INSIDE_TILE][9];
+__global__ __launch_bounds__(256) void k_inside_box(const double *__restrict__ cc, const uint4 *__restrict__ q,
+                                                    const uint32_t *__restrict__ src, uint32_t k, InnerBox box,
+                                                    uint8_t *__restrict__ flag, uint32_t *__restrict__ rest,
+                                                    uint32_t *__restrict__ nrest, double *__restrict__ cc2,
+                                                    uint4 *__restrict__ q2, uint32_t *__restrict__ src2,
+                                                    uint32_t *__restrict__ nin) {
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     P3 x = {0.0, 0.0, 0.0};
     if (i < k) x = {cc[3 * (size_t)i], cc[3 * (size_t)i + 1], cc[3 * (size_t)i + 2]};
-    bool in = i < k, unsure = false;
+    const bool boxed = i < k && x.x >= box.lo[0] && x.x <= box.hi[0] && x.y >= box.lo[1] && x.y <= box.hi[1] &&
+                       x.z >= box.lo[2] && x.z <= box.hi[2];
+    if (i < k) flag[i] = 0;
+    const uint32_t j = block_append<256 / 64>(i < k && !boxed, nrest, s_tmp);
+    if (i < k && !boxed) rest[j] = i;
+    inside_append(i, boxed, x, q, src, cc2, q2, src2, nin);
+}
+
+__global__ __launch_bounds__(256) void k_inside(const Vert *__restrict__ V, const uint4 *__restrict__ facets,
+                                                uint32_t nf, const double *__restrict__ cc,
+                                                const uint4 *__restrict__ q, const uint32_t *__restrict__ src,
+                                                const uint32_t *__restrict__ rest, const uint32_t *__restrict__ nrest,
+                                                uint8_t *__restrict__ flag, double *__restrict__ cc2,
+                                                uint4 *__restrict__ q2, uint32_t *__restrict__ src2,
+                                                uint32_t *__restrict__ nin) {
+    __shared__ double s_f[INSIDE_TILE][9];
+    const uint32_t n = *nrest;
+    if (blockIdx.x * blockDim.x >= n) return;  // the whole block: the list is shorter
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = r < n ? rest[r] : 0u;
+    P3 x = {0.0, 0.0, 0.0};
+    if (r < n) x = {cc[3 * (size_t)i], cc[3 * (size_t)i + 1], cc[3 * (size_t)i + 2]};
+    bool in = r < n, unsure = false;
     for (uint32_t f0 = 0; f0 < nf; f0 += INSIDE_TILE) {
         const uint32_t nt = min(INSIDE_TILE, nf - f0);
-        __syncthreads();
+        // also the barrier before the tile is overwritten (the loop bounds are the block's)
+        if (__syncthreads_or(in) == 0) break;
         for (uint32_t j = threadIdx.x; j < nt; j += blockDim.x) {
             const uint4 fa = facets[f0 + j];
             const Vert a = V[fa.x], b = V[fa.y], c = V[fa.z];
@@ -200,7 +227,6 @@ __global__ __launch_bounds__(256) void k_inside(const Vert *__restrict__ V, cons
             s_f[j][6] = c.x; s_f[j][7] = c.y; s_f[j][8] = c.z;
         }
         __syncthreads();
-        if (__syncthreads_or(in) == 0) break;
         for (uint32_t j = 0; j < nt && in; ++j) {
             const int o = orient3d_filter({s_f[j][0], s_f[j][1], s_f[j][2]}, {s_f[j][3], s_f[j][4], s_f[j][5]},
                                           {s_f[j][6], s_f[j][7], s_f[j][8]}, x);
@@ -208,7 +234,7 @@ __global__ __launch_bounds__(256) void k_inside(const Vert *__restrict__ V, cons
             else in = o < 0;
         }
     }
-    if (i < k) flag[i] = in && unsure ? 2 : 0;
+    if (r < n) flag[i] = in && unsure ? 2 : 0;
     inside_append(i, in && !unsure, x, q, src, cc2, q2, src2, nin);
 }
 
@@ -477,10 +503,11 @@ hipError_t launch_circum(const void *T, bool wide, const Vert *V, uint32_t count
 }
 
 hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const double *cc, const uint4 *q,
-                         const uint32_t *src, uint32_t k, uint8_t *flag, double *cc2, uint4 *q2, uint32_t *src2,
-                         uint32_t *nin, hipStream_t s) {
+                         const uint32_t *src, uint32_t k, const InnerBox &box, uint32_t *rest, uint32_t *nrest,
+                         uint8_t *flag, double *cc2, uint4 *q2, uint32_t *src2, uint32_t *nin, hipStream_t s) {
     if (k == 0) return hipSuccess;
-    k_inside<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, src, k, flag, cc2, q2, src2, nin);
+    k_inside_box<<<blocks256(k), 256, 0, s>>>(cc, q, src, k, box, flag, rest, nrest, cc2, q2, src2, nin);
+    k_inside<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, src, rest, nrest, flag, cc2, q2, src2, nin);
     k_inside_exact<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, src, k, flag, cc2, q2, src2, nin);
     return hipGetLastError();
 }
