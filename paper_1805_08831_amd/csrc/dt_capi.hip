@@ -219,9 +219,9 @@ struct dt_ctx {
     DevBuf<uint4> rf_q, rf_q2, rf_facets;
     DevBuf<unsigned long long> rf_moore, rf_k0, rf_k1;
     DevBuf<uint32_t> rf_v0, rf_v1, rf_ctr, rf_flags, rf_pos;
-    DevBuf<uint32_t> rf_src, rf_src2, rf_srcr, rf_hint, rf_rest;  // candidates' tetrahedron vertex records
+    DevBuf<uint32_t> rf_src, rf_src2, rf_srcr, rf_hint, rf_rest, rf_near;  // candidates' tetrahedron vertex records
     RoundGraph graphs[ROUND_GRAPH_SHAPES];              // graph-launched rounds, one per launch shape
-    DevBuf<uint8_t> rf_status, rf_flag, rf_pbig;
+    DevBuf<uint8_t> rf_status, rf_flag, rf_pbig, rf_nnear;
     DevBuf<uint4> rf_prev;  // each slot's vertices at the last refinement pass
     DevBuf<Cloud> rf_cloud;
     DevBuf<uint64_t> rf_off;
@@ -1881,8 +1881,8 @@ int dt_destroy(dt_ctx *c) {
     f(c->rf_cc.p); f(c->rf_cc2.p); f(c->rf_ccr.p); f(c->rf_pts.p); f(c->rf_partial.p);
     f(c->rf_q.p); f(c->rf_q2.p); f(c->rf_facets.p); f(c->rf_moore.p); f(c->rf_k0.p); f(c->rf_k1.p);
     f(c->rf_v0.p); f(c->rf_v1.p); f(c->rf_ctr.p); f(c->rf_flags.p); f(c->rf_pos.p);
-    f(c->rf_src.p); f(c->rf_src2.p); f(c->rf_srcr.p); f(c->rf_hint.p); f(c->rf_rest.p);
-    f(c->rf_status.p); f(c->rf_flag.p); f(c->rf_pbig.p); f(c->rf_prev.p); f(c->rf_cloud.p); f(c->rf_off.p);
+    f(c->rf_src.p); f(c->rf_src2.p); f(c->rf_srcr.p); f(c->rf_hint.p); f(c->rf_rest.p); f(c->rf_near.p);
+    f(c->rf_status.p); f(c->rf_flag.p); f(c->rf_pbig.p); f(c->rf_nnear.p); f(c->rf_prev.p); f(c->rf_cloud.p); f(c->rf_off.p);
     for (int k = 0; k < 3; ++k) {
         for (int j = 0; j < 3; ++j)
             if (c->ev[k][j]) hipEventDestroy(c->ev[k][j]);
@@ -2292,6 +2292,7 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
             (rc = ensure(c, c->hist, radix_hist_entries(sortn))) ||
             (rc = ensure(c, c->scan_tmp, scan_tmp_entries(radix_hist_entries(sortn)) + scan_tmp_entries(sortn) + 64)) ||
             (rc = ensure(c, c->rf_ccr, 3 * (size_t)K)) || (rc = ensure(c, c->rf_status, K)) ||
+            (rc = ensure(c, c->rf_near, FILTER_NEAR_MAX * (size_t)K)) || (rc = ensure(c, c->rf_nnear, K)) ||
             (rc = ensure(c, c->rf_srcr, K)) ||
             (rc = ensure(c, c->rf_flags, (size_t)K + 1)) || (rc = ensure(c, c->rf_pos, (size_t)K + 1)))
             return rc;
@@ -2325,14 +2326,17 @@ int dt_refine(dt_ctx *c, double h, uint32_t max_steps, uint32_t *step_counts, ui
         unsigned long long *ckeys = nullptr;
         uint32_t *crank = sort_into(c, c->rf_k0.p, c->rf_v0.p, c->rf_k1.p, c->rf_v1.p, K, gbits, &ckeys, &he);
         HIPCHK(he);
+        // the close earlier candidates of each, listed once for all the rounds
+        HIPCHK(launch_filter_near(lo, cell, G, ckeys, crank, K, c->rf_ccr.p, lim, c->rf_status.p, c->rf_near.p,
+                                  c->rf_nnear.p, c->stream));
         // two rounds per look at the flags: a round after the last deciding one is a pass that
         // changes nothing, cheaper than a wait for the host
         for (uint32_t round = 0;; round += 2) {
             if (round > K) return fail(c, DT_E_INTERNAL, "refinement filter did not settle");
             HIPCHK(hipMemsetAsync(c->rf_ctr.p + 2, 0, 2 * sizeof(uint32_t), c->stream));
             for (int r2 = 0; r2 < 2; ++r2)
-                HIPCHK(launch_filter_round(lo, cell, G, ckeys, crank, K, c->rf_ccr.p, lim, c->rf_status.p,
-                                           c->rf_ctr.p + 2 + r2, c->stream));
+                HIPCHK(launch_filter_round(lo, cell, G, ckeys, crank, K, c->rf_ccr.p, lim, c->rf_near.p,
+                                           c->rf_nnear.p, c->rf_status.p, c->rf_ctr.p + 2 + r2, c->stream));
             uint32_t und = 0;
             HIPCHK(hipMemcpyAsync(&und, c->rf_ctr.p + 3, sizeof und, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));

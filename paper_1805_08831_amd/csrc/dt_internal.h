@@ -346,9 +346,14 @@ hipError_t launch_near_vertex(const double *lo, double cell, uint64_t g, const V
                               const uint32_t *vidx, uint32_t nv, const double *cc, const uint32_t *src,
                               const uint32_t *perm, uint32_t k, double lim, double *ccr, uint32_t *srcr,
                               uint8_t *status, hipStream_t s);
+// the filter rounds' lists of close earlier candidates: near[8 * k], nnear[k]
+constexpr uint32_t FILTER_NEAR_MAX = 8;
+hipError_t launch_filter_near(const double *lo, double cell, uint64_t g, const unsigned long long *ckeys,
+                              const uint32_t *crank, uint32_t k, const double *ccr, double lim, const uint8_t *status,
+                              uint32_t *near, uint8_t *nnear, hipStream_t s);
 hipError_t launch_filter_round(const double *lo, double cell, uint64_t g, const unsigned long long *ckeys,
-                               const uint32_t *crank, uint32_t k, const double *ccr, double lim, uint8_t *status,
-                               uint32_t *undecided, hipStream_t s);
+                               const uint32_t *crank, uint32_t k, const double *ccr, double lim, const uint32_t *near,
+                               const uint8_t *nnear, uint8_t *status, uint32_t *undecided, hipStream_t s);
 hipError_t launch_kept(const uint8_t *status, uint32_t k, uint32_t *flags, const uint32_t *pos, const double *ccr,
                        const uint32_t *srcr, double *out, uint32_t *hint, int phase, hipStream_t s);
 hipError_t launch_vert_box(const Vert *V, uint32_t n, uint32_t m, double *partial, uint32_t nblocks, Cloud *cl,

@@ -362,6 +362,57 @@ __global__ void k_near_vertex(Grid G, const Vert *__restrict__ V, const unsigned
     status[r] = close ? 2 : 0;
 }
 
+// The earlier candidates (rank below r) closer than the limit: the three cells around the
+// point in each of the 9 rows of cells about it, found by binary search over the candidates'
+// sorted cell keys.  f(o) is called for each; returning false stops the search.
+template <class F>
+__device__ __forceinline__ void near_earlier(const Grid &G, const unsigned long long *__restrict__ ckeys,
+                                             const uint32_t *__restrict__ crank, uint32_t k,
+                                             const double *__restrict__ ccr, double lim, uint32_t r, F &&f) {
+    const double x = ccr[3 * (size_t)r], y = ccr[3 * (size_t)r + 1], z = ccr[3 * (size_t)r + 2];
+    const long long cx = cell_of(G, x, 0), cy = cell_of(G, y, 1), cz = cell_of(G, z, 2);
+    for (long long dz = -1; dz <= 1; ++dz)
+        for (long long dy = -1; dy <= 1; ++dy) {
+            const long long yy = cy + dy, zz = cz + dz;
+            if (yy < 0 || zz < 0 || yy >= (long long)G.g || zz >= (long long)G.g) continue;
+            const long long x0 = cx > 0 ? cx - 1 : 0, x1 = cx + 1 < (long long)G.g ? cx + 1 : (long long)G.g - 1;
+            uint32_t a = lower_bound(ckeys, k, cell_key(G, x0, yy, zz));
+            const unsigned long long kend = cell_key(G, x1, yy, zz);
+            for (; a < k && ckeys[a] <= kend; ++a) {
+                const uint32_t o = crank[a];
+                if (o >= r) continue;
+                if (sq_dist(ccr[3 * (size_t)o], ccr[3 * (size_t)o + 1], ccr[3 * (size_t)o + 2], x, y, z) < lim &&
+                    !f(o))
+                    return;
+            }
+        }
+}
+
+// The list every filter round reads, built once per pass (it depends on the points and their
+// order only): for each candidate still undecided, the earlier candidates closer than the
+// limit that the vertex test did not drop, up to NEAR_MAX of them, stored as near[j * k + r];
+// nnear[r] = their number, NEAR_MAX + 1 when there are more (that candidate searches the
+// grid in every round instead).
+constexpr uint32_t NEAR_MAX = FILTER_NEAR_MAX;
+
+__global__ __launch_bounds__(256) void k_filter_near(Grid G, const unsigned long long *__restrict__ ckeys,
+                                                     const uint32_t *__restrict__ crank, uint32_t k,
+                                                     const double *__restrict__ ccr, double lim,
+                                                     const uint8_t *__restrict__ status, uint32_t *__restrict__ near,
+                                                     uint8_t *__restrict__ nnear) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= k) return;
+    uint32_t c = 0;
+    if (status[r] == 0)
+        near_earlier(G, ckeys, crank, k, ccr, lim, r, [&](uint32_t o) {
+            if (status[o] == 2) return true;  // dropped by a vertex: never counts
+            if (c < NEAR_MAX) near[(size_t)c * k + r] = o;
+            ++c;
+            return c <= NEAR_MAX;
+        });
+    nnear[r] = (uint8_t)c;
+}
+
 // One round of the greedy filter over the candidates in rank order.  Candidate r (not yet
 // decided) looks at the earlier candidates r' < r closer than the limit that are not dropped:
 // any kept one drops r; none undecided keeps r; otherwise r waits.  Decisions never change,
@@ -369,32 +420,30 @@ __global__ void k_near_vertex(Grid G, const Vert *__restrict__ V, const unsigned
 // or the round before gives the same result.  *undecided becomes non-zero if any is left.
 __global__ __launch_bounds__(256) void k_filter_round(Grid G, const unsigned long long *__restrict__ ckeys,
                                                       const uint32_t *__restrict__ crank, uint32_t k,
-                                                      const double *__restrict__ ccr, double lim, uint8_t *status,
+                                                      const double *__restrict__ ccr, double lim,
+                                                      const uint32_t *__restrict__ near,
+                                                      const uint8_t *__restrict__ nnear, uint8_t *status,
                                                       uint32_t *__restrict__ undecided) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     bool pending = false;
     if (r < k && __hip_atomic_load(&status[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        const double x = ccr[3 * (size_t)r], y = ccr[3 * (size_t)r + 1], z = ccr[3 * (size_t)r + 2];
-        const long long cx = cell_of(G, x, 0), cy = cell_of(G, y, 1), cz = cell_of(G, z, 2);
         bool kept_near = false;
-        for (long long dz = -1; dz <= 1 && !kept_near; ++dz)
-            for (long long dy = -1; dy <= 1 && !kept_near; ++dy) {
-                const long long yy = cy + dy, zz = cz + dz;
-                if (yy < 0 || zz < 0 || yy >= (long long)G.g || zz >= (long long)G.g) continue;
-                const long long x0 = cx > 0 ? cx - 1 : 0, x1 = cx + 1 < (long long)G.g ? cx + 1 : (long long)G.g - 1;
-                uint32_t a = lower_bound(ckeys, k, cell_key(G, x0, yy, zz));
-                const unsigned long long kend = cell_key(G, x1, yy, zz);
-                for (; a < k && ckeys[a] <= kend && !kept_near; ++a) {
-                    const uint32_t o = crank[a];
-                    if (o >= r) continue;
-                    const uint8_t so = __hip_atomic_load(&status[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (so == 2) continue;
-                    if (sq_dist(ccr[3 * (size_t)o], ccr[3 * (size_t)o + 1], ccr[3 * (size_t)o + 2], x, y, z) < lim) {
-                        if (so == 1) kept_near = true;
-                        else pending = true;
-                    }
-                }
+        const uint32_t c = nnear[r];
+        if (c <= NEAR_MAX) {
+            for (uint32_t j = 0; j < c && !kept_near; ++j) {
+                const uint8_t so = __hip_atomic_load(&status[near[(size_t)j * k + r]], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                if (so == 1) kept_near = true;
+                else if (so == 0) pending = true;
             }
+        } else {
+            near_earlier(G, ckeys, crank, k, ccr, lim, r, [&](uint32_t o) {
+                const uint8_t so = __hip_atomic_load(&status[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (so == 1) kept_near = true;
+                else if (so == 0) pending = true;
+                return !kept_near;
+            });
+        }
         if (kept_near) {
             pending = false;
             __hip_atomic_store(&status[r], (uint8_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -538,12 +587,21 @@ hipError_t launch_near_vertex(const double *lo, double cell, uint64_t g, const V
     return hipGetLastError();
 }
 
-hipError_t launch_filter_round(const double *lo, double cell, uint64_t g, const unsigned long long *ckeys,
-                               const uint32_t *crank, uint32_t k, const double *ccr, double lim, uint8_t *status,
-                               uint32_t *undecided, hipStream_t s) {
+hipError_t launch_filter_near(const double *lo, double cell, uint64_t g, const unsigned long long *ckeys,
+                              const uint32_t *crank, uint32_t k, const double *ccr, double lim, const uint8_t *status,
+                              uint32_t *near, uint8_t *nnear, hipStream_t s) {
     if (k == 0) return hipSuccess;
     const Grid G = {{lo[0], lo[1], lo[2]}, cell, g};
-    k_filter_round<<<blocks256(k), 256, 0, s>>>(G, ckeys, crank, k, ccr, lim, status, undecided);
+    k_filter_near<<<blocks256(k), 256, 0, s>>>(G, ckeys, crank, k, ccr, lim, status, near, nnear);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_round(const double *lo, double cell, uint64_t g, const unsigned long long *ckeys,
+                               const uint32_t *crank, uint32_t k, const double *ccr, double lim, const uint32_t *near,
+                               const uint8_t *nnear, uint8_t *status, uint32_t *undecided, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    const Grid G = {{lo[0], lo[1], lo[2]}, cell, g};
+    k_filter_round<<<blocks256(k), 256, 0, s>>>(G, ckeys, crank, k, ccr, lim, near, nnear, status, undecided);
     return hipGetLastError();
 }
 
