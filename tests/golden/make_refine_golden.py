@@ -19,7 +19,10 @@ CASES = [("uniform", 600, 7, 0.08), ("uniform", 2000, 11, 0.05), ("clusters", 80
          ("uniform", 20000, 5, 0.03),
          # deep refinement: h n^(1/3) about 0.4, as in the benchmark workload (about six times
          # the input points)
-         ("uniform", 10000, 13, 0.0185)]
+         ("uniform", 10000, 13, 0.0185),
+         # near-cospherical input: the interior tetrahedra's circumcentres crowd the centre, so
+         # most candidates of the first steps have more than eight close earlier ones
+         ("shell", 300, 21, 0.15)]
 
 # the benchmark's refinement workload (bench.py --workload refine)
 FULLSIZE_CASES = [("uniform", 250000, 4007, 0.0064)]
@@ -28,8 +31,9 @@ FULLSIZE_CASES = [("uniform", 250000, 4007, 0.0064)]
 def run_case(kind, n, seed, h):
     import oracle
     from oracle import refine
-    from synth import cluster_points, uniform_points
-    xyz = uniform_points(n, seed) if kind == "uniform" else cluster_points(n, seed, clusters=4)
+    from synth import cluster_points, shell_points, uniform_points
+    xyz = (uniform_points(n, seed) if kind == "uniform" else shell_points(n, seed) if kind == "shell"
+           else cluster_points(n, seed, clusters=4))
     pts, tets, nbrs, steps = refine.refine(xyz, h)
     canon = oracle.canonical(tets).astype(np.int64)
     return (len(pts), ";".join(f"{a}/{b}" for a, b in steps),

@@ -8,7 +8,7 @@ import os
 import numpy as np
 import pytest
 
-from synth import cluster_points, uniform_points
+from synth import cluster_points, shell_points, uniform_points
 from test_gpu import dtlib, say  # noqa: F401  (fixture)
 from validators import check_invariants
 
@@ -34,7 +34,8 @@ def _cases():
 def test_refine_matches_the_oracle(dtlib, oracle_mod, case):
     kind, n, seed, h, npts, steps, ht, hp = case
     say(f"refine {kind} n={n} seed={seed} h={h}")
-    xyz = uniform_points(n, seed) if kind == "uniform" else cluster_points(n, seed, clusters=4)
+    xyz = (uniform_points(n, seed) if kind == "uniform" else shell_points(n, seed) if kind == "shell"
+           else cluster_points(n, seed, clusters=4))
     with dtlib.Triangulation() as tri:
         tri.insert(xyz)
         added, got_steps = dtlib.dt_refine(tri.ctx, h)
