@@ -200,6 +200,23 @@ __global__ __launch_bounds__(256) void k_inside_box(const double *__restrict__ c
     inside_append(i, boxed, x, q, src, cc2, q2, src2, nin);
 }
 
+// lanes per listed candidate in k_inside, each testing every INSIDE_LANES-th facet: the list
+// is short (the candidates near the hull), so one lane per candidate would leave most of the
+// chip idle through the long facet loop
+constexpr uint32_t INSIDE_LANES = 4;
+
+__device__ __forceinline__ bool lanes_and(bool v) {
+    int t = v ? 1 : 0;
+    for (uint32_t m = 1; m < INSIDE_LANES; m <<= 1) t &= __shfl_xor(t, (int)m);
+    return t != 0;
+}
+
+__device__ __forceinline__ bool lanes_or(bool v) {
+    int t = v ? 1 : 0;
+    for (uint32_t m = 1; m < INSIDE_LANES; m <<= 1) t |= __shfl_xor(t, (int)m);
+    return t != 0;
+}
+
 __global__ __launch_bounds__(256) void k_inside(const Vert *__restrict__ V, const uint4 *__restrict__ facets,
                                                 uint32_t nf, const double *__restrict__ cc,
                                                 const uint4 *__restrict__ q, const uint32_t *__restrict__ src,
@@ -207,13 +224,17 @@ __global__ __launch_bounds__(256) void k_inside(const Vert *__restrict__ V, cons
                                                 uint8_t *__restrict__ flag, double *__restrict__ cc2,
                                                 uint4 *__restrict__ q2, uint32_t *__restrict__ src2,
                                                 uint32_t *__restrict__ nin) {
+    constexpr uint32_t PER_BLOCK = 256 / INSIDE_LANES;
     __shared__ double s_f[INSIDE_TILE][9];
     const uint32_t n = *nrest;
-    if (blockIdx.x * blockDim.x >= n) return;  // the whole block: the list is shorter
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x * PER_BLOCK >= n) return;  // the whole block: the list is shorter
+    const uint32_t r = blockIdx.x * PER_BLOCK + threadIdx.x / INSIDE_LANES, l = threadIdx.x % INSIDE_LANES;
     const uint32_t i = r < n ? rest[r] : 0u;
     P3 x = {0.0, 0.0, 0.0};
     if (r < n) x = {cc[3 * (size_t)i], cc[3 * (size_t)i + 1], cc[3 * (size_t)i + 2]};
+    // the sign of each facet decides on its own (inside iff negative on all; a facet the
+    // filter leaves open matters only if none is decided non-negative), so the lanes split
+    // the facets and combine at the end
     bool in = r < n, unsure = false;
     for (uint32_t f0 = 0; f0 < nf; f0 += INSIDE_TILE) {
         const uint32_t nt = min(INSIDE_TILE, nf - f0);
@@ -227,15 +248,17 @@ __global__ __launch_bounds__(256) void k_inside(const Vert *__restrict__ V, cons
             s_f[j][6] = c.x; s_f[j][7] = c.y; s_f[j][8] = c.z;
         }
         __syncthreads();
-        for (uint32_t j = 0; j < nt && in; ++j) {
+        for (uint32_t j = l; j < nt && in; j += INSIDE_LANES) {
             const int o = orient3d_filter({s_f[j][0], s_f[j][1], s_f[j][2]}, {s_f[j][3], s_f[j][4], s_f[j][5]},
                                           {s_f[j][6], s_f[j][7], s_f[j][8]}, x);
             if (o == 2) unsure = true;
             else in = o < 0;
         }
+        in = lanes_and(in);  // a lane that found the candidate outside stops the others
     }
-    if (r < n) flag[i] = in && unsure ? 2 : 0;
-    inside_append(i, in && !unsure, x, q, src, cc2, q2, src2, nin);
+    unsure = lanes_or(unsure);
+    if (r < n && l == 0) flag[i] = in && unsure ? 2 : 0;
+    inside_append(i, l == 0 && in && !unsure, x, q, src, cc2, q2, src2, nin);
 }
 
 // the candidates k_inside left undecided, with exact orient3d
@@ -556,7 +579,8 @@ hipError_t launch_inside(const Vert *V, const uint4 *facets, uint32_t nf, const 
                          uint8_t *flag, double *cc2, uint4 *q2, uint32_t *src2, uint32_t *nin, hipStream_t s) {
     if (k == 0) return hipSuccess;
     k_inside_box<<<blocks256(k), 256, 0, s>>>(cc, q, src, k, box, flag, rest, nrest, cc2, q2, src2, nin);
-    k_inside<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, src, rest, nrest, flag, cc2, q2, src2, nin);
+    k_inside<<<(uint32_t)(((uint64_t)k + 256 / INSIDE_LANES - 1) / (256 / INSIDE_LANES)), 256, 0, s>>>(
+        V, facets, nf, cc, q, src, rest, nrest, flag, cc2, q2, src2, nin);
     k_inside_exact<<<blocks256(k), 256, 0, s>>>(V, facets, nf, cc, q, src, k, flag, cc2, q2, src2, nin);
     return hipGetLastError();
 }
