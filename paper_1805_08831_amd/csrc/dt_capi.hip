@@ -2124,7 +2124,7 @@ namespace {
 uint32_t *sort_into(dt_ctx *c, unsigned long long *k0, uint32_t *v0, unsigned long long *k1, uint32_t *v1,
                     uint32_t n, int bits, unsigned long long **ko, hipError_t *err) {
     bool swapped = false;
-    *err = radix_sort_pairs(k0, v0, k1, v1, c->hist.p, c->scan_tmp.p, n, bits, c->stream, &swapped);
+    *err = radix_sort_pairs_any(k0, v0, k1, v1, c->hist.p, c->scan_tmp.p, n, bits, c->stream, &swapped);
     if (ko) *ko = swapped ? k1 : k0;
     return swapped ? v1 : v0;
 }

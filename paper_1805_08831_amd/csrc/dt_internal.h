@@ -210,6 +210,10 @@ hipError_t launch_keys(const double *xyz, uint64_t n, const uint64_t *off, uint3
 hipError_t radix_sort_pairs(unsigned long long *keys, uint32_t *vals, unsigned long long *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *hist, uint32_t *scan_tmp, uint64_t n,
                             int nbits, hipStream_t s, bool *swapped);
+// the same, in one block (one launch) when n fits one tile of the multi-block form
+hipError_t radix_sort_pairs_any(unsigned long long *keys, uint32_t *vals, unsigned long long *keys_tmp,
+                                uint32_t *vals_tmp, uint32_t *hist, uint32_t *scan_tmp, uint64_t n, int nbits,
+                                hipStream_t s, bool *swapped);
 size_t radix_hist_entries(uint64_t n);
 hipError_t launch_permute(const double *xyz, const uint32_t *vals, const unsigned long long *skeys, int shift,
                           uint64_t n, uint64_t base, uint64_t idx_offset, Vert *V, uint32_t *vtet, uint8_t *dup,

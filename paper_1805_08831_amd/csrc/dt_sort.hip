@@ -444,6 +444,84 @@ hipError_t radix_sort_pairs(unsigned long long *keys, uint32_t *vals, unsigned l
     return hipGetLastError();
 }
 
+// The same sort in one block when the keys fit one tile (n <= RS_TILE): each digit pass is the
+// tile's histogram, its scan and the stable scatter above, and the passes alternate between
+// the two buffers as radix_sort_pairs does, so the result and its buffer are the same.  Short
+// lists (the late refinement passes) then take one launch instead of five per digit.
+__global__ __launch_bounds__(256) void k_rs_small(unsigned long long *ka, uint32_t *va, unsigned long long *kb,
+                                                  uint32_t *vb, uint32_t n, int nbits) {
+    __shared__ uint32_t off[256];
+    __shared__ uint32_t wt[4][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        off[threadIdx.x] = 0;
+        for (int w = 0; w < 4; ++w) wt[w][threadIdx.x] = 0;
+        __syncthreads();
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            const uint32_t e = it * 256 + threadIdx.x;
+            if (e < n) atomicAdd(&off[(ka[e] >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int d = 0; d < 256; ++d) {
+                const uint32_t c = off[d];
+                off[d] = t;
+                t += c;
+            }
+        }
+        __syncthreads();
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            const uint32_t e = it * 256 + threadIdx.x;
+            const bool valid = e < n;
+            const unsigned long long key = valid ? ka[e] : 0ull;
+            const uint32_t val = valid ? va[e] : 0u;
+            const unsigned d = (unsigned)(key >> shift) & 255u;
+            unsigned long long mask = __ballot(valid);
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const unsigned long long bb = __ballot(valid && bit);
+                mask &= bit ? bb : ~bb;
+            }
+            const unsigned rank = (unsigned)__popcll(mask & lt);
+            if (valid && rank == 0) wt[wave][d] = (unsigned)__popcll(mask);
+            __syncthreads();
+            if (valid) {
+                uint32_t pre = 0;
+                for (int w = 0; w < wave; ++w) pre += wt[w][d];
+                const uint32_t pos = off[d] + pre + rank;
+                kb[pos] = key;
+                vb[pos] = val;
+            }
+            __syncthreads();
+            off[threadIdx.x] += wt[0][threadIdx.x] + wt[1][threadIdx.x] + wt[2][threadIdx.x] + wt[3][threadIdx.x];
+            for (int w = 0; w < 4; ++w) wt[w][threadIdx.x] = 0;
+            __syncthreads();
+        }
+        unsigned long long *tk = ka;
+        ka = kb;
+        kb = tk;
+        uint32_t *tv = va;
+        va = vb;
+        vb = tv;
+        // the block's stores of this pass are what the next pass reads (the barriers above
+        // order them within the block)
+    }
+}
+
+hipError_t radix_sort_pairs_any(unsigned long long *keys, uint32_t *vals, unsigned long long *keys_tmp,
+                                uint32_t *vals_tmp, uint32_t *hist, uint32_t *scan_tmp, uint64_t n, int nbits,
+                                hipStream_t s, bool *swapped) {
+    if (n > (uint64_t)RS_TILE)
+        return radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, hist, scan_tmp, n, nbits, s, swapped);
+    *swapped = false;
+    if (n <= 1 || nbits <= 0) return hipSuccess;
+    k_rs_small<<<1, 256, 0, s>>>(keys, vals, keys_tmp, vals_tmp, (uint32_t)n, nbits);
+    *swapped = ((nbits + 7) / 8) % 2 == 1;
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ permutation, levels, anchors
 
 __global__ void k_permute(const double *__restrict__ xyz, const uint32_t *__restrict__ vals,
