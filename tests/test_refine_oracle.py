@@ -7,7 +7,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from synth import cluster_points, uniform_points
+from synth import cluster_points, shell_points, uniform_points
 from validators import check_invariants
 
 
@@ -125,14 +125,15 @@ def test_lattice_closed_form(R, oracle_mod):
     check_invariants(pts, tets, nbrs, oracle_mod, expect_vertices=np.arange(len(pts)))
 
 
-@pytest.mark.parametrize("kind,h", [("uniform", 0.08), ("uniform", 0.05), ("clusters", 0.03)])
+@pytest.mark.parametrize("kind,h", [("uniform", 0.08), ("uniform", 0.05), ("clusters", 0.03), ("shell", 0.15)])
 def test_refined_mesh_properties(R, oracle_mod, kind, h):
     """What the rule fixes at the end: the result is the Delaunay tetrahedralization of its
     points (I1-I7); no inserted point is closer than 0.7 h to another vertex; every
     tetrahedron still larger than 1.4 h with its circumcentre strictly inside the hull has a
     vertex closer than 0.7 h to that circumcentre (so the filter alone stopped it)."""
     from scipy.spatial import cKDTree
-    xyz = uniform_points(600, 7) if kind == "uniform" else cluster_points(800, 8, clusters=4)
+    xyz = (uniform_points(600, 7) if kind == "uniform" else shell_points(300, 21) if kind == "shell"
+           else cluster_points(800, 8, clusters=4))
     pts, tets, nbrs, steps = R.refine(xyz, h)
     n0 = len(xyz)
     assert len(pts) > n0 + 50 and steps[-1][1] == 0
